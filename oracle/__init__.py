@@ -1,0 +1,312 @@
+"""CPU oracle for the RNS-CKKS server-side path of BLB (arXiv 2508.19525).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no code with the
+HIP library under ``paper_2508_19525_amd``; the two meet only through the seeded input
+generators in ``paper_2508_19525_amd.workloads`` (which hold none of the method's
+arithmetic).
+
+The numerical work lives in ``blb_oracle.c`` (plain C, ``unsigned __int128`` and ``%``,
+a textbook NTT for ring products, quad precision for encode/decode).  This module is a thin
+ctypes wrapper that marshals numpy arrays.  All polynomials are in coefficient form,
+limb-major ``[poly][limb][N]`` uint64 residues.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "blb_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libblb_oracle.so")
+
+_u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_u8p = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+
+TAG_SK, TAG_ENC_A, TAG_ENC_E, TAG_KEY_A, TAG_KEY_E, TAG_MASK = 1, 2, 3, 4, 5, 6
+LIMB_INT = 0xFFFFFFFF
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain C + OpenMP + libquadmath)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC,
+                               "-lquadmath", "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = C.CDLL(_LIB_PATH)
+        vp = C.c_void_p
+        sig = {
+            "orc_primes": (C.c_int, [C.c_int, C.c_int, _u64p]),
+            "orc_philox4x32_10": (None, [_u32p, _u32p, _u32p]),
+            "orc_cdt_table": (None, [_u64p]),
+            "orc_sample_uniform_poly": (None, [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, C.c_int, _u64p]),
+            "orc_sample_ternary_poly": (None, [C.c_uint64, C.c_int, _i32p]),
+            "orc_sample_gauss_poly": (None, [C.c_uint64, C.c_uint32, C.c_uint32, C.c_int, _i32p]),
+            "orc_ctx_create": (vp, [C.c_int, C.c_int, C.c_int, C.c_int]),
+            "orc_ctx_destroy": (None, [vp]),
+            "orc_ctx_moduli": (None, [vp, _u64p]),
+            "orc_ntt_forward": (None, [vp, C.c_int, _u64p]),
+            "orc_ntt_inverse": (None, [vp, C.c_int, _u64p]),
+            "orc_polymul": (None, [vp, C.c_int, _u64p, _u64p, _u64p]),
+            "orc_automorphism": (None, [vp, C.c_int, _u64p, C.c_uint64, _u64p]),
+            "orc_galois_elt": (C.c_uint64, [vp, C.c_int64]),
+            "orc_encode": (C.c_int, [vp, _f64p, C.c_int64, C.c_double, _i64p]),
+            "orc_encode_rns": (C.c_int, [vp, _f64p, C.c_int64, C.c_double, C.c_int, _u64p]),
+            "orc_crt_centered": (None, [vp, _u64p, C.c_int, _f64p]),
+            "orc_decode": (None, [vp, _u64p, C.c_int, C.c_double, C.c_int64, _f64p]),
+            "orc_keygen": (vp, [vp, C.c_uint64, _u64p, C.c_int]),
+            "orc_keys_destroy": (None, [vp]),
+            "orc_keys_secret": (None, [vp, _i32p]),
+            "orc_keys_swk": (C.c_int, [vp, C.c_uint64, _u64p]),
+            "orc_encrypt": (None, [vp, _u64p, C.c_int, C.c_uint64, C.c_uint32, _u64p]),
+            "orc_decrypt": (None, [vp, _u64p, C.c_int, C.c_int, _u64p]),
+            "orc_rotate": (C.c_int, [vp, _u64p, C.c_int, C.c_int64, _u64p]),
+            "orc_relinearize": (C.c_int, [vp, _u64p, C.c_int, _u64p]),
+            "orc_rescale": (None, [vp, _u64p, C.c_int, C.c_int, _u64p]),
+            "orc_cp_geometry": (None, [vp, C.c_int, C.c_int, C.c_int, _i32p]),
+            "orc_pack_spatial": (None, [vp, _f64p, C.c_int, C.c_int, C.c_int, _f64p]),
+            "orc_matmul_cp": (C.c_int, [vp, _u64p, C.c_int, _f64p, C.c_int, C.c_int, C.c_int, C.c_void_p, _u64p]),
+            "orc_cp_galois": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, _u64p]),
+            "orc_mask_to_share": (None, [vp, _u64p, C.c_int, C.c_int, C.c_uint64, C.c_uint32, _u64p, _u64p]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def primes(log_n: int, count: int) -> np.ndarray:
+    out = np.zeros(count, np.uint64)
+    if lib().orc_primes(log_n, count, out) != 0:
+        raise ValueError("prime scan failed")
+    return out
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(_c(ctr, np.uint32), _c(key, np.uint32), out)
+    return out
+
+
+def cdt_table() -> np.ndarray:
+    out = np.zeros(20, np.uint64)
+    lib().orc_cdt_table(out)
+    return out
+
+
+def sample_uniform(seed, limb, obj, tag, q, n) -> np.ndarray:
+    out = np.zeros(n, np.uint64)
+    lib().orc_sample_uniform_poly(seed, limb, obj, tag, int(q), n, out)
+    return out
+
+
+def sample_ternary(seed, n) -> np.ndarray:
+    out = np.zeros(n, np.int32)
+    lib().orc_sample_ternary_poly(seed, n, out)
+    return out
+
+
+def sample_gauss(seed, obj, tag, n) -> np.ndarray:
+    out = np.zeros(n, np.int32)
+    lib().orc_sample_gauss_poly(seed, obj, tag, n, out)
+    return out
+
+
+class Context:
+    """Ring Z[X]/(X^N+1) with the RNS chain q_0..q_{n_q-1} and special primes p_0..p_{K-1}."""
+
+    def __init__(self, log_n: int, n_q: int, n_special: int, dnum: int):
+        self.log_n, self.n, self.n_q, self.n_special, self.dnum = log_n, 1 << log_n, n_q, n_special, dnum
+        self.alpha = (n_q + dnum - 1) // dnum
+        self._p = lib().orc_ctx_create(log_n, n_q, n_special, dnum)
+        if not self._p:
+            raise ValueError("bad parameters")
+        m = np.zeros(n_q + n_special, np.uint64)
+        lib().orc_ctx_moduli(self._p, m)
+        self.moduli = m
+        self.q = m[:n_q]
+        self.p = m[n_q:]
+
+    def __del__(self):
+        if getattr(self, "_p", None):
+            lib().orc_ctx_destroy(self._p)
+            self._p = None
+
+    @property
+    def slots(self) -> int:
+        return self.n // 2
+
+    # ---- ring primitives (coefficient form) ----
+    def ntt_forward(self, m, a):
+        a = _c(a, np.uint64).copy()
+        lib().orc_ntt_forward(self._p, m, a)
+        return a
+
+    def ntt_inverse(self, m, a):
+        a = _c(a, np.uint64).copy()
+        lib().orc_ntt_inverse(self._p, m, a)
+        return a
+
+    def polymul(self, m, a, b):
+        r = np.zeros(self.n, np.uint64)
+        lib().orc_polymul(self._p, m, _c(a, np.uint64), _c(b, np.uint64), r)
+        return r
+
+    def automorphism(self, m, a, g):
+        r = np.zeros(self.n, np.uint64)
+        lib().orc_automorphism(self._p, m, _c(a, np.uint64), int(g), r)
+        return r
+
+    def galois_elt(self, left_steps: int) -> int:
+        return int(lib().orc_galois_elt(self._p, int(left_steps)))
+
+    # ---- encode / decode ----
+    def encode(self, m, delta: float) -> np.ndarray:
+        m = _c(m, np.float64)
+        out = np.zeros(self.n, np.int64)
+        rc = lib().orc_encode(self._p, m, m.size, float(delta), out)
+        if rc != 0:
+            raise ValueError("encode overflow")
+        return out
+
+    def encode_rns(self, m, delta: float, level: int) -> np.ndarray:
+        m = _c(m, np.float64)
+        out = np.zeros((level + 1, self.n), np.uint64)
+        rc = lib().orc_encode_rns(self._p, m, m.size, float(delta), level, out)
+        if rc != 0:
+            raise ValueError("encode overflow")
+        return out
+
+    def crt_centered(self, poly, level: int) -> np.ndarray:
+        out = np.zeros(self.n, np.float64)
+        lib().orc_crt_centered(self._p, _c(poly, np.uint64), level, out)
+        return out
+
+    def decode(self, poly, level: int, delta: float, n_vals: int | None = None) -> np.ndarray:
+        n_vals = self.slots if n_vals is None else n_vals
+        out = np.zeros(n_vals, np.float64)
+        lib().orc_decode(self._p, _c(poly, np.uint64), level, float(delta), n_vals, out)
+        return out
+
+    def rescale(self, ct, level: int) -> np.ndarray:
+        ct = _c(ct, np.uint64)
+        n_poly = ct.size // ((level + 1) * self.n)
+        out = np.zeros((n_poly, level, self.n), np.uint64)
+        lib().orc_rescale(self._p, ct, level, n_poly, out)
+        return out
+
+    # ---- matmul_cp geometry / packing ----
+    def cp_geometry(self, L, d_in, d_out) -> dict:
+        g = np.zeros(8, np.int32)
+        lib().orc_cp_geometry(self._p, L, d_in, d_out, g)
+        return dict(zip(["Lp", "c", "c_eff", "c_out", "n_in", "n_out", "B", "G"], [int(v) for v in g]))
+
+    def pack_spatial(self, X, a: int) -> np.ndarray:
+        X = _c(X, np.float64)
+        out = np.zeros(self.slots, np.float64)
+        lib().orc_pack_spatial(self._p, X, X.shape[0], X.shape[1], a, out)
+        return out
+
+    def cp_galois(self, L, d_in, d_out) -> np.ndarray:
+        out = np.zeros(64, np.uint64)
+        k = lib().orc_cp_galois(self._p, L, d_in, d_out, out)
+        return out[:k].copy()
+
+    def mask_to_share(self, ct, level: int, target_level: int, seed: int, ct_id: int):
+        masked = np.zeros((2, target_level + 1, self.n), np.uint64)
+        share = np.zeros((target_level + 1, self.n), np.uint64)
+        lib().orc_mask_to_share(self._p, _c(ct, np.uint64), level, target_level, seed, ct_id, masked, share)
+        return masked, share
+
+
+class Keys:
+    """Secret key, relinearisation key and Galois keys (all host-side, coefficient form)."""
+
+    def __init__(self, ctx: Context, seed: int, galois=()):
+        self.ctx = ctx
+        self.galois = [int(g) for g in galois]
+        arr = np.array(self.galois if self.galois else [0], np.uint64)
+        self._p = lib().orc_keygen(ctx._p, seed, arr, len(self.galois))
+
+    def __del__(self):
+        if getattr(self, "_p", None):
+            lib().orc_keys_destroy(self._p)
+            self._p = None
+
+    @property
+    def secret(self) -> np.ndarray:
+        s = np.zeros(self.ctx.n, np.int32)
+        lib().orc_keys_secret(self._p, s)
+        return s
+
+    def switching_key(self, key_id: int) -> np.ndarray:
+        c = self.ctx
+        out = np.zeros((c.dnum, 2, c.n_q + c.n_special, c.n), np.uint64)
+        if lib().orc_keys_swk(self._p, key_id, out) != 0:
+            raise KeyError(key_id)
+        return out
+
+    def encrypt(self, pt, level: int, seed: int, ct_id: int = 0) -> np.ndarray:
+        out = np.zeros((2, level + 1, self.ctx.n), np.uint64)
+        lib().orc_encrypt(self._p, _c(pt, np.uint64), level, seed, ct_id, out)
+        return out
+
+    def decrypt(self, ct, level: int) -> np.ndarray:
+        ct = _c(ct, np.uint64)
+        degree = ct.size // ((level + 1) * self.ctx.n) - 1
+        out = np.zeros((level + 1, self.ctx.n), np.uint64)
+        lib().orc_decrypt(self._p, ct, level, degree, out)
+        return out
+
+    def rotate(self, ct, level: int, steps: int) -> np.ndarray:
+        out = np.zeros((2, level + 1, self.ctx.n), np.uint64)
+        if lib().orc_rotate(self._p, _c(ct, np.uint64), level, int(steps), out) != 0:
+            raise KeyError("missing Galois key")
+        return out
+
+    def relinearize(self, ct3, level: int) -> np.ndarray:
+        out = np.zeros((2, level + 1, self.ctx.n), np.uint64)
+        if lib().orc_relinearize(self._p, _c(ct3, np.uint64), level, out) != 0:
+            raise KeyError("missing relinearisation key")
+        return out
+
+    def matmul_cp(self, X_cts, level: int, W, L: int, outputs=None) -> np.ndarray:
+        c = self.ctx
+        W = _c(W, np.float64)
+        d_in, d_out = W.shape
+        g = c.cp_geometry(L, d_in, d_out)
+        Y = np.zeros((g["n_out"], 2, level, c.n), np.uint64)
+        mask = None
+        if outputs is not None:
+            m = np.zeros(g["n_out"], np.uint8)
+            m[list(outputs)] = 1
+            mask = m.ctypes.data_as(C.c_void_p)
+        rc = lib().orc_matmul_cp(self._p, _c(X_cts, np.uint64), level, W, L, d_in, d_out, mask, Y)
+        if rc != 0:
+            raise KeyError("missing Galois key")
+        return Y

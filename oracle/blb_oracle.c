@@ -1,0 +1,851 @@
+/*
+ * blb_oracle.c -- plain, slow CPU reference ("the oracle") for the server-side RNS-CKKS
+ * path of "Breaking the Layer Barrier" (BLB, arXiv 2508.19525).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU-baseline leg
+ * of the benchmark load this library.  It shares no code, header, table or constant
+ * generator with the HIP library: every constant here (primes, roots, CRT factors, the
+ * Gaussian CDT, Philox) is computed or written out independently in this file.
+ *
+ * Representation: every polynomial is kept in COEFFICIENT form as residues in [0, q_i),
+ * limb-major: ct[poly][limb][N].  Ring products are exact negacyclic convolutions computed
+ * with a textbook NTT (twist by psi^k, cyclic radix-2 DFT, pointwise, inverse); all modular
+ * arithmetic uses unsigned __int128 and '%'.
+ *
+ * What it follows (sections of the paper):
+ *   - CKKS primitives (Preliminaries, "Cryptographic Primitives"): ciphertext = pair of ring
+ *     elements, rescale, homomorphic add/mult, left/right rotation.
+ *   - Encoding (eq. ckks_encode, "CKKS Approximate HE and Message Encoding"): real slots only.
+ *   - matmul_cp with BSGS (Section "Efficient Protocol for Fused MatMuls" and Appendix
+ *     "BSGS Optimization"), spatial-first packing ("Consistent Packing for Single Operator").
+ *   - matmul_cc steps 1-3 with multi-head packing ("Building Blocks", Multi-Head Optimization).
+ *   - CKKS-to-MPC mask-and-share, step 1 of Algorithm ckks2mpc and F_C2M.
+ * Where the paper is silent (primes, randomness, key switching variant, schedules) the
+ * readings are documented with the function that implements them.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+#include <quadmath.h>
+
+typedef unsigned __int128 u128;
+typedef __float128 f128;
+
+#define MAXL 16 /* max primes (q's + p's) */
+
+/* ------------------------------------------------------------------------------------ */
+/* integer helpers                                                                       */
+/* ------------------------------------------------------------------------------------ */
+static inline uint64_t mulm(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)(((u128)a * b) % q); }
+static inline uint64_t addm(uint64_t a, uint64_t b, uint64_t q) { uint64_t s = a + b; return s >= q ? s - q : s; }
+static inline uint64_t subm(uint64_t a, uint64_t b, uint64_t q) { return a >= b ? a - b : a + q - b; }
+static uint64_t powm(uint64_t a, uint64_t e, uint64_t q) {
+  uint64_t r = 1 % q; a %= q;
+  while (e) { if (e & 1) r = mulm(r, a, q); a = mulm(a, a, q); e >>= 1; }
+  return r;
+}
+static inline uint64_t invm(uint64_t a, uint64_t q) { return powm(a, q - 2, q); } /* q prime */
+/* reduce a signed integer into [0,q) */
+static inline uint64_t smod(int64_t v, uint64_t q) {
+  int64_t r = v % (int64_t)q; if (r < 0) r += (int64_t)q; return (uint64_t)r;
+}
+
+/* deterministic Miller-Rabin for 64-bit n (bases 2..37 suffice below 3.3e24) */
+static int is_prime_u64(uint64_t n) {
+  static const uint64_t bases[12] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+  if (n < 2) return 0;
+  for (int i = 0; i < 12; ++i) { if (n == bases[i]) return 1; if (n % bases[i] == 0) return 0; }
+  uint64_t d = n - 1; int s = 0;
+  while ((d & 1) == 0) { d >>= 1; ++s; }
+  for (int i = 0; i < 12; ++i) {
+    uint64_t x = powm(bases[i], d, n);
+    if (x == 1 || x == n - 1) continue;
+    int comp = 1;
+    for (int r = 1; r < s; ++r) { x = mulm(x, x, n); if (x == n - 1) { comp = 0; break; } }
+    if (comp) return 0;
+  }
+  return 1;
+}
+
+/* Prime rule (the paper fixes only that parameters are RNS chains of NTT-friendly primes):
+ * scan q = k*2N + 1 downward from the largest such value below 2^50; the first n_q primes
+ * found are q_0, q_1, ... and the next n_special are p_0, p_1, ... */
+int orc_primes(int log_n, int count, uint64_t* out) {
+  uint64_t two_n = 2ull << log_n;
+  uint64_t k = ((1ull << 50) - 2) / two_n;
+  int found = 0;
+  for (; k > 0 && found < count; --k) {
+    uint64_t q = k * two_n + 1;
+    if (is_prime_u64(q)) out[found++] = q;
+  }
+  return found == count ? 0 : -1;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3",  */
+/* SC'11): 10 rounds of the 4x32 Philox S-box with multipliers 0xD2511F53 / 0xCD9E8D57 and   */
+/* Weyl key increments 0x9E3779B9 / 0xBB67AE85.                                            */
+/* ------------------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+  uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+  uint32_t k0 = key_in[0], k1 = key_in[1];
+  for (int r = 0; r < 10; ++r) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Randomness reading (the paper is silent): counter = (coefficient k, limb, object id,
+ * domain tag), key = the 64-bit seed split into (low, high) 32-bit words.  Integer-valued
+ * samples (secret, errors) use limb = 0xFFFFFFFF and are reduced into every limb. */
+enum { TAG_SK = 1, TAG_ENC_A = 2, TAG_ENC_E = 3, TAG_KEY_A = 4, TAG_KEY_E = 5, TAG_MASK = 6 };
+#define LIMB_INT 0xFFFFFFFFu
+
+static void philox_at(uint64_t seed, uint32_t k, uint32_t limb, uint32_t obj, uint32_t tag, uint32_t out[4]) {
+  uint32_t ctr[4] = {k, limb, obj, tag};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  orc_philox4x32_10(ctr, key, out);
+}
+
+/* uniform mod q: the 128-bit Philox block (word 0 least significant) reduced mod q */
+static uint64_t sample_uniform(uint64_t seed, uint32_t k, uint32_t limb, uint32_t obj, uint32_t tag, uint64_t q) {
+  uint32_t w[4]; philox_at(seed, k, limb, obj, tag, w);
+  u128 x = ((u128)w[3] << 96) | ((u128)w[2] << 64) | ((u128)w[1] << 32) | (u128)w[0];
+  return (uint64_t)(x % q);
+}
+/* ternary secret coefficient: (word0 mod 3) - 1 */
+static int sample_ternary(uint64_t seed, uint32_t k) {
+  uint32_t w[4]; philox_at(seed, k, LIMB_INT, 0, TAG_SK, w);
+  return (int)(w[0] % 3u) - 1;
+}
+
+/* Gaussian error: discrete Gaussian rho(x) = exp(-x^2/(2 sigma^2)), sigma = 3.2, support
+ * |x| <= 19 = floor(6 sigma), sampled by a cumulative distribution table on |x| with 63-bit
+ * thresholds T_k = floor(2^63 * P(|x| <= k)) and a separate sign bit.  The table is computed
+ * here in quad precision. */
+#define CDT_MAX 19
+static uint64_t g_cdt[CDT_MAX + 1];
+static int g_cdt_ready = 0;
+static void cdt_init(void) {
+  if (g_cdt_ready) return;
+  const f128 sigma = 3.2Q;
+  f128 rho[CDT_MAX + 1], z = 0;
+  for (int x = 0; x <= CDT_MAX; ++x) {
+    rho[x] = expq(-(f128)(x * x) / (2 * sigma * sigma));
+    z += (x == 0 ? 1 : 2) * rho[x];
+  }
+  f128 cum = 0;
+  for (int x = 0; x <= CDT_MAX; ++x) {
+    cum += (x == 0 ? 1 : 2) * rho[x] / z;
+    f128 t = floorq(cum * 9223372036854775808.0Q); /* 2^63 */
+    if (t >= 9223372036854775808.0Q) t = 9223372036854775807.0Q;
+    g_cdt[x] = (uint64_t)t;
+  }
+  g_cdt[CDT_MAX] = 0x7FFFFFFFFFFFFFFFull; /* the last bucket takes the remainder */
+  g_cdt_ready = 1;
+}
+void orc_cdt_table(uint64_t out[CDT_MAX + 1]) { cdt_init(); memcpy(out, g_cdt, sizeof(g_cdt)); }
+
+static int sample_gauss(uint64_t seed, uint32_t k, uint32_t obj, uint32_t tag) {
+  cdt_init();
+  uint32_t w[4]; philox_at(seed, k, LIMB_INT, obj, tag, w);
+  uint64_t r = (((uint64_t)w[1] << 32) | w[0]) >> 1; /* 63 uniform bits */
+  int x = 0;
+  while (x < CDT_MAX && r >= g_cdt[x]) ++x;
+  return (w[2] & 1u) ? -x : x;
+}
+
+/* exported samplers (used by the statistical pins) */
+void orc_sample_uniform_poly(uint64_t seed, uint32_t limb, uint32_t obj, uint32_t tag, uint64_t q, int n, uint64_t* out) {
+  for (int k = 0; k < n; ++k) out[k] = sample_uniform(seed, (uint32_t)k, limb, obj, tag, q);
+}
+void orc_sample_ternary_poly(uint64_t seed, int n, int32_t* out) {
+  for (int k = 0; k < n; ++k) out[k] = sample_ternary(seed, (uint32_t)k);
+}
+void orc_sample_gauss_poly(uint64_t seed, uint32_t obj, uint32_t tag, int n, int32_t* out) {
+  for (int k = 0; k < n; ++k) out[k] = sample_gauss(seed, (uint32_t)k, obj, tag);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* context: primes, textbook NTT tables, CRT constants                                   */
+/* ------------------------------------------------------------------------------------ */
+typedef struct {
+  int log_n, n, n_q, n_sp, dnum, alpha;
+  uint64_t mod[MAXL];      /* q_0..q_{n_q-1}, p_0..p_{n_sp-1} */
+  uint64_t* psi_pow[MAXL]; /* psi^k, k < N */
+  uint64_t* ipsi_pow[MAXL];/* psi^-k */
+  uint64_t* omega[MAXL];   /* omega^k = psi^(2k), k < N */
+  uint64_t* iomega[MAXL];
+  uint64_t n_inv[MAXL];
+  f128* cw_re; f128* cw_im; /* zeta^j = exp(i pi j / N), j < 2N, quad precision */
+} orc_ctx;
+
+static uint64_t find_psi(uint64_t q, int log_n) {
+  uint64_t two_n = 2ull << log_n;
+  for (uint64_t g = 2;; ++g) {
+    uint64_t psi = powm(g, (q - 1) / two_n, q);
+    if (powm(psi, two_n >> 1, q) == q - 1) return psi; /* order exactly 2N */
+  }
+}
+
+orc_ctx* orc_ctx_create(int log_n, int n_q, int n_special, int dnum) {
+  if (log_n < 2 || log_n > 16 || n_q < 1 || n_special < 0 || n_q + n_special > MAXL || dnum < 1) return NULL;
+  orc_ctx* c = (orc_ctx*)calloc(1, sizeof(orc_ctx));
+  c->log_n = log_n; c->n = 1 << log_n; c->n_q = n_q; c->n_sp = n_special; c->dnum = dnum;
+  c->alpha = (n_q + dnum - 1) / dnum;
+  if (orc_primes(log_n, n_q + n_special, c->mod) != 0) { free(c); return NULL; }
+  int n = c->n;
+  for (int m = 0; m < n_q + n_special; ++m) {
+    uint64_t q = c->mod[m], psi = find_psi(q, log_n), ipsi = invm(psi, q);
+    c->psi_pow[m] = (uint64_t*)malloc(8 * n); c->ipsi_pow[m] = (uint64_t*)malloc(8 * n);
+    c->omega[m] = (uint64_t*)malloc(8 * n); c->iomega[m] = (uint64_t*)malloc(8 * n);
+    uint64_t a = 1, b = 1;
+    for (int k = 0; k < n; ++k) { c->psi_pow[m][k] = a; c->ipsi_pow[m][k] = b; a = mulm(a, psi, q); b = mulm(b, ipsi, q); }
+    uint64_t w = mulm(psi, psi, q), iw = invm(w, q);
+    a = 1; b = 1;
+    for (int k = 0; k < n; ++k) { c->omega[m][k] = a; c->iomega[m][k] = b; a = mulm(a, w, q); b = mulm(b, iw, q); }
+    c->n_inv[m] = invm((uint64_t)n % q, q);
+  }
+  c->cw_re = (f128*)malloc(sizeof(f128) * 2 * n); c->cw_im = (f128*)malloc(sizeof(f128) * 2 * n);
+  for (int j = 0; j < 2 * n; ++j) {
+    f128 ang = M_PIq * (f128)j / (f128)n;
+    c->cw_re[j] = cosq(ang); c->cw_im[j] = sinq(ang);
+  }
+  return c;
+}
+void orc_ctx_destroy(orc_ctx* c) {
+  if (!c) return;
+  for (int m = 0; m < c->n_q + c->n_sp; ++m) { free(c->psi_pow[m]); free(c->ipsi_pow[m]); free(c->omega[m]); free(c->iomega[m]); }
+  free(c->cw_re); free(c->cw_im); free(c);
+}
+void orc_ctx_moduli(const orc_ctx* c, uint64_t* out) { memcpy(out, c->mod, 8 * (c->n_q + c->n_sp)); }
+
+/* ---- textbook negacyclic NTT: A[t] = sum_k a_k psi^((2t+1)k) mod q, natural order t ---- */
+static void bitrev_perm(uint64_t* a, int n) {
+  for (int i = 1, j = 0; i < n; ++i) {
+    int bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) { uint64_t t = a[i]; a[i] = a[j]; a[j] = t; }
+  }
+}
+/* cyclic DFT with root table w[k] = root^k (iterative radix-2 Cooley-Tukey) */
+static void cyclic_dft(uint64_t* a, int n, const uint64_t* w, uint64_t q) {
+  bitrev_perm(a, n);
+  for (int len = 2; len <= n; len <<= 1) {
+    int step = n / len;
+    for (int s = 0; s < n; s += len)
+      for (int j = 0; j < len / 2; ++j) {
+        uint64_t u = a[s + j], v = mulm(a[s + j + len / 2], w[j * step], q);
+        a[s + j] = addm(u, v, q); a[s + j + len / 2] = subm(u, v, q);
+      }
+  }
+}
+static void ntt_fwd(const orc_ctx* c, int m, uint64_t* a) {
+  uint64_t q = c->mod[m];
+  for (int k = 0; k < c->n; ++k) a[k] = mulm(a[k], c->psi_pow[m][k], q);
+  cyclic_dft(a, c->n, c->omega[m], q);
+}
+static void ntt_inv(const orc_ctx* c, int m, uint64_t* a) {
+  uint64_t q = c->mod[m];
+  cyclic_dft(a, c->n, c->iomega[m], q);
+  for (int k = 0; k < c->n; ++k) a[k] = mulm(mulm(a[k], c->n_inv[m], q), c->ipsi_pow[m][k], q);
+}
+/* exported for the pins */
+void orc_ntt_forward(const orc_ctx* c, int m, uint64_t* a) { ntt_fwd(c, m, a); }
+void orc_ntt_inverse(const orc_ctx* c, int m, uint64_t* a) { ntt_inv(c, m, a); }
+
+/* negacyclic product r = a*b mod (X^N+1, modulus index m); r may alias a or b */
+static void polymul(const orc_ctx* c, int m, const uint64_t* a, const uint64_t* b, uint64_t* r) {
+  int n = c->n; uint64_t q = c->mod[m];
+  uint64_t* fa = (uint64_t*)malloc(8 * n); uint64_t* fb = (uint64_t*)malloc(8 * n);
+  memcpy(fa, a, 8 * n); memcpy(fb, b, 8 * n);
+  ntt_fwd(c, m, fa); ntt_fwd(c, m, fb);
+  for (int k = 0; k < n; ++k) fa[k] = mulm(fa[k], fb[k], q);
+  ntt_inv(c, m, fa);
+  memcpy(r, fa, 8 * n);
+  free(fa); free(fb);
+}
+void orc_polymul(const orc_ctx* c, int m, const uint64_t* a, const uint64_t* b, uint64_t* r) { polymul(c, m, a, b, r); }
+
+/* Galois automorphism sigma_g: X^k -> X^(kg mod 2N), negated when kg mod 2N >= N */
+static void automorph(const orc_ctx* c, int m, const uint64_t* a, uint64_t g, uint64_t* r) {
+  int n = c->n; uint64_t q = c->mod[m]; uint64_t two_n = 2ull * n;
+  for (int k = 0; k < n; ++k) {
+    uint64_t e = ((uint64_t)k * g) % two_n;
+    if (e < (uint64_t)n) r[e] = a[k]; else r[e - n] = a[k] ? q - a[k] : 0;
+  }
+}
+void orc_automorphism(const orc_ctx* c, int m, const uint64_t* a, uint64_t g, uint64_t* r) { automorph(c, m, a, g, r); }
+
+/* slot index -> exponent: slot j sits at zeta^(5^j mod 2N) */
+static uint64_t galois_left(const orc_ctx* c, int64_t t) {
+  int64_t s = c->n / 2;
+  int64_t tt = ((t % s) + s) % s;
+  return powm(5, (uint64_t)tt, 2ull * c->n);
+}
+uint64_t orc_galois_elt(const orc_ctx* c, int64_t left_steps) { return galois_left(c, left_steps); }
+
+/* ------------------------------------------------------------------------------------ */
+/* encode / decode (eq. ckks_encode, real slots)                                         */
+/* ------------------------------------------------------------------------------------ */
+/* complex quad FFT in place, unnormalised: y[t] = sum_k x[k] * zeta^(2*sgn*t*k) */
+static void fft_quad(const orc_ctx* c, f128* re, f128* im, int sgn) {
+  int n = c->n;
+  for (int i = 1, j = 0; i < n; ++i) {
+    int bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) { f128 t = re[i]; re[i] = re[j]; re[j] = t; t = im[i]; im[i] = im[j]; im[j] = t; }
+  }
+  for (int len = 2; len <= n; len <<= 1) {
+    int step = n / len; /* omega^(j*step) = zeta^(2*j*step) */
+    for (int s = 0; s < n; s += len)
+      for (int j = 0; j < len / 2; ++j) {
+        int e = (2 * j * step) % (2 * n);
+        f128 wr = c->cw_re[e], wi = sgn > 0 ? c->cw_im[e] : -c->cw_im[e];
+        f128 xr = re[s + j + len / 2], xi = im[s + j + len / 2];
+        f128 vr = xr * wr - xi * wi, vi = xr * wi + xi * wr;
+        f128 ur = re[s + j], ui = im[s + j];
+        re[s + j] = ur + vr; im[s + j] = ui + vi;
+        re[s + j + len / 2] = ur - vr; im[s + j + len / 2] = ui - vi;
+      }
+  }
+}
+
+/* Encode: p_k = round_half_away( (2*Delta/N) * sum_j m_j cos(pi * e_j * k / N) ), e_j = 5^j mod 2N.
+ * Computed as the inverse transform over all odd exponents r: slot values sit at r = e_j
+ * and (real slots) at r = -e_j; p_k = (Delta/N) Re( zeta^(-k) sum_t z_t omega^(-t k) ) with
+ * r = 2t + 1.  Slots beyond n_vals are zero.  Output: signed integer coefficients. */
+int orc_encode(const orc_ctx* c, const double* m, int64_t n_vals, double delta, int64_t* out) {
+  int n = c->n, s = n / 2;
+  if (n_vals > s || n_vals < 0) return -1;
+  f128* re = (f128*)calloc(n, sizeof(f128)); f128* im = (f128*)calloc(n, sizeof(f128));
+  uint64_t e = 1, two_n = 2ull * n;
+  for (int j = 0; j < s; ++j) {
+    f128 v = j < n_vals ? (f128)m[j] : 0;
+    re[(e - 1) / 2] = v;
+    re[(two_n - e - 1) / 2] = v;
+    e = (e * 5) % two_n;
+  }
+  fft_quad(c, re, im, -1);
+  int rc = 0;
+  for (int k = 0; k < n; ++k) {
+    int ek = (2 * n - k) % (2 * n); /* zeta^(-k) */
+    f128 v = (re[k] * c->cw_re[ek] - im[k] * c->cw_im[ek]) * (f128)delta / (f128)n;
+    f128 r = v >= 0 ? floorq(v + 0.5Q) : -floorq(-v + 0.5Q);
+    if (fabsq(r) > 9.0e18Q) { rc = -2; r = 0; }
+    out[k] = (int64_t)r;
+  }
+  free(re); free(im);
+  return rc;
+}
+
+/* residues of a signed integer polynomial in limbs 0..n_limbs-1 */
+static void to_rns(const orc_ctx* c, const int64_t* p, int n_limbs, uint64_t* out) {
+  for (int i = 0; i < n_limbs; ++i)
+    for (int k = 0; k < c->n; ++k) out[(size_t)i * c->n + k] = smod(p[k], c->mod[i]);
+}
+int orc_encode_rns(const orc_ctx* c, const double* m, int64_t n_vals, double delta, int level, uint64_t* out) {
+  int64_t* p = (int64_t*)malloc(8 * c->n);
+  int rc = orc_encode(c, m, n_vals, delta, p);
+  if (rc == 0) to_rns(c, p, level + 1, out);
+  free(p);
+  return rc;
+}
+
+/* centred CRT lift of residues r[0..nl-1] (moduli c->mod[0..nl-1]) as a quad value, via
+ * Garner's mixed-radix digits; the lift is the representative in (-Q/2, Q/2]. */
+static f128 crt_centered(const orc_ctx* c, const uint64_t* r, int nl) {
+  uint64_t v[MAXL], vn[MAXL];
+  for (int i = 0; i < nl; ++i) {
+    uint64_t q = c->mod[i];
+    uint64_t t = r[i] % q, tn = (q - r[i] % q) % q;
+    for (int j = 0; j < i; ++j) {
+      uint64_t inv = invm(c->mod[j] % q, q);
+      t = mulm(subm(t, v[j] % q, q), inv, q);
+      tn = mulm(subm(tn, vn[j] % q, q), inv, q);
+    }
+    v[i] = t; vn[i] = tn;
+  }
+  f128 x = 0, xn = 0;
+  for (int i = nl - 1; i >= 0; --i) { x = x * (f128)c->mod[i] + (f128)v[i]; xn = xn * (f128)c->mod[i] + (f128)vn[i]; }
+  return x <= xn ? x : -xn;
+}
+void orc_crt_centered(const orc_ctx* c, const uint64_t* poly, int level, double* out) {
+  int nl = level + 1;
+  for (int k = 0; k < c->n; ++k) {
+    uint64_t r[MAXL];
+    for (int i = 0; i < nl; ++i) r[i] = poly[(size_t)i * c->n + k];
+    out[k] = (double)crt_centered(c, r, nl);
+  }
+}
+
+/* Decode: m_j = Delta^-1 * Re( p~(zeta^(e_j)) ), p~ = centred CRT lift (no rounding before
+ * the embedding; see the reading of eq. ckks_encode in the design notes). */
+void orc_decode(const orc_ctx* c, const uint64_t* poly, int level, double delta, int64_t n_vals, double* out) {
+  int n = c->n, nl = level + 1;
+  f128* re = (f128*)calloc(n, sizeof(f128)); f128* im = (f128*)calloc(n, sizeof(f128));
+  for (int k = 0; k < n; ++k) {
+    uint64_t r[MAXL];
+    for (int i = 0; i < nl; ++i) r[i] = poly[(size_t)i * n + k];
+    f128 pk = crt_centered(c, r, nl);
+    re[k] = pk * c->cw_re[k]; im[k] = pk * c->cw_im[k]; /* twist by zeta^k */
+  }
+  fft_quad(c, re, im, +1);
+  uint64_t e = 1, two_n = 2ull * n;
+  for (int64_t j = 0; j < n_vals && j < n / 2; ++j) {
+    out[j] = (double)(re[(e - 1) / 2] / (f128)delta);
+    e = (e * 5) % two_n;
+  }
+  free(re); free(im);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* keys                                                                                  */
+/* ------------------------------------------------------------------------------------ */
+/* switching key for target s': for digit j, (b_j, a_j) over all n_q + n_sp moduli.
+ * Hybrid key switching reading (the paper relies on a library for it): digits
+ * D_j = {q_{j*alpha}, ..., q_{min((j+1)alpha, n_q)-1}}; b_j = -a_j s + e_j + [P]_{q_i} s' 1{i in D_j}
+ * (mod q_i), b_j = -a_j s + e_j (mod p_k); a_j uniform mod each prime. */
+typedef struct {
+  uint64_t id;      /* 0 = relinearisation (s^2), otherwise the Galois element g */
+  uint64_t* data;   /* [digit][2 (b,a)][modulus][N] */
+} orc_swk;
+
+typedef struct {
+  const orc_ctx* c;
+  uint64_t seed;
+  int32_t* s;       /* ternary secret, N coefficients */
+  uint64_t* s_rns;  /* secret residues for all moduli [modulus][N] */
+  int n_keys;
+  orc_swk* keys;
+} orc_keys;
+
+static size_t swk_words(const orc_ctx* c) { return (size_t)c->dnum * 2 * (c->n_q + c->n_sp) * c->n; }
+static uint64_t* swk_ptr(const orc_ctx* c, const orc_swk* k, int j, int ba, int m) {
+  return k->data + (((size_t)j * 2 + ba) * (c->n_q + c->n_sp) + m) * c->n;
+}
+
+static void make_swk(const orc_ctx* c, const orc_keys* K, const int32_t* s_target, uint64_t id, orc_swk* out) {
+  int n = c->n, nm = c->n_q + c->n_sp;
+  out->id = id;
+  out->data = (uint64_t*)calloc(swk_words(c), 8);
+  /* P mod q_i */
+  for (int j = 0; j < c->dnum; ++j) {
+    uint32_t obj = (uint32_t)(id * 64 + (uint64_t)j);
+    int32_t* e = (int32_t*)malloc(4 * n);
+    for (int k = 0; k < n; ++k) e[k] = sample_gauss(K->seed, (uint32_t)k, obj, TAG_KEY_E);
+    #pragma omp parallel for schedule(dynamic)
+    for (int m = 0; m < nm; ++m) {
+      uint64_t q = c->mod[m];
+      uint64_t* b = swk_ptr(c, out, j, 0, m);
+      uint64_t* a = swk_ptr(c, out, j, 1, m);
+      for (int k = 0; k < n; ++k) a[k] = sample_uniform(K->seed, (uint32_t)k, (uint32_t)m, obj, TAG_KEY_A, q);
+      polymul(c, m, a, K->s_rns + (size_t)m * n, b); /* a*s */
+      for (int k = 0; k < n; ++k) b[k] = subm(smod(e[k], q), b[k], q); /* -a s + e */
+      if (m < c->n_q && m / c->alpha == j) {
+        uint64_t pmod = 1;
+        for (int t = 0; t < c->n_sp; ++t) pmod = mulm(pmod, c->mod[c->n_q + t] % q, q);
+        for (int k = 0; k < n; ++k) b[k] = addm(b[k], mulm(pmod, smod(s_target[k], q), q), q);
+      }
+    }
+    free(e);
+  }
+}
+
+/* integer (not reduced) products: s^2 and sigma_g(s) as integer polynomials */
+static void int_sq_secret(const orc_ctx* c, const int32_t* s, int32_t* out) {
+  /* negacyclic square of a ternary polynomial: |coeff| <= N, computed exactly with the
+   * first modulus (|value| < q/2) and centred. */
+  int n = c->n; uint64_t q = c->mod[0];
+  uint64_t* a = (uint64_t*)malloc(8 * n);
+  for (int k = 0; k < n; ++k) a[k] = smod(s[k], q);
+  polymul(c, 0, a, a, a);
+  for (int k = 0; k < n; ++k) out[k] = a[k] > q / 2 ? -(int32_t)(q - a[k]) : (int32_t)a[k];
+  free(a);
+}
+static void int_automorph(const orc_ctx* c, const int32_t* s, uint64_t g, int32_t* out) {
+  int n = c->n; uint64_t two_n = 2ull * n;
+  for (int k = 0; k < n; ++k) {
+    uint64_t e = ((uint64_t)k * g) % two_n;
+    if (e < (uint64_t)n) out[e] = s[k]; else out[e - n] = -s[k];
+  }
+}
+
+/* Key generation: secret s (tag sk), relinearisation key (id 0), Galois keys for the given
+ * Galois elements. */
+orc_keys* orc_keygen(const orc_ctx* c, uint64_t seed, const uint64_t* galois, int n_galois) {
+  int n = c->n, nm = c->n_q + c->n_sp;
+  orc_keys* K = (orc_keys*)calloc(1, sizeof(orc_keys));
+  K->c = c; K->seed = seed;
+  K->s = (int32_t*)malloc(4 * n);
+  for (int k = 0; k < n; ++k) K->s[k] = sample_ternary(seed, (uint32_t)k);
+  K->s_rns = (uint64_t*)malloc(8 * (size_t)nm * n);
+  for (int m = 0; m < nm; ++m)
+    for (int k = 0; k < n; ++k) K->s_rns[(size_t)m * n + k] = smod(K->s[k], c->mod[m]);
+  K->n_keys = 1 + n_galois;
+  K->keys = (orc_swk*)calloc(K->n_keys, sizeof(orc_swk));
+  int32_t* tgt = (int32_t*)malloc(4 * n);
+  int_sq_secret(c, K->s, tgt);
+  make_swk(c, K, tgt, 0, &K->keys[0]);
+  for (int i = 0; i < n_galois; ++i) {
+    int_automorph(c, K->s, galois[i], tgt);
+    make_swk(c, K, tgt, galois[i], &K->keys[1 + i]);
+  }
+  free(tgt);
+  return K;
+}
+void orc_keys_destroy(orc_keys* K) {
+  if (!K) return;
+  for (int i = 0; i < K->n_keys; ++i) free(K->keys[i].data);
+  free(K->keys); free(K->s); free(K->s_rns); free(K);
+}
+void orc_keys_secret(const orc_keys* K, int32_t* out) { memcpy(out, K->s, 4 * K->c->n); }
+/* copy out a switching key ([digit][2][modulus][N]); returns -1 if absent */
+int orc_keys_swk(const orc_keys* K, uint64_t id, uint64_t* out) {
+  for (int i = 0; i < K->n_keys; ++i)
+    if (K->keys[i].id == id) { memcpy(out, K->keys[i].data, 8 * swk_words(K->c)); return 0; }
+  return -1;
+}
+static const orc_swk* find_key(const orc_keys* K, uint64_t id) {
+  for (int i = 0; i < K->n_keys; ++i) if (K->keys[i].id == id) return &K->keys[i];
+  return NULL;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* encrypt / decrypt (secret-key form; the paper does not say which)                     */
+/* ------------------------------------------------------------------------------------ */
+/* ct = (-a s + e + pt, a) mod Q_level; a uniform per limb (tag enc-a), e Gaussian (tag
+ * enc-e), object id = ct_id.  pt: residues [limb][N]. ct: [2][limb][N]. */
+void orc_encrypt(const orc_keys* K, const uint64_t* pt, int level, uint64_t seed, uint32_t ct_id, uint64_t* ct) {
+  const orc_ctx* c = K->c; int n = c->n, nl = level + 1;
+  int32_t* e = (int32_t*)malloc(4 * n);
+  for (int k = 0; k < n; ++k) e[k] = sample_gauss(seed, (uint32_t)k, ct_id, TAG_ENC_E);
+  #pragma omp parallel for
+  for (int i = 0; i < nl; ++i) {
+    uint64_t q = c->mod[i];
+    uint64_t* c0 = ct + (size_t)i * n;
+    uint64_t* c1 = ct + ((size_t)nl + i) * n;
+    for (int k = 0; k < n; ++k) c1[k] = sample_uniform(seed, (uint32_t)k, (uint32_t)i, ct_id, TAG_ENC_A, q);
+    polymul(c, i, c1, K->s_rns + (size_t)i * n, c0);
+    for (int k = 0; k < n; ++k) c0[k] = addm(subm(smod(e[k], q), c0[k], q), pt[(size_t)i * n + k], q);
+  }
+  free(e);
+}
+/* m = c0 + c1 s (+ c2 s^2) ; degree = number of polys - 1 */
+void orc_decrypt(const orc_keys* K, const uint64_t* ct, int level, int degree, uint64_t* pt) {
+  const orc_ctx* c = K->c; int n = c->n, nl = level + 1;
+  #pragma omp parallel for
+  for (int i = 0; i < nl; ++i) {
+    uint64_t q = c->mod[i];
+    const uint64_t* s = K->s_rns + (size_t)i * n;
+    uint64_t* acc = pt + (size_t)i * n;
+    uint64_t* t = (uint64_t*)malloc(8 * n);
+    uint64_t* sp = (uint64_t*)malloc(8 * n);
+    memcpy(acc, ct + (size_t)i * n, 8 * n);
+    memcpy(sp, s, 8 * n);
+    for (int d = 1; d <= degree; ++d) {
+      polymul(c, i, ct + ((size_t)d * nl + i) * n, sp, t);
+      for (int k = 0; k < n; ++k) acc[k] = addm(acc[k], t[k], q);
+      if (d < degree) polymul(c, i, sp, s, sp);
+    }
+    free(t); free(sp);
+  }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* key switching, rotation, relinearisation, rescale                                     */
+/* ------------------------------------------------------------------------------------ */
+/* KeySwitch of d (coefficient form, limbs 0..level) with key `k`; if g != 1 the Galois
+ * automorphism sigma_g is applied to the extended digits after ModUp (hoisted order).
+ * Output u0, u1 at `level` ([limb][N] each).
+ *   ModUp (fast basis conversion, no centring), digit j over D = D_j cap {0..level}:
+ *     x_m = sum_{i in D} [d_i * (Q_D/q_i)^-1]_{q_i} * [(Q_D/q_i)]_m  (mod m)
+ *   inner product: u = sum_j x_j * (b_j, a_j) over {q_0..q_level} u {p_k}
+ *   ModDown (no centring): u_i <- (u_i - sum_k [u_{p_k} (P/p_k)^-1]_{p_k} [P/p_k]_{q_i}) * [P^-1]_{q_i} */
+static void key_switch(const orc_ctx* c, const orc_swk* key, const uint64_t* d, int level, uint64_t g,
+                       uint64_t* u0, uint64_t* u1) {
+  int n = c->n, nl = level + 1, nsp = c->n_sp;
+  int n_ext = nl + nsp;
+  int ext_mod[MAXL];
+  for (int i = 0; i < nl; ++i) ext_mod[i] = i;
+  for (int t = 0; t < nsp; ++t) ext_mod[nl + t] = c->n_q + t;
+  uint64_t* acc0 = (uint64_t*)calloc((size_t)n_ext * n, 8);
+  uint64_t* acc1 = (uint64_t*)calloc((size_t)n_ext * n, 8);
+  int n_digits = (nl + c->alpha - 1) / c->alpha;
+  for (int j = 0; j < n_digits; ++j) {
+    int lo = j * c->alpha, hi = (j + 1) * c->alpha; if (hi > nl) hi = nl;
+    /* per-digit CRT factors */
+    uint64_t qhat_inv[MAXL];
+    for (int i = lo; i < hi; ++i) {
+      uint64_t q = c->mod[i], prod = 1;
+      for (int i2 = lo; i2 < hi; ++i2) if (i2 != i) prod = mulm(prod, c->mod[i2] % q, q);
+      qhat_inv[i] = invm(prod, q);
+    }
+    #pragma omp parallel for schedule(dynamic)
+    for (int e = 0; e < n_ext; ++e) {
+      int m = ext_mod[e]; uint64_t mm = c->mod[m];
+      uint64_t* x = (uint64_t*)calloc(n, 8);
+      uint64_t* t = (uint64_t*)malloc(8 * n);
+      for (int i = lo; i < hi; ++i) {
+        uint64_t q = c->mod[i];
+        uint64_t qhat_m = 1; /* (Q_D / q_i) mod m */
+        for (int i2 = lo; i2 < hi; ++i2) if (i2 != i) qhat_m = mulm(qhat_m, c->mod[i2] % mm, mm);
+        const uint64_t* di = d + (size_t)i * n;
+        for (int k = 0; k < n; ++k) {
+          uint64_t y = mulm(di[k], qhat_inv[i], q);
+          x[k] = addm(x[k], mulm(y % mm, qhat_m, mm), mm);
+        }
+      }
+      if (g != 1) { automorph(c, m, x, g, t); memcpy(x, t, 8 * n); }
+      polymul(c, m, x, swk_ptr(c, key, j, 0, m), t);
+      for (int k = 0; k < n; ++k) acc0[(size_t)e * n + k] = addm(acc0[(size_t)e * n + k], t[k], mm);
+      polymul(c, m, x, swk_ptr(c, key, j, 1, m), t);
+      for (int k = 0; k < n; ++k) acc1[(size_t)e * n + k] = addm(acc1[(size_t)e * n + k], t[k], mm);
+      free(x); free(t);
+    }
+  }
+  /* ModDown */
+  uint64_t phat_inv[MAXL];
+  for (int t = 0; t < nsp; ++t) {
+    uint64_t p = c->mod[c->n_q + t], prod = 1;
+    for (int t2 = 0; t2 < nsp; ++t2) if (t2 != t) prod = mulm(prod, c->mod[c->n_q + t2] % p, p);
+    phat_inv[t] = invm(prod, p);
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    uint64_t* acc = pass == 0 ? acc0 : acc1;
+    uint64_t* u = pass == 0 ? u0 : u1;
+    #pragma omp parallel for
+    for (int i = 0; i < nl; ++i) {
+      uint64_t q = c->mod[i];
+      uint64_t pinv = 1, phat_q[MAXL];
+      for (int t = 0; t < nsp; ++t) pinv = mulm(pinv, c->mod[c->n_q + t] % q, q);
+      pinv = invm(pinv, q);
+      for (int t = 0; t < nsp; ++t) {
+        phat_q[t] = 1;
+        for (int t2 = 0; t2 < nsp; ++t2) if (t2 != t) phat_q[t] = mulm(phat_q[t], c->mod[c->n_q + t2] % q, q);
+      }
+      for (int k = 0; k < n; ++k) {
+        uint64_t corr = 0;
+        for (int t = 0; t < nsp; ++t) {
+          uint64_t p = c->mod[c->n_q + t];
+          uint64_t y = mulm(acc[((size_t)nl + t) * n + k], phat_inv[t], p);
+          corr = addm(corr, mulm(y % q, phat_q[t], q), q);
+        }
+        u[(size_t)i * n + k] = mulm(subm(acc[(size_t)i * n + k], corr, q), pinv, q);
+      }
+    }
+  }
+  free(acc0); free(acc1);
+}
+
+/* rotate left by `steps` slots: (sigma_g(c0) + u0, u1), (u0,u1) = KS_hoisted(c1) */
+int orc_rotate(const orc_keys* K, const uint64_t* ct, int level, int64_t steps, uint64_t* out) {
+  const orc_ctx* c = K->c; int n = c->n, nl = level + 1;
+  uint64_t g = galois_left(c, steps);
+  if (g == 1) { memcpy(out, ct, 8 * (size_t)2 * nl * n); return 0; }
+  const orc_swk* key = find_key(K, g);
+  if (!key) return -1;
+  uint64_t* u0 = (uint64_t*)malloc(8 * (size_t)nl * n);
+  uint64_t* u1 = (uint64_t*)malloc(8 * (size_t)nl * n);
+  key_switch(c, key, ct + (size_t)nl * n, level, g, u0, u1);
+  for (int i = 0; i < nl; ++i) {
+    uint64_t q = c->mod[i];
+    uint64_t* t = (uint64_t*)malloc(8 * n);
+    automorph(c, i, ct + (size_t)i * n, g, t);
+    for (int k = 0; k < n; ++k) out[(size_t)i * n + k] = addm(t[k], u0[(size_t)i * n + k], q);
+    memcpy(out + ((size_t)nl + i) * n, u1 + (size_t)i * n, 8 * n);
+    free(t);
+  }
+  free(u0); free(u1);
+  return 0;
+}
+
+/* relinearise (d0, d1, d2) -> (d0 + u0, d1 + u1), (u0,u1) = KS(d2) with the s^2 key */
+int orc_relinearize(const orc_keys* K, const uint64_t* ct3, int level, uint64_t* out) {
+  const orc_ctx* c = K->c; int n = c->n, nl = level + 1;
+  const orc_swk* key = find_key(K, 0);
+  if (!key) return -1;
+  uint64_t* u0 = (uint64_t*)malloc(8 * (size_t)nl * n);
+  uint64_t* u1 = (uint64_t*)malloc(8 * (size_t)nl * n);
+  key_switch(c, key, ct3 + (size_t)2 * nl * n, level, 1, u0, u1);
+  for (int i = 0; i < nl; ++i)
+    for (int k = 0; k < n; ++k) {
+      size_t o = (size_t)i * n + k;
+      out[o] = addm(ct3[o], u0[o], c->mod[i]);
+      out[(size_t)nl * n + o] = addm(ct3[(size_t)nl * n + o], u1[o], c->mod[i]);
+    }
+  free(u0); free(u1);
+  return 0;
+}
+
+/* Rescale (Preliminaries, "Rescaling"): c'_i = (c_i - [t]_{q_i}) * q_l^-1 mod q_i where t is the
+ * centred lift of the last limb; equals round(c / q_l) mod Q_{l-1}.  n_poly polys. */
+void orc_rescale(const orc_ctx* c, const uint64_t* ct, int level, int n_poly, uint64_t* out) {
+  int n = c->n, nl = level + 1;
+  uint64_t ql = c->mod[level];
+  for (int p = 0; p < n_poly; ++p)
+    for (int i = 0; i < level; ++i) {
+      uint64_t q = c->mod[i], inv = invm(ql % q, q);
+      const uint64_t* last = ct + ((size_t)p * nl + level) * n;
+      for (int k = 0; k < n; ++k) {
+        uint64_t v = last[k];
+        uint64_t tm = v <= ql / 2 ? v % q : subm(0, (ql - v) % q, q); /* centred lift mod q */
+        out[((size_t)p * level + i) * n + k] = mulm(subm(ct[((size_t)p * nl + i) * n + k], tm, q), inv, q);
+      }
+    }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* ciphertext-level helpers used by the schedules                                         */
+/* ------------------------------------------------------------------------------------ */
+/* acc += pt * ct  (pt: [limb][N], ct: [2][limb][N]) */
+static void mac_pt(const orc_ctx* c, uint64_t* acc, const uint64_t* pt, const uint64_t* ct, int nl) {
+  int n = c->n;
+  #pragma omp parallel for
+  for (int i = 0; i < 2 * nl; ++i) {
+    int limb = i % nl;
+    uint64_t q = c->mod[limb];
+    uint64_t* t = (uint64_t*)malloc(8 * n);
+    polymul(c, limb, pt + (size_t)limb * n, ct + (size_t)i * n, t);
+    for (int k = 0; k < n; ++k) acc[(size_t)i * n + k] = addm(acc[(size_t)i * n + k], t[k], q);
+    free(t);
+  }
+}
+static void add_ct(const orc_ctx* c, uint64_t* acc, const uint64_t* x, int nl, int n_poly) {
+  int n = c->n;
+  for (int p = 0; p < n_poly; ++p)
+    for (int i = 0; i < nl; ++i)
+      for (int k = 0; k < n; ++k) {
+        size_t o = ((size_t)p * nl + i) * n + k;
+        acc[o] = addm(acc[o], x[o], c->mod[i]);
+      }
+}
+
+static int ceil_log2(int64_t v) { int r = 0; while ((1ll << r) < v) ++r; return r; }
+
+/* ------------------------------------------------------------------------------------ */
+/* matmul_cp (pinned schedule)                                                           */
+/* ------------------------------------------------------------------------------------ */
+/* Geometry of the spatial-first packing ("Consistent Packing for Single Operator"): element
+ * (i, j) of an L x D matrix sits in ciphertext j / c at slot i + L' * (j mod c), L' = 2^ceil(log2 L),
+ * c = S / L'.  When D' * L' < S (D' = 2^ceil(log2 D)) the D' columns are replicated c / D' times. */
+void orc_cp_geometry(const orc_ctx* c, int L, int d_in, int d_out, int32_t* out /* [8] */) {
+  int s = c->n / 2;
+  int lp = 1 << ceil_log2(L);
+  int cc = s / lp;
+  int din_p = 1 << ceil_log2(d_in), dout_p = 1 << ceil_log2(d_out);
+  int c_eff = cc < din_p ? cc : din_p;
+  int c_out = cc < dout_p ? cc : dout_p;
+  int n_in = (d_in + cc - 1) / cc, n_out = (d_out + cc - 1) / cc;
+  int b = 1 << ((ceil_log2(c_eff) + 1) / 2);
+  int g = c_eff / b;
+  out[0] = lp; out[1] = cc; out[2] = c_eff; out[3] = c_out; out[4] = n_in; out[5] = n_out; out[6] = b; out[7] = g;
+}
+
+/* spatial-first slot vector of ciphertext a (length S) for an L x D row-major matrix */
+void orc_pack_spatial(const orc_ctx* c, const double* X, int L, int D, int a, double* out) {
+  int32_t g[8]; orc_cp_geometry(c, L, D, D, g);
+  int lp = g[0], cc = g[1];
+  int dp = 1 << ceil_log2(D);
+  int s = c->n / 2;
+  for (int slot = 0; slot < s; ++slot) {
+    int i = slot % lp, u = slot / lp;
+    int col = (dp < cc) ? (u % dp) : a * cc + u;
+    out[slot] = (i < L && col < D) ? X[(size_t)i * D + col] : 0.0;
+  }
+}
+
+/* Y_b = rescale( sum_{j<G} Rot_l^{jBL'}( sum_a sum_{i<B} Encode_{q_l}(Rot_r^{jBL'}(d_{a,b,jB+i})) * Rot_l^{iL'}(X_a) ) )
+ * with d_{a,b,t}[u L' + i] = W{a c + ((u + t) mod c_eff), b c + (u mod c_out)} (0 out of range).
+ * Inputs X: n_in cts at `level` ([ct][2][limb][N]); W: d_in x d_out row-major.  Outputs
+ * Y: n_out cts at level-1 ([ct][2][level][N]).  out_mask selects which outputs to compute
+ * (NULL = all; skipped outputs are left untouched).  Returns 0, or -1 on a missing key. */
+int orc_matmul_cp(const orc_keys* K, const uint64_t* X, int level, const double* W, int L, int d_in, int d_out,
+                  const uint8_t* out_mask, uint64_t* Y) {
+  const orc_ctx* c = K->c;
+  int n = c->n, s = n / 2, nl = level + 1;
+  int32_t g[8]; orc_cp_geometry(c, L, d_in, d_out, g);
+  int lp = g[0], cc = g[1], c_eff = g[2], c_out = g[3], n_in = g[4], n_out = g[5], B = g[6], G = g[7];
+  size_t ctw = (size_t)2 * nl * n;
+  double delta_w = (double)c->mod[level];
+  /* baby steps: Rot_l^{iL'}(X_a) */
+  uint64_t* rx = (uint64_t*)malloc(8 * ctw * (size_t)n_in * B);
+  for (int a = 0; a < n_in; ++a)
+    for (int i = 0; i < B; ++i)
+      if (orc_rotate(K, X + ctw * a, level, (int64_t)i * lp, rx + ctw * ((size_t)a * B + i)) != 0) { free(rx); return -1; }
+  double* vec = (double*)malloc(8 * s);
+  double* vrot = (double*)malloc(8 * s);
+  uint64_t* pt = (uint64_t*)malloc(8 * (size_t)nl * n);
+  uint64_t* inner = (uint64_t*)malloc(8 * ctw);
+  uint64_t* rot = (uint64_t*)malloc(8 * ctw);
+  uint64_t* acc = (uint64_t*)malloc(8 * ctw);
+  int rc = 0;
+  for (int b = 0; b < n_out && rc == 0; ++b) {
+    if (out_mask && !out_mask[b]) continue;
+    memset(acc, 0, 8 * ctw);
+    for (int j = 0; j < G && rc == 0; ++j) {
+      memset(inner, 0, 8 * ctw);
+      for (int a = 0; a < n_in; ++a)
+        for (int i = 0; i < B; ++i) {
+          int t = j * B + i;
+          for (int slot = 0; slot < s; ++slot) {
+            int u = slot / lp;
+            int row = a * cc + (u + t) % c_eff, col = b * cc + u % c_out;
+            vec[slot] = (row < d_in && col < d_out) ? W[(size_t)row * d_out + col] : 0.0;
+          }
+          int r = j * B * lp; /* Rot_r^r: out[slot] = in[slot - r] */
+          for (int slot = 0; slot < s; ++slot) vrot[slot] = vec[((slot - r) % s + s) % s];
+          orc_encode_rns(c, vrot, s, delta_w, level, pt);
+          mac_pt(c, inner, pt, rx + ctw * ((size_t)a * B + i), nl);
+        }
+      if (j == 0) add_ct(c, acc, inner, nl, 2);
+      else {
+        if (orc_rotate(K, inner, level, (int64_t)j * B * lp, rot) != 0) { rc = -1; break; }
+        add_ct(c, acc, rot, nl, 2);
+      }
+    }
+    if (rc == 0) orc_rescale(c, acc, level, 2, Y + (size_t)b * 2 * level * n);
+  }
+  free(rx); free(vec); free(vrot); free(pt); free(inner); free(rot); free(acc);
+  return rc;
+}
+
+/* Galois elements needed by matmul_cp at this geometry (baby and giant steps) */
+int orc_cp_galois(const orc_ctx* c, int L, int d_in, int d_out, uint64_t* out) {
+  int32_t g[8]; orc_cp_geometry(c, L, d_in, d_out, g);
+  int lp = g[0], B = g[6], G = g[7], cnt = 0;
+  for (int i = 1; i < B; ++i) out[cnt++] = galois_left(c, (int64_t)i * lp);
+  for (int j = 1; j < G; ++j) out[cnt++] = galois_left(c, (int64_t)j * B * lp);
+  return cnt;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* CKKS-to-MPC mask-and-share (Algorithm ckks2mpc step 1; F_C2M item 1)                   */
+/* ------------------------------------------------------------------------------------ */
+/* r ~ U(R_{Q_l}) in the coefficient domain, one independent uniform residue per limb
+ * (uniform mod Q_l by CRT); masked = (c0 + r, c1); share_1 = -r mod q_i.  If
+ * target_level < level the ciphertext is first reduced to target_level (top limbs dropped).
+ * ct: [2][level+1][N] in; masked: [2][target+1][N]; share: [target+1][N]. */
+void orc_mask_to_share(const orc_ctx* c, const uint64_t* ct, int level, int target_level, uint64_t seed, uint32_t ct_id,
+                       uint64_t* masked, uint64_t* share) {
+  int n = c->n, nl = level + 1, tl = target_level + 1;
+  for (int i = 0; i < tl; ++i) {
+    uint64_t q = c->mod[i];
+    for (int k = 0; k < n; ++k) {
+      uint64_t r = sample_uniform(seed, (uint32_t)k, (uint32_t)i, ct_id, TAG_MASK, q);
+      masked[(size_t)i * n + k] = addm(ct[(size_t)i * n + k], r, q);
+      masked[((size_t)tl + i) * n + k] = ct[((size_t)nl + i) * n + k];
+      share[(size_t)i * n + k] = (q - r) % q;
+    }
+  }
+}

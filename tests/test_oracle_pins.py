@@ -1,0 +1,513 @@
+"""Pins of the CPU oracle against facts fixed outside it: published known-answer vectors,
+closed forms, invariants, brute force on tiny rings and plain numpy/mpmath definitions.
+
+Each test names the mistake class it is meant to catch.  None of these tests touches the
+GPU or the HIP library.
+"""
+import os
+
+import mpmath
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# --------------------------------------------------------------------------------------
+# independent Python helpers (big integers, written from the definitions)
+# --------------------------------------------------------------------------------------
+def _is_prime(n):
+    if n < 2:
+        return False
+    for p in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37):
+        if n % p == 0:
+            return n == p
+    d, s = n - 1, 0
+    while d % 2 == 0:
+        d //= 2
+        s += 1
+    for a in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37):
+        x = pow(a, d, n)
+        if x in (1, n - 1):
+            continue
+        for _ in range(s - 1):
+            x = x * x % n
+            if x == n - 1:
+                break
+        else:
+            return False
+    return True
+
+
+def schoolbook_negacyclic(a, b, q):
+    n = len(a)
+    r = [0] * n
+    for i in range(n):
+        ai = int(a[i])
+        for j in range(n):
+            k = i + j
+            v = ai * int(b[j])
+            if k >= n:
+                r[k - n] -= v
+            else:
+                r[k] += v
+    return [x % q for x in r]
+
+
+def crt_lift_centered(residues, moduli):
+    Q = 1
+    for m in moduli:
+        Q *= int(m)
+    x = 0
+    for r, m in zip(residues, moduli):
+        m = int(m)
+        Mi = Q // m
+        x += int(r) * Mi * pow(Mi, -1, m)
+    x %= Q
+    return x - Q if x > Q // 2 else x
+
+
+def centered(v, q):
+    v = int(v) % q
+    return v - q if v > q // 2 else v
+
+
+# --------------------------------------------------------------------------------------
+# primes and Philox
+# --------------------------------------------------------------------------------------
+@pytest.mark.parametrize("log_n,count", [(12, 3), (13, 4), (14, 6)])
+def test_prime_rule(orc, log_n, count):
+    """Primes are the largest q = k*2N+1 < 2^50, scanned downward (catches an off-by-one
+    in the scan start, a non-prime, a wrong congruence or a skipped prime)."""
+    got = [int(x) for x in orc.primes(log_n, count)]
+    two_n = 2 << log_n
+    want, k = [], ((1 << 50) - 2) // two_n
+    while len(want) < count:
+        q = k * two_n + 1
+        if _is_prime(q):
+            want.append(q)
+        k -= 1
+    assert got == want
+    for q in got:
+        assert q < (1 << 50) and q % two_n == 1
+
+
+def test_prime_values_hand_checked(orc):
+    """The first primes for N = 4096 / 8192 / 16384, checked by hand outside the oracle."""
+    assert [hex(int(x)) for x in orc.primes(12, 3)] == ["0x3ffffffffc001", "0x3fffffffcc001", "0x3fffffff9a001"]
+    assert [hex(int(x)) for x in orc.primes(13, 4)] == ["0x3ffffffffc001", "0x3fffffffcc001", "0x3ffffffef4001",
+                                                        "0x3ffffffe94001"]
+    assert [hex(int(x)) for x in orc.primes(14, 6)] == ["0x3ffffffdf0001", "0x3ffffffd48001", "0x3ffffffd20001",
+                                                        "0x3ffffffd18001", "0x3ffffffcd0001", "0x3ffffffc70001"]
+
+
+def test_philox_known_answers(orc):
+    """Philox4x32-10 against the published Random123 known-answer vectors."""
+    rows = [l.split() for l in open(os.path.join(HERE, "golden", "philox4x32_10_kat.txt")) if l.strip() and l[0] != "#"]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        out = orc.philox4x32_10(v[0:4], v[4:6])
+        assert [int(x) for x in out] == v[6:10]
+
+
+def test_gaussian_cdt_matches_mpmath(orc):
+    """CDT thresholds floor(2^63 P(|x| <= k)) of the discrete Gaussian sigma = 3.2 on |x| <= 19,
+    recomputed with mpmath at 60 digits (catches a wrong sigma, a missing factor 2 for +-x,
+    or a normalisation over the wrong support)."""
+    mpmath.mp.dps = 60
+    sigma = mpmath.mpf("3.2")
+    rho = [mpmath.e ** (-(mpmath.mpf(x) ** 2) / (2 * sigma ** 2)) for x in range(20)]
+    z = rho[0] + 2 * sum(rho[1:])
+    cum, want = mpmath.mpf(0), []
+    for x in range(20):
+        cum += (1 if x == 0 else 2) * rho[x] / z
+        want.append(min(int(mpmath.floor(cum * 2 ** 63)), 2 ** 63 - 1))
+    want[19] = 2 ** 63 - 1
+    got = [int(v) for v in orc.cdt_table()]
+    assert got == want
+
+
+def test_samplers_statistics(orc):
+    """Uniform mod q (chi^2 over 16 buckets), ternary frequencies, Gaussian variance."""
+    q = int(orc.primes(13, 1)[0])
+    n = 1 << 16
+    u = orc.sample_uniform(7, 0, 0, orc.TAG_MASK, q, n).astype(object)
+    assert all(0 <= int(x) < q for x in u[:1000])
+    buckets = np.bincount([int(x) * 16 // q for x in u], minlength=16)
+    chi2 = float(((buckets - n / 16) ** 2 / (n / 16)).sum())
+    assert chi2 < 45.0  # 15 dof, p ~ 1e-4
+    t = orc.sample_ternary(11, n)
+    freq = np.bincount(t + 1, minlength=3) / n
+    assert np.all(np.abs(freq - 1 / 3) < 0.01)
+    g = orc.sample_gauss(13, 0, orc.TAG_ENC_E, n).astype(np.float64)
+    assert abs(g.mean()) < 0.05
+    assert abs(g.std() - 3.2) < 0.05
+    assert np.abs(g).max() <= 19
+    # different tags / objects give different streams
+    assert not np.array_equal(orc.sample_gauss(13, 1, orc.TAG_ENC_E, 64), orc.sample_gauss(13, 0, orc.TAG_ENC_E, 64))
+
+
+# --------------------------------------------------------------------------------------
+# ring arithmetic
+# --------------------------------------------------------------------------------------
+@pytest.mark.parametrize("log_n", [2, 4, 6])
+def test_polymul_equals_schoolbook(orc, log_n):
+    """Ring product via the textbook NTT equals the negacyclic schoolbook convolution
+    (catches a cyclic instead of negacyclic wrap, a wrong twist or a missing 1/N)."""
+    c = orc.Context(log_n, 2, 1, 1)
+    rng = np.random.default_rng(log_n)
+    for m in range(3):
+        q = int(c.moduli[m])
+        a = rng.integers(0, q, c.n, dtype=np.uint64)
+        b = rng.integers(0, q, c.n, dtype=np.uint64)
+        assert [int(x) for x in c.polymul(m, a, b)] == schoolbook_negacyclic(a, b, q)
+        assert np.array_equal(c.ntt_inverse(m, c.ntt_forward(m, a)), a)
+
+
+def test_polymul_full_size_sampled(orc):
+    """At N = 8192, sampled coefficients of the product equal the O(N) convolution sum."""
+    c = orc.Context(13, 1, 0, 1)
+    q = int(c.moduli[0])
+    rng = np.random.default_rng(3)
+    a = rng.integers(0, q, c.n, dtype=np.uint64)
+    b = rng.integers(0, q, c.n, dtype=np.uint64)
+    r = c.polymul(0, a, b)
+    ai = [int(x) for x in a]
+    bi = [int(x) for x in b]
+    n = c.n
+    for k in [0, 1, 77, n // 2, n - 1]:
+        s = 0
+        for i in range(n):
+            j = k - i
+            s += ai[i] * bi[j] if j >= 0 else -ai[i] * bi[j + n]
+        assert int(r[k]) == s % q
+
+
+def test_ntt_evaluates_at_odd_powers(orc):
+    """The forward transform is evaluation at psi^(2t+1): the product of two transforms is
+    the transform of the product, and the all-ones polynomial's transform at t matches a
+    geometric series (catches an ordering mistake in the textbook NTT)."""
+    c = orc.Context(4, 1, 0, 1)
+    q = int(c.moduli[0])
+    x = np.zeros(c.n, np.uint64)
+    x[1] = 1  # X
+    fx = [int(v) for v in c.ntt_forward(0, x)]  # values psi^(2t+1)
+    psi = fx[0]
+    assert pow(psi, 2 * c.n, q) == 1 and pow(psi, c.n, q) == q - 1
+    for t in range(c.n):
+        assert fx[t] == pow(psi, 2 * t + 1, q)
+
+
+def test_automorphism_definition_and_group(orc):
+    """sigma_g maps X^k to X^(kg mod 2N) with a sign flip past N; sigma_g o sigma_h = sigma_gh;
+    5 has order N/2 modulo 2N."""
+    c = orc.Context(5, 1, 0, 1)
+    q = int(c.moduli[0])
+    n = c.n
+    rng = np.random.default_rng(1)
+    a = rng.integers(0, q, n, dtype=np.uint64)
+    g, h = 5, 2 * n - 1
+    ra = c.automorphism(0, a, g)
+    want = [0] * n
+    for k in range(n):
+        e = k * g % (2 * n)
+        if e < n:
+            want[e] = int(a[k])
+        else:
+            want[e - n] = (-int(a[k])) % q
+    assert [int(x) for x in ra] == want
+    assert np.array_equal(c.automorphism(0, c.automorphism(0, a, h), g), c.automorphism(0, a, g * h % (2 * n)))
+    assert pow(5, n // 2, 2 * n) == 1 and all(pow(5, t, 2 * n) != 1 for t in range(1, n // 2))
+    assert c.galois_elt(3) == pow(5, 3, 2 * n)
+    assert c.galois_elt(-1) == pow(5, n // 2 - 1, 2 * n)
+
+
+# --------------------------------------------------------------------------------------
+# encode / decode (eq. ckks_encode)
+# --------------------------------------------------------------------------------------
+def test_encode_constant_vector(orc):
+    """A constant slot vector encodes to the constant polynomial (c*Delta, 0, ..., 0):
+    sum_j cos(pi e_j k / N) vanishes for 0 < k < N because {+-e_j} are all odd residues."""
+    c = orc.Context(10, 1, 0, 1)
+    for val, delta in [(0.75, 2.0 ** 30), (-1.25, 2.0 ** 40), (3.0, 2.0 ** 20)]:
+        p = c.encode(np.full(c.slots, val), delta)
+        assert int(p[0]) == int(round(val * delta))
+        assert not p[1:].any()
+
+
+@pytest.mark.parametrize("log_n", [3, 4, 5])
+def test_encode_matches_direct_formula(orc, log_n):
+    """At tiny N the encoding equals the direct formula
+    p_k = round_half_away((2 Delta / N) sum_j m_j cos(pi 5^j k / N)) evaluated in mpmath."""
+    mpmath.mp.dps = 50
+    c = orc.Context(log_n, 1, 0, 1)
+    n, s = c.n, c.slots
+    rng = np.random.default_rng(log_n)
+    m = rng.normal(0, 1, s)
+    delta = 2.0 ** 40
+    got = c.encode(m, delta)
+    for k in range(n):
+        acc = mpmath.mpf(0)
+        for j in range(s):
+            acc += mpmath.mpf(m[j]) * mpmath.cos(mpmath.pi * (pow(5, j, 2 * n) * k) / n)
+        v = 2 * mpmath.mpf(delta) / n * acc
+        r = int(mpmath.floor(abs(v) + mpmath.mpf("0.5")))
+        assert int(got[k]) == (r if v >= 0 else -r)
+
+
+def test_decode_inverts_encode(orc):
+    """Decode(Encode(m)) = m within the rounding bound (no rounding before pi): each slot error is
+    Delta^-1 sum_k eps_k cos(.), |eps_k| <= 1/2, so it is below N/(2 Delta) always and, with
+    eps_k uniform (variance 1/12), below 8 sqrt(N/24)/Delta in practice."""
+    c = orc.Context(13, 3, 0, 1)
+    rng = np.random.default_rng(2)
+    m = rng.normal(0, 1, c.slots)
+    delta = 2.0 ** 40
+    pt = c.encode_rns(m, delta, 2)
+    err = np.abs(c.decode(pt, 2, delta) - m).max()
+    assert err < c.n / (2 * delta)
+    assert err < 8 * np.sqrt(c.n / 24) / delta
+    # decode of the direct-formula definition at tiny N
+    ct = orc.Context(4, 2, 0, 1)
+    mm = rng.normal(0, 1, ct.slots)
+    p = ct.encode_rns(mm, 2.0 ** 30, 1)
+    lift = [crt_lift_centered([p[0, k], p[1, k]], ct.moduli[:2]) for k in range(ct.n)]
+    for j in range(ct.slots):
+        v = sum(lift[k] * np.cos(np.pi * pow(5, j, 2 * ct.n) * k / ct.n) for k in range(ct.n)) / 2.0 ** 30
+        assert abs(ct.decode(p, 1, 2.0 ** 30)[j] - v) < 1e-9
+
+
+def test_crt_centered_matches_bigint(orc):
+    c = orc.Context(4, 4, 0, 1)
+    rng = np.random.default_rng(9)
+    for level in range(4):
+        poly = np.stack([rng.integers(0, int(c.moduli[i]), c.n, dtype=np.uint64) for i in range(level + 1)])
+        got = c.crt_centered(poly, level)
+        for k in range(c.n):
+            want = crt_lift_centered(poly[:, k], c.moduli[: level + 1])
+            assert abs(got[k] - float(want)) <= abs(float(want)) * 1e-15 + 1e-9
+
+
+# --------------------------------------------------------------------------------------
+# encryption, keys, key switching, rescale
+# --------------------------------------------------------------------------------------
+def test_encrypt_decrypt_exact_error(orc):
+    """Dec(Enc(pt)) - pt equals exactly the Gaussian sample e drawn for (seed, ct_id, enc-e)
+    (catches a sign error in -a*s, a wrong tag, or per-limb instead of per-coefficient e)."""
+    c = orc.Context(11, 3, 1, 3)
+    k = orc.Keys(c, 5)
+    rng = np.random.default_rng(0)
+    pt = np.stack([rng.integers(0, int(q), c.n, dtype=np.uint64) for q in c.q])
+    ct = k.encrypt(pt, 2, 42, 7)
+    e = orc.sample_gauss(42, 7, orc.TAG_ENC_E, c.n)
+    d = k.decrypt(ct, 2)
+    for i, q in enumerate(c.q):
+        q = int(q)
+        diff = (d[i].astype(object) - pt[i].astype(object)) % q
+        assert [centered(x, q) for x in diff] == [int(x) for x in e]
+    # c1 is the uniform sample of tag enc-a for each limb
+    assert np.array_equal(ct[1, 1], orc.sample_uniform(42, 1, 7, orc.TAG_ENC_A, int(c.q[1]), c.n))
+
+
+def test_switching_key_structure(orc):
+    """b_j + a_j s - [P]_{q_i} s' 1{i in D_j} equals the digit's Gaussian error exactly, on every
+    modulus (catches a missing P factor, a wrong digit partition or an s' mix-up)."""
+    c = orc.Context(6, 4, 2, 2)
+    g = c.galois_elt(1)
+    k = orc.Keys(c, 77, [g])
+    s = [int(x) for x in k.secret]
+    n = c.n
+    # s' for the rotation key: sigma_g(s) over the integers
+    sp = [0] * n
+    for i in range(n):
+        e = i * g % (2 * n)
+        if e < n:
+            sp[e] = s[i]
+        else:
+            sp[e - n] = -s[i]
+    P = int(c.p[0]) * int(c.p[1])
+    swk = k.switching_key(g)
+    for j in range(c.dnum):
+        e = [int(x) for x in orc.sample_gauss(77, g * 64 + j, orc.TAG_KEY_E, n)]
+        for m in range(6):
+            q = int(c.moduli[m])
+            b = [int(x) for x in swk[j, 0, m]]
+            a = [int(x) for x in swk[j, 1, m]]
+            as_ = schoolbook_negacyclic(a, [x % q for x in s], q)
+            in_digit = m < 4 and m // c.alpha == j
+            for i in range(n):
+                v = (b[i] + as_[i] - (P * sp[i] if in_digit else 0)) % q
+                assert centered(v, q) == e[i]
+
+
+def _noise(ctx, diff, level):
+    """max |centred CRT lift| of a polynomial given by residues"""
+    lift = ctx.crt_centered(diff, level)
+    return np.abs(lift).max()
+
+
+@pytest.mark.parametrize("params", [(11, 3, 1, 3), (11, 4, 2, 2)])
+def test_rotation_keyswitch_invariant(orc, params):
+    """Dec(Rot_g(ct)) - sigma_g(Dec(ct)) has a small centred norm at every level: the hybrid key
+    switch (ModUp, hoisted automorphism, inner product, ModDown) adds only error of order
+    N*sigma*Q_digit/P (catches a wrong ModUp factor, a wrong ModDown sign or P^-1, or a
+    rotation applied before ModUp with the wrong key)."""
+    log_n, n_q, n_sp, dnum = params
+    c = orc.Context(log_n, n_q, n_sp, dnum)
+    gal = [c.galois_elt(1), c.galois_elt(-3)]
+    k = orc.Keys(c, 3, gal)
+    rng = np.random.default_rng(1)
+    m = rng.normal(0, 1, c.slots)
+    for level in range(n_q - 1, -1, -1):
+        delta = 2.0 ** 30
+        ct = k.encrypt(c.encode_rns(m, delta, level), level, 1000 + level, 0)
+        for steps, g in [(1, gal[0]), (-3, gal[1])]:
+            r = k.rotate(ct, level, steps)
+            d_rot = k.decrypt(r, level)
+            d = k.decrypt(ct, level)
+            sd = np.stack([c.automorphism(i, d[i], g) for i in range(level + 1)])
+            diff = np.stack([(d_rot[i].astype(object) - sd[i].astype(object)) % int(c.q[i]) for i in range(level + 1)]).astype(np.uint64)
+            assert _noise(c, diff, level) < 2.0 ** 30  # vs Q >= 2^49
+            dec = c.decode(d_rot, level, delta)
+            assert np.abs(dec - np.roll(m, -steps)).max() < 1e-3
+
+
+def test_relinearize_invariant(orc):
+    """Relin(d0, d1, d2) decrypts like (d0, d1, d2) under (1, s, s^2) up to key-switch noise."""
+    c = orc.Context(11, 3, 1, 3)
+    k = orc.Keys(c, 8)
+    rng = np.random.default_rng(4)
+    level = 2
+    m1, m2 = rng.normal(0, 1, c.slots), rng.normal(0, 1, c.slots)
+    a = k.encrypt(c.encode_rns(m1, 2.0 ** 30, level), level, 1, 0)
+    b = k.encrypt(c.encode_rns(m2, 2.0 ** 30, level), level, 2, 0)
+    ct3 = np.zeros((3, level + 1, c.n), np.uint64)
+    for i in range(level + 1):
+        q = int(c.q[i])
+        ct3[0, i] = c.polymul(i, a[0, i], b[0, i])
+        t1 = c.polymul(i, a[0, i], b[1, i]).astype(object) + c.polymul(i, a[1, i], b[0, i]).astype(object)
+        ct3[1, i] = (t1 % q).astype(np.uint64)
+        ct3[2, i] = c.polymul(i, a[1, i], b[1, i])
+    r = k.relinearize(ct3, level)
+    d3 = k.decrypt(ct3, level)
+    d2 = k.decrypt(r, level)
+    diff = np.stack([(d2[i].astype(object) - d3[i].astype(object)) % int(c.q[i]) for i in range(level + 1)]).astype(np.uint64)
+    assert _noise(c, diff, level) < 2.0 ** 30
+    dec = c.decode(d2, level, 2.0 ** 60)
+    assert np.abs(dec - m1 * m2).max() < 1e-3
+
+
+@pytest.mark.parametrize("log_n", [3, 10])
+def test_rescale_equals_rounded_division(orc, log_n):
+    """Rescale equals round(c~ / q_l) mod Q_{l-1} for the CRT lift c~ in [0, Q_l) (any lift gives
+    the same result because q_l is odd)."""
+    c = orc.Context(log_n, 3, 0, 1)
+    rng = np.random.default_rng(log_n)
+    level = 2
+    ct = np.stack([np.stack([rng.integers(0, int(q), c.n, dtype=np.uint64) for q in c.q]) for _ in range(2)])
+    out = c.rescale(ct, level)
+    Q = int(c.q[0]) * int(c.q[1]) * int(c.q[2])
+    ql = int(c.q[2])
+    for p in range(2):
+        for kk in range(0, c.n, max(1, c.n // 64)):
+            x = crt_lift_centered(ct[p, :, kk], c.q) % Q
+            r = (2 * x + ql) // (2 * ql)  # round half up; no ties since q_l is odd
+            for i in range(2):
+                assert int(out[p, i, kk]) == r % int(c.q[i])
+
+
+# --------------------------------------------------------------------------------------
+# matmul_cp and mask-to-share
+# --------------------------------------------------------------------------------------
+def _unpack(ctx, g, vecs, L, D):
+    out = np.zeros((L, D))
+    for col in range(D):
+        b, u = divmod(col, g["c"]) if g["c_out"] == g["c"] else (0, col)
+        out[:, col] = vecs[b][u * g["Lp"]: u * g["Lp"] + L]
+    return out
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 32), (20, 40, 24), (5, 96, 70)])
+def test_matmul_cp_decodes_to_fp64_matmul(orc, shape):
+    """Decoded matmul_cp output equals X @ W (FP64) within 2^-10 at Delta = 2^30, including
+    ragged L, D_in, D_out and replicated packings."""
+    L, d_in, d_out = shape
+    c = orc.Context(12, 2, 1, 2)
+    rng = np.random.default_rng(sum(shape))
+    X = rng.uniform(-1, 1, (L, d_in))
+    W = rng.normal(0, 0.02, (d_in, d_out))
+    g = c.cp_geometry(L, d_in, d_out)
+    k = orc.Keys(c, 9, c.cp_galois(L, d_in, d_out))
+    cts = np.stack([k.encrypt(c.encode_rns(c.pack_spatial(X, a), 2.0 ** 30, 1), 1, 100, a) for a in range(g["n_in"])])
+    Y = k.matmul_cp(cts, 1, W, L)
+    vecs = [c.decode(k.decrypt(Y[b], 0), 0, 2.0 ** 30) for b in range(g["n_out"])]
+    got = _unpack(c, g, vecs, L, d_out)
+    assert np.abs(got - X @ W).max() < 2.0 ** -10
+    # rows >= L of the output block are (near) zero, replicated blocks agree
+    if g["c_out"] < g["c"]:
+        v = vecs[0]
+        assert np.abs(v[: g["Lp"] * g["c_out"]] - v[g["Lp"] * g["c_out"]: 2 * g["Lp"] * g["c_out"]]).max() < 2.0 ** -10
+
+
+def test_matmul_cp_identity_and_counts(orc):
+    """W = I gives back X; BSGS geometry for the BERT-base shape gives B = 8, G = 4 and
+    n_in (B-1) + n_out (G-1) = 240 rotations on 10 Galois keys."""
+    c = orc.Context(12, 2, 1, 2)
+    L, D = 32, 64
+    rng = np.random.default_rng(0)
+    X = rng.uniform(-1, 1, (L, D))
+    g = c.cp_geometry(L, D, D)
+    k = orc.Keys(c, 9, c.cp_galois(L, D, D))
+    cts = np.stack([k.encrypt(c.encode_rns(c.pack_spatial(X, a), 2.0 ** 30, 1), 1, 100, a) for a in range(g["n_in"])])
+    Y = k.matmul_cp(cts, 1, np.eye(D), L)
+    vecs = [c.decode(k.decrypt(Y[b], 0), 0, 2.0 ** 30) for b in range(g["n_out"])]
+    assert np.abs(_unpack(c, g, vecs, L, D) - X).max() < 2.0 ** -12
+    c2 = orc.Context(13, 3, 1, 3)
+    g2 = c2.cp_geometry(128, 768, 768)
+    assert (g2["Lp"], g2["c"], g2["c_eff"], g2["n_in"], g2["n_out"], g2["B"], g2["G"]) == (128, 32, 32, 24, 24, 8, 4)
+    assert g2["n_in"] * (g2["B"] - 1) + g2["n_out"] * (g2["G"] - 1) == 240
+    assert len(c2.cp_galois(128, 768, 768)) == 10
+    # modular multiplications of the plaintext MACs: 2 polys * n_q limbs * N per plaintext
+    n_pt = g2["n_in"] * g2["n_out"] * g2["c_eff"]
+    assert n_pt == 18432
+    assert n_pt * 2 * 3 * 8192 == 905969664
+
+
+def test_mask_to_share_identity_and_uniformity(orc):
+    """Dec(masked) + share == Dec(ct) (mod Q) word for word; Dec(masked) is uniform (chi^2 on
+    its top bits); the share is -r for the mask stream of (seed, ct_id)."""
+    c = orc.Context(12, 3, 1, 3)
+    k = orc.Keys(c, 4)
+    rng = np.random.default_rng(7)
+    m = rng.normal(0, 1, c.slots)
+    ct = k.encrypt(c.encode_rns(m, 2.0 ** 40, 2), 2, 5, 0)
+    for target in (2, 1):
+        masked, share = c.mask_to_share(ct, 2, target, 99, 3)
+        d_m = k.decrypt(masked, target)
+        d = k.decrypt(ct, 2)[: target + 1]
+        for i in range(target + 1):
+            q = int(c.q[i])
+            assert np.array_equal((d_m[i].astype(object) + share[i].astype(object)) % q, d[i].astype(object))
+            r = orc.sample_uniform(99, i, 3, orc.TAG_MASK, q, c.n)
+            assert np.array_equal(share[i], ((q - r.astype(object)) % q).astype(np.uint64))
+            top = (d_m[i].astype(object) * 16 // q).astype(np.int64)
+            cnt = np.bincount(top, minlength=16)
+            chi2 = float(((cnt - c.n / 16) ** 2 / (c.n / 16)).sum())
+            assert chi2 < 45.0
+
+
+def test_encoded_mask_concentration_negative_control(orc):
+    """The insecure MP2ML mask Encode(Delta^-1 r), r uniform in Z_q^(N/2), has coefficients with
+    standard deviation q / sqrt(12 N) (N = 8192, q ~ 2^60 as in Figure distribution): far
+    narrower than the uniform q / sqrt(12) of the secure mask."""
+    n = 8192
+    c = orc.Context(13, 1, 0, 1)
+    q = float(2 ** 60 - 2 ** 40)
+    rng = np.random.default_rng(11)
+    r = rng.uniform(0, q, n // 2)
+    p = c.encode(r - q / 2, 1.0).astype(np.float64)  # centred uniform; only the spread matters
+    p = p[1:]  # coefficient 0 carries the mean
+    ratio = p.std() / (q / np.sqrt(12 * n))
+    assert abs(ratio - 1) < 0.05
+    assert p.std() < q / np.sqrt(12) / 50
