@@ -1,0 +1,131 @@
+/*
+ * blb.h -- C ABI of the MI355X (gfx950) engine for the server-side RNS-CKKS path of
+ * "Breaking the Layer Barrier" (BLB, arXiv 2508.19525): ciphertext-plaintext matmul
+ * (matmul_cp), multi-head ciphertext-ciphertext matmul (matmul_cc), rescale, and the
+ * CKKS-to-MPC mask-and-share step.
+ *
+ * Conventions for every call:
+ *   - Return value: BLB_OK (0) or a negative BLB_E* code.  On error no output buffer has been
+ *     written (arguments are validated before any work is enqueued).  blb_status_str() names
+ *     a code.  No C++ exception crosses this boundary.
+ *   - Ordering: work is enqueued on the context's HIP stream in call order.  Calls whose
+ *     outputs are host buffers (blb_export, blb_decode, blb_ctx_moduli...) synchronise that
+ *     stream before returning.
+ *   - Ownership: blb_ctx, blb_keys and blb_plan are library-owned and released with their
+ *     *_destroy call.  Ciphertext and plaintext buffers (blb_ct.data, pt_dev, share_dev) are
+ *     caller-owned DEVICE memory, borrowed for the duration of the enqueued work.
+ *   - Ring: Z[X]/(X^N + 1), N = 2^log_n; RNS chain q_0..q_{n_q-1} (50-bit primes, q = 1 mod 2N,
+ *     the largest such primes below 2^50 taken in decreasing order) followed by n_special
+ *     special primes p_0..p_{K-1} used only inside key switching.
+ *   - A ciphertext at level l has l+1 active limbs q_0..q_l.  Its device layout is
+ *     [degree+1][l+1][N] uint64 residues in [0, q_i), in the library's evaluation (NTT) form;
+ *     blb_export / blb_import convert from / to the canonical coefficient form.
+ *   - Plaintexts at the boundary (pt_dev) are coefficient-form residues [l+1][N] uint64.
+ */
+#ifndef BLB_H
+#define BLB_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  BLB_OK = 0,
+  BLB_EINVAL = -1,  /* malformed argument (null pointer, size, shape) */
+  BLB_ELEVEL = -2,  /* not enough limbs left for the operation, or level mismatch */
+  BLB_ESCALE = -3,  /* operand scales disagree beyond 2^-30 relative */
+  BLB_ENOKEY = -4,  /* a needed Galois / relinearisation key was not generated */
+  BLB_ENOMEM = -5,  /* device allocation failed or HBM budget exceeded */
+  BLB_EDEVICE = -6, /* HIP runtime error */
+  BLB_EBUSY = -7    /* serving queue full */
+};
+
+typedef struct blb_ctx blb_ctx;
+typedef struct blb_keys blb_keys;
+typedef struct blb_plan blb_plan;
+
+/* A ciphertext (Preliminaries, "CKKS Plaintext and Ciphertext": a pair of ring elements).
+ * data: caller-owned device buffer of (degree+1)*(level+1)*N uint64 words. */
+typedef struct {
+  uint64_t* data;
+  int32_t level;  /* active limbs = level + 1 */
+  int32_t degree; /* 1: (c0, c1); 2: (d0, d1, d2) after a tensor product */
+  double scale;   /* Delta of the encoded message */
+} blb_ct;
+
+typedef struct {
+  int32_t log_n;             /* 12..16 */
+  int32_t n_q;               /* ciphertext primes, 1..12 */
+  int32_t n_special;         /* key-switching primes K, 1..4 */
+  int32_t dnum;              /* number of key-switching digits, 1..n_q */
+  int32_t device;            /* HIP device ordinal */
+  void* stream;              /* hipStream_t, NULL = the null stream */
+  uint64_t hbm_budget_bytes; /* cap on library-owned device memory (keys, plans, scratch); 0 = none */
+} blb_params;
+
+/* ---- context ------------------------------------------------------------------------- */
+int blb_ctx_create(const blb_params* params, blb_ctx** out);
+void blb_ctx_destroy(blb_ctx* ctx);
+/* out: n_q + n_special moduli (q's then p's); synchronises nothing. */
+int blb_ctx_moduli(const blb_ctx* ctx, uint64_t* out);
+/* Library-owned device bytes currently allocated (keys, plans, scratch). */
+uint64_t blb_ctx_device_bytes(const blb_ctx* ctx);
+const char* blb_status_str(int code);
+
+/* ---- keys (Preliminaries, "Rotation"; hybrid key switching as the reading of the library
+ * the paper builds on) ------------------------------------------------------------------- */
+/* Ternary secret from `seed`; relinearisation key (target s^2); one Galois key per entry of
+ * rot_steps (left rotation by that many slots; negative = right).  Keys live on the device. */
+int blb_keygen(blb_ctx* ctx, uint64_t seed, const int32_t* rot_steps, int n_rot, blb_keys** out);
+void blb_keys_destroy(blb_keys* keys);
+/* Galois element 5^steps mod 2N of a left rotation by `steps` slots. */
+uint64_t blb_galois_elt(const blb_ctx* ctx, int32_t steps);
+
+/* ---- encode / encrypt / decrypt / decode (eq. ckks_encode; real slots only) ------------ */
+/* v: host array of n <= N/2 reals (missing slots are 0); writes round-half-away(Delta *
+ * pi^-1(v)) reduced into limbs 0..level of pt_dev (coefficient form, [level+1][N]). */
+int blb_encode(blb_ctx* ctx, const double* v, int64_t n, double scale, int level, uint64_t* pt_dev);
+/* Secret-key encryption (-a s + e + pt, a); a and e drawn from Philox4x32-10 keyed by seed,
+ * object id ct_id.  out->data must hold 2*(level+1)*N words. */
+int blb_encrypt(blb_ctx* ctx, const blb_keys* keys, const uint64_t* pt_dev, int level, double scale,
+                uint64_t seed, uint32_t ct_id, blb_ct* out);
+/* pt_dev <- c0 + c1 s (+ c2 s^2), coefficient form [level+1][N]. */
+int blb_decrypt(blb_ctx* ctx, const blb_keys* keys, const blb_ct* ct, uint64_t* pt_dev);
+/* v (host, n values) <- Delta^-1 * pi(centred CRT lift of pt_dev).  Synchronises. */
+int blb_decode(blb_ctx* ctx, const uint64_t* pt_dev, int level, double scale, double* v, int64_t n);
+/* Canonical coefficient-form words of a ciphertext to / from host memory ([degree+1][level+1][N]). */
+int blb_export(blb_ctx* ctx, const blb_ct* ct, uint64_t* host_words);
+int blb_import(blb_ctx* ctx, const uint64_t* host_words, blb_ct* ct);
+
+/* ---- homomorphic operations ------------------------------------------------------------ */
+/* Left rotation by `steps` slots (Preliminaries, "Rotation"): sigma_{5^steps} and a hybrid
+ * key switch with the automorphism applied after ModUp. in/out may not alias. */
+int blb_rotate(blb_ctx* ctx, const blb_keys* keys, const blb_ct* in, int32_t steps, blb_ct* out);
+/* Rescale (Preliminaries, "Rescaling"): divide by the last prime q_l with rounding.
+ * out->data must hold (degree+1)*level*N words; out gets level-1 and scale/q_l. */
+int blb_rescale(blb_ctx* ctx, const blb_ct* in, blb_ct* out);
+
+/* ---- matmul_cp (Section "Efficient Protocol for Fused MatMuls"; Appendix "BSGS
+ * Optimization"; spatial-first packing of "Consistent Packing for Single Operator") ----- */
+/* Builds the BSGS diagonal plaintexts of W (host, d_in x d_out row-major) for inputs of L rows
+ * at ciphertext level `level`: encoded on the device at scale q_level and kept resident.
+ * info (optional, 8 ints): L', c, c_eff, c_out, n_in, n_out, B, G. */
+int blb_plan_matmul_cp(blb_ctx* ctx, const double* W, int d_in, int d_out, int L, int level, blb_plan** out);
+void blb_plan_destroy(blb_plan* plan);
+int blb_plan_info(const blb_plan* plan, int32_t* info8);
+/* Y_b = Rescale( sum_j Rot^{jBL'}( sum_a sum_i pt_{a,b,j,i} (.) Rot^{iL'}(X_a) ) ), b < n_out.
+ * X: n_in ciphertexts at the plan's level; Y: n_out buffers of 2*level*N words. */
+int blb_matmul_cp(blb_ctx* ctx, const blb_keys* keys, const blb_plan* plan, const blb_ct* X, int n_in,
+                  blb_ct* Y, int n_out);
+
+/* ---- CKKS-to-MPC mask-and-share (Algorithm ckks2mpc, step 1; functionality F_C2M) ------- */
+/* For each ciphertext t < n_ct: reduce to target_level (dropping top limbs) if lower, sample
+ * r uniform in R_{Q_target} (Philox, object id t), set c0 <- c0 + r in place and write the
+ * server share -r mod q_i in coefficient form to share_dev[t][limb][N]. */
+int blb_mask_to_share(blb_ctx* ctx, blb_ct* cts, int n_ct, uint64_t seed, int target_level, uint64_t* share_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BLB_H */

@@ -1,0 +1,221 @@
+"""Python binding of the gfx950 RNS-CKKS engine (``libblb.so``, C ABI in ``include/blb.h``).
+
+Argument marshalling only: every step runs in the HIP library.  Device buffers are torch
+tensors (``torch.int64`` viewed as the uint64 residues) or raw device pointers; the context's
+HIP stream is passed at creation (torch's current stream by default).  If the shared library
+is missing the import of any entry point raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libblb.so")
+
+BLB_OK, BLB_EINVAL, BLB_ELEVEL, BLB_ESCALE, BLB_ENOKEY, BLB_ENOMEM, BLB_EDEVICE, BLB_EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
+
+
+class BlbError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {status_str(code)} ({code})")
+        self.code = code
+
+
+class blb_ct(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("level", C.c_int32), ("degree", C.c_int32), ("scale", C.c_double)]
+
+
+class blb_params(C.Structure):
+    _fields_ = [("log_n", C.c_int32), ("n_q", C.c_int32), ("n_special", C.c_int32), ("dnum", C.c_int32),
+                ("device", C.c_int32), ("stream", C.c_void_p), ("hbm_budget_bytes", C.c_uint64)]
+
+
+_lib = None
+
+_SIGS = {
+    "blb_status_str": (C.c_char_p, [C.c_int]),
+    "blb_ctx_create": (C.c_int, [C.POINTER(blb_params), C.POINTER(C.c_void_p)]),
+    "blb_ctx_destroy": (None, [C.c_void_p]),
+    "blb_ctx_moduli": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "blb_ctx_device_bytes": (C.c_uint64, [C.c_void_p]),
+    "blb_keygen": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.POINTER(C.c_void_p)]),
+    "blb_keys_destroy": (None, [C.c_void_p]),
+    "blb_galois_elt": (C.c_uint64, [C.c_void_p, C.c_int32]),
+    "blb_encode": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_int, C.c_void_p]),
+    "blb_encrypt": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_uint64, C.c_uint32,
+                              C.POINTER(blb_ct)]),
+    "blb_decrypt": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.c_void_p]),
+    "blb_decode": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_void_p, C.c_int64]),
+    "blb_export": (C.c_int, [C.c_void_p, C.POINTER(blb_ct), C.c_void_p]),
+    "blb_import": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(blb_ct)]),
+    "blb_rotate": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.c_int32, C.POINTER(blb_ct)]),
+    "blb_rescale": (C.c_int, [C.c_void_p, C.POINTER(blb_ct), C.POINTER(blb_ct)]),
+    "blb_plan_matmul_cp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)]),
+    "blb_plan_destroy": (None, [C.c_void_p]),
+    "blb_plan_info": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "blb_matmul_cp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.c_int, C.POINTER(blb_ct), C.c_int]),
+    "blb_mask_to_share": (C.c_int, [C.c_void_p, C.POINTER(blb_ct), C.c_int, C.c_uint64, C.c_int, C.c_void_p]),
+}
+
+
+def lib():
+    """Loads libblb.so (built by ``paper_2508_19525_amd.build``); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2508_19525_amd.build.build_lib()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def status_str(code: int) -> str:
+    return lib().blb_status_str(code).decode()
+
+
+def _check(rc, what):
+    if rc != BLB_OK:
+        raise BlbError(rc, what)
+
+
+def _ptr(x):
+    """device pointer of a torch tensor, or an int"""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _host_ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+# ---------------------------------------------------------------------------------------
+# C ABI, one function per entry point
+# ---------------------------------------------------------------------------------------
+def blb_ctx_create(log_n, n_q, n_special, dnum, device=0, stream=None, hbm_budget_bytes=0):
+    p = blb_params(log_n, n_q, n_special, dnum, device, stream, hbm_budget_bytes)
+    out = C.c_void_p()
+    _check(lib().blb_ctx_create(C.byref(p), C.byref(out)), "blb_ctx_create")
+    return out.value
+
+
+def blb_ctx_destroy(ctx):
+    lib().blb_ctx_destroy(ctx)
+
+
+def blb_ctx_moduli(ctx, count):
+    out = np.zeros(count, np.uint64)
+    _check(lib().blb_ctx_moduli(ctx, _host_ptr(out)), "blb_ctx_moduli")
+    return out
+
+
+def blb_ctx_device_bytes(ctx):
+    return int(lib().blb_ctx_device_bytes(ctx))
+
+
+def blb_keygen(ctx, seed, rot_steps=()):
+    steps = np.ascontiguousarray(rot_steps, dtype=np.int32)
+    out = C.c_void_p()
+    _check(lib().blb_keygen(ctx, seed, _host_ptr(steps) if steps.size else None, int(steps.size), C.byref(out)), "blb_keygen")
+    return out.value
+
+
+def blb_keys_destroy(keys):
+    lib().blb_keys_destroy(keys)
+
+
+def blb_galois_elt(ctx, steps):
+    return int(lib().blb_galois_elt(ctx, steps))
+
+
+def blb_encode(ctx, values, scale, level, pt_dev):
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    _check(lib().blb_encode(ctx, _host_ptr(v), v.size, float(scale), level, _ptr(pt_dev)), "blb_encode")
+
+
+def blb_encrypt(ctx, keys, pt_dev, level, scale, seed, ct_id, ct: blb_ct):
+    _check(lib().blb_encrypt(ctx, keys, _ptr(pt_dev), level, float(scale), seed, ct_id, C.byref(ct)), "blb_encrypt")
+
+
+def blb_decrypt(ctx, keys, ct: blb_ct, pt_dev):
+    _check(lib().blb_decrypt(ctx, keys, C.byref(ct), _ptr(pt_dev)), "blb_decrypt")
+
+
+def blb_decode(ctx, pt_dev, level, scale, n_vals):
+    out = np.zeros(n_vals, np.float64)
+    _check(lib().blb_decode(ctx, _ptr(pt_dev), level, float(scale), _host_ptr(out), n_vals), "blb_decode")
+    return out
+
+
+def blb_export(ctx, ct: blb_ct, n):
+    out = np.zeros((ct.degree + 1, ct.level + 1, n), np.uint64)
+    _check(lib().blb_export(ctx, C.byref(ct), _host_ptr(out)), "blb_export")
+    return out
+
+
+def blb_import(ctx, words: np.ndarray, ct: blb_ct):
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    _check(lib().blb_import(ctx, _host_ptr(w), C.byref(ct)), "blb_import")
+
+
+def blb_rotate(ctx, keys, ct_in: blb_ct, steps, ct_out: blb_ct):
+    _check(lib().blb_rotate(ctx, keys, C.byref(ct_in), steps, C.byref(ct_out)), "blb_rotate")
+
+
+def blb_rescale(ctx, ct_in: blb_ct, ct_out: blb_ct):
+    _check(lib().blb_rescale(ctx, C.byref(ct_in), C.byref(ct_out)), "blb_rescale")
+
+
+def blb_plan_matmul_cp(ctx, W: np.ndarray, L, level):
+    Wc = np.ascontiguousarray(W, dtype=np.float64)
+    out = C.c_void_p()
+    _check(lib().blb_plan_matmul_cp(ctx, _host_ptr(Wc), Wc.shape[0], Wc.shape[1], L, level, C.byref(out)), "blb_plan_matmul_cp")
+    return out.value
+
+
+def blb_plan_destroy(plan):
+    lib().blb_plan_destroy(plan)
+
+
+def blb_plan_info(plan):
+    out = np.zeros(8, np.int32)
+    _check(lib().blb_plan_info(plan, _host_ptr(out)), "blb_plan_info")
+    return dict(zip(["Lp", "c", "c_eff", "c_out", "n_in", "n_out", "B", "G"], [int(x) for x in out]))
+
+
+def blb_matmul_cp(ctx, keys, plan, X_cts, Y_cts):
+    Xa = (blb_ct * len(X_cts))(*X_cts)
+    Ya = (blb_ct * len(Y_cts))(*Y_cts)
+    _check(lib().blb_matmul_cp(ctx, keys, plan, Xa, len(X_cts), Ya, len(Y_cts)), "blb_matmul_cp")
+    for i in range(len(Y_cts)):
+        Y_cts[i].level, Y_cts[i].degree, Y_cts[i].scale = Ya[i].level, Ya[i].degree, Ya[i].scale
+
+
+def blb_mask_to_share(ctx, cts, seed, target_level, share_dev):
+    arr = (blb_ct * len(cts))(*cts)
+    _check(lib().blb_mask_to_share(ctx, arr, len(cts), seed, target_level, _ptr(share_dev)), "blb_mask_to_share")
+    for i in range(len(cts)):
+        cts[i].level = arr[i].level
+
+
+# ---------------------------------------------------------------------------------------
+# small conveniences over the ABI (buffer allocation with torch)
+# ---------------------------------------------------------------------------------------
+def new_ct(n, level, degree=1, device="cuda"):
+    """(blb_ct, backing tensor) for a ciphertext at `level`"""
+    import torch
+    t = torch.empty((degree + 1) * (level + 1) * n, dtype=torch.int64, device=device)
+    return blb_ct(t.data_ptr(), level, degree, 0.0), t

@@ -1,0 +1,179 @@
+// Internal declarations of the gfx950 engine: context / key / plan structures, the
+// FP64 modular arithmetic used by every kernel, and the host-side launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <deque>
+#include <vector>
+#include "../../include/blb.h"
+
+#define BLB_MAXM 16     // max moduli (q's + p's)
+#define BLB_MAXQ 12     // max ciphertext primes
+#define BLB_MAXSP 4     // max special primes
+#define BLB_MAXALPHA 8  // max primes per key-switching digit
+
+// ---------------------------------------------------------------------------------------
+// Modular arithmetic on FP64 lanes.
+//
+// All primes are below 2^50, so every residue, and every sum of a few residues, is an
+// integer that a double holds exactly.  A product a*b (|a|,|b| < 2q) is split exactly into
+// p = fl(a*b) and e = fma(a, b, -p) (error-free product); the quotient estimate
+// t = rint(p * (1/q)) is within one of a*b/q, so r = fma(-t, q, p) is an exact integer below
+// 2^51 and r + e = a*b - t*q exactly.  Results are "signed-lazy": |r| < q.  CDNA4 issues
+// FP64 FMA at full rate, which makes this cheaper than 32-bit limb integer products.
+// ---------------------------------------------------------------------------------------
+#define BLB_TWO52 4503599627370496.0
+
+__device__ __forceinline__ double u2d(uint64_t x) {  // x < 2^52
+  return __longlong_as_double((long long)(x | 0x4330000000000000ull)) - BLB_TWO52;
+}
+__device__ __forceinline__ uint64_t d2u(double d) {  // integer 0 <= d < 2^52
+  return (uint64_t)__double_as_longlong(d + BLB_TWO52) & 0x000FFFFFFFFFFFFFull;
+}
+// a*b - t*q with |result| < q for |a|,|b| < 2q
+__device__ __forceinline__ double mulmod_s(double a, double b, double q, double qinv) {
+  const double p = a * b;
+  const double e = __builtin_fma(a, b, -p);
+  const double t = __builtin_rint(p * qinv);
+  const double r = __builtin_fma(-t, q, p);
+  return r + e;
+}
+// x - round(x/q) q, |result| <= q/2 + tiny, for |x| < 2^52
+__device__ __forceinline__ double reduce_s(double x, double q, double qinv) {
+  const double t = __builtin_rint(x * qinv);
+  return __builtin_fma(-t, q, x);
+}
+// signed-lazy (|x| < q) -> canonical [0, q)
+__device__ __forceinline__ double canon(double x, double q) { return x < 0.0 ? x + q : x; }
+// any |x| < 2^52 -> canonical
+__device__ __forceinline__ double canon_full(double x, double q, double qinv) { return canon(reduce_s(x, q, qinv), q); }
+
+// ---------------------------------------------------------------------------------------
+// Shared structures (host and device)
+// ---------------------------------------------------------------------------------------
+struct ModEntry {
+  double q;
+  double qinv;  // fl(1/q)
+  double ninv;  // N^-1 mod q
+};
+struct ModTable {
+  ModEntry m[BLB_MAXM];
+};
+struct ModMap {
+  int len;               // period of the modulus pattern over consecutive polys
+  int idx[BLB_MAXM];     // modulus index of poly p = idx[p % len]
+};
+
+// Per-level key-switching constants.  Extended basis index e: 0..nl-1 = q_0..q_{nl-1},
+// nl..nl+K-1 = p_0..p_{K-1}.
+struct KsLevelConst {
+  int nl, n_ext, n_digits, n_key_mod;
+  int dlo[BLB_MAXQ], dhi[BLB_MAXQ];               // digit j covers extended indices [dlo, dhi)
+  ModEntry ext[BLB_MAXM];
+  double qhat_inv[BLB_MAXQ][BLB_MAXALPHA];        // [(Q_D/q_i)^-1]_{q_i}
+  double qhat_mod[BLB_MAXQ][BLB_MAXALPHA][BLB_MAXM];  // [Q_D/q_i]_{m_e}
+  double phat_inv[BLB_MAXSP];                     // [(P/p_t)^-1]_{p_t}
+  double phat_mod[BLB_MAXSP][BLB_MAXQ];           // [P/p_t]_{q_i}
+  double p_inv[BLB_MAXQ];                         // [P^-1]_{q_i}
+};
+
+// One key-switch output of a batch: source index (into the ModUp buffer), the source's c1
+// (evaluation form, for the digit's own limbs), the switching key and the Galois element
+// (0 = none).
+struct KsOut {
+  const uint64_t* c1;
+  const uint64_t* key;
+  uint32_t gal;
+  int32_t src;
+};
+
+struct CpGeom {
+  int d_in, d_out, L;
+  int Lp, c, c_eff, c_out, n_in, n_out, B, G;
+};
+
+// ---------------------------------------------------------------------------------------
+// Host-side structures
+// ---------------------------------------------------------------------------------------
+// Descriptor upload ring: pinned host staging + device mirror; a host region is reused only
+// after the copy that last read it has completed.
+struct Uploader {
+  char* host = nullptr;
+  char* dev = nullptr;
+  size_t cap = 0, head = 0;
+  std::deque<std::pair<size_t, hipEvent_t>> inflight;  // (end offset, event) in ring order
+  std::vector<hipEvent_t> free_events;
+};
+
+struct blb_ctx {
+  int log_n, n, n_q, n_sp, dnum, alpha;
+  int device;
+  hipStream_t stream;
+  uint64_t budget;
+  uint64_t dev_bytes = 0;
+  uint64_t mod[BLB_MAXM];
+  ModTable mt;
+  uint64_t* d_mods = nullptr;
+  double* d_tw_fwd = nullptr;
+  double* d_tw_inv = nullptr;
+  double* d_enc_tw = nullptr;     // [N/4][4] eta^k (dd complex), eta = exp(2 pi i / (N/2))
+  double* d_enc_twist = nullptr;  // [N/2][4] zeta^-k (dd complex)
+  int32_t* d_slot_u = nullptr;    // slot j -> (5^j mod 2N - 1) / 4
+  KsLevelConst* d_kc[BLB_MAXQ] = {};
+  KsLevelConst h_kc[BLB_MAXQ];
+  char* scratch = nullptr;
+  size_t scratch_cap = 0;
+  Uploader up;
+  int* d_flag = nullptr;          // device error flag (encoder overflow)
+};
+
+// Switching key in evaluation form: [digit][2 (b, a)][modulus (all q's then p's)][N] residues
+struct SwKey {
+  uint64_t id;  // 0 = relinearisation, else Galois element
+  uint64_t* data;
+};
+
+struct blb_keys {
+  blb_ctx* ctx;
+  uint64_t seed;
+  uint64_t* s_ntt;  // secret in evaluation form for all moduli [modulus][N]
+  std::vector<SwKey> keys;
+  size_t bytes;
+};
+
+struct blb_plan {
+  blb_ctx* ctx;
+  int kind;  // 1 = matmul_cp
+  int level;
+  CpGeom g;
+  uint64_t* pt;  // [(b, j)][(a, i)][limb][N] evaluation-form plaintexts
+  size_t bytes;
+};
+
+// ---------------------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------------------
+struct PolyDesc;
+void launch_sample_uniform(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag);
+void launch_sample_int(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag, bool gaussian);
+void upload_cdt(const uint64_t* table20);
+
+enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_MUL = 2, EW_NEG = 3, EW_COPY = 4, EW_MULADD = 5 };
+void launch_ew(blb_ctx* c, int op, uint64_t* out, const uint64_t* a, const uint64_t* b, const uint64_t* cc, int count, ModMap map);
+struct LimbVals {
+  int use;
+  double v[BLB_MAXM];  // per-limb multiplier of the `extra` term
+};
+void launch_rlwe_combine(blb_ctx* c, uint64_t* out0, const uint64_t* a, const uint64_t* s, const uint64_t* e, const uint64_t* extra,
+                         LimbVals extra_mul, int n_limbs, ModMap map);
+void launch_automorph(blb_ctx* c, uint64_t* out, const uint64_t* in, int count, uint32_t g);
+void launch_modup(blb_ctx* c, const uint64_t* dcoef, uint64_t* X, const KsLevelConst* kc_dev, int n_src, int nl, int n_ext, int n_digits);
+void launch_ks_inner(blb_ctx* c, const KsOut* outs_dev, int n_out, const uint64_t* X, const KsLevelConst* kc_dev, uint64_t* U, int nl,
+                     int n_ext, int n_digits);
+void launch_moddown_conv(blb_ctx* c, const uint64_t* U, uint64_t* Corr, const KsLevelConst* kc_dev, int n_out, int nl, int n_ext);
+void launch_cp_mac(blb_ctx* c, const uint64_t* pt, const uint64_t* RX, uint64_t* inner, int nl, int n_ai, int n_bj);
+void launch_mask_sample(blb_ctx* c, uint64_t* r_out, uint64_t* share, int n_ct, int tl, uint64_t seed, uint32_t tag);
+int run_encode_core(blb_ctx* c, double* bufA, double* bufB, int count, double scale, int nl, uint64_t* out, int* d_overflow);
+void launch_enc_scatter_dense(blb_ctx* c, const double* vals, int n_vals, int count, double* buf);
+void launch_enc_scatter_cp(blb_ctx* c, const double* W, CpGeom g, int p0, int count, double* buf);

@@ -1,0 +1,468 @@
+// Elementwise, sampling, key-switching, matmul_cp and encoder kernels for gfx950.
+// All modular arithmetic is the FP64 signed-lazy scheme of blb_internal.h.
+#include "blb_internal.h"
+#include "blb_kernels.h"
+
+// ---------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds, multipliers 0xD2511F53 / 0xCD9E8D57,
+// key schedule increments 0x9E3779B9 / 0xBB67AE85.  Counter = (coefficient, limb, object,
+// tag), key = (seed low word, seed high word).
+// ---------------------------------------------------------------------------------------
+struct U4 { uint32_t x, y, z, w; };
+__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+  }
+  return U4{c0, c1, c2, c3};
+}
+#define LIMB_INTEGER 0xFFFFFFFFu
+
+// (w3 2^96 + w2 2^64 + w1 2^32 + w0) mod q by Horner steps r <- r*2^32 + w (mod q) on FP64
+__device__ __forceinline__ double u128_mod(U4 w, double q, double qi) {
+  const double two32 = 4294967296.0;
+  double r = (double)w.w;  // < 2^32 < q
+  r = canon_full(mulmod_s(r, two32, q, qi) + (double)w.z, q, qi);
+  r = canon_full(mulmod_s(r, two32, q, qi) + (double)w.y, q, qi);
+  r = canon_full(mulmod_s(r, two32, q, qi) + (double)w.x, q, qi);
+  return r;
+}
+
+// out[limb][k] = uniform residue mod the limb's modulus; limb counter = mod index
+__global__ void k_sample_uniform(uint64_t* out, int n, ModMap map, ModTable mt, uint32_t k0, uint32_t k1, uint32_t obj, uint32_t tag) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int limb = blockIdx.y;
+  if (k >= n) return;
+  const int m = map.idx[limb % map.len];
+  const U4 w = philox10((uint32_t)k, (uint32_t)m, obj, tag, k0, k1);
+  out[(size_t)limb * n + k] = d2u(u128_mod(w, mt.m[m].q, mt.m[m].qinv));
+}
+
+// integer samples (ternary secret / Gaussian error), reduced into every limb of the map
+__constant__ uint64_t c_cdt[20];
+__global__ void k_sample_int(uint64_t* out, int n, int n_limbs, ModMap map, ModTable mt, uint32_t k0, uint32_t k1, uint32_t obj,
+                             uint32_t tag, int gaussian) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const U4 w = philox10((uint32_t)k, LIMB_INTEGER, obj, tag, k0, k1);
+  int v;
+  if (gaussian) {
+    const uint64_t r = ((((uint64_t)w.y) << 32) | w.x) >> 1;
+    int x = 0;
+    while (x < 19 && r >= c_cdt[x]) ++x;
+    v = (w.z & 1u) ? -x : x;
+  } else {
+    v = (int)(w.x % 3u) - 1;
+  }
+  for (int l = 0; l < n_limbs; ++l) {
+    const double q = mt.m[map.idx[l % map.len]].q;
+    out[(size_t)l * n + k] = d2u(v < 0 ? q + (double)v : (double)v);
+  }
+}
+
+void upload_cdt(const uint64_t* table20) { (void)hipMemcpyToSymbol(HIP_SYMBOL(c_cdt), table20, 20 * sizeof(uint64_t)); }
+
+void launch_sample_uniform(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag) {
+  dim3 grid((c->n + 255) / 256, n_limbs);
+  k_sample_uniform<<<grid, 256, 0, c->stream>>>(out, c->n, map, c->mt, (uint32_t)seed, (uint32_t)(seed >> 32), obj, tag);
+}
+void launch_sample_int(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag, bool gaussian) {
+  k_sample_int<<<(c->n + 255) / 256, 256, 0, c->stream>>>(out, c->n, n_limbs, map, c->mt, (uint32_t)seed, (uint32_t)(seed >> 32), obj,
+                                                          tag, gaussian ? 1 : 0);
+}
+
+// ---------------------------------------------------------------------------------------
+// Elementwise ops over [count][N] u64 arrays (evaluation or coefficient form alike)
+// ---------------------------------------------------------------------------------------
+__global__ void k_ew(int op, uint64_t* out, const uint64_t* a, const uint64_t* b, const uint64_t* cc, int n, ModMap map, ModTable mt) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (k >= n) return;
+  const ModEntry me = mt.m[map.idx[p % map.len]];
+  const size_t o = (size_t)p * n + k;
+  const double x = u2d(a[o]);
+  double r;
+  switch (op) {
+    case EW_ADD: { r = x + u2d(b[o]); r = r >= me.q ? r - me.q : r; break; }
+    case EW_SUB: { r = x - u2d(b[o]); r = r < 0 ? r + me.q : r; break; }
+    case EW_MUL: { r = canon(mulmod_s(x, u2d(b[o]), me.q, me.qinv), me.q); break; }
+    case EW_NEG: { r = x == 0.0 ? 0.0 : me.q - x; break; }
+    case EW_MULADD: { r = mulmod_s(x, u2d(b[o]), me.q, me.qinv) + u2d(cc[o]); r = canon_full(r, me.q, me.qinv); break; }
+    default: { r = x; break; }
+  }
+  out[o] = d2u(r);
+}
+void launch_ew(blb_ctx* c, int op, uint64_t* out, const uint64_t* a, const uint64_t* b, const uint64_t* cc, int count, ModMap map) {
+  if (count <= 0) return;
+  dim3 grid((c->n + 255) / 256, count);
+  k_ew<<<grid, 256, 0, c->stream>>>(op, out, a, b, cc, c->n, map, c->mt);
+}
+
+// encryption / key combination in evaluation form:
+//   out0 = -a*s + e + extra     (extra optional: plaintext or P*s' term, added modularly)
+__global__ void k_rlwe_combine(uint64_t* out0, const uint64_t* a, const uint64_t* s, const uint64_t* e, const uint64_t* extra,
+                               LimbVals extra_mul, int n, ModMap map, ModTable mt) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int l = blockIdx.y;
+  if (k >= n) return;
+  const ModEntry me = mt.m[map.idx[l % map.len]];
+  const size_t o = (size_t)l * n + k;
+  double r = u2d(e[o]) - mulmod_s(u2d(a[o]), u2d(s[o]), me.q, me.qinv);  // (-q, 2q)
+  if (extra) {
+    double x = u2d(extra[o]);
+    if (extra_mul.use) x = mulmod_s(x, extra_mul.v[l], me.q, me.qinv);
+    r += x;
+  }
+  out0[o] = d2u(canon_full(r, me.q, me.qinv));
+}
+void launch_rlwe_combine(blb_ctx* c, uint64_t* out0, const uint64_t* a, const uint64_t* s, const uint64_t* e, const uint64_t* extra,
+                         LimbVals extra_mul, int n_limbs, ModMap map) {
+  dim3 grid((c->n + 255) / 256, n_limbs);
+  k_rlwe_combine<<<grid, 256, 0, c->stream>>>(out0, a, s, e, extra, extra_mul, c->n, map, c->mt);
+}
+
+// evaluation-form automorphism of `count` polys
+__global__ void k_automorph(uint64_t* out, const uint64_t* in, int n, int log_n, uint32_t g) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (k >= n) return;
+  out[(size_t)p * n + k] = in[(size_t)p * n + gal_perm((uint32_t)k, g, log_n)];
+}
+void launch_automorph(blb_ctx* c, uint64_t* out, const uint64_t* in, int count, uint32_t g) {
+  dim3 grid((c->n + 255) / 256, count);
+  k_automorph<<<grid, 256, 0, c->stream>>>(out, in, c->n, c->log_n, g);
+}
+
+// ---------------------------------------------------------------------------------------
+// Key switching
+// ---------------------------------------------------------------------------------------
+// ModUp: fast basis conversion (no centring) of digit j of each source, coefficient form.
+//   x_m = sum_{i in D} [d_i * Qhat_i^-1]_{q_i} * [Qhat_i]_m  (mod m), for every extended
+//   modulus m outside the digit.  Writes X[s][j][e][k] for those e.
+// Thread per (s, j, k).
+__global__ void k_modup(const uint64_t* dcoef, uint64_t* X, const KsLevelConst* kc, int n, int nl, int n_ext, int n_digits) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y % n_digits;
+  const int s = blockIdx.y / n_digits;
+  if (k >= n) return;
+  const int lo = kc->dlo[j], hi = kc->dhi[j];
+  double y[8];
+#pragma unroll 4
+  for (int i = lo; i < hi; ++i) {
+    const ModEntry mq = kc->ext[i];
+    y[i - lo] = canon(mulmod_s(u2d(dcoef[((size_t)s * nl + i) * n + k]), kc->qhat_inv[j][i - lo], mq.q, mq.qinv), mq.q);
+  }
+  for (int e = 0; e < n_ext; ++e) {
+    if (e >= lo && e < hi) continue;
+    const ModEntry mm = kc->ext[e];
+    double acc = 0.0;
+    for (int i = lo; i < hi; ++i) acc += mulmod_s(y[i - lo], kc->qhat_mod[j][i - lo][e], mm.q, mm.qinv);
+    X[(((size_t)s * n_digits + j) * n_ext + e) * n + k] = d2u(canon_full(acc, mm.q, mm.qinv));
+  }
+}
+void launch_modup(blb_ctx* c, const uint64_t* dcoef, uint64_t* X, const KsLevelConst* kc_dev, int n_src, int nl, int n_ext, int n_digits) {
+  dim3 grid((c->n + 255) / 256, n_src * n_digits);
+  k_modup<<<grid, 256, 0, c->stream>>>(dcoef, X, kc_dev, c->n, nl, n_ext, n_digits);
+}
+
+// Inner product with the switching key, with the automorphism applied to the extended
+// digits (hoisted order).  Thread per (o, e, k); writes U[o][2][e][k] (evaluation form).
+__global__ void k_ks_inner(const KsOut* outs, const uint64_t* X, const KsLevelConst* kc, uint64_t* U, int n, int log_n, int nl, int n_ext,
+                           int n_digits, int n_q) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = blockIdx.y % n_ext;
+  const int o = blockIdx.y / n_ext;
+  if (k >= n) return;
+  const KsOut od = outs[o];
+  const uint32_t kk = od.gal ? gal_perm((uint32_t)k, od.gal, log_n) : (uint32_t)k;
+  const ModEntry mm = kc->ext[e];
+  const int key_mod = e < nl ? e : n_q + (e - nl);
+  double acc0 = 0.0, acc1 = 0.0;
+  for (int j = 0; j < n_digits; ++j) {
+    double x;
+    if (e >= kc->dlo[j] && e < kc->dhi[j]) x = u2d(od.c1[(size_t)e * n + kk]);
+    else x = u2d(X[(((size_t)od.src * n_digits + j) * n_ext + e) * n + kk]);
+    const uint64_t* kb = od.key + (((size_t)j * 2 + 0) * kc->n_key_mod + key_mod) * n;
+    const uint64_t* ka = od.key + (((size_t)j * 2 + 1) * kc->n_key_mod + key_mod) * n;
+    acc0 += mulmod_s(x, u2d(kb[k]), mm.q, mm.qinv);
+    acc1 += mulmod_s(x, u2d(ka[k]), mm.q, mm.qinv);
+    if ((j & 3) == 3) {  // keep |acc| < 5q < 2^53
+      acc0 = reduce_s(acc0, mm.q, mm.qinv);
+      acc1 = reduce_s(acc1, mm.q, mm.qinv);
+    }
+  }
+  U[(((size_t)o * 2 + 0) * n_ext + e) * n + k] = d2u(canon_full(acc0, mm.q, mm.qinv));
+  U[(((size_t)o * 2 + 1) * n_ext + e) * n + k] = d2u(canon_full(acc1, mm.q, mm.qinv));
+}
+void launch_ks_inner(blb_ctx* c, const KsOut* outs_dev, int n_out, const uint64_t* X, const KsLevelConst* kc_dev, uint64_t* U, int nl,
+                     int n_ext, int n_digits) {
+  dim3 grid((c->n + 255) / 256, n_out * n_ext);
+  k_ks_inner<<<grid, 256, 0, c->stream>>>(outs_dev, X, kc_dev, U, c->n, c->log_n, nl, n_ext, n_digits, c->n_q);
+}
+
+// ModDown conversion: corr_i = sum_t [u_{p_t} * Phat_t^-1]_{p_t} * [Phat_t]_{q_i}  (coefficient
+// form; U's special limbs must already be in coefficient form).  Thread per (o, poly, k).
+__global__ void k_moddown_conv(const uint64_t* U, uint64_t* Corr, const KsLevelConst* kc, int n, int nl, int n_ext, int n_sp) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int op = blockIdx.y;  // o * 2 + poly
+  if (k >= n) return;
+  double y[4];
+  for (int t = 0; t < n_sp; ++t) {
+    const ModEntry mp = kc->ext[nl + t];
+    y[t] = canon(mulmod_s(u2d(U[((size_t)op * n_ext + nl + t) * n + k]), kc->phat_inv[t], mp.q, mp.qinv), mp.q);
+  }
+  for (int i = 0; i < nl; ++i) {
+    const ModEntry mq = kc->ext[i];
+    double acc = 0.0;
+    for (int t = 0; t < n_sp; ++t) acc += mulmod_s(y[t], kc->phat_mod[t][i], mq.q, mq.qinv);
+    Corr[((size_t)op * nl + i) * n + k] = d2u(canon_full(acc, mq.q, mq.qinv));
+  }
+}
+void launch_moddown_conv(blb_ctx* c, const uint64_t* U, uint64_t* Corr, const KsLevelConst* kc_dev, int n_out, int nl, int n_ext) {
+  dim3 grid((c->n + 255) / 256, n_out * 2);
+  k_moddown_conv<<<grid, 256, 0, c->stream>>>(U, Corr, kc_dev, c->n, nl, n_ext, c->n_sp);
+}
+
+// ---------------------------------------------------------------------------------------
+// matmul_cp inner sums:  inner[bj][p][limb] = sum_{ai} pt[bj][ai][limb] (.) RX[ai][p][limb]
+// Thread per (coefficient k, limb) for a tile of TB outputs.  The plaintext stream is read
+// exactly once; RX tiles are re-read per output tile (L2 / MALL resident).
+// ---------------------------------------------------------------------------------------
+template <int TB>
+__global__ __launch_bounds__(256) void k_cp_mac(const uint64_t* __restrict__ pt, const uint64_t* __restrict__ RX, uint64_t* __restrict__ inner,
+                                                int n, int nl, int n_ai, int n_bj, ModTable mt, int n_kblk, int n_tiles) {
+  // XCD-aware block mapping: blocks that share a (k-chunk, limb) land on the same XCD
+  const int nb = gridDim.x;
+  const int per_xcd = nb / 8;
+  int lb = blockIdx.x;
+  if (per_xcd * 8 == nb) lb = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  const int tile = lb % n_tiles;
+  const int rest = lb / n_tiles;
+  const int kb = rest % n_kblk;
+  const int limb = rest / n_kblk;
+  const int k = kb * 256 + threadIdx.x;
+  if (k >= n) return;
+  const ModEntry me = mt.m[limb];
+  const double q = me.q, qi = me.qinv;
+  const int bj0 = tile * TB;
+  double a0[TB], a1[TB];
+#pragma unroll
+  for (int t = 0; t < TB; ++t) { a0[t] = 0.0; a1[t] = 0.0; }
+  const size_t pt_stride_bj = (size_t)n_ai * nl * n;
+  for (int ai = 0; ai < n_ai; ++ai) {
+    const double x0 = u2d(RX[(((size_t)ai * 2 + 0) * nl + limb) * n + k]);
+    const double x1 = u2d(RX[(((size_t)ai * 2 + 1) * nl + limb) * n + k]);
+    const uint64_t* p = pt + ((size_t)bj0 * n_ai + ai) * nl * n + (size_t)limb * n + k;
+#pragma unroll
+    for (int t = 0; t < TB; ++t) {
+      if (bj0 + t < n_bj) {
+        const double w = u2d(p[t * pt_stride_bj]);
+        a0[t] += mulmod_s(w, x0, q, qi);
+        a1[t] += mulmod_s(w, x1, q, qi);
+      }
+    }
+    if ((ai & 7) == 7) {
+#pragma unroll
+      for (int t = 0; t < TB; ++t) { a0[t] = reduce_s(a0[t], q, qi); a1[t] = reduce_s(a1[t], q, qi); }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < TB; ++t) {
+    if (bj0 + t < n_bj) {
+      inner[(((size_t)(bj0 + t) * 2 + 0) * nl + limb) * n + k] = d2u(canon_full(a0[t], q, qi));
+      inner[(((size_t)(bj0 + t) * 2 + 1) * nl + limb) * n + k] = d2u(canon_full(a1[t], q, qi));
+    }
+  }
+}
+void launch_cp_mac(blb_ctx* c, const uint64_t* pt, const uint64_t* RX, uint64_t* inner, int nl, int n_ai, int n_bj) {
+  constexpr int TB = 8;
+  const int n_kblk = (c->n + 255) / 256;
+  const int n_tiles = (n_bj + TB - 1) / TB;
+  const int blocks = n_kblk * nl * n_tiles;
+  k_cp_mac<TB><<<blocks, 256, 0, c->stream>>>(pt, RX, inner, c->n, nl, n_ai, n_bj, c->mt, n_kblk, n_tiles);
+}
+
+// ---------------------------------------------------------------------------------------
+// Mask-and-share: r uniform per limb in coefficient form (tag mask, object = ct index),
+// share = -r mod q_i; the mask is added to c0 in evaluation form by the caller after an NTT.
+// ---------------------------------------------------------------------------------------
+__global__ void k_mask_sample(uint64_t* r_out, uint64_t* share, int n, int tl, ModTable mt, uint32_t k0, uint32_t k1, uint32_t tag) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y % tl;
+  const int t = blockIdx.y / tl;
+  if (k >= n) return;
+  const ModEntry me = mt.m[i];
+  const U4 w = philox10((uint32_t)k, (uint32_t)i, (uint32_t)t, tag, k0, k1);
+  const double r = u128_mod(w, me.q, me.qinv);
+  const size_t o = ((size_t)t * tl + i) * n + k;
+  r_out[o] = d2u(r);
+  share[o] = d2u(r == 0.0 ? 0.0 : me.q - r);
+}
+void launch_mask_sample(blb_ctx* c, uint64_t* r_out, uint64_t* share, int n_ct, int tl, uint64_t seed, uint32_t tag) {
+  dim3 grid((c->n + 255) / 256, n_ct * tl);
+  k_mask_sample<<<grid, 256, 0, c->stream>>>(r_out, share, c->n, tl, c->mt, (uint32_t)seed, (uint32_t)(seed >> 32), tag);
+}
+
+// ---------------------------------------------------------------------------------------
+// Encoder (eq. ckks_encode) in double-double arithmetic.
+//   Slot j sits at zeta^(e_j), e_j = 5^j mod 2N = 4 u_j + 1.  With w_k = p_k + i p_{k+M}
+//   (M = N/2), p(zeta^(4u+1)) = sum_k zeta^k w_k eta^(uk), eta = exp(2 pi i / M), so
+//   w_k = zeta^-k (1/M) sum_u v_u eta^(-uk) with v_u the (real) slot value at u.
+//   Steps: scatter (v), radix-2 Stockham DFT of size M (exp(-i...)), finalize (twist, scale,
+//   round half away from zero, reduce into the limbs).
+// ---------------------------------------------------------------------------------------
+struct dd { double hi, lo; };
+__device__ __forceinline__ dd two_sum(double a, double b) {
+  const double s = a + b;
+  const double bb = s - a;
+  const double err = (a - (s - bb)) + (b - bb);
+  return dd{s, err};
+}
+__device__ __forceinline__ dd quick_two_sum(double a, double b) {
+  const double s = a + b;
+  return dd{s, b - (s - a)};
+}
+__device__ __forceinline__ dd dd_add(dd x, dd y) {
+  dd s = two_sum(x.hi, y.hi);
+  dd t = two_sum(x.lo, y.lo);
+  s.lo += t.hi;
+  s = quick_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return quick_two_sum(s.hi, s.lo);
+}
+__device__ __forceinline__ dd dd_neg(dd x) { return dd{-x.hi, -x.lo}; }
+__device__ __forceinline__ dd dd_mul(dd x, dd y) {
+  const double p = x.hi * y.hi;
+  double e = __builtin_fma(x.hi, y.hi, -p);
+  e += x.hi * y.lo + x.lo * y.hi;
+  return quick_two_sum(p, e);
+}
+__device__ __forceinline__ dd dd_mul_d(dd x, double y) {
+  const double p = x.hi * y;
+  double e = __builtin_fma(x.hi, y, -p);
+  e += x.lo * y;
+  return quick_two_sum(p, e);
+}
+struct cdd { dd re, im; };
+__device__ __forceinline__ cdd cdd_mul(cdd a, cdd b) {
+  return cdd{dd_add(dd_mul(a.re, b.re), dd_neg(dd_mul(a.im, b.im))), dd_add(dd_mul(a.re, b.im), dd_mul(a.im, b.re))};
+}
+__device__ __forceinline__ cdd cdd_add(cdd a, cdd b) { return cdd{dd_add(a.re, b.re), dd_add(a.im, b.im)}; }
+__device__ __forceinline__ cdd cdd_sub(cdd a, cdd b) { return cdd{dd_add(a.re, dd_neg(b.re)), dd_add(a.im, dd_neg(b.im))}; }
+__device__ __forceinline__ cdd ld_cdd(const double* p) { return cdd{dd{p[0], p[1]}, dd{p[2], p[3]}}; }
+__device__ __forceinline__ void st_cdd(double* p, cdd v) { p[0] = v.re.hi; p[1] = v.re.lo; p[2] = v.im.hi; p[3] = v.im.lo; }
+
+// scatter from a dense value array: vals[p][j] (n_vals per plaintext)
+__global__ void k_enc_scatter_dense(const double* vals, int n_vals, double* buf, const int32_t* slot_u, int M) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (j >= M) return;
+  const double v = j < n_vals ? vals[(size_t)p * n_vals + j] : 0.0;
+  double* o = buf + ((size_t)p * M + slot_u[j]) * 4;
+  o[0] = v; o[1] = 0.0; o[2] = 0.0; o[3] = 0.0;
+}
+
+// scatter of matmul_cp diagonal plaintexts: plaintext p = (bj, ai) in a chunk starting at p0:
+//   value at slot s = W{a c + ((u + t) mod c_eff), b c + (u mod c_out)}, u = ((s - r) mod S) / L',
+//   t = jB + i, r = j B L' (plaintext pre-rotated right by r).
+__global__ void k_enc_scatter_cp(const double* W, CpGeom g, int p0, double* buf, const int32_t* slot_u, int M) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int pl = blockIdx.y;
+  if (s >= M) return;
+  const int p = p0 + pl;
+  const int n_ai = g.n_in * g.B;
+  const int bj = p / n_ai, ai = p % n_ai;
+  const int b = bj / g.G, j = bj % g.G;
+  const int a = ai / g.B, i = ai % g.B;
+  const int t = j * g.B + i;
+  const int r = j * g.B * g.Lp;
+  const int slot = ((s - r) % M + M) % M;
+  const int u = slot / g.Lp;
+  const int row = a * g.c + (u + t) % g.c_eff;
+  const int col = b * g.c + (u % g.c_out);
+  const double v = (row < g.d_in && col < g.d_out) ? W[(size_t)row * g.d_out + col] : 0.0;
+  double* o = buf + ((size_t)pl * M + slot_u[s]) * 4;
+  o[0] = v; o[1] = 0.0; o[2] = 0.0; o[3] = 0.0;
+}
+
+// one radix-2 Stockham stage (forward sign) on [count][M] complex dd values
+__global__ void k_enc_stage(const double* in, double* out, const double* tw /* [M/2][4] eta^k */, int M, int ns) {
+  const int jj = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (jj >= M / 2) return;
+  const double* x = in + (size_t)p * M * 4;
+  double* y = out + (size_t)p * M * 4;
+  const int kpos = jj % ns;
+  const int tw_idx = kpos * (M / (2 * ns));
+  cdd w = ld_cdd(tw + (size_t)tw_idx * 4);
+  w.im = dd_neg(w.im);  // exp(-2 pi i k / (2 ns))
+  const cdd a = ld_cdd(x + (size_t)jj * 4);
+  const cdd b = cdd_mul(ld_cdd(x + (size_t)(jj + M / 2) * 4), w);
+  const int idx = (jj / ns) * 2 * ns + kpos;
+  st_cdd(y + (size_t)idx * 4, cdd_add(a, b));
+  st_cdd(y + (size_t)(idx + ns) * 4, cdd_sub(a, b));
+}
+
+__device__ __forceinline__ long long rhaz_dd(dd x, int* overflow) {
+  const bool neg = x.hi < 0.0;
+  if (neg) x = dd_neg(x);
+  if (!(x.hi < 4.0e18)) { *overflow = 1; return 0; }
+  const double f = floor(x.hi);
+  const double frac = (x.hi - f) + x.lo;
+  long long r = (long long)f + (long long)floor(frac + 0.5);
+  return neg ? -r : r;
+}
+
+// finalize: w_k = zeta^-k * y_k * (Delta / M); p_k = RHAZ(Re w_k), p_{k+M} = RHAZ(Im w_k);
+// residues into limbs 0..level of out[p][limb][N]
+__global__ void k_enc_final(const double* ybuf, const double* twist /* [M][4] zeta^-k */, double scale_over_m, int M, int nl,
+                            ModTable mt, const uint64_t* mods, uint64_t* out, int* overflow) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (k >= M) return;
+  const cdd y = ld_cdd(ybuf + ((size_t)p * M + k) * 4);
+  const cdd w = cdd_mul(y, ld_cdd(twist + (size_t)k * 4));
+  int of = 0;
+  const long long pr = rhaz_dd(dd_mul_d(w.re, scale_over_m), &of);
+  const long long pi = rhaz_dd(dd_mul_d(w.im, scale_over_m), &of);
+  if (of) atomicOr(overflow, 1);
+  const int n = 2 * M;
+  for (int i = 0; i < nl; ++i) {
+    const long long q = (long long)mods[i];
+    long long r0 = pr % q; if (r0 < 0) r0 += q;
+    long long r1 = pi % q; if (r1 < 0) r1 += q;
+    out[((size_t)p * nl + i) * n + k] = (uint64_t)r0;
+    out[((size_t)p * nl + i) * n + k + M] = (uint64_t)r1;
+  }
+}
+
+// Encodes `count` plaintexts already scattered into bufA ([count][M][4] doubles); output
+// coefficient-form residues out[count][nl][N].  bufB is a second buffer of the same size.
+int run_encode_core(blb_ctx* c, double* bufA, double* bufB, int count, double scale, int nl, uint64_t* out, int* d_overflow) {
+  const int M = c->n / 2;
+  double* in = bufA;
+  double* outb = bufB;
+  for (int ns = 1; ns < M; ns *= 2) {
+    dim3 grid((M / 2 + 255) / 256, count);
+    k_enc_stage<<<grid, 256, 0, c->stream>>>(in, outb, c->d_enc_tw, M, ns);
+    double* t = in; in = outb; outb = t;
+  }
+  dim3 grid((M + 255) / 256, count);
+  k_enc_final<<<grid, 256, 0, c->stream>>>(in, c->d_enc_twist, scale / (double)M, M, nl, c->mt, c->d_mods, out, d_overflow);
+  return 0;
+}
+void launch_enc_scatter_dense(blb_ctx* c, const double* vals, int n_vals, int count, double* buf) {
+  const int M = c->n / 2;
+  dim3 grid((M + 255) / 256, count);
+  k_enc_scatter_dense<<<grid, 256, 0, c->stream>>>(vals, n_vals, buf, c->d_slot_u, M);
+}
+void launch_enc_scatter_cp(blb_ctx* c, const double* W, CpGeom g, int p0, int count, double* buf) {
+  const int M = c->n / 2;
+  dim3 grid((M + 255) / 256, count);
+  k_enc_scatter_cp<<<grid, 256, 0, c->stream>>>(W, g, p0, buf, c->d_slot_u, M);
+}

@@ -1,0 +1,84 @@
+"""Workload definitions and seeded synthetic inputs.
+
+Shared by the tests, the benchmark and the smoke check.  Holds no CKKS arithmetic: only the
+parameter sets and the seeded numpy generators of the plaintext tensors (activations,
+weights, head matrices), with the shapes and value distributions of the paper's BERT-base /
+BERT-large / GPT-2 workloads (synthetic stand-ins for the GLUE inputs and pretrained weights).
+
+Seed rule: seed = 0xB1B0000 + 16 * config + role.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+ROLE_X, ROLE_W, ROLE_SK, ROLE_ENC, ROLE_KEYS, ROLE_MASK, ROLE_ARRIVALS = range(7)
+
+
+def seed_for(config: int, role: int) -> int:
+    return 0xB1B0000 + 16 * config + role
+
+
+@dataclass(frozen=True)
+class Params:
+    log_n: int
+    n_q: int
+    n_special: int
+    dnum: int
+    log_scale: int
+
+    @property
+    def n(self):
+        return 1 << self.log_n
+
+    @property
+    def scale(self):
+        return float(2 ** self.log_scale)
+
+
+# C1: plain matmul_cp, N=4096, 2 x 50-bit primes (+1 special, dnum 2), scale 2^30
+C1 = dict(params=Params(12, 2, 1, 2, 30), L=32, d_in=32, d_out=32, x_dist="uniform", w_std=0.02)
+# C2: BERT-base fused linear op, N=8192, 3 x 50-bit primes + 1 special (dnum 3), scale 2^40
+C2 = dict(params=Params(13, 3, 1, 3, 40), L=128, d_in=768, d_out=768, x_dist="normal", w_std=0.02)
+# C3: attention matmul_cc, N=16384, 4 x 50-bit primes + 2 special (dnum 2), scale 2^40
+C3 = dict(params=Params(14, 4, 2, 2, 40), heads=12, L=128, d_head=64)
+
+
+def activations(config: int, L: int, d: int, dist: str) -> np.ndarray:
+    rng = np.random.default_rng(seed_for(config, ROLE_X))
+    if dist == "uniform":
+        return rng.uniform(-1.0, 1.0, (L, d))
+    return rng.normal(0.0, 1.0, (L, d))
+
+
+def weights(config: int, d_in: int, d_out: int, std: float) -> np.ndarray:
+    rng = np.random.default_rng(seed_for(config, ROLE_W))
+    return rng.normal(0.0, std, (d_in, d_out))
+
+
+def pack_spatial(X: np.ndarray, slots: int, a: int) -> np.ndarray:
+    """Spatial-first slot vector of ciphertext `a` for the L x D matrix X: element (i, j) sits in
+    ciphertext j // c at slot i + L' (j mod c), L' = 2^ceil(log2 L), c = slots / L'; when the padded
+    width D' = 2^ceil(log2 D) is below c the D' columns repeat c / D' times.  (A data layout,
+    not CKKS arithmetic: the oracle and the library each implement their own.)"""
+    L, D = X.shape
+    lp = 1 << int(np.ceil(np.log2(L)))
+    c = slots // lp
+    dp = 1 << int(np.ceil(np.log2(D)))
+    out = np.zeros(slots)
+    for u in range(c):
+        col = (u % dp) if dp < c else a * c + u
+        if col < D:
+            out[u * lp: u * lp + L] = X[:, col]
+    return out
+
+
+def unpack_spatial(vecs, L: int, D: int, slots: int) -> np.ndarray:
+    lp = 1 << int(np.ceil(np.log2(L)))
+    c = slots // lp
+    out = np.zeros((L, D))
+    for col in range(D):
+        b, u = divmod(col, c)
+        out[:, col] = vecs[b][u * lp: u * lp + L]
+    return out

@@ -1,0 +1,244 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle, word for word.
+
+Ciphertexts are compared in canonical coefficient form (blb_export) against the oracle's
+coefficient-form words.  Encryption randomness comes from the same seeds on both sides
+(each side implements Philox4x32-10 itself).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def blb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2508_19525_amd as B
+    B.lib()
+    return B
+
+
+class Ctx:
+    """GPU context + oracle context with the same parameters"""
+
+    def __init__(self, B, orc, log_n, n_q, n_sp, dnum):
+        self.B, self.orc = B, orc
+        self.n = 1 << log_n
+        self.n_q = n_q
+        self.h = B.blb_ctx_create(log_n, n_q, n_sp, dnum, 0, torch.cuda.current_stream().cuda_stream)
+        self.o = orc.Context(log_n, n_q, n_sp, dnum)
+        self.keep = []
+
+    def close(self):
+        torch.cuda.synchronize()
+        self.B.blb_ctx_destroy(self.h)
+
+    def ct(self, level, degree=1):
+        c, t = self.B.new_ct(self.n, level, degree)
+        self.keep.append(t)
+        return c
+
+    def pt_dev(self, level):
+        t = torch.empty((level + 1) * self.n, dtype=torch.int64, device="cuda")
+        self.keep.append(t)
+        return t
+
+    def upload_words(self, words):
+        a = np.ascontiguousarray(words, dtype=np.uint64)
+        t = torch.from_numpy(a.view(np.int64).reshape(-1).copy()).cuda()
+        self.keep.append(t)
+        return t
+
+    def import_ct(self, words, level, degree=1):
+        c = self.ct(level, degree)
+        self.B.blb_import(self.h, words, c)
+        return c
+
+    def export(self, c):
+        torch.cuda.synchronize()
+        return self.B.blb_export(self.h, c, self.n)
+
+
+@pytest.fixture(scope="module")
+def c1(blb, orc):
+    x = Ctx(blb, orc, 12, 2, 1, 2)
+    yield x
+    x.close()
+
+
+@pytest.fixture(scope="module")
+def c2s(blb, orc):
+    x = Ctx(blb, orc, 13, 3, 1, 3)
+    yield x
+    x.close()
+
+
+@pytest.fixture(scope="module")
+def c3s(blb, orc):
+    x = Ctx(blb, orc, 14, 4, 2, 2)
+    yield x
+    x.close()
+
+
+def _ctxs(request, names):
+    return [request.getfixturevalue(n) for n in names]
+
+
+def test_moduli_match_oracle(c1, c2s, c3s):
+    for c in (c1, c2s, c3s):
+        m = c.B.blb_ctx_moduli(c.h, len(c.o.moduli))
+        assert np.array_equal(m, c.o.moduli)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2s", "c3s"])
+def test_encode_matches_oracle(request, name):
+    c = request.getfixturevalue(name)
+    rng = np.random.default_rng(1)
+    top = c.n_q - 1
+    for scale, dist in [(2.0 ** 40, "normal"), (2.0 ** 30, "uniform"), (float(c.o.q[top]), "weights")]:
+        if dist == "normal":
+            v = rng.normal(0, 1, c.n // 2)
+        elif dist == "uniform":
+            v = rng.uniform(-1, 1, c.n // 2 - 5)  # ragged: trailing slots zero
+        else:
+            v = rng.normal(0, 0.02, c.n // 2)
+        pt = c.pt_dev(top)
+        c.B.blb_encode(c.h, v, scale, top, pt)
+        torch.cuda.synchronize()
+        got = pt.cpu().numpy().view(np.uint64).reshape(top + 1, c.n)
+        want = c.o.encode_rns(v, scale, top)
+        mism = int((got != want).sum())
+        assert mism == 0, f"{mism} encode mismatches at scale {scale}"
+
+
+@pytest.mark.parametrize("name", ["c1", "c2s", "c3s"])
+def test_encrypt_decrypt_match_oracle(request, name):
+    c = request.getfixturevalue(name)
+    keys_o = c.orc.Keys(c.o, 11)
+    keys_g = c.B.blb_keygen(c.h, 11, [])
+    rng = np.random.default_rng(2)
+    for level in (c.n_q - 1, 0):
+        want_pt = c.o.encode_rns(rng.normal(0, 1, c.n // 2), 2.0 ** 30, level)
+        ct = c.ct(level)
+        c.B.blb_encrypt(c.h, keys_g, c.upload_words(want_pt), level, 2.0 ** 30, 77, 5, ct)
+        got = c.export(ct)
+        want = keys_o.encrypt(want_pt, level, 77, 5)
+        assert np.array_equal(got, want)
+        dec = c.pt_dev(level)
+        c.B.blb_decrypt(c.h, keys_g, ct, dec)
+        torch.cuda.synchronize()
+        assert np.array_equal(dec.cpu().numpy().view(np.uint64).reshape(level + 1, c.n), keys_o.decrypt(want, level))
+    c.B.blb_keys_destroy(keys_g)
+
+
+@pytest.mark.parametrize("name,steps", [("c1", [1, 5, -3]), ("c2s", [128, 1024, -1]), ("c3s", [128, 3, -128])])
+def test_rotate_matches_oracle(request, name, steps):
+    c = request.getfixturevalue(name)
+    keys_o = c.orc.Keys(c.o, 21, [c.o.galois_elt(s) for s in steps])
+    keys_g = c.B.blb_keygen(c.h, 21, steps)
+    rng = np.random.default_rng(3)
+    for level in sorted({c.n_q - 1, 1, 0}):
+        if level >= c.n_q:
+            continue
+        m = rng.normal(0, 1, c.n // 2)
+        want_ct = keys_o.encrypt(c.o.encode_rns(m, 2.0 ** 30, level), level, 9, 0)
+        ct = c.import_ct(want_ct, level)
+        for s in steps:
+            out = c.ct(level)
+            c.B.blb_rotate(c.h, keys_g, ct, s, out)
+            got = c.export(out)
+            want = keys_o.rotate(want_ct, level, s)
+            assert np.array_equal(got, want), f"rotation {s} at level {level}"
+    c.B.blb_keys_destroy(keys_g)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2s", "c3s"])
+def test_rescale_matches_oracle(request, name):
+    c = request.getfixturevalue(name)
+    rng = np.random.default_rng(4)
+    for level in range(c.n_q - 1, 0, -1):
+        words = np.stack([np.stack([rng.integers(0, int(q), c.n, dtype=np.uint64) for q in c.o.q[: level + 1]]) for _ in range(2)])
+        ct = c.import_ct(words, level)
+        out = c.ct(level - 1)
+        c.B.blb_rescale(c.h, ct, out)
+        assert out.level == level - 1
+        assert np.array_equal(c.export(out), c.o.rescale(words, level))
+
+
+def _cp_case(c, L, d_in, d_out, level, seed, x_std=None):
+    B, orc = c.B, c.orc
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-1, 1, (L, d_in)) if x_std is None else rng.normal(0, x_std, (L, d_in))
+    W = rng.normal(0, 0.02, (d_in, d_out))
+    g = c.o.cp_geometry(L, d_in, d_out)
+    gal = c.o.cp_galois(L, d_in, d_out)
+    steps = [i * g["Lp"] for i in range(1, g["B"])] + [j * g["B"] * g["Lp"] for j in range(1, g["G"])]
+    keys_o = orc.Keys(c.o, 31, gal)
+    keys_g = B.blb_keygen(c.h, 31, steps)
+    scale = 2.0 ** 30
+    X_words = np.stack([keys_o.encrypt(c.o.encode_rns(c.o.pack_spatial(X, a), scale, level), level, 100, a) for a in range(g["n_in"])])
+    Xc = []
+    for a in range(g["n_in"]):
+        ct = c.import_ct(X_words[a], level)
+        ct.scale = scale
+        Xc.append(ct)
+    plan = B.blb_plan_matmul_cp(c.h, W, L, level)
+    info = B.blb_plan_info(plan)
+    assert info == g
+    Yc = [c.ct(level - 1) for _ in range(g["n_out"])]
+    B.blb_matmul_cp(c.h, keys_g, plan, Xc, Yc)
+    return dict(X=X, W=W, g=g, keys_o=keys_o, keys_g=keys_g, X_words=X_words, Yc=Yc, plan=plan, scale=scale)
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 32), (20, 40, 24), (5, 96, 70)])
+def test_matmul_cp_matches_oracle_c1(c1, shape):
+    L, d_in, d_out = shape
+    r = _cp_case(c1, L, d_in, d_out, 1, sum(shape))
+    want = r["keys_o"].matmul_cp(r["X_words"], 1, r["W"], L)
+    for b in range(r["g"]["n_out"]):
+        assert np.array_equal(c1.export(r["Yc"][b]), want[b]), f"output {b}"
+    c1.B.blb_plan_destroy(r["plan"])
+    c1.B.blb_keys_destroy(r["keys_g"])
+
+
+def test_matmul_cp_matches_oracle_n8192_ragged(c2s):
+    """N = 8192, three primes, ragged L and widths spanning several output ciphertexts"""
+    L, d_in, d_out = 100, 96, 80
+    r = _cp_case(c2s, L, d_in, d_out, 2, 7, x_std=1.0)
+    want = r["keys_o"].matmul_cp(r["X_words"], 2, r["W"], L)
+    for b in range(r["g"]["n_out"]):
+        assert np.array_equal(c2s.export(r["Yc"][b]), want[b]), f"output {b}"
+    # decoded accuracy against FP64
+    vecs = []
+    for b in range(r["g"]["n_out"]):
+        pt = c2s.pt_dev(1)
+        c2s.B.blb_decrypt(c2s.h, r["keys_g"], r["Yc"][b], pt)
+        vecs.append(c2s.B.blb_decode(c2s.h, pt, 1, r["scale"], c2s.n // 2))
+    from paper_2508_19525_amd.workloads import unpack_spatial
+    got = unpack_spatial(vecs, L, d_out, c2s.n // 2)
+    assert np.abs(got - r["X"] @ r["W"]).max() < 2.0 ** -10
+    c2s.B.blb_plan_destroy(r["plan"])
+    c2s.B.blb_keys_destroy(r["keys_g"])
+
+
+@pytest.mark.parametrize("name", ["c1", "c2s"])
+def test_mask_to_share_matches_oracle(request, name):
+    c = request.getfixturevalue(name)
+    rng = np.random.default_rng(5)
+    keys_o = c.orc.Keys(c.o, 41)
+    level = c.n_q - 1
+    words = [keys_o.encrypt(c.o.encode_rns(rng.normal(0, 1, c.n // 2), 2.0 ** 30, level), level, 3, t) for t in range(3)]
+    for target in (level, 0):
+        cts = [c.import_ct(w, level) for w in words]
+        share = torch.zeros(3 * (target + 1) * c.n, dtype=torch.int64, device="cuda")
+        c.B.blb_mask_to_share(c.h, cts, 1234, target, share)
+        torch.cuda.synchronize()
+        sh = share.cpu().numpy().view(np.uint64).reshape(3, target + 1, c.n)
+        for t in range(3):
+            masked, want_share = c.o.mask_to_share(words[t], level, target, 1234, t)
+            assert cts[t].level == target
+            assert np.array_equal(c.export(cts[t]), masked)
+            assert np.array_equal(sh[t], want_share)
