@@ -87,6 +87,10 @@ def lib():
             "orc_matmul_cp": (C.c_int, [vp, _u64p, C.c_int, _f64p, C.c_int, C.c_int, C.c_int, C.c_void_p, _u64p]),
             "orc_cp_galois": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, _u64p]),
             "orc_mask_to_share": (None, [vp, _u64p, C.c_int, C.c_int, C.c_uint64, C.c_uint32, _u64p, _u64p]),
+            "orc_num_threads": (C.c_int, []),
+            "orc_cc_geometry": (None, [vp, C.c_int, C.c_int, C.c_int, _i32p]),
+            "orc_matmul_cc": (C.c_int, [vp, _u64p, _u64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, _u64p]),
+            "orc_cc_galois": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, _u64p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -94,6 +98,10 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def _c(a, dt):
@@ -237,6 +245,38 @@ class Context:
         k = lib().orc_cp_galois(self._p, L, d_in, d_out, out)
         return out[:k].copy()
 
+    # ---- matmul_cc geometry ----
+    def cc_geometry(self, H_g, L, d) -> dict:
+        g = np.zeros(4, np.int32)
+        lib().orc_cc_geometry(self._p, H_g, L, d, g)
+        return dict(zip(["Lp", "c", "n_ct", "n_out"], [int(v) for v in g]))
+
+    def cc_galois(self, H_g, L, d) -> np.ndarray:
+        out = np.zeros(4096, np.uint64)
+        k = lib().orc_cc_galois(self._p, H_g, L, d, out)
+        return out[:k].copy()
+
+    def pack_mhp(self, mats, H_g, L, d, a, operand):
+        """Multi-head packing of ciphertext a for one head group: operand 'A' puts A_h{i, a c + kappa}
+        at slot i + L'(h + H_g kappa); operand 'Bp' puts B_h{a c + kappa, (i + kappa) mod L'} there
+        (B_h = mats[h], d x L, rows pre-rotated by kappa)."""
+        g = self.cc_geometry(H_g, L, d)
+        lp, cc = g["Lp"], g["c"]
+        v = np.zeros(self.slots)
+        for h in range(H_g):
+            for kap in range(cc):
+                k = a * cc + kap
+                if k >= d:
+                    continue
+                base = lp * (h + H_g * kap)
+                for i in range(lp):
+                    if operand == "A":
+                        v[base + i] = mats[h][i, k] if i < L else 0.0
+                    else:
+                        j = (i + kap) % lp
+                        v[base + i] = mats[h][k, j] if j < L else 0.0
+        return v
+
     def mask_to_share(self, ct, level: int, target_level: int, seed: int, ct_id: int):
         masked = np.zeros((2, target_level + 1, self.n), np.uint64)
         share = np.zeros((target_level + 1, self.n), np.uint64)
@@ -294,6 +334,21 @@ class Keys:
         if lib().orc_relinearize(self._p, _c(ct3, np.uint64), level, out) != 0:
             raise KeyError("missing relinearisation key")
         return out
+
+    def matmul_cc(self, A_cts, Bp_cts, level: int, H_g: int, L: int, d: int, outputs=None) -> np.ndarray:
+        """One head group; A_cts / Bp_cts: [n_ct][2][level+1][N]; returns [n_out][2][level-2][N]"""
+        c = self.ctx
+        g = c.cc_geometry(H_g, L, d)
+        O = np.zeros((g["n_out"], 2, level - 2, c.n), np.uint64)
+        mask = None
+        if outputs is not None:
+            m = np.zeros(g["n_out"], np.uint8)
+            m[list(outputs)] = 1
+            mask = m.ctypes.data_as(C.c_void_p)
+        rc = lib().orc_matmul_cc(self._p, _c(A_cts, np.uint64), _c(Bp_cts, np.uint64), g["n_ct"], level, H_g, L, d, mask, O)
+        if rc != 0:
+            raise ValueError(f"matmul_cc failed ({rc})")
+        return O
 
     def matmul_cp(self, X_cts, level: int, W, L: int, outputs=None) -> np.ndarray:
         c = self.ctx

@@ -849,3 +849,136 @@ void orc_mask_to_share(const orc_ctx* c, const uint64_t* ct, int level, int targ
     }
   }
 }
+
+/* number of OpenMP threads the oracle's parallel loops use */
+#include <omp.h>
+int orc_num_threads(void) { return omp_get_max_threads(); }
+
+/* ------------------------------------------------------------------------------------ */
+/* matmul_cc (Section "Efficient Protocol for Fused MatMuls", "Building Blocks": observations */
+/* 1-2, steps 1-3, and the Multi-Head Optimization), one head group, B pre-rotated        */
+/* ------------------------------------------------------------------------------------ */
+/* Packing of a group of H_g heads (reading of the multi-head packing, the layout figure is not
+ * available): with L' = 2^ceil(log2 L), c = S / (L' H_g) columns per ciphertext and n = d/c
+ * ciphertexts per operand, ciphertext a holds at slot i + L'(h + H_g kappa):
+ *   A_h{i, a c + kappa}                      (A = Q_h, spatial-first per head)
+ *   B_h{a c + kappa, (i + kappa) mod L'}     (B = K_h^T rows, reduce-first, pre-rotated by kappa)
+ * Output ciphertext g (g < L'/c) holds at slot i + L'(h + H_g kappa'):
+ *   C_h{i, (i + g c + kappa') mod L'}        (diagonal packing: diagonal g c + kappa')       */
+void orc_cc_geometry(const orc_ctx* c, int H_g, int L, int d, int32_t* out /* [4] */) {
+  int s = c->n / 2;
+  int lp = 1 << ceil_log2(L);
+  int cc = s / (lp * H_g);
+  out[0] = lp; out[1] = cc; out[2] = (d + cc - 1) / cc; out[3] = lp / cc;
+}
+
+/* slot vectors of the masks */
+static void mask_lo(int s, int lp, int t, double* v) { for (int j = 0; j < s; ++j) v[j] = (j % lp) < lp - t ? 1.0 : 0.0; }
+static void mask_hi(int s, int lp, int t, double* v) { for (int j = 0; j < s; ++j) v[j] = (j % lp) >= lp - t ? 1.0 : 0.0; }
+static void mask_blk_ge(int s, int blk, int tau, double* v) { for (int j = 0; j < s; ++j) v[j] = (j / blk) >= tau ? 1.0 : 0.0; }
+static void mask_blk_lt(int s, int blk, int tau, double* v) { for (int j = 0; j < s; ++j) v[j] = (j / blk) < tau ? 1.0 : 0.0; }
+
+/* acc (+)= pt (.) ct  for a degree-1 ct at nl limbs (pt encoded from a slot vector) */
+static void mac_vec(const orc_ctx* c, uint64_t* acc, const double* vec, double delta, const uint64_t* ct, int level) {
+  int n = c->n, nl = level + 1;
+  uint64_t* pt = (uint64_t*)malloc(8 * (size_t)nl * n);
+  orc_encode_rns(c, vec, n / 2, delta, level, pt);
+  mac_pt(c, acc, pt, ct, nl);
+  free(pt);
+}
+
+/* tensor product accumulation: acc3 += (a0 r0, a0 r1 + a1 r0, a1 r1), all at nl limbs */
+static void tensor_acc(const orc_ctx* c, uint64_t* acc3, const uint64_t* a, const uint64_t* r, int nl) {
+  int n = c->n;
+  #pragma omp parallel for
+  for (int i = 0; i < nl; ++i) {
+    uint64_t q = c->mod[i];
+    uint64_t* t = (uint64_t*)malloc(8 * n);
+    const uint64_t *a0 = a + (size_t)i * n, *a1 = a + ((size_t)nl + i) * n;
+    const uint64_t *r0 = r + (size_t)i * n, *r1 = r + ((size_t)nl + i) * n;
+    uint64_t *d0 = acc3 + (size_t)i * n, *d1 = acc3 + ((size_t)nl + i) * n, *d2 = acc3 + ((size_t)2 * nl + i) * n;
+    polymul(c, i, a0, r0, t); for (int k = 0; k < n; ++k) d0[k] = addm(d0[k], t[k], q);
+    polymul(c, i, a0, r1, t); for (int k = 0; k < n; ++k) d1[k] = addm(d1[k], t[k], q);
+    polymul(c, i, a1, r0, t); for (int k = 0; k < n; ++k) d1[k] = addm(d1[k], t[k], q);
+    polymul(c, i, a1, r1, t); for (int k = 0; k < n; ++k) d2[k] = addm(d2[k], t[k], q);
+    free(t);
+  }
+}
+
+/* Pinned schedule, inputs at `level` (A_a and pre-rotated B'_a, n_ct each, [ct][2][level+1][N]):
+ *  step 2 (for t < L'): R_{a,t} = Rescale( Rot_l^t(B'_a) (.) M^lo_t + Rot_r^{L'-t}(B'_a) (.) M^hi_t ),
+ *          masks encoded at q_level * 2^10 (t = 0: B'_a times the all-ones mask);
+ *          T_t = Rescale( Relin( sum_a Drop(A_a) (x) R_{a,t} ) )   (summed before relinearising)
+ *  step 3 (t = g c + tau): V_t = Rot_r^{tau H_g L'}(T_t);
+ *          O_g += V_t (.) M^{>=tau};  O_{(g+1) mod (L'/c)} += V_t (.) M^{<tau}  (masks at q_{level-2});
+ *          O_g = Rescale(O_g).
+ * Output: L'/c cts at level-3, [g][2][level-2][N].  out_mask (NULL = all) selects the outputs;
+ * only the t that feed them are computed. */
+int orc_matmul_cc(const orc_keys* K, const uint64_t* A, const uint64_t* Bp, int n_ct, int level, int H_g, int L, int d,
+                  const uint8_t* out_mask, uint64_t* O) {
+  const orc_ctx* c = K->c;
+  int n = c->n, s = n / 2;
+  if (level < 3) return -2;
+  int32_t geo[4]; orc_cc_geometry(c, H_g, L, d, geo);
+  int lp = geo[0], cc = geo[1], n_out = geo[3];
+  if (n_ct != geo[2] || cc < 1 || cc > lp || lp * H_g * cc != s) return -3;
+  int nl = level + 1, l2 = level - 1, l1 = level - 2;
+  size_t w3 = (size_t)2 * nl * n, w2 = (size_t)2 * (l2 + 1) * n, w1 = (size_t)2 * (l1 + 1) * n;
+  double dm2 = (double)c->mod[level] * 1024.0, dm3 = (double)c->mod[l1];
+  double* v = (double*)malloc(8 * s);
+  uint64_t* rot = (uint64_t*)malloc(8 * w3);
+  uint64_t* racc = (uint64_t*)malloc(8 * w3);
+  uint64_t* R = (uint64_t*)malloc(8 * w2);
+  uint64_t* Ad = (uint64_t*)malloc(8 * w2);
+  uint64_t* T3 = (uint64_t*)malloc(8 * (size_t)3 * (l2 + 1) * n);
+  uint64_t* T = (uint64_t*)malloc(8 * w2);
+  uint64_t* Tr = (uint64_t*)malloc(8 * w1);
+  uint64_t* V = (uint64_t*)malloc(8 * w1);
+  uint64_t* acc = (uint64_t*)calloc((size_t)n_out * w1, 8);
+  int rc = 0;
+  for (int t = 0; t < lp && rc == 0; ++t) {
+    int g = t / cc, tau = t % cc, g2 = (g + 1) % n_out;
+    int need = !out_mask || out_mask[g] || (tau > 0 && out_mask[g2]);
+    if (!need) continue;
+    memset(T3, 0, 8 * (size_t)3 * (l2 + 1) * n);
+    for (int a = 0; a < n_ct && rc == 0; ++a) {
+      const uint64_t* b = Bp + (size_t)a * w3;
+      memset(racc, 0, 8 * w3);
+      if (t == 0) {
+        mask_lo(s, lp, 0, v); mac_vec(c, racc, v, dm2, b, level);
+      } else {
+        if (orc_rotate(K, b, level, t, rot) != 0) { rc = -1; break; }
+        mask_lo(s, lp, t, v); mac_vec(c, racc, v, dm2, rot, level);
+        if (orc_rotate(K, b, level, -(int64_t)(lp - t), rot) != 0) { rc = -1; break; }
+        mask_hi(s, lp, t, v); mac_vec(c, racc, v, dm2, rot, level);
+      }
+      orc_rescale(c, racc, level, 2, R);
+      /* drop A_a to level-1: keep limbs 0..l2 of each poly */
+      const uint64_t* aa = A + (size_t)a * w3;
+      for (int p = 0; p < 2; ++p) memcpy(Ad + (size_t)p * (l2 + 1) * n, aa + (size_t)p * nl * n, 8 * (size_t)(l2 + 1) * n);
+      tensor_acc(c, T3, Ad, R, l2 + 1);
+    }
+    if (rc) break;
+    if (orc_relinearize(K, T3, l2, T) != 0) { rc = -1; break; }
+    orc_rescale(c, T, l2, 2, Tr);
+    if (tau == 0) memcpy(V, Tr, 8 * w1);
+    else if (orc_rotate(K, Tr, l1, -(int64_t)tau * H_g * lp, V) != 0) { rc = -1; break; }
+    int blk = lp * H_g;
+    if (!out_mask || out_mask[g]) { mask_blk_ge(s, blk, tau, v); mac_vec(c, acc + (size_t)g * w1, v, dm3, V, l1); }
+    if (tau > 0 && (!out_mask || out_mask[g2])) { mask_blk_lt(s, blk, tau, v); mac_vec(c, acc + (size_t)g2 * w1, v, dm3, V, l1); }
+  }
+  if (rc == 0)
+    for (int g = 0; g < n_out; ++g)
+      if (!out_mask || out_mask[g]) orc_rescale(c, acc + (size_t)g * w1, l1, 2, O + (size_t)g * 2 * l1 * n);
+  free(v); free(rot); free(racc); free(R); free(Ad); free(T3); free(T); free(Tr); free(V); free(acc);
+  return rc;
+}
+
+/* Galois elements of one group's matmul_cc: left t and right L'-t for t < L', right tau H_g L' */
+int orc_cc_galois(const orc_ctx* c, int H_g, int L, int d, uint64_t* out) {
+  int32_t geo[4]; orc_cc_geometry(c, H_g, L, d, geo);
+  int lp = geo[0], cc = geo[1], cnt = 0;
+  for (int t = 1; t < lp; ++t) { out[cnt++] = galois_left(c, t); out[cnt++] = galois_left(c, -(int64_t)(lp - t)); }
+  for (int tau = 1; tau < cc; ++tau) out[cnt++] = galois_left(c, -(int64_t)tau * H_g * lp);
+  return cnt;
+}

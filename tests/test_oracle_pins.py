@@ -511,3 +511,65 @@ def test_encoded_mask_concentration_negative_control(orc):
     ratio = p.std() / (q / np.sqrt(12 * n))
     assert abs(ratio - 1) < 0.05
     assert p.std() < q / np.sqrt(12) / 50
+
+
+# --------------------------------------------------------------------------------------
+# matmul_cc (multi-head, diagonal-packed output)
+# --------------------------------------------------------------------------------------
+def _cc_small(orc, H_g, L, d, seed):
+    c = orc.Context(12, 4, 2, 2)
+    g = c.cc_geometry(H_g, L, d)
+    rng = np.random.default_rng(seed)
+    Q = [rng.normal(0, 1, (L, d)) for _ in range(H_g)]
+    K = [rng.normal(0, 1, (L, d)) for _ in range(H_g)]
+    Bm = [k.T.copy() for k in K]
+    keys = orc.Keys(c, 5, c.cc_galois(H_g, L, d))
+    level, scale = 3, 2.0 ** 40
+    A = np.stack([keys.encrypt(c.encode_rns(c.pack_mhp(Q, H_g, L, d, a, "A"), scale, level), level, 10, a) for a in range(g["n_ct"])])
+    Bp = np.stack([keys.encrypt(c.encode_rns(c.pack_mhp(Bm, H_g, L, d, a, "Bp"), scale, level), level, 11, a) for a in range(g["n_ct"])])
+    return c, g, keys, Q, K, A, Bp, level, scale
+
+
+@pytest.mark.parametrize("H_g,L,d", [(2, 32, 64), (4, 20, 32)])
+def test_matmul_cc_decodes_to_qkt(orc, H_g, L, d):
+    """Decoded diagonal-packed output equals Q_h K_h^T (FP64) for every head, within 2^-20 at
+    the final scale ~2^40 (catches a wrong inner-rotation mask, a wrong step-3 block rotation
+    or a wrong output index g+1 for the wrapped blocks)."""
+    c, g, keys, Q, K, A, Bp, level, scale = _cc_small(orc, H_g, L, d, H_g + L)
+    O = keys.matmul_cc(A, Bp, level, H_g, L, d)
+    lp, cc = g["Lp"], g["c"]
+    # scale after the schedule: scale * (q3 2^10 / q3) * scale / q2 * (q1 / q1)
+    out_scale = scale * 1024.0 * scale / float(c.q[2])
+    got = [[np.zeros((lp, lp)) for _ in range(H_g)]]
+    for gi in range(g["n_out"]):
+        v = c.decode(keys.decrypt(O[gi], 0), 0, out_scale)
+        for h in range(H_g):
+            for kap in range(cc):
+                D = gi * cc + kap
+                for i in range(lp):
+                    got[0][h][i, (i + D) % lp] = v[i + lp * (h + H_g * kap)]
+    for h in range(H_g):
+        ref = Q[h] @ K[h].T
+        assert np.abs(got[0][h][:L, :L] - ref).max() < 2.0 ** -20 * 64
+        if L < lp:
+            assert np.abs(got[0][h][L:, :]).max() < 1e-4 and np.abs(got[0][h][:, L:]).max() < 1e-4
+
+
+def test_matmul_cc_counts():
+    """Theoretical ct-ct multiplication count m^2 d / s of the paper's Table complexity_compare
+    (BERT-large, s = 16384): 1024 for Q_h K_h^T and m^3 H / s = 2048 for Softmax x V_h; the
+    12-head BERT-base group split 8 + 4 at N = 16384 gives 1536 tensors (= 128^2 * 768 / 8192) and
+    2 x 128 relinearisations."""
+    rows = [l.split() for l in open(os.path.join(HERE, "golden", "complexity_bert_large.txt")) if l.strip() and l[0] != "#"]
+    for name, m, d, H, s, cm in rows:
+        m, d, H, s, cm = int(m), int(d), int(H), int(s), int(cm)
+        if name == "QK":
+            assert m * m * d // s == cm
+        else:
+            assert m ** 3 * H // s == cm
+    # this build's schedule: tensors = sum over groups of L' * n_ct
+    n_tensor = 0
+    for H_g in (8, 4):
+        c_ = 8192 // (128 * H_g)
+        n_tensor += 128 * (64 // c_)
+    assert n_tensor == 1536 == 128 * 128 * 768 // 8192
