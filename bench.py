@@ -1,15 +1,20 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the server-side BLB hot path on one MI355X.
 
-Workload (one step): the BERT-base fused linear operator -- encrypted X (128 x 768, N(0,1))
-times plaintext W (768 x 768, N(0, 0.02)) with matmul_cp (BSGS, hoisted baby steps), rescale,
-then CKKS-to-MPC mask-and-share of the 24 output ciphertexts.  RNS-CKKS with N = 8192,
-three 50-bit primes plus one special prime (dnum 3), scale 2^40.  Inputs (ciphertexts, keys,
-plaintext diagonals) are resident in HBM before the timed region.
+Headline workload (one step): the BERT-base fused linear operator -- encrypted X (128 x 768,
+N(0,1)) times plaintext W (768 x 768, N(0, 0.02)) with matmul_cp (BSGS, hoisted baby steps),
+rescale, then CKKS-to-MPC mask-and-share of the 24 output ciphertexts with a fresh mask seed
+per step.  RNS-CKKS with N = 8192, three 50-bit primes plus one special prime (dnum 3),
+scale 2^40.  Inputs (ciphertexts, keys, plaintext diagonals) are resident in HBM before the
+timed region; a step is one replay of the recorded graph executor (one graph launch).
 
-Prints one JSON line.  `value` = fused ops per second on one GPU; `roofline` covers the
-dominant kernel (the plaintext-streaming MAC, HBM-bound) timed with HIP events on the
-library's stream; `cpu_baseline` times the CPU oracle on a bounded sample of the same op.
+Also measured (extra fields): the same step issued eagerly (per-kernel HIP-event timing,
+used for the roofline of the dominant kernel), the 12-head attention matmul_cc
+(Q_h K_h^T, 128 tokens, N = 16384, 4 primes + 2 special) as ct-ct matmul/s, and the NTT
+throughput of all transforms inside the steps.
+
+Prints one JSON line.  `cpu_baseline` times the CPU oracle on a bounded sample of the
+headline op.
 """
 import argparse
 import json
@@ -29,9 +34,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_gpu(args):
-    import torch
-    import paper_2508_19525_amd as B
+def run_cp(args, B, torch):
     from paper_2508_19525_amd import workloads as wl
 
     cfg = wl.C2
@@ -40,8 +43,6 @@ def run_gpu(args):
     n, level = p.n, p.n_q - 1
     X = wl.activations(2, L, d_in, cfg["x_dist"])
     W = wl.weights(2, d_in, d_out, cfg["w_std"])
-
-    torch.cuda.init()
     stream = torch.cuda.current_stream().cuda_stream
     ctx = B.blb_ctx_create(p.log_n, p.n_q, p.n_special, p.dnum, 0, stream)
     t_setup = time.time()
@@ -65,13 +66,13 @@ def run_gpu(args):
         Y_cts.append(ct)
     share = torch.empty(g["n_out"] * level * n, dtype=torch.int64, device="cuda")
     torch.cuda.synchronize()
-    log(f"setup {time.time() - t_setup:.1f}s: plan {g}, library device bytes {B.blb_ctx_device_bytes(ctx) / 1e9:.2f} GB")
+    log(f"cp setup {time.time() - t_setup:.1f}s: plan {g}, library device bytes {B.blb_ctx_device_bytes(ctx) / 1e9:.2f} GB")
 
-    def step(k):
+    def eager_step(k):
         B.blb_matmul_cp(ctx, keys, plan, X_cts, Y_cts)
         B.blb_mask_to_share(ctx, Y_cts, wl.seed_for(2, wl.ROLE_MASK) + k, level - 1, share)
 
-    # accuracy check of the unmasked output (outside the timed region)
+    # accuracy of the unmasked output (outside the timed regions)
     B.blb_matmul_cp(ctx, keys, plan, X_cts, Y_cts)
     vecs = []
     dec = torch.empty(level * n, dtype=torch.int64, device="cuda")
@@ -85,52 +86,72 @@ def run_gpu(args):
     log(f"decoded max abs err {err:.3e}, mse {mse:.3e}")
 
     for k in range(args.warmup):
-        step(k)
+        eager_step(k)
     torch.cuda.synchronize()
-    log(f"warmup {args.warmup} done")
+    tune = {}
+    if not args.no_tune:
+        # autotuner: pick the MAC launch shape (results are bit-identical across variants)
+        B.blb_ctx_set_timing(ctx, True)
+        for var in range(5):
+            B.blb_ctx_set_knob(ctx, B.BLB_KNOB_MAC_VARIANT, var)
+            B.blb_ctx_reset_timing(ctx)
+            for k in range(3):
+                eager_step(500 + k)
+            ms, cnt, _ = B.blb_ctx_read_timing(ctx, B.BLB_T_CP_MAC)
+            tune[var] = ms / max(cnt, 1)
+        best = min(tune, key=tune.get)
+        B.blb_ctx_set_knob(ctx, B.BLB_KNOB_MAC_VARIANT, best)
+        B.blb_ctx_set_timing(ctx, False)
+        log(f"mac variants (avg ms): {tune} -> {best}")
+
+    # eager steps with per-kernel HIP events on the library stream
     B.blb_ctx_set_timing(ctx, True)
     B.blb_ctx_reset_timing(ctx)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(1000 + k)
+        eager_step(1000 + k)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dt = t1 - t0
-    log(f"timed {args.steps} steps in {dt:.3f}s")
-
+    dt_eager = time.perf_counter() - t0
     mac_ms, mac_n, _ = B.blb_ctx_read_timing(ctx, B.BLB_T_CP_MAC)
     ntt_ms, ntt_n, ntt_polys = B.blb_ctx_read_timing(ctx, B.BLB_T_NTT)
-    ks_ms, _, _ = B.blb_ctx_read_timing(ctx, B.BLB_T_KS_INNER)
-    mu_ms, _, _ = B.blb_ctx_read_timing(ctx, B.BLB_T_MODUP)
-    md_ms, _, _ = B.blb_ctx_read_timing(ctx, B.BLB_T_MODDOWN)
+    split = {}
+    for name, kind in [("cp_mac", B.BLB_T_CP_MAC), ("ntt", B.BLB_T_NTT), ("ks_inner", B.BLB_T_KS_INNER), ("modup", B.BLB_T_MODUP),
+                       ("moddown_conv", B.BLB_T_MODDOWN), ("mask", B.BLB_T_MASK), ("sum", B.BLB_T_EW)]:
+        split[name] = B.blb_ctx_read_timing(ctx, kind)[0] / args.steps
     B.blb_ctx_set_timing(ctx, False)
+    log(f"eager: {args.steps} steps in {dt_eager:.3f}s")
+
+    # graph executor: the whole step recorded once, one launch per step
+    ex = B.blb_exec_create_cp(ctx, keys, plan, X_cts, Y_cts, level - 1, share)
+    for k in range(args.warmup):
+        B.blb_exec_run(ex, wl.seed_for(2, wl.ROLE_MASK) + k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        B.blb_exec_run(ex, wl.seed_for(2, wl.ROLE_MASK) + 2000 + k)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"graph: {args.steps} steps in {dt:.3f}s ({B.blb_exec_device_bytes(ex) / 1e9:.2f} GB executor memory)")
 
     nl = level + 1
     n_ai, n_bj = g["n_in"] * g["B"], g["n_out"] * g["G"]
-    pt_bytes = n_ai * n_bj * nl * n * 8
-    rx_bytes = n_ai * 2 * nl * n * 8
-    inner_bytes = n_bj * 2 * nl * n * 8
-    mac_alg_bytes = pt_bytes + rx_bytes + inner_bytes
+    mac_alg_bytes = (n_ai * n_bj * nl * n + n_ai * 2 * nl * n + n_bj * 2 * nl * n) * 8
     mac_avg_s = mac_ms / 1e3 / max(mac_n, 1)
-    mac_gbps = mac_alg_bytes / mac_avg_s / 1e9
-    ntt_gbps = ntt_polys * 16 * n / (ntt_ms / 1e3) / 1e9 if ntt_ms > 0 else 0.0
-
     res = {
         "value": args.steps / dt,
         "ms_per_step": dt / args.steps * 1e3,
-        "err": err,
-        "mse": mse,
+        "eager_ops_s": args.steps / dt_eager,
+        "err": err, "mse": mse,
         "mac_avg_ms": mac_avg_s * 1e3,
-        "mac_gbps": mac_gbps,
+        "mac_gbps": mac_alg_bytes / mac_avg_s / 1e9,
         "mac_alg_bytes": mac_alg_bytes,
-        "ntt_gbps": ntt_gbps,
-        "ntt_launches_per_step": ntt_n / args.steps,
+        "ntt_gbps": ntt_polys * 16 * n / (ntt_ms / 1e3) / 1e9 if ntt_ms > 0 else 0.0,
         "ntt_polys_per_step": ntt_polys / args.steps,
-        "time_split_ms_per_step": {
-            "cp_mac": mac_ms / args.steps, "ntt": ntt_ms / args.steps, "ks_inner": ks_ms / args.steps,
-            "modup": mu_ms / args.steps, "moddown_conv": md_ms / args.steps},
-        "geometry": g,
+        "ntt_launches_per_step": ntt_n / args.steps,
+        "split": split,
+        "mac_variant": B.blb_ctx_get_knob(ctx, B.BLB_KNOB_MAC_VARIANT),
+        "mac_tune_ms": tune,
     }
     if args.copy_probe:
         # plain copy of 1 GiB: the reference point for the FETCH_SIZE / WRITE_SIZE counters
@@ -138,6 +159,97 @@ def run_gpu(args):
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
+    B.blb_exec_destroy(ex)
+    B.blb_plan_destroy(plan)
+    B.blb_keys_destroy(keys)
+    B.blb_ctx_destroy(ctx)
+    return res
+
+
+def run_cc(args, B, torch):
+    """12-head Q_h K_h^T (BERT-base shape, 128 tokens), N = 16384, 4 primes + 2 special (dnum 2)."""
+    from paper_2508_19525_amd import workloads as wl
+
+    cfg = wl.C3
+    p = cfg["params"]
+    heads, L, d = cfg["heads"], cfg["L"], cfg["d_head"]
+    n, level = p.n, p.n_q - 1
+    rng = np.random.default_rng(wl.seed_for(3, wl.ROLE_X))
+    Q = [rng.normal(0, 1, (L, d)) for _ in range(heads)]
+    Kt = [rng.normal(0, 1, (L, d)).T.copy() for _ in range(heads)]
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = B.blb_ctx_create(p.log_n, p.n_q, p.n_special, p.dnum, 0, stream)
+    t_setup = time.time()
+    steps_rot = B.blb_cc_rotations(ctx, heads, L)
+    keys = B.blb_keygen(ctx, wl.seed_for(3, wl.ROLE_KEYS), steps_rot)
+    plan = B.blb_plan_matmul_cc(ctx, heads, L, d, level)
+    info = B.blb_plan_cc_info(plan)
+    keep, A, Bp = [], [], []
+    pt = torch.empty((level + 1) * n, dtype=torch.int64, device="cuda")
+    h0 = 0
+    for grp in info["groups"]:
+        H = grp["H"]
+        for a in range(grp["n_ct"]):
+            for mats, op, dst, tag in ((Q, "A", A, 0), (Kt, "Bp", Bp, 1)):
+                B.blb_encode(ctx, wl.pack_mhp(mats[h0:h0 + H], H, L, d, a, op, n // 2), p.scale, level, pt)
+                ct, t = B.new_ct(n, level)
+                keep.append(t)
+                B.blb_encrypt(ctx, keys, pt, level, p.scale, wl.seed_for(3, wl.ROLE_ENC), 2 * (grp["ct0"] + a) + tag, ct)
+                dst.append(ct)
+        h0 += H
+    Cd = []
+    for o in range(info["n_out"]):
+        ct, t = B.new_ct(n, level - 3)
+        keep.append(t)
+        Cd.append(ct)
+    torch.cuda.synchronize()
+    log(f"cc setup {time.time() - t_setup:.1f}s: {len(steps_rot)} rotation keys, plan {info}, "
+        f"device bytes {B.blb_ctx_device_bytes(ctx) / 1e9:.2f} GB")
+    # accuracy
+    B.blb_matmul_cc(ctx, keys, plan, A, Bp, Cd)
+    err, h0, base = 0.0, 0, 0
+    dec = torch.empty(n, dtype=torch.int64, device="cuda")
+    for grp in info["groups"]:
+        vecs = []
+        for o in range(grp["n_out"]):
+            B.blb_decrypt(ctx, keys, Cd[base + o], dec)
+            vecs.append(B.blb_decode(ctx, dec, 0, Cd[base + o].scale, n // 2))
+        Cs = wl.unpack_diag(vecs, grp["H"], L, n // 2)
+        for h in range(grp["H"]):
+            err = max(err, float(np.abs(Cs[h] - Q[h0 + h] @ Kt[h0 + h]).max()))
+        h0 += grp["H"]
+        base += grp["n_out"]
+    log(f"cc decoded max abs err {err:.3e}")
+    # eager (timed, with kernel timing)
+    B.blb_matmul_cc(ctx, keys, plan, A, Bp, Cd)
+    torch.cuda.synchronize()
+    B.blb_ctx_set_timing(ctx, True)
+    B.blb_ctx_reset_timing(ctx)
+    steps = max(1, args.steps // 4)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        B.blb_matmul_cc(ctx, keys, plan, A, Bp, Cd)
+    torch.cuda.synchronize()
+    dt_eager = time.perf_counter() - t0
+    split = {}
+    for name, kind in [("ntt", B.BLB_T_NTT), ("ks_inner", B.BLB_T_KS_INNER), ("modup", B.BLB_T_MODUP), ("moddown_conv", B.BLB_T_MODDOWN),
+                       ("tensor", B.BLB_T_CC_TENSOR), ("masks", B.BLB_T_EW)]:
+        split[name] = B.blb_ctx_read_timing(ctx, kind)[0] / steps
+    ntt_ms, _, ntt_polys = B.blb_ctx_read_timing(ctx, B.BLB_T_NTT)
+    B.blb_ctx_set_timing(ctx, False)
+    ex = B.blb_exec_create_cc(ctx, keys, plan, A, Bp, Cd)
+    B.blb_exec_run(ex, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        B.blb_exec_run(ex, 0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"cc: eager {steps / dt_eager:.1f}/s, graph {steps / dt:.1f}/s")
+    res = {"value": steps / dt, "eager": steps / dt_eager, "ms": dt / steps * 1e3, "err": err, "split_ms": split,
+           "ntt_gbps": ntt_polys * 16 * n / (ntt_ms / 1e3) / 1e9 if ntt_ms > 0 else 0.0,
+           "rotation_keys": len(steps_rot), "groups": info["groups"]}
+    B.blb_exec_destroy(ex)
     B.blb_plan_destroy(plan)
     B.blb_keys_destroy(keys)
     B.blb_ctx_destroy(ctx)
@@ -147,8 +259,8 @@ def run_gpu(args):
 def run_cpu_baseline():
     """The oracle on a bounded sample: one of the 24 output ciphertexts (all its 32 diagonal
     groups, 768 plaintext encodes + MACs, its 3 giant-step rotations and the rescale) timed
-    directly; the 168 hoisted baby-step rotations that every output shares are estimated
-    from 8 timed oracle rotations.  Full op time = baby + 24 x per-output + 24 masks."""
+    directly; the 168 hoisted baby-step rotations that every output shares are priced from
+    8 timed oracle rotations.  Full op time = baby + 24 x per-output + 24 masks."""
     import oracle
     from paper_2508_19525_amd import workloads as wl
     cfg = wl.C2
@@ -193,13 +305,19 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cc", action="store_true", help="skip the matmul_cc measurement")
+    ap.add_argument("--no-tune", action="store_true", help="skip the MAC launch-shape autotuner")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB plain copy (counter reference)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(the path shards by independent instances: see the design notes)"}))
         sys.exit(2)
-    r = run_gpu(args)
+    import torch
+    import paper_2508_19525_amd as B
+    torch.cuda.init()
+    r = run_cp(args, B, torch)
+    cc = None if args.no_cc else run_cc(args, B, torch)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -220,17 +338,23 @@ def main():
         "data": "synthetic (seeded X ~ N(0,1), W ~ N(0,0.02); no GLUE data or pretrained weights)",
         "config": {
             "workload": "BERT-base fused linear op: Enc(X 128x768) x W 768x768, rescale, mask-to-share of 24 cts; "
-                        "RNS-CKKS N=8192, 3x50-bit q + 1 special, dnum 3, scale 2^40",
+                        "RNS-CKKS N=8192, 3x50-bit q + 1 special, dnum 3, scale 2^40; one graph launch per step",
             "global_batch": 1, "seq_len": 128, "parallelism": "none (1 GPU)"},
         "roofline": {
             "bound": "hbm", "achieved": r["mac_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": r["mac_gbps"] / HBM_PEAK_GBPS, "traffic": None,
             "kernel": "k_cp_mac (plaintext-streaming ct-pt MAC)",
             "alg_bytes_per_launch": r["mac_alg_bytes"], "avg_launch_ms": r["mac_avg_ms"]},
+        "eager_value": r["eager_ops_s"],
         "ntt": {"GBps": r["ntt_gbps"], "frac_hbm_peak": r["ntt_gbps"] / HBM_PEAK_GBPS,
                 "polys_per_step": r["ntt_polys_per_step"], "launches_per_step": r["ntt_launches_per_step"]},
-        "time_split_ms_per_step": r["time_split_ms_per_step"],
+        "time_split_ms_per_step": r["split"],
+        "autotune": {"mac_variant": r["mac_variant"], "mac_avg_ms_by_variant": r["mac_tune_ms"]},
         "accuracy": {"max_abs_err": r["err"], "mse": r["mse"], "tolerance": 2.0 ** -20},
+        "matmul_cc": None if cc is None else {
+            "metric": "ct-ct matmul/s (12-head Q_h K_h^T, 128 tokens, N=16384, 4 primes + 2 special)",
+            "value": cc["value"], "eager_value": cc["eager"], "ms": cc["ms"], "max_abs_err": cc["err"],
+            "ntt_GBps": cc["ntt_gbps"], "split_ms": cc["split_ms"], "rotation_keys": cc["rotation_keys"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

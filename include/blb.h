@@ -73,6 +73,22 @@ int blb_ctx_moduli(const blb_ctx* ctx, uint64_t* out);
 uint64_t blb_ctx_device_bytes(const blb_ctx* ctx);
 const char* blb_status_str(int code);
 
+/* ---- kernel timing (HIP events on the context stream) ----------------------------------
+ * When enabled, every launch of the listed kernel families is bracketed by HIP events.
+ * blb_ctx_read_timing synchronises the stream and returns, for one family, the summed
+ * elapsed milliseconds, the number of launches and the summed work units (polynomials for
+ * the NTT family, output ciphertext-limbs x coefficients for the others). */
+enum { BLB_T_CP_MAC = 0, BLB_T_NTT = 1, BLB_T_KS_INNER = 2, BLB_T_MODUP = 3, BLB_T_MODDOWN = 4, BLB_T_MASK = 5,
+       BLB_T_EW = 6, BLB_T_CC_TENSOR = 7, BLB_T_KINDS = 8 };
+int blb_ctx_set_timing(blb_ctx* ctx, int enable);
+int blb_ctx_read_timing(blb_ctx* ctx, int kind, double* total_ms, int64_t* launches, double* units);
+int blb_ctx_reset_timing(blb_ctx* ctx);
+
+/* ---- launch-shape knobs (never change a result bit; chosen by the autotuner) ------------ */
+enum { BLB_KNOB_MAC_VARIANT = 0, BLB_KNOB_KINDS = 1 };
+int blb_ctx_set_knob(blb_ctx* ctx, int knob, int value);
+int blb_ctx_get_knob(const blb_ctx* ctx, int knob);
+
 /* ---- keys (Preliminaries, "Rotation"; hybrid key switching as the reading of the library
  * the paper builds on) ------------------------------------------------------------------- */
 /* Ternary secret from `seed`; relinearisation key (target s^2); one Galois key per entry of
@@ -119,11 +135,50 @@ int blb_plan_info(const blb_plan* plan, int32_t* info8);
 int blb_matmul_cp(blb_ctx* ctx, const blb_keys* keys, const blb_plan* plan, const blb_ct* X, int n_in,
                   blb_ct* Y, int n_out);
 
+/* ---- matmul_cc (Section "Efficient Protocol for Fused MatMuls": observations 1-2, the three
+ * steps and the Multi-Head Optimization; output in diagonal packing) ---------------------
+ * Heads are split into power-of-two groups, largest first (12 = 8 + 4).  For a group of H heads
+ * with L' = 2^ceil(log2 L) and c = (N/2) / (L' H) columns per ciphertext, operand ciphertext a
+ * of the group holds at slot i + L'(h + H kappa):
+ *     A:  A_h{i, a c + kappa}                      (Q_h, spatial-first per head)
+ *     B': B_h{a c + kappa, (i + kappa) mod L'}      (K_h^T rows, reduce-first, step 1 applied by
+ *                                                   the client before encryption)
+ * and output ciphertext g (g < L'/c) of the group holds C_h{i, (i + g c + kappa) mod L'}.
+ * Operands are at the plan's level (>= 3); outputs come out 3 levels lower.
+ * Step 2 rotations per group: 2 (L'-1) per B' ciphertext (hoisted); step 3: L' - L'/c. */
+/* Rotation steps the keys must cover (left t, right L'-t, right tau H L'); returns the count
+ * written to steps (or needed, when steps is NULL). */
+int blb_cc_rotations(const blb_ctx* ctx, int n_heads, int L, int32_t* steps, int cap);
+/* Masks of steps 2 and 3 encoded on the device (step 2 at scale q_level 2^10, step 3 at
+ * q_{level-2}). */
+int blb_plan_matmul_cc(blb_ctx* ctx, int n_heads, int L, int d_head, int level, blb_plan** out);
+/* info: L', n_ct, n_out, then per group (H, c, n_ct, n_out, first ct); returns group count. */
+int blb_plan_cc_info(const blb_plan* plan, int32_t* info, int cap);
+/* C_g for every group; n_ct operands each (groups concatenated), n_out outputs. */
+int blb_matmul_cc(blb_ctx* ctx, const blb_keys* keys, const blb_plan* plan, const blb_ct* A, const blb_ct* Bp, int n_ct,
+                  blb_ct* C_diag, int n_out);
+
 /* ---- CKKS-to-MPC mask-and-share (Algorithm ckks2mpc, step 1; functionality F_C2M) ------- */
 /* For each ciphertext t < n_ct: reduce to target_level (dropping top limbs) if lower, sample
  * r uniform in R_{Q_target} (Philox, object id t), set c0 <- c0 + r in place and write the
  * server share -r mod q_i in coefficient form to share_dev[t][limb][N]. */
 int blb_mask_to_share(blb_ctx* ctx, blb_ct* cts, int n_ct, uint64_t seed, int target_level, uint64_t* share_dev);
+
+/* ---- graph executors -------------------------------------------------------------------
+ * One fused operator invocation over fixed ciphertext buffers (matmul_cp or matmul_cc,
+ * optionally followed by mask-and-share of its outputs to mask_target_level; -1 = no mask)
+ * recorded into a HIP graph.  Scratch and descriptor tables are owned by the executor, so a
+ * replay issues a single graph launch on the context stream.  The mask seed is a replay
+ * parameter (fresh masks per run).  The output blb_ct structs are updated (level, scale) at
+ * creation.  Buffers and keys passed at creation must stay alive while the executor is used. */
+typedef struct blb_exec blb_exec;
+int blb_exec_create_cp(blb_ctx* ctx, const blb_keys* keys, const blb_plan* plan, const blb_ct* X, int n_in, blb_ct* Y, int n_out,
+                       int mask_target_level, uint64_t* share_dev, blb_exec** out);
+int blb_exec_create_cc(blb_ctx* ctx, const blb_keys* keys, const blb_plan* plan, const blb_ct* A, const blb_ct* Bp, int n_ct,
+                       blb_ct* C_diag, int n_out, int mask_target_level, uint64_t* share_dev, blb_exec** out);
+int blb_exec_run(blb_exec* exec, uint64_t mask_seed);
+uint64_t blb_exec_device_bytes(const blb_exec* exec);
+void blb_exec_destroy(blb_exec* exec);
 
 #ifdef __cplusplus
 }

@@ -41,6 +41,11 @@ _SIGS = {
     "blb_ctx_destroy": (None, [C.c_void_p]),
     "blb_ctx_moduli": (C.c_int, [C.c_void_p, C.c_void_p]),
     "blb_ctx_device_bytes": (C.c_uint64, [C.c_void_p]),
+    "blb_ctx_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
+    "blb_ctx_read_timing": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    "blb_ctx_reset_timing": (C.c_int, [C.c_void_p]),
+    "blb_ctx_set_knob": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    "blb_ctx_get_knob": (C.c_int, [C.c_void_p, C.c_int]),
     "blb_keygen": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.POINTER(C.c_void_p)]),
     "blb_keys_destroy": (None, [C.c_void_p]),
     "blb_galois_elt": (C.c_uint64, [C.c_void_p, C.c_int32]),
@@ -58,6 +63,18 @@ _SIGS = {
     "blb_plan_info": (C.c_int, [C.c_void_p, C.c_void_p]),
     "blb_matmul_cp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.c_int, C.POINTER(blb_ct), C.c_int]),
     "blb_mask_to_share": (C.c_int, [C.c_void_p, C.POINTER(blb_ct), C.c_int, C.c_uint64, C.c_int, C.c_void_p]),
+    "blb_cc_rotations": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int]),
+    "blb_plan_matmul_cc": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)]),
+    "blb_plan_cc_info": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "blb_matmul_cc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.POINTER(blb_ct), C.c_int,
+                                C.POINTER(blb_ct), C.c_int]),
+    "blb_exec_create_cp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.c_int, C.POINTER(blb_ct), C.c_int,
+                                     C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "blb_exec_create_cc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.POINTER(blb_ct), C.c_int,
+                                     C.POINTER(blb_ct), C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "blb_exec_run": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "blb_exec_device_bytes": (C.c_uint64, [C.c_void_p]),
+    "blb_exec_destroy": (None, [C.c_void_p]),
 }
 
 
@@ -124,6 +141,35 @@ def blb_ctx_moduli(ctx, count):
 
 def blb_ctx_device_bytes(ctx):
     return int(lib().blb_ctx_device_bytes(ctx))
+
+
+BLB_T_CP_MAC, BLB_T_NTT, BLB_T_KS_INNER, BLB_T_MODUP, BLB_T_MODDOWN, BLB_T_MASK, BLB_T_EW, BLB_T_CC_TENSOR = range(8)
+
+
+def blb_ctx_set_timing(ctx, enable):
+    _check(lib().blb_ctx_set_timing(ctx, 1 if enable else 0), "blb_ctx_set_timing")
+
+
+def blb_ctx_read_timing(ctx, kind):
+    """(total_ms, launches, units) for one kernel family"""
+    ms, n, u = C.c_double(), C.c_int64(), C.c_double()
+    _check(lib().blb_ctx_read_timing(ctx, kind, C.byref(ms), C.byref(n), C.byref(u)), "blb_ctx_read_timing")
+    return ms.value, n.value, u.value
+
+
+def blb_ctx_reset_timing(ctx):
+    _check(lib().blb_ctx_reset_timing(ctx), "blb_ctx_reset_timing")
+
+
+BLB_KNOB_MAC_VARIANT = 0
+
+
+def blb_ctx_set_knob(ctx, knob, value):
+    _check(lib().blb_ctx_set_knob(ctx, knob, value), "blb_ctx_set_knob")
+
+
+def blb_ctx_get_knob(ctx, knob):
+    return int(lib().blb_ctx_get_knob(ctx, knob))
 
 
 def blb_keygen(ctx, seed, rot_steps=()):
@@ -209,6 +255,86 @@ def blb_mask_to_share(ctx, cts, seed, target_level, share_dev):
     _check(lib().blb_mask_to_share(ctx, arr, len(cts), seed, target_level, _ptr(share_dev)), "blb_mask_to_share")
     for i in range(len(cts)):
         cts[i].level = arr[i].level
+
+
+def blb_cc_rotations(ctx, n_heads, L):
+    k = lib().blb_cc_rotations(ctx, n_heads, L, None, 0)
+    if k < 0:
+        raise BlbError(k, "blb_cc_rotations")
+    out = np.zeros(max(k, 1), np.int32)
+    _check(0 if lib().blb_cc_rotations(ctx, n_heads, L, _host_ptr(out), k) >= 0 else BLB_EINVAL, "blb_cc_rotations")
+    return [int(x) for x in out[:k]]
+
+
+def blb_plan_matmul_cc(ctx, n_heads, L, d_head, level):
+    out = C.c_void_p()
+    _check(lib().blb_plan_matmul_cc(ctx, n_heads, L, d_head, level, C.byref(out)), "blb_plan_matmul_cc")
+    return out.value
+
+
+def blb_plan_cc_info(plan):
+    buf = np.zeros(64, np.int32)
+    ng = lib().blb_plan_cc_info(plan, _host_ptr(buf), 64)
+    if ng < 0:
+        raise BlbError(ng, "blb_plan_cc_info")
+    groups = [dict(zip(["H", "c", "n_ct", "n_out", "ct0"], [int(x) for x in buf[3 + 5 * i: 8 + 5 * i]])) for i in range(ng)]
+    return {"Lp": int(buf[0]), "n_ct": int(buf[1]), "n_out": int(buf[2]), "groups": groups}
+
+
+def blb_matmul_cc(ctx, keys, plan, A_cts, Bp_cts, C_cts):
+    Aa = (blb_ct * len(A_cts))(*A_cts)
+    Ba = (blb_ct * len(Bp_cts))(*Bp_cts)
+    Ca = (blb_ct * len(C_cts))(*C_cts)
+    _check(lib().blb_matmul_cc(ctx, keys, plan, Aa, Ba, len(A_cts), Ca, len(C_cts)), "blb_matmul_cc")
+    for i in range(len(C_cts)):
+        C_cts[i].level, C_cts[i].degree, C_cts[i].scale = Ca[i].level, Ca[i].degree, Ca[i].scale
+
+
+class Exec:
+    """A recorded graph executor; keeps the ctypes arrays it was created with alive."""
+
+    def __init__(self, handle, arrays, outs, out_arr):
+        self.h, self._arrays, self._outs, self._out_arr = handle, arrays, outs, out_arr
+
+    def sync_outputs(self):
+        for i in range(len(self._outs)):
+            self._outs[i].level, self._outs[i].degree, self._outs[i].scale = (
+                self._out_arr[i].level, self._out_arr[i].degree, self._out_arr[i].scale)
+
+
+def blb_exec_create_cp(ctx, keys, plan, X_cts, Y_cts, mask_target_level=-1, share_dev=None):
+    Xa = (blb_ct * len(X_cts))(*X_cts)
+    Ya = (blb_ct * len(Y_cts))(*Y_cts)
+    out = C.c_void_p()
+    _check(lib().blb_exec_create_cp(ctx, keys, plan, Xa, len(X_cts), Ya, len(Y_cts), mask_target_level, _ptr(share_dev),
+                                    C.byref(out)), "blb_exec_create_cp")
+    e = Exec(out.value, (Xa,), Y_cts, Ya)
+    e.sync_outputs()
+    return e
+
+
+def blb_exec_create_cc(ctx, keys, plan, A_cts, Bp_cts, C_cts, mask_target_level=-1, share_dev=None):
+    Aa = (blb_ct * len(A_cts))(*A_cts)
+    Ba = (blb_ct * len(Bp_cts))(*Bp_cts)
+    Ca = (blb_ct * len(C_cts))(*C_cts)
+    out = C.c_void_p()
+    _check(lib().blb_exec_create_cc(ctx, keys, plan, Aa, Ba, len(A_cts), Ca, len(C_cts), mask_target_level, _ptr(share_dev),
+                                    C.byref(out)), "blb_exec_create_cc")
+    e = Exec(out.value, (Aa, Ba), C_cts, Ca)
+    e.sync_outputs()
+    return e
+
+
+def blb_exec_run(ex, mask_seed=0):
+    _check(lib().blb_exec_run(ex.h if isinstance(ex, Exec) else ex, mask_seed), "blb_exec_run")
+
+
+def blb_exec_device_bytes(ex):
+    return int(lib().blb_exec_device_bytes(ex.h if isinstance(ex, Exec) else ex))
+
+
+def blb_exec_destroy(ex):
+    lib().blb_exec_destroy(ex.h if isinstance(ex, Exec) else ex)
 
 
 # ---------------------------------------------------------------------------------------

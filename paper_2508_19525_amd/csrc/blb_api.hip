@@ -109,6 +109,17 @@ struct Tmp {
   T* get(size_t count) {
     void* p = nullptr;
     if (count == 0) count = 1;
+    if (c->rec) {  // recording a graph: carve from the executor's arena, never freed
+      ExecRec* r = c->rec;
+      const size_t off = align_up(r->arena_off, 256), bytes = count * sizeof(T);
+      if (off + bytes > r->arena_cap) {
+        r->overflow = true;
+        failed = true;
+        return nullptr;
+      }
+      r->arena_off = off + bytes;
+      return (T*)(r->arena + off);
+    }
     if (hipMallocAsync(&p, count * sizeof(T), c->stream) != hipSuccess) {
       (void)hipGetLastError();
       failed = true;
@@ -144,6 +155,17 @@ void uploader_free(blb_ctx* c) {
 // Copies `bytes` from host memory to a device region that stays valid for all work enqueued
 // on the stream before the ring wraps back onto it.
 void* upload(blb_ctx* c, const void* data, size_t bytes) {
+  if (c->rec) {  // recording: the table lives in the executor's blob, copied once after capture
+    ExecRec* r = c->rec;
+    const size_t off = align_up(r->blob_host.size(), 256);
+    if (off + bytes > r->blob_cap) {
+      r->overflow = true;
+      return nullptr;
+    }
+    r->blob_host.resize(off + bytes);
+    memcpy(r->blob_host.data() + off, data, bytes);
+    return r->blob_dev + off;
+  }
   Uploader& u = c->up;
   bytes = align_up(bytes, 256);
   if (bytes > u.cap) return nullptr;
@@ -191,6 +213,39 @@ const T* upload_vec(blb_ctx* c, const std::vector<T>& v) {
   return (const T*)upload(c, v.data(), v.size() * sizeof(T));
 }
 
+// ------------------------------------------------------------------------------------------
+// kernel timing spans
+// ------------------------------------------------------------------------------------------
+hipEvent_t pool_event(blb_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+struct Span {
+  blb_ctx* c;
+  int kind;
+  double units;
+  hipEvent_t a = nullptr;
+  Span(blb_ctx* cc, int k, double u) : c(cc), kind(k), units(u) {
+    if (c->timing && !c->rec) {
+      a = pool_event(c);
+      (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~Span() {
+    if (c->timing && a) {
+      hipEvent_t b = pool_event(c);
+      (void)hipEventRecord(b, c->stream);
+      c->spans.push_back(TimedSpan{kind, a, b, units});
+    }
+  }
+};
+
 // descriptor batches can exceed the ring: split into chunks
 void ntt_descs(blb_ctx* c, const std::vector<PolyDesc>& d, int kind) {
   const size_t chunk = 16384;
@@ -198,6 +253,7 @@ void ntt_descs(blb_ctx* c, const std::vector<PolyDesc>& d, int kind) {
     const size_t cnt = std::min(chunk, d.size() - off);
     const PolyDesc* dd = (const PolyDesc*)upload(c, d.data() + off, cnt * sizeof(PolyDesc));
     if (!dd) return;
+    Span sp(c, BLB_T_NTT, (double)cnt);
     switch (kind) {
       case 0: launch_ntt(c, dd, (int)cnt, true); break;
       case 1: launch_ntt(c, dd, (int)cnt, false); break;
@@ -309,23 +365,24 @@ struct KsReq {
 
 // All sources are evaluation-form polys [nl][N] at `level`.  Each request writes
 //   dst = (add0' + KS_0, add1 + KS_1), KS = ModDown(sum_j sigma(ModUp_j(src)) * key_j).
-int ks_batch(blb_ctx* c, int level, const std::vector<const uint64_t*>& srcs, const std::vector<KsReq>& reqs) {
-  if (srcs.empty() || reqs.empty()) return BLB_OK;
+// ModUp of every source (hoisted part of the key switch): X[s][j][e] in evaluation form for
+// the moduli outside digit j (the digit's own limbs are the source's limbs themselves).
+int ks_modup(blb_ctx* c, int level, const std::vector<const uint64_t*>& srcs, uint64_t* X) {
   const KsLevelConst& kc = c->h_kc[level];
   const int nl = kc.nl, n_ext = kc.n_ext, nd = kc.n_digits, n = c->n;
-  const int S = (int)srcs.size(), O = (int)reqs.size();
+  const int S = (int)srcs.size();
   Tmp tmp(c);
   uint64_t* dcoef = tmp.get<uint64_t>((size_t)S * nl * n);
-  uint64_t* X = tmp.get<uint64_t>((size_t)S * nd * n_ext * n);
-  uint64_t* U = tmp.get<uint64_t>((size_t)O * 2 * n_ext * n);
-  uint64_t* corr = tmp.get<uint64_t>((size_t)O * 2 * nl * n);
   if (tmp.failed) return BLB_ENOMEM;
   std::vector<PolyDesc> d;
   d.reserve((size_t)S * nl);
   for (int s = 0; s < S; ++s)
     for (int i = 0; i < nl; ++i) d.push_back(pd(srcs[s] + (size_t)i * n, dcoef + ((size_t)s * nl + i) * n, i, c->log_n));
   ntt_descs(c, d, NTT_INV);
-  launch_modup(c, dcoef, X, c->d_kc[level], S, nl, n_ext, nd);
+  {
+    Span sp(c, BLB_T_MODUP, (double)S * nd * n);
+    launch_modup(c, dcoef, X, c->d_kc[level], S, nl, n_ext, nd);
+  }
   d.clear();
   for (int s = 0; s < S; ++s)
     for (int j = 0; j < nd; ++j)
@@ -335,6 +392,24 @@ int ks_batch(blb_ctx* c, int level, const std::vector<const uint64_t*>& srcs, co
         d.push_back(pd(p, p, e < nl ? e : c->n_q + (e - nl), c->log_n));
       }
   ntt_descs(c, d, NTT_FWD);
+  return hipGetLastError() == hipSuccess ? BLB_OK : BLB_EDEVICE;
+}
+size_t ks_modup_words(const blb_ctx* c, int level, int n_src) {
+  const KsLevelConst& kc = c->h_kc[level];
+  return (size_t)n_src * kc.n_digits * kc.n_ext * c->n;
+}
+
+// Inner product with the keys (automorphism applied to the hoisted digits), ModDown, and the
+// final additions, for each request.
+int ks_apply(blb_ctx* c, int level, const std::vector<const uint64_t*>& srcs, const uint64_t* X, const std::vector<KsReq>& reqs) {
+  if (reqs.empty()) return BLB_OK;
+  const KsLevelConst& kc = c->h_kc[level];
+  const int nl = kc.nl, n_ext = kc.n_ext, nd = kc.n_digits, n = c->n;
+  const int O = (int)reqs.size();
+  Tmp tmp(c);
+  uint64_t* U = tmp.get<uint64_t>((size_t)O * 2 * n_ext * n);
+  uint64_t* corr = tmp.get<uint64_t>((size_t)O * 2 * nl * n);
+  if (tmp.failed) return BLB_ENOMEM;
   std::vector<KsOut> ko(O);
   for (int o = 0; o < O; ++o) {
     ko[o].c1 = srcs[reqs[o].src];
@@ -344,8 +419,11 @@ int ks_batch(blb_ctx* c, int level, const std::vector<const uint64_t*>& srcs, co
   }
   const KsOut* ko_dev = upload_vec(c, ko);
   if (!ko_dev) return BLB_EDEVICE;
-  launch_ks_inner(c, ko_dev, O, X, c->d_kc[level], U, nl, n_ext, nd);
-  d.clear();
+  {
+    Span sp(c, BLB_T_KS_INNER, (double)O * n_ext * n);
+    launch_ks_inner(c, ko_dev, O, X, c->d_kc[level], U, nl, n_ext, nd);
+  }
+  std::vector<PolyDesc> d;
   for (int o = 0; o < O; ++o)
     for (int p = 0; p < 2; ++p)
       for (int t = 0; t < c->n_sp; ++t) {
@@ -353,7 +431,10 @@ int ks_batch(blb_ctx* c, int level, const std::vector<const uint64_t*>& srcs, co
         d.push_back(pd(ptr, ptr, c->n_q + t, c->log_n));
       }
   ntt_descs(c, d, NTT_INV);
-  launch_moddown_conv(c, U, corr, c->d_kc[level], O, nl, n_ext);
+  {
+    Span sp(c, BLB_T_MODDOWN, (double)O * 2 * n);
+    launch_moddown_conv(c, U, corr, c->d_kc[level], O, nl, n_ext);
+  }
   d.clear();
   for (int o = 0; o < O; ++o)
     for (int p = 0; p < 2; ++p)
@@ -368,6 +449,18 @@ int ks_batch(blb_ctx* c, int level, const std::vector<const uint64_t*>& srcs, co
       }
   ntt_descs(c, d, NTT_MODDOWN);
   return hipGetLastError() == hipSuccess ? BLB_OK : BLB_EDEVICE;
+}
+
+// All sources are evaluation-form polys [nl][N] at `level`.  Each request writes
+//   dst = (add0' + KS_0, add1 + KS_1), KS = ModDown(sum_j sigma(ModUp_j(src)) * key_j).
+int ks_batch(blb_ctx* c, int level, const std::vector<const uint64_t*>& srcs, const std::vector<KsReq>& reqs) {
+  if (srcs.empty() || reqs.empty()) return BLB_OK;
+  Tmp tmp(c);
+  uint64_t* X = tmp.get<uint64_t>(ks_modup_words(c, level, (int)srcs.size()));
+  if (tmp.failed) return BLB_ENOMEM;
+  int rc = ks_modup(c, level, srcs, X);
+  if (rc) return rc;
+  return ks_apply(c, level, srcs, X, reqs);
 }
 
 // batched rescale: in[t] at `level` (degree+1 polys) -> out[t] at level-1 (compact)
@@ -536,6 +629,11 @@ int blb_ctx_create(const blb_params* prm, blb_ctx** out) {
 void blb_ctx_destroy(blb_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  for (TimedSpan& t : c->spans) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   uploader_free(c);
   const int nm = c->n_q + c->n_sp;
   dfree(c, c->d_tw_fwd, sizeof(double) * nm * c->n);
@@ -555,6 +653,58 @@ int blb_ctx_moduli(const blb_ctx* c, uint64_t* out) {
   return BLB_OK;
 }
 uint64_t blb_ctx_device_bytes(const blb_ctx* c) { return c ? c->dev_bytes : 0; }
+
+int blb_ctx_set_knob(blb_ctx* c, int knob, int value) {
+  if (!c) return BLB_EINVAL;
+  switch (knob) {
+    case BLB_KNOB_MAC_VARIANT:
+      if (value < 0 || value > 4) return BLB_EINVAL;
+      c->mac_variant = value;
+      return BLB_OK;
+    default: return BLB_EINVAL;
+  }
+}
+int blb_ctx_get_knob(const blb_ctx* c, int knob) {
+  if (!c) return BLB_EINVAL;
+  switch (knob) {
+    case BLB_KNOB_MAC_VARIANT: return c->mac_variant;
+    default: return BLB_EINVAL;
+  }
+}
+
+int blb_ctx_set_timing(blb_ctx* c, int enable) {
+  if (!c) return BLB_EINVAL;
+  c->timing = enable != 0;
+  return BLB_OK;
+}
+int blb_ctx_reset_timing(blb_ctx* c) {
+  if (!c) return BLB_EINVAL;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return BLB_EDEVICE;
+  for (TimedSpan& t : c->spans) {
+    c->ev_pool.push_back(t.a);
+    c->ev_pool.push_back(t.b);
+  }
+  c->spans.clear();
+  return BLB_OK;
+}
+int blb_ctx_read_timing(blb_ctx* c, int kind, double* total_ms, int64_t* launches, double* units) {
+  if (!c || kind < 0 || kind >= BLB_T_KINDS) return BLB_EINVAL;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return BLB_EDEVICE;
+  double ms = 0, u = 0;
+  int64_t cnt = 0;
+  for (const TimedSpan& t : c->spans) {
+    if (t.kind != kind) continue;
+    float e = 0;
+    if (hipEventElapsedTime(&e, t.a, t.b) != hipSuccess) return BLB_EDEVICE;
+    ms += e;
+    u += t.units;
+    ++cnt;
+  }
+  if (total_ms) *total_ms = ms;
+  if (launches) *launches = cnt;
+  if (units) *units = u;
+  return BLB_OK;
+}
 uint64_t blb_galois_elt(const blb_ctx* c, int32_t steps) { return c ? galois_left(c, steps) : 0; }
 
 // ------------------------------------------------------------------------------------------
@@ -928,6 +1078,7 @@ void blb_plan_destroy(blb_plan* P) {
   if (!P) return;
   (void)hipStreamSynchronize(P->ctx->stream);
   dfree(P->ctx, P->pt, P->bytes);
+  for (size_t i = 0; i < P->extra.size(); ++i) dfree(P->ctx, P->extra[i], P->extra_bytes[i]);
   delete P;
 }
 
@@ -959,27 +1110,34 @@ int blb_matmul_cp(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct
   const size_t ctw = (size_t)2 * nl * n;
   const int n_ai = g.n_in * g.B, n_bj = g.n_out * g.G;
   Tmp tmp(c);
-  uint64_t* RX = tmp.get<uint64_t>((size_t)n_ai * ctw);
+  uint64_t* RX = tmp.get<uint64_t>((size_t)std::max(1, g.n_in * (g.B - 1)) * ctw);
   uint64_t* inner = tmp.get<uint64_t>((size_t)n_bj * ctw);
   uint64_t* rot = tmp.get<uint64_t>((size_t)std::max(1, g.n_out * (g.G - 1)) * ctw);
   uint64_t* acc = tmp.get<uint64_t>((size_t)g.n_out * ctw);
   if (tmp.failed) return BLB_ENOMEM;
-  // baby steps, hoisted per input: RX[a][i] = Rot_l^{i L'}(X_a)
+  // baby steps, hoisted per input: RX[a][i-1] = Rot_l^{i L'}(X_a), i >= 1
   std::vector<const uint64_t*> srcs;
   std::vector<KsReq> reqs;
+  std::vector<const uint64_t*> rx_tab(n_ai);
   for (int a = 0; a < n_in; ++a) {
-    if (hipMemcpyAsync(RX + (size_t)(a * g.B) * ctw, X[a].data, ctw * 8, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
-      return BLB_EDEVICE;
     srcs.push_back(X[a].data + (size_t)nl * n);
+    rx_tab[(size_t)a * g.B] = X[a].data;
     for (int i = 1; i < g.B; ++i) {
       const uint32_t gal = galois_left(c, (int64_t)i * g.Lp);
-      reqs.push_back(KsReq{a, kb[i], gal, RX + (size_t)(a * g.B + i) * ctw, X[a].data, gal, nullptr});
+      uint64_t* dst = RX + (size_t)(a * (g.B - 1) + i - 1) * ctw;
+      rx_tab[(size_t)a * g.B + i] = dst;
+      reqs.push_back(KsReq{a, kb[i], gal, dst, X[a].data, gal, nullptr});
     }
   }
   int rc = ks_batch(c, level, srcs, reqs);
   if (rc) return rc;
   // plaintext MACs
-  launch_cp_mac(c, P->pt, RX, inner, nl, n_ai, n_bj);
+  {
+    const uint64_t* const* rx_dev = upload_vec(c, rx_tab);
+    if (!rx_dev) return BLB_EDEVICE;
+    Span sp(c, BLB_T_CP_MAC, (double)n_bj * nl * n);
+    launch_cp_mac(c, P->pt, rx_dev, inner, nl, n_ai, n_bj, c->mac_variant);
+  }
   // giant steps
   if (g.G > 1) {
     srcs.clear();
@@ -993,16 +1151,19 @@ int blb_matmul_cp(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct
       }
     if ((rc = ks_batch(c, level, srcs, reqs))) return rc;
   }
-  const ModMap lim = map_identity(nl);
-  for (int b = 0; b < g.n_out; ++b) {
-    uint64_t* ab = acc + (size_t)b * ctw;
-    const uint64_t* first = inner + (size_t)(b * g.G) * ctw;
-    if (g.G == 1) {
-      if (hipMemcpyAsync(ab, first, ctw * 8, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) return BLB_EDEVICE;
-    } else {
-      launch_ew(c, EW_ADD, ab, first, rot + (size_t)(b * (g.G - 1)) * ctw, nullptr, 2 * nl, lim);
-      for (int j = 2; j < g.G; ++j) launch_ew(c, EW_ADD, ab, ab, rot + (size_t)(b * (g.G - 1) + j - 1) * ctw, nullptr, 2 * nl, lim);
+  {
+    std::vector<const uint64_t*> terms;
+    std::vector<uint64_t*> outs;
+    for (int b = 0; b < g.n_out; ++b) {
+      terms.push_back(inner + (size_t)(b * g.G) * ctw);
+      for (int j = 1; j < g.G; ++j) terms.push_back(rot + (size_t)(b * (g.G - 1) + j - 1) * ctw);
+      outs.push_back(acc + (size_t)b * ctw);
     }
+    const uint64_t* const* t_dev = upload_vec(c, terms);
+    uint64_t* const* o_dev = (uint64_t* const*)upload(c, outs.data(), outs.size() * sizeof(uint64_t*));
+    if (!t_dev || !o_dev) return BLB_EDEVICE;
+    Span sp(c, BLB_T_EW, (double)g.n_out * ctw);
+    launch_sum_cts(c, t_dev, o_dev, g.n_out, g.G, nl);
   }
   std::vector<const uint64_t*> rin;
   std::vector<uint64_t*> rout;
@@ -1044,7 +1205,10 @@ int blb_mask_to_share(blb_ctx* c, blb_ct* cts, int n_ct, uint64_t seed, int targ
         return BLB_EDEVICE;
     }
   }
-  launch_mask_sample(c, r, share_dev, n_ct, tl, seed, 6 /* mask */);
+  {
+    Span sp(c, BLB_T_MASK, (double)n_ct * tl * n);
+    launch_mask_sample(c, r, share_dev, n_ct, tl, seed, c->rec ? c->rec->param : nullptr, 6 /* mask */);
+  }
   std::vector<PolyDesc> d;
   for (int t = 0; t < n_ct; ++t)
     for (int i = 0; i < tl; ++i) {
@@ -1055,6 +1219,503 @@ int blb_mask_to_share(blb_ctx* c, blb_ct* cts, int n_ct, uint64_t seed, int targ
   ntt_descs(c, d, NTT_ADDTO);
   for (int t = 0; t < n_ct; ++t) cts[t].level = target_level;
   return hipGetLastError() == hipSuccess ? BLB_OK : BLB_EDEVICE;
+}
+
+}  // extern "C"
+
+// ==========================================================================================
+// matmul_cc (Section "Efficient Protocol for Fused MatMuls": building blocks, multi-head
+// packing), diagonal-packed output
+// ==========================================================================================
+namespace {
+
+void cc_group_sizes(int heads, std::vector<int>& out) {  // powers of two, largest first
+  int h = heads;
+  while (h > 0) {
+    int g = 1;
+    while (g * 2 <= h) g *= 2;
+    out.push_back(g);
+    h -= g;
+  }
+}
+
+// encode `count` host slot vectors (S values each) at `scale` into evaluation-form
+// plaintexts out[count][level+1][N]
+int encode_vectors_ntt(blb_ctx* c, const std::vector<double>& vecs, int count, double scale, int level, uint64_t* out) {
+  const int S = c->n / 2, nl = level + 1, n = c->n;
+  const int chunk = 256;
+  Tmp tmp(c);
+  double* dv = tmp.get<double>((size_t)chunk * S);
+  if (tmp.failed) return BLB_ENOMEM;
+  for (int p0 = 0; p0 < count; p0 += chunk) {
+    const int cnt = std::min(chunk, count - p0);
+    if (hipMemcpyAsync(dv, vecs.data() + (size_t)p0 * S, (size_t)cnt * S * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+      return BLB_EDEVICE;
+    uint64_t* dst = out + (size_t)p0 * nl * n;
+    int rc = encode_dense_dev(c, dv, S, cnt, scale, level, dst);
+    if (rc) return rc;
+    std::vector<PolyDesc> d;
+    for (int p = 0; p < cnt; ++p)
+      for (int i = 0; i < nl; ++i) {
+        uint64_t* x = dst + ((size_t)p * nl + i) * n;
+        d.push_back(pd(x, x, i, c->log_n));
+      }
+    ntt_descs(c, d, NTT_FWD);
+  }
+  return hipStreamSynchronize(c->stream) == hipSuccess ? BLB_OK : BLB_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+int blb_cc_rotations(const blb_ctx* c, int n_heads, int L, int32_t* steps, int cap) {
+  if (!c || n_heads < 1 || L < 1 || L > c->n / 2) return BLB_EINVAL;
+  const int S = c->n / 2, lp = 1 << ceil_log2(L);
+  std::vector<int> gs;
+  cc_group_sizes(n_heads, gs);
+  std::vector<int32_t> v;
+  for (int t = 1; t < lp; ++t) {
+    v.push_back(t);
+    v.push_back(-(lp - t));
+  }
+  for (int H : gs) {
+    if (S % (lp * H)) return BLB_EINVAL;
+    const int cc = S / (lp * H);
+    for (int tau = 1; tau < cc; ++tau) v.push_back(-(tau * H * lp));
+  }
+  std::vector<int32_t> u;
+  for (int32_t x : v) {
+    bool dup = false;
+    for (int32_t y : u) dup |= galois_left(c, x) == galois_left(c, y);
+    if (!dup) u.push_back(x);
+  }
+  if (steps) {
+    if ((int)u.size() > cap) return BLB_EINVAL;
+    memcpy(steps, u.data(), u.size() * sizeof(int32_t));
+  }
+  return (int)u.size();
+}
+
+int blb_plan_matmul_cc(blb_ctx* c, int n_heads, int L, int d_head, int level, blb_plan** out) {
+  if (!c || !out || n_heads < 1 || L < 1 || d_head < 1 || level < 3 || level >= c->n_q) return BLB_EINVAL;
+  *out = nullptr;
+  const int S = c->n / 2, n = c->n, lp = 1 << ceil_log2(L);
+  if (lp > S) return BLB_EINVAL;
+  std::vector<int> gs;
+  cc_group_sizes(n_heads, gs);
+  blb_plan* P = new (std::nothrow) blb_plan();
+  if (!P) return BLB_ENOMEM;
+  P->ctx = c;
+  P->kind = 2;
+  P->level = level;
+  P->heads = n_heads;
+  P->L = L;
+  P->d = d_head;
+  P->Lp = lp;
+  P->pt = nullptr;
+  P->bytes = 0;
+  int ct0 = 0, out0 = 0;
+  for (int H : gs) {
+    if (S % (lp * H)) {
+      delete P;
+      return BLB_EINVAL;
+    }
+    CcGroup g;
+    g.H = H;
+    g.c = S / (lp * H);
+    if (g.c > lp || g.c < 1) {
+      delete P;
+      return BLB_EINVAL;
+    }
+    g.n_ct = (d_head + g.c - 1) / g.c;
+    g.n_out = lp / g.c;
+    g.ct0 = ct0;
+    g.out0 = out0;
+    g.m_ge = g.m_lt = nullptr;
+    ct0 += g.n_ct;
+    out0 += g.n_out;
+    P->groups.push_back(g);
+  }
+  P->n_ct = ct0;
+  P->n_out = out0;
+  const int nl = level + 1, nl3 = level - 1;
+  // step-2 masks at `level`, scale q_level * 2^10: M^lo_t (slot mod L' < L'-t), M^hi_t
+  P->bytes = (size_t)2 * lp * nl * n * 8;
+  int rc = dalloc(c, (void**)&P->pt, P->bytes);
+  if (rc) {
+    delete P;
+    return rc;
+  }
+  {
+    std::vector<double> vecs((size_t)2 * lp * S);
+    for (int t = 0; t < lp; ++t)
+      for (int j = 0; j < S; ++j) {
+        vecs[(size_t)t * S + j] = (j % lp) < lp - t ? 1.0 : 0.0;
+        vecs[(size_t)(lp + t) * S + j] = (j % lp) >= lp - t ? 1.0 : 0.0;
+      }
+    if ((rc = encode_vectors_ntt(c, vecs, 2 * lp, (double)c->mod[level] * 1024.0, level, P->pt))) {
+      blb_plan_destroy(P);
+      return rc;
+    }
+  }
+  // step-3 masks per group at level-2, scale q_{level-2}: M^{>=tau}, M^{<tau} over blocks of L' H
+  for (CcGroup& g : P->groups) {
+    const size_t b = (size_t)g.c * nl3 * n * 8;
+    if ((rc = dalloc(c, (void**)&g.m_ge, b)) || (P->extra.push_back(g.m_ge), P->extra_bytes.push_back(b), 0) ||
+        (rc = dalloc(c, (void**)&g.m_lt, b)) || (P->extra.push_back(g.m_lt), P->extra_bytes.push_back(b), 0)) {
+      blb_plan_destroy(P);
+      return rc ? rc : BLB_ENOMEM;
+    }
+    const int blk = lp * g.H;
+    std::vector<double> ge((size_t)g.c * S), lt((size_t)g.c * S);
+    for (int tau = 0; tau < g.c; ++tau)
+      for (int j = 0; j < S; ++j) {
+        ge[(size_t)tau * S + j] = (j / blk) >= tau ? 1.0 : 0.0;
+        lt[(size_t)tau * S + j] = (j / blk) < tau ? 1.0 : 0.0;
+      }
+    const double sc = (double)c->mod[level - 2];
+    if ((rc = encode_vectors_ntt(c, ge, g.c, sc, level - 2, g.m_ge)) || (rc = encode_vectors_ntt(c, lt, g.c, sc, level - 2, g.m_lt))) {
+      blb_plan_destroy(P);
+      return rc;
+    }
+  }
+  *out = P;
+  return BLB_OK;
+}
+
+int blb_plan_cc_info(const blb_plan* P, int32_t* info, int cap) {
+  if (!P || P->kind != 2) return BLB_EINVAL;
+  const int ng = (int)P->groups.size();
+  if (info) {
+    if (cap < 3 + 5 * ng) return BLB_EINVAL;
+    info[0] = P->Lp;
+    info[1] = P->n_ct;
+    info[2] = P->n_out;
+    for (int i = 0; i < ng; ++i) {
+      const CcGroup& g = P->groups[i];
+      info[3 + 5 * i + 0] = g.H;
+      info[3 + 5 * i + 1] = g.c;
+      info[3 + 5 * i + 2] = g.n_ct;
+      info[3 + 5 * i + 3] = g.n_out;
+      info[3 + 5 * i + 4] = g.ct0;
+    }
+  }
+  return ng;
+}
+
+int blb_matmul_cc(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct* A, const blb_ct* Bp, int n_ct, blb_ct* Cd, int n_out) {
+  if (!c || !K || !P || !A || !Bp || !Cd || P->kind != 2) return BLB_EINVAL;
+  if (n_ct != P->n_ct || n_out != P->n_out) return BLB_EINVAL;
+  const int level = P->level, n = c->n, lp = P->Lp;
+  for (int a = 0; a < n_ct; ++a) {
+    if (check_ct(c, &A[a]) || check_ct(c, &Bp[a]) || A[a].degree != 1 || Bp[a].degree != 1) return BLB_EINVAL;
+    if (A[a].level != level || Bp[a].level != level) return BLB_ELEVEL;
+    if (fabs(A[a].scale / A[0].scale - 1.0) > 1e-9 || fabs(Bp[a].scale / Bp[0].scale - 1.0) > 1e-9) return BLB_ESCALE;
+  }
+  for (int o = 0; o < n_out; ++o)
+    if (!Cd[o].data) return BLB_EINVAL;
+  const SwKey* relin = find_key(K, 0);
+  if (!relin) return BLB_ENOKEY;
+  std::vector<const SwKey*> kl(lp, nullptr), kr(lp, nullptr);
+  for (int t = 1; t < lp; ++t) {
+    if (!(kl[t] = find_key(K, galois_left(c, t)))) return BLB_ENOKEY;
+    if (!(kr[t] = find_key(K, galois_left(c, -(lp - t))))) return BLB_ENOKEY;
+  }
+  for (const CcGroup& g : P->groups)
+    for (int tau = 1; tau < g.c; ++tau)
+      if (!find_key(K, galois_left(c, -(int64_t)tau * g.H * lp))) return BLB_ENOKEY;
+  const int nl = level + 1, nl2 = level, nl3 = level - 1;
+  const size_t w1 = (size_t)2 * nl * n, w2 = (size_t)2 * nl2 * n, w3 = (size_t)2 * nl3 * n;
+  const int TC = 16;  // t values per chunk
+  int rc = BLB_OK;
+  for (const CcGroup& g : P->groups) {
+    const int m = g.n_ct;
+    Tmp tmp(c);
+    std::vector<const uint64_t*> srcs;
+    for (int a = 0; a < m; ++a) srcs.push_back(Bp[g.ct0 + a].data + (size_t)nl * n);
+    uint64_t* X = tmp.get<uint64_t>(ks_modup_words(c, level, m));
+    uint64_t* Oacc = tmp.get<uint64_t>((size_t)g.n_out * w3);
+    uint64_t* RL = tmp.get<uint64_t>((size_t)TC * m * w1);
+    uint64_t* RR = tmp.get<uint64_t>((size_t)TC * m * w1);
+    uint64_t* Rpre = tmp.get<uint64_t>((size_t)TC * m * w1);
+    uint64_t* R = tmp.get<uint64_t>((size_t)TC * m * w2);
+    uint64_t* T3 = tmp.get<uint64_t>((size_t)TC * 3 * nl2 * n);
+    uint64_t* Trl = tmp.get<uint64_t>((size_t)TC * w2);
+    uint64_t* T = tmp.get<uint64_t>((size_t)TC * w3);
+    uint64_t* V = tmp.get<uint64_t>((size_t)TC * w3);
+    if (tmp.failed) return BLB_ENOMEM;
+    launch_zero(c, Oacc, (size_t)g.n_out * w3);
+    if ((rc = ks_modup(c, level, srcs, X))) return rc;
+    std::vector<const uint64_t*> a_tab;
+    for (int a = 0; a < m; ++a) a_tab.push_back(A[g.ct0 + a].data);
+    const uint64_t* const* a_dev = upload_vec(c, a_tab);
+    if (!a_dev) return BLB_EDEVICE;
+    for (int t0 = 0; t0 < lp; t0 += TC) {
+      const int nt = std::min(TC, lp - t0);
+      // step 2: inner rotations of every B'_a by t (two hoisted rotations, then masks)
+      std::vector<KsReq> reqs;
+      std::vector<CcPair> pairs;
+      for (int tt = 0; tt < nt; ++tt) {
+        const int t = t0 + tt;
+        for (int a = 0; a < m; ++a) {
+          const size_t slot = (size_t)tt * m + a;
+          const uint64_t* b = Bp[g.ct0 + a].data;
+          CcPair pr;
+          pr.mx = P->pt + (size_t)t * nl * n;
+          pr.my = P->pt + (size_t)(lp + t) * nl * n;
+          pr.out = Rpre + slot * w1;
+          if (t == 0) {
+            pr.x = b;
+            pr.y = nullptr;
+          } else {
+            const uint32_t gl = galois_left(c, t), gr = galois_left(c, -(lp - t));
+            reqs.push_back(KsReq{a, kl[t], gl, RL + slot * w1, b, gl, nullptr});
+            reqs.push_back(KsReq{a, kr[t], gr, RR + slot * w1, b, gr, nullptr});
+            pr.x = RL + slot * w1;
+            pr.y = RR + slot * w1;
+          }
+          pairs.push_back(pr);
+        }
+      }
+      if ((rc = ks_apply(c, level, srcs, X, reqs))) return rc;
+      const CcPair* pairs_dev = upload_vec(c, pairs);
+      if (!pairs_dev) return BLB_EDEVICE;
+      {
+        Span sp(c, BLB_T_EW, (double)pairs.size() * w1);
+        launch_mask_pair(c, pairs_dev, (int)pairs.size(), nl);
+      }
+      std::vector<const uint64_t*> rin;
+      std::vector<uint64_t*> rout;
+      std::vector<const uint64_t*> r_tab;
+      for (int i = 0; i < nt * m; ++i) {
+        rin.push_back(Rpre + (size_t)i * w1);
+        rout.push_back(R + (size_t)i * w2);
+        r_tab.push_back(R + (size_t)i * w2);
+      }
+      if ((rc = rescale_batch(c, level, 2, rin, rout))) return rc;
+      // tensor with A (dropped one level) summed over a, one relinearisation per t
+      const uint64_t* const* r_dev = upload_vec(c, r_tab);
+      if (!r_dev) return BLB_EDEVICE;
+      {
+        Span sp(c, BLB_T_CC_TENSOR, (double)nt * nl2 * n);
+        launch_tensor_sum(c, a_dev, r_dev, T3, nt, m, nl, nl2);
+      }
+      std::vector<const uint64_t*> rs;
+      std::vector<KsReq> rr;
+      for (int tt = 0; tt < nt; ++tt) {
+        const uint64_t* t3 = T3 + (size_t)tt * 3 * nl2 * n;
+        rs.push_back(t3 + (size_t)2 * nl2 * n);
+        rr.push_back(KsReq{tt, relin, 0, Trl + (size_t)tt * w2, t3, 0, t3 + (size_t)nl2 * n});
+      }
+      if ((rc = ks_batch(c, level - 1, rs, rr))) return rc;
+      rin.clear();
+      rout.clear();
+      for (int tt = 0; tt < nt; ++tt) {
+        rin.push_back(Trl + (size_t)tt * w2);
+        rout.push_back(T + (size_t)tt * w3);
+      }
+      if ((rc = rescale_batch(c, level - 1, 2, rin, rout))) return rc;
+      // step 3: rotate T_t right by tau blocks (t = g c + tau), split masks into O_g, O_{g+1}
+      std::vector<const uint64_t*> vs;
+      std::vector<KsReq> vr;
+      std::vector<const uint64_t*> vsrc(nt);
+      for (int tt = 0; tt < nt; ++tt) {
+        const int t = t0 + tt, tau = t % g.c;
+        const uint64_t* tp = T + (size_t)tt * w3;
+        if (tau == 0) {
+          vsrc[tt] = tp;
+          continue;
+        }
+        const uint32_t gal = galois_left(c, -(int64_t)tau * g.H * lp);
+        vs.push_back(tp + (size_t)nl3 * n);
+        vr.push_back(KsReq{(int)vs.size() - 1, find_key(K, gal), gal, V + (size_t)tt * w3, tp, gal, nullptr});
+        vsrc[tt] = V + (size_t)tt * w3;
+      }
+      if ((rc = ks_batch(c, level - 2, vs, vr))) return rc;
+      std::vector<std::vector<CcTerm>> per_out(g.n_out);
+      for (int tt = 0; tt < nt; ++tt) {
+        const int t = t0 + tt, gi = t / g.c, tau = t % g.c;
+        per_out[gi].push_back(CcTerm{vsrc[tt], g.m_ge + (size_t)tau * nl3 * n});
+        if (tau > 0) per_out[(gi + 1) % g.n_out].push_back(CcTerm{vsrc[tt], g.m_lt + (size_t)tau * nl3 * n});
+      }
+      std::vector<CcTerm> terms;
+      std::vector<int> off{0};
+      std::vector<uint64_t*> outs;
+      for (int o = 0; o < g.n_out; ++o) {
+        if (per_out[o].empty()) continue;
+        terms.insert(terms.end(), per_out[o].begin(), per_out[o].end());
+        off.push_back((int)terms.size());
+        outs.push_back(Oacc + (size_t)o * w3);
+      }
+      const CcTerm* terms_dev = upload_vec(c, terms);
+      const int* off_dev = upload_vec(c, off);
+      uint64_t* const* outs_dev = (uint64_t* const*)upload(c, outs.data(), outs.size() * sizeof(uint64_t*));
+      if (!terms_dev || !off_dev || !outs_dev) return BLB_EDEVICE;
+      {
+        Span sp(c, BLB_T_EW, (double)outs.size() * w3);
+        launch_masked_acc(c, terms_dev, off_dev, outs_dev, (int)outs.size(), nl3, true);
+      }
+    }
+    std::vector<const uint64_t*> oin;
+    std::vector<uint64_t*> oout;
+    for (int o = 0; o < g.n_out; ++o) {
+      oin.push_back(Oacc + (size_t)o * w3);
+      oout.push_back(Cd[g.out0 + o].data);
+    }
+    if ((rc = rescale_batch(c, level - 2, 2, oin, oout))) return rc;
+  }
+  const double out_scale = A[0].scale * Bp[0].scale * 1024.0 / (double)c->mod[level - 1];
+  for (int o = 0; o < n_out; ++o) {
+    Cd[o].level = level - 3;
+    Cd[o].degree = 1;
+    Cd[o].scale = out_scale;
+  }
+  return BLB_OK;
+}
+
+}  // extern "C"
+
+// ==========================================================================================
+// Graph executors: one fused operator invocation recorded into a HIP graph with
+// executor-owned scratch and descriptor memory, replayed with one launch.
+// ==========================================================================================
+struct blb_exec {
+  blb_ctx* c = nullptr;
+  ExecRec rec;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  size_t arena_bytes = 0, blob_bytes = 0;
+  int has_mask = 0;
+};
+
+namespace {
+
+void exec_release(blb_exec* E) {
+  if (!E) return;
+  blb_ctx* c = E->c;
+  if (E->exec) (void)hipGraphExecDestroy(E->exec);
+  if (E->graph) (void)hipGraphDestroy(E->graph);
+  if (E->cap_stream) (void)hipStreamDestroy(E->cap_stream);
+  dfree(c, E->rec.arena, E->arena_bytes);
+  dfree(c, E->rec.blob_dev, E->blob_bytes);
+  dfree(c, E->rec.param, 256);
+  E->exec = nullptr;
+  E->graph = nullptr;
+  E->cap_stream = nullptr;
+  E->rec = ExecRec();
+}
+
+// Records body() into E's graph.  Retries with a larger arena when the first guess is short.
+template <class F>
+int exec_record(blb_ctx* c, blb_exec* E, size_t arena_guess, F body) {
+  size_t arena = arena_guess;
+  for (int attempt = 0; attempt < 5; ++attempt, arena *= 2) {
+    exec_release(E);
+    E->c = c;
+    E->arena_bytes = arena;
+    E->blob_bytes = 64u << 20;
+    int rc;
+    if ((rc = dalloc(c, (void**)&E->rec.arena, E->arena_bytes))) return rc;
+    E->rec.arena_cap = E->arena_bytes;
+    if ((rc = dalloc(c, (void**)&E->rec.blob_dev, E->blob_bytes))) return rc;
+    E->rec.blob_cap = E->blob_bytes;
+    if ((rc = dalloc(c, (void**)&E->rec.param, 256))) return rc;
+    if (hipStreamCreateWithFlags(&E->cap_stream, hipStreamNonBlocking) != hipSuccess) return BLB_EDEVICE;
+    hipStream_t saved = c->stream;
+    if (hipStreamSynchronize(saved) != hipSuccess) return BLB_EDEVICE;
+    c->stream = E->cap_stream;
+    c->rec = &E->rec;
+    if (hipStreamBeginCapture(E->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      c->rec = nullptr;
+      c->stream = saved;
+      return BLB_EDEVICE;
+    }
+    rc = body();
+    const hipError_t ec = hipStreamEndCapture(E->cap_stream, &E->graph);
+    c->rec = nullptr;
+    c->stream = saved;
+    if (E->rec.overflow) continue;  // arena or blob too small: retry bigger
+    if (rc) return rc;
+    if (ec != hipSuccess || !E->graph) return BLB_EDEVICE;
+    if (hipGraphInstantiate(&E->exec, E->graph, nullptr, nullptr, 0) != hipSuccess) return BLB_EDEVICE;
+    if (!E->rec.blob_host.empty() &&
+        hipMemcpy(E->rec.blob_dev, E->rec.blob_host.data(), E->rec.blob_host.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return BLB_EDEVICE;
+    return BLB_OK;
+  }
+  return BLB_ENOMEM;
+}
+
+}  // namespace
+
+extern "C" {
+
+int blb_exec_create_cp(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct* X, int n_in, blb_ct* Y, int n_out,
+                       int mask_target_level, uint64_t* share_dev, blb_exec** out) {
+  if (!c || !K || !P || !X || !Y || !out || P->kind != 1) return BLB_EINVAL;
+  if (mask_target_level >= 0 && !share_dev) return BLB_EINVAL;
+  *out = nullptr;
+  blb_exec* E = new (std::nothrow) blb_exec();
+  if (!E) return BLB_ENOMEM;
+  E->has_mask = mask_target_level >= 0;
+  const size_t ctw = (size_t)2 * (P->level + 1) * c->n * 8;
+  const size_t guess = ctw * (size_t)(P->g.n_in * P->g.B * 6 + P->g.n_out * P->g.G * 6 + 64);
+  const int rc = exec_record(c, E, guess, [&]() -> int {
+    int r = blb_matmul_cp(c, K, P, X, n_in, Y, n_out);
+    if (r) return r;
+    if (mask_target_level >= 0) r = blb_mask_to_share(c, Y, n_out, 0, mask_target_level, share_dev);
+    return r;
+  });
+  if (rc) {
+    exec_release(E);
+    delete E;
+    return rc;
+  }
+  *out = E;
+  return BLB_OK;
+}
+
+int blb_exec_create_cc(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct* A, const blb_ct* Bp, int n_ct, blb_ct* Cd, int n_out,
+                       int mask_target_level, uint64_t* share_dev, blb_exec** out) {
+  if (!c || !K || !P || !A || !Bp || !Cd || !out || P->kind != 2) return BLB_EINVAL;
+  if (mask_target_level >= 0 && !share_dev) return BLB_EINVAL;
+  *out = nullptr;
+  blb_exec* E = new (std::nothrow) blb_exec();
+  if (!E) return BLB_ENOMEM;
+  E->has_mask = mask_target_level >= 0;
+  const size_t ctw = (size_t)2 * (P->level + 1) * c->n * 8;
+  const size_t guess = ctw * (size_t)(P->n_ct * 16 * 8 + 256);
+  const int rc = exec_record(c, E, guess, [&]() -> int {
+    int r = blb_matmul_cc(c, K, P, A, Bp, n_ct, Cd, n_out);
+    if (r) return r;
+    if (mask_target_level >= 0) r = blb_mask_to_share(c, Cd, n_out, 0, mask_target_level, share_dev);
+    return r;
+  });
+  if (rc) {
+    exec_release(E);
+    delete E;
+    return rc;
+  }
+  *out = E;
+  return BLB_OK;
+}
+
+int blb_exec_run(blb_exec* E, uint64_t mask_seed) {
+  if (!E || !E->exec) return BLB_EINVAL;
+  blb_ctx* c = E->c;
+  if (E->has_mask) launch_set_u64(c, E->rec.param, mask_seed);
+  return hipGraphLaunch(E->exec, c->stream) == hipSuccess ? BLB_OK : BLB_EDEVICE;
+}
+
+uint64_t blb_exec_device_bytes(const blb_exec* E) { return E ? E->arena_bytes + E->blob_bytes + 256 : 0; }
+
+void blb_exec_destroy(blb_exec* E) {
+  if (!E) return;
+  if (E->c) (void)hipStreamSynchronize(E->c->stream);
+  exec_release(E);
+  delete E;
 }
 
 }  // extern "C"

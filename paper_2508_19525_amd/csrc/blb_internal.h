@@ -88,6 +88,19 @@ struct KsOut {
   int32_t src;
 };
 
+// matmul_cc launch records
+struct CcPair {
+  const uint64_t* x;
+  const uint64_t* mx;
+  const uint64_t* y;
+  const uint64_t* my;
+  uint64_t* out;
+};
+struct CcTerm {
+  const uint64_t* ct;
+  const uint64_t* mask;
+};
+
 struct CpGeom {
   int d_in, d_out, L;
   int Lp, c, c_eff, c_out, n_in, n_out, B, G;
@@ -106,8 +119,32 @@ struct Uploader {
   std::vector<hipEvent_t> free_events;
 };
 
+// Kernel timing spans recorded with HIP events on the context stream (when enabled).
+struct TimedSpan {
+  int kind;
+  hipEvent_t a, b;
+  double units;
+};
+
+// Recording state of a graph executor: while set on a context, temporaries come from the
+// executor's arena, descriptor tables go to its blob, timing spans are off, and the mask
+// seed is read from its parameter block.
+struct ExecRec {
+  char* arena = nullptr;
+  size_t arena_cap = 0, arena_off = 0;
+  char* blob_dev = nullptr;
+  size_t blob_cap = 0;
+  std::vector<char> blob_host;
+  uint64_t* param = nullptr;  // device: [0] = mask seed
+  bool overflow = false;
+};
+
 struct blb_ctx {
   int log_n, n, n_q, n_sp, dnum, alpha;
+  ExecRec* rec = nullptr;
+  bool timing = false;
+  std::vector<TimedSpan> spans;
+  std::vector<hipEvent_t> ev_pool;
   int device;
   hipStream_t stream;
   uint64_t budget;
@@ -126,6 +163,7 @@ struct blb_ctx {
   size_t scratch_cap = 0;
   Uploader up;
   int* d_flag = nullptr;          // device error flag (encoder overflow)
+  int mac_variant = 0;            // k_cp_mac tile shape (autotuned; never changes results)
 };
 
 // Switching key in evaluation form: [digit][2 (b, a)][modulus (all q's then p's)][N] residues
@@ -142,13 +180,31 @@ struct blb_keys {
   size_t bytes;
 };
 
+// matmul_cc geometry of one head group
+struct CcGroup {
+  int H;      // heads in the group
+  int c;      // columns (of d) per ciphertext
+  int n_ct;   // ciphertexts per operand
+  int n_out;  // diagonal-packed output ciphertexts (L'/c)
+  int ct0;    // first operand ciphertext of the group
+  int out0;   // first output ciphertext of the group
+  uint64_t* m_ge;  // [c][nl3][N] masks M^{>=tau} at level-2, scale q_{level-2}
+  uint64_t* m_lt;  // [c][nl3][N] masks M^{<tau}
+};
+
 struct blb_plan {
   blb_ctx* ctx;
-  int kind;  // 1 = matmul_cp
+  int kind;  // 1 = matmul_cp, 2 = matmul_cc
   int level;
   CpGeom g;
-  uint64_t* pt;  // [(b, j)][(a, i)][limb][N] evaluation-form plaintexts
+  uint64_t* pt;  // matmul_cp: [(b, j)][(a, i)][limb][N] evaluation-form plaintexts
+                 // matmul_cc: [2][L'][limb][N] step-2 masks M^lo_t, M^hi_t (level, scale q_level 2^10)
   size_t bytes;
+  // matmul_cc
+  int heads, L, d, Lp, n_ct, n_out;
+  std::vector<CcGroup> groups;
+  std::vector<void*> extra;
+  std::vector<size_t> extra_bytes;
 };
 
 // ---------------------------------------------------------------------------------------
@@ -172,8 +228,15 @@ void launch_modup(blb_ctx* c, const uint64_t* dcoef, uint64_t* X, const KsLevelC
 void launch_ks_inner(blb_ctx* c, const KsOut* outs_dev, int n_out, const uint64_t* X, const KsLevelConst* kc_dev, uint64_t* U, int nl,
                      int n_ext, int n_digits);
 void launch_moddown_conv(blb_ctx* c, const uint64_t* U, uint64_t* Corr, const KsLevelConst* kc_dev, int n_out, int nl, int n_ext);
-void launch_cp_mac(blb_ctx* c, const uint64_t* pt, const uint64_t* RX, uint64_t* inner, int nl, int n_ai, int n_bj);
-void launch_mask_sample(blb_ctx* c, uint64_t* r_out, uint64_t* share, int n_ct, int tl, uint64_t seed, uint32_t tag);
+void launch_cp_mac(blb_ctx* c, const uint64_t* pt, const uint64_t* const* rx_tab, uint64_t* inner, int nl, int n_ai, int n_bj, int variant);
+void launch_sum_cts(blb_ctx* c, const uint64_t* const* srcs, uint64_t* const* dsts, int n_out, int n_terms, int nl);
+void launch_mask_pair(blb_ctx* c, const CcPair* pairs_dev, int n_pairs, int nl);
+void launch_tensor_sum(blb_ctx* c, const uint64_t* const* A_tab, const uint64_t* const* R_tab, uint64_t* T3, int n_t, int n_ct, int nlA,
+                       int nl2);
+void launch_masked_acc(blb_ctx* c, const CcTerm* terms, const int* off, uint64_t* const* outs, int n_out, int nl, bool accumulate);
+void launch_mask_sample(blb_ctx* c, uint64_t* r_out, uint64_t* share, int n_ct, int tl, uint64_t seed, const uint64_t* seed_dev, uint32_t tag);
+void launch_set_u64(blb_ctx* c, uint64_t* dst, uint64_t value);
+void launch_zero(blb_ctx* c, uint64_t* dst, size_t words);
 int run_encode_core(blb_ctx* c, double* bufA, double* bufB, int count, double scale, int nl, uint64_t* out, int* d_overflow);
 void launch_enc_scatter_dense(blb_ctx* c, const double* vals, int n_vals, int count, double* buf);
 void launch_enc_scatter_cp(blb_ctx* c, const double* W, CpGeom g, int p0, int count, double* buf);

@@ -233,10 +233,15 @@ void launch_moddown_conv(blb_ctx* c, const uint64_t* U, uint64_t* Corr, const Ks
 // Thread per (coefficient k, limb) for a tile of TB outputs.  The plaintext stream is read
 // exactly once; RX tiles are re-read per output tile (L2 / MALL resident).
 // ---------------------------------------------------------------------------------------
-template <int TB>
-__global__ __launch_bounds__(256) void k_cp_mac(const uint64_t* __restrict__ pt, const uint64_t* __restrict__ RX, uint64_t* __restrict__ inner,
-                                                int n, int nl, int n_ai, int n_bj, ModTable mt, int n_kblk, int n_tiles) {
-  // XCD-aware block mapping: blocks that share a (k-chunk, limb) land on the same XCD
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+
+template <int TB, int CPT>
+__global__ __launch_bounds__(256) void k_cp_mac(const uint64_t* __restrict__ pt, const uint64_t* const* __restrict__ rx_tab,
+                                                uint64_t* __restrict__ inner, int n, int nl, int n_ai, int n_bj, ModTable mt, int n_kblk,
+                                                int n_tiles) {
+  static_assert(CPT == 1 || CPT == 2, "coefficients per thread");
+  // XCD-aware block mapping: blocks that share a (k-chunk, limb) land on the same XCD, so
+  // the rotated inputs they all read stay in that XCD's L2
   const int nb = gridDim.x;
   const int per_xcd = nb / 8;
   int lb = blockIdx.x;
@@ -245,57 +250,124 @@ __global__ __launch_bounds__(256) void k_cp_mac(const uint64_t* __restrict__ pt,
   const int rest = lb / n_tiles;
   const int kb = rest % n_kblk;
   const int limb = rest / n_kblk;
-  const int k = kb * 256 + threadIdx.x;
-  if (k >= n) return;
+  const int k0 = (kb * 256 + threadIdx.x) * CPT;
+  if (k0 >= n) return;
   const ModEntry me = mt.m[limb];
   const double q = me.q, qi = me.qinv;
   const int bj0 = tile * TB;
-  double a0[TB], a1[TB];
+  double a0[TB][CPT], a1[TB][CPT];
 #pragma unroll
-  for (int t = 0; t < TB; ++t) { a0[t] = 0.0; a1[t] = 0.0; }
+  for (int t = 0; t < TB; ++t)
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) { a0[t][c] = 0.0; a1[t][c] = 0.0; }
   const size_t pt_stride_bj = (size_t)n_ai * nl * n;
   for (int ai = 0; ai < n_ai; ++ai) {
-    const double x0 = u2d(RX[(((size_t)ai * 2 + 0) * nl + limb) * n + k]);
-    const double x1 = u2d(RX[(((size_t)ai * 2 + 1) * nl + limb) * n + k]);
-    const uint64_t* p = pt + ((size_t)bj0 * n_ai + ai) * nl * n + (size_t)limb * n + k;
+    const uint64_t* rx = rx_tab[ai];
+    double x0[CPT], x1[CPT];
+    if (CPT == 2) {
+      const u64x2 v0 = *(const u64x2*)(rx + (size_t)limb * n + k0);
+      const u64x2 v1 = *(const u64x2*)(rx + (size_t)(nl + limb) * n + k0);
+      x0[0] = u2d(v0.x); x0[CPT - 1] = u2d(v0.y);
+      x1[0] = u2d(v1.x); x1[CPT - 1] = u2d(v1.y);
+    } else {
+      x0[0] = u2d(rx[(size_t)limb * n + k0]);
+      x1[0] = u2d(rx[(size_t)(nl + limb) * n + k0]);
+    }
+    const uint64_t* p = pt + ((size_t)bj0 * n_ai + ai) * nl * n + (size_t)limb * n + k0;
 #pragma unroll
     for (int t = 0; t < TB; ++t) {
       if (bj0 + t < n_bj) {
-        const double w = u2d(p[t * pt_stride_bj]);
-        a0[t] += mulmod_s(w, x0, q, qi);
-        a1[t] += mulmod_s(w, x1, q, qi);
+        double w[CPT];
+        if (CPT == 2) {
+          const u64x2 v = __builtin_nontemporal_load((const u64x2*)(p + t * pt_stride_bj));
+          w[0] = u2d(v.x); w[CPT - 1] = u2d(v.y);
+        } else {
+          w[0] = u2d(__builtin_nontemporal_load(p + t * pt_stride_bj));
+        }
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+          a0[t][c] += mulmod_s(w[c], x0[c], q, qi);
+          a1[t][c] += mulmod_s(w[c], x1[c], q, qi);
+        }
       }
     }
     if ((ai & 7) == 7) {
 #pragma unroll
-      for (int t = 0; t < TB; ++t) { a0[t] = reduce_s(a0[t], q, qi); a1[t] = reduce_s(a1[t], q, qi); }
+      for (int t = 0; t < TB; ++t)
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) { a0[t][c] = reduce_s(a0[t][c], q, qi); a1[t][c] = reduce_s(a1[t][c], q, qi); }
     }
   }
 #pragma unroll
   for (int t = 0; t < TB; ++t) {
     if (bj0 + t < n_bj) {
-      inner[(((size_t)(bj0 + t) * 2 + 0) * nl + limb) * n + k] = d2u(canon_full(a0[t], q, qi));
-      inner[(((size_t)(bj0 + t) * 2 + 1) * nl + limb) * n + k] = d2u(canon_full(a1[t], q, qi));
+      uint64_t* o0 = inner + (((size_t)(bj0 + t) * 2 + 0) * nl + limb) * n + k0;
+      uint64_t* o1 = inner + (((size_t)(bj0 + t) * 2 + 1) * nl + limb) * n + k0;
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        o0[c] = d2u(canon_full(a0[t][c], q, qi));
+        o1[c] = d2u(canon_full(a1[t][c], q, qi));
+      }
     }
   }
 }
-void launch_cp_mac(blb_ctx* c, const uint64_t* pt, const uint64_t* RX, uint64_t* inner, int nl, int n_ai, int n_bj) {
-  constexpr int TB = 8;
-  const int n_kblk = (c->n + 255) / 256;
+
+// Tuning knob (does not change any result bit): outputs per block x coefficients per thread.
+void launch_cp_mac(blb_ctx* c, const uint64_t* pt, const uint64_t* const* rx_tab, uint64_t* inner, int nl, int n_ai, int n_bj, int variant) {
+  int TB = 8, CPT = 2;
+  switch (variant) {
+    case 1: TB = 8; CPT = 1; break;
+    case 2: TB = 16; CPT = 2; break;
+    case 3: TB = 4; CPT = 2; break;
+    case 4: TB = 12; CPT = 2; break;
+    default: break;
+  }
+  const int n_kblk = c->n / (256 * CPT);
   const int n_tiles = (n_bj + TB - 1) / TB;
   const int blocks = n_kblk * nl * n_tiles;
-  k_cp_mac<TB><<<blocks, 256, 0, c->stream>>>(pt, RX, inner, c->n, nl, n_ai, n_bj, c->mt, n_kblk, n_tiles);
+#define CPMAC(tb, cpt) k_cp_mac<tb, cpt><<<blocks, 256, 0, c->stream>>>(pt, rx_tab, inner, c->n, nl, n_ai, n_bj, c->mt, n_kblk, n_tiles)
+  if (TB == 8 && CPT == 2) CPMAC(8, 2);
+  else if (TB == 8 && CPT == 1) CPMAC(8, 1);
+  else if (TB == 16) CPMAC(16, 2);
+  else if (TB == 4) CPMAC(4, 2);
+  else CPMAC(12, 2);
+#undef CPMAC
+}
+
+// out[o] = sum_t src[o * n_terms + t] over whole ciphertexts ([2][nl][N] words), mod q_limb
+__global__ void k_sum_cts(const uint64_t* const* __restrict__ srcs, uint64_t* const* __restrict__ dsts, int n_terms, int n, int nl,
+                          ModTable mt) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  const int o = blockIdx.y;
+  if (w >= 2 * nl * n) return;
+  const ModEntry me = mt.m[(w / n) % nl];
+  double acc = 0.0;
+  for (int t = 0; t < n_terms; ++t) {
+    acc += u2d(srcs[(size_t)o * n_terms + t][w]);
+    if ((t & 3) == 3) acc = reduce_s(acc, me.q, me.qinv);
+  }
+  dsts[o][w] = d2u(canon_full(acc, me.q, me.qinv));
+}
+void launch_sum_cts(blb_ctx* c, const uint64_t* const* srcs, uint64_t* const* dsts, int n_out, int n_terms, int nl) {
+  dim3 grid((2 * nl * c->n + 255) / 256, n_out);
+  k_sum_cts<<<grid, 256, 0, c->stream>>>(srcs, dsts, n_terms, c->n, nl, c->mt);
 }
 
 // ---------------------------------------------------------------------------------------
 // Mask-and-share: r uniform per limb in coefficient form (tag mask, object = ct index),
 // share = -r mod q_i; the mask is added to c0 in evaluation form by the caller after an NTT.
 // ---------------------------------------------------------------------------------------
-__global__ void k_mask_sample(uint64_t* r_out, uint64_t* share, int n, int tl, ModTable mt, uint32_t k0, uint32_t k1, uint32_t tag) {
+__global__ void k_mask_sample(uint64_t* r_out, uint64_t* share, int n, int tl, ModTable mt, uint32_t k0, uint32_t k1,
+                              const uint64_t* seed_dev, uint32_t tag) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y % tl;
   const int t = blockIdx.y / tl;
   if (k >= n) return;
+  if (seed_dev) {
+    const uint64_t sd = *seed_dev;
+    k0 = (uint32_t)sd;
+    k1 = (uint32_t)(sd >> 32);
+  }
   const ModEntry me = mt.m[i];
   const U4 w = philox10((uint32_t)k, (uint32_t)i, (uint32_t)t, tag, k0, k1);
   const double r = u128_mod(w, me.q, me.qinv);
@@ -303,9 +375,22 @@ __global__ void k_mask_sample(uint64_t* r_out, uint64_t* share, int n, int tl, M
   r_out[o] = d2u(r);
   share[o] = d2u(r == 0.0 ? 0.0 : me.q - r);
 }
-void launch_mask_sample(blb_ctx* c, uint64_t* r_out, uint64_t* share, int n_ct, int tl, uint64_t seed, uint32_t tag) {
+void launch_mask_sample(blb_ctx* c, uint64_t* r_out, uint64_t* share, int n_ct, int tl, uint64_t seed, const uint64_t* seed_dev,
+                        uint32_t tag) {
   dim3 grid((c->n + 255) / 256, n_ct * tl);
-  k_mask_sample<<<grid, 256, 0, c->stream>>>(r_out, share, c->n, tl, c->mt, (uint32_t)seed, (uint32_t)(seed >> 32), tag);
+  k_mask_sample<<<grid, 256, 0, c->stream>>>(r_out, share, c->n, tl, c->mt, (uint32_t)seed, (uint32_t)(seed >> 32), seed_dev, tag);
+}
+
+__global__ void k_set_u64(uint64_t* dst, uint64_t v) { *dst = v; }
+void launch_set_u64(blb_ctx* c, uint64_t* dst, uint64_t value) { k_set_u64<<<1, 1, 0, c->stream>>>(dst, value); }
+
+__global__ void k_zero(uint64_t* dst, size_t words) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < words) dst[i] = 0;
+}
+void launch_zero(blb_ctx* c, uint64_t* dst, size_t words) {
+  if (!words) return;
+  k_zero<<<(unsigned)((words + 255) / 256), 256, 0, c->stream>>>(dst, words);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -465,4 +550,83 @@ void launch_enc_scatter_cp(blb_ctx* c, const double* W, CpGeom g, int p0, int co
   const int M = c->n / 2;
   dim3 grid((M + 255) / 256, count);
   k_enc_scatter_cp<<<grid, 256, 0, c->stream>>>(W, g, p0, buf, c->d_slot_u, M);
+}
+
+// ---------------------------------------------------------------------------------------
+// matmul_cc helpers
+// ---------------------------------------------------------------------------------------
+// out = x (.) mx + y (.) my over a whole degree-1 ciphertext ([2][nl][N]); masks are
+// evaluation-form plaintexts [nl][N] shared by both polys; y may be null.
+__global__ void k_mask_pair(const CcPair* __restrict__ pairs, int nl, int n, ModTable mt) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= 2 * nl * n) return;
+  const CcPair pr = pairs[blockIdx.y];
+  const int mw = w % (nl * n);
+  const ModEntry me = mt.m[mw / n];
+  double r = mulmod_s(u2d(pr.x[w]), u2d(pr.mx[mw]), me.q, me.qinv);
+  if (pr.y) r += mulmod_s(u2d(pr.y[w]), u2d(pr.my[mw]), me.q, me.qinv);
+  pr.out[w] = d2u(canon_full(r, me.q, me.qinv));
+}
+void launch_mask_pair(blb_ctx* c, const CcPair* pairs_dev, int n_pairs, int nl) {
+  if (n_pairs <= 0) return;
+  dim3 grid((2 * nl * c->n + 255) / 256, n_pairs);
+  k_mask_pair<<<grid, 256, 0, c->stream>>>(pairs_dev, nl, c->n, c->mt);
+}
+
+// T3[t] = sum_a A_a (x) R[t][a]: degree-2 output (d0, d1, d2) at nl2 limbs.  A_a is at a
+// higher level (nlA limbs per poly) and is used through its first nl2 limbs.
+__global__ void k_tensor_sum(const uint64_t* const* __restrict__ A_tab, const uint64_t* const* __restrict__ R_tab,
+                             uint64_t* __restrict__ T3, int n_ct, int nlA, int nl2, int n, ModTable mt) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int limb = blockIdx.y % nl2;
+  const int t = blockIdx.y / nl2;
+  if (k >= n) return;
+  const ModEntry me = mt.m[limb];
+  const double q = me.q, qi = me.qinv;
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+  for (int a = 0; a < n_ct; ++a) {
+    const uint64_t* A = A_tab[a];
+    const uint64_t* R = R_tab[(size_t)t * n_ct + a];
+    const double a0 = u2d(A[(size_t)limb * n + k]), a1 = u2d(A[(size_t)(nlA + limb) * n + k]);
+    const double r0 = u2d(R[(size_t)limb * n + k]), r1 = u2d(R[(size_t)(nl2 + limb) * n + k]);
+    d0 += mulmod_s(a0, r0, q, qi);
+    d1 += mulmod_s(a0, r1, q, qi) + mulmod_s(a1, r0, q, qi);
+    d2 += mulmod_s(a1, r1, q, qi);
+    if ((a & 1) == 1) {
+      d0 = reduce_s(d0, q, qi);
+      d1 = reduce_s(d1, q, qi);
+      d2 = reduce_s(d2, q, qi);
+    }
+  }
+  uint64_t* o = T3 + (size_t)t * 3 * nl2 * n;
+  o[(size_t)limb * n + k] = d2u(canon_full(d0, q, qi));
+  o[(size_t)(nl2 + limb) * n + k] = d2u(canon_full(d1, q, qi));
+  o[(size_t)(2 * nl2 + limb) * n + k] = d2u(canon_full(d2, q, qi));
+}
+void launch_tensor_sum(blb_ctx* c, const uint64_t* const* A_tab, const uint64_t* const* R_tab, uint64_t* T3, int n_t, int n_ct, int nlA,
+                       int nl2) {
+  dim3 grid((c->n + 255) / 256, n_t * nl2);
+  k_tensor_sum<<<grid, 256, 0, c->stream>>>(A_tab, R_tab, T3, n_ct, nlA, nl2, c->n, c->mt);
+}
+
+// out[o] (+)= sum over its terms of ct (.) mask, whole degree-1 ciphertexts at nl limbs
+__global__ void k_masked_acc(const CcTerm* __restrict__ terms, const int* __restrict__ off, uint64_t* const* __restrict__ outs, int nl,
+                             int n, ModTable mt, int accumulate) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  const int o = blockIdx.y;
+  if (w >= 2 * nl * n) return;
+  const int mw = w % (nl * n);
+  const ModEntry me = mt.m[mw / n];
+  double acc = accumulate ? u2d(outs[o][w]) : 0.0;
+  int cnt = 0;
+  for (int i = off[o]; i < off[o + 1]; ++i) {
+    acc += mulmod_s(u2d(terms[i].ct[w]), u2d(terms[i].mask[mw]), me.q, me.qinv);
+    if ((++cnt & 3) == 0) acc = reduce_s(acc, me.q, me.qinv);
+  }
+  outs[o][w] = d2u(canon_full(acc, me.q, me.qinv));
+}
+void launch_masked_acc(blb_ctx* c, const CcTerm* terms, const int* off, uint64_t* const* outs, int n_out, int nl, bool accumulate) {
+  if (n_out <= 0) return;
+  dim3 grid((2 * nl * c->n + 255) / 256, n_out);
+  k_masked_acc<<<grid, 256, 0, c->stream>>>(terms, off, outs, nl, c->n, c->mt, accumulate ? 1 : 0);
 }

@@ -82,3 +82,57 @@ def unpack_spatial(vecs, L: int, D: int, slots: int) -> np.ndarray:
         b, u = divmod(col, c)
         out[:, col] = vecs[b][u * lp: u * lp + L]
     return out
+
+
+def head_groups(heads: int):
+    """power-of-two head groups, largest first (12 -> [8, 4])"""
+    out, h = [], heads
+    while h > 0:
+        g = 1
+        while g * 2 <= h:
+            g *= 2
+        out.append(g)
+        h -= g
+    return out
+
+
+def pack_mhp(mats, H: int, L: int, d: int, a: int, operand: str, slots: int) -> np.ndarray:
+    """Multi-head packing of operand ciphertext `a` of one head group (client side, before
+    encryption): slot i + L'(h + H kappa) holds A_h{i, a c + kappa} for operand "A" and the
+    row-pre-rotated B_h{a c + kappa, (i + kappa) mod L'} for operand "Bp" (B_h = mats[h], d x L),
+    with L' = 2^ceil(log2 L) and c = slots / (L' H)."""
+    lp = 1 << int(np.ceil(np.log2(L)))
+    c = slots // (lp * H)
+    v = np.zeros(slots)
+    i = np.arange(lp)
+    for h in range(H):
+        for kap in range(c):
+            k = a * c + kap
+            if k >= d:
+                continue
+            base = lp * (h + H * kap)
+            if operand == "A":
+                col = np.zeros(lp)
+                col[:L] = mats[h][:, k]
+                v[base: base + lp] = col
+            else:
+                j = (i + kap) % lp
+                row = np.zeros(lp)
+                row[:L] = mats[h][k, :]
+                v[base: base + lp] = row[j]
+    return v
+
+
+def unpack_diag(vecs, H: int, L: int, slots: int, g0: int = 0):
+    """C_h (L x L) for each head of a group from its diagonal-packed output vectors: output g,
+    slot i + L'(h + H kappa) holds C_h{i, (i + g c + kappa) mod L'}."""
+    lp = 1 << int(np.ceil(np.log2(L)))
+    c = slots // (lp * H)
+    C = [np.zeros((lp, lp)) for _ in range(H)]
+    i = np.arange(lp)
+    for g, v in enumerate(vecs):
+        for h in range(H):
+            for kap in range(c):
+                D = (g0 + g) * c + kap
+                C[h][i, (i + D) % lp] = v[lp * (h + H * kap) + i]
+    return [m[:L, :L] for m in C]

@@ -242,3 +242,140 @@ def test_mask_to_share_matches_oracle(request, name):
             assert cts[t].level == target
             assert np.array_equal(c.export(cts[t]), masked)
             assert np.array_equal(sh[t], want_share)
+
+
+# --------------------------------------------------------------------------------------
+# matmul_cc
+# --------------------------------------------------------------------------------------
+def _cc_case(c, heads, L, d, seed, outputs=None):
+    from paper_2508_19525_amd import workloads as wl
+    B, orc = c.B, c.orc
+    rng = np.random.default_rng(seed)
+    Q = [rng.normal(0, 1, (L, d)) for _ in range(heads)]
+    Kt = [rng.normal(0, 1, (L, d)).T.copy() for _ in range(heads)]
+    level, scale = c.n_q - 1, 2.0 ** 40
+    steps = B.blb_cc_rotations(c.h, heads, L)
+    gal = sorted({c.o.galois_elt(s) for s in steps})
+    keys_o = orc.Keys(c.o, 51, gal)
+    keys_g = B.blb_keygen(c.h, 51, steps)
+    plan = B.blb_plan_matmul_cc(c.h, heads, L, d, level)
+    info = B.blb_plan_cc_info(plan)
+    A_g, B_g, want, h0 = [], [], [], 0
+    for gi, grp in enumerate(info["groups"]):
+        H = grp["H"]
+        assert H == wl.head_groups(heads)[gi]
+        og = c.o.cc_geometry(H, L, d)
+        assert (og["c"], og["n_ct"], og["n_out"]) == (grp["c"], grp["n_ct"], grp["n_out"])
+        Aw = np.stack([keys_o.encrypt(c.o.encode_rns(c.o.pack_mhp(Q[h0:h0 + H], H, L, d, a, "A"), scale, level), level, 60 + gi, a)
+                       for a in range(og["n_ct"])])
+        Bw = np.stack([keys_o.encrypt(c.o.encode_rns(c.o.pack_mhp(Kt[h0:h0 + H], H, L, d, a, "Bp"), scale, level), level, 70 + gi, a)
+                       for a in range(og["n_ct"])])
+        # the client-side packing of the library's helper module agrees with the oracle's
+        assert np.array_equal(wl.pack_mhp(Q[h0:h0 + H], H, L, d, 0, "A", c.n // 2), c.o.pack_mhp(Q[h0:h0 + H], H, L, d, 0, "A"))
+        assert np.array_equal(wl.pack_mhp(Kt[h0:h0 + H], H, L, d, 0, "Bp", c.n // 2), c.o.pack_mhp(Kt[h0:h0 + H], H, L, d, 0, "Bp"))
+        for a in range(og["n_ct"]):
+            x = c.import_ct(Aw[a], level)
+            x.scale = scale
+            A_g.append(x)
+            y = c.import_ct(Bw[a], level)
+            y.scale = scale
+            B_g.append(y)
+        outs = None if outputs is None else [o for o in outputs if o < og["n_out"]]
+        want.append((keys_o.matmul_cc(Aw, Bw, level, H, L, d, outputs=outs), outs, grp))
+        h0 += H
+    Cd = [c.ct(level - 3) for _ in range(info["n_out"])]
+    B.blb_matmul_cc(c.h, keys_g, plan, A_g, B_g, Cd)
+    return dict(Q=Q, Kt=Kt, keys_o=keys_o, keys_g=keys_g, plan=plan, info=info, A=A_g, B=B_g, C=Cd, want=want, level=level)
+
+
+@pytest.mark.parametrize("heads,L,d,outputs", [(8, 32, 32, None), (12, 64, 32, [0, 1])])
+def test_matmul_cc_matches_oracle(c3s, heads, L, d, outputs):
+    """Multi-head ct-ct matmul (steps 2-3, pre-rotated B) word for word against the oracle,
+    including the 8 + 4 head-group split; decoded outputs equal Q_h K_h^T."""
+    from paper_2508_19525_amd import workloads as wl
+    r = _cc_case(c3s, heads, L, d, heads + L, outputs)
+    h0 = 0
+    for O_want, outs, grp in r["want"]:
+        sel = range(grp["n_out"]) if outs is None else outs
+        for o in sel:
+            got = c3s.export(r["C"][_out_index(r["info"], grp, o)])
+            assert np.array_equal(got, O_want[o]), f"group H={grp['H']} output {o}"
+        if outs is None:
+            vecs = []
+            for o in range(grp["n_out"]):
+                ct = r["C"][_out_index(r["info"], grp, o)]
+                pt = c3s.pt_dev(0)
+                c3s.B.blb_decrypt(c3s.h, r["keys_g"], ct, pt)
+                vecs.append(c3s.B.blb_decode(c3s.h, pt, 0, ct.scale, c3s.n // 2))
+            Cs = wl.unpack_diag(vecs, grp["H"], L, c3s.n // 2)
+            for h in range(grp["H"]):
+                ref = r["Q"][h0 + h] @ r["Kt"][h0 + h]
+                assert np.abs(Cs[h] - ref).max() < 2.0 ** -20 * 64
+        h0 += grp["H"]
+    c3s.B.blb_plan_destroy(r["plan"])
+    c3s.B.blb_keys_destroy(r["keys_g"])
+
+
+def _out_index(info, grp, o):
+    base = 0
+    for g in info["groups"]:
+        if g is grp or g == grp:
+            return base + o
+        base += g["n_out"]
+    raise AssertionError
+
+
+# --------------------------------------------------------------------------------------
+# graph executors: every replay equals the eager result
+# --------------------------------------------------------------------------------------
+def test_exec_cp_replays_match_eager(c2s):
+    B = c2s.B
+    L, d_in, d_out, level = 64, 96, 64, 2
+    r = _cp_case(c2s, L, d_in, d_out, level, 77, x_std=1.0)
+    n_out = r["g"]["n_out"]
+    Ye = [c2s.ct(level - 1) for _ in range(n_out)]
+    Yg = [c2s.ct(level - 1) for _ in range(n_out)]
+    share_e = torch.zeros(n_out * level * c2s.n, dtype=torch.int64, device="cuda")
+    share_g = torch.zeros_like(share_e)
+    ex = B.blb_exec_create_cp(c2s.h, r["keys_g"], r["plan"], _xcts(c2s, r, level), Yg, level - 1, share_g)
+    for rep, seed in enumerate([5, 6, 5]):
+        B.blb_exec_run(ex, seed)
+        torch.cuda.synchronize()
+        got = [c2s.export(y) for y in Yg]
+        got_share = share_g.cpu().numpy().copy()
+        # eager work between replays
+        B.blb_matmul_cp(c2s.h, r["keys_g"], r["plan"], _xcts(c2s, r, level), Ye)
+        B.blb_mask_to_share(c2s.h, Ye, seed, level - 1, share_e)
+        torch.cuda.synchronize()
+        for b in range(n_out):
+            assert np.array_equal(got[b], c2s.export(Ye[b])), f"replay {rep} output {b}"
+        assert np.array_equal(got_share, share_e.cpu().numpy()), f"replay {rep} share"
+    B.blb_exec_destroy(ex)
+
+
+def _xcts(c, r, level):
+    if "_xc" not in r:
+        xs = []
+        for a in range(r["g"]["n_in"]):
+            ct = c.import_ct(r["X_words"][a], level)
+            ct.scale = r["scale"]
+            xs.append(ct)
+        r["_xc"] = xs
+    return r["_xc"]
+
+
+def test_exec_cc_replays_match_eager(c3s):
+    B = c3s.B
+    r = _cc_case(c3s, 8, 32, 32, 3)
+    n_out = r["info"]["n_out"]
+    Cg = [c3s.ct(r["level"] - 3) for _ in range(n_out)]
+    ex = B.blb_exec_create_cc(c3s.h, r["keys_g"], r["plan"], r["A"], r["B"], Cg)
+    for rep in range(3):
+        B.blb_exec_run(ex, 0)
+        torch.cuda.synchronize()
+        got = [c3s.export(x) for x in Cg]
+        B.blb_matmul_cc(c3s.h, r["keys_g"], r["plan"], r["A"], r["B"], r["C"])
+        torch.cuda.synchronize()
+        for o in range(n_out):
+            assert np.array_equal(got[o], c3s.export(r["C"][o])), f"replay {rep} output {o}"
+    B.blb_exec_destroy(ex)
