@@ -85,7 +85,7 @@ int blb_ctx_read_timing(blb_ctx* ctx, int kind, double* total_ms, int64_t* launc
 int blb_ctx_reset_timing(blb_ctx* ctx);
 
 /* ---- launch-shape knobs (never change a result bit; chosen by the autotuner) ------------ */
-enum { BLB_KNOB_MAC_VARIANT = 0, BLB_KNOB_KINDS = 1 };
+enum { BLB_KNOB_MAC_VARIANT = 0, BLB_KNOB_BATCH_VARIANT = 1, BLB_KNOB_BATCH_GRID = 2, BLB_KNOB_KINDS = 3 };
 int blb_ctx_set_knob(blb_ctx* ctx, int knob, int value);
 int blb_ctx_get_knob(const blb_ctx* ctx, int knob);
 
@@ -164,6 +164,23 @@ int blb_matmul_cc(blb_ctx* ctx, const blb_keys* keys, const blb_plan* plan, cons
  * server share -r mod q_i in coefficient form to share_dev[t][limb][N]. */
 int blb_mask_to_share(blb_ctx* ctx, blb_ct* cts, int n_ct, uint64_t seed, int target_level, uint64_t* share_dev);
 
+/* ---- batched matmul_cp over independent instances ------------------------------------
+ * Each instance has its own keys (its client), plan (plans may be shared between instances
+ * with the same weights and L'), inputs and outputs; all plans must be at one level.  Every
+ * stage (baby-step key switches, plaintext MACs, giant-step key switches, sums, rescale) runs
+ * once for the whole batch; the MACs of all instances are one persistent launch that applies
+ * each plaintext word to several instances sharing its plan.  Results are bit-identical to
+ * per-instance blb_matmul_cp calls. */
+typedef struct {
+  const blb_keys* keys;
+  const blb_plan* plan;
+  const blb_ct* X;
+  int n_in;
+  blb_ct* Y;
+  int n_out;
+} blb_cp_instance;
+int blb_batch_matmul_cp(blb_ctx* ctx, const blb_cp_instance* inst, int n_inst);
+
 /* ---- graph executors -------------------------------------------------------------------
  * One fused operator invocation over fixed ciphertext buffers (matmul_cp or matmul_cc,
  * optionally followed by mask-and-share of its outputs to mask_target_level; -1 = no mask)
@@ -176,6 +193,10 @@ int blb_exec_create_cp(blb_ctx* ctx, const blb_keys* keys, const blb_plan* plan,
                        int mask_target_level, uint64_t* share_dev, blb_exec** out);
 int blb_exec_create_cc(blb_ctx* ctx, const blb_keys* keys, const blb_plan* plan, const blb_ct* A, const blb_ct* Bp, int n_ct,
                        blb_ct* C_diag, int n_out, int mask_target_level, uint64_t* share_dev, blb_exec** out);
+/* The whole batch in one graph launch; with a mask, all outputs (instance order) are masked as
+ * one list, share_dev receiving [output][limb][N] for them in that order. */
+int blb_exec_create_batch_cp(blb_ctx* ctx, const blb_cp_instance* inst, int n_inst, int mask_target_level, uint64_t* share_dev,
+                             blb_exec** out);
 int blb_exec_run(blb_exec* exec, uint64_t mask_seed);
 uint64_t blb_exec_device_bytes(const blb_exec* exec);
 void blb_exec_destroy(blb_exec* exec);

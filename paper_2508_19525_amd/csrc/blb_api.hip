@@ -661,6 +661,14 @@ int blb_ctx_set_knob(blb_ctx* c, int knob, int value) {
       if (value < 0 || value > 4) return BLB_EINVAL;
       c->mac_variant = value;
       return BLB_OK;
+    case BLB_KNOB_BATCH_VARIANT:
+      if (value < 0 || value > 4) return BLB_EINVAL;
+      c->batch_variant = value;
+      return BLB_OK;
+    case BLB_KNOB_BATCH_GRID:
+      if (value < 1 || value > (1 << 20)) return BLB_EINVAL;
+      c->batch_grid = value;
+      return BLB_OK;
     default: return BLB_EINVAL;
   }
 }
@@ -668,6 +676,8 @@ int blb_ctx_get_knob(const blb_ctx* c, int knob) {
   if (!c) return BLB_EINVAL;
   switch (knob) {
     case BLB_KNOB_MAC_VARIANT: return c->mac_variant;
+    case BLB_KNOB_BATCH_VARIANT: return c->batch_variant;
+    case BLB_KNOB_BATCH_GRID: return c->batch_grid;
     default: return BLB_EINVAL;
   }
 }
@@ -1716,6 +1726,221 @@ void blb_exec_destroy(blb_exec* E) {
   if (E->c) (void)hipStreamSynchronize(E->c->stream);
   exec_release(E);
   delete E;
+}
+
+}  // extern "C"
+
+// ==========================================================================================
+// Batched matmul_cp over independent instances (own keys, shared or own plans, uneven
+// lengths): every stage runs once for the whole batch.
+// ==========================================================================================
+extern "C" {
+
+int blb_batch_matmul_cp(blb_ctx* c, const blb_cp_instance* inst, int n_inst) {
+  if (!c || !inst || n_inst < 1) return BLB_EINVAL;
+  const int n = c->n;
+  const int level = inst[0].plan ? inst[0].plan->level : -1;
+  // validate everything before enqueuing work
+  struct Ik {
+    std::vector<const SwKey*> kb, kg;
+  };
+  std::vector<Ik> ik(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    const blb_cp_instance& I = inst[i];
+    if (!I.keys || !I.plan || !I.X || !I.Y || I.plan->kind != 1) return BLB_EINVAL;
+    const CpGeom& g = I.plan->g;
+    if (I.plan->level != level) return BLB_ELEVEL;
+    if (I.n_in != g.n_in || I.n_out != g.n_out) return BLB_EINVAL;
+    for (int a = 0; a < I.n_in; ++a) {
+      if (check_ct(c, &I.X[a]) || I.X[a].degree != 1) return BLB_EINVAL;
+      if (I.X[a].level != level) return BLB_ELEVEL;
+    }
+    for (int b = 0; b < I.n_out; ++b)
+      if (!I.Y[b].data) return BLB_EINVAL;
+    ik[i].kb.assign(g.B, nullptr);
+    ik[i].kg.assign(g.G, nullptr);
+    for (int b = 1; b < g.B; ++b)
+      if (!(ik[i].kb[b] = find_key(I.keys, galois_left(c, (int64_t)b * g.Lp)))) return BLB_ENOKEY;
+    for (int j = 1; j < g.G; ++j)
+      if (!(ik[i].kg[j] = find_key(I.keys, galois_left(c, (int64_t)j * g.B * g.Lp)))) return BLB_ENOKEY;
+  }
+  const int nl = level + 1;
+  const size_t ctw = (size_t)2 * nl * n;
+  Tmp tmp(c);
+  std::vector<uint64_t*> RX(n_inst), inner(n_inst), rot(n_inst), acc(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    const CpGeom& g = inst[i].plan->g;
+    RX[i] = tmp.get<uint64_t>((size_t)std::max(1, g.n_in * (g.B - 1)) * ctw);
+    inner[i] = tmp.get<uint64_t>((size_t)g.n_out * g.G * ctw);
+    rot[i] = tmp.get<uint64_t>((size_t)std::max(1, g.n_out * (g.G - 1)) * ctw);
+    acc[i] = tmp.get<uint64_t>((size_t)g.n_out * ctw);
+  }
+  if (tmp.failed) return BLB_ENOMEM;
+  // baby steps of every instance in one key-switch batch
+  std::vector<const uint64_t*> srcs;
+  std::vector<KsReq> reqs;
+  std::vector<std::vector<const uint64_t*>> rx_tab(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    const blb_cp_instance& I = inst[i];
+    const CpGeom& g = I.plan->g;
+    rx_tab[i].assign((size_t)g.n_in * g.B, nullptr);
+    for (int a = 0; a < g.n_in; ++a) {
+      srcs.push_back(I.X[a].data + (size_t)nl * n);
+      const int s = (int)srcs.size() - 1;
+      rx_tab[i][(size_t)a * g.B] = I.X[a].data;
+      for (int b = 1; b < g.B; ++b) {
+        const uint32_t gal = galois_left(c, (int64_t)b * g.Lp);
+        uint64_t* dst = RX[i] + (size_t)(a * (g.B - 1) + b - 1) * ctw;
+        rx_tab[i][(size_t)a * g.B + b] = dst;
+        reqs.push_back(KsReq{s, ik[i].kb[b], gal, dst, I.X[a].data, gal, nullptr});
+      }
+    }
+  }
+  int rc = ks_batch(c, level, srcs, reqs);
+  if (rc) return rc;
+  // MACs: one persistent launch over all plan groups
+  {
+    std::vector<const blb_plan*> plans;
+    std::vector<std::vector<int>> members;
+    for (int i = 0; i < n_inst; ++i) {
+      int gi = -1;
+      for (size_t k = 0; k < plans.size(); ++k)
+        if (plans[k] == inst[i].plan) gi = (int)k;
+      if (gi < 0) {
+        plans.push_back(inst[i].plan);
+        members.emplace_back();
+        gi = (int)plans.size() - 1;
+      }
+      members[gi].push_back(i);
+    }
+    int tb, ib, cpt;
+    batch_mac_shape(c->batch_variant, &tb, &ib, &cpt);
+    std::vector<MacGroup> groups;
+    std::vector<MacItem> items;
+    for (size_t gi = 0; gi < plans.size(); ++gi) {
+      const CpGeom& g = plans[gi]->g;
+      const int n_ai = g.n_in * g.B, n_bj = g.n_out * g.G;
+      std::vector<const uint64_t*> rx;
+      std::vector<uint64_t*> outs;
+      for (int i : members[gi]) {
+        rx.insert(rx.end(), rx_tab[i].begin(), rx_tab[i].end());
+        outs.push_back(inner[i]);
+      }
+      MacGroup mg;
+      mg.pt = plans[gi]->pt;
+      mg.rx = upload_vec(c, rx);
+      mg.inner = (uint64_t* const*)upload(c, outs.data(), outs.size() * sizeof(uint64_t*));
+      if (!mg.rx || !mg.inner) return BLB_EDEVICE;
+      mg.n_ai = n_ai;
+      mg.n_bj = n_bj;
+      mg.nl = nl;
+      mg.n_inst = (int)members[gi].size();
+      groups.push_back(mg);
+      const int n_kb = n / (256 * cpt);
+      for (int i0 = 0; i0 < mg.n_inst; i0 += ib)
+        for (int limb = 0; limb < nl; ++limb)
+          for (int kb = 0; kb < n_kb; ++kb)
+            for (int t = 0; t * tb < n_bj; ++t) items.push_back(MacItem{(int)gi, i0, t, kb, limb});
+    }
+    const MacGroup* g_dev = upload_vec(c, groups);
+    const MacItem* it_dev = upload_vec(c, items);
+    if (!g_dev || !it_dev) return BLB_EDEVICE;
+    double units = 0;
+    for (int i = 0; i < n_inst; ++i) units += (double)inst[i].plan->g.n_out * inst[i].plan->g.G * nl * n;
+    Span sp(c, BLB_T_CP_MAC, units);
+    launch_cp_mac_batch(c, g_dev, it_dev, (int)items.size(), c->batch_variant, c->batch_grid);
+  }
+  // giant steps of every instance in one key-switch batch
+  srcs.clear();
+  reqs.clear();
+  for (int i = 0; i < n_inst; ++i) {
+    const CpGeom& g = inst[i].plan->g;
+    for (int b = 0; b < g.n_out; ++b)
+      for (int j = 1; j < g.G; ++j) {
+        const uint64_t* src = inner[i] + (size_t)(b * g.G + j) * ctw;
+        const uint32_t gal = galois_left(c, (int64_t)j * g.B * g.Lp);
+        srcs.push_back(src + (size_t)nl * n);
+        reqs.push_back(KsReq{(int)srcs.size() - 1, ik[i].kg[j], gal, rot[i] + (size_t)(b * (g.G - 1) + j - 1) * ctw, src, gal, nullptr});
+      }
+  }
+  if ((rc = ks_batch(c, level, srcs, reqs))) return rc;
+  {
+    std::vector<const uint64_t*> terms;
+    std::vector<int> off{0};
+    std::vector<uint64_t*> outs;
+    for (int i = 0; i < n_inst; ++i) {
+      const CpGeom& g = inst[i].plan->g;
+      for (int b = 0; b < g.n_out; ++b) {
+        terms.push_back(inner[i] + (size_t)(b * g.G) * ctw);
+        for (int j = 1; j < g.G; ++j) terms.push_back(rot[i] + (size_t)(b * (g.G - 1) + j - 1) * ctw);
+        off.push_back((int)terms.size());
+        outs.push_back(acc[i] + (size_t)b * ctw);
+      }
+    }
+    const uint64_t* const* t_dev = upload_vec(c, terms);
+    const int* off_dev = upload_vec(c, off);
+    uint64_t* const* o_dev = (uint64_t* const*)upload(c, outs.data(), outs.size() * sizeof(uint64_t*));
+    if (!t_dev || !off_dev || !o_dev) return BLB_EDEVICE;
+    Span sp(c, BLB_T_EW, (double)outs.size() * ctw);
+    launch_sum_var(c, t_dev, off_dev, o_dev, (int)outs.size(), nl);
+  }
+  std::vector<const uint64_t*> rin;
+  std::vector<uint64_t*> rout;
+  for (int i = 0; i < n_inst; ++i)
+    for (int b = 0; b < inst[i].n_out; ++b) {
+      rin.push_back(acc[i] + (size_t)b * ctw);
+      rout.push_back(inst[i].Y[b].data);
+    }
+  if ((rc = rescale_batch(c, level, 2, rin, rout))) return rc;
+  for (int i = 0; i < n_inst; ++i)
+    for (int b = 0; b < inst[i].n_out; ++b) {
+      inst[i].Y[b].level = level - 1;
+      inst[i].Y[b].degree = 1;
+      inst[i].Y[b].scale = inst[i].X[0].scale;
+    }
+  return BLB_OK;
+}
+
+int blb_exec_create_batch_cp(blb_ctx* c, const blb_cp_instance* inst, int n_inst, int mask_target_level, uint64_t* share_dev,
+                             blb_exec** out) {
+  if (!c || !inst || n_inst < 1 || !out) return BLB_EINVAL;
+  if (mask_target_level >= 0 && !share_dev) return BLB_EINVAL;
+  *out = nullptr;
+  blb_exec* E = new (std::nothrow) blb_exec();
+  if (!E) return BLB_ENOMEM;
+  E->has_mask = mask_target_level >= 0;
+  size_t guess = 64u << 20;
+  int n_outs = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    if (!inst[i].plan) {
+      delete E;
+      return BLB_EINVAL;
+    }
+    const CpGeom& g = inst[i].plan->g;
+    guess += (size_t)2 * (inst[i].plan->level + 1) * c->n * 8 * (size_t)(g.n_in * g.B * 6 + g.n_out * g.G * 6 + 8);
+    n_outs += inst[i].n_out;
+  }
+  std::vector<blb_ct> all;
+  const int rc = exec_record(c, E, guess, [&]() -> int {
+    int r = blb_batch_matmul_cp(c, inst, n_inst);
+    if (r || mask_target_level < 0) return r;
+    all.clear();
+    for (int i = 0; i < n_inst; ++i)
+      for (int b = 0; b < inst[i].n_out; ++b) all.push_back(inst[i].Y[b]);
+    r = blb_mask_to_share(c, all.data(), (int)all.size(), 0, mask_target_level, share_dev);
+    int k = 0;
+    for (int i = 0; i < n_inst; ++i)
+      for (int b = 0; b < inst[i].n_out; ++b) inst[i].Y[b].level = all[k++].level;
+    return r;
+  });
+  (void)n_outs;
+  if (rc) {
+    exec_release(E);
+    delete E;
+    return rc;
+  }
+  *out = E;
+  return BLB_OK;
 }
 
 }  // extern "C"

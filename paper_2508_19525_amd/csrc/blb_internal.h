@@ -101,6 +101,17 @@ struct CcTerm {
   const uint64_t* mask;
 };
 
+// batched matmul_cp MAC
+struct MacGroup {
+  const uint64_t* pt;           // plan plaintexts [(b, j)][(a, i)][limb][N]
+  const uint64_t* const* rx;    // [instance][n_ai] rotated inputs ([2][nl][N] each)
+  uint64_t* const* inner;       // [instance] -> [n_bj][2][nl][N]
+  int n_ai, n_bj, nl, n_inst;
+};
+struct MacItem {
+  int group, inst0, tile, kb, limb;
+};
+
 struct CpGeom {
   int d_in, d_out, L;
   int Lp, c, c_eff, c_out, n_in, n_out, B, G;
@@ -164,6 +175,8 @@ struct blb_ctx {
   Uploader up;
   int* d_flag = nullptr;          // device error flag (encoder overflow)
   int mac_variant = 0;            // k_cp_mac tile shape (autotuned; never changes results)
+  int batch_variant = 0;          // k_cp_mac_batch shape (autotuned)
+  int batch_grid = 2048;          // persistent grid size of k_cp_mac_batch (autotuned)
 };
 
 // Switching key in evaluation form: [digit][2 (b, a)][modulus (all q's then p's)][N] residues
@@ -231,6 +244,9 @@ void launch_moddown_conv(blb_ctx* c, const uint64_t* U, uint64_t* Corr, const Ks
 void launch_cp_mac(blb_ctx* c, const uint64_t* pt, const uint64_t* const* rx_tab, uint64_t* inner, int nl, int n_ai, int n_bj, int variant);
 void launch_sum_cts(blb_ctx* c, const uint64_t* const* srcs, uint64_t* const* dsts, int n_out, int n_terms, int nl);
 void launch_mask_pair(blb_ctx* c, const CcPair* pairs_dev, int n_pairs, int nl);
+int batch_mac_shape(int variant, int* tb, int* ib, int* cpt);
+void launch_cp_mac_batch(blb_ctx* c, const MacGroup* groups, const MacItem* items, int n_items, int variant, int grid);
+void launch_sum_var(blb_ctx* c, const uint64_t* const* srcs, const int* off, uint64_t* const* dsts, int n_out, int nl);
 void launch_tensor_sum(blb_ctx* c, const uint64_t* const* A_tab, const uint64_t* const* R_tab, uint64_t* T3, int n_t, int n_ct, int nlA,
                        int nl2);
 void launch_masked_acc(blb_ctx* c, const CcTerm* terms, const int* off, uint64_t* const* outs, int n_out, int nl, bool accumulate);

@@ -2,6 +2,7 @@
 // All modular arithmetic is the FP64 signed-lazy scheme of blb_internal.h.
 #include "blb_internal.h"
 #include "blb_kernels.h"
+#include <algorithm>
 
 // ---------------------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): 10 rounds, multipliers 0xD2511F53 / 0xCD9E8D57,
@@ -629,4 +630,139 @@ void launch_masked_acc(blb_ctx* c, const CcTerm* terms, const int* off, uint64_t
   if (n_out <= 0) return;
   dim3 grid((2 * nl * c->n + 255) / 256, n_out);
   k_masked_acc<<<grid, 256, 0, c->stream>>>(terms, off, outs, nl, c->n, c->mt, accumulate ? 1 : 0);
+}
+
+// ---------------------------------------------------------------------------------------
+// Batched matmul_cp MAC over many independent instances (uneven lengths, several plans).
+// Work item = (plan group, IB consecutive instances of the group, TB outputs, 256*CPT
+// coefficients, one limb).  A persistent grid walks the item list with a grid stride; each
+// plaintext word loaded is applied to IB instances' rotated inputs, so instances sharing a
+// plan read its diagonals once per IB instances.
+// ---------------------------------------------------------------------------------------
+template <int TB, int IB, int CPT>
+__global__ __launch_bounds__(256) void k_cp_mac_batch(const MacGroup* __restrict__ groups, const MacItem* __restrict__ items, int n_items,
+                                                      int n, ModTable mt) {
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const MacItem item = items[it];
+    const MacGroup gr = groups[item.group];
+    const int k0 = (item.kb * 256 + threadIdx.x) * CPT;
+    if (k0 >= n) continue;
+    const int limb = item.limb, nl = gr.nl, n_ai = gr.n_ai, n_bj = gr.n_bj;
+    const ModEntry me = mt.m[limb];
+    const double q = me.q, qi = me.qinv;
+    const int bj0 = item.tile * TB;
+    const int ninst = min(IB, gr.n_inst - item.inst0);
+    double a0[IB][TB][CPT], a1[IB][TB][CPT];
+#pragma unroll
+    for (int u = 0; u < IB; ++u)
+#pragma unroll
+      for (int t = 0; t < TB; ++t)
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) { a0[u][t][c] = 0.0; a1[u][t][c] = 0.0; }
+    const size_t pt_stride_bj = (size_t)n_ai * nl * n;
+    for (int ai = 0; ai < n_ai; ++ai) {
+      double x0[IB][CPT], x1[IB][CPT];
+#pragma unroll
+      for (int u = 0; u < IB; ++u) {
+        if (u < ninst) {
+          const uint64_t* rx = gr.rx[(size_t)(item.inst0 + u) * n_ai + ai];
+#pragma unroll
+          for (int c = 0; c < CPT; ++c) {
+            x0[u][c] = u2d(rx[(size_t)limb * n + k0 + c]);
+            x1[u][c] = u2d(rx[(size_t)(nl + limb) * n + k0 + c]);
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < CPT; ++c) { x0[u][c] = 0.0; x1[u][c] = 0.0; }
+        }
+      }
+      const uint64_t* p = gr.pt + ((size_t)bj0 * n_ai + ai) * nl * n + (size_t)limb * n + k0;
+#pragma unroll
+      for (int t = 0; t < TB; ++t) {
+        if (bj0 + t < n_bj) {
+          double w[CPT];
+#pragma unroll
+          for (int c = 0; c < CPT; ++c) w[c] = u2d(__builtin_nontemporal_load(p + t * pt_stride_bj + c));
+#pragma unroll
+          for (int u = 0; u < IB; ++u)
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+              a0[u][t][c] += mulmod_s(w[c], x0[u][c], q, qi);
+              a1[u][t][c] += mulmod_s(w[c], x1[u][c], q, qi);
+            }
+        }
+      }
+      if ((ai & 7) == 7) {
+#pragma unroll
+        for (int u = 0; u < IB; ++u)
+#pragma unroll
+          for (int t = 0; t < TB; ++t)
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) { a0[u][t][c] = reduce_s(a0[u][t][c], q, qi); a1[u][t][c] = reduce_s(a1[u][t][c], q, qi); }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < IB; ++u) {
+      if (u >= ninst) continue;
+      uint64_t* out = gr.inner[item.inst0 + u];
+#pragma unroll
+      for (int t = 0; t < TB; ++t) {
+        if (bj0 + t < n_bj) {
+          uint64_t* o0 = out + (((size_t)(bj0 + t) * 2 + 0) * nl + limb) * n + k0;
+          uint64_t* o1 = out + (((size_t)(bj0 + t) * 2 + 1) * nl + limb) * n + k0;
+#pragma unroll
+          for (int c = 0; c < CPT; ++c) {
+            o0[c] = d2u(canon_full(a0[u][t][c], q, qi));
+            o1[c] = d2u(canon_full(a1[u][t][c], q, qi));
+          }
+        }
+      }
+    }
+  }
+}
+
+int batch_mac_shape(int variant, int* tb, int* ib, int* cpt) {
+  switch (variant) {
+    case 1: *tb = 4; *ib = 1; *cpt = 2; break;
+    case 2: *tb = 2; *ib = 4; *cpt = 2; break;
+    case 3: *tb = 4; *ib = 4; *cpt = 1; break;
+    case 4: *tb = 8; *ib = 2; *cpt = 1; break;
+    default: *tb = 4; *ib = 2; *cpt = 2; break;
+  }
+  return 0;
+}
+
+void launch_cp_mac_batch(blb_ctx* c, const MacGroup* groups, const MacItem* items, int n_items, int variant, int grid) {
+  if (n_items <= 0) return;
+  int tb, ib, cpt;
+  batch_mac_shape(variant, &tb, &ib, &cpt);
+  const int blocks = std::min(n_items, grid);
+#define MB(a, b, d) k_cp_mac_batch<a, b, d><<<blocks, 256, 0, c->stream>>>(groups, items, n_items, c->n, c->mt)
+  if (tb == 4 && ib == 1) MB(4, 1, 2);
+  else if (tb == 2 && ib == 4) MB(2, 4, 2);
+  else if (tb == 4 && ib == 4) MB(4, 4, 1);
+  else if (tb == 8 && ib == 2) MB(8, 2, 1);
+  else MB(4, 2, 2);
+#undef MB
+}
+
+// out[o] = sum of its terms (offsets per output), whole ciphertexts of `words` u64 each
+__global__ void k_sum_var(const uint64_t* const* __restrict__ srcs, const int* __restrict__ off, uint64_t* const* __restrict__ dsts,
+                          int n, int nl, ModTable mt) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  const int o = blockIdx.y;
+  if (w >= 2 * nl * n) return;
+  const ModEntry me = mt.m[(w / n) % nl];
+  double acc = 0.0;
+  int cnt = 0;
+  for (int t = off[o]; t < off[o + 1]; ++t) {
+    acc += u2d(srcs[t][w]);
+    if ((++cnt & 3) == 0) acc = reduce_s(acc, me.q, me.qinv);
+  }
+  dsts[o][w] = d2u(canon_full(acc, me.q, me.qinv));
+}
+void launch_sum_var(blb_ctx* c, const uint64_t* const* srcs, const int* off, uint64_t* const* dsts, int n_out, int nl) {
+  if (n_out <= 0) return;
+  dim3 grid((2 * nl * c->n + 255) / 256, n_out);
+  k_sum_var<<<grid, 256, 0, c->stream>>>(srcs, off, dsts, c->n, nl, c->mt);
 }
