@@ -256,6 +256,128 @@ def run_cc(args, B, torch):
     return res
 
 
+def run_batch(args, B, torch):
+    """64 independent matmul_cp instances (own keys; one weight matrix per hidden size; lengths
+    uniform in 16..512): per-instance calls vs the batched path vs its one-launch graph."""
+    import ctypes
+    from paper_2508_19525_amd import workloads as wl
+
+    cfg = wl.C4
+    p = cfg["params"]
+    n, level = p.n, p.n_q - 1
+    shapes = wl.batch_instances(cfg["n_inst"], cfg["L_lo"], cfg["L_hi"], cfg["hidden"])
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = B.blb_ctx_create(p.log_n, p.n_q, p.n_special, p.dnum, 0, stream)
+    t_setup = time.time()
+    Ws = {D: wl.batch_weights(D) for D in cfg["hidden"]}
+    plans, insts, keep = {}, [], []
+    pt = torch.empty((level + 1) * n, dtype=torch.int64, device="cuda")
+    modmul = 0
+    for i, (L, D) in enumerate(shapes):
+        lp = wl.lp_of(L)
+        if (D, lp) not in plans:
+            plans[(D, lp)] = B.blb_plan_matmul_cp(ctx, Ws[D], lp, level)
+        plan = plans[(D, lp)]
+        g = B.blb_plan_info(plan)
+        modmul += g["n_in"] * g["n_out"] * g["c_eff"] * 2 * (level + 1) * n
+        steps = [k * g["Lp"] for k in range(1, g["B"])] + [j * g["B"] * g["Lp"] for j in range(1, g["G"])]
+        keys = B.blb_keygen(ctx, wl.seed_for(4, wl.ROLE_KEYS) * 100 + i, steps)
+        X = wl.batch_activations(i, L, D)
+        xs, ys, ys2 = [], [], []
+        for a in range(g["n_in"]):
+            B.blb_encode(ctx, wl.pack_spatial(X, n // 2, a), p.scale, level, pt)
+            ct, t = B.new_ct(n, level)
+            keep.append(t)
+            B.blb_encrypt(ctx, keys, pt, level, p.scale, wl.seed_for(4, wl.ROLE_ENC) * 100 + i, a, ct)
+            xs.append(ct)
+        for b in range(g["n_out"]):
+            for lst in (ys, ys2):
+                ct, t = B.new_ct(n, level - 1)
+                keep.append(t)
+                lst.append(ct)
+        insts.append(dict(keys=keys, plan=plan, X=xs, Y=ys, Y2=ys2))
+    arr = (B.blb_cp_instance * len(insts))()
+    hold = []
+    for k, I in enumerate(insts):
+        Xa = (B.blb_ct * len(I["X"]))(*I["X"])
+        Ya = (B.blb_ct * len(I["Y"]))(*I["Y"])
+        hold += [Xa, Ya]
+        arr[k] = B.blb_cp_instance(I["keys"], I["plan"], ctypes.cast(Xa, ctypes.c_void_p), len(I["X"]),
+                                   ctypes.cast(Ya, ctypes.c_void_p), len(I["Y"]))
+    torch.cuda.synchronize()
+    log(f"batch setup {time.time() - t_setup:.1f}s: {len(insts)} instances, {len(plans)} plans, "
+        f"{B.blb_ctx_device_bytes(ctx) / 1e9:.1f} GB library memory, {modmul / 1e9:.1f}e9 modmul per batch")
+
+    def unbatched():
+        for I in insts:
+            B.blb_matmul_cp(ctx, I["keys"], I["plan"], I["X"], I["Y2"])
+
+    reps = max(2, args.steps // 10)
+    unbatched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        unbatched()
+    torch.cuda.synchronize()
+    t_unb = (time.perf_counter() - t0) / reps
+    B.blb_ctx_trim(ctx)
+    # autotune the batched MAC (shape x persistent grid): bit-identical variants
+    tune = {}
+    B.blb_ctx_set_timing(ctx, True)
+    for var in range(5):
+        for grid in (1024, 4096):
+            B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_VARIANT, var)
+            B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_GRID, grid)
+            B.blb_ctx_reset_timing(ctx)
+            B.blb_batch_matmul_cp(ctx, arr)
+            tune[f"{var}/{grid}"] = B.blb_ctx_read_timing(ctx, B.BLB_T_CP_MAC)[0]
+    best = min(tune, key=tune.get)
+    var, grid = (int(x) for x in best.split("/"))
+    B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_VARIANT, var)
+    B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_GRID, grid)
+    B.blb_ctx_reset_timing(ctx)
+    B.blb_ctx_set_timing(ctx, False)
+    log(f"batched MAC variants (ms): {tune} -> {best}")
+    B.blb_batch_matmul_cp(ctx, arr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        B.blb_batch_matmul_cp(ctx, arr)
+    torch.cuda.synchronize()
+    t_bat = (time.perf_counter() - t0) / reps
+    # bit identity (first and last output of every instance)
+    same = True
+    for k, I in enumerate(insts):
+        for b in (0, len(I["Y"]) - 1):
+            got = B.blb_export(ctx, B.blb_ct.from_address(arr[k].Y + b * ctypes.sizeof(B.blb_ct)), n)
+            same &= bool(np.array_equal(got, B.blb_export(ctx, I["Y2"][b], n)))
+    B.blb_ctx_trim(ctx)
+    ex = B.blb_exec_create_batch_cp(ctx, arr)
+    B.blb_exec_run(ex)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        B.blb_exec_run(ex)
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / reps
+    for k, I in enumerate(insts):
+        got = B.blb_export(ctx, B.blb_ct.from_address(arr[k].Y), n)
+        same &= bool(np.array_equal(got, B.blb_export(ctx, I["Y2"][0], n)))
+    log(f"batch: unbatched {t_unb * 1e3:.1f} ms, batched {t_bat * 1e3:.1f} ms, graph {t_graph * 1e3:.1f} ms, identical {same}")
+    res = {"instances": len(insts), "plans": len(plans), "modmul_per_batch": modmul,
+           "unbatched_ms": t_unb * 1e3, "batched_ms": t_bat * 1e3, "graph_ms": t_graph * 1e3,
+           "speedup_graph_vs_unbatched": t_unb / t_graph, "speedup_batched_vs_unbatched": t_unb / t_bat,
+           "modmul_per_s_graph": modmul / t_graph, "bit_identical": same, "autotune": {"best": best, "mac_ms": tune},
+           "executor_GB": B.blb_exec_device_bytes(ex) / 1e9}
+    B.blb_exec_destroy(ex)
+    for I in insts:
+        B.blb_keys_destroy(I["keys"])
+    for pl in plans.values():
+        B.blb_plan_destroy(pl)
+    B.blb_ctx_destroy(ctx)
+    return res
+
+
 def run_cpu_baseline():
     """The oracle on a bounded sample: one of the 24 output ciphertexts (all its 32 diagonal
     groups, 768 plaintext encodes + MACs, its 3 giant-step rotations and the rescale) timed
@@ -307,6 +429,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cc", action="store_true", help="skip the matmul_cc measurement")
     ap.add_argument("--no-tune", action="store_true", help="skip the MAC launch-shape autotuner")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched measurement")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB plain copy (counter reference)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -318,6 +441,7 @@ def main():
     torch.cuda.init()
     r = run_cp(args, B, torch)
     cc = None if args.no_cc else run_cc(args, B, torch)
+    bt = None if args.no_batch else run_batch(args, B, torch)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -355,6 +479,9 @@ def main():
             "metric": "ct-ct matmul/s (12-head Q_h K_h^T, 128 tokens, N=16384, 4 primes + 2 special)",
             "value": cc["value"], "eager_value": cc["eager"], "ms": cc["ms"], "max_abs_err": cc["err"],
             "ntt_GBps": cc["ntt_gbps"], "split_ms": cc["split_ms"], "rotation_keys": cc["rotation_keys"]},
+        "batched": None if bt is None else dict(
+            bt, workload="64 independent matmul_cp instances, L ~ U{16..512}, hidden 768/1024 (W shared per hidden size), "
+                         "N=8192, 3 primes; per-instance eager calls vs batched stages vs one graph launch"),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

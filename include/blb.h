@@ -71,6 +71,8 @@ void blb_ctx_destroy(blb_ctx* ctx);
 int blb_ctx_moduli(const blb_ctx* ctx, uint64_t* out);
 /* Library-owned device bytes currently allocated (keys, plans, scratch). */
 uint64_t blb_ctx_device_bytes(const blb_ctx* ctx);
+/* Synchronises the stream and returns cached temporary memory of the eager path to the device. */
+int blb_ctx_trim(blb_ctx* ctx);
 const char* blb_status_str(int code);
 
 /* ---- kernel timing (HIP events on the context stream) ----------------------------------
@@ -125,7 +127,9 @@ int blb_rescale(blb_ctx* ctx, const blb_ct* in, blb_ct* out);
 /* ---- matmul_cp (Section "Efficient Protocol for Fused MatMuls"; Appendix "BSGS
  * Optimization"; spatial-first packing of "Consistent Packing for Single Operator") ----- */
 /* Builds the BSGS diagonal plaintexts of W (host, d_in x d_out row-major) for inputs of L rows
- * at ciphertext level `level`: encoded on the device at scale q_level and kept resident.
+ * at ciphertext level `level`: encoded on the device at scale q_level / 2^10 and kept resident
+ * (the inputs are multiplied by the integer 2^10 before their key-switched rotations, which
+ * shrinks the key-switch noise relative to the message; the product scale is Delta_X q_level).
  * info (optional, 8 ints): L', c, c_eff, c_out, n_in, n_out, B, G. */
 int blb_plan_matmul_cp(blb_ctx* ctx, const double* W, int d_in, int d_out, int L, int level, blb_plan** out);
 void blb_plan_destroy(blb_plan* plan);
@@ -150,7 +154,8 @@ int blb_matmul_cp(blb_ctx* ctx, const blb_keys* keys, const blb_plan* plan, cons
  * written to steps (or needed, when steps is NULL). */
 int blb_cc_rotations(const blb_ctx* ctx, int n_heads, int L, int32_t* steps, int cap);
 /* Masks of steps 2 and 3 encoded on the device (step 2 at scale q_level 2^10, step 3 at
- * q_{level-2}). */
+ * q_{level-2} / 2^10; B' is multiplied by the integer 2^10 before its key-switched rotations
+ * so their noise shrinks relative to the message, which the step-3 mask scale undoes). */
 int blb_plan_matmul_cc(blb_ctx* ctx, int n_heads, int L, int d_head, int level, blb_plan** out);
 /* info: L', n_ct, n_out, then per group (H, c, n_ct, n_out, first ct); returns group count. */
 int blb_plan_cc_info(const blb_plan* plan, int32_t* info, int cap);

@@ -733,6 +733,21 @@ static void add_ct(const orc_ctx* c, uint64_t* acc, const uint64_t* x, int nl, i
 
 static int ceil_log2(int64_t v) { int r = 0; while ((1ll << r) < v) ++r; return r; }
 
+/* Noise boost applied before key-switched rotations inside the matmuls (reading: the paper
+ * gives no noise management; 2^10 keeps key-switch noise ~2^-27 of a 2^40-scaled message). */
+#define NOISE_BOOST 1024.0
+
+/* out = k * ct (integer scalar, every limb of both polys) */
+static void scale_ct(const orc_ctx* c, const uint64_t* ct, uint64_t k, int nl, uint64_t* out) {
+  int n = c->n;
+  for (int p = 0; p < 2; ++p)
+    for (int i = 0; i < nl; ++i)
+      for (int j = 0; j < n; ++j) {
+        size_t o = ((size_t)p * nl + i) * n + j;
+        out[o] = mulm(ct[o], k % c->mod[i], c->mod[i]);
+      }
+}
+
 /* ------------------------------------------------------------------------------------ */
 /* matmul_cp (pinned schedule)                                                           */
 /* ------------------------------------------------------------------------------------ */
@@ -777,12 +792,18 @@ int orc_matmul_cp(const orc_keys* K, const uint64_t* X, int level, const double*
   int32_t g[8]; orc_cp_geometry(c, L, d_in, d_out, g);
   int lp = g[0], cc = g[1], c_eff = g[2], c_out = g[3], n_in = g[4], n_out = g[5], B = g[6], G = g[7];
   size_t ctw = (size_t)2 * nl * n;
-  double delta_w = (double)c->mod[level];
+  /* noise boost: the inputs are multiplied by the integer 2^10 before their rotations (the
+   * key-switch noise is absolute, so it shrinks by 2^10 relative to the message) and the
+   * diagonals are encoded at q_l / 2^10, which leaves the product's scale Delta_X * q_l */
+  double delta_w = (double)c->mod[level] / NOISE_BOOST;
+  uint64_t* xs = (uint64_t*)malloc(8 * ctw * (size_t)n_in);
+  for (int a = 0; a < n_in; ++a) scale_ct(c, X + ctw * a, (uint64_t)NOISE_BOOST, nl, xs + ctw * a);
   /* baby steps: Rot_l^{iL'}(X_a) */
   uint64_t* rx = (uint64_t*)malloc(8 * ctw * (size_t)n_in * B);
   for (int a = 0; a < n_in; ++a)
     for (int i = 0; i < B; ++i)
-      if (orc_rotate(K, X + ctw * a, level, (int64_t)i * lp, rx + ctw * ((size_t)a * B + i)) != 0) { free(rx); return -1; }
+      if (orc_rotate(K, xs + ctw * a, level, (int64_t)i * lp, rx + ctw * ((size_t)a * B + i)) != 0) { free(rx); free(xs); return -1; }
+  free(xs);
   double* vec = (double*)malloc(8 * s);
   double* vrot = (double*)malloc(8 * s);
   uint64_t* pt = (uint64_t*)malloc(8 * (size_t)nl * n);
@@ -906,11 +927,12 @@ static void tensor_acc(const orc_ctx* c, uint64_t* acc3, const uint64_t* a, cons
 }
 
 /* Pinned schedule, inputs at `level` (A_a and pre-rotated B'_a, n_ct each, [ct][2][level+1][N]):
- *  step 2 (for t < L'): R_{a,t} = Rescale( Rot_l^t(B'_a) (.) M^lo_t + Rot_r^{L'-t}(B'_a) (.) M^hi_t ),
- *          masks encoded at q_level * 2^10 (t = 0: B'_a times the all-ones mask);
+ *  step 2 (for t < L'): B''_a = 2^10 B'_a (noise boost, an exact integer scalar), then
+ *          R_{a,t} = Rescale( Rot_l^t(B''_a) (.) M^lo_t + Rot_r^{L'-t}(B''_a) (.) M^hi_t ),
+ *          masks encoded at q_level * 2^10 (t = 0: B''_a times the all-ones mask);
  *          T_t = Rescale( Relin( sum_a Drop(A_a) (x) R_{a,t} ) )   (summed before relinearising)
  *  step 3 (t = g c + tau): V_t = Rot_r^{tau H_g L'}(T_t);
- *          O_g += V_t (.) M^{>=tau};  O_{(g+1) mod (L'/c)} += V_t (.) M^{<tau}  (masks at q_{level-2});
+ *          O_g += V_t (.) M^{>=tau};  O_{(g+1) mod (L'/c)} += V_t (.) M^{<tau}  (masks at q_{level-2} / 2^10);
  *          O_g = Rescale(O_g).
  * Output: L'/c cts at level-3, [g][2][level-2][N].  out_mask (NULL = all) selects the outputs;
  * only the t that feed them are computed. */
@@ -924,7 +946,9 @@ int orc_matmul_cc(const orc_keys* K, const uint64_t* A, const uint64_t* Bp, int 
   if (n_ct != geo[2] || cc < 1 || cc > lp || lp * H_g * cc != s) return -3;
   int nl = level + 1, l2 = level - 1, l1 = level - 2;
   size_t w3 = (size_t)2 * nl * n, w2 = (size_t)2 * (l2 + 1) * n, w1 = (size_t)2 * (l1 + 1) * n;
-  double dm2 = (double)c->mod[level] * 1024.0, dm3 = (double)c->mod[l1];
+  double dm2 = (double)c->mod[level] * 1024.0, dm3 = (double)c->mod[l1] / NOISE_BOOST;
+  uint64_t* bs = (uint64_t*)malloc(8 * w3 * (size_t)n_ct);
+  for (int a = 0; a < n_ct; ++a) scale_ct(c, Bp + (size_t)a * w3, (uint64_t)NOISE_BOOST, nl, bs + (size_t)a * w3);
   double* v = (double*)malloc(8 * s);
   uint64_t* rot = (uint64_t*)malloc(8 * w3);
   uint64_t* racc = (uint64_t*)malloc(8 * w3);
@@ -942,7 +966,7 @@ int orc_matmul_cc(const orc_keys* K, const uint64_t* A, const uint64_t* Bp, int 
     if (!need) continue;
     memset(T3, 0, 8 * (size_t)3 * (l2 + 1) * n);
     for (int a = 0; a < n_ct && rc == 0; ++a) {
-      const uint64_t* b = Bp + (size_t)a * w3;
+      const uint64_t* b = bs + (size_t)a * w3;
       memset(racc, 0, 8 * w3);
       if (t == 0) {
         mask_lo(s, lp, 0, v); mac_vec(c, racc, v, dm2, b, level);
@@ -970,7 +994,7 @@ int orc_matmul_cc(const orc_keys* K, const uint64_t* A, const uint64_t* Bp, int 
   if (rc == 0)
     for (int g = 0; g < n_out; ++g)
       if (!out_mask || out_mask[g]) orc_rescale(c, acc + (size_t)g * w1, l1, 2, O + (size_t)g * 2 * l1 * n);
-  free(v); free(rot); free(racc); free(R); free(Ad); free(T3); free(T); free(Tr); free(V); free(acc);
+  free(v); free(rot); free(racc); free(R); free(Ad); free(T3); free(T); free(Tr); free(V); free(acc); free(bs);
   return rc;
 }
 

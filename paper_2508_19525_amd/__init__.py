@@ -28,6 +28,11 @@ class blb_ct(C.Structure):
     _fields_ = [("data", C.c_void_p), ("level", C.c_int32), ("degree", C.c_int32), ("scale", C.c_double)]
 
 
+class blb_cp_instance(C.Structure):
+    _fields_ = [("keys", C.c_void_p), ("plan", C.c_void_p), ("X", C.c_void_p), ("n_in", C.c_int), ("Y", C.c_void_p),
+                ("n_out", C.c_int)]
+
+
 class blb_params(C.Structure):
     _fields_ = [("log_n", C.c_int32), ("n_q", C.c_int32), ("n_special", C.c_int32), ("dnum", C.c_int32),
                 ("device", C.c_int32), ("stream", C.c_void_p), ("hbm_budget_bytes", C.c_uint64)]
@@ -41,6 +46,7 @@ _SIGS = {
     "blb_ctx_destroy": (None, [C.c_void_p]),
     "blb_ctx_moduli": (C.c_int, [C.c_void_p, C.c_void_p]),
     "blb_ctx_device_bytes": (C.c_uint64, [C.c_void_p]),
+    "blb_ctx_trim": (C.c_int, [C.c_void_p]),
     "blb_ctx_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
     "blb_ctx_read_timing": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "blb_ctx_reset_timing": (C.c_int, [C.c_void_p]),
@@ -73,6 +79,9 @@ _SIGS = {
     "blb_exec_create_cc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.POINTER(blb_ct), C.c_int,
                                      C.POINTER(blb_ct), C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
     "blb_exec_run": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "blb_batch_matmul_cp": (C.c_int, [C.c_void_p, C.POINTER(blb_cp_instance), C.c_int]),
+    "blb_exec_create_batch_cp": (C.c_int, [C.c_void_p, C.POINTER(blb_cp_instance), C.c_int, C.c_int, C.c_void_p,
+                                           C.POINTER(C.c_void_p)]),
     "blb_exec_device_bytes": (C.c_uint64, [C.c_void_p]),
     "blb_exec_destroy": (None, [C.c_void_p]),
 }
@@ -143,6 +152,10 @@ def blb_ctx_device_bytes(ctx):
     return int(lib().blb_ctx_device_bytes(ctx))
 
 
+def blb_ctx_trim(ctx):
+    _check(lib().blb_ctx_trim(ctx), "blb_ctx_trim")
+
+
 BLB_T_CP_MAC, BLB_T_NTT, BLB_T_KS_INNER, BLB_T_MODUP, BLB_T_MODDOWN, BLB_T_MASK, BLB_T_EW, BLB_T_CC_TENSOR = range(8)
 
 
@@ -161,7 +174,7 @@ def blb_ctx_reset_timing(ctx):
     _check(lib().blb_ctx_reset_timing(ctx), "blb_ctx_reset_timing")
 
 
-BLB_KNOB_MAC_VARIANT = 0
+BLB_KNOB_MAC_VARIANT, BLB_KNOB_BATCH_VARIANT, BLB_KNOB_BATCH_GRID = 0, 1, 2
 
 
 def blb_ctx_set_knob(ctx, knob, value):
@@ -323,6 +336,18 @@ def blb_exec_create_cc(ctx, keys, plan, A_cts, Bp_cts, C_cts, mask_target_level=
     e = Exec(out.value, (Aa, Ba), C_cts, Ca)
     e.sync_outputs()
     return e
+
+
+def blb_batch_matmul_cp(ctx, instances):
+    """instances: a ctypes array of blb_cp_instance (X / Y point at blb_ct arrays kept alive by the caller)"""
+    _check(lib().blb_batch_matmul_cp(ctx, instances, len(instances)), "blb_batch_matmul_cp")
+
+
+def blb_exec_create_batch_cp(ctx, instances, mask_target_level=-1, share_dev=None):
+    out = C.c_void_p()
+    _check(lib().blb_exec_create_batch_cp(ctx, instances, len(instances), mask_target_level, _ptr(share_dev), C.byref(out)),
+           "blb_exec_create_batch_cp")
+    return Exec(out.value, (instances,), [], [])
 
 
 def blb_exec_run(ex, mask_seed=0):

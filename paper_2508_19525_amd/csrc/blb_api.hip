@@ -654,6 +654,14 @@ int blb_ctx_moduli(const blb_ctx* c, uint64_t* out) {
 }
 uint64_t blb_ctx_device_bytes(const blb_ctx* c) { return c ? c->dev_bytes : 0; }
 
+int blb_ctx_trim(blb_ctx* c) {
+  if (!c) return BLB_EINVAL;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return BLB_EDEVICE;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, c->device) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+  return BLB_OK;
+}
+
 int blb_ctx_set_knob(blb_ctx* c, int knob, int value) {
   if (!c) return BLB_EINVAL;
   switch (knob) {
@@ -1058,7 +1066,7 @@ int blb_plan_matmul_cp(blb_ctx* c, const double* W, int d_in, int d_out, int L, 
       return BLB_EDEVICE;
     }
     (void)hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream);
-    const double scale = (double)c->mod[level];
+    const double scale = (double)c->mod[level] / BLB_NOISE_BOOST;
     std::vector<PolyDesc> d;
     for (size_t p0 = 0; p0 < n_pt; p0 += chunk) {
       const int cnt = (int)std::min<size_t>(chunk, n_pt - p0);
@@ -1125,18 +1133,29 @@ int blb_matmul_cp(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct
   uint64_t* rot = tmp.get<uint64_t>((size_t)std::max(1, g.n_out * (g.G - 1)) * ctw);
   uint64_t* acc = tmp.get<uint64_t>((size_t)g.n_out * ctw);
   if (tmp.failed) return BLB_ENOMEM;
-  // baby steps, hoisted per input: RX[a][i-1] = Rot_l^{i L'}(X_a), i >= 1
+  // noise boost: Xs_a = 2^10 X_a (the diagonals are encoded at q_level / 2^10)
+  uint64_t* Xs = tmp.get<uint64_t>((size_t)n_in * ctw);
+  if (!Xs) return BLB_ENOMEM;
+  {
+    std::vector<const uint64_t*> xin;
+    for (int a = 0; a < n_in; ++a) xin.push_back(X[a].data);
+    const uint64_t* const* xin_dev = upload_vec(c, xin);
+    if (!xin_dev) return BLB_EDEVICE;
+    launch_scale_cts(c, xin_dev, Xs, n_in, nl, BLB_NOISE_BOOST);
+  }
+  // baby steps, hoisted per input: RX[a][i-1] = Rot_l^{i L'}(Xs_a), i >= 1
   std::vector<const uint64_t*> srcs;
   std::vector<KsReq> reqs;
   std::vector<const uint64_t*> rx_tab(n_ai);
   for (int a = 0; a < n_in; ++a) {
-    srcs.push_back(X[a].data + (size_t)nl * n);
-    rx_tab[(size_t)a * g.B] = X[a].data;
+    const uint64_t* xa = Xs + (size_t)a * ctw;
+    srcs.push_back(xa + (size_t)nl * n);
+    rx_tab[(size_t)a * g.B] = xa;
     for (int i = 1; i < g.B; ++i) {
       const uint32_t gal = galois_left(c, (int64_t)i * g.Lp);
       uint64_t* dst = RX + (size_t)(a * (g.B - 1) + i - 1) * ctw;
       rx_tab[(size_t)a * g.B + i] = dst;
-      reqs.push_back(KsReq{a, kb[i], gal, dst, X[a].data, gal, nullptr});
+      reqs.push_back(KsReq{a, kb[i], gal, dst, xa, gal, nullptr});
     }
   }
   int rc = ks_batch(c, level, srcs, reqs);
@@ -1384,7 +1403,7 @@ int blb_plan_matmul_cc(blb_ctx* c, int n_heads, int L, int d_head, int level, bl
         ge[(size_t)tau * S + j] = (j / blk) >= tau ? 1.0 : 0.0;
         lt[(size_t)tau * S + j] = (j / blk) < tau ? 1.0 : 0.0;
       }
-    const double sc = (double)c->mod[level - 2];
+    const double sc = (double)c->mod[level - 2] / BLB_NOISE_BOOST;
     if ((rc = encode_vectors_ntt(c, ge, g.c, sc, level - 2, g.m_ge)) || (rc = encode_vectors_ntt(c, lt, g.c, sc, level - 2, g.m_lt))) {
       blb_plan_destroy(P);
       return rc;
@@ -1442,8 +1461,18 @@ int blb_matmul_cc(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct
   for (const CcGroup& g : P->groups) {
     const int m = g.n_ct;
     Tmp tmp(c);
+    // noise boost: Bs_a = 2^10 B'_a before the inner rotations (step-3 masks are at q/2^10)
+    uint64_t* Bs = tmp.get<uint64_t>((size_t)m * w1);
+    if (!Bs) return BLB_ENOMEM;
+    {
+      std::vector<const uint64_t*> bin;
+      for (int a = 0; a < m; ++a) bin.push_back(Bp[g.ct0 + a].data);
+      const uint64_t* const* bin_dev = upload_vec(c, bin);
+      if (!bin_dev) return BLB_EDEVICE;
+      launch_scale_cts(c, bin_dev, Bs, m, nl, BLB_NOISE_BOOST);
+    }
     std::vector<const uint64_t*> srcs;
-    for (int a = 0; a < m; ++a) srcs.push_back(Bp[g.ct0 + a].data + (size_t)nl * n);
+    for (int a = 0; a < m; ++a) srcs.push_back(Bs + (size_t)a * w1 + (size_t)nl * n);
     uint64_t* X = tmp.get<uint64_t>(ks_modup_words(c, level, m));
     uint64_t* Oacc = tmp.get<uint64_t>((size_t)g.n_out * w3);
     uint64_t* RL = tmp.get<uint64_t>((size_t)TC * m * w1);
@@ -1470,7 +1499,7 @@ int blb_matmul_cc(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct
         const int t = t0 + tt;
         for (int a = 0; a < m; ++a) {
           const size_t slot = (size_t)tt * m + a;
-          const uint64_t* b = Bp[g.ct0 + a].data;
+          const uint64_t* b = Bs + (size_t)a * w1;
           CcPair pr;
           pr.mx = P->pt + (size_t)t * nl * n;
           pr.my = P->pt + (size_t)(lp + t) * nl * n;
@@ -1776,23 +1805,37 @@ int blb_batch_matmul_cp(blb_ctx* c, const blb_cp_instance* inst, int n_inst) {
     acc[i] = tmp.get<uint64_t>((size_t)g.n_out * ctw);
   }
   if (tmp.failed) return BLB_ENOMEM;
-  // baby steps of every instance in one key-switch batch
+  // noise boost of every input, then the baby steps of every instance in one key-switch batch
+  int n_x = 0;
+  for (int i = 0; i < n_inst; ++i) n_x += inst[i].n_in;
+  uint64_t* Xs = tmp.get<uint64_t>((size_t)n_x * ctw);
+  if (!Xs) return BLB_ENOMEM;
+  {
+    std::vector<const uint64_t*> xin;
+    for (int i = 0; i < n_inst; ++i)
+      for (int a = 0; a < inst[i].n_in; ++a) xin.push_back(inst[i].X[a].data);
+    const uint64_t* const* xin_dev = upload_vec(c, xin);
+    if (!xin_dev) return BLB_EDEVICE;
+    launch_scale_cts(c, xin_dev, Xs, n_x, nl, BLB_NOISE_BOOST);
+  }
   std::vector<const uint64_t*> srcs;
   std::vector<KsReq> reqs;
   std::vector<std::vector<const uint64_t*>> rx_tab(n_inst);
+  int xk = 0;
   for (int i = 0; i < n_inst; ++i) {
     const blb_cp_instance& I = inst[i];
     const CpGeom& g = I.plan->g;
     rx_tab[i].assign((size_t)g.n_in * g.B, nullptr);
-    for (int a = 0; a < g.n_in; ++a) {
-      srcs.push_back(I.X[a].data + (size_t)nl * n);
+    for (int a = 0; a < g.n_in; ++a, ++xk) {
+      const uint64_t* xa = Xs + (size_t)xk * ctw;
+      srcs.push_back(xa + (size_t)nl * n);
       const int s = (int)srcs.size() - 1;
-      rx_tab[i][(size_t)a * g.B] = I.X[a].data;
+      rx_tab[i][(size_t)a * g.B] = xa;
       for (int b = 1; b < g.B; ++b) {
         const uint32_t gal = galois_left(c, (int64_t)b * g.Lp);
         uint64_t* dst = RX[i] + (size_t)(a * (g.B - 1) + b - 1) * ctw;
         rx_tab[i][(size_t)a * g.B + b] = dst;
-        reqs.push_back(KsReq{s, ik[i].kb[b], gal, dst, I.X[a].data, gal, nullptr});
+        reqs.push_back(KsReq{s, ik[i].kb[b], gal, dst, xa, gal, nullptr});
       }
     }
   }

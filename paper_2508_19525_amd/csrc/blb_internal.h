@@ -247,6 +247,12 @@ void launch_mask_pair(blb_ctx* c, const CcPair* pairs_dev, int n_pairs, int nl);
 int batch_mac_shape(int variant, int* tb, int* ib, int* cpt);
 void launch_cp_mac_batch(blb_ctx* c, const MacGroup* groups, const MacItem* items, int n_items, int variant, int grid);
 void launch_sum_var(blb_ctx* c, const uint64_t* const* srcs, const int* off, uint64_t* const* dsts, int n_out, int nl);
+void launch_scale_cts(blb_ctx* c, const uint64_t* const* in, uint64_t* out, int count, int nl, double k);
+
+// Noise boost: operands of key-switched rotations inside the matmuls are multiplied by this
+// integer first (key-switch noise is absolute, so it shrinks relative to the message); the
+// plaintext factors that follow are encoded at scales divided by it.
+#define BLB_NOISE_BOOST 1024.0
 void launch_tensor_sum(blb_ctx* c, const uint64_t* const* A_tab, const uint64_t* const* R_tab, uint64_t* T3, int n_t, int n_ct, int nlA,
                        int nl2);
 void launch_masked_acc(blb_ctx* c, const CcTerm* terms, const int* off, uint64_t* const* outs, int n_out, int nl, bool accumulate);

@@ -766,3 +766,17 @@ void launch_sum_var(blb_ctx* c, const uint64_t* const* srcs, const int* off, uin
   dim3 grid((2 * nl * c->n + 255) / 256, n_out);
   k_sum_var<<<grid, 256, 0, c->stream>>>(srcs, off, dsts, c->n, nl, c->mt);
 }
+
+// out[t] = k * in[t] for whole degree-1 ciphertexts (exact integer scalar, every limb)
+__global__ void k_scale_cts(const uint64_t* const* __restrict__ in, uint64_t* __restrict__ out, int n, int nl, double k, ModTable mt) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  if (w >= 2 * nl * n) return;
+  const ModEntry me = mt.m[(w / n) % nl];
+  out[(size_t)t * 2 * nl * n + w] = d2u(canon(mulmod_s(u2d(in[t][w]), k, me.q, me.qinv), me.q));
+}
+void launch_scale_cts(blb_ctx* c, const uint64_t* const* in, uint64_t* out, int count, int nl, double k) {
+  if (count <= 0) return;
+  dim3 grid((2 * nl * c->n + 255) / 256, count);
+  k_scale_cts<<<grid, 256, 0, c->stream>>>(in, out, c->n, nl, k, c->mt);
+}

@@ -136,3 +136,30 @@ def unpack_diag(vecs, H: int, L: int, slots: int, g0: int = 0):
                 D = (g0 + g) * c + kap
                 C[h][i, (i + D) % lp] = v[lp * (h + H * kap) + i]
     return [m[:L, :L] for m in C]
+
+
+# C4: 64 independent matmul_cp instances, lengths uniform in {16..512}, hidden 768 or 1024,
+# one weight matrix per hidden size, N=8192, 3 primes (+1 special, dnum 3), scale 2^40
+C4 = dict(params=Params(13, 3, 1, 3, 40), n_inst=64, L_lo=16, L_hi=512, hidden=(768, 1024), w_std=0.02)
+
+
+def batch_instances(n_inst: int = 64, L_lo: int = 16, L_hi: int = 512, hidden=(768, 1024), config: int = 4):
+    """[(L_i, D_i)] for the batched workload, seeded"""
+    rng = np.random.default_rng(seed_for(config, ROLE_X))
+    Ls = rng.integers(L_lo, L_hi + 1, n_inst)
+    Ds = rng.choice(np.array(hidden), n_inst)
+    return [(int(L), int(D)) for L, D in zip(Ls, Ds)]
+
+
+def batch_activations(i: int, L: int, D: int, config: int = 4) -> np.ndarray:
+    rng = np.random.default_rng(seed_for(config, ROLE_X) * 1000 + i)
+    return rng.normal(0.0, 1.0, (L, D))
+
+
+def batch_weights(D: int, std: float = 0.02, config: int = 4) -> np.ndarray:
+    rng = np.random.default_rng(seed_for(config, ROLE_W) * 10000 + D)
+    return rng.normal(0.0, std, (D, D))
+
+
+def lp_of(L: int) -> int:
+    return 1 << int(np.ceil(np.log2(L)))
