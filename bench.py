@@ -378,6 +378,81 @@ def run_batch(args, B, torch):
     return res
 
 
+def run_serving(args, B, torch):
+    """Poisson arrivals of mixed BERT-large / GPT-2-base linear ops (lengths 16..512) into the
+    serving runtime: cold plan cache, HBM-budget admission, continuous batching."""
+    import ctypes
+    from paper_2508_19525_amd import workloads as wl
+
+    cfg = wl.C5
+    p = cfg["params"]
+    n, level = p.n, p.n_q - 1
+    reqs = wl.serving_requests(args.serve_requests, args.serve_rate, cfg["ops"], cfg["L_lo"], cfg["L_hi"], n_clients=4)
+    shapes = {wid: shape for _, wid, shape, _, _ in reqs}
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = B.blb_ctx_create(p.log_n, p.n_q, p.n_special, p.dnum, 0, stream)
+    t_setup = time.time()
+    steps = set()
+    for wid, (d_in, d_out) in shapes.items():
+        for lp in (16, 32, 64, 128, 256, 512):
+            cc = (n // 2) // lp
+            ce = min(cc, 1 << int(np.ceil(np.log2(d_in))))
+            Bb = 1 << ((int(np.ceil(np.log2(ce))) + 1) // 2)
+            steps |= {k * lp for k in range(1, Bb)} | {j * Bb * lp for j in range(1, ce // Bb)}
+    keys = [B.blb_keygen(ctx, wl.seed_for(5, wl.ROLE_KEYS) * 10 + k, sorted(steps)) for k in range(4)]
+    keep, inputs, pt = [], {}, torch.empty((level + 1) * n, dtype=torch.int64, device="cuda")
+    work = []
+    for i, (t_arr, wid, (d_in, d_out), L, client) in enumerate(reqs):
+        lp = wl.lp_of(L)
+        cc = (n // 2) // lp
+        n_in, n_out = -(-d_in // cc), -(-d_out // cc)
+        key = (wid, lp, client)
+        if key not in inputs:  # encrypted activations, resident in HBM (shared read-only per key)
+            X = np.random.default_rng(wl.seed_for(5, wl.ROLE_X) + i).normal(0, 1, (lp, d_in))
+            cts = []
+            for a in range(n_in):
+                B.blb_encode(ctx, wl.pack_spatial(X, n // 2, a), p.scale, level, pt)
+                ct, t = B.new_ct(n, level)
+                keep.append(t)
+                B.blb_encrypt(ctx, keys[client], pt, level, p.scale, wl.seed_for(5, wl.ROLE_ENC) + i, a, ct)
+                cts.append(ct)
+            inputs[key] = (B.blb_ct * n_in)(*cts)
+        ys = []
+        for b in range(n_out):
+            ct, t = B.new_ct(n, level - 1)
+            keep.append(t)
+            ys.append(ct)
+        work.append((t_arr, wid, L, client, inputs[key], (B.blb_ct * n_out)(*ys)))
+    torch.cuda.synchronize()
+    log(f"serving setup {time.time() - t_setup:.1f}s: {len(reqs)} requests, {len(inputs)} input sets, {len(steps)} rotation keys")
+    srv = B.blb_server_create(ctx, int(args.serve_cache_gb * 1e9), max_batch=8, max_queue=100000, n_streams=2)
+    try:
+        for wid, shape in shapes.items():
+            B.blb_server_add_weights(srv, wid, wl.serving_weights(wid, shape), level)
+        t0 = time.perf_counter()
+        ids = []
+        for t_arr, wid, L, client, X, Y in work:
+            dt = t0 + t_arr - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            ids.append(B.blb_server_submit(srv, keys[client], wid, L, X, Y))
+        log(f"serving: all {len(ids)} submitted after {time.perf_counter() - t0:.1f}s; draining")
+        B.blb_server_drain(srv, 1200)
+        t_end = time.perf_counter()
+        st = B.blb_server_stats(srv)
+    finally:
+        B.blb_server_destroy(srv)
+    st["offered_rate_rps"] = args.serve_rate
+    st["throughput_rps"] = st["completed"] / (t_end - t0)
+    st["wall_s"] = t_end - t0
+    st["plan_cache_GB"] = args.serve_cache_gb
+    log(f"serving: {st}")
+    for k in keys:
+        B.blb_keys_destroy(k)
+    B.blb_ctx_destroy(ctx)
+    return st
+
+
 def run_cpu_baseline():
     """The oracle on a bounded sample: one of the 24 output ciphertexts (all its 32 diagonal
     groups, 768 plaintext encodes + MACs, its 3 giant-step rotations and the rescale) timed
@@ -430,6 +505,10 @@ def main():
     ap.add_argument("--no-cc", action="store_true", help="skip the matmul_cc measurement")
     ap.add_argument("--no-tune", action="store_true", help="skip the MAC launch-shape autotuner")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched measurement")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-cache-gb", type=float, default=120.0)
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB plain copy (counter reference)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -442,6 +521,7 @@ def main():
     r = run_cp(args, B, torch)
     cc = None if args.no_cc else run_cc(args, B, torch)
     bt = None if args.no_batch else run_batch(args, B, torch)
+    sv = None if args.no_serve else run_serving(args, B, torch)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -482,6 +562,10 @@ def main():
         "batched": None if bt is None else dict(
             bt, workload="64 independent matmul_cp instances, L ~ U{16..512}, hidden 768/1024 (W shared per hidden size), "
                          "N=8192, 3 primes; per-instance eager calls vs batched stages vs one graph launch"),
+        "serving": None if sv is None else dict(
+            sv, workload="Poisson arrivals of BERT-large (1024x1024, 1024x4096, 4096x1024) and GPT-2-base (768x768, "
+                         "768x3072, 3072x768) matmul_cp ops, 50/50 by model, L ~ U{16..512}, N=16384, 4 primes + 2 special; "
+                         "cold plan cache, HBM-budget admission, continuous batching"),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

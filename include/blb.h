@@ -206,6 +206,40 @@ int blb_exec_run(blb_exec* exec, uint64_t mask_seed);
 uint64_t blb_exec_device_bytes(const blb_exec* exec);
 void blb_exec_destroy(blb_exec* exec);
 
+/* ---- serving: a request loop with HBM-budget admission and continuous batching ---------
+ * A worker thread owns the context while the server exists (create keys and buffers before
+ * creating it; afterwards use the context only through the server calls).  Weights are
+ * registered once (host copy kept); the diagonal plaintexts of (weight, L') are generated on
+ * the device when a request needs them and kept in a plan cache of at most plan_cache_bytes,
+ * evicting least-recently-used plans no running request uses.  A request is admitted when its
+ * plan is resident or fits; admitted requests join the next batch (one blb_batch_matmul_cp
+ * plus per-request mask-and-share) launched on one of n_streams streams, so requests that
+ * arrive while earlier batches run are admitted and overlap with them.  Latency is measured
+ * from submission to completion (host clock).  A request whose plan can never fit is rejected
+ * with BLB_ENOMEM; a full queue returns BLB_EBUSY at submission. */
+typedef struct blb_server blb_server;
+typedef struct {
+  uint64_t plan_cache_bytes;
+  int max_batch;  /* requests per batch */
+  int max_queue;  /* queued (not yet admitted) requests */
+  int n_streams;  /* batches in flight, 1..8 */
+} blb_server_config;
+int blb_server_create(blb_ctx* ctx, const blb_server_config* cfg, blb_server** out);
+/* W: host d_in x d_out row-major; inputs of requests on this weight are at `level`. */
+int blb_server_add_weights(blb_server* server, int weight_id, const double* W, int d_in, int d_out, int level);
+/* X (n_in cts) and Y (n_out buffers of 2*level*N words) must stay alive until completion; the
+ * blb_ct array Y is updated (level, scale) by the worker.  mask_target_level < 0: no mask. */
+int blb_server_submit(blb_server* server, const blb_keys* keys, int weight_id, int L, const blb_ct* X, int n_in, blb_ct* Y, int n_out,
+                      uint64_t mask_seed, int mask_target_level, uint64_t* share_dev, int64_t* req_id);
+/* state: 0 queued, 1 running, 2 done, < 0 the error code; latency_ms (done only, else -1). */
+int blb_server_poll(blb_server* server, int64_t req_id, int* state, double* latency_ms);
+/* waits until nothing is queued or running (BLB_EBUSY on timeout) */
+int blb_server_drain(blb_server* server, double timeout_s);
+/* out[10]: completed, rejected, p50 ms, p99 ms, mean ms, plan hits, plan misses, batches,
+ * plan generation seconds, resident plan bytes */
+int blb_server_stats(blb_server* server, double* out, int cap);
+void blb_server_destroy(blb_server* server);
+
 #ifdef __cplusplus
 }
 #endif

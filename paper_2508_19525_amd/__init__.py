@@ -33,6 +33,10 @@ class blb_cp_instance(C.Structure):
                 ("n_out", C.c_int)]
 
 
+class blb_server_config(C.Structure):
+    _fields_ = [("plan_cache_bytes", C.c_uint64), ("max_batch", C.c_int), ("max_queue", C.c_int), ("n_streams", C.c_int)]
+
+
 class blb_params(C.Structure):
     _fields_ = [("log_n", C.c_int32), ("n_q", C.c_int32), ("n_special", C.c_int32), ("dnum", C.c_int32),
                 ("device", C.c_int32), ("stream", C.c_void_p), ("hbm_budget_bytes", C.c_uint64)]
@@ -80,6 +84,14 @@ _SIGS = {
                                      C.POINTER(blb_ct), C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
     "blb_exec_run": (C.c_int, [C.c_void_p, C.c_uint64]),
     "blb_batch_matmul_cp": (C.c_int, [C.c_void_p, C.POINTER(blb_cp_instance), C.c_int]),
+    "blb_server_create": (C.c_int, [C.c_void_p, C.POINTER(blb_server_config), C.POINTER(C.c_void_p)]),
+    "blb_server_add_weights": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int]),
+    "blb_server_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_int,
+                                    C.c_uint64, C.c_int, C.c_void_p, C.POINTER(C.c_int64)]),
+    "blb_server_poll": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "blb_server_drain": (C.c_int, [C.c_void_p, C.c_double]),
+    "blb_server_stats": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "blb_server_destroy": (None, [C.c_void_p]),
     "blb_exec_create_batch_cp": (C.c_int, [C.c_void_p, C.POINTER(blb_cp_instance), C.c_int, C.c_int, C.c_void_p,
                                            C.POINTER(C.c_void_p)]),
     "blb_exec_device_bytes": (C.c_uint64, [C.c_void_p]),
@@ -360,6 +372,49 @@ def blb_exec_device_bytes(ex):
 
 def blb_exec_destroy(ex):
     lib().blb_exec_destroy(ex.h if isinstance(ex, Exec) else ex)
+
+
+def blb_server_create(ctx, plan_cache_bytes, max_batch=16, max_queue=4096, n_streams=2):
+    cfg = blb_server_config(plan_cache_bytes, max_batch, max_queue, n_streams)
+    out = C.c_void_p()
+    _check(lib().blb_server_create(ctx, C.byref(cfg), C.byref(out)), "blb_server_create")
+    return out.value
+
+
+def blb_server_add_weights(server, weight_id, W, level):
+    Wc = np.ascontiguousarray(W, dtype=np.float64)
+    _check(lib().blb_server_add_weights(server, weight_id, _host_ptr(Wc), Wc.shape[0], Wc.shape[1], level), "blb_server_add_weights")
+
+
+def blb_server_submit(server, keys, weight_id, L, X_arr, Y_arr, mask_seed=0, mask_target_level=-1, share_dev=None):
+    """X_arr / Y_arr: ctypes arrays of blb_ct kept alive by the caller until completion"""
+    rid = C.c_int64()
+    rc = lib().blb_server_submit(server, keys, weight_id, L, C.cast(X_arr, C.c_void_p), len(X_arr), C.cast(Y_arr, C.c_void_p),
+                                 len(Y_arr), mask_seed, mask_target_level, _ptr(share_dev), C.byref(rid))
+    _check(rc, "blb_server_submit")
+    return rid.value
+
+
+def blb_server_poll(server, req_id):
+    st, lat = C.c_int(), C.c_double()
+    _check(lib().blb_server_poll(server, req_id, C.byref(st), C.byref(lat)), "blb_server_poll")
+    return st.value, lat.value
+
+
+def blb_server_drain(server, timeout_s=600.0):
+    _check(lib().blb_server_drain(server, timeout_s), "blb_server_drain")
+
+
+def blb_server_stats(server):
+    out = np.zeros(10, np.float64)
+    _check(lib().blb_server_stats(server, _host_ptr(out), 10), "blb_server_stats")
+    keys = ["completed", "rejected", "p50_ms", "p99_ms", "mean_ms", "plan_hits", "plan_misses", "batches", "plan_gen_s",
+            "plan_bytes"]
+    return dict(zip(keys, [float(x) for x in out]))
+
+
+def blb_server_destroy(server):
+    lib().blb_server_destroy(server)
 
 
 # ---------------------------------------------------------------------------------------

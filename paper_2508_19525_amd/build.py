@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libblb.so")
 
-HIP_SOURCES = ["blb_ntt.hip", "blb_kernels.hip", "blb_api.hip"]
+HIP_SOURCES = ["blb_ntt.hip", "blb_kernels.hip", "blb_api.hip", "blb_serve.hip"]
 HOST_SOURCES = ["blb_host_tables.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",

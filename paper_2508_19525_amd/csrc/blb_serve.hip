@@ -1,0 +1,392 @@
+// Serving runtime: a native request loop for private-inference linear operators.
+//
+// Clients submit matmul_cp requests (their own keys, a registered weight matrix, encrypted
+// inputs resident in HBM, caller-owned output buffers).  A worker thread owns the context:
+//   - admission: a request is admitted when the plan (diagonal plaintexts of its weight at
+//     its padded length L') is resident or can be generated within the plan-cache budget;
+//     least-recently-used plans that no admitted request uses are evicted to make room;
+//   - continuous batching: every admitted request joins the next batch; a batch runs as one
+//     blb_batch_matmul_cp (plus per-request mask-and-share) on one of several streams, so
+//     requests that arrive while earlier batches are on the GPU are admitted and launched
+//     while those batches still run;
+//   - completion is detected with events; latency = completion - submission (host clock).
+// Results do not depend on the batch a request lands in (exact modular arithmetic).
+#include <hip/hip_runtime.h>
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "blb_internal.h"
+
+namespace {
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Weights {
+  std::vector<double> W;
+  int d_in = 0, d_out = 0, level = 0;
+};
+
+struct PlanEntry {
+  blb_plan* plan = nullptr;
+  size_t bytes = 0;
+  int users = 0;
+  double last_use = 0;
+};
+
+struct Request {
+  int64_t id;
+  const blb_keys* keys;
+  int weight_id;
+  int L, Lp;
+  std::vector<blb_ct> X;
+  blb_ct* Y;  // caller's array
+  int n_out;
+  uint64_t mask_seed;
+  uint64_t* share;
+  int target_level;
+  double t_submit = 0, t_done = 0;
+  int state = 0;  // 0 queued, 1 running, 2 done, < 0 error code
+  PlanEntry* pe = nullptr;
+};
+
+struct Batch {
+  std::vector<Request*> reqs;
+  hipEvent_t done = nullptr;
+  int stream = 0;
+};
+
+int ceil_log2i(int64_t v) {
+  int r = 0;
+  while ((1ll << r) < v) ++r;
+  return r;
+}
+
+}  // namespace
+
+struct blb_server {
+  blb_ctx* c;
+  blb_server_config cfg;
+  std::vector<hipStream_t> streams;
+  std::map<int, Weights> weights;
+  std::map<std::pair<int, int>, PlanEntry> plans;  // (weight id, L') -> plan
+  size_t plan_bytes = 0;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Request*> queue;
+  std::map<int64_t, Request*> all;
+  std::deque<Batch> running;
+  int64_t next_id = 1;
+  bool stop = false;
+  std::thread worker;
+  // statistics
+  int64_t hits = 0, misses = 0, rejected = 0, completed = 0, batches = 0;
+  double gen_s = 0;
+  std::vector<double> latencies;
+};
+
+namespace {
+
+// make room for `need` bytes of plans by evicting unused LRU plans; true if it fits
+bool make_room(blb_server* S, size_t need) {
+  while (S->plan_bytes + need > S->cfg.plan_cache_bytes) {
+    auto victim = S->plans.end();
+    for (auto it = S->plans.begin(); it != S->plans.end(); ++it)
+      if (it->second.users == 0 && (victim == S->plans.end() || it->second.last_use < victim->second.last_use)) victim = it;
+    if (victim == S->plans.end()) return false;
+    S->plan_bytes -= victim->second.bytes;
+    blb_plan_destroy(victim->second.plan);
+    S->plans.erase(victim);
+  }
+  return true;
+}
+
+size_t plan_bytes_estimate(const blb_ctx* c, const Weights& w, int Lp) {
+  const int s = c->n / 2, cc = s / Lp;
+  const int din_p = 1 << ceil_log2i(w.d_in);
+  const int c_eff = std::min(cc, din_p);
+  const size_t n_in = (w.d_in + cc - 1) / cc, n_out = (w.d_out + cc - 1) / cc;
+  return n_in * n_out * (size_t)c_eff * (w.level + 1) * c->n * 8;
+}
+
+// returns 1 admitted, 0 must wait, < 0 rejected (error code)
+int admit(blb_server* S, Request* r) {
+  blb_ctx* c = S->c;
+  auto key = std::make_pair(r->weight_id, r->Lp);
+  auto it = S->plans.find(key);
+  if (it != S->plans.end()) {
+    ++S->hits;
+    it->second.users++;
+    it->second.last_use = now_s();
+    r->pe = &it->second;
+    return 1;
+  }
+  const Weights& w = S->weights[r->weight_id];
+  const size_t need = plan_bytes_estimate(c, w, r->Lp);
+  if (need > S->cfg.plan_cache_bytes) return BLB_ENOMEM;
+  if (!make_room(S, need)) return 0;  // memory frees up when running batches finish
+  const double t0 = now_s();
+  blb_plan* P = nullptr;
+  const int rc = blb_plan_matmul_cp(c, w.W.data(), w.d_in, w.d_out, r->Lp, w.level, &P);
+  if (rc == BLB_ENOMEM) return 0;
+  if (rc) return rc;
+  S->gen_s += now_s() - t0;
+  ++S->misses;
+  PlanEntry& pe = S->plans[key];
+  pe.plan = P;
+  pe.bytes = P->bytes;
+  pe.users = 1;
+  pe.last_use = now_s();
+  S->plan_bytes += P->bytes;
+  r->pe = &pe;
+  return 1;
+}
+
+void finish_batches(blb_server* S, bool block) {
+  while (!S->running.empty()) {
+    Batch& b = S->running.front();
+    if (block) (void)hipEventSynchronize(b.done);
+    else if (hipEventQuery(b.done) != hipSuccess) return;
+    const double t = now_s();
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (Request* r : b.reqs) {
+        r->t_done = t;
+        r->state = 2;
+        r->pe->users--;
+        S->latencies.push_back(t - r->t_submit);
+        ++S->completed;
+      }
+    }
+    (void)hipEventDestroy(b.done);
+    S->running.pop_front();
+    S->cv.notify_all();
+  }
+}
+
+void worker_loop(blb_server* S) {
+  blb_ctx* c = S->c;
+  (void)hipSetDevice(c->device);
+  int next_stream = 0;
+  for (;;) {
+    std::vector<Request*> pending;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv.wait_for(lk, std::chrono::microseconds(200), [&] { return S->stop || !S->queue.empty(); });
+      if (S->stop && S->queue.empty() && S->running.empty()) return;
+      pending.assign(S->queue.begin(), S->queue.end());
+    }
+    finish_batches(S, false);
+    if (pending.empty()) continue;
+    // admission in arrival order, up to max_batch
+    std::vector<Request*> batch;
+    std::vector<Request*> rejected;
+    for (Request* r : pending) {
+      if ((int)batch.size() >= S->cfg.max_batch) break;
+      const int a = admit(S, r);
+      if (a == 1) batch.push_back(r);
+      else if (a < 0) {
+        r->state = a;
+        rejected.push_back(r);
+      } else {
+        break;  // keep arrival order: wait for memory
+      }
+    }
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (Request* r : batch) S->queue.erase(std::find(S->queue.begin(), S->queue.end(), r));
+      for (Request* r : rejected) {
+        S->queue.erase(std::find(S->queue.begin(), S->queue.end(), r));
+        r->t_done = now_s();
+        ++S->rejected;
+      }
+    }
+    if (!rejected.empty()) S->cv.notify_all();
+    if (batch.empty()) {
+      if (!S->running.empty()) finish_batches(S, true);  // wait for memory to free up
+      continue;
+    }
+    // launch the batch on the next stream
+    hipStream_t saved = c->stream;
+    c->stream = S->streams[next_stream];
+    std::vector<blb_cp_instance> inst;
+    for (Request* r : batch) {
+      blb_cp_instance I;
+      I.keys = r->keys;
+      I.plan = r->pe->plan;
+      I.X = r->X.data();
+      I.n_in = (int)r->X.size();
+      I.Y = r->Y;
+      I.n_out = r->n_out;
+      inst.push_back(I);
+      r->state = 1;
+    }
+    int rc = blb_batch_matmul_cp(c, inst.data(), (int)inst.size());
+    for (size_t k = 0; k < batch.size() && rc == BLB_OK; ++k)
+      if (batch[k]->share) rc = blb_mask_to_share(c, batch[k]->Y, batch[k]->n_out, batch[k]->mask_seed, batch[k]->target_level, batch[k]->share);
+    Batch b;
+    b.reqs = batch;
+    b.stream = next_stream;
+    (void)hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
+    (void)hipEventRecord(b.done, c->stream);
+    c->stream = saved;
+    next_stream = (next_stream + 1) % (int)S->streams.size();
+    if (rc != BLB_OK) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (Request* r : batch) r->state = rc;
+    }
+    ++S->batches;
+    S->running.push_back(b);
+    // bound the number of batches in flight
+    while ((int)S->running.size() >= (int)S->streams.size() + 1) finish_batches(S, true);
+  }
+}
+
+double percentile(std::vector<double> v, double p) {
+  if (v.empty()) return 0;
+  std::sort(v.begin(), v.end());
+  const double idx = p * (v.size() - 1);
+  const size_t lo = (size_t)idx, hi = std::min(v.size() - 1, lo + 1);
+  return v[lo] + (v[hi] - v[lo]) * (idx - lo);
+}
+
+}  // namespace
+
+extern "C" {
+
+int blb_server_create(blb_ctx* c, const blb_server_config* cfg, blb_server** out) {
+  if (!c || !cfg || !out || cfg->max_batch < 1 || cfg->max_queue < 1 || cfg->n_streams < 1 || cfg->n_streams > 8) return BLB_EINVAL;
+  *out = nullptr;
+  blb_server* S = new (std::nothrow) blb_server();
+  if (!S) return BLB_ENOMEM;
+  S->c = c;
+  S->cfg = *cfg;
+  for (int i = 0; i < cfg->n_streams; ++i) {
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      for (hipStream_t t : S->streams) (void)hipStreamDestroy(t);
+      delete S;
+      return BLB_EDEVICE;
+    }
+    S->streams.push_back(s);
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return BLB_EDEVICE;
+  S->worker = std::thread(worker_loop, S);
+  *out = S;
+  return BLB_OK;
+}
+
+int blb_server_add_weights(blb_server* S, int weight_id, const double* W, int d_in, int d_out, int level) {
+  if (!S || !W || d_in < 1 || d_out < 1 || level < 1 || level >= S->c->n_q) return BLB_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  Weights& w = S->weights[weight_id];
+  w.W.assign(W, W + (size_t)d_in * d_out);
+  w.d_in = d_in;
+  w.d_out = d_out;
+  w.level = level;
+  return BLB_OK;
+}
+
+int blb_server_submit(blb_server* S, const blb_keys* keys, int weight_id, int L, const blb_ct* X, int n_in, blb_ct* Y, int n_out,
+                      uint64_t mask_seed, int mask_target_level, uint64_t* share_dev, int64_t* req_id) {
+  if (!S || !keys || !X || !Y || !req_id || L < 1 || L > S->c->n / 2) return BLB_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto wit = S->weights.find(weight_id);
+  if (wit == S->weights.end()) return BLB_EINVAL;
+  if ((int)S->queue.size() >= S->cfg.max_queue) return BLB_EBUSY;
+  const Weights& w = wit->second;
+  const int Lp = 1 << ceil_log2i(L);
+  const int cc = (S->c->n / 2) / Lp;
+  if (n_in != (w.d_in + cc - 1) / cc || n_out != (w.d_out + cc - 1) / cc) return BLB_EINVAL;
+  for (int a = 0; a < n_in; ++a)
+    if (!X[a].data || X[a].level != w.level || X[a].degree != 1) return BLB_ELEVEL;
+  Request* r = new (std::nothrow) Request();
+  if (!r) return BLB_ENOMEM;
+  r->id = S->next_id++;
+  r->keys = keys;
+  r->weight_id = weight_id;
+  r->L = L;
+  r->Lp = Lp;
+  r->X.assign(X, X + n_in);
+  r->Y = Y;
+  r->n_out = n_out;
+  r->mask_seed = mask_seed;
+  r->share = mask_target_level >= 0 ? share_dev : nullptr;
+  r->target_level = mask_target_level;
+  r->t_submit = now_s();
+  S->queue.push_back(r);
+  S->all[r->id] = r;
+  *req_id = r->id;
+  S->cv.notify_all();
+  return BLB_OK;
+}
+
+int blb_server_poll(blb_server* S, int64_t req_id, int* state, double* latency_ms) {
+  if (!S) return BLB_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->all.find(req_id);
+  if (it == S->all.end()) return BLB_EINVAL;
+  if (state) *state = it->second->state;
+  if (latency_ms) *latency_ms = it->second->state == 2 ? (it->second->t_done - it->second->t_submit) * 1e3 : -1.0;
+  return BLB_OK;
+}
+
+int blb_server_drain(blb_server* S, double timeout_s) {
+  if (!S) return BLB_EINVAL;
+  const double t_end = now_s() + timeout_s;
+  std::unique_lock<std::mutex> lk(S->mu);
+  for (;;) {
+    bool busy = !S->queue.empty();
+    for (auto& kv : S->all) busy |= kv.second->state == 0 || kv.second->state == 1;
+    if (!busy) return BLB_OK;
+    if (now_s() > t_end) return BLB_EBUSY;
+    S->cv.wait_for(lk, std::chrono::milliseconds(1));
+  }
+}
+
+int blb_server_stats(blb_server* S, double* out, int cap) {
+  if (!S || !out || cap < 10) return BLB_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  out[0] = (double)S->completed;
+  out[1] = (double)S->rejected;
+  out[2] = percentile(S->latencies, 0.5) * 1e3;
+  out[3] = percentile(S->latencies, 0.99) * 1e3;
+  double m = 0;
+  for (double v : S->latencies) m += v;
+  out[4] = S->latencies.empty() ? 0 : m / S->latencies.size() * 1e3;
+  out[5] = (double)S->hits;
+  out[6] = (double)S->misses;
+  out[7] = (double)S->batches;
+  out[8] = S->gen_s;
+  out[9] = (double)S->plan_bytes;
+  return BLB_OK;
+}
+
+void blb_server_destroy(blb_server* S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv.notify_all();
+  if (S->worker.joinable()) S->worker.join();
+  for (hipStream_t s : S->streams) {
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  }
+  for (auto& kv : S->plans) blb_plan_destroy(kv.second.plan);
+  for (auto& kv : S->all) delete kv.second;
+  delete S;
+}
+
+}  // extern "C"

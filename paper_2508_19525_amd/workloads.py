@@ -163,3 +163,31 @@ def batch_weights(D: int, std: float = 0.02, config: int = 4) -> np.ndarray:
 
 def lp_of(L: int) -> int:
     return 1 << int(np.ceil(np.log2(L)))
+
+
+# C5: serving -- Poisson arrivals of mixed BERT-large-shaped and GPT-2-base-shaped linear ops,
+# lengths 16..512, N=16384, 4 primes (+2 special, dnum 2), scale 2^40
+C5 = dict(params=Params(14, 4, 2, 2, 40), rate=50.0, L_lo=16, L_hi=512,
+          ops={"bert_large": [(1024, 1024), (1024, 4096), (4096, 1024)], "gpt2_base": [(768, 768), (768, 3072), (3072, 768)]})
+
+
+def serving_requests(n_req: int, rate: float, ops: dict, L_lo: int = 16, L_hi: int = 512, n_clients: int = 4, config: int = 5):
+    """[(arrival_s, weight_id, (d_in, d_out), L, client)] with exponential inter-arrival times;
+    model chosen 50/50, op uniformly within the model"""
+    rng = np.random.default_rng(seed_for(config, ROLE_ARRIVALS))
+    names = sorted(ops)
+    table = [(mi * 8 + oi, shape) for mi, m in enumerate(names) for oi, shape in enumerate(ops[m])]
+    out, t = [], 0.0
+    for _ in range(n_req):
+        t += rng.exponential(1.0 / rate)
+        m = int(rng.integers(0, len(names)))
+        o = int(rng.integers(0, len(ops[names[m]])))
+        wid = m * 8 + o
+        shape = dict(table)[wid]
+        out.append((t, wid, shape, int(rng.integers(L_lo, L_hi + 1)), int(rng.integers(0, n_clients))))
+    return out
+
+
+def serving_weights(wid: int, shape, std: float = 0.02, config: int = 5) -> np.ndarray:
+    rng = np.random.default_rng(seed_for(config, ROLE_W) * 100 + wid)
+    return rng.normal(0.0, std, shape)

@@ -1,0 +1,144 @@
+"""Serving runtime: a request's result is the same alone and inside a mix of concurrent
+requests of other lengths and operators (word for word), requests are admitted by the
+plan-cache budget (eviction, rejection of a plan that can never fit), and latency statistics
+are reported."""
+import ctypes
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2508_19525_amd as B
+    from paper_2508_19525_amd import workloads as wl
+    ctx = B.blb_ctx_create(13, 3, 1, 3, 0, torch.cuda.current_stream().cuda_stream)
+    yield B, wl, ctx
+    torch.cuda.synchronize()
+    B.blb_ctx_destroy(ctx)
+
+
+SHAPES = {0: (64, 64), 1: (64, 128), 2: (128, 64)}
+
+
+def _make_requests(B, wl, ctx, specs, keys, level=2, n=8192, scale=2.0 ** 40):
+    """specs: [(weight_id, L, client, input seed)] -> list of dicts with ABI arrays"""
+    keep, reqs = [], []
+    pt = torch.empty((level + 1) * n, dtype=torch.int64, device="cuda")
+    keep.append(pt)
+    for wid, L, client, xs in specs:
+        d_in, d_out = SHAPES[wid]
+        lp = wl.lp_of(L)
+        cc = (n // 2) // lp
+        n_in, n_out = -(-d_in // cc), -(-d_out // cc)
+        X = np.random.default_rng(xs).normal(0, 1, (L, d_in))
+        xcts, ycts = [], []
+        for a in range(n_in):
+            B.blb_encode(ctx, wl.pack_spatial(X, n // 2, a), scale, level, pt)
+            ct, t = B.new_ct(n, level)
+            keep.append(t)
+            B.blb_encrypt(ctx, keys[client], pt, level, scale, 7000 + xs, a, ct)
+            xcts.append(ct)
+        for b in range(n_out):
+            ct, t = B.new_ct(n, level - 1)
+            keep.append(t)
+            ycts.append(ct)
+        share = torch.zeros(n_out * level * n, dtype=torch.int64, device="cuda")
+        keep.append(share)
+        reqs.append(dict(wid=wid, L=L, client=client, X=(B.blb_ct * n_in)(*xcts), Y=(B.blb_ct * n_out)(*ycts), share=share, Xm=X))
+    torch.cuda.synchronize()
+    return reqs, keep
+
+
+def _keys_for_all(B, wl, ctx, n_clients):
+    steps = set()
+    for wid, (d_in, d_out) in SHAPES.items():
+        for lp in (16, 32, 64, 128, 256, 512):
+            cc = 4096 // lp
+            dp = 1 << int(np.ceil(np.log2(d_in)))
+            ce = min(cc, dp)
+            Bb = 1 << ((int(np.ceil(np.log2(ce))) + 1) // 2)
+            G = ce // Bb
+            steps |= {k * lp for k in range(1, Bb)} | {j * Bb * lp for j in range(1, G)}
+    return [B.blb_keygen(ctx, 6100 + c, sorted(steps)) for c in range(n_clients)]
+
+
+def test_alone_equals_in_mix(env):
+    B, wl, ctx = env
+    keys = _keys_for_all(B, wl, ctx, 3)
+    specs = [(0, 40, 0, 1)] + [(i % 3, [16, 100, 33, 200, 64, 7, 300][i % 7], i % 3, 10 + i) for i in range(12)]
+    reqs, keep = _make_requests(B, wl, ctx, specs, keys)
+    Ws = {wid: wl.serving_weights(wid, SHAPES[wid]) for wid in SHAPES}
+    # plan budget fits a handful of plans: forces eviction between batches
+    srv = B.blb_server_create(ctx, plan_cache_bytes=600 << 20, max_batch=6, n_streams=2)
+    try:
+        for wid, W in Ws.items():
+            B.blb_server_add_weights(srv, wid, W, 2)
+        r0 = reqs[0]
+        rid = B.blb_server_submit(srv, keys[r0["client"]], r0["wid"], r0["L"], r0["X"], r0["Y"], 55, 1, r0["share"])
+        B.blb_server_drain(srv, 120)
+        st, lat = B.blb_server_poll(srv, rid)
+        assert st == 2 and lat > 0
+        alone = [B.blb_export(ctx, r0["Y"][b], 8192) for b in range(len(r0["Y"]))]
+        alone_share = r0["share"].cpu().numpy().copy()
+        ids = []
+        for k, r in enumerate(reqs):  # request 0 again, inside the mix
+            seed = 55 if k == 0 else 1000 + k
+            ids.append(B.blb_server_submit(srv, keys[r["client"]], r["wid"], r["L"], r["X"], r["Y"], seed, 1, r["share"]))
+        B.blb_server_drain(srv, 300)
+        for rid in ids:
+            assert B.blb_server_poll(srv, rid)[0] == 2
+        mix = [B.blb_export(ctx, r0["Y"][b], 8192) for b in range(len(r0["Y"]))]
+        for b in range(len(mix)):
+            assert np.array_equal(alone[b], mix[b]), f"output {b} differs alone vs in the mix"
+        assert np.array_equal(alone_share, r0["share"].cpu().numpy())
+        st = B.blb_server_stats(srv)
+        assert st["completed"] == len(reqs) + 1 and st["rejected"] == 0
+        assert st["plan_misses"] >= 3 and st["batches"] >= 2
+        assert st["p99_ms"] >= st["p50_ms"] > 0
+        assert st["plan_bytes"] <= 600 << 20
+        # every request decodes (after unmasking with its share) to X @ W
+        dec = torch.empty(2 * 8192, dtype=torch.int64, device="cuda")
+        for r in reqs[1:4]:
+            vecs = []
+            for b in range(len(r["Y"])):
+                B.blb_decrypt(ctx, keys[r["client"]], r["Y"][b], dec)
+                d = dec.cpu().numpy().view(np.uint64).reshape(2, 8192).copy()
+                sh = r["share"].cpu().numpy().view(np.uint64).reshape(len(r["Y"]), 2, 8192)[b]
+                mods = B.blb_ctx_moduli(ctx, 4)
+                for i in range(2):
+                    q = int(mods[i])
+                    d[i] = ((d[i].astype(object) + sh[i].astype(object)) % q).astype(np.uint64)
+                t = torch.from_numpy(d.view(np.int64).reshape(-1).copy()).cuda()
+                vecs.append(B.blb_decode(ctx, t, 1, r["Y"][b].scale, 4096))
+            got = wl.unpack_spatial(vecs, r["L"], SHAPES[r["wid"]][1], 4096)
+            assert np.abs(got - r["Xm"] @ Ws[r["wid"]]).max() < 2.0 ** -20
+    finally:
+        B.blb_server_destroy(srv)
+        for k in keys:
+            B.blb_keys_destroy(k)
+
+
+def test_admission_rejects_plan_over_budget(env):
+    B, wl, ctx = env
+    keys = _keys_for_all(B, wl, ctx, 1)
+    reqs, keep = _make_requests(B, wl, ctx, [(1, 500, 0, 3)], keys)
+    srv = B.blb_server_create(ctx, plan_cache_bytes=1 << 20, max_batch=4, n_streams=1)
+    try:
+        B.blb_server_add_weights(srv, 1, wl.serving_weights(1, SHAPES[1]), 2)
+        r = reqs[0]
+        rid = B.blb_server_submit(srv, keys[0], 1, r["L"], r["X"], r["Y"])
+        B.blb_server_drain(srv, 60)
+        st, lat = B.blb_server_poll(srv, rid)
+        assert st == B.BLB_ENOMEM
+        assert B.blb_server_stats(srv)["rejected"] == 1
+    finally:
+        B.blb_server_destroy(srv)
+        for k in keys:
+            B.blb_keys_destroy(k)
