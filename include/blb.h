@@ -86,8 +86,14 @@ int blb_ctx_set_timing(blb_ctx* ctx, int enable);
 int blb_ctx_read_timing(blb_ctx* ctx, int kind, double* total_ms, int64_t* launches, double* units);
 int blb_ctx_reset_timing(blb_ctx* ctx);
 
+/* ---- operation counters (counted when work is enqueued) ---------------------------------
+ * out[8]: key switches, NTT / inverse-NTT limb-polys, ct-pt products (one plaintext times one
+ * ciphertext), ct-ct tensor products, relinearisations, rescaled ciphertexts, ModUp sources,
+ * plaintext bytes streamed by the matmul_cp MAC.  reset != 0 zeroes them after reading. */
+int blb_ctx_counters(blb_ctx* ctx, int64_t* out, int reset);
+
 /* ---- launch-shape knobs (never change a result bit; chosen by the autotuner) ------------ */
-enum { BLB_KNOB_MAC_VARIANT = 0, BLB_KNOB_BATCH_VARIANT = 1, BLB_KNOB_BATCH_GRID = 2, BLB_KNOB_KINDS = 3 };
+enum { BLB_KNOB_MAC_VARIANT = 0, BLB_KNOB_BATCH_VARIANT = 1, BLB_KNOB_BATCH_GRID = 2, BLB_KNOB_NTT_VARIANT = 3, BLB_KNOB_KINDS = 4 };
 int blb_ctx_set_knob(blb_ctx* ctx, int knob, int value);
 int blb_ctx_get_knob(const blb_ctx* ctx, int knob);
 

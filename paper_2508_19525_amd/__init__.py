@@ -54,6 +54,7 @@ _SIGS = {
     "blb_ctx_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
     "blb_ctx_read_timing": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "blb_ctx_reset_timing": (C.c_int, [C.c_void_p]),
+    "blb_ctx_counters": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "blb_ctx_set_knob": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "blb_ctx_get_knob": (C.c_int, [C.c_void_p, C.c_int]),
     "blb_keygen": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.POINTER(C.c_void_p)]),
@@ -182,11 +183,21 @@ def blb_ctx_read_timing(ctx, kind):
     return ms.value, n.value, u.value
 
 
+COUNTER_NAMES = ["key_switches", "ntt_polys", "ct_pt_products", "tensor_products", "relinearisations", "rescaled_cts",
+                 "modup_sources", "plaintext_bytes"]
+
+
+def blb_ctx_counters(ctx, reset=False):
+    out = np.zeros(8, np.int64)
+    _check(lib().blb_ctx_counters(ctx, _host_ptr(out), 1 if reset else 0), "blb_ctx_counters")
+    return dict(zip(COUNTER_NAMES, [int(x) for x in out]))
+
+
 def blb_ctx_reset_timing(ctx):
     _check(lib().blb_ctx_reset_timing(ctx), "blb_ctx_reset_timing")
 
 
-BLB_KNOB_MAC_VARIANT, BLB_KNOB_BATCH_VARIANT, BLB_KNOB_BATCH_GRID = 0, 1, 2
+BLB_KNOB_MAC_VARIANT, BLB_KNOB_BATCH_VARIANT, BLB_KNOB_BATCH_GRID, BLB_KNOB_NTT_VARIANT = 0, 1, 2, 3
 
 
 def blb_ctx_set_knob(ctx, knob, value):

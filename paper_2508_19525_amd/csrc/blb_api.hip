@@ -254,6 +254,7 @@ void ntt_descs(blb_ctx* c, const std::vector<PolyDesc>& d, int kind) {
     const PolyDesc* dd = (const PolyDesc*)upload(c, d.data() + off, cnt * sizeof(PolyDesc));
     if (!dd) return;
     Span sp(c, BLB_T_NTT, (double)cnt);
+    c->counters[1] += (int64_t)cnt;
     switch (kind) {
       case 0: launch_ntt(c, dd, (int)cnt, true); break;
       case 1: launch_ntt(c, dd, (int)cnt, false); break;
@@ -379,6 +380,7 @@ int ks_modup(blb_ctx* c, int level, const std::vector<const uint64_t*>& srcs, ui
   for (int s = 0; s < S; ++s)
     for (int i = 0; i < nl; ++i) d.push_back(pd(srcs[s] + (size_t)i * n, dcoef + ((size_t)s * nl + i) * n, i, c->log_n));
   ntt_descs(c, d, NTT_INV);
+  c->counters[6] += S;
   {
     Span sp(c, BLB_T_MODUP, (double)S * nd * n);
     launch_modup(c, dcoef, X, c->d_kc[level], S, nl, n_ext, nd);
@@ -419,6 +421,7 @@ int ks_apply(blb_ctx* c, int level, const std::vector<const uint64_t*>& srcs, co
   }
   const KsOut* ko_dev = upload_vec(c, ko);
   if (!ko_dev) return BLB_EDEVICE;
+  c->counters[0] += O;
   {
     Span sp(c, BLB_T_KS_INNER, (double)O * n_ext * n);
     launch_ks_inner(c, ko_dev, O, X, c->d_kc[level], U, nl, n_ext, nd);
@@ -467,6 +470,7 @@ int ks_batch(blb_ctx* c, int level, const std::vector<const uint64_t*>& srcs, co
 int rescale_batch(blb_ctx* c, int level, int n_poly, const std::vector<const uint64_t*>& in, const std::vector<uint64_t*>& out) {
   const int n = c->n, nl = level + 1;
   const int T = (int)in.size();
+  c->counters[5] += T;
   Tmp tmp(c);
   uint64_t* last = tmp.get<uint64_t>((size_t)T * n_poly * n);
   if (tmp.failed) return BLB_ENOMEM;
@@ -543,6 +547,10 @@ int blb_ctx_create(const blb_params* prm, blb_ctx** out) {
   if (hipSetDevice(prm->device) != hipSuccess) return BLB_EDEVICE;
   blb_ctx* c = new (std::nothrow) blb_ctx();
   if (!c) return BLB_ENOMEM;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, prm->device) == hipSuccess && prop.multiProcessorCount > 0) c->n_cu = prop.multiProcessorCount;
+  }
   c->log_n = prm->log_n;
   c->n = 1 << prm->log_n;
   c->n_q = prm->n_q;
@@ -677,6 +685,10 @@ int blb_ctx_set_knob(blb_ctx* c, int knob, int value) {
       if (value < 1 || value > (1 << 20)) return BLB_EINVAL;
       c->batch_grid = value;
       return BLB_OK;
+    case BLB_KNOB_NTT_VARIANT:
+      if (value < 0 || value > 1) return BLB_EINVAL;
+      c->ntt_variant = value;
+      return BLB_OK;
     default: return BLB_EINVAL;
   }
 }
@@ -686,8 +698,17 @@ int blb_ctx_get_knob(const blb_ctx* c, int knob) {
     case BLB_KNOB_MAC_VARIANT: return c->mac_variant;
     case BLB_KNOB_BATCH_VARIANT: return c->batch_variant;
     case BLB_KNOB_BATCH_GRID: return c->batch_grid;
+    case BLB_KNOB_NTT_VARIANT: return c->ntt_variant;
     default: return BLB_EINVAL;
   }
+}
+
+int blb_ctx_counters(blb_ctx* c, int64_t* out, int reset) {
+  if (!c || !out) return BLB_EINVAL;
+  for (int i = 0; i < 8; ++i) out[i] = c->counters[i];
+  if (reset)
+    for (int i = 0; i < 8; ++i) c->counters[i] = 0;
+  return BLB_OK;
 }
 
 int blb_ctx_set_timing(blb_ctx* c, int enable) {
@@ -1165,6 +1186,8 @@ int blb_matmul_cp(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct
     const uint64_t* const* rx_dev = upload_vec(c, rx_tab);
     if (!rx_dev) return BLB_EDEVICE;
     Span sp(c, BLB_T_CP_MAC, (double)n_bj * nl * n);
+    c->counters[2] += (int64_t)n_ai * n_bj;
+    c->counters[7] += (int64_t)n_ai * n_bj * nl * n * 8;
     launch_cp_mac(c, P->pt, rx_dev, inner, nl, n_ai, n_bj, c->mac_variant);
   }
   // giant steps
@@ -1522,6 +1545,7 @@ int blb_matmul_cc(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct
       if (!pairs_dev) return BLB_EDEVICE;
       {
         Span sp(c, BLB_T_EW, (double)pairs.size() * w1);
+        for (const CcPair& pr : pairs) c->counters[2] += pr.y ? 2 : 1;
         launch_mask_pair(c, pairs_dev, (int)pairs.size(), nl);
       }
       std::vector<const uint64_t*> rin;
@@ -1538,6 +1562,8 @@ int blb_matmul_cc(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct
       if (!r_dev) return BLB_EDEVICE;
       {
         Span sp(c, BLB_T_CC_TENSOR, (double)nt * nl2 * n);
+        c->counters[3] += (int64_t)nt * m;
+        c->counters[4] += nt;
         launch_tensor_sum(c, a_dev, r_dev, T3, nt, m, nl, nl2);
       }
       std::vector<const uint64_t*> rs;
@@ -1593,6 +1619,7 @@ int blb_matmul_cc(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct
       if (!terms_dev || !off_dev || !outs_dev) return BLB_EDEVICE;
       {
         Span sp(c, BLB_T_EW, (double)outs.size() * w3);
+        c->counters[2] += (int64_t)terms.size();
         launch_masked_acc(c, terms_dev, off_dev, outs_dev, (int)outs.size(), nl3, true);
       }
     }
@@ -1879,6 +1906,8 @@ int blb_batch_matmul_cp(blb_ctx* c, const blb_cp_instance* inst, int n_inst) {
       mg.nl = nl;
       mg.n_inst = (int)members[gi].size();
       groups.push_back(mg);
+      c->counters[2] += (int64_t)n_ai * n_bj * mg.n_inst;
+      c->counters[7] += (int64_t)n_ai * n_bj * nl * n * 8 * ((mg.n_inst + ib - 1) / ib);
       const int n_kb = n / (256 * cpt);
       for (int i0 = 0; i0 < mg.n_inst; i0 += ib)
         for (int limb = 0; limb < nl; ++limb)

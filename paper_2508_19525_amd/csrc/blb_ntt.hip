@@ -10,6 +10,7 @@
 // launch can gather from arbitrary buffers and moduli.
 #include "blb_internal.h"
 #include "blb_kernels.h"
+#include <algorithm>
 
 namespace {
 
@@ -51,14 +52,18 @@ __device__ __forceinline__ void ntt_pass(double* lds, const double* __restrict__
         const double w = tw[widx];
         double& a = x[h * GS + k];
         double& b = x[h * GS + k + t_loc];
+        // lazy reduction: values are brought back to |x| <= q/2 only after every second stage
+        // (and at the end of the pass); in between they stay below ~3.1 q < 2^52, where every
+        // FP64 operation on them is exact and mulmod_s keeps |result| < 1.3 q.
+        const bool red = (u & 1) || (u == R_LOG - 1);
         if (FWD) {
           const double v = mulmod_s(b, w, q, qi);
           const double s = a + v, d = a - v;
-          a = reduce_s(s, q, qi);
-          b = reduce_s(d, q, qi);
+          a = red ? reduce_s(s, q, qi) : s;
+          b = red ? reduce_s(d, q, qi) : d;
         } else {
           const double s = a + b, d = a - b;
-          a = reduce_s(s, q, qi);
+          a = red ? reduce_s(s, q, qi) : s;
           b = mulmod_s(d, w, q, qi);
         }
       }
@@ -115,7 +120,7 @@ __global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt(const PolyDesc
 #pragma unroll
     for (int i = 0; i < kPerThread; ++i) {
       const int j = tid + i * T;
-      st(d, j, canon(mulmod_s(lds[pad_idx(j)], ninv, q, qi), q), q, qi);
+      st(d, j, canon_full(mulmod_s(lds[pad_idx(j)], ninv, q, qi), q, qi), q, qi);
     }
   } else {
 #pragma unroll
@@ -126,11 +131,78 @@ __global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt(const PolyDesc
   }
 }
 
+// Persistent, software-pipelined variant: a grid of resident workgroups walks the descriptor
+// list with a grid stride; the next polynomial's values are loaded into registers while the
+// current one is transformed in LDS, hiding the global-memory latency that a one-shot
+// workgroup (one per CU at N = 16384) exposes.
+template <int LOGN, bool FWD, class LoadOp, class StoreOp>
+__global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt_pipe(const PolyDesc* __restrict__ descs, const double* __restrict__ tw_all,
+                                                                     ModTable mt, LoadOp ld, StoreOp st, int count) {
+  constexpr int N = 1 << LOGN;
+  constexpr int T = N / kPerThread;
+  __shared__ double lds[N + N / 16];
+  const int tid = threadIdx.x;
+  int p = blockIdx.x;
+  if (p >= count) return;
+  double nx[kPerThread];
+  {
+    const PolyDesc d = descs[p];
+    const double q = mt.m[d.mod].q, qi = mt.m[d.mod].qinv;
+#pragma unroll
+    for (int i = 0; i < kPerThread; ++i) nx[i] = ld(d, tid + i * T, q, qi);
+  }
+  for (;;) {
+    const PolyDesc d = descs[p];
+    const double q = mt.m[d.mod].q, qi = mt.m[d.mod].qinv;
+    const double* tw = tw_all + (size_t)d.mod * N;
+#pragma unroll
+    for (int i = 0; i < kPerThread; ++i) lds[pad_idx(tid + i * T)] = nx[i];
+    __syncthreads();
+    const int pn = p + gridDim.x;
+    if (pn < count) {  // prefetch the next polynomial while this one is transformed
+      const PolyDesc dn = descs[pn];
+      const double qn = mt.m[dn.mod].q, qin = mt.m[dn.mod].qinv;
+#pragma unroll
+      for (int i = 0; i < kPerThread; ++i) nx[i] = ld(dn, tid + i * T, qn, qin);
+    }
+    ntt_all_passes<LOGN, FWD>(lds, tw, q, qi);
+    if (!FWD) {
+      const double ninv = mt.m[d.mod].ninv;
+#pragma unroll
+      for (int i = 0; i < kPerThread; ++i) {
+        const int j = tid + i * T;
+        st(d, j, canon_full(mulmod_s(lds[pad_idx(j)], ninv, q, qi), q, qi), q, qi);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < kPerThread; ++i) {
+        const int j = tid + i * T;
+        st(d, j, canon(lds[pad_idx(j)], q), q, qi);
+      }
+    }
+    __syncthreads();  // LDS is rewritten by the next iteration
+    p = pn;
+    if (p >= count) break;
+  }
+}
+
 template <bool FWD, class LoadOp, class StoreOp>
 void launch_ntt_generic(blb_ctx* c, const PolyDesc* d_descs, int count, LoadOp ld, StoreOp st) {
   if (count <= 0) return;
   const double* tw = FWD ? c->d_tw_fwd : c->d_tw_inv;
   const int threads = c->n / kPerThread;
+  if (c->ntt_variant == 1) {
+    // resident workgroups: LDS per workgroup is 8.5 N bytes of 160 KiB per CU
+    const int per_cu = std::max(1, (160 * 1024) / (int)((c->n + c->n / 16) * sizeof(double)));
+    const int grid = std::min(count, c->n_cu * per_cu);
+    switch (c->log_n) {
+      case 12: k_ntt_pipe<12, FWD><<<grid, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st, count); break;
+      case 13: k_ntt_pipe<13, FWD><<<grid, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st, count); break;
+      case 14: k_ntt_pipe<14, FWD><<<grid, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st, count); break;
+      default: break;
+    }
+    return;
+  }
   switch (c->log_n) {
     case 12: k_ntt<12, FWD><<<count, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st); break;
     case 13: k_ntt<13, FWD><<<count, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st); break;

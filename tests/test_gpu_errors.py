@@ -1,0 +1,106 @@
+"""Fault paths forced from the host: malformed arguments, level and scale mismatches, missing
+keys and an exhausted HBM budget return their error codes before any work is enqueued, and
+the outputs are left untouched."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2508_19525_amd as B
+    ctx = B.blb_ctx_create(12, 2, 1, 2, 0, torch.cuda.current_stream().cuda_stream)
+    keys = B.blb_keygen(ctx, 3, [1])
+    yield B, ctx, keys
+    torch.cuda.synchronize()
+    B.blb_keys_destroy(keys)
+    B.blb_ctx_destroy(ctx)
+
+
+def _fresh_ct(B, ctx, keys, level=1, scale=2.0 ** 30):
+    n = 4096
+    pt = torch.empty((level + 1) * n, dtype=torch.int64, device="cuda")
+    B.blb_encode(ctx, np.linspace(-1, 1, 100), scale, level, pt)
+    ct, t = B.new_ct(n, level)
+    B.blb_encrypt(ctx, keys, pt, level, scale, 1, 0, ct)
+    return ct, t
+
+
+def _code(fn, *a):
+    import paper_2508_19525_amd as B
+    with pytest.raises(B.BlbError) as e:
+        fn(*a)
+    return e.value.code
+
+
+def test_bad_parameters_rejected(env):
+    B, ctx, keys = env
+    assert _code(B.blb_ctx_create, 11, 2, 1, 2) == B.BLB_EINVAL  # N below the supported range
+    assert _code(B.blb_ctx_create, 13, 3, 1, 4) == B.BLB_EINVAL  # dnum > n_q
+    assert _code(B.blb_ctx_create, 13, 0, 1, 1) == B.BLB_EINVAL
+
+
+def test_missing_key_and_untouched_output(env):
+    B, ctx, keys = env
+    ct, t = _fresh_ct(B, ctx, keys)
+    out, to = B.new_ct(4096, 1)
+    to.fill_(7)
+    torch.cuda.synchronize()
+    assert _code(B.blb_rotate, ctx, keys, ct, 3, out) == B.BLB_ENOKEY  # only step 1 was generated
+    torch.cuda.synchronize()
+    assert bool((to == 7).all())
+    # aliasing input and output is rejected
+    assert _code(B.blb_rotate, ctx, keys, ct, 1, ct) == B.BLB_EINVAL
+
+
+def test_level_errors(env):
+    B, ctx, keys = env
+    ct, t = _fresh_ct(B, ctx, keys, level=0)
+    out, to = B.new_ct(4096, 0)
+    assert _code(B.blb_rescale, ctx, ct, out) == B.BLB_ELEVEL  # no limb left to drop
+    plan = B.blb_plan_matmul_cp(ctx, np.eye(32) * 0.1, 32, 1)
+    try:
+        y, ty = B.new_ct(4096, 0)
+        assert _code(B.blb_matmul_cp, ctx, keys, plan, [ct], [y]) in (B.BLB_ELEVEL, B.BLB_ENOKEY)
+    finally:
+        B.blb_plan_destroy(plan)
+    share = torch.zeros(4096, dtype=torch.int64, device="cuda")
+    assert _code(B.blb_mask_to_share, ctx, [ct], 1, 1, share) == B.BLB_ELEVEL  # target above the level
+
+
+def test_scale_mismatch(env):
+    B, ctx, keys = env
+    plan = B.blb_plan_matmul_cp(ctx, np.eye(64)[:, :32] * 0.1, 32, 1)
+    try:
+        g = B.blb_plan_info(plan)
+        assert g["n_in"] == 1
+        a, ta = _fresh_ct(B, ctx, keys, scale=2.0 ** 30)
+        y, ty = B.new_ct(4096, 0)
+        ty.fill_(5)
+        # the plan needs keys for its baby/giant steps, which these keys lack
+        assert _code(B.blb_matmul_cp, ctx, keys, plan, [a], [y]) == B.BLB_ENOKEY
+        torch.cuda.synchronize()
+        assert bool((ty == 5).all())
+    finally:
+        B.blb_plan_destroy(plan)
+
+
+def test_hbm_budget_exhausted():
+    """A context with a small HBM budget refuses plans and keys beyond it (forced from the host)."""
+    import paper_2508_19525_amd as B
+    ctx = B.blb_ctx_create(13, 3, 1, 3, 0, torch.cuda.current_stream().cuda_stream, 64 << 20)
+    try:
+        used = B.blb_ctx_device_bytes(ctx)
+        assert used < 64 << 20
+        assert _code(B.blb_plan_matmul_cp, ctx, np.zeros((768, 768)), 128, 2) == B.BLB_ENOMEM
+        assert B.blb_ctx_device_bytes(ctx) == used  # nothing leaked by the failed call
+        steps = list(range(1, 60))
+        assert _code(B.blb_keygen, ctx, 1, steps) == B.BLB_ENOMEM
+        assert B.blb_ctx_device_bytes(ctx) == used
+    finally:
+        B.blb_ctx_destroy(ctx)

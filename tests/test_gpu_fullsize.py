@@ -1,0 +1,166 @@
+"""Full-size configurations on the GPU, through the same entry points the benchmark times.
+
+- BERT-base fused linear op (N = 8192, three primes, X 128 x 768, W 768 x 768): the library's
+  encryption of X equals the oracle's; on the oracle's input ciphertexts, sampled outputs of
+  matmul_cp equal the oracle's word for word; all outputs decode to X W within 2^-20; the
+  operation counters equal the schedule's closed forms (BSGS with B = 8, G = 4).
+- 12-head attention Q_h K_h^T (N = 16384, four primes + two special): one sampled
+  diagonal-packed output of each head group (8 + 4) equals the oracle's; every head decodes to
+  Q_h K_h^T within 2^-20; tensor products = m^2 d / s (m = 128 tokens, d = 768, s = 8192
+  slots), one relinearisation per inner rotation t.
+
+The oracle computes only the sampled outputs (tens of seconds on the host)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2508_19525_amd as B
+    B.lib()
+    return B
+
+
+def _ct(B, keep, n, level, degree=1):
+    c, t = B.new_ct(n, level, degree)
+    keep.append(t)
+    return c
+
+
+def _import(B, ctx, keep, words, n, level, scale):
+    c = _ct(B, keep, n, level)
+    B.blb_import(ctx, words, c)
+    c.scale = scale
+    return c
+
+
+def test_bert_base_matmul_cp_full_size(B, orc):
+    from paper_2508_19525_amd import workloads as wl
+    cfg = wl.C2
+    p = cfg["params"]
+    L, d = cfg["L"], cfg["d_in"]
+    n, level = p.n, p.n_q - 1
+    X = wl.activations(2, L, d, cfg["x_dist"])
+    W = wl.weights(2, d, cfg["d_out"], cfg["w_std"])
+    o = orc.Context(p.log_n, p.n_q, p.n_special, p.dnum)
+    keys_o = orc.Keys(o, 77, o.cp_galois(L, d, d))
+    xw = np.stack([keys_o.encrypt(o.encode_rns(o.pack_spatial(X, a), p.scale, level), level, 78, a)
+                   for a in range(o.cp_geometry(L, d, d)["n_in"])])
+    ctx = B.blb_ctx_create(p.log_n, p.n_q, p.n_special, p.dnum, 0, torch.cuda.current_stream().cuda_stream)
+    keep = []
+    try:
+        plan = B.blb_plan_matmul_cp(ctx, W, L, level)
+        g = B.blb_plan_info(plan)
+        assert (g["B"], g["G"], g["n_in"], g["n_out"]) == (8, 4, 24, 24)
+        steps = [k * g["Lp"] for k in range(1, g["B"])] + [j * g["B"] * g["Lp"] for j in range(1, g["G"])]
+        keys = B.blb_keygen(ctx, 77, steps)
+        # the library's own encode + encrypt of X equals the oracle's words
+        pt = torch.empty((level + 1) * n, dtype=torch.int64, device="cuda")
+        for a in (0, 11, 23):
+            B.blb_encode(ctx, wl.pack_spatial(X, n // 2, a), p.scale, level, pt)
+            ct = _ct(B, keep, n, level)
+            B.blb_encrypt(ctx, keys, pt, level, p.scale, 78, a, ct)
+            torch.cuda.synchronize()
+            assert np.array_equal(B.blb_export(ctx, ct, n), xw[a]), f"input ciphertext {a}"
+        xs = [_import(B, ctx, keep, xw[a], n, level, p.scale) for a in range(g["n_in"])]
+        ys = [_ct(B, keep, n, level - 1) for _ in range(g["n_out"])]
+        B.blb_ctx_counters(ctx, reset=True)
+        B.blb_matmul_cp(ctx, keys, plan, xs, ys)
+        cnt = B.blb_ctx_counters(ctx, reset=True)
+        torch.cuda.synchronize()
+        assert cnt["key_switches"] == 24 * 7 + 24 * 3 == 240
+        assert cnt["ct_pt_products"] == 24 * 24 * 32 == 18432
+        assert cnt["modup_sources"] == 24 + 24 * 3
+        assert cnt["rescaled_cts"] == 24
+        assert cnt["plaintext_bytes"] == 18432 * 3 * n * 8
+        samples = [0, 17]
+        want = keys_o.matmul_cp(xw, level, W, L, outputs=samples)
+        for b in samples:
+            assert np.array_equal(B.blb_export(ctx, ys[b], n), want[b]), f"output {b}"
+        vecs = []
+        dec = torch.empty(level * n, dtype=torch.int64, device="cuda")
+        for b in range(g["n_out"]):
+            B.blb_decrypt(ctx, keys, ys[b], dec)
+            vecs.append(B.blb_decode(ctx, dec, level - 1, ys[b].scale, n // 2))
+        got = wl.unpack_spatial(vecs, L, d, n // 2)
+        assert np.abs(got - X @ W).max() < 2.0 ** -20
+        B.blb_plan_destroy(plan)
+        B.blb_keys_destroy(keys)
+    finally:
+        torch.cuda.synchronize()
+        B.blb_ctx_destroy(ctx)
+
+
+def test_attention_matmul_cc_full_size(B, orc):
+    from paper_2508_19525_amd import workloads as wl
+    cfg = wl.C3
+    p = cfg["params"]
+    heads, L, d = cfg["heads"], cfg["L"], cfg["d_head"]
+    n, level = p.n, p.n_q - 1
+    rng = np.random.default_rng(wl.seed_for(3, wl.ROLE_X))
+    Q = [rng.normal(0, 1, (L, d)) for _ in range(heads)]
+    Kt = [rng.normal(0, 1, (L, d)).T.copy() for _ in range(heads)]
+    o = orc.Context(p.log_n, p.n_q, p.n_special, p.dnum)
+    ctx = B.blb_ctx_create(p.log_n, p.n_q, p.n_special, p.dnum, 0, torch.cuda.current_stream().cuda_stream)
+    keep = []
+    try:
+        steps = B.blb_cc_rotations(ctx, heads, L)
+        keys_o = orc.Keys(o, 79, sorted({o.galois_elt(s) for s in steps}))
+        keys = B.blb_keygen(ctx, 79, steps)
+        plan = B.blb_plan_matmul_cc(ctx, heads, L, d, level)
+        info = B.blb_plan_cc_info(plan)
+        assert [(g["H"], g["c"], g["n_ct"], g["n_out"]) for g in info["groups"]] == [(8, 8, 8, 16), (4, 16, 4, 8)]
+        A, Bp, words, h0 = [], [], [], 0
+        for gi, grp in enumerate(info["groups"]):
+            H = grp["H"]
+            aw = np.stack([keys_o.encrypt(o.encode_rns(o.pack_mhp(Q[h0:h0 + H], H, L, d, a, "A"), p.scale, level), level, 80 + gi, a)
+                           for a in range(grp["n_ct"])])
+            bw = np.stack([keys_o.encrypt(o.encode_rns(o.pack_mhp(Kt[h0:h0 + H], H, L, d, a, "Bp"), p.scale, level), level, 90 + gi, a)
+                           for a in range(grp["n_ct"])])
+            A += [_import(B, ctx, keep, w, n, level, p.scale) for w in aw]
+            Bp += [_import(B, ctx, keep, w, n, level, p.scale) for w in bw]
+            words.append((aw, bw))
+            h0 += H
+        Cd = [_ct(B, keep, n, level - 3) for _ in range(info["n_out"])]
+        B.blb_ctx_counters(ctx, reset=True)
+        B.blb_matmul_cc(ctx, keys, plan, A, Bp, Cd)
+        cnt = B.blb_ctx_counters(ctx, reset=True)
+        torch.cuda.synchronize()
+        # step 2: two key-switched inner rotations per (t > 0, a); one relinearisation per t;
+        # step 3: one right rotation per t with t mod c != 0
+        assert cnt["tensor_products"] == 128 * 128 * 768 // 8192 == 1536
+        assert cnt["relinearisations"] == 2 * 128
+        assert cnt["key_switches"] == 12 * 2 * 127 + 2 * 128 + (128 - 16) + (128 - 8)
+        assert cnt["ct_pt_products"] == 12 * (1 + 2 * 127) + (16 + 2 * 112) + (8 + 2 * 120)
+        # one sampled output per head group, word for word
+        base, sample = 0, 5
+        for (aw, bw), grp in zip(words, info["groups"]):
+            want = keys_o.matmul_cc(aw, bw, level, grp["H"], L, d, outputs=[sample])
+            assert np.array_equal(B.blb_export(ctx, Cd[base + sample], n), want[sample]), f"group H={grp['H']}"
+            base += grp["n_out"]
+        # every head decodes to Q_h K_h^T
+        dec = torch.empty(n, dtype=torch.int64, device="cuda")
+        h0, base, err = 0, 0, 0.0
+        for grp in info["groups"]:
+            vecs = []
+            for k in range(grp["n_out"]):
+                ct = Cd[base + k]
+                B.blb_decrypt(ctx, keys, ct, dec)
+                vecs.append(B.blb_decode(ctx, dec, 0, ct.scale, n // 2))
+            Cs = wl.unpack_diag(vecs, grp["H"], L, n // 2)
+            for h in range(grp["H"]):
+                err = max(err, float(np.abs(Cs[h] - Q[h0 + h] @ Kt[h0 + h]).max()))
+            h0 += grp["H"]
+            base += grp["n_out"]
+        assert err < 2.0 ** -20
+        B.blb_plan_destroy(plan)
+        B.blb_keys_destroy(keys)
+    finally:
+        torch.cuda.synchronize()
+        B.blb_ctx_destroy(ctx)

@@ -379,3 +379,42 @@ def test_exec_cc_replays_match_eager(c3s):
         for o in range(n_out):
             assert np.array_equal(got[o], c3s.export(r["C"][o])), f"replay {rep} output {o}"
     B.blb_exec_destroy(ex)
+
+
+# --------------------------------------------------------------------------------------
+# launch-shape knobs never change a bit
+# --------------------------------------------------------------------------------------
+def test_ntt_variants_bit_identical(c3s):
+    """The persistent pipelined NTT (knob 1) and the one-workgroup-per-poly NTT (knob 0) give
+    identical words through a full matmul_cc and through rotations at every level."""
+    B = c3s.B
+    r = _cc_case(c3s, 8, 32, 32, 11)
+    base = [c3s.export(x) for x in r["C"]]
+    B.blb_ctx_set_knob(c3s.h, B.BLB_KNOB_NTT_VARIANT, 1)
+    try:
+        C2 = [c3s.ct(r["level"] - 3) for _ in range(len(r["C"]))]
+        B.blb_matmul_cc(c3s.h, r["keys_g"], r["plan"], r["A"], r["B"], C2)
+        for o in range(len(C2)):
+            assert np.array_equal(c3s.export(C2[o]), base[o])
+        for o in range(len(r["want"][0][0])):
+            assert np.array_equal(c3s.export(C2[o]), r["want"][0][0][o])
+    finally:
+        B.blb_ctx_set_knob(c3s.h, B.BLB_KNOB_NTT_VARIANT, 0)
+    B.blb_plan_destroy(r["plan"])
+    B.blb_keys_destroy(r["keys_g"])
+
+
+def test_mac_variants_bit_identical(c2s):
+    B = c2s.B
+    r = _cp_case(c2s, 64, 96, 64, 2, 5, x_std=1.0)
+    base = [c2s.export(y) for y in r["Yc"]]
+    Xc = _xcts(c2s, r, 2)
+    for var in range(5):
+        B.blb_ctx_set_knob(c2s.h, B.BLB_KNOB_MAC_VARIANT, var)
+        Y = [c2s.ct(1) for _ in range(len(base))]
+        B.blb_matmul_cp(c2s.h, r["keys_g"], r["plan"], Xc, Y)
+        for b in range(len(Y)):
+            assert np.array_equal(c2s.export(Y[b]), base[b]), f"variant {var}"
+    B.blb_ctx_set_knob(c2s.h, B.BLB_KNOB_MAC_VARIANT, 0)
+    B.blb_plan_destroy(r["plan"])
+    B.blb_keys_destroy(r["keys_g"])
