@@ -129,6 +129,16 @@ int blb_rotate(blb_ctx* ctx, const blb_keys* keys, const blb_ct* in, int32_t ste
 /* Rescale (Preliminaries, "Rescaling"): divide by the last prime q_l with rounding.
  * out->data must hold (degree+1)*level*N words; out gets level-1 and scale/q_l. */
 int blb_rescale(blb_ctx* ctx, const blb_ct* in, blb_ct* out);
+/* Batched negacyclic NTT over R_q = Z_q[X]/(X^N + 1) (Preliminaries, the ring of CKKS
+ * polynomials), in place on caller-owned device words laid out [n_polys][n_limbs][N]; limb i
+ * of every poly is reduced modulo prime i of the chain (the n_q ciphertext primes, then the
+ * special primes), 1 <= n_limbs <= n_q + n_special.  Inputs must be canonical residues in
+ * [0, q_i); outputs are canonical.  Forward (inverse = 0): word j of the output is
+ * sum_k a_k psi^((2 brv(j) + 1) k) mod q_i, brv = bit reversal over log2 N bits, psi =
+ * x^((q_i - 1) / 2N) for the smallest integer x >= 2 whose result has psi^N = -1 (the order
+ * every ciphertext of this library is held in).  Inverse (inverse = 1) undoes it exactly.
+ * Stream-ordered; EINVAL on bad sizes or a null pointer with n_polys > 0. */
+int blb_ntt(blb_ctx* ctx, uint64_t* data, int64_t n_polys, int32_t n_limbs, int32_t inverse);
 
 /* ---- matmul_cp (Section "Efficient Protocol for Fused MatMuls"; Appendix "BSGS
  * Optimization"; spatial-first packing of "Consistent Packing for Single Operator") ----- */
@@ -152,22 +162,40 @@ int blb_matmul_cp(blb_ctx* ctx, const blb_keys* keys, const blb_plan* plan, cons
  * of the group holds at slot i + L'(h + H kappa):
  *     A:  A_h{i, a c + kappa}                      (Q_h, spatial-first per head)
  *     B': B_h{a c + kappa, (i + kappa) mod L'}      (K_h^T rows, reduce-first, step 1 applied by
- *                                                   the client before encryption)
+ *                                                   the client before encryption), or
+ *     B:  B_h{a c + kappa, i}                       (no pre-rotation: step 1 runs on the server)
  * and output ciphertext g (g < L'/c) of the group holds C_h{i, (i + g c + kappa) mod L'}.
- * Operands are at the plan's level (>= 3); outputs come out 3 levels lower.
- * Step 2 rotations per group: 2 (L'-1) per B' ciphertext (hoisted); step 3: L' - L'/c. */
+ * Operands are at the plan's level; outputs come out 3 levels lower (level >= 3) with B', or
+ * 4 levels lower (level >= 4) with B.
+ * Rotations per group: step 1 (server side only) 2 (c-1) per B ciphertext (hoisted); step 2
+ * 2 (L'-1) per B' ciphertext (hoisted); step 3 L' - L'/c.  Step 1 needs no keys beyond step 2's. */
 /* Rotation steps the keys must cover (left t, right L'-t, right tau H L'); returns the count
  * written to steps (or needed, when steps is NULL). */
 int blb_cc_rotations(const blb_ctx* ctx, int n_heads, int L, int32_t* steps, int cap);
-/* Masks of steps 2 and 3 encoded on the device (step 2 at scale q_level 2^10, step 3 at
- * q_{level-2} / 2^10; B' is multiplied by the integer 2^10 before its key-switched rotations
- * so their noise shrinks relative to the message, which the step-3 mask scale undoes). */
-int blb_plan_matmul_cc(blb_ctx* ctx, int n_heads, int L, int d_head, int level, blb_plan** out);
+/* Masks encoded on the device.  b_prerotated = 1: step-2 masks at scale q_level 2^10, step-3
+ * masks at q_{level-2} / 2^10.  b_prerotated = 0: step-1 masks at q_level / 2^10 (M^0: blocks of
+ * class kappa = 0; M^1_kappa: class kappa, i < L' - kappa; M^2_kappa: class kappa, i >= L' - kappa),
+ * then steps 2-3 as above one level lower.  Before each batch of key-switched rotations the
+ * rotated ciphertext is multiplied by the integer 2^10, so the key-switch noise shrinks
+ * relative to the message; the mask scales undo the factor. */
+int blb_plan_matmul_cc(blb_ctx* ctx, int n_heads, int L, int d_head, int level, int32_t b_prerotated, blb_plan** out);
 /* info: L', n_ct, n_out, then per group (H, c, n_ct, n_out, first ct); returns group count. */
 int blb_plan_cc_info(const blb_plan* plan, int32_t* info, int cap);
-/* C_g for every group; n_ct operands each (groups concatenated), n_out outputs. */
+/* C_g for every group; n_ct operands each (groups concatenated), n_out outputs, each of
+ * 2 (level - 2) N words (B pre-rotated) or 2 (level - 3) N words (step 1 on the server). */
 int blb_matmul_cc(blb_ctx* ctx, const blb_keys* keys, const blb_plan* plan, const blb_ct* A, const blb_ct* Bp, int n_ct,
                   blb_ct* C_diag, int n_out);
+
+/* ---- re-randomisation before mask-to-share (opt-in) -----------------------------------
+ * Algorithm ckks2mpc hands the masked ciphertext to the client as evaluated; its c1 depends on
+ * the server's weights, which the paper does not address.  This call adds a public-key
+ * encryption of zero with a flooding term, in place, at each ciphertext's level:
+ *     (c0 + v p0 + e0, c1 + v p1 + e1),  pk = (p0, p1) = (-a s + e, a) made by blb_keygen
+ * (a uniform: tag 7, e Gaussian: tag 8, object 0, key seed), v ternary (tag 9), e1 Gaussian
+ * (tag 11), e0 uniform in [-2^F, 2^F] (tag 10: the 128-bit Philox block mod 2^(F+1) + 1,
+ * minus 2^F), object id = index t in cts, key `seed`.  F = flood_bits in [32, 48]; the decoded
+ * value moves by about 2^F / scale.  EINVAL on bad arguments (nothing written). */
+int blb_rerandomize(blb_ctx* ctx, const blb_keys* keys, blb_ct* cts, int n_ct, uint64_t seed, int flood_bits);
 
 /* ---- CKKS-to-MPC mask-and-share (Algorithm ckks2mpc, step 1; functionality F_C2M) ------- */
 /* For each ciphertext t < n_ct: reduce to target_level (dropping top limbs) if lower, sample

@@ -89,7 +89,8 @@ def lib():
             "orc_mask_to_share": (None, [vp, _u64p, C.c_int, C.c_int, C.c_uint64, C.c_uint32, _u64p, _u64p]),
             "orc_num_threads": (C.c_int, []),
             "orc_cc_geometry": (None, [vp, C.c_int, C.c_int, C.c_int, _i32p]),
-            "orc_matmul_cc": (C.c_int, [vp, _u64p, _u64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, _u64p]),
+            "orc_rerandomize": (C.c_int, [vp, _u64p, C.c_int, C.c_uint64, C.c_uint32, C.c_int, _u64p]),
+            "orc_matmul_cc": (C.c_int, [vp, _u64p, _u64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, _u64p]),
             "orc_cc_galois": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, _u64p]),
         }
         for name, (res, args) in sig.items():
@@ -335,17 +336,26 @@ class Keys:
             raise KeyError("missing relinearisation key")
         return out
 
-    def matmul_cc(self, A_cts, Bp_cts, level: int, H_g: int, L: int, d: int, outputs=None) -> np.ndarray:
-        """One head group; A_cts / Bp_cts: [n_ct][2][level+1][N]; returns [n_out][2][level-2][N]"""
+    def rerandomize(self, ct, level: int, seed: int, ct_id: int, flood_bits: int) -> np.ndarray:
+        """ct + Enc_pk(0) with a flooding term uniform in [-2^F, 2^F] (coefficient form)"""
+        out = np.zeros((2, level + 1, self.ctx.n), np.uint64)
+        if lib().orc_rerandomize(self._p, _c(ct, np.uint64), level, seed, ct_id, flood_bits, out) != 0:
+            raise ValueError("rerandomize: bad arguments")
+        return out
+
+    def matmul_cc(self, A_cts, Bp_cts, level: int, H_g: int, L: int, d: int, outputs=None, b_prerotated=True) -> np.ndarray:
+        """One head group; A_cts / Bp_cts: [n_ct][2][level+1][N]; returns [n_out][2][level-2][N]
+        (B pre-rotated by the client) or [n_out][2][level-3][N] (step 1 run homomorphically)."""
         c = self.ctx
         g = c.cc_geometry(H_g, L, d)
-        O = np.zeros((g["n_out"], 2, level - 2, c.n), np.uint64)
+        O = np.zeros((g["n_out"], 2, level - (2 if b_prerotated else 3), c.n), np.uint64)
         mask = None
         if outputs is not None:
             m = np.zeros(g["n_out"], np.uint8)
             m[list(outputs)] = 1
             mask = m.ctypes.data_as(C.c_void_p)
-        rc = lib().orc_matmul_cc(self._p, _c(A_cts, np.uint64), _c(Bp_cts, np.uint64), g["n_ct"], level, H_g, L, d, mask, O)
+        rc = lib().orc_matmul_cc(self._p, _c(A_cts, np.uint64), _c(Bp_cts, np.uint64), g["n_ct"], level, H_g, L, d,
+                                 1 if b_prerotated else 0, mask, O)
         if rc != 0:
             raise ValueError(f"matmul_cc failed ({rc})")
         return O

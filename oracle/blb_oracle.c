@@ -871,6 +871,59 @@ void orc_mask_to_share(const orc_ctx* c, const uint64_t* ct, int level, int targ
   }
 }
 
+/* ------------------------------------------------------------------------------------ */
+/* Re-randomisation before mask-to-share (opt-in; the paper leaves c1 as the evaluation    */
+/* produced it, and c1 depends on the server's weights)                                    */
+/* ------------------------------------------------------------------------------------ */
+/* Public key over the ciphertext primes: p1 = a (uniform per limb, tag pk-a, object 0, key
+ * seed), p0 = -a s + e (e Gaussian, tag pk-e).  Re-randomised ciphertext:
+ *   (c0 + v p0 + e0, c1 + v p1 + e1) mod Q_level,
+ * v ternary (tag rr-v), e1 Gaussian (tag rr-e1), e0 a uniform integer in [-2^F, 2^F] (tag
+ * rr-e0: the 128-bit Philox block mod 2^(F+1) + 1, minus 2^F), object id ct_id, key `seed`;
+ * it decrypts to m + v e + e0 + e1 s, so the flooding term e0 hides the evaluation noise. */
+enum { TAG_PK_A = 7, TAG_PK_E = 8, TAG_RR_V = 9, TAG_RR_E0 = 10, TAG_RR_E1 = 11 };
+static int64_t sample_flood(uint64_t seed, uint32_t k, uint32_t obj, int bits) {
+  uint32_t w[4]; philox_at(seed, k, LIMB_INT, obj, TAG_RR_E0, w);
+  u128 x = ((u128)w[3] << 96) | ((u128)w[2] << 64) | ((u128)w[1] << 32) | (u128)w[0];
+  u128 m = ((u128)2 << bits) + 1;
+  return (int64_t)(uint64_t)(x % m) - ((int64_t)1 << bits);
+}
+int orc_rerandomize(const orc_keys* K, const uint64_t* ct, int level, uint64_t seed, uint32_t ct_id, int flood_bits, uint64_t* out) {
+  const orc_ctx* c = K->c;
+  if (flood_bits < 32 || flood_bits > 48 || level < 0 || level >= c->n_q) return -1;
+  int n = c->n, nl = level + 1;
+  int32_t* v = (int32_t*)malloc(4 * n);
+  int32_t* epk = (int32_t*)malloc(4 * n);
+  int32_t* e1 = (int32_t*)malloc(4 * n);
+  int64_t* e0 = (int64_t*)malloc(8 * n);
+  for (int k = 0; k < n; ++k) {
+    uint32_t w[4]; philox_at(seed, (uint32_t)k, LIMB_INT, ct_id, TAG_RR_V, w);
+    v[k] = (int)(w[0] % 3u) - 1;
+    epk[k] = sample_gauss(K->seed, (uint32_t)k, 0, TAG_PK_E);
+    e1[k] = sample_gauss(seed, (uint32_t)k, ct_id, TAG_RR_E1);
+    e0[k] = sample_flood(seed, (uint32_t)k, ct_id, flood_bits);
+  }
+  #pragma omp parallel for
+  for (int i = 0; i < nl; ++i) {
+    uint64_t q = c->mod[i];
+    uint64_t* a = (uint64_t*)malloc(8 * n);
+    uint64_t* p0 = (uint64_t*)malloc(8 * n);
+    uint64_t* vq = (uint64_t*)malloc(8 * n);
+    uint64_t* t = (uint64_t*)malloc(8 * n);
+    for (int k = 0; k < n; ++k) a[k] = sample_uniform(K->seed, (uint32_t)k, (uint32_t)i, 0, TAG_PK_A, q);
+    polymul(c, i, a, K->s_rns + (size_t)i * n, p0);
+    for (int k = 0; k < n; ++k) { p0[k] = subm(smod(epk[k], q), p0[k], q); vq[k] = smod(v[k], q); }
+    polymul(c, i, vq, p0, t);
+    for (int k = 0; k < n; ++k) out[(size_t)i * n + k] = addm(addm(ct[(size_t)i * n + k], t[k], q), smod(e0[k], q), q);
+    polymul(c, i, vq, a, t);
+    for (int k = 0; k < n; ++k)
+      out[((size_t)nl + i) * n + k] = addm(addm(ct[((size_t)nl + i) * n + k], t[k], q), smod(e1[k], q), q);
+    free(a); free(p0); free(vq); free(t);
+  }
+  free(v); free(epk); free(e1); free(e0);
+  return 0;
+}
+
 /* number of OpenMP threads the oracle's parallel loops use */
 #include <omp.h>
 int orc_num_threads(void) { return omp_get_max_threads(); }
@@ -936,8 +989,8 @@ static void tensor_acc(const orc_ctx* c, uint64_t* acc3, const uint64_t* a, cons
  *          O_g = Rescale(O_g).
  * Output: L'/c cts at level-3, [g][2][level-2][N].  out_mask (NULL = all) selects the outputs;
  * only the t that feed them are computed. */
-int orc_matmul_cc(const orc_keys* K, const uint64_t* A, const uint64_t* Bp, int n_ct, int level, int H_g, int L, int d,
-                  const uint8_t* out_mask, uint64_t* O) {
+static int cc_steps23(const orc_keys* K, const uint64_t* A, const uint64_t* Bp, int n_ct, int level, int H_g, int L, int d,
+                      const uint8_t* out_mask, uint64_t* O) {
   const orc_ctx* c = K->c;
   int n = c->n, s = n / 2;
   if (level < 3) return -2;
@@ -995,6 +1048,75 @@ int orc_matmul_cc(const orc_keys* K, const uint64_t* A, const uint64_t* Bp, int 
     for (int g = 0; g < n_out; ++g)
       if (!out_mask || out_mask[g]) orc_rescale(c, acc + (size_t)g * w1, l1, 2, O + (size_t)g * 2 * l1 * n);
   free(v); free(rot); free(racc); free(R); free(Ad); free(T3); free(T); free(Tr); free(V); free(acc); free(bs);
+  return rc;
+}
+
+/* slot vector of the step-1 mask for class kappa: slot i + L' beta (class beta / H_g) is 1 when
+ * its class is kappa and lo <= i < hi */
+static void mask_cls(int s, int lp, int H_g, int kap, int lo, int hi, double* v) {
+  for (int j = 0; j < s; ++j) {
+    int i = j % lp, cls = (j / lp) / H_g;
+    v[j] = (cls == kap && i >= lo && i < hi) ? 1.0 : 0.0;
+  }
+}
+
+/* Step 1 (B row pre-rotation by kappa) in homomorphic form, for B_a that the client did not
+ * pre-rotate: with B''_a = 2^10 B_a (noise boost, an exact integer scalar),
+ *   B'_a = Rescale( B''_a (.) M^0 + sum_{kappa=1}^{c-1} [ Rot_l^kappa(B''_a) (.) M^1_kappa
+ *                                                   + Rot_r^{L'-kappa}(B''_a) (.) M^2_kappa ] ),
+ * masks encoded at q_level / 2^10: M^0 selects the blocks of class 0, M^1_kappa the slots of
+ * class kappa with i < L' - kappa, M^2_kappa those with i >= L' - kappa.  Block (h, kappa) of
+ * B'_a then holds B_h{a c + kappa, (i + kappa) mod L'} at scale Delta_B, one level down; A_a is
+ * dropped to the same level and steps 2-3 follow.  Output: L'/c cts at level-4. */
+static int cc_step1(const orc_keys* K, const uint64_t* A, const uint64_t* B, int n_ct, int level, int H_g, int L, int d,
+                    uint64_t* Ad, uint64_t* Bq) {
+  const orc_ctx* c = K->c;
+  int n = c->n, s = n / 2;
+  int32_t geo[4]; orc_cc_geometry(c, H_g, L, d, geo);
+  int lp = geo[0], cc = geo[1];
+  int nl = level + 1;
+  size_t w = (size_t)2 * nl * n, wq = (size_t)2 * level * n;
+  double dm1 = (double)c->mod[level] / NOISE_BOOST;
+  double* v = (double*)malloc(8 * s);
+  uint64_t* bs = (uint64_t*)malloc(8 * w);
+  uint64_t* rot = (uint64_t*)malloc(8 * w);
+  uint64_t* acc = (uint64_t*)malloc(8 * w);
+  int rc = 0;
+  for (int a = 0; a < n_ct && rc == 0; ++a) {
+    scale_ct(c, B + (size_t)a * w, (uint64_t)NOISE_BOOST, nl, bs);
+    memset(acc, 0, 8 * w);
+    mask_cls(s, lp, H_g, 0, 0, lp, v); mac_vec(c, acc, v, dm1, bs, level);
+    for (int kap = 1; kap < cc; ++kap) {
+      if (orc_rotate(K, bs, level, kap, rot) != 0) { rc = -1; break; }
+      mask_cls(s, lp, H_g, kap, 0, lp - kap, v); mac_vec(c, acc, v, dm1, rot, level);
+      if (orc_rotate(K, bs, level, -(int64_t)(lp - kap), rot) != 0) { rc = -1; break; }
+      mask_cls(s, lp, H_g, kap, lp - kap, lp, v); mac_vec(c, acc, v, dm1, rot, level);
+    }
+    if (rc) break;
+    orc_rescale(c, acc, level, 2, Bq + (size_t)a * wq);
+    const uint64_t* aa = A + (size_t)a * w;
+    for (int p = 0; p < 2; ++p) memcpy(Ad + (size_t)a * wq + (size_t)p * level * n, aa + (size_t)p * nl * n, 8 * (size_t)level * n);
+  }
+  free(v); free(bs); free(rot); free(acc);
+  return rc;
+}
+
+/* One head group of matmul_cc.  b_prerotated != 0: B_a arrive pre-rotated by the client
+ * (step 1 applied to the plaintext), inputs at `level` >= 3, output at level-3; else step 1
+ * runs homomorphically first, inputs at `level` >= 4, output at level-4. */
+int orc_matmul_cc(const orc_keys* K, const uint64_t* A, const uint64_t* B, int n_ct, int level, int H_g, int L, int d, int b_prerotated,
+                  const uint8_t* out_mask, uint64_t* O) {
+  if (b_prerotated) return cc_steps23(K, A, B, n_ct, level, H_g, L, d, out_mask, O);
+  const orc_ctx* c = K->c;
+  if (level < 4) return -2;
+  int32_t geo[4]; orc_cc_geometry(c, H_g, L, d, geo);
+  if (n_ct != geo[2] || geo[1] < 1 || geo[1] > geo[0]) return -3;
+  size_t wq = (size_t)2 * level * c->n * n_ct;
+  uint64_t* Ad = (uint64_t*)malloc(8 * wq);
+  uint64_t* Bq = (uint64_t*)malloc(8 * wq);
+  int rc = cc_step1(K, A, B, n_ct, level, H_g, L, d, Ad, Bq);
+  if (rc == 0) rc = cc_steps23(K, Ad, Bq, n_ct, level - 1, H_g, L, d, out_mask, O);
+  free(Ad); free(Bq);
   return rc;
 }
 

@@ -69,13 +69,15 @@ _SIGS = {
     "blb_import": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(blb_ct)]),
     "blb_rotate": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.c_int32, C.POINTER(blb_ct)]),
     "blb_rescale": (C.c_int, [C.c_void_p, C.POINTER(blb_ct), C.POINTER(blb_ct)]),
+    "blb_ntt": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32]),
+    "blb_rerandomize": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.c_int, C.c_uint64, C.c_int]),
     "blb_plan_matmul_cp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)]),
     "blb_plan_destroy": (None, [C.c_void_p]),
     "blb_plan_info": (C.c_int, [C.c_void_p, C.c_void_p]),
     "blb_matmul_cp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.c_int, C.POINTER(blb_ct), C.c_int]),
     "blb_mask_to_share": (C.c_int, [C.c_void_p, C.POINTER(blb_ct), C.c_int, C.c_uint64, C.c_int, C.c_void_p]),
     "blb_cc_rotations": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int]),
-    "blb_plan_matmul_cc": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)]),
+    "blb_plan_matmul_cc": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int32, C.POINTER(C.c_void_p)]),
     "blb_plan_cc_info": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "blb_matmul_cc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.POINTER(blb_ct), C.c_int,
                                 C.POINTER(blb_ct), C.c_int]),
@@ -261,6 +263,11 @@ def blb_rescale(ctx, ct_in: blb_ct, ct_out: blb_ct):
     _check(lib().blb_rescale(ctx, C.byref(ct_in), C.byref(ct_out)), "blb_rescale")
 
 
+def blb_ntt(ctx, data_dev, n_polys, n_limbs, inverse=False):
+    """In-place batched NTT of device words [n_polys][n_limbs][N] (int64 tensor or pointer)."""
+    _check(lib().blb_ntt(ctx, _ptr(data_dev), n_polys, n_limbs, 1 if inverse else 0), "blb_ntt")
+
+
 def blb_plan_matmul_cp(ctx, W: np.ndarray, L, level):
     Wc = np.ascontiguousarray(W, dtype=np.float64)
     out = C.c_void_p()
@@ -293,6 +300,11 @@ def blb_mask_to_share(ctx, cts, seed, target_level, share_dev):
         cts[i].level = arr[i].level
 
 
+def blb_rerandomize(ctx, keys, cts, seed, flood_bits):
+    arr = (blb_ct * len(cts))(*cts)
+    _check(lib().blb_rerandomize(ctx, keys, arr, len(cts), seed, flood_bits), "blb_rerandomize")
+
+
 def blb_cc_rotations(ctx, n_heads, L):
     k = lib().blb_cc_rotations(ctx, n_heads, L, None, 0)
     if k < 0:
@@ -302,9 +314,9 @@ def blb_cc_rotations(ctx, n_heads, L):
     return [int(x) for x in out[:k]]
 
 
-def blb_plan_matmul_cc(ctx, n_heads, L, d_head, level):
+def blb_plan_matmul_cc(ctx, n_heads, L, d_head, level, b_prerotated=True):
     out = C.c_void_p()
-    _check(lib().blb_plan_matmul_cc(ctx, n_heads, L, d_head, level, C.byref(out)), "blb_plan_matmul_cc")
+    _check(lib().blb_plan_matmul_cc(ctx, n_heads, L, d_head, level, 1 if b_prerotated else 0, C.byref(out)), "blb_plan_matmul_cc")
     return out.value
 
 

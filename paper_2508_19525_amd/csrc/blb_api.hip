@@ -814,6 +814,28 @@ int blb_keygen(blb_ctx* c, uint64_t seed, const int32_t* rot_steps, int n_rot, b
     blb_keys_destroy(K);
     return BLB_ENOMEM;
   }
+  // public key over the ciphertext primes: p1 = a (uniform, tag pk-a), p0 = -a s + e (tag pk-e)
+  {
+    const size_t pkw = (size_t)2 * c->n_q * n;
+    if ((rc = dalloc(c, (void**)&K->pk, pkw * 8))) {
+      blb_keys_destroy(K);
+      return rc;
+    }
+    K->bytes += pkw * 8;
+    const ModMap qs = map_identity(c->n_q);
+    uint64_t* p1 = K->pk + (size_t)c->n_q * n;
+    launch_sample_uniform(c, p1, c->n_q, qs, seed, 0, 7 /* pk-a */);
+    launch_sample_int(c, sp, c->n_q, qs, seed, 0, 8 /* pk-e */, true);
+    d.clear();
+    for (int m = 0; m < c->n_q; ++m) {
+      d.push_back(pd(p1 + (size_t)m * n, p1 + (size_t)m * n, m, c->log_n));
+      d.push_back(pd(sp + (size_t)m * n, sp + (size_t)m * n, m, c->log_n));
+    }
+    ntt_descs(c, d, NTT_FWD);
+    LimbVals none;
+    none.use = 0;
+    launch_rlwe_combine(c, K->pk, p1, K->s_ntt, sp, nullptr, none, c->n_q, qs);
+  }
   // relinearisation key: s' = s^2
   launch_ew(c, EW_MUL, sp, K->s_ntt, K->s_ntt, nullptr, nm, all);
   K->keys.push_back(SwKey{0, nullptr});
@@ -846,6 +868,7 @@ void blb_keys_destroy(blb_keys* K) {
   const size_t kw = (size_t)c->dnum * 2 * (c->n_q + c->n_sp) * c->n * 8;
   for (SwKey& s : K->keys) dfree(c, s.data, kw);
   dfree(c, K->s_ntt, (size_t)(c->n_q + c->n_sp) * c->n * 8);
+  dfree(c, K->pk, (size_t)2 * c->n_q * c->n * 8);
   delete K;
 }
 
@@ -1023,6 +1046,24 @@ int blb_rescale(blb_ctx* c, const blb_ct* in, blb_ct* out) {
   out->degree = in->degree;
   out->scale = in->scale / (double)c->mod[in->level];
   return BLB_OK;
+}
+
+// Batched negacyclic transform of caller-owned limb-polys [n_polys][n_limbs][N], in place;
+// limb i is taken modulo prime i of the chain (ciphertext primes, then special primes).
+int blb_ntt(blb_ctx* c, uint64_t* data, int64_t n_polys, int32_t n_limbs, int32_t inverse) {
+  if (!c || n_polys < 0 || n_limbs < 1 || n_limbs > c->n_q + c->n_sp || (inverse != 0 && inverse != 1)) return BLB_EINVAL;
+  if (n_polys == 0) return BLB_OK;
+  if (!data) return BLB_EINVAL;
+  const int n = c->n;
+  std::vector<PolyDesc> d;
+  d.reserve((size_t)n_polys * n_limbs);
+  for (int64_t p = 0; p < n_polys; ++p)
+    for (int i = 0; i < n_limbs; ++i) {
+      uint64_t* x = data + ((size_t)p * n_limbs + i) * n;
+      d.push_back(pd(x, x, i, c->log_n));
+    }
+  ntt_descs(c, d, inverse ? NTT_INV : NTT_FWD);
+  return hipGetLastError() == hipSuccess ? BLB_OK : BLB_EDEVICE;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1235,6 +1276,42 @@ int blb_matmul_cp(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct
 // ------------------------------------------------------------------------------------------
 // mask-and-share
 // ------------------------------------------------------------------------------------------
+int blb_rerandomize(blb_ctx* c, const blb_keys* K, blb_ct* cts, int n_ct, uint64_t seed, int flood_bits) {
+  if (!c || !K || !cts || n_ct < 1 || flood_bits < 32 || flood_bits > 48) return BLB_EINVAL;
+  int max_nl = 0;
+  for (int t = 0; t < n_ct; ++t) {
+    if (check_ct(c, &cts[t]) || cts[t].degree != 1) return BLB_EINVAL;
+    max_nl = std::max(max_nl, cts[t].level + 1);
+  }
+  if (!K->pk) return BLB_ENOKEY;
+  const int n = c->n;
+  Tmp tmp(c);
+  uint64_t* V = tmp.get<uint64_t>((size_t)4 * max_nl * n);
+  if (tmp.failed) return BLB_ENOMEM;
+  for (int t = 0; t < n_ct; ++t) {
+    const int nl = cts[t].level + 1;
+    uint64_t *E0 = V + (size_t)nl * n, *E1 = V + (size_t)2 * nl * n, *T = V + (size_t)3 * nl * n;
+    const ModMap lim = map_identity(nl);
+    launch_sample_int(c, V, nl, lim, seed, (uint32_t)t, 9 /* rr-v */, false);
+    launch_sample_flood(c, E0, nl, lim, seed, (uint32_t)t, 10 /* rr-e0 */, flood_bits);
+    launch_sample_int(c, E1, nl, lim, seed, (uint32_t)t, 11 /* rr-e1 */, true);
+    std::vector<PolyDesc> d;
+    for (int p = 0; p < 3; ++p)
+      for (int i = 0; i < nl; ++i) {
+        uint64_t* x = V + ((size_t)p * nl + i) * n;
+        d.push_back(pd(x, x, i, c->log_n));
+      }
+    ntt_descs(c, d, NTT_FWD);
+    uint64_t* c0 = cts[t].data;
+    uint64_t* c1 = cts[t].data + (size_t)nl * n;
+    launch_ew(c, EW_MULADD, T, V, K->pk, E0, nl, lim);
+    launch_ew(c, EW_ADD, c0, c0, T, nullptr, nl, lim);
+    launch_ew(c, EW_MULADD, T, V, K->pk + (size_t)c->n_q * n, E1, nl, lim);
+    launch_ew(c, EW_ADD, c1, c1, T, nullptr, nl, lim);
+  }
+  return hipGetLastError() == hipSuccess ? BLB_OK : BLB_EDEVICE;
+}
+
 int blb_mask_to_share(blb_ctx* c, blb_ct* cts, int n_ct, uint64_t seed, int target_level, uint64_t* share_dev) {
   if (!c || !cts || n_ct < 1 || !share_dev) return BLB_EINVAL;
   for (int t = 0; t < n_ct; ++t) {
@@ -1349,8 +1426,9 @@ int blb_cc_rotations(const blb_ctx* c, int n_heads, int L, int32_t* steps, int c
   return (int)u.size();
 }
 
-int blb_plan_matmul_cc(blb_ctx* c, int n_heads, int L, int d_head, int level, blb_plan** out) {
-  if (!c || !out || n_heads < 1 || L < 1 || d_head < 1 || level < 3 || level >= c->n_q) return BLB_EINVAL;
+int blb_plan_matmul_cc(blb_ctx* c, int n_heads, int L, int d_head, int level, int32_t b_prerotated, blb_plan** out) {
+  if (!c || !out || n_heads < 1 || L < 1 || d_head < 1 || (b_prerotated != 0 && b_prerotated != 1)) return BLB_EINVAL;
+  if (level < (b_prerotated ? 3 : 4) || level >= c->n_q) return BLB_EINVAL;
   *out = nullptr;
   const int S = c->n / 2, n = c->n, lp = 1 << ceil_log2(L);
   if (lp > S) return BLB_EINVAL;
@@ -1361,6 +1439,7 @@ int blb_plan_matmul_cc(blb_ctx* c, int n_heads, int L, int d_head, int level, bl
   P->ctx = c;
   P->kind = 2;
   P->level = level;
+  P->hom1 = b_prerotated ? 0 : 1;
   P->heads = n_heads;
   P->L = L;
   P->d = d_head;
@@ -1384,17 +1463,42 @@ int blb_plan_matmul_cc(blb_ctx* c, int n_heads, int L, int d_head, int level, bl
     g.n_out = lp / g.c;
     g.ct0 = ct0;
     g.out0 = out0;
-    g.m_ge = g.m_lt = nullptr;
+    g.m_ge = g.m_lt = g.m_s1 = nullptr;
     ct0 += g.n_ct;
     out0 += g.n_out;
     P->groups.push_back(g);
   }
   P->n_ct = ct0;
   P->n_out = out0;
+  int rc = BLB_OK;
+  // step 1 on the server: masks at the input level, scale q_level / 2^10
+  if (P->hom1) {
+    for (CcGroup& g : P->groups) {
+      const size_t b = (size_t)2 * g.c * (level + 1) * n * 8;
+      if ((rc = dalloc(c, (void**)&g.m_s1, b))) {
+        blb_plan_destroy(P);
+        return rc;
+      }
+      P->extra.push_back(g.m_s1);
+      P->extra_bytes.push_back(b);
+      std::vector<double> v((size_t)2 * g.c * S, 0.0);
+      for (int j = 0; j < S; ++j) {
+        const int i = j % lp, cls = (j / lp) / g.H;
+        if (cls == 0) v[j] = 1.0;
+        else if (i < lp - cls) v[(size_t)cls * S + j] = 1.0;
+        else v[(size_t)(g.c + cls) * S + j] = 1.0;
+      }
+      if ((rc = encode_vectors_ntt(c, v, 2 * g.c, (double)c->mod[level] / BLB_NOISE_BOOST, level, g.m_s1))) {
+        blb_plan_destroy(P);
+        return rc;
+      }
+    }
+    level -= 1;  // steps 2-3 start one level down
+  }
   const int nl = level + 1, nl3 = level - 1;
   // step-2 masks at `level`, scale q_level * 2^10: M^lo_t (slot mod L' < L'-t), M^hi_t
   P->bytes = (size_t)2 * lp * nl * n * 8;
-  int rc = dalloc(c, (void**)&P->pt, P->bytes);
+  rc = dalloc(c, (void**)&P->pt, P->bytes);
   if (rc) {
     delete P;
     return rc;
@@ -1459,10 +1563,10 @@ int blb_plan_cc_info(const blb_plan* P, int32_t* info, int cap) {
 int blb_matmul_cc(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct* A, const blb_ct* Bp, int n_ct, blb_ct* Cd, int n_out) {
   if (!c || !K || !P || !A || !Bp || !Cd || P->kind != 2) return BLB_EINVAL;
   if (n_ct != P->n_ct || n_out != P->n_out) return BLB_EINVAL;
-  const int level = P->level, n = c->n, lp = P->Lp;
+  const int level_in = P->level, level = P->level - P->hom1, n = c->n, lp = P->Lp;
   for (int a = 0; a < n_ct; ++a) {
     if (check_ct(c, &A[a]) || check_ct(c, &Bp[a]) || A[a].degree != 1 || Bp[a].degree != 1) return BLB_EINVAL;
-    if (A[a].level != level || Bp[a].level != level) return BLB_ELEVEL;
+    if (A[a].level != level_in || Bp[a].level != level_in) return BLB_ELEVEL;
     if (fabs(A[a].scale / A[0].scale - 1.0) > 1e-9 || fabs(Bp[a].scale / Bp[0].scale - 1.0) > 1e-9) return BLB_ESCALE;
   }
   for (int o = 0; o < n_out; ++o)
@@ -1477,19 +1581,77 @@ int blb_matmul_cc(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct
   for (const CcGroup& g : P->groups)
     for (int tau = 1; tau < g.c; ++tau)
       if (!find_key(K, galois_left(c, -(int64_t)tau * g.H * lp))) return BLB_ENOKEY;
-  const int nl = level + 1, nl2 = level, nl3 = level - 1;
+  const int nl = level + 1, nl2 = level, nl3 = level - 1, nlA = level_in + 1;
   const size_t w1 = (size_t)2 * nl * n, w2 = (size_t)2 * nl2 * n, w3 = (size_t)2 * nl3 * n;
   const int TC = 16;  // t values per chunk
   int rc = BLB_OK;
+  double b_scale = Bp[0].scale;
   for (const CcGroup& g : P->groups) {
     const int m = g.n_ct;
     Tmp tmp(c);
+    // step 1 on the server: B'_a = Rescale(sum of the masked rotations of 2^10 B_a)
+    std::vector<const uint64_t*> bsrc;
+    for (int a = 0; a < m; ++a) bsrc.push_back(Bp[g.ct0 + a].data);
+    if (P->hom1) {
+      const int nl0 = level_in + 1;
+      const size_t w0 = (size_t)2 * nl0 * n;
+      uint64_t* B0 = tmp.get<uint64_t>((size_t)m * w0);
+      uint64_t* X0 = tmp.get<uint64_t>(ks_modup_words(c, level_in, m));
+      uint64_t* R0 = tmp.get<uint64_t>((size_t)2 * (g.c - 1) * m * w0 + 1);
+      uint64_t* S0 = tmp.get<uint64_t>((size_t)m * w0);
+      uint64_t* Bq = tmp.get<uint64_t>((size_t)m * w1);
+      if (tmp.failed) return BLB_ENOMEM;
+      {
+        const uint64_t* const* bin_dev = upload_vec(c, bsrc);
+        if (!bin_dev) return BLB_EDEVICE;
+        launch_scale_cts(c, bin_dev, B0, m, nl0, BLB_NOISE_BOOST);
+      }
+      std::vector<const uint64_t*> srcs0;
+      for (int a = 0; a < m; ++a) srcs0.push_back(B0 + (size_t)a * w0 + (size_t)nl0 * n);
+      if ((rc = ks_modup(c, level_in, srcs0, X0))) return rc;
+      std::vector<KsReq> reqs0;
+      std::vector<CcTerm> terms0;
+      std::vector<int> off0{0};
+      std::vector<uint64_t*> outs0;
+      for (int a = 0; a < m; ++a) {
+        const uint64_t* b = B0 + (size_t)a * w0;
+        terms0.push_back(CcTerm{b, g.m_s1});
+        for (int kap = 1; kap < g.c; ++kap) {
+          uint64_t* rl = R0 + ((size_t)(2 * (kap - 1)) * m + a) * w0;
+          uint64_t* rr = R0 + ((size_t)(2 * (kap - 1) + 1) * m + a) * w0;
+          const uint32_t gl = galois_left(c, kap), gr = galois_left(c, -(int64_t)(lp - kap));
+          reqs0.push_back(KsReq{a, kl[kap], gl, rl, b, gl, nullptr});
+          reqs0.push_back(KsReq{a, kr[kap], gr, rr, b, gr, nullptr});
+          terms0.push_back(CcTerm{rl, g.m_s1 + (size_t)kap * nl0 * n});
+          terms0.push_back(CcTerm{rr, g.m_s1 + (size_t)(g.c + kap) * nl0 * n});
+        }
+        off0.push_back((int)terms0.size());
+        outs0.push_back(S0 + (size_t)a * w0);
+      }
+      if (!reqs0.empty() && (rc = ks_apply(c, level_in, srcs0, X0, reqs0))) return rc;
+      const CcTerm* terms_dev = upload_vec(c, terms0);
+      const int* off_dev = upload_vec(c, off0);
+      uint64_t* const* outs_dev = (uint64_t* const*)upload(c, outs0.data(), outs0.size() * sizeof(uint64_t*));
+      if (!terms_dev || !off_dev || !outs_dev) return BLB_EDEVICE;
+      {
+        Span sp(c, BLB_T_EW, (double)m * w0);
+        c->counters[2] += (int64_t)terms0.size();
+        launch_masked_acc(c, terms_dev, off_dev, outs_dev, m, nl0, false);
+      }
+      std::vector<const uint64_t*> rin;
+      std::vector<uint64_t*> rout;
+      for (int a = 0; a < m; ++a) {
+        rin.push_back(S0 + (size_t)a * w0);
+        rout.push_back(Bq + (size_t)a * w1);
+        bsrc[a] = Bq + (size_t)a * w1;
+      }
+      if ((rc = rescale_batch(c, level_in, 2, rin, rout))) return rc;
+    }
     // noise boost: Bs_a = 2^10 B'_a before the inner rotations (step-3 masks are at q/2^10)
     uint64_t* Bs = tmp.get<uint64_t>((size_t)m * w1);
     if (!Bs) return BLB_ENOMEM;
     {
-      std::vector<const uint64_t*> bin;
-      for (int a = 0; a < m; ++a) bin.push_back(Bp[g.ct0 + a].data);
+      std::vector<const uint64_t*> bin = bsrc;
       const uint64_t* const* bin_dev = upload_vec(c, bin);
       if (!bin_dev) return BLB_EDEVICE;
       launch_scale_cts(c, bin_dev, Bs, m, nl, BLB_NOISE_BOOST);
@@ -1564,7 +1726,7 @@ int blb_matmul_cc(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct
         Span sp(c, BLB_T_CC_TENSOR, (double)nt * nl2 * n);
         c->counters[3] += (int64_t)nt * m;
         c->counters[4] += nt;
-        launch_tensor_sum(c, a_dev, r_dev, T3, nt, m, nl, nl2);
+        launch_tensor_sum(c, a_dev, r_dev, T3, nt, m, nlA, nl2);
       }
       std::vector<const uint64_t*> rs;
       std::vector<KsReq> rr;
@@ -1631,7 +1793,8 @@ int blb_matmul_cc(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct
     }
     if ((rc = rescale_batch(c, level - 2, 2, oin, oout))) return rc;
   }
-  const double out_scale = A[0].scale * Bp[0].scale * 1024.0 / (double)c->mod[level - 1];
+  if (P->hom1) b_scale = b_scale * BLB_NOISE_BOOST * ((double)c->mod[level_in] / BLB_NOISE_BOOST) / (double)c->mod[level_in];
+  const double out_scale = A[0].scale * b_scale * 1024.0 / (double)c->mod[level - 1];
   for (int o = 0; o < n_out; ++o) {
     Cd[o].level = level - 3;
     Cd[o].degree = 1;

@@ -192,6 +192,7 @@ struct blb_keys {
   blb_ctx* ctx;
   uint64_t seed;
   uint64_t* s_ntt;  // secret in evaluation form for all moduli [modulus][N]
+  uint64_t* pk = nullptr;  // public key (-a s + e, a), evaluation form [2][n_q][N]
   std::vector<SwKey> keys;
   size_t bytes;
 };
@@ -206,12 +207,15 @@ struct CcGroup {
   int out0;   // first output ciphertext of the group
   uint64_t* m_ge;  // [c][nl3][N] masks M^{>=tau} at level-2, scale q_{level-2}
   uint64_t* m_lt;  // [c][nl3][N] masks M^{<tau}
+  uint64_t* m_s1;  // step 1 on the server: [2c][level+1][N] masks M^0, M^1_kappa (index kappa),
+                   // M^2_kappa (index c + kappa) at the input level, scale q_level / 2^10
 };
 
 struct blb_plan {
   blb_ctx* ctx;
   int kind;  // 1 = matmul_cp, 2 = matmul_cc
-  int level;
+  int level;  // input level
+  int hom1 = 0;  // matmul_cc: step 1 (row pre-rotation of B) runs on the server
   CpGeom g;
   uint64_t* pt;  // matmul_cp: [(b, j)][(a, i)][limb][N] evaluation-form plaintexts
                  // matmul_cc: [2][L'][limb][N] step-2 masks M^lo_t, M^hi_t (level, scale q_level 2^10)
@@ -229,6 +233,7 @@ struct blb_plan {
 struct PolyDesc;
 void launch_sample_uniform(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag);
 void launch_sample_int(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag, bool gaussian);
+void launch_sample_flood(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag, int bits);
 void upload_cdt(const uint64_t* table20);
 
 enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_MUL = 2, EW_NEG = 3, EW_COPY = 4, EW_MULADD = 5 };

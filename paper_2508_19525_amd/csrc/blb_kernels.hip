@@ -44,25 +44,30 @@ __global__ void k_sample_uniform(uint64_t* out, int n, ModMap map, ModTable mt, 
   out[(size_t)limb * n + k] = d2u(u128_mod(w, mt.m[m].q, mt.m[m].qinv));
 }
 
-// integer samples (ternary secret / Gaussian error), reduced into every limb of the map
+// integer samples reduced into every limb of the map.  mode 0: ternary (w0 mod 3) - 1;
+// mode 1: Gaussian (CDT); mode F in [32, 48]: uniform integer in [-2^F, 2^F] (the 128-bit
+// block mod 2^(F+1) + 1, minus 2^F; |v| <= 2^48 stays below every modulus)
 __constant__ uint64_t c_cdt[20];
 __global__ void k_sample_int(uint64_t* out, int n, int n_limbs, ModMap map, ModTable mt, uint32_t k0, uint32_t k1, uint32_t obj,
-                             uint32_t tag, int gaussian) {
+                             uint32_t tag, int mode) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const U4 w = philox10((uint32_t)k, LIMB_INTEGER, obj, tag, k0, k1);
-  int v;
-  if (gaussian) {
+  double v;
+  if (mode == 1) {
     const uint64_t r = ((((uint64_t)w.y) << 32) | w.x) >> 1;
     int x = 0;
     while (x < 19 && r >= c_cdt[x]) ++x;
     v = (w.z & 1u) ? -x : x;
+  } else if (mode == 0) {
+    v = (double)((int)(w.x % 3u) - 1);
   } else {
-    v = (int)(w.x % 3u) - 1;
+    const double m = (double)((2ull << mode) + 1ull);
+    v = u128_mod(w, m, 1.0 / m) - (double)(1ull << mode);
   }
   for (int l = 0; l < n_limbs; ++l) {
     const double q = mt.m[map.idx[l % map.len]].q;
-    out[(size_t)l * n + k] = d2u(v < 0 ? q + (double)v : (double)v);
+    out[(size_t)l * n + k] = d2u(v < 0 ? q + v : v);
   }
 }
 
@@ -75,6 +80,10 @@ void launch_sample_uniform(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, u
 void launch_sample_int(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag, bool gaussian) {
   k_sample_int<<<(c->n + 255) / 256, 256, 0, c->stream>>>(out, c->n, n_limbs, map, c->mt, (uint32_t)seed, (uint32_t)(seed >> 32), obj,
                                                           tag, gaussian ? 1 : 0);
+}
+void launch_sample_flood(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag, int bits) {
+  k_sample_int<<<(c->n + 255) / 256, 256, 0, c->stream>>>(out, c->n, n_limbs, map, c->mt, (uint32_t)seed, (uint32_t)(seed >> 32), obj,
+                                                          tag, bits);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -1,9 +1,10 @@
 // Batched negacyclic NTT / inverse NTT for gfx950 on FP64 lanes.
 //
-// One workgroup transforms one N-word polynomial (N = 4096 / 8192 / 16384) held in LDS
-// (N doubles + 1/16 padding, 136 KiB at N = 16384 against 160 KiB per CU).  Each of the N/16
-// work-items keeps 16 values in registers and runs up to four radix-2 stages on them per
-// pass, so a transform costs ceil(log2 N / 4) LDS round trips.  The forward transform is the
+// One workgroup transforms one N-word polynomial (N = 4096 / 8192 / 16384), exchanging
+// values through LDS (N doubles + 1/16 padding, 136 KiB at N = 16384 against 160 KiB per
+// CU).  Each of the N/16 work-items keeps 16 values in registers and runs up to four radix-2
+// stages on them per pass; the first pass reads global memory and the last writes it, so a
+// transform costs ceil(log2 N / 4) - 1 LDS round trips.  The forward transform is the
 // Cooley-Tukey ordering with twiddles psi^brv(m+i) (natural in, bit-reversed out, value j is
 // the evaluation at psi^(2 brv(j) + 1)); the inverse is the Gentleman-Sande ordering with
 // psi^-brv(m+i) followed by N^-1.  Polys are addressed through a descriptor table so a
@@ -11,6 +12,7 @@
 #include "blb_internal.h"
 #include "blb_kernels.h"
 #include <algorithm>
+#include <type_traits>
 
 namespace {
 
@@ -18,128 +20,165 @@ constexpr int kPerThread = 16;
 
 __device__ __forceinline__ int pad_idx(int j) { return j + (j >> 4); }
 
-// One pass of R_LOG radix-2 stages, starting at global stage s0.  FWD selects Cooley-Tukey
-// (stages in increasing order) or Gentleman-Sande (decreasing order, inverse twiddles).
-template <int LOGN, int R_LOG, bool FWD>
-__device__ __forceinline__ void ntt_pass(double* lds, const double* __restrict__ tw, int s0, double q, double qi) {
-  constexpr int N = 1 << LOGN;
-  constexpr int T = N / kPerThread;
-  constexpr int GS = 1 << R_LOG;
-  constexpr int GPT = kPerThread / GS;
-  const int tid = threadIdx.x;
-  const int t_last = N >> (s0 + R_LOG);
-  double x[kPerThread];
-  int his[GPT];
-#pragma unroll
-  for (int h = 0; h < GPT; ++h) {
+// One pass of R_LOG radix-2 stages starting at global stage S0.  Work-item `tid` holds
+// kPerThread values in registers: GPT groups of GS = 2^R_LOG values each, group h being the
+// butterfly group g = tid + h T (T = N / kPerThread) whose members sit TL = N >> (S0 + R_LOG)
+// words apart.
+template <int LOGN, int S0, int R_LOG>
+struct Pass {
+  static constexpr int N = 1 << LOGN;
+  static constexpr int T = N / kPerThread;
+  static constexpr int GS = 1 << R_LOG;
+  static constexpr int GPT = kPerThread / GS;
+  static constexpr int TL = N >> (S0 + R_LOG);
+  static_assert(S0 + R_LOG <= LOGN && GS <= kPerThread, "pass shape");
+
+  // coefficient index of register slot i (= h GS + k)
+  __device__ static __forceinline__ int idx(int tid, int i) {
+    const int h = i / GS, k = i % GS;
     const int g = tid + h * T;
-    const int lo = g % t_last, hi = g / t_last;
-    his[h] = hi;
-    const int base = hi * (t_last << R_LOG) + lo;
-#pragma unroll
-    for (int k = 0; k < GS; ++k) x[h * GS + k] = lds[pad_idx(base + k * t_last)];
+    return (g / TL) * (TL << R_LOG) + (g % TL) + k * TL;
   }
+
+  // FWD: Cooley-Tukey stages in increasing order; else Gentleman-Sande in decreasing order.
+  template <bool FWD>
+  __device__ static __forceinline__ void run(double (&x)[kPerThread], const double* __restrict__ tw, double q, double qi, int tid) {
 #pragma unroll
-  for (int uu = 0; uu < R_LOG; ++uu) {
-    const int u = FWD ? uu : (R_LOG - 1 - uu);
-    const int t_loc = GS >> (u + 1);
+    for (int uu = 0; uu < R_LOG; ++uu) {
+      const int u = FWD ? uu : (R_LOG - 1 - uu);
+      const int t_loc = GS >> (u + 1);
 #pragma unroll
-    for (int h = 0; h < GPT; ++h) {
+      for (int h = 0; h < GPT; ++h) {
+        const int hi = (tid + h * T) / TL;
 #pragma unroll
-      for (int k = 0; k < GS; ++k) {
-        if (k & t_loc) continue;
-        const int widx = (1 << (s0 + u)) + (his[h] << u) + (k >> (R_LOG - u));
-        const double w = tw[widx];
-        double& a = x[h * GS + k];
-        double& b = x[h * GS + k + t_loc];
-        // lazy reduction: values are brought back to |x| <= q/2 only after every second stage
-        // (and at the end of the pass); in between they stay below ~3.1 q < 2^52, where every
-        // FP64 operation on them is exact and mulmod_s keeps |result| < 1.3 q.
-        const bool red = (u & 1) || (u == R_LOG - 1);
-        if (FWD) {
-          const double v = mulmod_s(b, w, q, qi);
-          const double s = a + v, d = a - v;
-          a = red ? reduce_s(s, q, qi) : s;
-          b = red ? reduce_s(d, q, qi) : d;
-        } else {
-          const double s = a + b, d = a - b;
-          a = red ? reduce_s(s, q, qi) : s;
-          b = mulmod_s(d, w, q, qi);
+        for (int k = 0; k < GS; ++k) {
+          if (k & t_loc) continue;
+          const int widx = (1 << (S0 + u)) + (hi << u) + (k >> (R_LOG - u));
+          const double w = tw[widx];
+          double& a = x[h * GS + k];
+          double& b = x[h * GS + k + t_loc];
+          // lazy reduction: values are brought back to |x| <= q/2 only after every second
+          // stage (and at the end of the pass); in between they stay below ~3.1 q < 2^52,
+          // where every FP64 operation on them is exact and mulmod_s keeps |result| < 1.3 q.
+          const bool red = (u & 1) || (u == R_LOG - 1);
+          if (FWD) {
+            const double v = mulmod_s(b, w, q, qi);
+            const double sum = a + v, dif = a - v;
+            a = red ? reduce_s(sum, q, qi) : sum;
+            b = red ? reduce_s(dif, q, qi) : dif;
+          } else {
+            const double sum = a + b, dif = a - b;
+            a = red ? reduce_s(sum, q, qi) : sum;
+            b = mulmod_s(dif, w, q, qi);
+          }
         }
       }
     }
   }
+};
+
+// Move the register values from the layout of pass PA to the layout of pass PB through LDS.
+// The leading barrier keeps the writes behind every read of the previous exchange (also of
+// the previous polynomial in the persistent kernel).
+template <class PA, class PB>
+__device__ __forceinline__ void relayout(double* lds, double (&x)[kPerThread], int tid) {
   __syncthreads();
 #pragma unroll
-  for (int h = 0; h < GPT; ++h) {
-    const int base = his[h] * (t_last << R_LOG) + ((tid + h * T) % t_last);
-#pragma unroll
-    for (int k = 0; k < GS; ++k) lds[pad_idx(base + k * t_last)] = x[h * GS + k];
-  }
+  for (int i = 0; i < kPerThread; ++i) lds[pad_idx(PA::idx(tid, i))] = x[i];
   __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) x[i] = lds[pad_idx(PB::idx(tid, i))];
 }
 
+// Pass schedule: three passes of four stages, then the remaining LOGN - 12 stages (forward
+// order).  The first pass reads its operands straight from global memory and the last pass
+// writes straight to global memory, so a transform makes (passes - 1) LDS round trips.
+template <int LOGN>
+struct Sched {
+  static constexpr int REM = LOGN - 12;
+  using P0 = Pass<LOGN, 0, 4>;
+  using P1 = Pass<LOGN, 4, 4>;
+  using P2 = Pass<LOGN, 8, 4>;
+  using P3 = Pass<LOGN, 12, (REM > 0 ? REM : 1)>;
+  using Tail = std::conditional_t<(REM > 0), P3, P2>;  // forward-last / inverse-first pass
+};
 template <int LOGN, bool FWD>
-__device__ __forceinline__ void ntt_all_passes(double* lds, const double* tw, double q, double qi) {
-  // passes of 4 stages, the remainder last (forward order); the inverse runs them reversed
-  constexpr int REM = LOGN - 12;
-  if (FWD) {
-    ntt_pass<LOGN, 4, true>(lds, tw, 0, q, qi);
-    ntt_pass<LOGN, 4, true>(lds, tw, 4, q, qi);
-    ntt_pass<LOGN, 4, true>(lds, tw, 8, q, qi);
-    if constexpr (REM > 0) ntt_pass<LOGN, (REM > 0 ? REM : 1), true>(lds, tw, 12, q, qi);
+using FirstPass = std::conditional_t<FWD, typename Sched<LOGN>::P0, typename Sched<LOGN>::Tail>;
+template <int LOGN, bool FWD>
+using LastPass = std::conditional_t<FWD, typename Sched<LOGN>::Tail, typename Sched<LOGN>::P0>;
+
+// x holds the first pass's operands on entry and the last pass's results on exit.
+template <int LOGN, bool FWD>
+__device__ __forceinline__ void ntt_core(double* lds, double (&x)[kPerThread], const double* tw, double q, double qi, int tid) {
+  using S = Sched<LOGN>;
+  using P0 = typename S::P0;
+  using P1 = typename S::P1;
+  using P2 = typename S::P2;
+  using P3 = typename S::P3;
+  if constexpr (FWD) {
+    P0::template run<true>(x, tw, q, qi, tid);
+    relayout<P0, P1>(lds, x, tid);
+    P1::template run<true>(x, tw, q, qi, tid);
+    relayout<P1, P2>(lds, x, tid);
+    P2::template run<true>(x, tw, q, qi, tid);
+    if constexpr (S::REM > 0) {
+      relayout<P2, P3>(lds, x, tid);
+      P3::template run<true>(x, tw, q, qi, tid);
+    }
   } else {
-    if constexpr (REM > 0) ntt_pass<LOGN, (REM > 0 ? REM : 1), false>(lds, tw, 12, q, qi);
-    ntt_pass<LOGN, 4, false>(lds, tw, 8, q, qi);
-    ntt_pass<LOGN, 4, false>(lds, tw, 4, q, qi);
-    ntt_pass<LOGN, 4, false>(lds, tw, 0, q, qi);
+    if constexpr (S::REM > 0) {
+      P3::template run<false>(x, tw, q, qi, tid);
+      relayout<P3, P2>(lds, x, tid);
+    }
+    P2::template run<false>(x, tw, q, qi, tid);
+    relayout<P2, P1>(lds, x, tid);
+    P1::template run<false>(x, tw, q, qi, tid);
+    relayout<P1, P0>(lds, x, tid);
+    P0::template run<false>(x, tw, q, qi, tid);
   }
 }
 
-// Generic transform: load (LoadOp) -> passes -> store (StoreOp).  The load/store functors
-// receive the descriptor, coefficient index and value.
+template <int LOGN, bool FWD, class LoadOp>
+__device__ __forceinline__ void ntt_load(double (&x)[kPerThread], const PolyDesc& d, const LoadOp& ld, double q, double qi, int tid) {
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) x[i] = ld(d, FirstPass<LOGN, FWD>::idx(tid, i), q, qi);
+}
+
+// canonical results of the last pass to global memory (the inverse applies N^-1 here; the
+// lazy passes leave |x| below ~2.5 q, which canon_full brings into [0, q))
+template <int LOGN, bool FWD, class StoreOp>
+__device__ __forceinline__ void ntt_store(double (&x)[kPerThread], const PolyDesc& d, const StoreOp& st, double q, double qi, double ninv, int tid) {
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    const int j = LastPass<LOGN, FWD>::idx(tid, i);
+    const double v = FWD ? canon(x[i], q) : canon_full(mulmod_s(x[i], ninv, q, qi), q, qi);
+    st(d, j, v, q, qi);
+  }
+}
+
+// One workgroup per polynomial.
 template <int LOGN, bool FWD, class LoadOp, class StoreOp>
 __global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt(const PolyDesc* __restrict__ descs, const double* __restrict__ tw_all,
                                                                 ModTable mt, LoadOp ld, StoreOp st) {
   constexpr int N = 1 << LOGN;
-  constexpr int T = N / kPerThread;
   __shared__ double lds[N + N / 16];
   const PolyDesc d = descs[blockIdx.x];
   const double q = mt.m[d.mod].q, qi = mt.m[d.mod].qinv;
-  const double* tw = tw_all + (size_t)d.mod * N;
   const int tid = threadIdx.x;
-#pragma unroll
-  for (int i = 0; i < kPerThread; ++i) {
-    const int j = tid + i * T;
-    lds[pad_idx(j)] = ld(d, j, q, qi);
-  }
-  __syncthreads();
-  ntt_all_passes<LOGN, FWD>(lds, tw, q, qi);
-  if (!FWD) {
-    const double ninv = mt.m[d.mod].ninv;
-#pragma unroll
-    for (int i = 0; i < kPerThread; ++i) {
-      const int j = tid + i * T;
-      st(d, j, canon_full(mulmod_s(lds[pad_idx(j)], ninv, q, qi), q, qi), q, qi);
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < kPerThread; ++i) {
-      const int j = tid + i * T;
-      st(d, j, canon(lds[pad_idx(j)], q), q, qi);
-    }
-  }
+  double x[kPerThread];
+  ntt_load<LOGN, FWD>(x, d, ld, q, qi, tid);
+  ntt_core<LOGN, FWD>(lds, x, tw_all + (size_t)d.mod * N, q, qi, tid);
+  ntt_store<LOGN, FWD>(x, d, st, q, qi, mt.m[d.mod].ninv, tid);
 }
 
 // Persistent, software-pipelined variant: a grid of resident workgroups walks the descriptor
-// list with a grid stride; the next polynomial's values are loaded into registers while the
-// current one is transformed in LDS, hiding the global-memory latency that a one-shot
-// workgroup (one per CU at N = 16384) exposes.
+// list with a grid stride; the next polynomial's operands are loaded into registers while the
+// current one is transformed, hiding the global-memory latency that a one-shot workgroup (one
+// per CU at N = 16384) exposes.
 template <int LOGN, bool FWD, class LoadOp, class StoreOp>
 __global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt_pipe(const PolyDesc* __restrict__ descs, const double* __restrict__ tw_all,
                                                                      ModTable mt, LoadOp ld, StoreOp st, int count) {
   constexpr int N = 1 << LOGN;
-  constexpr int T = N / kPerThread;
   __shared__ double lds[N + N / 16];
   const int tid = threadIdx.x;
   int p = blockIdx.x;
@@ -147,40 +186,21 @@ __global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt_pipe(const Pol
   double nx[kPerThread];
   {
     const PolyDesc d = descs[p];
-    const double q = mt.m[d.mod].q, qi = mt.m[d.mod].qinv;
-#pragma unroll
-    for (int i = 0; i < kPerThread; ++i) nx[i] = ld(d, tid + i * T, q, qi);
+    ntt_load<LOGN, FWD>(nx, d, ld, mt.m[d.mod].q, mt.m[d.mod].qinv, tid);
   }
   for (;;) {
     const PolyDesc d = descs[p];
     const double q = mt.m[d.mod].q, qi = mt.m[d.mod].qinv;
-    const double* tw = tw_all + (size_t)d.mod * N;
+    double x[kPerThread];
 #pragma unroll
-    for (int i = 0; i < kPerThread; ++i) lds[pad_idx(tid + i * T)] = nx[i];
-    __syncthreads();
+    for (int i = 0; i < kPerThread; ++i) x[i] = nx[i];
     const int pn = p + gridDim.x;
-    if (pn < count) {  // prefetch the next polynomial while this one is transformed
+    if (pn < count) {
       const PolyDesc dn = descs[pn];
-      const double qn = mt.m[dn.mod].q, qin = mt.m[dn.mod].qinv;
-#pragma unroll
-      for (int i = 0; i < kPerThread; ++i) nx[i] = ld(dn, tid + i * T, qn, qin);
+      ntt_load<LOGN, FWD>(nx, dn, ld, mt.m[dn.mod].q, mt.m[dn.mod].qinv, tid);
     }
-    ntt_all_passes<LOGN, FWD>(lds, tw, q, qi);
-    if (!FWD) {
-      const double ninv = mt.m[d.mod].ninv;
-#pragma unroll
-      for (int i = 0; i < kPerThread; ++i) {
-        const int j = tid + i * T;
-        st(d, j, canon_full(mulmod_s(lds[pad_idx(j)], ninv, q, qi), q, qi), q, qi);
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < kPerThread; ++i) {
-        const int j = tid + i * T;
-        st(d, j, canon(lds[pad_idx(j)], q), q, qi);
-      }
-    }
-    __syncthreads();  // LDS is rewritten by the next iteration
+    ntt_core<LOGN, FWD>(lds, x, tw_all + (size_t)d.mod * N, q, qi, tid);
+    ntt_store<LOGN, FWD>(x, d, st, q, qi, mt.m[d.mod].ninv, tid);
     p = pn;
     if (p >= count) break;
   }

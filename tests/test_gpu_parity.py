@@ -27,7 +27,7 @@ class Ctx:
     def __init__(self, B, orc, log_n, n_q, n_sp, dnum):
         self.B, self.orc = B, orc
         self.n = 1 << log_n
-        self.n_q = n_q
+        self.n_q, self.n_sp = n_q, n_sp
         self.h = B.blb_ctx_create(log_n, n_q, n_sp, dnum, 0, torch.cuda.current_stream().cuda_stream)
         self.o = orc.Context(log_n, n_q, n_sp, dnum)
         self.keep = []
@@ -244,10 +244,43 @@ def test_mask_to_share_matches_oracle(request, name):
             assert np.array_equal(sh[t], want_share)
 
 
+@pytest.mark.parametrize("name", ["c1", "c2s"])
+def test_rerandomize_matches_oracle(request, name):
+    """Public-key re-randomisation with flooding (object id = position in the list), word for
+    word, at two levels and two flooding widths; then mask-to-share on the result."""
+    c = request.getfixturevalue(name)
+    rng = np.random.default_rng(6)
+    keys_o = c.orc.Keys(c.o, 43)
+    keys_g = c.B.blb_keygen(c.h, 43, [])
+    level = c.n_q - 1
+    for lvl, bits in ((level, 40), (0, 32)):
+        words = [keys_o.encrypt(c.o.encode_rns(rng.normal(0, 1, c.n // 2), 2.0 ** 30, lvl), lvl, 7, t) for t in range(3)]
+        cts = [c.import_ct(w, lvl) for w in words]
+        c.B.blb_rerandomize(c.h, keys_g, cts, 555, bits)
+        for t in range(3):
+            assert np.array_equal(c.export(cts[t]), keys_o.rerandomize(words[t], lvl, 555, t, bits)), f"level {lvl} ct {t}"
+    with pytest.raises(c.B.BlbError):
+        c.B.blb_rerandomize(c.h, keys_g, cts, 1, 49)
+    c.B.blb_keys_destroy(keys_g)
+
+
 # --------------------------------------------------------------------------------------
 # matmul_cc
 # --------------------------------------------------------------------------------------
-def _cc_case(c, heads, L, d, seed, outputs=None):
+def _unrotated_b(mats, H, L, d, a, slots):
+    """B operand without the client-side row rotation: slot i + L'(h + H kappa) <- B_h{a c + kappa, i}"""
+    lp = 1 << int(np.ceil(np.log2(L)))
+    cc = slots // (lp * H)
+    v = np.zeros(slots)
+    for h in range(H):
+        for kap in range(cc):
+            k = a * cc + kap
+            if k < d:
+                v[lp * (h + H * kap): lp * (h + H * kap) + L] = mats[h][k, :]
+    return v
+
+
+def _cc_case(c, heads, L, d, seed, outputs=None, prerot=True):
     from paper_2508_19525_amd import workloads as wl
     B, orc = c.B, c.orc
     rng = np.random.default_rng(seed)
@@ -258,7 +291,7 @@ def _cc_case(c, heads, L, d, seed, outputs=None):
     gal = sorted({c.o.galois_elt(s) for s in steps})
     keys_o = orc.Keys(c.o, 51, gal)
     keys_g = B.blb_keygen(c.h, 51, steps)
-    plan = B.blb_plan_matmul_cc(c.h, heads, L, d, level)
+    plan = B.blb_plan_matmul_cc(c.h, heads, L, d, level, b_prerotated=prerot)
     info = B.blb_plan_cc_info(plan)
     A_g, B_g, want, h0 = [], [], [], 0
     for gi, grp in enumerate(info["groups"]):
@@ -268,8 +301,9 @@ def _cc_case(c, heads, L, d, seed, outputs=None):
         assert (og["c"], og["n_ct"], og["n_out"]) == (grp["c"], grp["n_ct"], grp["n_out"])
         Aw = np.stack([keys_o.encrypt(c.o.encode_rns(c.o.pack_mhp(Q[h0:h0 + H], H, L, d, a, "A"), scale, level), level, 60 + gi, a)
                        for a in range(og["n_ct"])])
-        Bw = np.stack([keys_o.encrypt(c.o.encode_rns(c.o.pack_mhp(Kt[h0:h0 + H], H, L, d, a, "Bp"), scale, level), level, 70 + gi, a)
-                       for a in range(og["n_ct"])])
+        bvec = [c.o.pack_mhp(Kt[h0:h0 + H], H, L, d, a, "Bp") if prerot else _unrotated_b(Kt[h0:h0 + H], H, L, d, a, c.n // 2)
+                for a in range(og["n_ct"])]
+        Bw = np.stack([keys_o.encrypt(c.o.encode_rns(v, scale, level), level, 70 + gi, a) for a, v in enumerate(bvec)])
         # the client-side packing of the library's helper module agrees with the oracle's
         assert np.array_equal(wl.pack_mhp(Q[h0:h0 + H], H, L, d, 0, "A", c.n // 2), c.o.pack_mhp(Q[h0:h0 + H], H, L, d, 0, "A"))
         assert np.array_equal(wl.pack_mhp(Kt[h0:h0 + H], H, L, d, 0, "Bp", c.n // 2), c.o.pack_mhp(Kt[h0:h0 + H], H, L, d, 0, "Bp"))
@@ -281,19 +315,31 @@ def _cc_case(c, heads, L, d, seed, outputs=None):
             y.scale = scale
             B_g.append(y)
         outs = None if outputs is None else [o for o in outputs if o < og["n_out"]]
-        want.append((keys_o.matmul_cc(Aw, Bw, level, H, L, d, outputs=outs), outs, grp))
+        want.append((keys_o.matmul_cc(Aw, Bw, level, H, L, d, outputs=outs, b_prerotated=prerot), outs, grp))
         h0 += H
-    Cd = [c.ct(level - 3) for _ in range(info["n_out"])]
+    Cd = [c.ct(level - (3 if prerot else 4)) for _ in range(info["n_out"])]
     B.blb_matmul_cc(c.h, keys_g, plan, A_g, B_g, Cd)
     return dict(Q=Q, Kt=Kt, keys_o=keys_o, keys_g=keys_g, plan=plan, info=info, A=A_g, B=B_g, C=Cd, want=want, level=level)
 
 
-@pytest.mark.parametrize("heads,L,d,outputs", [(8, 32, 32, None), (12, 64, 32, [0, 1])])
-def test_matmul_cc_matches_oracle(c3s, heads, L, d, outputs):
-    """Multi-head ct-ct matmul (steps 2-3, pre-rotated B) word for word against the oracle,
-    including the 8 + 4 head-group split; decoded outputs equal Q_h K_h^T."""
+@pytest.fixture(scope="module")
+def c5p(blb, orc):
+    """five ciphertext primes at N = 16384 (two special, digits of two primes): room for step 1
+    on the server"""
+    x = Ctx(blb, orc, 14, 5, 2, 3)
+    yield x
+    x.close()
+
+
+@pytest.mark.parametrize("heads,L,d,outputs,prerot", [(8, 32, 32, None, True), (12, 64, 32, [0, 1], True),
+                                                       (8, 32, 32, None, False), (12, 40, 32, [0, 3], False)])
+def test_matmul_cc_matches_oracle(request, heads, L, d, outputs, prerot):
+    """Multi-head ct-ct matmul word for word against the oracle, including the 8 + 4 head-group
+    split; decoded outputs equal Q_h K_h^T.  prerot: B pre-rotated by the client (steps 2-3,
+    four primes); otherwise step 1 runs on the server first (five primes)."""
     from paper_2508_19525_amd import workloads as wl
-    r = _cc_case(c3s, heads, L, d, heads + L, outputs)
+    c3s = request.getfixturevalue("c3s" if prerot else "c5p")
+    r = _cc_case(c3s, heads, L, d, heads + L, outputs, prerot)
     h0 = 0
     for O_want, outs, grp in r["want"]:
         sel = range(grp["n_out"]) if outs is None else outs
@@ -386,7 +432,7 @@ def test_exec_cc_replays_match_eager(c3s):
 # --------------------------------------------------------------------------------------
 def test_ntt_variants_bit_identical(c3s):
     """The persistent pipelined NTT (knob 1) and the one-workgroup-per-poly NTT (knob 0) give
-    identical words through a full matmul_cc and through rotations at every level."""
+    identical words through a full matmul_cc (rotations, rescales and ModDowns at three levels)."""
     B = c3s.B
     r = _cc_case(c3s, 8, 32, 32, 11)
     base = [c3s.export(x) for x in r["C"]]
@@ -418,3 +464,49 @@ def test_mac_variants_bit_identical(c2s):
     B.blb_ctx_set_knob(c2s.h, B.BLB_KNOB_MAC_VARIANT, 0)
     B.blb_plan_destroy(r["plan"])
     B.blb_keys_destroy(r["keys_g"])
+
+
+# --------------------------------------------------------------------------------------
+# the batched transform on its own
+# --------------------------------------------------------------------------------------
+def _brv(log_n):
+    j = np.arange(1 << log_n)
+    r = np.zeros_like(j)
+    for b in range(log_n):
+        r |= ((j >> b) & 1) << (log_n - 1 - b)
+    return r
+
+
+@pytest.mark.parametrize("name,n_polys", [("c1", 3), ("c2s", 5), ("c3s", 37)])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_ntt_matches_oracle(request, name, n_polys, variant):
+    """blb_ntt: word j of the forward transform is the evaluation at psi^(2 brv(j) + 1), which is
+    entry brv(j) of the oracle's natural-order textbook transform; every prime of the chain
+    (special primes included); the inverse returns the input exactly; a ragged poly count."""
+    c = request.getfixturevalue(name)
+    B = c.B
+    mods = B.blb_ctx_moduli(c.h, c.n_q + c.n_sp)
+    nl = len(mods)
+    log_n = int(np.log2(c.n))
+    rng = np.random.default_rng(1000 + n_polys)
+    words = np.stack([np.stack([rng.integers(0, int(q), c.n, dtype=np.uint64) for q in mods]) for _ in range(n_polys)])
+    dev = c.upload_words(words)
+    B.blb_ctx_set_knob(c.h, B.BLB_KNOB_NTT_VARIANT, variant)
+    try:
+        B.blb_ntt(c.h, dev, n_polys, nl, inverse=False)
+        torch.cuda.synchronize()
+        got = dev.cpu().numpy().view(np.uint64).reshape(n_polys, nl, c.n)
+        perm = _brv(log_n)
+        for p in sorted({0, n_polys - 1}):
+            for m in range(nl):
+                want = c.o.ntt_forward(m, words[p, m])
+                assert np.array_equal(got[p, m], want[perm]), f"poly {p} limb {m}"
+        B.blb_ntt(c.h, dev, n_polys, nl, inverse=True)
+        torch.cuda.synchronize()
+        back = dev.cpu().numpy().view(np.uint64).reshape(n_polys, nl, c.n)
+        assert np.array_equal(back, words)
+    finally:
+        B.blb_ctx_set_knob(c.h, B.BLB_KNOB_NTT_VARIANT, 0)
+    with pytest.raises(B.BlbError):
+        B.blb_ntt(c.h, dev, 1, nl + 1)
+    B.blb_ntt(c.h, dev, 0, 1)

@@ -497,6 +497,46 @@ def test_mask_to_share_identity_and_uniformity(orc):
             assert chi2 < 45.0
 
 
+@pytest.mark.parametrize("bits", [32, 40])
+def test_rerandomize_adds_flooded_encryption_of_zero(orc, bits):
+    """Dec(rerand(ct)) - Dec(ct) = v e_pk + e0 + e1 s, the same integer in every limb (CRT
+    consistency, so the term is a genuine small polynomial); it lies within 2^F + 2 * 19 * N and is
+    uniform over [-2^F, 2^F] (chi^2 over 16 bins, standard deviation 2^F / sqrt(3)); c1 moves by a
+    value that looks uniform mod q; other seeds or object ids give other noise; the message
+    decodes within 8 sqrt(N) 2^F / Delta (the slot sums of N flooding coefficients)."""
+    c = orc.Context(12, 3, 1, 3)
+    k = orc.Keys(c, 4)
+    rng = np.random.default_rng(8)
+    m = rng.normal(0, 1, c.slots)
+    lvl, delta = 2, 2.0 ** 40
+    ct = k.encrypt(c.encode_rns(m, delta, lvl), lvl, 5, 0)
+    rr = k.rerandomize(ct, lvl, 1234, 3, bits)
+    diff = (k.decrypt(rr, lvl).astype(object) - k.decrypt(ct, lvl).astype(object))
+    vals = []
+    for i in range(lvl + 1):
+        q = int(c.q[i])
+        vals.append([(int(x) % q) if (int(x) % q) <= q // 2 else (int(x) % q) - q for x in diff[i]])
+    vals = np.array(vals, dtype=np.int64)
+    assert all(np.array_equal(vals[0], vals[i]) for i in range(1, lvl + 1))
+    e = vals[0].astype(np.float64)
+    B = float(2 ** bits)
+    assert np.abs(e).max() <= B + 2 * 19 * c.n
+    assert np.abs(e).max() > 0.95 * B
+    assert abs(e.std() / (B / np.sqrt(3)) - 1) < 0.05
+    cnt = np.bincount(np.clip(((e + B) * 16 / (2 * B + 1)).astype(np.int64), 0, 15), minlength=16)
+    assert float(((cnt - c.n / 16) ** 2 / (c.n / 16)).sum()) < 45.0
+    q0 = int(c.q[0])
+    dc1 = (rr[1, 0].astype(object) - ct[1, 0].astype(object)) % q0
+    top = np.array([int(x) * 16 // q0 for x in dc1])
+    assert float(((np.bincount(top, minlength=16) - c.n / 16) ** 2 / (c.n / 16)).sum()) < 45.0
+    assert not np.array_equal(k.rerandomize(ct, lvl, 1234, 4, bits), rr)
+    assert not np.array_equal(k.rerandomize(ct, lvl, 1235, 3, bits), rr)
+    got = c.decode(k.decrypt(rr, lvl), lvl, delta)
+    assert np.abs(got - m).max() < 8 * np.sqrt(c.n) * B / delta
+    with pytest.raises(ValueError):
+        k.rerandomize(ct, lvl, 1, 0, 31)
+
+
 def test_encoded_mask_concentration_negative_control(orc):
     """The insecure MP2ML mask Encode(Delta^-1 r), r uniform in Z_q^(N/2), has coefficients with
     standard deviation q / sqrt(12 N) (N = 8192, q ~ 2^60 as in Figure distribution): far
@@ -516,27 +556,49 @@ def test_encoded_mask_concentration_negative_control(orc):
 # --------------------------------------------------------------------------------------
 # matmul_cc (multi-head, diagonal-packed output)
 # --------------------------------------------------------------------------------------
-def _cc_small(orc, H_g, L, d, seed):
-    c = orc.Context(12, 4, 2, 2)
+def _unrotated_b(mats, H_g, L, d, a, slots):
+    """slot i + L'(h + H_g kappa) <- B_h{a c + kappa, i}: the B operand before step 1 (built
+    here by hand, independently of the packing helpers)"""
+    lp = 1 << int(np.ceil(np.log2(L)))
+    cc = slots // (lp * H_g)
+    v = np.zeros(slots)
+    for h in range(H_g):
+        for kap in range(cc):
+            k = a * cc + kap
+            if k < d:
+                v[lp * (h + H_g * kap): lp * (h + H_g * kap) + L] = mats[h][k, :]
+    return v
+
+
+def _cc_small(orc, H_g, L, d, seed, prerot=True):
+    c = orc.Context(12, 4, 2, 2) if prerot else orc.Context(12, 5, 2, 3)  # digits of at most K = 2 primes
     g = c.cc_geometry(H_g, L, d)
     rng = np.random.default_rng(seed)
     Q = [rng.normal(0, 1, (L, d)) for _ in range(H_g)]
     K = [rng.normal(0, 1, (L, d)) for _ in range(H_g)]
     Bm = [k.T.copy() for k in K]
     keys = orc.Keys(c, 5, c.cc_galois(H_g, L, d))
-    level, scale = 3, 2.0 ** 40
+    level, scale = (3 if prerot else 4), 2.0 ** 40
     A = np.stack([keys.encrypt(c.encode_rns(c.pack_mhp(Q, H_g, L, d, a, "A"), scale, level), level, 10, a) for a in range(g["n_ct"])])
-    Bp = np.stack([keys.encrypt(c.encode_rns(c.pack_mhp(Bm, H_g, L, d, a, "Bp"), scale, level), level, 11, a) for a in range(g["n_ct"])])
+    if prerot:
+        bv = [c.pack_mhp(Bm, H_g, L, d, a, "Bp") for a in range(g["n_ct"])]
+    else:
+        bv = [_unrotated_b(Bm, H_g, L, d, a, c.slots) for a in range(g["n_ct"])]
+    Bp = np.stack([keys.encrypt(c.encode_rns(v, scale, level), level, 11, a) for a, v in enumerate(bv)])
     return c, g, keys, Q, K, A, Bp, level, scale
 
 
-@pytest.mark.parametrize("H_g,L,d", [(2, 32, 64), (4, 20, 32)])
-def test_matmul_cc_decodes_to_qkt(orc, H_g, L, d):
+@pytest.mark.parametrize("H_g,L,d,prerot", [(2, 32, 64, True), (4, 20, 32, True), (2, 32, 64, False), (4, 20, 32, False)])
+def test_matmul_cc_decodes_to_qkt(orc, H_g, L, d, prerot):
     """Decoded diagonal-packed output equals Q_h K_h^T (FP64) for every head, within 2^-20 at
     the final scale ~2^40 (catches a wrong inner-rotation mask, a wrong step-3 block rotation
-    or a wrong output index g+1 for the wrapped blocks)."""
-    c, g, keys, Q, K, A, Bp, level, scale = _cc_small(orc, H_g, L, d, H_g + L)
-    O = keys.matmul_cc(A, Bp, level, H_g, L, d)
+    or a wrong output index g+1 for the wrapped blocks).  prerot=False feeds B without the
+    client-side row rotation and runs step 1 homomorphically (one more level, five primes);
+    a wrong step-1 mask or rotation direction breaks the same check."""
+    c, g, keys, Q, K, A, Bp, level, scale = _cc_small(orc, H_g, L, d, H_g + L, prerot)
+    O = keys.matmul_cc(A, Bp, level, H_g, L, d, b_prerotated=prerot)
+    if not prerot:
+        level -= 1  # steps 2-3 run one level lower; step 1 keeps the scale
     lp, cc = g["Lp"], g["c"]
     # scale after the schedule: scale * (q3 2^10 / q3) * scale / q2 * (q1 / q1)
     out_scale = scale * 1024.0 * scale / float(c.q[2])
