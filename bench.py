@@ -473,28 +473,47 @@ def run_serving(args, B, torch):
         work.append((t_arr, wid, L, client, inputs[key], (B.blb_ct * n_out)(*ys)))
     torch.cuda.synchronize()
     log(f"serving setup {time.time() - t_setup:.1f}s: {len(reqs)} requests, {len(inputs)} input sets, {len(steps)} rotation keys")
-    srv = B.blb_server_create(ctx, int(args.serve_cache_gb * 1e9), max_batch=8, max_queue=100000, n_streams=2)
-    try:
-        for wid, shape in shapes.items():
-            B.blb_server_add_weights(srv, wid, wl.serving_weights(wid, shape), level)
-        t0 = time.perf_counter()
-        ids = []
-        for t_arr, wid, L, client, X, Y in work:
-            dt = t0 + t_arr - time.perf_counter()
-            if dt > 0:
-                time.sleep(dt)
-            ids.append(B.blb_server_submit(srv, keys[client], wid, L, X, Y))
-        log(f"serving: all {len(ids)} submitted after {time.perf_counter() - t0:.1f}s; draining")
-        B.blb_server_drain(srv, 1200)
-        t_end = time.perf_counter()
-        st = B.blb_server_stats(srv)
-    finally:
-        B.blb_server_destroy(srv)
+
+    def serve(policy, max_batch, n_streams):
+        srv = B.blb_server_create(ctx, int(args.serve_cache_gb * 1e9), max_batch=max_batch, max_queue=100000, n_streams=n_streams,
+                                  policy=policy, max_wait_ms=args.serve_max_wait_ms)
+        try:
+            for wid, shape in shapes.items():
+                B.blb_server_add_weights(srv, wid, wl.serving_weights(wid, shape), level)
+            t0 = time.perf_counter()
+            ids = []
+            for t_arr, wid, L, client, X, Y in work:
+                dt = t0 + t_arr - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                ids.append(B.blb_server_submit(srv, keys[client], wid, L, X, Y))
+            log(f"serving (policy {policy}, batch {max_batch}, streams {n_streams}): all {len(ids)} submitted after "
+                f"{time.perf_counter() - t0:.1f}s; draining")
+            B.blb_server_drain(srv, 1200)
+            t_end = time.perf_counter()
+            st = B.blb_server_stats(srv)
+            states = [B.blb_server_poll(srv, i)[0] for i in ids]
+        finally:
+            B.blb_server_destroy(srv)
+        st["throughput_rps"] = st["completed"] / (t_end - t0)
+        st["wall_s"] = t_end - t0
+        st["all_done"] = all(x == 2 for x in states)
+        torch.cuda.synchronize()
+        # output words of a few requests, to compare across runs (same arithmetic => same bits)
+        sample = [B.blb_export(ctx, work[i][5][0], n) for i in range(0, len(work), max(1, len(work) // 4))]
+        log(f"  -> {st}")
+        return st, sample
+
+    served, s1 = serve(B.SERVE_RESIDENT_FIRST, 8, 2)
+    per_op, s0 = serve(B.SERVE_FIFO, 1, 1)
+    st = dict(served)
     st["offered_rate_rps"] = args.serve_rate
-    st["throughput_rps"] = st["completed"] / (t_end - t0)
-    st["wall_s"] = t_end - t0
     st["plan_cache_GB"] = args.serve_cache_gb
-    log(f"serving: {st}")
+    st["policy"] = "resident plans first, oldest after max_wait_ms; max_batch 8; 2 streams"
+    st["per_op_baseline"] = dict(per_op, policy="arrival order, one request per launch, one stream (unbatched per-op path)")
+    st["served_vs_per_op_throughput"] = served["throughput_rps"] / max(per_op["throughput_rps"], 1e-12)
+    st["identical_outputs"] = all(np.array_equal(a, b) for a, b in zip(s1, s0))
+    log(f"serving: served {served['throughput_rps']:.2f} rps vs per-op {per_op['throughput_rps']:.2f} rps, identical {st['identical_outputs']}")
     for k in keys:
         B.blb_keys_destroy(k)
     B.blb_ctx_destroy(ctx)
@@ -555,9 +574,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-ntt", action="store_true", help="skip the standalone NTT measurement")
-    ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--serve-requests", type=int, default=80)
     ap.add_argument("--serve-rate", type=float, default=50.0)
-    ap.add_argument("--serve-cache-gb", type=float, default=120.0)
+    ap.add_argument("--serve-cache-gb", type=float, default=150.0)
+    ap.add_argument("--serve-max-wait-ms", type=float, default=2000.0)
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB plain copy (counter reference)")
     args = ap.parse_args()
     if args.gpus != 1:

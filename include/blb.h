@@ -257,20 +257,27 @@ typedef struct {
   int max_batch;  /* requests per batch */
   int max_queue;  /* queued (not yet admitted) requests */
   int n_streams;  /* batches in flight, 1..8 */
+  int policy;     /* 0: admit in arrival order; 1: requests whose plan is resident first, then the
+                   * oldest (its plan generated, then every queued request on the same plan); a
+                   * request older than max_wait_ms goes first in any case */
+  double max_wait_ms;
 } blb_server_config;
 int blb_server_create(blb_ctx* ctx, const blb_server_config* cfg, blb_server** out);
 /* W: host d_in x d_out row-major; inputs of requests on this weight are at `level`. */
 int blb_server_add_weights(blb_server* server, int weight_id, const double* W, int d_in, int d_out, int level);
 /* X (n_in cts) and Y (n_out buffers of 2*level*N words) must stay alive until completion; the
- * blb_ct array Y is updated (level, scale) by the worker.  mask_target_level < 0: no mask. */
+ * blb_ct array Y is updated (level, scale) by the worker.  mask_target_level < 0: no mask.
+ * Refused at submission: EINVAL (shapes), ELEVEL (input level), ENOKEY (keys lack a rotation
+ * of this request's schedule), EBUSY (queue full). */
 int blb_server_submit(blb_server* server, const blb_keys* keys, int weight_id, int L, const blb_ct* X, int n_in, blb_ct* Y, int n_out,
                       uint64_t mask_seed, int mask_target_level, uint64_t* share_dev, int64_t* req_id);
 /* state: 0 queued, 1 running, 2 done, < 0 the error code; latency_ms (done only, else -1). */
 int blb_server_poll(blb_server* server, int64_t req_id, int* state, double* latency_ms);
 /* waits until nothing is queued or running (BLB_EBUSY on timeout) */
 int blb_server_drain(blb_server* server, double timeout_s);
-/* out[10]: completed, rejected, p50 ms, p99 ms, mean ms, plan hits, plan misses, batches,
- * plan generation seconds, resident plan bytes */
+/* out[cap >= 10]: completed, rejected, p50 ms, p99 ms, mean ms, plan hits, plan misses,
+ * batches, plan generation seconds, resident plan bytes; out[10] (cap > 10): requests whose
+ * batch failed at launch (their poll state holds the error code). */
 int blb_server_stats(blb_server* server, double* out, int cap);
 void blb_server_destroy(blb_server* server);
 

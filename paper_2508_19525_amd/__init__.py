@@ -34,7 +34,8 @@ class blb_cp_instance(C.Structure):
 
 
 class blb_server_config(C.Structure):
-    _fields_ = [("plan_cache_bytes", C.c_uint64), ("max_batch", C.c_int), ("max_queue", C.c_int), ("n_streams", C.c_int)]
+    _fields_ = [("plan_cache_bytes", C.c_uint64), ("max_batch", C.c_int), ("max_queue", C.c_int), ("n_streams", C.c_int),
+                ("policy", C.c_int), ("max_wait_ms", C.c_double)]
 
 
 class blb_params(C.Structure):
@@ -397,8 +398,12 @@ def blb_exec_destroy(ex):
     lib().blb_exec_destroy(ex.h if isinstance(ex, Exec) else ex)
 
 
-def blb_server_create(ctx, plan_cache_bytes, max_batch=16, max_queue=4096, n_streams=2):
-    cfg = blb_server_config(plan_cache_bytes, max_batch, max_queue, n_streams)
+SERVE_FIFO, SERVE_RESIDENT_FIRST = 0, 1
+
+
+def blb_server_create(ctx, plan_cache_bytes, max_batch=16, max_queue=4096, n_streams=2, policy=SERVE_RESIDENT_FIRST,
+                      max_wait_ms=1000.0):
+    cfg = blb_server_config(plan_cache_bytes, max_batch, max_queue, n_streams, policy, max_wait_ms)
     out = C.c_void_p()
     _check(lib().blb_server_create(ctx, C.byref(cfg), C.byref(out)), "blb_server_create")
     return out.value
@@ -429,10 +434,10 @@ def blb_server_drain(server, timeout_s=600.0):
 
 
 def blb_server_stats(server):
-    out = np.zeros(10, np.float64)
-    _check(lib().blb_server_stats(server, _host_ptr(out), 10), "blb_server_stats")
+    out = np.zeros(11, np.float64)
+    _check(lib().blb_server_stats(server, _host_ptr(out), 11), "blb_server_stats")
     keys = ["completed", "rejected", "p50_ms", "p99_ms", "mean_ms", "plan_hits", "plan_misses", "batches", "plan_gen_s",
-            "plan_bytes"]
+            "plan_bytes", "failed"]
     return dict(zip(keys, [float(x) for x in out]))
 
 

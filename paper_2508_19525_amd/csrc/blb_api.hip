@@ -1093,6 +1093,20 @@ static CpGeom cp_geometry(const blb_ctx* c, int L, int d_in, int d_out) {
   return g;
 }
 
+}  // extern "C"
+
+// BLB_OK when K holds every Galois key matmul_cp needs at this geometry (baby and giant steps)
+int cp_check_keys(const blb_ctx* c, const blb_keys* K, int L, int d_in, int d_out) {
+  const CpGeom g = cp_geometry(c, L, d_in, d_out);
+  for (int i = 1; i < g.B; ++i)
+    if (!find_key(K, galois_left(c, (int64_t)i * g.Lp))) return BLB_ENOKEY;
+  for (int j = 1; j < g.G; ++j)
+    if (!find_key(K, galois_left(c, (int64_t)j * g.B * g.Lp))) return BLB_ENOKEY;
+  return BLB_OK;
+}
+
+extern "C" {
+
 int blb_plan_matmul_cp(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, blb_plan** out) {
   if (!c || !W || !out || d_in < 1 || d_out < 1 || L < 1 || L > c->n / 2 || level < 1 || level >= c->n_q) return BLB_EINVAL;
   *out = nullptr;

@@ -233,6 +233,7 @@ struct blb_plan {
 struct PolyDesc;
 void launch_sample_uniform(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag);
 void launch_sample_int(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag, bool gaussian);
+int cp_check_keys(const blb_ctx* c, const blb_keys* K, int L, int d_in, int d_out);
 void launch_sample_flood(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag, int bits);
 void upload_cdt(const uint64_t* table20);
 

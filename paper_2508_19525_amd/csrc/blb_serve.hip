@@ -5,6 +5,9 @@
 //   - admission: a request is admitted when the plan (diagonal plaintexts of its weight at
 //     its padded length L') is resident or can be generated within the plan-cache budget;
 //     least-recently-used plans that no admitted request uses are evicted to make room;
+//     requests are taken in arrival order, or (policy 1) those whose plan is resident first,
+//     then the oldest together with every queued request on the plan generated for it, with
+//     a request older than max_wait_ms always first;
 //   - continuous batching: every admitted request joins the next batch; a batch runs as one
 //     blb_batch_matmul_cp (plus per-request mask-and-share) on one of several streams, so
 //     requests that arrive while earlier batches are on the GPU are admitted and launched
@@ -90,7 +93,7 @@ struct blb_server {
   bool stop = false;
   std::thread worker;
   // statistics
-  int64_t hits = 0, misses = 0, rejected = 0, completed = 0, batches = 0;
+  int64_t hits = 0, misses = 0, rejected = 0, completed = 0, batches = 0, failed = 0;
   double gen_s = 0;
   std::vector<double> latencies;
 };
@@ -162,8 +165,12 @@ void finish_batches(blb_server* S, bool block) {
       std::lock_guard<std::mutex> lk(S->mu);
       for (Request* r : b.reqs) {
         r->t_done = t;
-        r->state = 2;
         r->pe->users--;
+        if (r->state != 1) {  // the batch failed at launch: keep its error code
+          ++S->failed;
+          continue;
+        }
+        r->state = 2;
         S->latencies.push_back(t - r->t_submit);
         ++S->completed;
       }
@@ -188,10 +195,21 @@ void worker_loop(blb_server* S) {
     }
     finish_batches(S, false);
     if (pending.empty()) continue;
-    // admission in arrival order, up to max_batch
+    // admission order: arrival order (policy 0), or resident plans first (policy 1)
+    std::vector<Request*> order;
+    if (S->cfg.policy == 1) {
+      Request* oldest = pending.front();
+      const bool overdue = (now_s() - oldest->t_submit) * 1e3 > S->cfg.max_wait_ms;
+      if (overdue) order.push_back(oldest);
+      for (Request* r : pending)
+        if (!(overdue && r == oldest) && S->plans.count(std::make_pair(r->weight_id, r->Lp))) order.push_back(r);
+      if (order.empty()) order.push_back(oldest);
+    } else {
+      order = pending;
+    }
     std::vector<Request*> batch;
     std::vector<Request*> rejected;
-    for (Request* r : pending) {
+    for (Request* r : order) {
       if ((int)batch.size() >= S->cfg.max_batch) break;
       const int a = admit(S, r);
       if (a == 1) batch.push_back(r);
@@ -199,7 +217,16 @@ void worker_loop(blb_server* S) {
         r->state = a;
         rejected.push_back(r);
       } else {
-        break;  // keep arrival order: wait for memory
+        break;  // wait for memory
+      }
+    }
+    if (S->cfg.policy == 1 && !batch.empty()) {
+      // a plan generated for this batch also serves every queued request on it
+      for (Request* r : pending) {
+        if ((int)batch.size() >= S->cfg.max_batch) break;
+        if (std::find(batch.begin(), batch.end(), r) != batch.end() || std::find(rejected.begin(), rejected.end(), r) != rejected.end())
+          continue;
+        if (S->plans.count(std::make_pair(r->weight_id, r->Lp)) && admit(S, r) == 1) batch.push_back(r);
       }
     }
     {
@@ -265,7 +292,9 @@ double percentile(std::vector<double> v, double p) {
 extern "C" {
 
 int blb_server_create(blb_ctx* c, const blb_server_config* cfg, blb_server** out) {
-  if (!c || !cfg || !out || cfg->max_batch < 1 || cfg->max_queue < 1 || cfg->n_streams < 1 || cfg->n_streams > 8) return BLB_EINVAL;
+  if (!c || !cfg || !out || cfg->max_batch < 1 || cfg->max_queue < 1 || cfg->n_streams < 1 || cfg->n_streams > 8 ||
+      (cfg->policy != 0 && cfg->policy != 1) || !(cfg->max_wait_ms >= 0))
+    return BLB_EINVAL;
   *out = nullptr;
   blb_server* S = new (std::nothrow) blb_server();
   if (!S) return BLB_ENOMEM;
@@ -310,6 +339,8 @@ int blb_server_submit(blb_server* S, const blb_keys* keys, int weight_id, int L,
   if (n_in != (w.d_in + cc - 1) / cc || n_out != (w.d_out + cc - 1) / cc) return BLB_EINVAL;
   for (int a = 0; a < n_in; ++a)
     if (!X[a].data || X[a].level != w.level || X[a].degree != 1) return BLB_ELEVEL;
+  // a request whose keys lack a rotation is refused here rather than failing a whole batch
+  if (cp_check_keys(S->c, keys, L, w.d_in, w.d_out) != BLB_OK) return BLB_ENOKEY;
   Request* r = new (std::nothrow) Request();
   if (!r) return BLB_ENOMEM;
   r->id = S->next_id++;
@@ -369,6 +400,7 @@ int blb_server_stats(blb_server* S, double* out, int cap) {
   out[7] = (double)S->batches;
   out[8] = S->gen_s;
   out[9] = (double)S->plan_bytes;
+  if (cap > 10) out[10] = (double)S->failed;
   return BLB_OK;
 }
 

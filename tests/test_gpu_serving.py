@@ -59,7 +59,7 @@ def _make_requests(B, wl, ctx, specs, keys, level=2, n=8192, scale=2.0 ** 40):
 def _keys_for_all(B, wl, ctx, n_clients):
     steps = set()
     for wid, (d_in, d_out) in SHAPES.items():
-        for lp in (16, 32, 64, 128, 256, 512):
+        for lp in (8, 16, 32, 64, 128, 256, 512):
             cc = 4096 // lp
             dp = 1 << int(np.ceil(np.log2(d_in)))
             ce = min(cc, dp)
@@ -69,14 +69,15 @@ def _keys_for_all(B, wl, ctx, n_clients):
     return [B.blb_keygen(ctx, 6100 + c, sorted(steps)) for c in range(n_clients)]
 
 
-def test_alone_equals_in_mix(env):
+@pytest.mark.parametrize("policy", [1, 0])
+def test_alone_equals_in_mix(env, policy):
     B, wl, ctx = env
     keys = _keys_for_all(B, wl, ctx, 3)
     specs = [(0, 40, 0, 1)] + [(i % 3, [16, 100, 33, 200, 64, 7, 300][i % 7], i % 3, 10 + i) for i in range(12)]
     reqs, keep = _make_requests(B, wl, ctx, specs, keys)
     Ws = {wid: wl.serving_weights(wid, SHAPES[wid]) for wid in SHAPES}
     # plan budget fits a handful of plans: forces eviction between batches
-    srv = B.blb_server_create(ctx, plan_cache_bytes=600 << 20, max_batch=6, n_streams=2)
+    srv = B.blb_server_create(ctx, plan_cache_bytes=600 << 20, max_batch=6, n_streams=2, policy=policy, max_wait_ms=50.0)
     try:
         for wid, W in Ws.items():
             B.blb_server_add_weights(srv, wid, W, 2)
@@ -92,8 +93,8 @@ def test_alone_equals_in_mix(env):
             seed = 55 if k == 0 else 1000 + k
             ids.append(B.blb_server_submit(srv, keys[r["client"]], r["wid"], r["L"], r["X"], r["Y"], seed, 1, r["share"]))
         B.blb_server_drain(srv, 300)
-        for rid in ids:
-            assert B.blb_server_poll(srv, rid)[0] == 2
+        states = [B.blb_server_poll(srv, rid)[0] for rid in ids]
+        assert states == [2] * len(ids), f"request states {states}"
         mix = [B.blb_export(ctx, r0["Y"][b], 8192) for b in range(len(r0["Y"]))]
         for b in range(len(mix)):
             assert np.array_equal(alone[b], mix[b]), f"output {b} differs alone vs in the mix"
@@ -140,5 +141,31 @@ def test_admission_rejects_plan_over_budget(env):
         assert B.blb_server_stats(srv)["rejected"] == 1
     finally:
         B.blb_server_destroy(srv)
+        for k in keys:
+            B.blb_keys_destroy(k)
+
+
+def test_submit_refuses_request_without_its_keys(env):
+    """A request whose keys lack a rotation of its schedule is refused at submission (ENOKEY)
+    instead of failing the batch it would have joined; the server keeps serving."""
+    B, wl, ctx = env
+    keys = _keys_for_all(B, wl, ctx, 1)
+    bare = B.blb_keygen(ctx, 98, [])
+    reqs, keep = _make_requests(B, wl, ctx, [(0, 40, 0, 4)], keys)
+    srv = B.blb_server_create(ctx, plan_cache_bytes=256 << 20, max_batch=4, n_streams=1)
+    try:
+        B.blb_server_add_weights(srv, 0, wl.serving_weights(0, SHAPES[0]), 2)
+        r = reqs[0]
+        with pytest.raises(B.BlbError) as ei:
+            B.blb_server_submit(srv, bare, 0, r["L"], r["X"], r["Y"])
+        assert ei.value.code == B.BLB_ENOKEY
+        rid = B.blb_server_submit(srv, keys[0], 0, r["L"], r["X"], r["Y"])
+        B.blb_server_drain(srv, 60)
+        assert B.blb_server_poll(srv, rid)[0] == 2
+        st = B.blb_server_stats(srv)
+        assert st["completed"] == 1 and st["failed"] == 0
+    finally:
+        B.blb_server_destroy(srv)
+        B.blb_keys_destroy(bare)
         for k in keys:
             B.blb_keys_destroy(k)
