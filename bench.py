@@ -89,10 +89,12 @@ def run_cp(args, B, torch):
         eager_step(k)
     torch.cuda.synchronize()
     tune = {}
-    if not args.no_tune:
+    if args.mac_variant is not None:
+        B.blb_ctx_set_knob(ctx, B.BLB_KNOB_MAC_VARIANT, args.mac_variant)
+    elif not args.no_tune:
         # autotuner: pick the MAC launch shape (results are bit-identical across variants)
         B.blb_ctx_set_timing(ctx, True)
-        for var in range(5):
+        for var in range(B.BLB_MAC_VARIANTS):
             B.blb_ctx_set_knob(ctx, B.BLB_KNOB_MAC_VARIANT, var)
             B.blb_ctx_reset_timing(ctx)
             for k in range(3):
@@ -220,6 +222,20 @@ def run_cc(args, B, torch):
         h0 += grp["H"]
         base += grp["n_out"]
     log(f"cc decoded max abs err {err:.3e}")
+    # autotuner: NTT launch variant (results are bit-identical across variants)
+    ntt_tune = {}
+    if not args.no_tune:
+        for var in (0, 1):
+            B.blb_ctx_set_knob(ctx, B.BLB_KNOB_NTT_VARIANT, var)
+            B.blb_matmul_cc(ctx, keys, plan, A, Bp, Cd)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(2):
+                B.blb_matmul_cc(ctx, keys, plan, A, Bp, Cd)
+            torch.cuda.synchronize()
+            ntt_tune[var] = (time.perf_counter() - t0) / 2 * 1e3
+        B.blb_ctx_set_knob(ctx, B.BLB_KNOB_NTT_VARIANT, min(ntt_tune, key=ntt_tune.get))
+        log(f"cc NTT variants (ms per op): {ntt_tune}")
     # eager (timed, with kernel timing)
     B.blb_matmul_cc(ctx, keys, plan, A, Bp, Cd)
     torch.cuda.synchronize()
@@ -248,7 +264,8 @@ def run_cc(args, B, torch):
     log(f"cc: eager {steps / dt_eager:.1f}/s, graph {steps / dt:.1f}/s")
     res = {"value": steps / dt, "eager": steps / dt_eager, "ms": dt / steps * 1e3, "err": err, "split_ms": split,
            "ntt_gbps": ntt_polys * 16 * n / (ntt_ms / 1e3) / 1e9 if ntt_ms > 0 else 0.0,
-           "rotation_keys": len(steps_rot), "groups": info["groups"]}
+           "rotation_keys": len(steps_rot), "groups": info["groups"],
+           "ntt_variant": B.blb_ctx_get_knob(ctx, B.BLB_KNOB_NTT_VARIANT), "ntt_tune_ms": ntt_tune}
     B.blb_exec_destroy(ex)
     B.blb_plan_destroy(plan)
     B.blb_keys_destroy(keys)
@@ -474,7 +491,8 @@ def run_serving(args, B, torch):
     torch.cuda.synchronize()
     log(f"serving setup {time.time() - t_setup:.1f}s: {len(reqs)} requests, {len(inputs)} input sets, {len(steps)} rotation keys")
 
-    def serve(policy, max_batch, n_streams):
+    def serve(policy, max_batch, n_streams, rate=None):
+        stretch = 1.0 if rate is None else args.serve_rate / rate  # same request sequence, other offered rate
         srv = B.blb_server_create(ctx, int(args.serve_cache_gb * 1e9), max_batch=max_batch, max_queue=100000, n_streams=n_streams,
                                   policy=policy, max_wait_ms=args.serve_max_wait_ms)
         try:
@@ -483,7 +501,7 @@ def run_serving(args, B, torch):
             t0 = time.perf_counter()
             ids = []
             for t_arr, wid, L, client, X, Y in work:
-                dt = t0 + t_arr - time.perf_counter()
+                dt = t0 + t_arr * stretch - time.perf_counter()
                 if dt > 0:
                     time.sleep(dt)
                 ids.append(B.blb_server_submit(srv, keys[client], wid, L, X, Y))
@@ -514,6 +532,13 @@ def run_serving(args, B, torch):
     st["served_vs_per_op_throughput"] = served["throughput_rps"] / max(per_op["throughput_rps"], 1e-12)
     st["identical_outputs"] = all(np.array_equal(a, b) for a, b in zip(s1, s0))
     log(f"serving: served {served['throughput_rps']:.2f} rps vs per-op {per_op['throughput_rps']:.2f} rps, identical {st['identical_outputs']}")
+    if args.serve_sweep:
+        curve = []
+        for rate in [float(x) for x in args.serve_sweep.split(",")]:
+            r_st, _ = serve(B.SERVE_RESIDENT_FIRST, 8, 2, rate)
+            curve.append({"offered_rps": rate, "throughput_rps": r_st["throughput_rps"], "p50_ms": r_st["p50_ms"],
+                          "p99_ms": r_st["p99_ms"], "plan_misses": r_st["plan_misses"]})
+        st["saturation_curve"] = curve
     for k in keys:
         B.blb_keys_destroy(k)
     B.blb_ctx_destroy(ctx)
@@ -571,13 +596,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cc", action="store_true", help="skip the matmul_cc measurement")
     ap.add_argument("--no-tune", action="store_true", help="skip the MAC launch-shape autotuner")
+    ap.add_argument("--mac-variant", type=int, default=None, help="use this MAC launch shape instead of autotuning")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-ntt", action="store_true", help="skip the standalone NTT measurement")
+    ap.add_argument("--ntt-only", action="store_true", help="run only the standalone NTT measurement (diagnostic)")
     ap.add_argument("--serve-requests", type=int, default=80)
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-cache-gb", type=float, default=150.0)
     ap.add_argument("--serve-max-wait-ms", type=float, default=2000.0)
+    ap.add_argument("--serve-sweep", type=str, default="", help="comma-separated offered rates (req/s) for a saturation curve")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB plain copy (counter reference)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -587,6 +615,9 @@ def main():
     import torch
     import paper_2508_19525_amd as B
     torch.cuda.init()
+    if args.ntt_only:  # diagnostic mode: the standalone NTT measurement alone
+        print(json.dumps({"ntt_standalone_1GiB": run_ntt(args, B, torch)}))
+        return
     r = run_cp(args, B, torch)
     nt = None if args.no_ntt else run_ntt(args, B, torch)
     cc = None if args.no_cc else run_cc(args, B, torch)
@@ -631,7 +662,8 @@ def main():
         "matmul_cc": None if cc is None else {
             "metric": "ct-ct matmul/s (12-head Q_h K_h^T, 128 tokens, N=16384, 4 primes + 2 special)",
             "value": cc["value"], "eager_value": cc["eager"], "ms": cc["ms"], "max_abs_err": cc["err"],
-            "ntt_GBps": cc["ntt_gbps"], "split_ms": cc["split_ms"], "rotation_keys": cc["rotation_keys"]},
+            "ntt_GBps": cc["ntt_gbps"], "split_ms": cc["split_ms"], "rotation_keys": cc["rotation_keys"],
+            "ntt_variant": cc["ntt_variant"], "ntt_tune_ms_per_op": cc["ntt_tune_ms"]},
         "batched": None if bt is None else dict(
             bt, workload="64 independent matmul_cp instances, L ~ U{16..512}, hidden 768/1024 (W shared per hidden size), "
                          "N=8192, 3 primes; per-instance eager calls vs batched stages vs one graph launch"),

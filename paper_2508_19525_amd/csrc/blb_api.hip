@@ -674,7 +674,7 @@ int blb_ctx_set_knob(blb_ctx* c, int knob, int value) {
   if (!c) return BLB_EINVAL;
   switch (knob) {
     case BLB_KNOB_MAC_VARIANT:
-      if (value < 0 || value > 4) return BLB_EINVAL;
+      if (value < 0 || value >= BLB_MAC_VARIANTS) return BLB_EINVAL;
       c->mac_variant = value;
       return BLB_OK;
     case BLB_KNOB_BATCH_VARIANT:

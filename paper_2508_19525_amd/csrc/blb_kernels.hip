@@ -245,11 +245,82 @@ void launch_moddown_conv(blb_ctx* c, const uint64_t* U, uint64_t* Corr, const Ks
 // ---------------------------------------------------------------------------------------
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 
-template <int TB, int CPT>
+// One block's (tile, k-chunk, limb): sums over the n_ai rotated inputs of plaintext x input,
+// for `rows` output rows of the tile (FULL: rows == TB, no per-row guards).
+template <int TB, int CPT, int UNR, bool FULL>
+__device__ __forceinline__ void cp_mac_tile(const uint64_t* __restrict__ pbase, const uint64_t* const* __restrict__ rx_tab,
+                                            size_t pt_stride_bj, int n, int nl, int n_ai, int limb, int k0, int rows, double q, double qi,
+                                            double (&a0)[TB][CPT], double (&a1)[TB][CPT]) {
+  auto load2 = [&](const uint64_t* a, double (&v)[CPT], bool stream) {
+    if (CPT == 2) {
+      const u64x2 w = stream ? __builtin_nontemporal_load((const u64x2*)a) : *(const u64x2*)a;
+      v[0] = u2d(w.x);
+      v[CPT - 1] = u2d(w.y);
+    } else {
+      v[0] = u2d(stream ? __builtin_nontemporal_load(a) : *a);
+    }
+  };
+  auto reduce_all = [&]() {
+#pragma unroll
+    for (int t = 0; t < TB; ++t)
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) { a0[t][c] = reduce_s(a0[t][c], q, qi); a1[t][c] = reduce_s(a1[t][c], q, qi); }
+  };
+  int ai = 0;
+  for (; ai + UNR <= n_ai; ai += UNR) {
+    double x0[UNR][CPT], x1[UNR][CPT], w[UNR][TB][CPT];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const uint64_t* rx = rx_tab[ai + u];
+      load2(rx + (size_t)limb * n + k0, x0[u], false);
+      load2(rx + (size_t)(nl + limb) * n + k0, x1[u], false);
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int t = 0; t < TB; ++t)
+        if (FULL || t < rows) load2(pbase + (size_t)t * pt_stride_bj + (size_t)(ai + u) * nl * n, w[u][t], true);
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int t = 0; t < TB; ++t)
+        if (FULL || t < rows) {
+#pragma unroll
+          for (int c = 0; c < CPT; ++c) {
+            a0[t][c] += mulmod_s(w[u][t][c], x0[u][c], q, qi);
+            a1[t][c] += mulmod_s(w[u][t][c], x1[u][c], q, qi);
+          }
+        }
+    if (((ai + UNR) & 7) == 0) reduce_all();  // every 8 terms: |acc| stays below 2^53
+  }
+  for (; ai < n_ai; ++ai) {
+    double x0[CPT], x1[CPT];
+    const uint64_t* rx = rx_tab[ai];
+    load2(rx + (size_t)limb * n + k0, x0, false);
+    load2(rx + (size_t)(nl + limb) * n + k0, x1, false);
+#pragma unroll
+    for (int t = 0; t < TB; ++t)
+      if (FULL || t < rows) {
+        double w[CPT];
+        load2(pbase + (size_t)t * pt_stride_bj + (size_t)ai * nl * n, w, true);
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+          a0[t][c] += mulmod_s(w[c], x0[c], q, qi);
+          a1[t][c] += mulmod_s(w[c], x1[c], q, qi);
+        }
+      }
+    if ((ai & 7) == 7) reduce_all();
+  }
+}
+
+// SPLIT: full tiles run a body without per-row guards (separately compiled from the guarded
+// body of the last, partial tile); otherwise one guarded body serves every tile.
+template <int TB, int CPT, int UNR, bool SPLIT>
 __global__ __launch_bounds__(256) void k_cp_mac(const uint64_t* __restrict__ pt, const uint64_t* const* __restrict__ rx_tab,
                                                 uint64_t* __restrict__ inner, int n, int nl, int n_ai, int n_bj, ModTable mt, int n_kblk,
                                                 int n_tiles) {
   static_assert(CPT == 1 || CPT == 2, "coefficients per thread");
+  static_assert(UNR == 1 || UNR == 2, "unroll of the input loop");
   // XCD-aware block mapping: blocks that share a (k-chunk, limb) land on the same XCD, so
   // the rotated inputs they all read stay in that XCD's L2
   const int nb = gridDim.x;
@@ -265,52 +336,19 @@ __global__ __launch_bounds__(256) void k_cp_mac(const uint64_t* __restrict__ pt,
   const ModEntry me = mt.m[limb];
   const double q = me.q, qi = me.qinv;
   const int bj0 = tile * TB;
+  const int rows = min(TB, n_bj - bj0);
   double a0[TB][CPT], a1[TB][CPT];
 #pragma unroll
   for (int t = 0; t < TB; ++t)
 #pragma unroll
     for (int c = 0; c < CPT; ++c) { a0[t][c] = 0.0; a1[t][c] = 0.0; }
   const size_t pt_stride_bj = (size_t)n_ai * nl * n;
-  for (int ai = 0; ai < n_ai; ++ai) {
-    const uint64_t* rx = rx_tab[ai];
-    double x0[CPT], x1[CPT];
-    if (CPT == 2) {
-      const u64x2 v0 = *(const u64x2*)(rx + (size_t)limb * n + k0);
-      const u64x2 v1 = *(const u64x2*)(rx + (size_t)(nl + limb) * n + k0);
-      x0[0] = u2d(v0.x); x0[CPT - 1] = u2d(v0.y);
-      x1[0] = u2d(v1.x); x1[CPT - 1] = u2d(v1.y);
-    } else {
-      x0[0] = u2d(rx[(size_t)limb * n + k0]);
-      x1[0] = u2d(rx[(size_t)(nl + limb) * n + k0]);
-    }
-    const uint64_t* p = pt + ((size_t)bj0 * n_ai + ai) * nl * n + (size_t)limb * n + k0;
-#pragma unroll
-    for (int t = 0; t < TB; ++t) {
-      if (bj0 + t < n_bj) {
-        double w[CPT];
-        if (CPT == 2) {
-          const u64x2 v = __builtin_nontemporal_load((const u64x2*)(p + t * pt_stride_bj));
-          w[0] = u2d(v.x); w[CPT - 1] = u2d(v.y);
-        } else {
-          w[0] = u2d(__builtin_nontemporal_load(p + t * pt_stride_bj));
-        }
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-          a0[t][c] += mulmod_s(w[c], x0[c], q, qi);
-          a1[t][c] += mulmod_s(w[c], x1[c], q, qi);
-        }
-      }
-    }
-    if ((ai & 7) == 7) {
-#pragma unroll
-      for (int t = 0; t < TB; ++t)
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) { a0[t][c] = reduce_s(a0[t][c], q, qi); a1[t][c] = reduce_s(a1[t][c], q, qi); }
-    }
-  }
+  const uint64_t* pbase = pt + (size_t)bj0 * pt_stride_bj + (size_t)limb * n + k0;
+  if (SPLIT && rows == TB) cp_mac_tile<TB, CPT, UNR, true>(pbase, rx_tab, pt_stride_bj, n, nl, n_ai, limb, k0, rows, q, qi, a0, a1);
+  else cp_mac_tile<TB, CPT, UNR, false>(pbase, rx_tab, pt_stride_bj, n, nl, n_ai, limb, k0, rows, q, qi, a0, a1);
 #pragma unroll
   for (int t = 0; t < TB; ++t) {
-    if (bj0 + t < n_bj) {
+    if (t < rows) {
       uint64_t* o0 = inner + (((size_t)(bj0 + t) * 2 + 0) * nl + limb) * n + k0;
       uint64_t* o1 = inner + (((size_t)(bj0 + t) * 2 + 1) * nl + limb) * n + k0;
 #pragma unroll
@@ -322,25 +360,34 @@ __global__ __launch_bounds__(256) void k_cp_mac(const uint64_t* __restrict__ pt,
   }
 }
 
-// Tuning knob (does not change any result bit): outputs per block x coefficients per thread.
+// Tuning knob (does not change any result bit): outputs per block x coefficients per thread
+// x unroll of the input loop x split full / partial tiles.
 void launch_cp_mac(blb_ctx* c, const uint64_t* pt, const uint64_t* const* rx_tab, uint64_t* inner, int nl, int n_ai, int n_bj, int variant) {
-  int TB = 8, CPT = 2;
-  switch (variant) {
-    case 1: TB = 8; CPT = 1; break;
-    case 2: TB = 16; CPT = 2; break;
-    case 3: TB = 4; CPT = 2; break;
-    case 4: TB = 12; CPT = 2; break;
-    default: break;
-  }
-  const int n_kblk = c->n / (256 * CPT);
-  const int n_tiles = (n_bj + TB - 1) / TB;
+  struct Shape { int tb, cpt; };
+  static const Shape shapes[BLB_MAC_VARIANTS] = {{8, 2}, {8, 1}, {16, 2}, {4, 2}, {12, 2}, {2, 2}, {4, 2}, {2, 2}, {4, 1}, {4, 1},
+                                                 {4, 2}, {4, 2}, {8, 1}, {4, 1}};
+  const Shape sh = shapes[(variant >= 0 && variant < BLB_MAC_VARIANTS) ? variant : 0];
+  const int n_kblk = c->n / (256 * sh.cpt);
+  const int n_tiles = (n_bj + sh.tb - 1) / sh.tb;
   const int blocks = n_kblk * nl * n_tiles;
-#define CPMAC(tb, cpt) k_cp_mac<tb, cpt><<<blocks, 256, 0, c->stream>>>(pt, rx_tab, inner, c->n, nl, n_ai, n_bj, c->mt, n_kblk, n_tiles)
-  if (TB == 8 && CPT == 2) CPMAC(8, 2);
-  else if (TB == 8 && CPT == 1) CPMAC(8, 1);
-  else if (TB == 16) CPMAC(16, 2);
-  else if (TB == 4) CPMAC(4, 2);
-  else CPMAC(12, 2);
+#define CPMAC(tb, cpt, unr, split) \
+  k_cp_mac<tb, cpt, unr, split><<<blocks, 256, 0, c->stream>>>(pt, rx_tab, inner, c->n, nl, n_ai, n_bj, c->mt, n_kblk, n_tiles)
+  switch (variant) {
+    case 1: CPMAC(8, 1, 1, false); break;
+    case 2: CPMAC(16, 2, 1, false); break;
+    case 3: CPMAC(4, 2, 1, false); break;
+    case 4: CPMAC(12, 2, 1, false); break;
+    case 5: CPMAC(2, 2, 1, false); break;
+    case 6: CPMAC(4, 2, 2, false); break;
+    case 7: CPMAC(2, 2, 2, false); break;
+    case 8: CPMAC(4, 1, 1, false); break;
+    case 9: CPMAC(4, 1, 2, false); break;
+    case 10: CPMAC(4, 2, 2, true); break;
+    case 11: CPMAC(4, 2, 1, true); break;
+    case 12: CPMAC(8, 1, 1, true); break;
+    case 13: CPMAC(4, 1, 2, true); break;
+    default: CPMAC(8, 2, 1, false); break;
+  }
 #undef CPMAC
 }
 

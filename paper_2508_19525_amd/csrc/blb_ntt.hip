@@ -49,7 +49,11 @@ struct Pass {
       const int t_loc = GS >> (u + 1);
 #pragma unroll
       for (int h = 0; h < GPT; ++h) {
-        const int hi = (tid + h * T) / TL;
+        // group index; compile-time when a pass spans whole columns (first pass), and uniform
+        // over the 64-lane wave when TL >= 64, so the twiddles come through scalar loads
+        int hi = (tid + h * T) / TL;
+        if constexpr (TL >= T) hi = (h * T) / TL;
+        else if constexpr (TL >= 64) hi = __builtin_amdgcn_readfirstlane(hi);
 #pragma unroll
         for (int k = 0; k < GS; ++k) {
           if (k & t_loc) continue;
@@ -77,15 +81,25 @@ struct Pass {
   }
 };
 
+// Workgroup barrier that orders LDS accesses only: global loads in flight (the persistent
+// kernel's prefetch of the next polynomial) are not waited for, unlike __syncthreads().
+// Global memory is never exchanged between work-items of a workgroup here: each work-item
+// consumes its own loads before its first barrier, and stores come after the last one.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Move the register values from the layout of pass PA to the layout of pass PB through LDS.
 // The leading barrier keeps the writes behind every read of the previous exchange (also of
 // the previous polynomial in the persistent kernel).
 template <class PA, class PB>
 __device__ __forceinline__ void relayout(double* lds, double (&x)[kPerThread], int tid) {
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int i = 0; i < kPerThread; ++i) lds[pad_idx(PA::idx(tid, i))] = x[i];
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int i = 0; i < kPerThread; ++i) x[i] = lds[pad_idx(PB::idx(tid, i))];
 }
@@ -174,30 +188,44 @@ __global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt(const PolyDesc
 // Persistent, software-pipelined variant: a grid of resident workgroups walks the descriptor
 // list with a grid stride; the next polynomial's operands are loaded into registers while the
 // current one is transformed, hiding the global-memory latency that a one-shot workgroup (one
-// per CU at N = 16384) exposes.
+// per CU at N = 16384) exposes.  At N = 16384 (1024 work-items, at most 128 registers each)
+// only the first half of the next operands is prefetched, which keeps it free of spills.
 template <int LOGN, bool FWD, class LoadOp, class StoreOp>
 __global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt_pipe(const PolyDesc* __restrict__ descs, const double* __restrict__ tw_all,
                                                                      ModTable mt, LoadOp ld, StoreOp st, int count) {
   constexpr int N = 1 << LOGN;
+  constexpr int PF = kPerThread;
+  using First = FirstPass<LOGN, FWD>;
   __shared__ double lds[N + N / 16];
-  const int tid = threadIdx.x;
+  const int tid0 = threadIdx.x;
   int p = blockIdx.x;
   if (p >= count) return;
-  double nx[kPerThread];
+  double nx[PF];
   {
     const PolyDesc d = descs[p];
-    ntt_load<LOGN, FWD>(nx, d, ld, mt.m[d.mod].q, mt.m[d.mod].qinv, tid);
+#pragma unroll
+    for (int i = 0; i < PF; ++i) nx[i] = ld(d, First::idx(tid0, i), mt.m[d.mod].q, mt.m[d.mod].qinv);
   }
   for (;;) {
+    // an opaque copy of the work-item index: keeps the compiler from hoisting every
+    // index computation of the loop body out of the loop (which would spill registers)
+    int tid = tid0;
+    asm volatile("" : "+v"(tid));
     const PolyDesc d = descs[p];
     const double q = mt.m[d.mod].q, qi = mt.m[d.mod].qinv;
     double x[kPerThread];
 #pragma unroll
-    for (int i = 0; i < kPerThread; ++i) x[i] = nx[i];
+    for (int i = 0; i < PF; ++i) x[i] = nx[i];
+#pragma unroll
+    for (int i = PF; i < kPerThread; ++i) x[i] = ld(d, First::idx(tid, i), q, qi);
     const int pn = p + gridDim.x;
-    if (pn < count) {
-      const PolyDesc dn = descs[pn];
-      ntt_load<LOGN, FWD>(nx, dn, ld, mt.m[dn.mod].q, mt.m[dn.mod].qinv, tid);
+    {
+      // unconditional (the last round re-reads its own polynomial), so the loads land in nx
+      // directly and are only waited for when the next round starts
+      const PolyDesc dn = descs[pn < count ? pn : p];
+      const double qn = mt.m[dn.mod].q, qin = mt.m[dn.mod].qinv;
+#pragma unroll
+      for (int i = 0; i < PF; ++i) nx[i] = ld(dn, First::idx(tid, i), qn, qin);
     }
     ntt_core<LOGN, FWD>(lds, x, tw_all + (size_t)d.mod * N, q, qi, tid);
     ntt_store<LOGN, FWD>(x, d, st, q, qi, mt.m[d.mod].ninv, tid);
@@ -234,19 +262,25 @@ void launch_ntt_generic(blb_ctx* c, const PolyDesc* d_descs, int count, LoadOp l
 }  // namespace
 
 // ---------------------------------------------------------------------------------------
-// Load / store variants
+// Load / store variants.  Descriptor pointers are global memory; accessing them through the
+// global address space (not generic) keeps the loads off the LDS counter, so the LDS-only
+// barriers do not wait for them, and lets a uniform base pointer stay in scalar registers.
 // ---------------------------------------------------------------------------------------
+typedef __attribute__((address_space(1))) uint64_t gu64;
+__device__ __forceinline__ uint64_t gld(const uint64_t* p, int j) { return ((const gu64*)p)[j]; }
+__device__ __forceinline__ void gst(uint64_t* p, int j, uint64_t v) { ((gu64*)p)[j] = v; }
+
 struct LdPlain {
-  __device__ double operator()(const PolyDesc& d, int j, double, double) const { return u2d(d.src[j]); }
+  __device__ double operator()(const PolyDesc& d, int j, double, double) const { return u2d(gld(d.src, j)); }
 };
 struct StPlain {
-  __device__ void operator()(const PolyDesc& d, int j, double v, double, double) const { d.dst[j] = d2u(v); }
+  __device__ void operator()(const PolyDesc& d, int j, double v, double, double) const { gst(d.dst, j, d2u(v)); }
 };
 // load a residue of another modulus (aux = that modulus as double) and lift it centred into
 // this modulus: used by rescale (last limb -> limb i)
 struct LdCentredLift {
   __device__ double operator()(const PolyDesc& d, int j, double q, double qi) const {
-    const double v = u2d(d.src[j]);
+    const double v = u2d(gld(d.src, j));
     const double ql = d.aux;
     const double t = v > 0.5 * ql ? v - ql : v;  // centred, |t| < q_l / 2
     return reduce_s(t, q, qi);
@@ -255,31 +289,31 @@ struct LdCentredLift {
 // rescale epilogue: dst[j] <- (c_i[j] - v) * q_l^-1 mod q_i, c_i = d.src2, aux2 = q_l^-1 mod q_i
 struct StRescale {
   __device__ void operator()(const PolyDesc& d, int j, double v, double q, double qi) const {
-    const double ci = u2d(d.src2[j]);
+    const double ci = u2d(gld(d.src2, j));
     const double r = mulmod_s(ci - v, d.aux2, q, qi);
-    d.dst[j] = d2u(canon(r, q));
+    gst(d.dst, j, d2u(canon(r, q)));
   }
 };
 // ModDown epilogue: dst[j] <- (u_i[j] - v) * P^-1 (+ add[j] if src3), u_i = src2 (u64)
 struct StModDown {
   __device__ void operator()(const PolyDesc& d, int j, double v, double q, double qi) const {
-    const double ui = u2d(d.src2[j]);
+    const double ui = u2d(gld(d.src2, j));
     double r = canon(mulmod_s(ui - v, d.aux2, q, qi), q);
     if (d.src3) {
       const uint32_t jj = d.gal ? gal_perm((uint32_t)j, d.gal, d.log_n) : (uint32_t)j;
-      r += u2d(d.src3[jj]);
+      r += u2d(gld(d.src3, (int)jj));
       r = r >= q ? r - q : r;
     }
-    d.dst[j] = d2u(r);
+    gst(d.dst, j, d2u(r));
   }
 };
 
 // add-into epilogue: dst[j] <- src2[j] + v mod q  (mask added to c0 in evaluation form)
 struct StAddTo {
   __device__ void operator()(const PolyDesc& d, int j, double v, double q, double) const {
-    double r = u2d(d.src2[j]) + v;
+    double r = u2d(gld(d.src2, j)) + v;
     r = r >= q ? r - q : r;
-    d.dst[j] = d2u(r);
+    gst(d.dst, j, d2u(r));
   }
 };
 

@@ -436,7 +436,8 @@ def test_ntt_variants_bit_identical(c3s):
     B = c3s.B
     r = _cc_case(c3s, 8, 32, 32, 11)
     base = [c3s.export(x) for x in r["C"]]
-    B.blb_ctx_set_knob(c3s.h, B.BLB_KNOB_NTT_VARIANT, 1)
+    default = B.blb_ctx_get_knob(c3s.h, B.BLB_KNOB_NTT_VARIANT)
+    B.blb_ctx_set_knob(c3s.h, B.BLB_KNOB_NTT_VARIANT, 1 - default)
     try:
         C2 = [c3s.ct(r["level"] - 3) for _ in range(len(r["C"]))]
         B.blb_matmul_cc(c3s.h, r["keys_g"], r["plan"], r["A"], r["B"], C2)
@@ -445,17 +446,22 @@ def test_ntt_variants_bit_identical(c3s):
         for o in range(len(r["want"][0][0])):
             assert np.array_equal(c3s.export(C2[o]), r["want"][0][0][o])
     finally:
-        B.blb_ctx_set_knob(c3s.h, B.BLB_KNOB_NTT_VARIANT, 0)
+        B.blb_ctx_set_knob(c3s.h, B.BLB_KNOB_NTT_VARIANT, default)
     B.blb_plan_destroy(r["plan"])
     B.blb_keys_destroy(r["keys_g"])
 
 
-def test_mac_variants_bit_identical(c2s):
+@pytest.mark.parametrize("shape", [(64, 96, 64), (20, 1, 24)])
+def test_mac_variants_bit_identical(c2s, shape):
+    """Every MAC launch shape gives the same words (the second shape has a single rotated input,
+    so the unrolled variants run their remainder loop, and a partial last output tile)."""
     B = c2s.B
-    r = _cp_case(c2s, 64, 96, 64, 2, 5, x_std=1.0)
+    r = _cp_case(c2s, *shape, 2, 5, x_std=1.0)
     base = [c2s.export(y) for y in r["Yc"]]
+    want = r["keys_o"].matmul_cp(r["X_words"], 2, r["W"], shape[0])
+    assert all(np.array_equal(base[b], want[b]) for b in range(len(base)))
     Xc = _xcts(c2s, r, 2)
-    for var in range(5):
+    for var in range(B.BLB_MAC_VARIANTS):
         B.blb_ctx_set_knob(c2s.h, B.BLB_KNOB_MAC_VARIANT, var)
         Y = [c2s.ct(1) for _ in range(len(base))]
         B.blb_matmul_cp(c2s.h, r["keys_g"], r["plan"], Xc, Y)
@@ -491,6 +497,7 @@ def test_ntt_matches_oracle(request, name, n_polys, variant):
     rng = np.random.default_rng(1000 + n_polys)
     words = np.stack([np.stack([rng.integers(0, int(q), c.n, dtype=np.uint64) for q in mods]) for _ in range(n_polys)])
     dev = c.upload_words(words)
+    default = B.blb_ctx_get_knob(c.h, B.BLB_KNOB_NTT_VARIANT)
     B.blb_ctx_set_knob(c.h, B.BLB_KNOB_NTT_VARIANT, variant)
     try:
         B.blb_ntt(c.h, dev, n_polys, nl, inverse=False)
@@ -506,7 +513,7 @@ def test_ntt_matches_oracle(request, name, n_polys, variant):
         back = dev.cpu().numpy().view(np.uint64).reshape(n_polys, nl, c.n)
         assert np.array_equal(back, words)
     finally:
-        B.blb_ctx_set_knob(c.h, B.BLB_KNOB_NTT_VARIANT, 0)
+        B.blb_ctx_set_knob(c.h, B.BLB_KNOB_NTT_VARIANT, default)
     with pytest.raises(B.BlbError):
         B.blb_ntt(c.h, dev, 1, nl + 1)
     B.blb_ntt(c.h, dev, 0, 1)
