@@ -29,6 +29,23 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 
+# HBM bytes per k_cp_mac launch on the BERT-base workload, by launch variant: rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch), each scaled by what the counter reads for a
+# plain 1 GiB copy (FETCH_SIZE x 1.99981, WRITE_SIZE x 1.0).  Valid only for the MAC source text
+# with this hash; any later change of that code reports traffic as null until re-measured.
+MAC_TRAFFIC_SRC_SHA256 = "0bbdaa4037a560f21b464eb00dc9e8562491c2bae7a0f7048babf1af5db2bc15"
+MAC_TRAFFIC_BYTES = {0: 3772255748, 1: 3759417293, 2: 3775985761, 3: 3774165864, 4: 3742168526, 5: 3780224342, 6: 3787542265,
+                     7: 3787866206, 8: 3748317708, 9: 3746432573, 10: 3864620077, 11: 3813634323, 12: 3800206758, 13: 3807150531}
+
+
+def mac_traffic(variant):
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2508_19525_amd", "csrc", "blb_kernels.hip")).read()
+    a, b = src.find("// One block's (tile, k-chunk, limb)"), src.find("// out[o] = sum_t src[o * n_terms + t]")
+    if a < 0 or b < 0 or hashlib.sha256(src[a:b].encode()).hexdigest() != MAC_TRAFFIC_SRC_SHA256:
+        return None
+    return MAC_TRAFFIC_BYTES.get(variant)
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -333,6 +350,7 @@ def run_batch(args, B, torch):
     shapes = wl.batch_instances(cfg["n_inst"], cfg["L_lo"], cfg["L_hi"], cfg["hidden"])
     stream = torch.cuda.current_stream().cuda_stream
     ctx = B.blb_ctx_create(p.log_n, p.n_q, p.n_special, p.dnum, 0, stream)
+    B.blb_ctx_set_knob(ctx, B.BLB_KNOB_MAC_VARIANT, getattr(args, "tuned_mac_variant", 0))
     t_setup = time.time()
     Ws = {D: wl.batch_weights(D) for D in cfg["hidden"]}
     plans, insts, keep = {}, [], []
@@ -621,6 +639,7 @@ def main():
     r = run_cp(args, B, torch)
     nt = None if args.no_ntt else run_ntt(args, B, torch)
     cc = None if args.no_cc else run_cc(args, B, torch)
+    args.tuned_mac_variant = r["mac_variant"]  # the per-instance (unbatched) path uses the tuned MAC shape too
     bt = None if args.no_batch else run_batch(args, B, torch)
     sv = None if args.no_serve else run_serving(args, B, torch)
     cpu = None
@@ -647,7 +666,7 @@ def main():
             "global_batch": 1, "seq_len": 128, "parallelism": "none (1 GPU)"},
         "roofline": {
             "bound": "hbm", "achieved": r["mac_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": r["mac_gbps"] / HBM_PEAK_GBPS, "traffic": None,
+            "frac": r["mac_gbps"] / HBM_PEAK_GBPS, "traffic": mac_traffic(r["mac_variant"]),
             "kernel": "k_cp_mac (plaintext-streaming ct-pt MAC)",
             "alg_bytes_per_launch": r["mac_alg_bytes"], "avg_launch_ms": r["mac_avg_ms"]},
         "eager_value": r["eager_ops_s"],
