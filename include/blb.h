@@ -247,8 +247,9 @@ void blb_exec_destroy(blb_exec* exec);
  * A worker thread owns the context while the server exists (create keys and buffers before
  * creating it; afterwards use the context only through the server calls).  Weights are
  * registered once (host copy kept); the diagonal plaintexts of (weight, L') are generated on
- * the device when a request needs them and kept in a plan cache of at most plan_cache_bytes,
- * evicting least-recently-used plans no running request uses.  A request is admitted when its
+ * the device when a request needs them and kept in a plan cache: one device allocation of
+ * plan_cache_bytes made at creation (ENOMEM if it cannot be made), carved into plans first-fit,
+ * evicting least-recently-used plans no running request uses until a contiguous range is free.  A request is admitted when its
  * plan is resident or fits; admitted requests join the next batch (one blb_batch_matmul_cp
  * plus per-request mask-and-share) launched on one of n_streams streams, so requests that
  * arrive while earlier batches run are admitted and overlap with them.  Latency is measured

@@ -1105,9 +1105,14 @@ int cp_check_keys(const blb_ctx* c, const blb_keys* K, int L, int d_in, int d_ou
   return BLB_OK;
 }
 
-extern "C" {
+size_t cp_plan_bytes(const blb_ctx* c, int L, int d_in, int d_out, int level) {
+  const CpGeom g = cp_geometry(c, L, d_in, d_out);
+  return (size_t)g.n_out * g.G * g.n_in * g.B * (level + 1) * c->n * 8;
+}
 
-int blb_plan_matmul_cp(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, blb_plan** out) {
+// matmul_cp plan; the plaintexts go to `mem` (cp_plan_bytes bytes, caller-owned) when given,
+// else to library memory
+int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, uint64_t* mem, blb_plan** out) {
   if (!c || !W || !out || d_in < 1 || d_out < 1 || L < 1 || L > c->n / 2 || level < 1 || level >= c->n_q) return BLB_EINVAL;
   *out = nullptr;
   const CpGeom g = cp_geometry(c, L, d_in, d_out);
@@ -1121,8 +1126,11 @@ int blb_plan_matmul_cp(blb_ctx* c, const double* W, int d_in, int d_out, int L, 
   P->level = level;
   P->g = g;
   P->bytes = n_pt * nl * n * 8;
-  int rc = dalloc(c, (void**)&P->pt, P->bytes);
-  if (rc) {
+  int rc = BLB_OK;
+  if (mem) {
+    P->pt = mem;
+    P->owns_pt = false;
+  } else if ((rc = dalloc(c, (void**)&P->pt, P->bytes))) {
     delete P;
     return rc;
   }
@@ -1168,10 +1176,16 @@ int blb_plan_matmul_cp(blb_ctx* c, const double* W, int d_in, int d_out, int L, 
   return BLB_OK;
 }
 
+extern "C" {
+
+int blb_plan_matmul_cp(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, blb_plan** out) {
+  return cp_plan_create(c, W, d_in, d_out, L, level, nullptr, out);
+}
+
 void blb_plan_destroy(blb_plan* P) {
   if (!P) return;
   (void)hipStreamSynchronize(P->ctx->stream);
-  dfree(P->ctx, P->pt, P->bytes);
+  if (P->owns_pt) dfree(P->ctx, P->pt, P->bytes);
   for (size_t i = 0; i < P->extra.size(); ++i) dfree(P->ctx, P->extra[i], P->extra_bytes[i]);
   delete P;
 }

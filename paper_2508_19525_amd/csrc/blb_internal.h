@@ -217,6 +217,7 @@ struct blb_plan {
   int level;  // input level
   int hom1 = 0;  // matmul_cc: step 1 (row pre-rotation of B) runs on the server
   CpGeom g;
+  bool owns_pt = true;  // false: pt lives in caller memory (the serving plan arena)
   uint64_t* pt;  // matmul_cp: [(b, j)][(a, i)][limb][N] evaluation-form plaintexts
                  // matmul_cc: [2][L'][limb][N] step-2 masks M^lo_t, M^hi_t (level, scale q_level 2^10)
   size_t bytes;
@@ -234,6 +235,8 @@ struct PolyDesc;
 void launch_sample_uniform(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag);
 void launch_sample_int(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag, bool gaussian);
 int cp_check_keys(const blb_ctx* c, const blb_keys* K, int L, int d_in, int d_out);
+size_t cp_plan_bytes(const blb_ctx* c, int L, int d_in, int d_out, int level);
+int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, uint64_t* mem, blb_plan** out);
 void launch_sample_flood(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag, int bits);
 void upload_cdt(const uint64_t* table20);
 

@@ -550,6 +550,38 @@ __global__ void k_enc_stage(const double* in, double* out, const double* tw /* [
   st_cdd(y + (size_t)(idx + ns) * 4, cdd_sub(a, b));
 }
 
+// one radix-4 Stockham pass (two radix-2 stages at once, forward sign), same layout: thread j
+// (k = j mod ns) reads x[j + r M/4], twiddles them by exp(-2 pi i r k / (4 ns)), runs a 4-point
+// DFT and writes y[(j / ns) 4 ns + k + r ns].  Half the global-memory passes of radix 2.
+__global__ void k_enc_stage4(const double* in, double* out, const double* tw /* [M/2][4] eta^k */, int M, int ns) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (j >= M / 4) return;
+  const double* x = in + (size_t)p * M * 4;
+  double* y = out + (size_t)p * M * 4;
+  const int k = j % ns;
+  const int step = M / (4 * ns);
+  const int half = M / 2;
+  cdd v[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) v[r] = ld_cdd(x + (size_t)(j + r * (M / 4)) * 4);
+#pragma unroll
+  for (int r = 1; r < 4; ++r) {
+    const int e = r * k * step;  // < 3M/4; eta^(e) = -eta^(e - M/2) past M/2
+    cdd w = ld_cdd(tw + (size_t)(e >= half ? e - half : e) * 4);
+    w.im = dd_neg(w.im);  // exp(-2 pi i e / M)
+    if (e >= half) { w.re = dd_neg(w.re); w.im = dd_neg(w.im); }
+    v[r] = cdd_mul(v[r], w);
+  }
+  const cdd t0 = cdd_add(v[0], v[2]), t1 = cdd_sub(v[0], v[2]), t2 = cdd_add(v[1], v[3]), d = cdd_sub(v[1], v[3]);
+  const cdd t3 = cdd{d.im, dd_neg(d.re)};  // (v1 - v3) * (-i)
+  const int idx = (j / ns) * 4 * ns + k;
+  st_cdd(y + (size_t)idx * 4, cdd_add(t0, t2));
+  st_cdd(y + (size_t)(idx + ns) * 4, cdd_add(t1, t3));
+  st_cdd(y + (size_t)(idx + 2 * ns) * 4, cdd_sub(t0, t2));
+  st_cdd(y + (size_t)(idx + 3 * ns) * 4, cdd_sub(t1, t3));
+}
+
 __device__ __forceinline__ long long rhaz_dd(dd x, int* overflow) {
   const bool neg = x.hi < 0.0;
   if (neg) x = dd_neg(x);
@@ -589,9 +621,16 @@ int run_encode_core(blb_ctx* c, double* bufA, double* bufB, int count, double sc
   const int M = c->n / 2;
   double* in = bufA;
   double* outb = bufB;
-  for (int ns = 1; ns < M; ns *= 2) {
+  int ns = 1;
+  if ((c->log_n - 1) & 1) {  // odd number of stages: one radix-2 stage first
     dim3 grid((M / 2 + 255) / 256, count);
     k_enc_stage<<<grid, 256, 0, c->stream>>>(in, outb, c->d_enc_tw, M, ns);
+    double* t = in; in = outb; outb = t;
+    ns = 2;
+  }
+  for (; ns < M; ns *= 4) {
+    dim3 grid((M / 4 + 255) / 256, count);
+    k_enc_stage4<<<grid, 256, 0, c->stream>>>(in, outb, c->d_enc_tw, M, ns);
     double* t = in; in = outb; outb = t;
   }
   dim3 grid((M + 255) / 256, count);

@@ -161,12 +161,14 @@ __device__ __forceinline__ void ntt_load(double (&x)[kPerThread], const PolyDesc
 // canonical results of the last pass to global memory (the inverse applies N^-1 here; the
 // lazy passes leave |x| below ~2.5 q, which canon_full brings into [0, q))
 template <int LOGN, bool FWD, class StoreOp>
-__device__ __forceinline__ void ntt_store(double (&x)[kPerThread], const PolyDesc& d, const StoreOp& st, double q, double qi, double ninv, int tid) {
+__device__ __forceinline__ void ntt_store(double (&x)[kPerThread], const PolyDesc& d, const StoreOp& st, double q, double qi, double ninv, int tid,
+                                          double* lds) {
+  st.prepare(d, lds, tid);  // the epilogue may stage an operand in LDS (free after the last pass)
 #pragma unroll
   for (int i = 0; i < kPerThread; ++i) {
     const int j = LastPass<LOGN, FWD>::idx(tid, i);
     const double v = FWD ? canon(x[i], q) : canon_full(mulmod_s(x[i], ninv, q, qi), q, qi);
-    st(d, j, v, q, qi);
+    st(d, j, v, q, qi, lds);
   }
 }
 
@@ -182,7 +184,7 @@ __global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt(const PolyDesc
   double x[kPerThread];
   ntt_load<LOGN, FWD>(x, d, ld, q, qi, tid);
   ntt_core<LOGN, FWD>(lds, x, tw_all + (size_t)d.mod * N, q, qi, tid);
-  ntt_store<LOGN, FWD>(x, d, st, q, qi, mt.m[d.mod].ninv, tid);
+  ntt_store<LOGN, FWD>(x, d, st, q, qi, mt.m[d.mod].ninv, tid, lds);
 }
 
 // Persistent, software-pipelined variant: a grid of resident workgroups walks the descriptor
@@ -228,7 +230,7 @@ __global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt_pipe(const Pol
       for (int i = 0; i < PF; ++i) nx[i] = ld(dn, First::idx(tid, i), qn, qin);
     }
     ntt_core<LOGN, FWD>(lds, x, tw_all + (size_t)d.mod * N, q, qi, tid);
-    ntt_store<LOGN, FWD>(x, d, st, q, qi, mt.m[d.mod].ninv, tid);
+    ntt_store<LOGN, FWD>(x, d, st, q, qi, mt.m[d.mod].ninv, tid, lds);
     p = pn;
     if (p >= count) break;
   }
@@ -274,7 +276,8 @@ struct LdPlain {
   __device__ double operator()(const PolyDesc& d, int j, double, double) const { return u2d(gld(d.src, j)); }
 };
 struct StPlain {
-  __device__ void operator()(const PolyDesc& d, int j, double v, double, double) const { gst(d.dst, j, d2u(v)); }
+  __device__ void prepare(const PolyDesc&, double*, int) const {}
+  __device__ void operator()(const PolyDesc& d, int j, double v, double, double, const double*) const { gst(d.dst, j, d2u(v)); }
 };
 // load a residue of another modulus (aux = that modulus as double) and lift it centred into
 // this modulus: used by rescale (last limb -> limb i)
@@ -288,20 +291,33 @@ struct LdCentredLift {
 };
 // rescale epilogue: dst[j] <- (c_i[j] - v) * q_l^-1 mod q_i, c_i = d.src2, aux2 = q_l^-1 mod q_i
 struct StRescale {
-  __device__ void operator()(const PolyDesc& d, int j, double v, double q, double qi) const {
+  __device__ void prepare(const PolyDesc&, double*, int) const {}
+  __device__ void operator()(const PolyDesc& d, int j, double v, double q, double qi, const double*) const {
     const double ci = u2d(gld(d.src2, j));
     const double r = mulmod_s(ci - v, d.aux2, q, qi);
     gst(d.dst, j, d2u(canon(r, q)));
   }
 };
-// ModDown epilogue: dst[j] <- (u_i[j] - v) * P^-1 (+ add[j] if src3), u_i = src2 (u64)
+// ModDown epilogue: dst[j] <- (u_i[j] - v) * P^-1 (+ add[j] if src3), u_i = src2 (u64).
+// For a rotation add = sigma_g(c0), a permuted read of src3: src3 is first staged in LDS with
+// coalesced reads, then read there at the permuted index.
 struct StModDown {
-  __device__ void operator()(const PolyDesc& d, int j, double v, double q, double qi) const {
+  __device__ void prepare(const PolyDesc& d, double* lds, int tid) const {
+    if (!d.src3 || !d.gal) return;  // uniform over the workgroup (one descriptor)
+    const int T = (1 << d.log_n) / kPerThread;
+    lds_barrier();
+#pragma unroll
+    for (int i = 0; i < kPerThread; ++i) {
+      const int j = tid + i * T;
+      lds[pad_idx(j)] = u2d(gld(d.src3, j));
+    }
+    lds_barrier();
+  }
+  __device__ void operator()(const PolyDesc& d, int j, double v, double q, double qi, const double* lds) const {
     const double ui = u2d(gld(d.src2, j));
     double r = canon(mulmod_s(ui - v, d.aux2, q, qi), q);
     if (d.src3) {
-      const uint32_t jj = d.gal ? gal_perm((uint32_t)j, d.gal, d.log_n) : (uint32_t)j;
-      r += u2d(gld(d.src3, (int)jj));
+      r += d.gal ? lds[pad_idx((int)gal_perm((uint32_t)j, d.gal, d.log_n))] : u2d(gld(d.src3, j));
       r = r >= q ? r - q : r;
     }
     gst(d.dst, j, d2u(r));
@@ -310,7 +326,8 @@ struct StModDown {
 
 // add-into epilogue: dst[j] <- src2[j] + v mod q  (mask added to c0 in evaluation form)
 struct StAddTo {
-  __device__ void operator()(const PolyDesc& d, int j, double v, double q, double) const {
+  __device__ void prepare(const PolyDesc&, double*, int) const {}
+  __device__ void operator()(const PolyDesc& d, int j, double v, double q, double, const double*) const {
     double r = u2d(gld(d.src2, j)) + v;
     r = r >= q ? r - q : r;
     gst(d.dst, j, d2u(r));

@@ -20,6 +20,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <iterator>
 #include <map>
 #include <mutex>
 #include <new>
@@ -43,8 +44,48 @@ struct Weights {
 struct PlanEntry {
   blb_plan* plan = nullptr;
   size_t bytes = 0;
+  size_t off = 0;  // position in the plan arena
   int users = 0;
   double last_use = 0;
+};
+
+// First-fit allocator over one device allocation made when the server starts: plans are
+// carved out of it and returned to it on eviction, so the cache never calls hipMalloc /
+// hipFree (which cost about a millisecond per GB at plan sizes of tens of GB).
+struct Arena {
+  uint64_t* base = nullptr;
+  size_t cap = 0;
+  std::map<size_t, size_t> free_;  // offset -> size, coalesced
+  static constexpr size_t kAlign = 4096;
+  static size_t round(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+  bool alloc(size_t bytes, size_t* off) {
+    const size_t b = round(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= b) {
+        *off = it->first;
+        const size_t rest = it->second - b, at = it->first + b;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        return true;
+      }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    size_t b = round(bytes);
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + b == next->first) {
+      b += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += b;
+        return;
+      }
+    }
+    free_[off] = b;
+  }
 };
 
 struct Request {
@@ -84,6 +125,7 @@ struct blb_server {
   std::map<int, Weights> weights;
   std::map<std::pair<int, int>, PlanEntry> plans;  // (weight id, L') -> plan
   size_t plan_bytes = 0;
+  Arena arena;
   std::mutex mu;
   std::condition_variable cv;
   std::deque<Request*> queue;
@@ -100,26 +142,20 @@ struct blb_server {
 
 namespace {
 
-// make room for `need` bytes of plans by evicting unused LRU plans; true if it fits
-bool make_room(blb_server* S, size_t need) {
-  while (S->plan_bytes + need > S->cfg.plan_cache_bytes) {
+// carve `need` bytes out of the plan arena, evicting least-recently-used plans that no
+// admitted request uses until a contiguous range is free; false if that is impossible now
+bool make_room(blb_server* S, size_t need, size_t* off) {
+  while (!S->arena.alloc(need, off)) {
     auto victim = S->plans.end();
     for (auto it = S->plans.begin(); it != S->plans.end(); ++it)
       if (it->second.users == 0 && (victim == S->plans.end() || it->second.last_use < victim->second.last_use)) victim = it;
     if (victim == S->plans.end()) return false;
     S->plan_bytes -= victim->second.bytes;
     blb_plan_destroy(victim->second.plan);
+    S->arena.release(victim->second.off, victim->second.bytes);
     S->plans.erase(victim);
   }
   return true;
-}
-
-size_t plan_bytes_estimate(const blb_ctx* c, const Weights& w, int Lp) {
-  const int s = c->n / 2, cc = s / Lp;
-  const int din_p = 1 << ceil_log2i(w.d_in);
-  const int c_eff = std::min(cc, din_p);
-  const size_t n_in = (w.d_in + cc - 1) / cc, n_out = (w.d_out + cc - 1) / cc;
-  return n_in * n_out * (size_t)c_eff * (w.level + 1) * c->n * 8;
 }
 
 // returns 1 admitted, 0 must wait, < 0 rejected (error code)
@@ -135,18 +171,22 @@ int admit(blb_server* S, Request* r) {
     return 1;
   }
   const Weights& w = S->weights[r->weight_id];
-  const size_t need = plan_bytes_estimate(c, w, r->Lp);
-  if (need > S->cfg.plan_cache_bytes) return BLB_ENOMEM;
-  if (!make_room(S, need)) return 0;  // memory frees up when running batches finish
+  const size_t need = cp_plan_bytes(c, r->Lp, w.d_in, w.d_out, w.level);
+  if (Arena::round(need) > S->arena.cap) return BLB_ENOMEM;
+  size_t off = 0;
+  if (!make_room(S, need, &off)) return 0;  // memory frees up when running batches finish
   const double t0 = now_s();
   blb_plan* P = nullptr;
-  const int rc = blb_plan_matmul_cp(c, w.W.data(), w.d_in, w.d_out, r->Lp, w.level, &P);
-  if (rc == BLB_ENOMEM) return 0;
-  if (rc) return rc;
+  const int rc = cp_plan_create(c, w.W.data(), w.d_in, w.d_out, r->Lp, w.level, (uint64_t*)((char*)S->arena.base + off), &P);
+  if (rc) {
+    S->arena.release(off, need);
+    return rc == BLB_ENOMEM ? 0 : rc;
+  }
   S->gen_s += now_s() - t0;
   ++S->misses;
   PlanEntry& pe = S->plans[key];
   pe.plan = P;
+  pe.off = off;
   pe.bytes = P->bytes;
   pe.users = 1;
   pe.last_use = now_s();
@@ -300,10 +340,28 @@ int blb_server_create(blb_ctx* c, const blb_server_config* cfg, blb_server** out
   if (!S) return BLB_ENOMEM;
   S->c = c;
   S->cfg = *cfg;
+  S->arena.cap = cfg->plan_cache_bytes / Arena::kAlign * Arena::kAlign;
+  if (S->arena.cap > 0) {
+    if (c->budget && c->dev_bytes + S->arena.cap > c->budget) {
+      delete S;
+      return BLB_ENOMEM;
+    }
+    if (hipMalloc((void**)&S->arena.base, S->arena.cap) != hipSuccess) {
+      (void)hipGetLastError();
+      delete S;
+      return BLB_ENOMEM;
+    }
+    c->dev_bytes += S->arena.cap;
+    S->arena.free_[0] = S->arena.cap;
+  }
   for (int i = 0; i < cfg->n_streams; ++i) {
     hipStream_t s;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
       for (hipStream_t t : S->streams) (void)hipStreamDestroy(t);
+      if (S->arena.base) {
+        (void)hipFree(S->arena.base);
+        c->dev_bytes -= S->arena.cap;
+      }
       delete S;
       return BLB_EDEVICE;
     }
@@ -417,6 +475,10 @@ void blb_server_destroy(blb_server* S) {
     (void)hipStreamDestroy(s);
   }
   for (auto& kv : S->plans) blb_plan_destroy(kv.second.plan);
+  if (S->arena.base) {
+    (void)hipFree(S->arena.base);
+    S->c->dev_bytes -= S->arena.cap;
+  }
   for (auto& kv : S->all) delete kv.second;
   delete S;
 }
