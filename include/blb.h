@@ -279,8 +279,9 @@ int blb_server_submit(blb_server* server, const blb_keys* keys, int weight_id, i
 int blb_server_poll(blb_server* server, int64_t req_id, int* state, double* latency_ms);
 /* waits until nothing is queued or running (BLB_EBUSY on timeout) */
 int blb_server_drain(blb_server* server, double timeout_s);
-/* out[cap >= 10]: completed, rejected, p50 ms, p99 ms, mean ms, plan hits, plan misses,
- * batches, plan generation seconds, resident plan bytes; out[10] (cap > 10): requests whose
+/* out[cap >= 10]: completed, rejected, p50 ms, p99 ms, mean ms, plan hits (requests whose plan
+ * was ready when first considered), plan misses (plans generated), batches, plan generation
+ * seconds (enqueue to completion), resident plan bytes; out[10] (cap > 10): requests whose
  * batch failed at launch (their poll state holds the error code). */
 int blb_server_stats(blb_server* server, double* out, int cap);
 void blb_server_destroy(blb_server* server);

@@ -147,7 +147,7 @@ int uploader_init(blb_ctx* c) {
 }
 void uploader_free(blb_ctx* c) {
   Uploader& u = c->up;
-  for (auto& e : u.inflight) (void)hipEventDestroy(e.second);
+  for (auto& e : u.inflight) (void)hipEventDestroy(e.copied);
   for (auto e : u.free_events) (void)hipEventDestroy(e);
   if (u.host) (void)hipHostFree(u.host);
   if (u.dev) (void)hipFree(u.dev);
@@ -172,20 +172,19 @@ void* upload(blb_ctx* c, const void* data, size_t bytes) {
   size_t lo = u.head;
   if (lo + bytes > u.cap) lo = 0;
   const size_t hi = lo + bytes;
-  // the pinned region may be read by a copy still in flight: wait for those copies
-  std::deque<std::pair<size_t, hipEvent_t>> keep;
-  size_t prev_end = 0;
-  (void)prev_end;
-  while (!u.inflight.empty()) {
-    auto e = u.inflight.front();
-    u.inflight.pop_front();
-    const size_t e_end = e.first & 0xFFFFFFFFFFull;
-    const size_t e_lo = e.first >> 40;
-    if (e_lo < hi && lo < e_end) {
-      (void)hipEventSynchronize(e.second);
-      u.free_events.push_back(e.second);
-    } else if (hipEventQuery(e.second) == hipSuccess) {
-      u.free_events.push_back(e.second);
+  // Regions about to be overwritten: their host bytes may still be in an unfinished copy (wait
+  // for it), and their device bytes may still be read by kernels of another stream (make this
+  // stream wait for everything that stream has enqueued so far, which includes those kernels).
+  std::deque<UploadRegion> keep;
+  for (const UploadRegion& e : u.inflight) {
+    if (e.lo < hi && lo < e.hi) {
+      (void)hipEventSynchronize(e.copied);
+      if (e.stream != c->stream) {
+        (void)hipEventRecord(e.copied, e.stream);
+        (void)hipStreamWaitEvent(c->stream, e.copied, 0);
+        (void)hipEventSynchronize(e.copied);  // the event is recycled below
+      }
+      u.free_events.push_back(e.copied);
     } else {
       keep.push_back(e);
     }
@@ -203,7 +202,7 @@ void* upload(blb_ctx* c, const void* data, size_t bytes) {
     return u.dev + lo;
   }
   (void)hipEventRecord(ev, c->stream);
-  u.inflight.push_back({(lo << 40) | hi, ev});
+  u.inflight.push_back(UploadRegion{lo, hi, ev, c->stream});
   u.head = hi;
   return u.dev + lo;
 }
@@ -508,7 +507,7 @@ int encode_dense_dev(blb_ctx* c, const double* d_vals, int n_vals, int count, do
   if (tmp.failed) return BLB_ENOMEM;
   launch_enc_scatter_dense(c, d_vals, n_vals, count, a);
   (void)hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream);
-  run_encode_core(c, a, b, count, scale, level + 1, out, c->d_flag);
+  run_encode_core(c, a, b, count, scale, level + 1, out, c->d_flag, false);
   int flag = 0;
   (void)hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
   if (hipStreamSynchronize(c->stream) != hipSuccess) return BLB_EDEVICE;
@@ -516,6 +515,12 @@ int encode_dense_dev(blb_ctx* c, const double* d_vals, int n_vals, int count, do
 }
 
 }  // namespace
+
+// a stream is about to be destroyed after a synchronisation: its regions need no more waiting
+void uploader_forget_stream(blb_ctx* c, hipStream_t s) {
+  for (UploadRegion& e : c->up.inflight)
+    if (e.stream == s) e.stream = c->stream;
+}
 
 // ==========================================================================================
 // C ABI
@@ -1111,8 +1116,10 @@ size_t cp_plan_bytes(const blb_ctx* c, int L, int d_in, int d_out, int level) {
 }
 
 // matmul_cp plan; the plaintexts go to `mem` (cp_plan_bytes bytes, caller-owned) when given,
-// else to library memory
-int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, uint64_t* mem, blb_plan** out) {
+// else to library memory.  With flag_host (pinned) the call returns once the work is enqueued:
+// the encoder's overflow flag lands in *flag_host when the stream reaches it (non-zero: the
+// plan is unusable), and W must stay valid until then.
+int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, uint64_t* mem, blb_plan** out, int* flag_host) {
   if (!c || !W || !out || d_in < 1 || d_out < 1 || L < 1 || L > c->n / 2 || level < 1 || level >= c->n_q) return BLB_EINVAL;
   *out = nullptr;
   const CpGeom g = cp_geometry(c, L, d_in, d_out);
@@ -1156,7 +1163,7 @@ int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int 
       const int cnt = (int)std::min<size_t>(chunk, n_pt - p0);
       launch_enc_scatter_cp(c, dW, g, (int)p0, cnt, a);
       uint64_t* dst = P->pt + p0 * nl * n;
-      run_encode_core(c, a, b, cnt, scale, nl, dst, c->d_flag);
+      run_encode_core(c, a, b, cnt, scale, nl, dst, c->d_flag, true);
       d.clear();
       for (int p = 0; p < cnt; ++p)
         for (int i = 0; i < nl; ++i) {
@@ -1165,11 +1172,19 @@ int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int 
         }
       ntt_descs(c, d, NTT_FWD);
     }
-    int flag = 0;
-    (void)hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
-    if (hipStreamSynchronize(c->stream) != hipSuccess || flag) {
-      blb_plan_destroy(P);
-      return flag ? BLB_EINVAL : BLB_EDEVICE;
+    if (flag_host) {
+      if (hipMemcpyAsync(flag_host, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess) {
+        (void)hipStreamSynchronize(c->stream);
+        blb_plan_destroy(P);
+        return BLB_EDEVICE;
+      }
+    } else {
+      int flag = 0;
+      (void)hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+      if (hipStreamSynchronize(c->stream) != hipSuccess || flag) {
+        blb_plan_destroy(P);
+        return flag ? BLB_EINVAL : BLB_EDEVICE;
+      }
     }
   }
   *out = P;
@@ -1179,7 +1194,7 @@ int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int 
 extern "C" {
 
 int blb_plan_matmul_cp(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, blb_plan** out) {
-  return cp_plan_create(c, W, d_in, d_out, L, level, nullptr, out);
+  return cp_plan_create(c, W, d_in, d_out, L, level, nullptr, out, nullptr);
 }
 
 void blb_plan_destroy(blb_plan* P) {

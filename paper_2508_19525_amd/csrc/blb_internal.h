@@ -122,11 +122,19 @@ struct CpGeom {
 // ---------------------------------------------------------------------------------------
 // Descriptor upload ring: pinned host staging + device mirror; a host region is reused only
 // after the copy that last read it has completed.
+// Pinned staging ring for descriptor tables: host bytes are copied to the same offsets of a
+// device ring on the calling stream.  Each region remembers the copy's completion event and
+// the stream whose kernels read it, until a later upload overwrites it.
+struct UploadRegion {
+  size_t lo, hi;
+  hipEvent_t copied;
+  hipStream_t stream;
+};
 struct Uploader {
   char* host = nullptr;
   char* dev = nullptr;
   size_t cap = 0, head = 0;
-  std::deque<std::pair<size_t, hipEvent_t>> inflight;  // (end offset, event) in ring order
+  std::deque<UploadRegion> inflight;
   std::vector<hipEvent_t> free_events;
 };
 
@@ -235,8 +243,9 @@ struct PolyDesc;
 void launch_sample_uniform(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag);
 void launch_sample_int(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag, bool gaussian);
 int cp_check_keys(const blb_ctx* c, const blb_keys* K, int L, int d_in, int d_out);
+void uploader_forget_stream(blb_ctx* c, hipStream_t s);
 size_t cp_plan_bytes(const blb_ctx* c, int L, int d_in, int d_out, int level);
-int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, uint64_t* mem, blb_plan** out);
+int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, uint64_t* mem, blb_plan** out, int* flag_host);
 void launch_sample_flood(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag, int bits);
 void upload_cdt(const uint64_t* table20);
 
@@ -271,6 +280,7 @@ void launch_masked_acc(blb_ctx* c, const CcTerm* terms, const int* off, uint64_t
 void launch_mask_sample(blb_ctx* c, uint64_t* r_out, uint64_t* share, int n_ct, int tl, uint64_t seed, const uint64_t* seed_dev, uint32_t tag);
 void launch_set_u64(blb_ctx* c, uint64_t* dst, uint64_t value);
 void launch_zero(blb_ctx* c, uint64_t* dst, size_t words);
-int run_encode_core(blb_ctx* c, double* bufA, double* bufB, int count, double scale, int nl, uint64_t* out, int* d_overflow);
+// paired: the buffers hold (count + 1) / 2 complex vectors, each packing two real inputs
+int run_encode_core(blb_ctx* c, double* bufA, double* bufB, int count, double scale, int nl, uint64_t* out, int* d_overflow, bool paired);
 void launch_enc_scatter_dense(blb_ctx* c, const double* vals, int n_vals, int count, double* buf);
 void launch_enc_scatter_cp(blb_ctx* c, const double* W, CpGeom g, int p0, int count, double* buf);

@@ -509,14 +509,11 @@ __global__ void k_enc_scatter_dense(const double* vals, int n_vals, double* buf,
   o[0] = v; o[1] = 0.0; o[2] = 0.0; o[3] = 0.0;
 }
 
-// scatter of matmul_cp diagonal plaintexts: plaintext p = (bj, ai) in a chunk starting at p0:
+// scatter of matmul_cp diagonal plaintexts, two per complex vector (plaintext p0 + 2 pp in the
+// real part, p0 + 2 pp + 1 in the imaginary part); plaintext p = (bj, ai):
 //   value at slot s = W{a c + ((u + t) mod c_eff), b c + (u mod c_out)}, u = ((s - r) mod S) / L',
 //   t = jB + i, r = j B L' (plaintext pre-rotated right by r).
-__global__ void k_enc_scatter_cp(const double* W, CpGeom g, int p0, double* buf, const int32_t* slot_u, int M) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  const int pl = blockIdx.y;
-  if (s >= M) return;
-  const int p = p0 + pl;
+__device__ __forceinline__ double cp_diag_value(const double* W, const CpGeom& g, int p, int s, int M) {
   const int n_ai = g.n_in * g.B;
   const int bj = p / n_ai, ai = p % n_ai;
   const int b = bj / g.G, j = bj % g.G;
@@ -527,9 +524,17 @@ __global__ void k_enc_scatter_cp(const double* W, CpGeom g, int p0, double* buf,
   const int u = slot / g.Lp;
   const int row = a * g.c + (u + t) % g.c_eff;
   const int col = b * g.c + (u % g.c_out);
-  const double v = (row < g.d_in && col < g.d_out) ? W[(size_t)row * g.d_out + col] : 0.0;
-  double* o = buf + ((size_t)pl * M + slot_u[s]) * 4;
-  o[0] = v; o[1] = 0.0; o[2] = 0.0; o[3] = 0.0;
+  return (row < g.d_in && col < g.d_out) ? W[(size_t)row * g.d_out + col] : 0.0;
+}
+__global__ void k_enc_scatter_cp(const double* W, CpGeom g, int p0, int count, double* buf, const int32_t* slot_u, int M) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int pp = blockIdx.y;
+  if (s >= M) return;
+  const int pl = 2 * pp;
+  const double v1 = cp_diag_value(W, g, p0 + pl, s, M);
+  const double v2 = pl + 1 < count ? cp_diag_value(W, g, p0 + pl + 1, s, M) : 0.0;
+  double* o = buf + ((size_t)pp * M + slot_u[s]) * 4;
+  o[0] = v1; o[1] = 0.0; o[2] = v2; o[3] = 0.0;
 }
 
 // one radix-2 Stockham stage (forward sign) on [count][M] complex dd values
@@ -594,12 +599,20 @@ __device__ __forceinline__ long long rhaz_dd(dd x, int* overflow) {
 
 // finalize: w_k = zeta^-k * y_k * (Delta / M); p_k = RHAZ(Re w_k), p_{k+M} = RHAZ(Im w_k);
 // residues into limbs 0..level of out[p][limb][N]
-__global__ void k_enc_final(const double* ybuf, const double* twist /* [M][4] zeta^-k */, double scale_over_m, int M, int nl,
-                            ModTable mt, const uint64_t* mods, uint64_t* out, int* overflow) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const int p = blockIdx.y;
-  if (k >= M) return;
-  const cdd y = ld_cdd(ybuf + ((size_t)p * M + k) * 4);
+// r mod q for |r| < 2^62 without a 64-bit division: quotient from FP64 (off by at most one),
+// exact remainder in integers, one correction
+__device__ __forceinline__ uint64_t mod_i64(long long r, long long q, double qinv) {
+  const long long t = (long long)rint((double)r * qinv);
+  long long m = r - t * q;
+  if (m < 0) m += q;
+  if (m >= q) m -= q;
+  return (uint64_t)m;
+}
+
+// rounding and residues of one transformed value y_k: w = zeta^-k y_k (Delta / M),
+// p_k = RHAZ(Re w), p_{k+M} = RHAZ(Im w) into limbs 0..nl-1 of out_p[limb][N]
+__device__ __forceinline__ void enc_round_store(cdd y, const double* twist, double scale_over_m, int M, int k, int nl, const ModTable& mt,
+                                                const uint64_t* mods, uint64_t* out_p, int* overflow) {
   const cdd w = cdd_mul(y, ld_cdd(twist + (size_t)k * 4));
   int of = 0;
   const long long pr = rhaz_dd(dd_mul_d(w.re, scale_over_m), &of);
@@ -608,33 +621,65 @@ __global__ void k_enc_final(const double* ybuf, const double* twist /* [M][4] ze
   const int n = 2 * M;
   for (int i = 0; i < nl; ++i) {
     const long long q = (long long)mods[i];
-    long long r0 = pr % q; if (r0 < 0) r0 += q;
-    long long r1 = pi % q; if (r1 < 0) r1 += q;
-    out[((size_t)p * nl + i) * n + k] = (uint64_t)r0;
-    out[((size_t)p * nl + i) * n + k + M] = (uint64_t)r1;
+    const double qinv = mt.m[i].qinv;
+    out_p[(size_t)i * n + k] = mod_i64(pr, q, qinv);
+    out_p[(size_t)i * n + k + M] = mod_i64(pi, q, qinv);
   }
+}
+
+// finalize: w_k = zeta^-k * y_k * (Delta / M); p_k = RHAZ(Re w_k), p_{k+M} = RHAZ(Im w_k);
+// residues into limbs 0..level of out[p][limb][N]
+__global__ void k_enc_final(const double* ybuf, const double* twist /* [M][4] zeta^-k */, double scale_over_m, int M, int nl,
+                            ModTable mt, const uint64_t* mods, uint64_t* out, int* overflow) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (k >= M) return;
+  const cdd y = ld_cdd(ybuf + ((size_t)p * M + k) * 4);
+  enc_round_store(y, twist, scale_over_m, M, k, nl, mt, mods, out + (size_t)p * nl * 2 * M, overflow);
+}
+
+// paired finalize: buffer pp holds FFT(x_{2pp} + i x_{2pp+1}) of two real inputs; their
+// transforms are X1_k = (Y_k + conj Y_{M-k}) / 2 and X2_k = (Y_k - conj Y_{M-k}) / (2i)
+__global__ void k_enc_final_pair(const double* ybuf, const double* twist, double scale_over_m, int M, int nl, ModTable mt,
+                                 const uint64_t* mods, uint64_t* out, int count, int* overflow) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int pp = blockIdx.y;
+  if (k >= M) return;
+  const cdd y = ld_cdd(ybuf + ((size_t)pp * M + k) * 4);
+  const cdd yc = ld_cdd(ybuf + ((size_t)pp * M + (k == 0 ? 0 : M - k)) * 4);
+  const dd half_re1 = dd_add(y.re, yc.re), half_im1 = dd_add(y.im, dd_neg(yc.im));  // Y + conj(Yc)
+  const dd half_re2 = dd_add(y.im, yc.im), half_im2 = dd_add(yc.re, dd_neg(y.re));  // (Y - conj(Yc)) / i
+  const cdd x1 = cdd{dd_mul_d(half_re1, 0.5), dd_mul_d(half_im1, 0.5)};
+  const cdd x2 = cdd{dd_mul_d(half_re2, 0.5), dd_mul_d(half_im2, 0.5)};
+  const size_t stride = (size_t)nl * 2 * M;
+  enc_round_store(x1, twist, scale_over_m, M, k, nl, mt, mods, out + (size_t)(2 * pp) * stride, overflow);
+  if (2 * pp + 1 < count) enc_round_store(x2, twist, scale_over_m, M, k, nl, mt, mods, out + (size_t)(2 * pp + 1) * stride, overflow);
 }
 
 // Encodes `count` plaintexts already scattered into bufA ([count][M][4] doubles); output
 // coefficient-form residues out[count][nl][N].  bufB is a second buffer of the same size.
-int run_encode_core(blb_ctx* c, double* bufA, double* bufB, int count, double scale, int nl, uint64_t* out, int* d_overflow) {
+int run_encode_core(blb_ctx* c, double* bufA, double* bufB, int count, double scale, int nl, uint64_t* out, int* d_overflow, bool paired) {
   const int M = c->n / 2;
+  const int n_vec = paired ? (count + 1) / 2 : count;  // complex vectors transformed
   double* in = bufA;
   double* outb = bufB;
   int ns = 1;
   if ((c->log_n - 1) & 1) {  // odd number of stages: one radix-2 stage first
-    dim3 grid((M / 2 + 255) / 256, count);
+    dim3 grid((M / 2 + 255) / 256, n_vec);
     k_enc_stage<<<grid, 256, 0, c->stream>>>(in, outb, c->d_enc_tw, M, ns);
     double* t = in; in = outb; outb = t;
     ns = 2;
   }
   for (; ns < M; ns *= 4) {
-    dim3 grid((M / 4 + 255) / 256, count);
+    dim3 grid((M / 4 + 255) / 256, n_vec);
     k_enc_stage4<<<grid, 256, 0, c->stream>>>(in, outb, c->d_enc_tw, M, ns);
     double* t = in; in = outb; outb = t;
   }
-  dim3 grid((M + 255) / 256, count);
-  k_enc_final<<<grid, 256, 0, c->stream>>>(in, c->d_enc_twist, scale / (double)M, M, nl, c->mt, c->d_mods, out, d_overflow);
+  dim3 grid((M + 255) / 256, n_vec);
+  if (paired)
+    k_enc_final_pair<<<grid, 256, 0, c->stream>>>(in, c->d_enc_twist, scale / (double)M, M, nl, c->mt, c->d_mods, out, count, d_overflow);
+  else
+    k_enc_final<<<grid, 256, 0, c->stream>>>(in, c->d_enc_twist, scale / (double)M, M, nl, c->mt, c->d_mods, out, d_overflow);
   return 0;
 }
 void launch_enc_scatter_dense(blb_ctx* c, const double* vals, int n_vals, int count, double* buf) {
@@ -644,8 +689,8 @@ void launch_enc_scatter_dense(blb_ctx* c, const double* vals, int n_vals, int co
 }
 void launch_enc_scatter_cp(blb_ctx* c, const double* W, CpGeom g, int p0, int count, double* buf) {
   const int M = c->n / 2;
-  dim3 grid((M + 255) / 256, count);
-  k_enc_scatter_cp<<<grid, 256, 0, c->stream>>>(W, g, p0, buf, c->d_slot_u, M);
+  dim3 grid((M + 255) / 256, (count + 1) / 2);
+  k_enc_scatter_cp<<<grid, 256, 0, c->stream>>>(W, g, p0, count, buf, c->d_slot_u, M);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -45,8 +45,10 @@ struct PlanEntry {
   blb_plan* plan = nullptr;
   size_t bytes = 0;
   size_t off = 0;  // position in the plan arena
-  int users = 0;
+  int users = 0;   // admitted requests (and the generation itself while pending)
   double last_use = 0;
+  bool pending = false;  // generation enqueued, not yet complete
+  hipEvent_t ready = nullptr;
 };
 
 // First-fit allocator over one device allocation made when the server starts: plans are
@@ -102,6 +104,7 @@ struct Request {
   double t_submit = 0, t_done = 0;
   int state = 0;  // 0 queued, 1 running, 2 done, < 0 error code
   PlanEntry* pe = nullptr;
+  bool seen = false;  // plan residency recorded (plan hit: ready when first considered)
 };
 
 struct Batch {
@@ -126,6 +129,13 @@ struct blb_server {
   std::map<std::pair<int, int>, PlanEntry> plans;  // (weight id, L') -> plan
   size_t plan_bytes = 0;
   Arena arena;
+  // asynchronous plan generation (policy 1): one at a time on its own stream
+  hipStream_t gen_stream = nullptr;
+  int* gen_flag = nullptr;  // pinned: the encoder's overflow flag of the generation in flight
+  PlanEntry* gen_entry = nullptr;
+  std::pair<int, int> gen_key;
+  double gen_t0 = 0;
+  std::map<std::pair<int, int>, int> bad_plans;  // keys whose plan cannot be built -> error
   std::mutex mu;
   std::condition_variable cv;
   std::deque<Request*> queue;
@@ -158,18 +168,34 @@ bool make_room(blb_server* S, size_t need, size_t* off) {
   return true;
 }
 
-// returns 1 admitted, 0 must wait, < 0 rejected (error code)
-int admit(blb_server* S, Request* r) {
-  blb_ctx* c = S->c;
-  auto key = std::make_pair(r->weight_id, r->Lp);
-  auto it = S->plans.find(key);
-  if (it != S->plans.end()) {
-    ++S->hits;
-    it->second.users++;
-    it->second.last_use = now_s();
-    r->pe = &it->second;
-    return 1;
+bool plan_ready(blb_server* S, const Request* r) {
+  auto it = S->plans.find(std::make_pair(r->weight_id, r->Lp));
+  return it != S->plans.end() && !it->second.pending;
+}
+
+// admit a request whose plan is resident and ready: 1; else 0.  A request counts as a plan
+// hit when its plan was ready the first time it was considered.
+int admit_ready(blb_server* S, Request* r) {
+  auto it = S->plans.find(std::make_pair(r->weight_id, r->Lp));
+  const bool ready = it != S->plans.end() && !it->second.pending;
+  if (!r->seen) {
+    r->seen = true;
+    if (ready) ++S->hits;
   }
+  if (!ready) return 0;
+  it->second.users++;
+  it->second.last_use = now_s();
+  r->pe = &it->second;
+  return 1;
+}
+
+// build the plan of r's (weight, L'): synchronously (async = false) or enqueued on the
+// generation stream.  1: built / enqueued, 0: no room now, < 0: the request cannot be served.
+int generate_plan(blb_server* S, Request* r, bool async) {
+  blb_ctx* c = S->c;
+  const auto key = std::make_pair(r->weight_id, r->Lp);
+  auto bad = S->bad_plans.find(key);
+  if (bad != S->bad_plans.end()) return bad->second;
   const Weights& w = S->weights[r->weight_id];
   const size_t need = cp_plan_bytes(c, r->Lp, w.d_in, w.d_out, w.level);
   if (Arena::round(need) > S->arena.cap) return BLB_ENOMEM;
@@ -177,22 +203,58 @@ int admit(blb_server* S, Request* r) {
   if (!make_room(S, need, &off)) return 0;  // memory frees up when running batches finish
   const double t0 = now_s();
   blb_plan* P = nullptr;
-  const int rc = cp_plan_create(c, w.W.data(), w.d_in, w.d_out, r->Lp, w.level, (uint64_t*)((char*)S->arena.base + off), &P);
+  hipStream_t saved = c->stream;
+  if (async) c->stream = S->gen_stream;
+  const int rc = cp_plan_create(c, w.W.data(), w.d_in, w.d_out, r->Lp, w.level, (uint64_t*)((char*)S->arena.base + off), &P,
+                                async ? S->gen_flag : nullptr);
+  hipEvent_t ev = nullptr;
+  if (rc == BLB_OK && async && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) (void)hipEventRecord(ev, c->stream);
+  c->stream = saved;
   if (rc) {
     S->arena.release(off, need);
-    return rc == BLB_ENOMEM ? 0 : rc;
+    if (rc == BLB_ENOMEM) return 0;
+    S->bad_plans[key] = rc;
+    return rc;
   }
-  S->gen_s += now_s() - t0;
   ++S->misses;
   PlanEntry& pe = S->plans[key];
   pe.plan = P;
   pe.off = off;
   pe.bytes = P->bytes;
-  pe.users = 1;
+  pe.users = 0;
   pe.last_use = now_s();
   S->plan_bytes += P->bytes;
-  r->pe = &pe;
+  if (async) {
+    if (!ev) (void)hipStreamSynchronize(S->gen_stream);
+    pe.pending = ev != nullptr;
+    pe.ready = ev;
+    pe.users = pe.pending ? 1 : 0;  // not evictable while being written
+    S->gen_entry = pe.pending ? &pe : nullptr;
+    S->gen_key = key;
+    S->gen_t0 = t0;
+  } else {
+    S->gen_s += now_s() - t0;
+  }
   return 1;
+}
+
+// completes the asynchronous generation in flight when its event has fired
+void poll_generation(blb_server* S) {
+  if (!S->gen_entry || hipEventQuery(S->gen_entry->ready) != hipSuccess) return;
+  PlanEntry* pe = S->gen_entry;
+  S->gen_entry = nullptr;
+  S->gen_s += now_s() - S->gen_t0;
+  (void)hipEventDestroy(pe->ready);
+  pe->ready = nullptr;
+  pe->pending = false;
+  pe->users--;
+  if (*S->gen_flag) {  // encoder overflow: the weights cannot be encoded at this scale
+    S->bad_plans[S->gen_key] = BLB_EINVAL;
+    S->plan_bytes -= pe->bytes;
+    blb_plan_destroy(pe->plan);
+    S->arena.release(pe->off, pe->bytes);
+    S->plans.erase(S->gen_key);
+  }
 }
 
 void finish_batches(blb_server* S, bool block) {
@@ -235,38 +297,48 @@ void worker_loop(blb_server* S) {
     }
     finish_batches(S, false);
     if (pending.empty()) continue;
-    // admission order: arrival order (policy 0), or resident plans first (policy 1)
-    std::vector<Request*> order;
-    if (S->cfg.policy == 1) {
-      Request* oldest = pending.front();
-      const bool overdue = (now_s() - oldest->t_submit) * 1e3 > S->cfg.max_wait_ms;
-      if (overdue) order.push_back(oldest);
-      for (Request* r : pending)
-        if (!(overdue && r == oldest) && S->plans.count(std::make_pair(r->weight_id, r->Lp))) order.push_back(r);
-      if (order.empty()) order.push_back(oldest);
-    } else {
-      order = pending;
-    }
     std::vector<Request*> batch;
     std::vector<Request*> rejected;
-    for (Request* r : order) {
-      if ((int)batch.size() >= S->cfg.max_batch) break;
-      const int a = admit(S, r);
-      if (a == 1) batch.push_back(r);
-      else if (a < 0) {
-        r->state = a;
-        rejected.push_back(r);
-      } else {
-        break;  // wait for memory
-      }
-    }
-    if (S->cfg.policy == 1 && !batch.empty()) {
-      // a plan generated for this batch also serves every queued request on it
+    auto reject = [&](Request* r, int code) {
+      r->state = code;
+      rejected.push_back(r);
+    };
+    if (S->cfg.policy == 1) {
+      poll_generation(S);
+      // requests whose plan is ready, the oldest first when it is overdue
+      Request* oldest = pending.front();
+      const bool overdue = (now_s() - oldest->t_submit) * 1e3 > S->cfg.max_wait_ms;
+      if (overdue && admit_ready(S, oldest)) batch.push_back(oldest);
       for (Request* r : pending) {
         if ((int)batch.size() >= S->cfg.max_batch) break;
-        if (std::find(batch.begin(), batch.end(), r) != batch.end() || std::find(rejected.begin(), rejected.end(), r) != rejected.end())
-          continue;
-        if (S->plans.count(std::make_pair(r->weight_id, r->Lp)) && admit(S, r) == 1) batch.push_back(r);
+        if (r == oldest && overdue) continue;
+        if (S->bad_plans.count(std::make_pair(r->weight_id, r->Lp))) reject(r, S->bad_plans[std::make_pair(r->weight_id, r->Lp)]);
+        else if (admit_ready(S, r)) batch.push_back(r);
+      }
+      // start the plan of the oldest request that has none, unless one is being built
+      if (!S->gen_entry) {
+        for (Request* r : pending) {
+          if (std::find(rejected.begin(), rejected.end(), r) != rejected.end()) continue;
+          if (S->plans.count(std::make_pair(r->weight_id, r->Lp))) continue;
+          const int g = generate_plan(S, r, true);
+          if (g < 0) reject(r, g);
+          break;  // one generation in flight; 0 = no room until batches finish
+        }
+      }
+    } else {
+      // arrival order; a missing plan is built synchronously before its request runs
+      for (Request* r : pending) {
+        if ((int)batch.size() >= S->cfg.max_batch) break;
+        if (!plan_ready(S, r)) {
+          const int g = generate_plan(S, r, false);
+          if (g < 0) {
+            reject(r, g);
+            continue;
+          }
+          if (g == 0) break;  // wait for memory
+        }
+        if (admit_ready(S, r)) batch.push_back(r);
+        else break;
       }
     }
     {
@@ -280,7 +352,8 @@ void worker_loop(blb_server* S) {
     }
     if (!rejected.empty()) S->cv.notify_all();
     if (batch.empty()) {
-      if (!S->running.empty()) finish_batches(S, true);  // wait for memory to free up
+      if (S->gen_entry) std::this_thread::sleep_for(std::chrono::microseconds(50));  // a plan is on its way
+      else if (!S->running.empty()) finish_batches(S, true);  // wait for memory to free up
       continue;
     }
     // launch the batch on the next stream
@@ -354,10 +427,23 @@ int blb_server_create(blb_ctx* c, const blb_server_config* cfg, blb_server** out
     c->dev_bytes += S->arena.cap;
     S->arena.free_[0] = S->arena.cap;
   }
+  if (hipStreamCreateWithFlags(&S->gen_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipHostMalloc((void**)&S->gen_flag, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    if (S->gen_stream) (void)hipStreamDestroy(S->gen_stream);
+    if (S->arena.base) {
+      (void)hipFree(S->arena.base);
+      c->dev_bytes -= S->arena.cap;
+    }
+    delete S;
+    return BLB_EDEVICE;
+  }
+  *S->gen_flag = 0;
   for (int i = 0; i < cfg->n_streams; ++i) {
     hipStream_t s;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
       for (hipStream_t t : S->streams) (void)hipStreamDestroy(t);
+      (void)hipStreamDestroy(S->gen_stream);
+      (void)hipHostFree(S->gen_flag);
       if (S->arena.base) {
         (void)hipFree(S->arena.base);
         c->dev_bytes -= S->arena.cap;
@@ -472,8 +558,15 @@ void blb_server_destroy(blb_server* S) {
   if (S->worker.joinable()) S->worker.join();
   for (hipStream_t s : S->streams) {
     (void)hipStreamSynchronize(s);
+    uploader_forget_stream(S->c, s);
     (void)hipStreamDestroy(s);
   }
+  (void)hipStreamSynchronize(S->gen_stream);
+  uploader_forget_stream(S->c, S->gen_stream);
+  (void)hipStreamDestroy(S->gen_stream);
+  (void)hipHostFree(S->gen_flag);
+  for (auto& kv : S->plans)
+    if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
   for (auto& kv : S->plans) blb_plan_destroy(kv.second.plan);
   if (S->arena.base) {
     (void)hipFree(S->arena.base);
