@@ -1626,7 +1626,9 @@ int blb_matmul_cc(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct
       if (!find_key(K, galois_left(c, -(int64_t)tau * g.H * lp))) return BLB_ENOKEY;
   const int nl = level + 1, nl2 = level, nl3 = level - 1, nlA = level_in + 1;
   const size_t w1 = (size_t)2 * nl * n, w2 = (size_t)2 * nl2 * n, w3 = (size_t)2 * nl3 * n;
-  const int TC = 16;  // t values per chunk
+  // t values per chunk: large chunks give every stage launch hundreds of limb-polys (the
+  // relinearisation and step-3 stages only have one ciphertext per t); about 40 MB per t
+  const int TC = std::min(lp, 128);
   int rc = BLB_OK;
   double b_scale = Bp[0].scale;
   for (const CcGroup& g : P->groups) {
@@ -1958,7 +1960,10 @@ int blb_exec_create_cc(blb_ctx* c, const blb_keys* K, const blb_plan* P, const b
   if (!E) return BLB_ENOMEM;
   E->has_mask = mask_target_level >= 0;
   const size_t ctw = (size_t)2 * (P->level + 1) * c->n * 8;
-  const size_t guess = ctw * (size_t)(P->n_ct * 16 * 8 + 256);
+  int max_m = 1;
+  for (const CcGroup& g : P->groups) max_m = std::max(max_m, g.n_ct);
+  const size_t tc = (size_t)std::min(P->Lp, 128);  // t values per chunk in blb_matmul_cc
+  const size_t guess = ctw * (5 * tc * max_m + 8 * tc + 64 * (size_t)P->n_ct + 256);
   const int rc = exec_record(c, E, guess, [&]() -> int {
     int r = blb_matmul_cc(c, K, P, A, Bp, n_ct, Cd, n_out);
     if (r) return r;
