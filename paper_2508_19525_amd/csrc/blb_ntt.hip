@@ -61,10 +61,14 @@ struct Pass {
           const double w = tw[widx];
           double& a = x[h * GS + k];
           double& b = x[h * GS + k + t_loc];
-          // lazy reduction: values are brought back to |x| <= q/2 only after every second
-          // stage (and at the end of the pass); in between they stay below ~3.1 q < 2^52,
-          // where every FP64 operation on them is exact and mulmod_s keeps |result| < 1.3 q.
-          const bool red = (u & 1) || (u == R_LOG - 1);
+          // lazy reduction.  For |b| <= B, mulmod_s returns |v| < q/2 + 1.5 B q 2^-52
+          // < q/2 + 0.375 B (the quotient estimate is off by < B 2^-52, the dropped low part
+          // of b w is < B q 2^-53), so in the forward (Cooley-Tukey) butterfly the bound grows
+          // as B' = 1.375 B + q/2: from |x| <= q at the start of a pass, four stages stay below
+          // 7.01 q < 2^53, where every FP64 sum and product step is exact; values are reduced
+          // at the end of the pass only.  In the inverse (Gentleman-Sande) butterfly a + b can
+          // double, so it reduces after every second stage and at the end of the pass.
+          const bool red = FWD ? (u == R_LOG - 1) : ((u & 1) || (u == R_LOG - 1));
           if (FWD) {
             const double v = mulmod_s(b, w, q, qi);
             const double sum = a + v, dif = a - v;
