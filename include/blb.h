@@ -267,7 +267,8 @@ typedef struct {
   double max_wait_ms;
 } blb_server_config;
 int blb_server_create(blb_ctx* ctx, const blb_server_config* cfg, blb_server** out);
-/* W: host d_in x d_out row-major; inputs of requests on this weight are at `level`. */
+/* W: host d_in x d_out row-major (copied); inputs of requests on this weight are at `level`.
+ * A weight id can be registered once (EINVAL on a second registration). */
 int blb_server_add_weights(blb_server* server, int weight_id, const double* W, int d_in, int d_out, int level);
 /* X (n_in cts) and Y (n_out buffers of 2*level*N words) must stay alive until completion; the
  * blb_ct array Y is updated (level, scale) by the worker.  mask_target_level < 0: no mask.

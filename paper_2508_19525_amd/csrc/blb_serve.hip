@@ -127,7 +127,7 @@ struct blb_server {
   std::vector<hipStream_t> streams;
   std::map<int, Weights> weights;
   std::map<std::pair<int, int>, PlanEntry> plans;  // (weight id, L') -> plan
-  size_t plan_bytes = 0;
+  std::atomic<size_t> plan_bytes{0};
   Arena arena;
   // asynchronous plan generation (policy 1): one at a time on its own stream
   hipStream_t gen_stream = nullptr;
@@ -145,8 +145,10 @@ struct blb_server {
   bool stop = false;
   std::thread worker;
   // statistics
-  int64_t hits = 0, misses = 0, rejected = 0, completed = 0, batches = 0, failed = 0;
-  double gen_s = 0;
+  // statistics written by the worker and read by blb_server_stats: atomics; the others
+  // change under `mu`
+  std::atomic<int64_t> hits{0}, misses{0}, batches{0}, gen_ns{0};
+  int64_t rejected = 0, completed = 0, failed = 0;
   std::vector<double> latencies;
 };
 
@@ -196,7 +198,12 @@ int generate_plan(blb_server* S, Request* r, bool async) {
   const auto key = std::make_pair(r->weight_id, r->Lp);
   auto bad = S->bad_plans.find(key);
   if (bad != S->bad_plans.end()) return bad->second;
-  const Weights& w = S->weights[r->weight_id];
+  const Weights* wp;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);  // registered weights never change (map nodes are stable)
+    wp = &S->weights.at(r->weight_id);
+  }
+  const Weights& w = *wp;
   const size_t need = cp_plan_bytes(c, r->Lp, w.d_in, w.d_out, w.level);
   if (Arena::round(need) > S->arena.cap) return BLB_ENOMEM;
   size_t off = 0;
@@ -233,7 +240,7 @@ int generate_plan(blb_server* S, Request* r, bool async) {
     S->gen_key = key;
     S->gen_t0 = t0;
   } else {
-    S->gen_s += now_s() - t0;
+    S->gen_ns += (int64_t)((now_s() - t0) * 1e9);
   }
   return 1;
 }
@@ -243,7 +250,7 @@ void poll_generation(blb_server* S) {
   if (!S->gen_entry || hipEventQuery(S->gen_entry->ready) != hipSuccess) return;
   PlanEntry* pe = S->gen_entry;
   S->gen_entry = nullptr;
-  S->gen_s += now_s() - S->gen_t0;
+  S->gen_ns += (int64_t)((now_s() - S->gen_t0) * 1e9);
   (void)hipEventDestroy(pe->ready);
   pe->ready = nullptr;
   pe->pending = false;
@@ -462,6 +469,7 @@ int blb_server_create(blb_ctx* c, const blb_server_config* cfg, blb_server** out
 int blb_server_add_weights(blb_server* S, int weight_id, const double* W, int d_in, int d_out, int level) {
   if (!S || !W || d_in < 1 || d_out < 1 || level < 1 || level >= S->c->n_q) return BLB_EINVAL;
   std::lock_guard<std::mutex> lk(S->mu);
+  if (S->weights.count(weight_id)) return BLB_EINVAL;  // a registered weight id is immutable
   Weights& w = S->weights[weight_id];
   w.W.assign(W, W + (size_t)d_in * d_out);
   w.d_in = d_in;
@@ -539,11 +547,11 @@ int blb_server_stats(blb_server* S, double* out, int cap) {
   double m = 0;
   for (double v : S->latencies) m += v;
   out[4] = S->latencies.empty() ? 0 : m / S->latencies.size() * 1e3;
-  out[5] = (double)S->hits;
-  out[6] = (double)S->misses;
-  out[7] = (double)S->batches;
-  out[8] = S->gen_s;
-  out[9] = (double)S->plan_bytes;
+  out[5] = (double)S->hits.load();
+  out[6] = (double)S->misses.load();
+  out[7] = (double)S->batches.load();
+  out[8] = (double)S->gen_ns.load() * 1e-9;
+  out[9] = (double)S->plan_bytes.load();
   if (cap > 10) out[10] = (double)S->failed;
   return BLB_OK;
 }

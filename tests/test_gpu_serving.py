@@ -155,6 +155,8 @@ def test_submit_refuses_request_without_its_keys(env):
     srv = B.blb_server_create(ctx, plan_cache_bytes=256 << 20, max_batch=4, n_streams=1)
     try:
         B.blb_server_add_weights(srv, 0, wl.serving_weights(0, SHAPES[0]), 2)
+        with pytest.raises(B.BlbError):  # registered weights are immutable
+            B.blb_server_add_weights(srv, 0, wl.serving_weights(0, SHAPES[0]), 2)
         r = reqs[0]
         with pytest.raises(B.BlbError) as ei:
             B.blb_server_submit(srv, bare, 0, r["L"], r["X"], r["Y"])
