@@ -621,7 +621,7 @@ def main():
     ap.add_argument("--ntt-only", action="store_true", help="run only the standalone NTT measurement (diagnostic)")
     ap.add_argument("--serve-requests", type=int, default=80)
     ap.add_argument("--serve-rate", type=float, default=50.0)
-    ap.add_argument("--serve-cache-gb", type=float, default=150.0)
+    ap.add_argument("--serve-cache-gb", type=float, default=200.0)
     ap.add_argument("--serve-max-wait-ms", type=float, default=2000.0)
     ap.add_argument("--serve-sweep", type=str, default="", help="comma-separated offered rates (req/s) for a saturation curve")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB plain copy (counter reference)")

@@ -136,7 +136,7 @@ struct Tmp {
 // ------------------------------------------------------------------------------------------
 // descriptor upload ring
 // ------------------------------------------------------------------------------------------
-const size_t kUploadCap = 32u << 20;
+const size_t kUploadCap = 128u << 20;
 
 int uploader_init(blb_ctx* c) {
   Uploader& u = c->up;
@@ -264,6 +264,17 @@ void ntt_descs(blb_ctx* c, const std::vector<PolyDesc>& d, int kind) {
   }
 }
 enum { NTT_FWD = 0, NTT_INV = 1, NTT_RESCALE = 2, NTT_MODDOWN = 3, NTT_ADDTO = 4 };
+
+// in-place transform of count limb-polys stored back to back ([item][nl][N]); no table upload
+void ntt_regular(blb_ctx* c, uint64_t* base, size_t count, int nl, bool fwd) {
+  const size_t chunk = ((size_t)1 << 20) / nl * nl;  // a multiple of nl: every chunk starts at limb 0
+  for (size_t off = 0; off < count; off += chunk) {
+    const int cnt = (int)std::min(chunk, count - off);
+    Span sp(c, BLB_T_NTT, (double)cnt);
+    c->counters[1] += cnt;
+    launch_ntt_regular(c, base + off * c->n, cnt, nl, fwd);
+  }
+}
 
 PolyDesc pd(const uint64_t* src, uint64_t* dst, int mod, int log_n) {
   PolyDesc d;
@@ -1059,15 +1070,7 @@ int blb_ntt(blb_ctx* c, uint64_t* data, int64_t n_polys, int32_t n_limbs, int32_
   if (!c || n_polys < 0 || n_limbs < 1 || n_limbs > c->n_q + c->n_sp || (inverse != 0 && inverse != 1)) return BLB_EINVAL;
   if (n_polys == 0) return BLB_OK;
   if (!data) return BLB_EINVAL;
-  const int n = c->n;
-  std::vector<PolyDesc> d;
-  d.reserve((size_t)n_polys * n_limbs);
-  for (int64_t p = 0; p < n_polys; ++p)
-    for (int i = 0; i < n_limbs; ++i) {
-      uint64_t* x = data + ((size_t)p * n_limbs + i) * n;
-      d.push_back(pd(x, x, i, c->log_n));
-    }
-  ntt_descs(c, d, inverse ? NTT_INV : NTT_FWD);
+  ntt_regular(c, data, (size_t)n_polys * n_limbs, n_limbs, inverse == 0);
   return hipGetLastError() == hipSuccess ? BLB_OK : BLB_EDEVICE;
 }
 
@@ -1158,19 +1161,12 @@ int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int 
     }
     (void)hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream);
     const double scale = (double)c->mod[level] / BLB_NOISE_BOOST;
-    std::vector<PolyDesc> d;
     for (size_t p0 = 0; p0 < n_pt; p0 += chunk) {
       const int cnt = (int)std::min<size_t>(chunk, n_pt - p0);
       launch_enc_scatter_cp(c, dW, g, (int)p0, cnt, a);
       uint64_t* dst = P->pt + p0 * nl * n;
       run_encode_core(c, a, b, cnt, scale, nl, dst, c->d_flag, true);
-      d.clear();
-      for (int p = 0; p < cnt; ++p)
-        for (int i = 0; i < nl; ++i) {
-          uint64_t* x = dst + ((size_t)p * nl + i) * n;
-          d.push_back(pd(x, x, i, c->log_n));
-        }
-      ntt_descs(c, d, NTT_FWD);
+      ntt_regular(c, dst, (size_t)cnt * nl, nl, true);
     }
     if (flag_host) {
       if (hipMemcpyAsync(flag_host, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess) {

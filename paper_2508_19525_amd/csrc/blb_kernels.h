@@ -33,3 +33,6 @@ void launch_ntt(blb_ctx* c, const PolyDesc* d_descs, int count, bool fwd);
 void launch_ntt_rescale(blb_ctx* c, const PolyDesc* d_descs, int count);
 void launch_ntt_moddown(blb_ctx* c, const PolyDesc* d_descs, int count);
 void launch_ntt_addto(blb_ctx* c, const PolyDesc* d_descs, int count);
+// in-place transform of `count` limb-polys stored back to back at base ([item][nl][N]), no
+// descriptor table
+void launch_ntt_regular(blb_ctx* c, uint64_t* base, int count, int nl, bool fwd);

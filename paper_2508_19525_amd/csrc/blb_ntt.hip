@@ -18,6 +18,31 @@ namespace {
 
 constexpr int kPerThread = 16;
 
+// Where a launch finds its polynomials: a descriptor table, or (descs == null) a regular
+// batch of `count` limb-polys stored back to back at `base`, transformed in place, poly p
+// taken modulo prime p mod nl (the [item][limb][N] layout of ciphertexts and plaintexts).
+struct NttSrc {
+  const PolyDesc* descs;
+  uint64_t* base;
+  int nl;
+  int log_n;
+  __device__ __forceinline__ PolyDesc get(int p) const {
+    if (descs) return descs[p];
+    PolyDesc d;
+    d.src = base + ((size_t)p << log_n);
+    d.dst = base + ((size_t)p << log_n);
+    d.src2 = nullptr;
+    d.src3 = nullptr;
+    d.aux = 0.0;
+    d.aux2 = 0.0;
+    d.mod = p % nl;
+    d.gal = 0;
+    d.log_n = log_n;
+    d.pad = 0;
+    return d;
+  }
+};
+
 __device__ __forceinline__ int pad_idx(int j) { return j + (j >> 4); }
 
 // One pass of R_LOG radix-2 stages starting at global stage S0.  Work-item `tid` holds
@@ -178,11 +203,11 @@ __device__ __forceinline__ void ntt_store(double (&x)[kPerThread], const PolyDes
 
 // One workgroup per polynomial.
 template <int LOGN, bool FWD, class LoadOp, class StoreOp>
-__global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt(const PolyDesc* __restrict__ descs, const double* __restrict__ tw_all,
+__global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt(NttSrc descs, const double* __restrict__ tw_all,
                                                                 ModTable mt, LoadOp ld, StoreOp st) {
   constexpr int N = 1 << LOGN;
   __shared__ double lds[N + N / 16];
-  const PolyDesc d = descs[blockIdx.x];
+  const PolyDesc d = descs.get(blockIdx.x);
   const double q = mt.m[d.mod].q, qi = mt.m[d.mod].qinv;
   const int tid = threadIdx.x;
   double x[kPerThread];
@@ -197,7 +222,7 @@ __global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt(const PolyDesc
 // per CU at N = 16384) exposes.  At N = 16384 (1024 work-items, at most 128 registers each)
 // only the first half of the next operands is prefetched, which keeps it free of spills.
 template <int LOGN, bool FWD, class LoadOp, class StoreOp>
-__global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt_pipe(const PolyDesc* __restrict__ descs, const double* __restrict__ tw_all,
+__global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt_pipe(NttSrc descs, const double* __restrict__ tw_all,
                                                                      ModTable mt, LoadOp ld, StoreOp st, int count) {
   constexpr int N = 1 << LOGN;
   constexpr int PF = kPerThread;
@@ -208,7 +233,7 @@ __global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt_pipe(const Pol
   if (p >= count) return;
   double nx[PF];
   {
-    const PolyDesc d = descs[p];
+    const PolyDesc d = descs.get(p);
 #pragma unroll
     for (int i = 0; i < PF; ++i) nx[i] = ld(d, First::idx(tid0, i), mt.m[d.mod].q, mt.m[d.mod].qinv);
   }
@@ -217,7 +242,7 @@ __global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt_pipe(const Pol
     // index computation of the loop body out of the loop (which would spill registers)
     int tid = tid0;
     asm volatile("" : "+v"(tid));
-    const PolyDesc d = descs[p];
+    const PolyDesc d = descs.get(p);
     const double q = mt.m[d.mod].q, qi = mt.m[d.mod].qinv;
     double x[kPerThread];
 #pragma unroll
@@ -228,7 +253,7 @@ __global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt_pipe(const Pol
     {
       // unconditional (the last round re-reads its own polynomial), so the loads land in nx
       // directly and are only waited for when the next round starts
-      const PolyDesc dn = descs[pn < count ? pn : p];
+      const PolyDesc dn = descs.get(pn < count ? pn : p);
       const double qn = mt.m[dn.mod].q, qin = mt.m[dn.mod].qinv;
 #pragma unroll
       for (int i = 0; i < PF; ++i) nx[i] = ld(dn, First::idx(tid, i), qn, qin);
@@ -241,7 +266,7 @@ __global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt_pipe(const Pol
 }
 
 template <bool FWD, class LoadOp, class StoreOp>
-void launch_ntt_generic(blb_ctx* c, const PolyDesc* d_descs, int count, LoadOp ld, StoreOp st) {
+void launch_ntt_generic(blb_ctx* c, NttSrc d_descs, int count, LoadOp ld, StoreOp st) {
   if (count <= 0) return;
   const double* tw = FWD ? c->d_tw_fwd : c->d_tw_inv;
   const int threads = c->n / kPerThread;
@@ -338,16 +363,22 @@ struct StAddTo {
   }
 };
 
+static NttSrc table(blb_ctx* c, const PolyDesc* d_descs) { return NttSrc{d_descs, nullptr, 1, c->log_n}; }
 void launch_ntt_addto(blb_ctx* c, const PolyDesc* d_descs, int count) {
-  launch_ntt_generic<true>(c, d_descs, count, LdPlain{}, StAddTo{});
+  launch_ntt_generic<true>(c, table(c, d_descs), count, LdPlain{}, StAddTo{});
 }
 void launch_ntt(blb_ctx* c, const PolyDesc* d_descs, int count, bool fwd) {
-  if (fwd) launch_ntt_generic<true>(c, d_descs, count, LdPlain{}, StPlain{});
-  else launch_ntt_generic<false>(c, d_descs, count, LdPlain{}, StPlain{});
+  if (fwd) launch_ntt_generic<true>(c, table(c, d_descs), count, LdPlain{}, StPlain{});
+  else launch_ntt_generic<false>(c, table(c, d_descs), count, LdPlain{}, StPlain{});
 }
 void launch_ntt_rescale(blb_ctx* c, const PolyDesc* d_descs, int count) {
-  launch_ntt_generic<true>(c, d_descs, count, LdCentredLift{}, StRescale{});
+  launch_ntt_generic<true>(c, table(c, d_descs), count, LdCentredLift{}, StRescale{});
 }
 void launch_ntt_moddown(blb_ctx* c, const PolyDesc* d_descs, int count) {
-  launch_ntt_generic<true>(c, d_descs, count, LdPlain{}, StModDown{});
+  launch_ntt_generic<true>(c, table(c, d_descs), count, LdPlain{}, StModDown{});
+}
+void launch_ntt_regular(blb_ctx* c, uint64_t* base, int count, int nl, bool fwd) {
+  const NttSrc src{nullptr, base, nl, c->log_n};
+  if (fwd) launch_ntt_generic<true>(c, src, count, LdPlain{}, StPlain{});
+  else launch_ntt_generic<false>(c, src, count, LdPlain{}, StPlain{});
 }

@@ -337,6 +337,7 @@ void worker_loop(blb_server* S) {
       for (Request* r : pending) {
         if ((int)batch.size() >= S->cfg.max_batch) break;
         if (!plan_ready(S, r)) {
+          r->seen = true;  // a miss
           const int g = generate_plan(S, r, false);
           if (g < 0) {
             reject(r, g);
