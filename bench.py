@@ -296,10 +296,11 @@ NTT_OPS_PER_BUTTERFLY = 8  # 6 for the error-free modular product, 1 add, 1 subt
 
 def run_ntt(args, B, torch):
     """Batched negacyclic NTT / iNTT on its own: 1 GiB of limb-polys per launch (8192 polys at
-    N = 16384 over the four ciphertext primes; 16384 at N = 8192), both launch variants timed
-    (autotuner: the faster one is kept; results are bit-identical), round trip checked."""
+    N = 16384 over the four ciphertext primes; about 16384 at N = 8192 and 32768 at N = 4096),
+    both launch variants timed (autotuner: the faster one is kept; results are bit-identical),
+    round trip checked."""
     out = {}
-    for log_n, n_q, n_sp, dnum in ((14, 4, 2, 2), (13, 3, 1, 3)):
+    for log_n, n_q, n_sp, dnum in ((14, 4, 2, 2), (13, 3, 1, 3), (12, 2, 1, 2)):
         n = 1 << log_n
         ctx = B.blb_ctx_create(log_n, n_q, n_sp, dnum, 0, torch.cuda.current_stream().cuda_stream)
         mods = B.blb_ctx_moduli(ctx, n_q + n_sp)

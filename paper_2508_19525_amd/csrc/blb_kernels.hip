@@ -587,6 +587,56 @@ __global__ void k_enc_stage4(const double* in, double* out, const double* tw /* 
   st_cdd(y + (size_t)(idx + 3 * ns) * 4, cdd_sub(t1, t3));
 }
 
+// 4-point forward DFT in place (exact: only sums and multiplications by -i)
+__device__ __forceinline__ void dft4(cdd& a0, cdd& a1, cdd& a2, cdd& a3) {
+  const cdd t0 = cdd_add(a0, a2), t1 = cdd_sub(a0, a2), t2 = cdd_add(a1, a3), d = cdd_sub(a1, a3);
+  const cdd t3 = cdd{d.im, dd_neg(d.re)};  // (a1 - a3) * (-i)
+  a0 = cdd_add(t0, t2);
+  a1 = cdd_add(t1, t3);
+  a2 = cdd_sub(t0, t2);
+  a3 = cdd_sub(t1, t3);
+}
+
+// one radix-8 Stockham pass (three radix-2 stages at once, forward sign): thread j (k = j mod ns)
+// reads x[j + r M/8], twiddles them by exp(-2 pi i r k / (8 ns)), runs an 8-point DFT (two
+// 4-point DFTs and the odd-part factors exp(-2 pi i s / 8)) and writes y[(j / ns) 8 ns + k + r ns]
+__global__ void k_enc_stage8(const double* in, double* out, const double* tw /* [M/2][4] eta^k */, int M, int ns) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (j >= M / 8) return;
+  const double* x = in + (size_t)p * M * 4;
+  double* y = out + (size_t)p * M * 4;
+  const int k = j % ns;
+  const int step = M / (8 * ns);
+  const int half = M / 2;
+  cdd v[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) v[r] = ld_cdd(x + (size_t)(j + r * (M / 8)) * 4);
+#pragma unroll
+  for (int r = 1; r < 8; ++r) {
+    const int e = r * k * step;  // < 7M/8
+    cdd w = ld_cdd(tw + (size_t)(e >= half ? e - half : e) * 4);
+    w.im = dd_neg(w.im);  // exp(-2 pi i e / M)
+    if (e >= half) { w.re = dd_neg(w.re); w.im = dd_neg(w.im); }
+    v[r] = cdd_mul(v[r], w);
+  }
+  dft4(v[0], v[2], v[4], v[6]);  // even part E
+  dft4(v[1], v[3], v[5], v[7]);  // odd part O
+  const dd rh = dd{0.70710678118654757, -4.8336466567264567e-17};  // 1/sqrt(2) in double-double
+  cdd o[4] = {v[1], v[3], v[5], v[7]};
+  // o[s] *= exp(-2 pi i s / 8): s = 1: (1 - i)/sqrt 2, s = 2: -i, s = 3: -(1 + i)/sqrt 2
+  o[1] = cdd{dd_mul(dd_add(o[1].re, o[1].im), rh), dd_mul(dd_add(o[1].im, dd_neg(o[1].re)), rh)};
+  o[2] = cdd{o[2].im, dd_neg(o[2].re)};
+  o[3] = cdd{dd_mul(dd_add(o[3].im, dd_neg(o[3].re)), rh), dd_neg(dd_mul(dd_add(o[3].re, o[3].im), rh))};
+  const cdd e4[4] = {v[0], v[2], v[4], v[6]};
+  const int idx = (j / ns) * 8 * ns + k;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    st_cdd(y + (size_t)(idx + q * ns) * 4, cdd_add(e4[q], o[q]));
+    st_cdd(y + (size_t)(idx + (q + 4) * ns) * 4, cdd_sub(e4[q], o[q]));
+  }
+}
+
 __device__ __forceinline__ long long rhaz_dd(dd x, int* overflow) {
   const bool neg = x.hi < 0.0;
   if (neg) x = dd_neg(x);
@@ -663,16 +713,23 @@ int run_encode_core(blb_ctx* c, double* bufA, double* bufB, int count, double sc
   const int n_vec = paired ? (count + 1) / 2 : count;  // complex vectors transformed
   double* in = bufA;
   double* outb = bufB;
+  // radix-8 passes, with one radix-2 or radix-4 pass first when log2 M is not a multiple of 3
   int ns = 1;
-  if ((c->log_n - 1) & 1) {  // odd number of stages: one radix-2 stage first
+  const int rem = (c->log_n - 1) % 3;
+  if (rem == 1) {
     dim3 grid((M / 2 + 255) / 256, n_vec);
     k_enc_stage<<<grid, 256, 0, c->stream>>>(in, outb, c->d_enc_tw, M, ns);
     double* t = in; in = outb; outb = t;
     ns = 2;
-  }
-  for (; ns < M; ns *= 4) {
+  } else if (rem == 2) {
     dim3 grid((M / 4 + 255) / 256, n_vec);
     k_enc_stage4<<<grid, 256, 0, c->stream>>>(in, outb, c->d_enc_tw, M, ns);
+    double* t = in; in = outb; outb = t;
+    ns = 4;
+  }
+  for (; ns < M; ns *= 8) {
+    dim3 grid((M / 8 + 255) / 256, n_vec);
+    k_enc_stage8<<<grid, 256, 0, c->stream>>>(in, outb, c->d_enc_tw, M, ns);
     double* t = in; in = outb; outb = t;
   }
   dim3 grid((M + 255) / 256, n_vec);

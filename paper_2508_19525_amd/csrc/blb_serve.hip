@@ -129,12 +129,18 @@ struct blb_server {
   std::map<std::pair<int, int>, PlanEntry> plans;  // (weight id, L') -> plan
   std::atomic<size_t> plan_bytes{0};
   Arena arena;
-  // asynchronous plan generation (policy 1): one at a time on its own stream
+  // asynchronous plan generation (policy 1): up to kGenDepth generations queued on their own
+  // stream (stream order keeps the device overflow flag of each one separate)
+  static constexpr int kGenDepth = 2;
   hipStream_t gen_stream = nullptr;
-  int* gen_flag = nullptr;  // pinned: the encoder's overflow flag of the generation in flight
-  PlanEntry* gen_entry = nullptr;
-  std::pair<int, int> gen_key;
-  double gen_t0 = 0;
+  int* gen_flag = nullptr;  // pinned [kGenDepth]: each generation's overflow flag
+  struct Gen {
+    PlanEntry* pe;
+    std::pair<int, int> key;
+    double t0;
+    int slot;
+  };
+  std::deque<Gen> gens;  // in stream order
   std::map<std::pair<int, int>, int> bad_plans;  // keys whose plan cannot be built -> error
   std::mutex mu;
   std::condition_variable cv;
@@ -212,8 +218,15 @@ int generate_plan(blb_server* S, Request* r, bool async) {
   blb_plan* P = nullptr;
   hipStream_t saved = c->stream;
   if (async) c->stream = S->gen_stream;
+  int slot = 0;  // a flag slot no queued generation uses
+  if (async)
+    for (slot = 0; slot < blb_server::kGenDepth; ++slot) {
+      bool used = false;
+      for (const auto& g : S->gens) used |= g.slot == slot;
+      if (!used) break;
+    }
   const int rc = cp_plan_create(c, w.W.data(), w.d_in, w.d_out, r->Lp, w.level, (uint64_t*)((char*)S->arena.base + off), &P,
-                                async ? S->gen_flag : nullptr);
+                                async ? S->gen_flag + slot : nullptr);
   hipEvent_t ev = nullptr;
   if (rc == BLB_OK && async && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) (void)hipEventRecord(ev, c->stream);
   c->stream = saved;
@@ -236,31 +249,32 @@ int generate_plan(blb_server* S, Request* r, bool async) {
     pe.pending = ev != nullptr;
     pe.ready = ev;
     pe.users = pe.pending ? 1 : 0;  // not evictable while being written
-    S->gen_entry = pe.pending ? &pe : nullptr;
-    S->gen_key = key;
-    S->gen_t0 = t0;
+    if (pe.pending) S->gens.push_back(blb_server::Gen{&pe, key, t0, slot});
   } else {
     S->gen_ns += (int64_t)((now_s() - t0) * 1e9);
   }
   return 1;
 }
 
-// completes the asynchronous generation in flight when its event has fired
+// completes the asynchronous generations whose events have fired (in stream order)
 void poll_generation(blb_server* S) {
-  if (!S->gen_entry || hipEventQuery(S->gen_entry->ready) != hipSuccess) return;
-  PlanEntry* pe = S->gen_entry;
-  S->gen_entry = nullptr;
-  S->gen_ns += (int64_t)((now_s() - S->gen_t0) * 1e9);
-  (void)hipEventDestroy(pe->ready);
-  pe->ready = nullptr;
-  pe->pending = false;
-  pe->users--;
-  if (*S->gen_flag) {  // encoder overflow: the weights cannot be encoded at this scale
-    S->bad_plans[S->gen_key] = BLB_EINVAL;
-    S->plan_bytes -= pe->bytes;
-    blb_plan_destroy(pe->plan);
-    S->arena.release(pe->off, pe->bytes);
-    S->plans.erase(S->gen_key);
+  while (!S->gens.empty() && hipEventQuery(S->gens.front().pe->ready) == hipSuccess) {
+    const blb_server::Gen g = S->gens.front();
+    S->gens.pop_front();
+    PlanEntry* pe = g.pe;
+    S->gen_ns += (int64_t)((now_s() - g.t0) * 1e9);
+    (void)hipEventDestroy(pe->ready);
+    pe->ready = nullptr;
+    pe->pending = false;
+    pe->users--;
+    if (S->gen_flag[g.slot]) {  // encoder overflow: the weights cannot be encoded at this scale
+      S->gen_flag[g.slot] = 0;
+      S->bad_plans[g.key] = BLB_EINVAL;
+      S->plan_bytes -= pe->bytes;
+      blb_plan_destroy(pe->plan);
+      S->arena.release(pe->off, pe->bytes);
+      S->plans.erase(g.key);
+    }
   }
 }
 
@@ -312,25 +326,26 @@ void worker_loop(blb_server* S) {
     };
     if (S->cfg.policy == 1) {
       poll_generation(S);
-      // requests whose plan is ready, the oldest first when it is overdue
+      // requests whose plan is ready, the oldest first when it is overdue; no new batch while
+      // n_streams + 1 are in flight (the worker keeps queueing plan generations meanwhile)
+      const bool can_launch = (int)S->running.size() < (int)S->streams.size() + 1;
       Request* oldest = pending.front();
       const bool overdue = (now_s() - oldest->t_submit) * 1e3 > S->cfg.max_wait_ms;
-      if (overdue && admit_ready(S, oldest)) batch.push_back(oldest);
+      if (can_launch && overdue && admit_ready(S, oldest)) batch.push_back(oldest);
       for (Request* r : pending) {
-        if ((int)batch.size() >= S->cfg.max_batch) break;
+        if (!can_launch || (int)batch.size() >= S->cfg.max_batch) break;
         if (r == oldest && overdue) continue;
         if (S->bad_plans.count(std::make_pair(r->weight_id, r->Lp))) reject(r, S->bad_plans[std::make_pair(r->weight_id, r->Lp)]);
         else if (admit_ready(S, r)) batch.push_back(r);
       }
-      // start the plan of the oldest request that has none, unless one is being built
-      if (!S->gen_entry) {
-        for (Request* r : pending) {
-          if (std::find(rejected.begin(), rejected.end(), r) != rejected.end()) continue;
-          if (S->plans.count(std::make_pair(r->weight_id, r->Lp))) continue;
-          const int g = generate_plan(S, r, true);
-          if (g < 0) reject(r, g);
-          break;  // one generation in flight; 0 = no room until batches finish
-        }
+      // queue the plans of the oldest requests that have none, up to kGenDepth at a time
+      for (Request* r : pending) {
+        if ((int)S->gens.size() >= blb_server::kGenDepth) break;
+        if (std::find(rejected.begin(), rejected.end(), r) != rejected.end()) continue;
+        if (S->plans.count(std::make_pair(r->weight_id, r->Lp))) continue;
+        const int g = generate_plan(S, r, true);
+        if (g < 0) reject(r, g);
+        if (g == 0) break;  // no room until running batches finish
       }
     } else {
       // arrival order; a missing plan is built synchronously before its request runs
@@ -360,8 +375,8 @@ void worker_loop(blb_server* S) {
     }
     if (!rejected.empty()) S->cv.notify_all();
     if (batch.empty()) {
-      if (S->gen_entry) std::this_thread::sleep_for(std::chrono::microseconds(50));  // a plan is on its way
-      else if (!S->running.empty()) finish_batches(S, true);  // wait for memory to free up
+      if (!S->gens.empty()) std::this_thread::sleep_for(std::chrono::microseconds(50));  // a plan is on its way
+      else if (!S->running.empty()) finish_batches(S, true);  // a batch slot or memory frees up
       continue;
     }
     // launch the batch on the next stream
@@ -395,8 +410,9 @@ void worker_loop(blb_server* S) {
     }
     ++S->batches;
     S->running.push_back(b);
-    // bound the number of batches in flight
-    while ((int)S->running.size() >= (int)S->streams.size() + 1) finish_batches(S, true);
+    // policy 0 (the synchronous per-op baseline) waits here; policy 1 checks before launching
+    if (S->cfg.policy == 0)
+      while ((int)S->running.size() >= (int)S->streams.size() + 1) finish_batches(S, true);
   }
 }
 
@@ -436,7 +452,7 @@ int blb_server_create(blb_ctx* c, const blb_server_config* cfg, blb_server** out
     S->arena.free_[0] = S->arena.cap;
   }
   if (hipStreamCreateWithFlags(&S->gen_stream, hipStreamNonBlocking) != hipSuccess ||
-      hipHostMalloc((void**)&S->gen_flag, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&S->gen_flag, sizeof(int) * blb_server::kGenDepth, hipHostMallocDefault) != hipSuccess) {
     if (S->gen_stream) (void)hipStreamDestroy(S->gen_stream);
     if (S->arena.base) {
       (void)hipFree(S->arena.base);
@@ -445,7 +461,7 @@ int blb_server_create(blb_ctx* c, const blb_server_config* cfg, blb_server** out
     delete S;
     return BLB_EDEVICE;
   }
-  *S->gen_flag = 0;
+  for (int i = 0; i < blb_server::kGenDepth; ++i) S->gen_flag[i] = 0;
   for (int i = 0; i < cfg->n_streams; ++i) {
     hipStream_t s;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
