@@ -136,21 +136,35 @@ struct Tmp {
 // ------------------------------------------------------------------------------------------
 // descriptor upload ring
 // ------------------------------------------------------------------------------------------
-const size_t kUploadCap = 128u << 20;
+const size_t kUploadCap = 64u << 20;
 
-int uploader_init(blb_ctx* c) {
-  Uploader& u = c->up;
-  u.cap = kUploadCap;
-  HIP_OK(hipHostMalloc((void**)&u.host, u.cap, hipHostMallocDefault));
-  HIP_OK(hipMalloc((void**)&u.dev, u.cap));
-  return BLB_OK;
+void ring_free(Uploader* u) {
+  for (auto& e : u->inflight) (void)hipEventDestroy(e.copied);
+  for (auto e : u->free_events) (void)hipEventDestroy(e);
+  if (u->host) (void)hipHostFree(u->host);
+  if (u->dev) (void)hipFree(u->dev);
+  delete u;
 }
+// the ring of the context's current stream, created on first use
+Uploader* ring_for(blb_ctx* c) {
+  for (Uploader* u : c->ups)
+    if (u->stream == c->stream) return u;
+  Uploader* u = new (std::nothrow) Uploader();
+  if (!u) return nullptr;
+  u->stream = c->stream;
+  u->cap = kUploadCap;
+  if (hipHostMalloc((void**)&u->host, u->cap, hipHostMallocDefault) != hipSuccess || hipMalloc((void**)&u->dev, u->cap) != hipSuccess) {
+    (void)hipGetLastError();
+    ring_free(u);
+    return nullptr;
+  }
+  c->ups.push_back(u);
+  return u;
+}
+int uploader_init(blb_ctx* c) { return ring_for(c) ? BLB_OK : BLB_ENOMEM; }
 void uploader_free(blb_ctx* c) {
-  Uploader& u = c->up;
-  for (auto& e : u.inflight) (void)hipEventDestroy(e.copied);
-  for (auto e : u.free_events) (void)hipEventDestroy(e);
-  if (u.host) (void)hipHostFree(u.host);
-  if (u.dev) (void)hipFree(u.dev);
+  for (Uploader* u : c->ups) ring_free(u);
+  c->ups.clear();
 }
 // Copies `bytes` from host memory to a device region that stays valid for all work enqueued
 // on the stream before the ring wraps back onto it.
@@ -166,24 +180,19 @@ void* upload(blb_ctx* c, const void* data, size_t bytes) {
     memcpy(r->blob_host.data() + off, data, bytes);
     return r->blob_dev + off;
   }
-  Uploader& u = c->up;
+  Uploader* up = ring_for(c);
+  if (!up) return nullptr;
+  Uploader& u = *up;
   bytes = align_up(bytes, 256);
   if (bytes > u.cap) return nullptr;
   size_t lo = u.head;
   if (lo + bytes > u.cap) lo = 0;
   const size_t hi = lo + bytes;
-  // Regions about to be overwritten: their host bytes may still be in an unfinished copy (wait
-  // for it), and their device bytes may still be read by kernels of another stream (make this
-  // stream wait for everything that stream has enqueued so far, which includes those kernels).
+  // staging bytes about to be rewritten may still be read by their earlier copy
   std::deque<UploadRegion> keep;
   for (const UploadRegion& e : u.inflight) {
     if (e.lo < hi && lo < e.hi) {
       (void)hipEventSynchronize(e.copied);
-      if (e.stream != c->stream) {
-        (void)hipEventRecord(e.copied, e.stream);
-        (void)hipStreamWaitEvent(c->stream, e.copied, 0);
-        (void)hipEventSynchronize(e.copied);  // the event is recycled below
-      }
       u.free_events.push_back(e.copied);
     } else {
       keep.push_back(e);
@@ -202,7 +211,7 @@ void* upload(blb_ctx* c, const void* data, size_t bytes) {
     return u.dev + lo;
   }
   (void)hipEventRecord(ev, c->stream);
-  u.inflight.push_back(UploadRegion{lo, hi, ev, c->stream});
+  u.inflight.push_back(UploadRegion{lo, hi, ev});
   u.head = hi;
   return u.dev + lo;
 }
@@ -527,10 +536,14 @@ int encode_dense_dev(blb_ctx* c, const double* d_vals, int n_vals, int count, do
 
 }  // namespace
 
-// a stream is about to be destroyed after a synchronisation: its regions need no more waiting
+// a stream is about to be destroyed after a synchronisation: drop its upload ring
 void uploader_forget_stream(blb_ctx* c, hipStream_t s) {
-  for (UploadRegion& e : c->up.inflight)
-    if (e.stream == s) e.stream = c->stream;
+  for (size_t i = 0; i < c->ups.size(); ++i)
+    if (c->ups[i]->stream == s) {
+      ring_free(c->ups[i]);
+      c->ups.erase(c->ups.begin() + i);
+      return;
+    }
 }
 
 // ==========================================================================================
@@ -1122,8 +1135,9 @@ size_t cp_plan_bytes(const blb_ctx* c, int L, int d_in, int d_out, int level) {
 // else to library memory.  With flag_host (pinned) the call returns once the work is enqueued:
 // the encoder's overflow flag lands in *flag_host when the stream reaches it (non-zero: the
 // plan is unusable), and W must stay valid until then.
-int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, uint64_t* mem, blb_plan** out, int* flag_host) {
-  if (!c || !W || !out || d_in < 1 || d_out < 1 || L < 1 || L > c->n / 2 || level < 1 || level >= c->n_q) return BLB_EINVAL;
+int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, uint64_t* mem, blb_plan** out, int* flag_host,
+                   const double* W_dev) {
+  if (!c || (!W && !W_dev) || !out || d_in < 1 || d_out < 1 || L < 1 || L > c->n / 2 || level < 1 || level >= c->n_q) return BLB_EINVAL;
   *out = nullptr;
   const CpGeom g = cp_geometry(c, L, d_in, d_out);
   const int n = c->n, nl = level + 1;
@@ -1148,16 +1162,20 @@ int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int 
   const int chunk = 512;
   {
     Tmp tmp(c);
-    double* dW = tmp.get<double>((size_t)d_in * d_out);
+    const double* dW = W_dev;
     double* a = tmp.get<double>((size_t)chunk * M * 4);
     double* b = tmp.get<double>((size_t)chunk * M * 4);
+    if (!dW) {
+      double* w = tmp.get<double>((size_t)d_in * d_out);
+      if (w && hipMemcpyAsync(w, W, (size_t)d_in * d_out * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+        blb_plan_destroy(P);
+        return BLB_EDEVICE;
+      }
+      dW = w;
+    }
     if (tmp.failed) {
       blb_plan_destroy(P);
       return BLB_ENOMEM;
-    }
-    if (hipMemcpyAsync(dW, W, (size_t)d_in * d_out * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
-      blb_plan_destroy(P);
-      return BLB_EDEVICE;
     }
     (void)hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream);
     const double scale = (double)c->mod[level] / BLB_NOISE_BOOST;
@@ -1190,7 +1208,7 @@ int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int 
 extern "C" {
 
 int blb_plan_matmul_cp(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, blb_plan** out) {
-  return cp_plan_create(c, W, d_in, d_out, L, level, nullptr, out, nullptr);
+  return cp_plan_create(c, W, d_in, d_out, L, level, nullptr, out, nullptr, nullptr);
 }
 
 void blb_plan_destroy(blb_plan* P) {

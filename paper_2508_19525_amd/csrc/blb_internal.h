@@ -122,15 +122,16 @@ struct CpGeom {
 // ---------------------------------------------------------------------------------------
 // Descriptor upload ring: pinned host staging + device mirror; a host region is reused only
 // after the copy that last read it has completed.
-// Pinned staging ring for descriptor tables: host bytes are copied to the same offsets of a
-// device ring on the calling stream.  Each region remembers the copy's completion event and
-// the stream whose kernels read it, until a later upload overwrites it.
+// Pinned staging ring for descriptor tables, one per stream: host bytes are copied to the
+// same offsets of a device ring on that stream, so a region's readers (kernels enqueued on the
+// stream after its copy) always run before the copy that later overwrites it; the host only
+// waits for the earlier copy of a region before rewriting its staging bytes.
 struct UploadRegion {
   size_t lo, hi;
   hipEvent_t copied;
-  hipStream_t stream;
 };
 struct Uploader {
+  hipStream_t stream = nullptr;
   char* host = nullptr;
   char* dev = nullptr;
   size_t cap = 0, head = 0;
@@ -180,7 +181,7 @@ struct blb_ctx {
   KsLevelConst h_kc[BLB_MAXQ];
   char* scratch = nullptr;
   size_t scratch_cap = 0;
-  Uploader up;
+  std::vector<Uploader*> ups;      // upload rings by stream
   int* d_flag = nullptr;          // device error flag (encoder overflow)
   int mac_variant = 0;            // k_cp_mac tile shape (autotuned; never changes results)
   int batch_variant = 0;          // k_cp_mac_batch shape (autotuned)
@@ -245,7 +246,8 @@ void launch_sample_int(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint6
 int cp_check_keys(const blb_ctx* c, const blb_keys* K, int L, int d_in, int d_out);
 void uploader_forget_stream(blb_ctx* c, hipStream_t s);
 size_t cp_plan_bytes(const blb_ctx* c, int L, int d_in, int d_out, int level);
-int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, uint64_t* mem, blb_plan** out, int* flag_host);
+int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, uint64_t* mem, blb_plan** out, int* flag_host,
+                   const double* W_dev);
 void launch_sample_flood(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag, int bits);
 void upload_cdt(const uint64_t* table20);
 

@@ -38,6 +38,7 @@ double now_s() {
 
 struct Weights {
   std::vector<double> W;
+  double* W_dev = nullptr;  // device copy (plans are generated from it without a host copy)
   int d_in = 0, d_out = 0, level = 0;
 };
 
@@ -226,7 +227,7 @@ int generate_plan(blb_server* S, Request* r, bool async) {
       if (!used) break;
     }
   const int rc = cp_plan_create(c, w.W.data(), w.d_in, w.d_out, r->Lp, w.level, (uint64_t*)((char*)S->arena.base + off), &P,
-                                async ? S->gen_flag + slot : nullptr);
+                                async ? S->gen_flag + slot : nullptr, w.W_dev);
   hipEvent_t ev = nullptr;
   if (rc == BLB_OK && async && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) (void)hipEventRecord(ev, c->stream);
   c->stream = saved;
@@ -487,7 +488,18 @@ int blb_server_add_weights(blb_server* S, int weight_id, const double* W, int d_
   if (!S || !W || d_in < 1 || d_out < 1 || level < 1 || level >= S->c->n_q) return BLB_EINVAL;
   std::lock_guard<std::mutex> lk(S->mu);
   if (S->weights.count(weight_id)) return BLB_EINVAL;  // a registered weight id is immutable
+  const size_t bytes = (size_t)d_in * d_out * 8;
+  double* dev = nullptr;
+  if (hipMalloc((void**)&dev, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return BLB_ENOMEM;
+  }
+  if (hipMemcpy(dev, W, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(dev);
+    return BLB_EDEVICE;
+  }
   Weights& w = S->weights[weight_id];
+  w.W_dev = dev;
   w.W.assign(W, W + (size_t)d_in * d_out);
   w.d_in = d_in;
   w.d_out = d_out;
@@ -593,6 +605,7 @@ void blb_server_destroy(blb_server* S) {
   for (auto& kv : S->plans)
     if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
   for (auto& kv : S->plans) blb_plan_destroy(kv.second.plan);
+  for (auto& kv : S->weights) (void)hipFree(kv.second.W_dev);
   if (S->arena.base) {
     (void)hipFree(S->arena.base);
     S->c->dev_bytes -= S->arena.cap;
