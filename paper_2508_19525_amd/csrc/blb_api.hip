@@ -120,6 +120,12 @@ struct Tmp {
       r->arena_off = off + bytes;
       return (T*)(r->arena + off);
     }
+    if (Workspace* w = c->ws) {
+      const size_t off = align_up(w->off, 256);
+      w->off = off + count * sizeof(T);
+      w->need = std::max(w->need, w->off);
+      if (w->off <= w->cap) return (T*)(w->base + off);
+    }
     if (hipMallocAsync(&p, count * sizeof(T), c->stream) != hipSuccess) {
       (void)hipGetLastError();
       failed = true;

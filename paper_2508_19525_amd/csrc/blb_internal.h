@@ -159,9 +159,20 @@ struct ExecRec {
   bool overflow = false;
 };
 
+// Stream-private workspace: while set on a context, temporaries of a call are carved from it
+// one after another (none is released before the call returns), so calls enqueued on one stream
+// reuse the same bytes in stream order and never reach the allocator.  A call whose temporaries
+// do not fit takes the rest from the stream-ordered pool; `need` records the largest total
+// any call asked for, so the owner can grow the workspace between calls.
+struct Workspace {
+  char* base = nullptr;
+  size_t cap = 0, off = 0, need = 0;
+};
+
 struct blb_ctx {
   int log_n, n, n_q, n_sp, dnum, alpha;
   ExecRec* rec = nullptr;
+  Workspace* ws = nullptr;
   bool timing = false;
   std::vector<TimedSpan> spans;
   std::vector<hipEvent_t> ev_pool;
