@@ -27,7 +27,21 @@ struct NttSrc {
   int nl;
   int log_n;
   __device__ __forceinline__ PolyDesc get(int p) const {
-    if (descs) return descs[p];
+    if (descs) {
+      // scalar loads (the table is read-only while the kernel runs): they do not join the
+      // in-order vector-memory counter, so fetching a descriptor never waits for the stores
+      // of the previous polynomial
+      typedef __attribute__((address_space(4))) const uint64_t ku64;
+      static_assert(sizeof(PolyDesc) == 64, "descriptor layout");
+      const ku64* w = (const ku64*)(descs + p);
+      union {
+        uint64_t u[8];
+        PolyDesc d;
+      } r;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) r.u[i] = w[i];
+      return r.d;
+    }
     PolyDesc d;
     d.src = base + ((size_t)p << log_n);
     d.dst = base + ((size_t)p << log_n);
@@ -193,17 +207,23 @@ template <int LOGN, bool FWD, class StoreOp>
 __device__ __forceinline__ void ntt_store(double (&x)[kPerThread], const PolyDesc& d, const StoreOp& st, double q, double qi, double ninv, int tid,
                                           double* lds) {
   st.prepare(d, lds, tid);  // the epilogue may stage an operand in LDS (free after the last pass)
+  // Every operand load of the epilogue is issued before the first store: vector-memory
+  // completion is tracked in issue order, so a load issued after a store could only be
+  // consumed once that store had completed.
+  typename StoreOp::Operand e[kPerThread];
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) e[i] = st.fetch(d, LastPass<LOGN, FWD>::idx(tid, i));
 #pragma unroll
   for (int i = 0; i < kPerThread; ++i) {
     const int j = LastPass<LOGN, FWD>::idx(tid, i);
     const double v = FWD ? canon(x[i], q) : canon_full(mulmod_s(x[i], ninv, q, qi), q, qi);
-    st(d, j, v, q, qi, lds);
+    st.put(d, j, v, e[i], q, qi, lds);
   }
 }
 
 // One workgroup per polynomial.
 template <int LOGN, bool FWD, class LoadOp, class StoreOp>
-__global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt(NttSrc descs, const double* __restrict__ tw_all,
+__global__ __launch_bounds__((1 << LOGN) / kPerThread) __attribute__((amdgpu_waves_per_eu(4))) void k_ntt(NttSrc descs, const double* __restrict__ tw_all,
                                                                 ModTable mt, LoadOp ld, StoreOp st) {
   constexpr int N = 1 << LOGN;
   __shared__ double lds[N + N / 16];
@@ -219,10 +239,9 @@ __global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt(NttSrc descs, 
 // Persistent, software-pipelined variant: a grid of resident workgroups walks the descriptor
 // list with a grid stride; the next polynomial's operands are loaded into registers while the
 // current one is transformed, hiding the global-memory latency that a one-shot workgroup (one
-// per CU at N = 16384) exposes.  At N = 16384 (1024 work-items, at most 128 registers each)
-// only the first half of the next operands is prefetched, which keeps it free of spills.
+// per CU at N = 16384) exposes.
 template <int LOGN, bool FWD, class LoadOp, class StoreOp>
-__global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt_pipe(NttSrc descs, const double* __restrict__ tw_all,
+__global__ __launch_bounds__((1 << LOGN) / kPerThread) __attribute__((amdgpu_waves_per_eu(4))) void k_ntt_pipe(NttSrc descs, const double* __restrict__ tw_all,
                                                                      ModTable mt, LoadOp ld, StoreOp st, int count) {
   constexpr int N = 1 << LOGN;
   constexpr int PF = kPerThread;
@@ -231,11 +250,19 @@ __global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt_pipe(NttSrc de
   const int tid0 = threadIdx.x;
   int p = blockIdx.x;
   if (p >= count) return;
-  double nx[PF];
+  // The next polynomial's words are prefetched raw (converted only when its round starts, so
+  // nothing waits for them earlier).  Vector-memory completion is tracked in issue order,
+  // stores included: the only wait in a round is for its own prefetch, issued before the
+  // previous round's stores.
+  uint64_t nx[PF];
   {
     const PolyDesc d = descs.get(p);
 #pragma unroll
-    for (int i = 0; i < PF; ++i) nx[i] = ld(d, First::idx(tid0, i), mt.m[d.mod].q, mt.m[d.mod].qinv);
+    for (int i = 0; i < PF; ++i) nx[i] = ld.raw(d, First::idx(tid0, i));
+    // the first polynomial's loads complete before the loop: registers still pending on entry
+    // would make the loop head wait for the previous round's stores as well
+#pragma unroll
+    for (int i = 0; i < PF; ++i) asm volatile("" : "+v"(nx[i]));
   }
   for (;;) {
     // an opaque copy of the work-item index: keeps the compiler from hoisting every
@@ -246,7 +273,11 @@ __global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt_pipe(NttSrc de
     const double q = mt.m[d.mod].q, qi = mt.m[d.mod].qinv;
     double x[kPerThread];
 #pragma unroll
-    for (int i = 0; i < PF; ++i) x[i] = nx[i];
+    for (int i = 0; i < PF; ++i) {
+      uint64_t u = nx[i];
+      asm volatile("" : "+v"(u));  // the conversion stays in this round
+      x[i] = ld.cvt(d, u, q, qi);
+    }
 #pragma unroll
     for (int i = PF; i < kPerThread; ++i) x[i] = ld(d, First::idx(tid, i), q, qi);
     const int pn = p + gridDim.x;
@@ -256,7 +287,7 @@ __global__ __launch_bounds__((1 << LOGN) / kPerThread) void k_ntt_pipe(NttSrc de
       const PolyDesc dn = descs.get(pn < count ? pn : p);
       const double qn = mt.m[dn.mod].q, qin = mt.m[dn.mod].qinv;
 #pragma unroll
-      for (int i = 0; i < PF; ++i) nx[i] = ld(dn, First::idx(tid, i), qn, qin);
+      for (int i = 0; i < PF; ++i) nx[i] = ld.raw(dn, First::idx(tid, i));
     }
     ntt_core<LOGN, FWD>(lds, x, tw_all + (size_t)d.mod * N, q, qi, tid);
     ntt_store<LOGN, FWD>(x, d, st, q, qi, mt.m[d.mod].ninv, tid, lds);
@@ -270,17 +301,19 @@ void launch_ntt_generic(blb_ctx* c, NttSrc d_descs, int count, LoadOp ld, StoreO
   if (count <= 0) return;
   const double* tw = FWD ? c->d_tw_fwd : c->d_tw_inv;
   const int threads = c->n / kPerThread;
-  if (c->ntt_variant == 1) {
-    // resident workgroups: LDS per workgroup is 8.5 N bytes of 160 KiB per CU
-    const int per_cu = std::max(1, (160 * 1024) / (int)((c->n + c->n / 16) * sizeof(double)));
-    const int grid = std::min(count, c->n_cu * per_cu);
-    switch (c->log_n) {
-      case 12: k_ntt_pipe<12, FWD><<<grid, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st, count); break;
-      case 13: k_ntt_pipe<13, FWD><<<grid, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st, count); break;
-      case 14: k_ntt_pipe<14, FWD><<<grid, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st, count); break;
-      default: break;
+  if constexpr (StoreOp::kPersistent) {
+    if (c->ntt_variant == 1) {
+      // resident workgroups: LDS per workgroup is 8.5 N bytes of 160 KiB per CU
+      const int per_cu = std::max(1, (160 * 1024) / (int)((c->n + c->n / 16) * sizeof(double)));
+      const int grid = std::min(count, c->n_cu * per_cu);
+      switch (c->log_n) {
+        case 12: k_ntt_pipe<12, FWD><<<grid, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st, count); break;
+        case 13: k_ntt_pipe<13, FWD><<<grid, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st, count); break;
+        case 14: k_ntt_pipe<14, FWD><<<grid, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st, count); break;
+        default: break;
+      }
+      return;
     }
-    return;
   }
   switch (c->log_n) {
     case 12: k_ntt<12, FWD><<<count, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st); break;
@@ -301,38 +334,56 @@ typedef __attribute__((address_space(1))) uint64_t gu64;
 __device__ __forceinline__ uint64_t gld(const uint64_t* p, int j) { return ((const gu64*)p)[j]; }
 __device__ __forceinline__ void gst(uint64_t* p, int j, uint64_t v) { ((gu64*)p)[j] = v; }
 
+// Loads: raw(d, j) fetches word j, cvt() turns it into this pass's double operand.
 struct LdPlain {
-  __device__ double operator()(const PolyDesc& d, int j, double, double) const { return u2d(gld(d.src, j)); }
+  __device__ uint64_t raw(const PolyDesc& d, int j) const { return gld(d.src, j); }
+  __device__ double cvt(const PolyDesc&, uint64_t u, double, double) const { return u2d(u); }
+  __device__ double operator()(const PolyDesc& d, int j, double q, double qi) const { return cvt(d, raw(d, j), q, qi); }
 };
+// Stores: prepare() may stage an operand in LDS, fetch(d, j) loads the epilogue's global
+// operand for word j, put() writes word j.
+// kPersistent: whether the persistent kernel may run this epilogue.  The ModDown epilogue
+// stages an operand through registers into LDS; next to a register prefetch of the following
+// polynomial that no longer fits 128 VGPRs, so it always runs one polynomial per workgroup.
 struct StPlain {
+  static constexpr bool kPersistent = true;
+  struct Operand {};
   __device__ void prepare(const PolyDesc&, double*, int) const {}
-  __device__ void operator()(const PolyDesc& d, int j, double v, double, double, const double*) const { gst(d.dst, j, d2u(v)); }
+  __device__ Operand fetch(const PolyDesc&, int) const { return {}; }
+  __device__ void put(const PolyDesc& d, int j, double v, Operand, double, double, const double*) const { gst(d.dst, j, d2u(v)); }
 };
 // load a residue of another modulus (aux = that modulus as double) and lift it centred into
 // this modulus: used by rescale (last limb -> limb i)
 struct LdCentredLift {
-  __device__ double operator()(const PolyDesc& d, int j, double q, double qi) const {
-    const double v = u2d(gld(d.src, j));
+  __device__ uint64_t raw(const PolyDesc& d, int j) const { return gld(d.src, j); }
+  __device__ double cvt(const PolyDesc& d, uint64_t u, double q, double qi) const {
+    const double v = u2d(u);
     const double ql = d.aux;
     const double t = v > 0.5 * ql ? v - ql : v;  // centred, |t| < q_l / 2
     return reduce_s(t, q, qi);
   }
+  __device__ double operator()(const PolyDesc& d, int j, double q, double qi) const { return cvt(d, raw(d, j), q, qi); }
 };
 // rescale epilogue: dst[j] <- (c_i[j] - v) * q_l^-1 mod q_i, c_i = d.src2, aux2 = q_l^-1 mod q_i
 struct StRescale {
+  static constexpr bool kPersistent = true;
+  using Operand = uint64_t;
   __device__ void prepare(const PolyDesc&, double*, int) const {}
-  __device__ void operator()(const PolyDesc& d, int j, double v, double q, double qi, const double*) const {
-    const double ci = u2d(gld(d.src2, j));
-    const double r = mulmod_s(ci - v, d.aux2, q, qi);
+  __device__ Operand fetch(const PolyDesc& d, int j) const { return gld(d.src2, j); }
+  __device__ void put(const PolyDesc& d, int j, double v, Operand ci, double q, double qi, const double*) const {
+    const double r = mulmod_s(u2d(ci) - v, d.aux2, q, qi);
     gst(d.dst, j, d2u(canon(r, q)));
   }
 };
 // ModDown epilogue: dst[j] <- (u_i[j] - v) * P^-1 (+ add[j] if src3), u_i = src2 (u64).
-// For a rotation add = sigma_g(c0), a permuted read of src3: src3 is first staged in LDS with
-// coalesced reads, then read there at the permuted index.
+// For a rotation add = sigma_g(c0), a permuted read of src3.  src3 is staged in LDS with
+// coalesced reads (then read there, at the permuted index for a rotation), which keeps the
+// epilogue's global loads to one word per output.
 struct StModDown {
+  static constexpr bool kPersistent = false;
+  using Operand = uint64_t;
   __device__ void prepare(const PolyDesc& d, double* lds, int tid) const {
-    if (!d.src3 || !d.gal) return;  // uniform over the workgroup (one descriptor)
+    if (!d.src3) return;  // uniform over the workgroup (one descriptor)
     const int T = (1 << d.log_n) / kPerThread;
     lds_barrier();
 #pragma unroll
@@ -342,11 +393,11 @@ struct StModDown {
     }
     lds_barrier();
   }
-  __device__ void operator()(const PolyDesc& d, int j, double v, double q, double qi, const double* lds) const {
-    const double ui = u2d(gld(d.src2, j));
-    double r = canon(mulmod_s(ui - v, d.aux2, q, qi), q);
+  __device__ Operand fetch(const PolyDesc& d, int j) const { return gld(d.src2, j); }
+  __device__ void put(const PolyDesc& d, int j, double v, Operand ui, double q, double qi, const double* lds) const {
+    double r = canon(mulmod_s(u2d(ui) - v, d.aux2, q, qi), q);
     if (d.src3) {
-      r += d.gal ? lds[pad_idx((int)gal_perm((uint32_t)j, d.gal, d.log_n))] : u2d(gld(d.src3, j));
+      r += lds[pad_idx(d.gal ? (int)gal_perm((uint32_t)j, d.gal, d.log_n) : j)];
       r = r >= q ? r - q : r;
     }
     gst(d.dst, j, d2u(r));
@@ -355,9 +406,12 @@ struct StModDown {
 
 // add-into epilogue: dst[j] <- src2[j] + v mod q  (mask added to c0 in evaluation form)
 struct StAddTo {
+  static constexpr bool kPersistent = true;
+  using Operand = uint64_t;
   __device__ void prepare(const PolyDesc&, double*, int) const {}
-  __device__ void operator()(const PolyDesc& d, int j, double v, double q, double, const double*) const {
-    double r = u2d(gld(d.src2, j)) + v;
+  __device__ Operand fetch(const PolyDesc& d, int j) const { return gld(d.src2, j); }
+  __device__ void put(const PolyDesc& d, int j, double v, Operand a, double q, double, const double*) const {
+    double r = u2d(a) + v;
     r = r >= q ? r - q : r;
     gst(d.dst, j, d2u(r));
   }
