@@ -531,9 +531,8 @@ int encode_dense_dev(blb_ctx* c, const double* d_vals, int n_vals, int count, do
   double* a = tmp.get<double>((size_t)count * M * 4);
   double* b = tmp.get<double>((size_t)count * M * 4);
   if (tmp.failed) return BLB_ENOMEM;
-  launch_enc_scatter_dense(c, d_vals, n_vals, count, a);
   (void)hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream);
-  run_encode_core(c, a, b, count, scale, level + 1, out, c->d_flag, false);
+  run_encode_dense(c, d_vals, n_vals, count, a, b, scale, level + 1, out, c->d_flag);
   int flag = 0;
   (void)hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
   if (hipStreamSynchronize(c->stream) != hipSuccess) return BLB_EDEVICE;
@@ -634,19 +633,19 @@ int blb_ctx_create(const blb_params* prm, blb_ctx** out) {
     const int M = n / 2;
     std::vector<double> tw((size_t)(M / 2) * 4), twist((size_t)M * 4);
     blb_host_enc_tables(c->log_n, tw.data(), twist.data());
-    std::vector<int32_t> su(M);
+    std::vector<int32_t> su(M);  // position (5^j mod 2N - 1) / 4 -> slot j
     uint64_t e = 1;
     for (int j = 0; j < M; ++j) {
-      su[j] = (int32_t)((e - 1) / 4);
+      su[(e - 1) / 4] = j;
       e = e * 5 % (2ull * n);
     }
     if ((rc = dalloc(c, (void**)&c->d_enc_tw, tw.size() * sizeof(double)))) return fail(rc);
     if ((rc = dalloc(c, (void**)&c->d_enc_twist, twist.size() * sizeof(double)))) return fail(rc);
-    if ((rc = dalloc(c, (void**)&c->d_slot_u, su.size() * sizeof(int32_t)))) return fail(rc);
+    if ((rc = dalloc(c, (void**)&c->d_slot_inv, su.size() * sizeof(int32_t)))) return fail(rc);
     if ((rc = dalloc(c, (void**)&c->d_flag, 256))) return fail(rc);
     if (hipMemcpy(c->d_enc_tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(BLB_EDEVICE);
     if (hipMemcpy(c->d_enc_twist, twist.data(), twist.size() * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(BLB_EDEVICE);
-    if (hipMemcpy(c->d_slot_u, su.data(), su.size() * 4, hipMemcpyHostToDevice) != hipSuccess) return fail(BLB_EDEVICE);
+    if (hipMemcpy(c->d_slot_inv, su.data(), su.size() * 4, hipMemcpyHostToDevice) != hipSuccess) return fail(BLB_EDEVICE);
   }
   for (int l = 0; l < c->n_q; ++l) {
     build_ks_level(c, l, &c->h_kc[l]);
@@ -684,7 +683,7 @@ void blb_ctx_destroy(blb_ctx* c) {
   dfree(c, c->d_mods, sizeof(uint64_t) * BLB_MAXM);
   dfree(c, c->d_enc_tw, sizeof(double) * (c->n / 4) * 4);
   dfree(c, c->d_enc_twist, sizeof(double) * (c->n / 2) * 4);
-  dfree(c, c->d_slot_u, sizeof(int32_t) * (c->n / 2));
+  dfree(c, c->d_slot_inv, sizeof(int32_t) * (c->n / 2));
   dfree(c, c->d_flag, 256);
   for (int l = 0; l < BLB_MAXQ; ++l) dfree(c, c->d_kc[l], sizeof(KsLevelConst));
   delete c;
@@ -1187,9 +1186,8 @@ int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int 
     const double scale = (double)c->mod[level] / BLB_NOISE_BOOST;
     for (size_t p0 = 0; p0 < n_pt; p0 += chunk) {
       const int cnt = (int)std::min<size_t>(chunk, n_pt - p0);
-      launch_enc_scatter_cp(c, dW, g, (int)p0, cnt, a);
       uint64_t* dst = P->pt + p0 * nl * n;
-      run_encode_core(c, a, b, cnt, scale, nl, dst, c->d_flag, true);
+      run_encode_cp(c, dW, g, (int)p0, cnt, a, b, scale, nl, dst, c->d_flag);
       ntt_regular(c, dst, (size_t)cnt * nl, nl, true);
     }
     if (flag_host) {

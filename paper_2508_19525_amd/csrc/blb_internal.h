@@ -187,7 +187,7 @@ struct blb_ctx {
   double* d_tw_inv = nullptr;
   double* d_enc_tw = nullptr;     // [N/4][4] eta^k (dd complex), eta = exp(2 pi i / (N/2))
   double* d_enc_twist = nullptr;  // [N/2][4] zeta^-k (dd complex)
-  int32_t* d_slot_u = nullptr;    // slot j -> (5^j mod 2N - 1) / 4
+  int32_t* d_slot_inv = nullptr;  // DFT position u -> slot j with (5^j mod 2N - 1) / 4 = u
   KsLevelConst* d_kc[BLB_MAXQ] = {};
   KsLevelConst h_kc[BLB_MAXQ];
   char* scratch = nullptr;
@@ -294,6 +294,7 @@ void launch_mask_sample(blb_ctx* c, uint64_t* r_out, uint64_t* share, int n_ct, 
 void launch_set_u64(blb_ctx* c, uint64_t* dst, uint64_t value);
 void launch_zero(blb_ctx* c, uint64_t* dst, size_t words);
 // paired: the buffers hold (count + 1) / 2 complex vectors, each packing two real inputs
-int run_encode_core(blb_ctx* c, double* bufA, double* bufB, int count, double scale, int nl, uint64_t* out, int* d_overflow, bool paired);
-void launch_enc_scatter_dense(blb_ctx* c, const double* vals, int n_vals, int count, double* buf);
-void launch_enc_scatter_cp(blb_ctx* c, const double* W, CpGeom g, int p0, int count, double* buf);
+int run_encode_dense(blb_ctx* c, const double* vals, int n_vals, int count, double* bufA, double* bufB, double scale, int nl, uint64_t* out,
+                     int* d_overflow);
+int run_encode_cp(blb_ctx* c, const double* W, CpGeom g, int p0, int count, double* bufA, double* bufB, double scale, int nl, uint64_t* out,
+                  int* d_overflow);

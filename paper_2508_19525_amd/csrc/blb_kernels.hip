@@ -455,8 +455,8 @@ void launch_zero(blb_ctx* c, uint64_t* dst, size_t words) {
 //   Slot j sits at zeta^(e_j), e_j = 5^j mod 2N = 4 u_j + 1.  With w_k = p_k + i p_{k+M}
 //   (M = N/2), p(zeta^(4u+1)) = sum_k zeta^k w_k eta^(uk), eta = exp(2 pi i / M), so
 //   w_k = zeta^-k (1/M) sum_u v_u eta^(-uk) with v_u the (real) slot value at u.
-//   Steps: scatter (v), radix-2 Stockham DFT of size M (exp(-i...)), finalize (twist, scale,
-//   round half away from zero, reduce into the limbs).
+//   Steps: DFT of size M (exp(-i...)) of the slot values placed at their positions u, then
+//   finalize (twist, scale, round half away from zero, reduce into the limbs).
 // ---------------------------------------------------------------------------------------
 struct dd { double hi, lo; };
 __device__ __forceinline__ dd two_sum(double a, double b) {
@@ -499,141 +499,135 @@ __device__ __forceinline__ cdd cdd_sub(cdd a, cdd b) { return cdd{dd_add(a.re, d
 __device__ __forceinline__ cdd ld_cdd(const double* p) { return cdd{dd{p[0], p[1]}, dd{p[2], p[3]}}; }
 __device__ __forceinline__ void st_cdd(double* p, cdd v) { p[0] = v.re.hi; p[1] = v.re.lo; p[2] = v.im.hi; p[3] = v.im.lo; }
 
-// scatter from a dense value array: vals[p][j] (n_vals per plaintext)
-__global__ void k_enc_scatter_dense(const double* vals, int n_vals, double* buf, const int32_t* slot_u, int M) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int p = blockIdx.y;
-  if (j >= M) return;
-  const double v = j < n_vals ? vals[(size_t)p * n_vals + j] : 0.0;
-  double* o = buf + ((size_t)p * M + slot_u[j]) * 4;
-  o[0] = v; o[1] = 0.0; o[2] = 0.0; o[3] = 0.0;
-}
+// Slot values.  Position u of the DFT input holds slot j = slot_inv[u] (u_j = (5^j mod 2N - 1) / 4).
+// Dense source: vals[p][j], n_vals per plaintext, one plaintext per complex vector.
+// begin(p) gathers what is uniform over complex vector p, (ctx, u) gives the value at u.
+struct EncSrcDense {
+  const double* vals;
+  int n_vals;
+  const int32_t* slot_inv;
+  __device__ const double* begin(int p) const { return vals + (size_t)p * n_vals; }
+  __device__ cdd operator()(const double* v, int u) const {
+    const int j = slot_inv[u];
+    return cdd{dd{j < n_vals ? v[j] : 0.0, 0.0}, dd{0.0, 0.0}};
+  }
+};
 
-// scatter of matmul_cp diagonal plaintexts, two per complex vector (plaintext p0 + 2 pp in the
-// real part, p0 + 2 pp + 1 in the imaginary part); plaintext p = (bj, ai):
+// matmul_cp diagonal plaintexts, two per complex vector (plaintext p0 + 2 pp in the real part,
+// p0 + 2 pp + 1 in the imaginary part); plaintext p = (bj, ai):
 //   value at slot s = W{a c + ((u + t) mod c_eff), b c + (u mod c_out)}, u = ((s - r) mod S) / L',
 //   t = jB + i, r = j B L' (plaintext pre-rotated right by r).
-__device__ __forceinline__ double cp_diag_value(const double* W, const CpGeom& g, int p, int s, int M) {
-  const int n_ai = g.n_in * g.B;
-  const int bj = p / n_ai, ai = p % n_ai;
-  const int b = bj / g.G, j = bj % g.G;
-  const int a = ai / g.B, i = ai % g.B;
-  const int t = j * g.B + i;
-  const int r = j * g.B * g.Lp;
-  const int slot = ((s - r) % M + M) % M;
-  const int u = slot / g.Lp;
-  const int row = a * g.c + (u + t) % g.c_eff;
-  const int col = b * g.c + (u % g.c_out);
-  return (row < g.d_in && col < g.d_out) ? W[(size_t)row * g.d_out + col] : 0.0;
-}
-__global__ void k_enc_scatter_cp(const double* W, CpGeom g, int p0, int count, double* buf, const int32_t* slot_u, int M) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  const int pp = blockIdx.y;
-  if (s >= M) return;
-  const int pl = 2 * pp;
-  const double v1 = cp_diag_value(W, g, p0 + pl, s, M);
-  const double v2 = pl + 1 < count ? cp_diag_value(W, g, p0 + pl + 1, s, M) : 0.0;
-  double* o = buf + ((size_t)pp * M + slot_u[s]) * 4;
-  o[0] = v1; o[1] = 0.0; o[2] = v2; o[3] = 0.0;
-}
-
-// one radix-2 Stockham stage (forward sign) on [count][M] complex dd values
-__global__ void k_enc_stage(const double* in, double* out, const double* tw /* [M/2][4] eta^k */, int M, int ns) {
-  const int jj = blockIdx.x * blockDim.x + threadIdx.x;
-  const int p = blockIdx.y;
-  if (jj >= M / 2) return;
-  const double* x = in + (size_t)p * M * 4;
-  double* y = out + (size_t)p * M * 4;
-  const int kpos = jj % ns;
-  const int tw_idx = kpos * (M / (2 * ns));
-  cdd w = ld_cdd(tw + (size_t)tw_idx * 4);
-  w.im = dd_neg(w.im);  // exp(-2 pi i k / (2 ns))
-  const cdd a = ld_cdd(x + (size_t)jj * 4);
-  const cdd b = cdd_mul(ld_cdd(x + (size_t)(jj + M / 2) * 4), w);
-  const int idx = (jj / ns) * 2 * ns + kpos;
-  st_cdd(y + (size_t)idx * 4, cdd_add(a, b));
-  st_cdd(y + (size_t)(idx + ns) * 4, cdd_sub(a, b));
-}
-
-// one radix-4 Stockham pass (two radix-2 stages at once, forward sign), same layout: thread j
-// (k = j mod ns) reads x[j + r M/4], twiddles them by exp(-2 pi i r k / (4 ns)), runs a 4-point
-// DFT and writes y[(j / ns) 4 ns + k + r ns].  Half the global-memory passes of radix 2.
-__global__ void k_enc_stage4(const double* in, double* out, const double* tw /* [M/2][4] eta^k */, int M, int ns) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int p = blockIdx.y;
-  if (j >= M / 4) return;
-  const double* x = in + (size_t)p * M * 4;
-  double* y = out + (size_t)p * M * 4;
-  const int k = j % ns;
-  const int step = M / (4 * ns);
-  const int half = M / 2;
-  cdd v[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) v[r] = ld_cdd(x + (size_t)(j + r * (M / 4)) * 4);
-#pragma unroll
-  for (int r = 1; r < 4; ++r) {
-    const int e = r * k * step;  // < 3M/4; eta^(e) = -eta^(e - M/2) past M/2
-    cdd w = ld_cdd(tw + (size_t)(e >= half ? e - half : e) * 4);
-    w.im = dd_neg(w.im);  // exp(-2 pi i e / M)
-    if (e >= half) { w.re = dd_neg(w.re); w.im = dd_neg(w.im); }
-    v[r] = cdd_mul(v[r], w);
+// L', c, c_eff, c_out and S are powers of two (lLp = log2 L').
+struct EncSrcCp {
+  const double* W;
+  CpGeom g;
+  int p0, count, M, lLp;
+  const int32_t* slot_inv;
+  struct Diag {
+    int r, t, row0, col0;
+    bool used;
+  };
+  struct Pair {
+    Diag x, y;
+  };
+  __device__ Diag diag(int p) const {
+    const int n_ai = g.n_in * g.B;
+    const int bj = p / n_ai, ai = p % n_ai;
+    const int b = bj / g.G, j = bj % g.G;
+    const int a = ai / g.B, i = ai % g.B;
+    return Diag{j * g.B * g.Lp, j * g.B + i, a * g.c, b * g.c, p < p0 + count};
   }
-  const cdd t0 = cdd_add(v[0], v[2]), t1 = cdd_sub(v[0], v[2]), t2 = cdd_add(v[1], v[3]), d = cdd_sub(v[1], v[3]);
-  const cdd t3 = cdd{d.im, dd_neg(d.re)};  // (v1 - v3) * (-i)
-  const int idx = (j / ns) * 4 * ns + k;
-  st_cdd(y + (size_t)idx * 4, cdd_add(t0, t2));
-  st_cdd(y + (size_t)(idx + ns) * 4, cdd_add(t1, t3));
-  st_cdd(y + (size_t)(idx + 2 * ns) * 4, cdd_sub(t0, t2));
-  st_cdd(y + (size_t)(idx + 3 * ns) * 4, cdd_sub(t1, t3));
-}
-
-// 4-point forward DFT in place (exact: only sums and multiplications by -i)
-__device__ __forceinline__ void dft4(cdd& a0, cdd& a1, cdd& a2, cdd& a3) {
-  const cdd t0 = cdd_add(a0, a2), t1 = cdd_sub(a0, a2), t2 = cdd_add(a1, a3), d = cdd_sub(a1, a3);
-  const cdd t3 = cdd{d.im, dd_neg(d.re)};  // (a1 - a3) * (-i)
-  a0 = cdd_add(t0, t2);
-  a1 = cdd_add(t1, t3);
-  a2 = cdd_sub(t0, t2);
-  a3 = cdd_sub(t1, t3);
-}
-
-// one radix-8 Stockham pass (three radix-2 stages at once, forward sign): thread j (k = j mod ns)
-// reads x[j + r M/8], twiddles them by exp(-2 pi i r k / (8 ns)), runs an 8-point DFT (two
-// 4-point DFTs and the odd-part factors exp(-2 pi i s / 8)) and writes y[(j / ns) 8 ns + k + r ns]
-__global__ void k_enc_stage8(const double* in, double* out, const double* tw /* [M/2][4] eta^k */, int M, int ns) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int p = blockIdx.y;
-  if (j >= M / 8) return;
-  const double* x = in + (size_t)p * M * 4;
-  double* y = out + (size_t)p * M * 4;
-  const int k = j % ns;
-  const int step = M / (8 * ns);
-  const int half = M / 2;
-  cdd v[8];
-#pragma unroll
-  for (int r = 0; r < 8; ++r) v[r] = ld_cdd(x + (size_t)(j + r * (M / 8)) * 4);
-#pragma unroll
-  for (int r = 1; r < 8; ++r) {
-    const int e = r * k * step;  // < 7M/8
-    cdd w = ld_cdd(tw + (size_t)(e >= half ? e - half : e) * 4);
-    w.im = dd_neg(w.im);  // exp(-2 pi i e / M)
-    if (e >= half) { w.re = dd_neg(w.re); w.im = dd_neg(w.im); }
-    v[r] = cdd_mul(v[r], w);
+  __device__ double value(const Diag& d, int s) const {
+    if (!d.used) return 0.0;
+    const int u = ((s - d.r) & (M - 1)) >> lLp;
+    const int row = d.row0 + ((u + d.t) & (g.c_eff - 1));
+    const int col = d.col0 + (u & (g.c_out - 1));
+    return (row < g.d_in && col < g.d_out) ? W[(size_t)row * g.d_out + col] : 0.0;
   }
-  dft4(v[0], v[2], v[4], v[6]);  // even part E
-  dft4(v[1], v[3], v[5], v[7]);  // odd part O
-  const dd rh = dd{0.70710678118654757, -4.8336466567264567e-17};  // 1/sqrt(2) in double-double
-  cdd o[4] = {v[1], v[3], v[5], v[7]};
-  // o[s] *= exp(-2 pi i s / 8): s = 1: (1 - i)/sqrt 2, s = 2: -i, s = 3: -(1 + i)/sqrt 2
-  o[1] = cdd{dd_mul(dd_add(o[1].re, o[1].im), rh), dd_mul(dd_add(o[1].im, dd_neg(o[1].re)), rh)};
-  o[2] = cdd{o[2].im, dd_neg(o[2].re)};
-  o[3] = cdd{dd_mul(dd_add(o[3].im, dd_neg(o[3].re)), rh), dd_neg(dd_mul(dd_add(o[3].re, o[3].im), rh))};
-  const cdd e4[4] = {v[0], v[2], v[4], v[6]};
-  const int idx = (j / ns) * 8 * ns + k;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    st_cdd(y + (size_t)(idx + q * ns) * 4, cdd_add(e4[q], o[q]));
-    st_cdd(y + (size_t)(idx + (q + 4) * ns) * 4, cdd_sub(e4[q], o[q]));
+  __device__ Pair begin(int pp) const { return Pair{diag(p0 + 2 * pp), diag(p0 + 2 * pp + 1)}; }
+  __device__ cdd operator()(const Pair& pr, int u) const {
+    const int s = slot_inv[u];
+    return cdd{dd{value(pr.x, s), 0.0}, dd{value(pr.y, s), 0.0}};
+  }
+};
+
+// The size-M DFT (forward sign) in four steps, M = M1 M2 with M2 = 128, n = M2 n1 + n2,
+// k = k1 + M1 k2:
+//   Y[k1 + M1 k2] = sum_n2 e^(-2 pi i n2 k2 / M2) [ e^(-2 pi i n2 k1 / M) sum_n1 v[M2 n1 + n2] e^(-2 pi i n1 k1 / M1) ].
+// The column pass does the inner M1-point DFTs and the twiddles (Z[k1][n2]), the row pass the
+// outer M2-point DFTs.  Both run in LDS, so the transform makes two passes over HBM.
+constexpr int kEncM2 = 128;
+constexpr int kEncCB = 8;     // columns (n2) per workgroup in the column pass
+constexpr int kEncRB = 4;     // rows (k1) per workgroup in the row pass
+constexpr int kEncM1Max = 64;  // M <= 8192
+
+// e^(-2 pi i e / M), 0 <= e < M, from the table of eta^k = e^(2 pi i k / M), k < M/2
+__device__ __forceinline__ cdd enc_twiddle(const double* tw, int e, int M) {
+  const int half = M / 2;
+  cdd w = ld_cdd(tw + (size_t)(e >= half ? e - half : e) * 4);
+  w.im = dd_neg(w.im);
+  if (e >= half) {
+    w.re = dd_neg(w.re);
+    w.im = dd_neg(w.im);
+  }
+  return w;
+}
+
+// radix-2 Stockham DFT (forward sign) of nv length-L vectors in LDS (vector v at a + v L),
+// with b as the second buffer; every work-item of the block takes part.  Returns the buffer
+// that holds the result.
+__device__ cdd* lds_dft(cdd* a, cdd* b, int L, int nv, const double* tw, int M) {
+  for (int ns = 1; ns < L; ns *= 2) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < nv * (L / 2); t += blockDim.x) {
+      const int v = t / (L / 2), jj = t % (L / 2);
+      const int kpos = jj % ns;
+      const cdd w = enc_twiddle(tw, kpos * (M / (2 * ns)), M);  // e^(-2 pi i kpos / (2 ns))
+      const cdd x0 = a[v * L + jj];
+      const cdd x1 = cdd_mul(a[v * L + jj + L / 2], w);
+      const int idx = (jj / ns) * 2 * ns + kpos;
+      b[v * L + idx] = cdd_add(x0, x1);
+      b[v * L + idx + ns] = cdd_sub(x0, x1);
+    }
+    cdd* t = a;
+    a = b;
+    b = t;
+  }
+  __syncthreads();
+  return a;
+}
+
+// column pass: kEncCB columns n2 of complex vector p; writes Z[p][k1][n2] (rows of M2)
+template <class Src>
+__global__ __launch_bounds__(256) void k_enc_cols(Src src, double* zbuf, const double* tw, int M, int M1) {
+  __shared__ cdd sa[kEncM1Max * kEncCB], sb[kEncM1Max * kEncCB];
+  const int n2_0 = blockIdx.x * kEncCB;
+  const int p = blockIdx.y;
+  const auto ctx = src.begin(p);
+  for (int t = threadIdx.x; t < M1 * kEncCB; t += blockDim.x) {
+    const int n1 = t / kEncCB, cc = t % kEncCB;
+    sa[cc * M1 + n1] = src(ctx, kEncM2 * n1 + n2_0 + cc);
+  }
+  const cdd* r = lds_dft(sa, sb, M1, kEncCB, tw, M);
+  for (int t = threadIdx.x; t < M1 * kEncCB; t += blockDim.x) {
+    const int k1 = t / kEncCB, cc = t % kEncCB;
+    const int n2 = n2_0 + cc;
+    const cdd z = cdd_mul(r[cc * M1 + k1], enc_twiddle(tw, n2 * k1, M));  // n2 k1 < M2 M1 = M
+    st_cdd(zbuf + ((size_t)p * M + (size_t)k1 * kEncM2 + n2) * 4, z);
+  }
+}
+
+// row pass: kEncRB rows k1 of vector p; writes Y[p][k1 + M1 k2]
+__global__ __launch_bounds__(256) void k_enc_rows(const double* zbuf, double* ybuf, const double* tw, int M, int M1) {
+  __shared__ cdd sa[kEncRB * kEncM2], sb[kEncRB * kEncM2];
+  const int k1_0 = blockIdx.x * kEncRB;
+  const int p = blockIdx.y;
+  for (int t = threadIdx.x; t < kEncRB * kEncM2; t += blockDim.x)
+    sa[t] = ld_cdd(zbuf + ((size_t)p * M + (size_t)k1_0 * kEncM2 + t) * 4);
+  const cdd* r = lds_dft(sa, sb, kEncM2, kEncRB, tw, M);
+  for (int t = threadIdx.x; t < kEncRB * kEncM2; t += blockDim.x) {
+    const int k2 = t / kEncRB, rr = t % kEncRB;
+    st_cdd(ybuf + ((size_t)p * M + k1_0 + rr + (size_t)M1 * k2) * 4, r[rr * kEncM2 + k2]);
   }
 }
 
@@ -706,48 +700,32 @@ __global__ void k_enc_final_pair(const double* ybuf, const double* twist, double
   if (2 * pp + 1 < count) enc_round_store(x2, twist, scale_over_m, M, k, nl, mt, mods, out + (size_t)(2 * pp + 1) * stride, overflow);
 }
 
-// Encodes `count` plaintexts already scattered into bufA ([count][M][4] doubles); output
-// coefficient-form residues out[count][nl][N].  bufB is a second buffer of the same size.
-int run_encode_core(blb_ctx* c, double* bufA, double* bufB, int count, double scale, int nl, uint64_t* out, int* d_overflow, bool paired) {
-  const int M = c->n / 2;
+// Encodes `count` plaintexts into coefficient-form residues out[count][nl][N] (the DFT of the
+// slot values from src, then twist, scale, rounding and residues).  bufA, bufB: [count][M][4].
+template <class Src>
+int encode_with(blb_ctx* c, const Src& src, int count, double* bufA, double* bufB, double scale, int nl, uint64_t* out, int* d_overflow,
+                bool paired) {
+  const int M = c->n / 2, M1 = M / kEncM2;
+  if (M1 < kEncRB || M1 > kEncM1Max) return BLB_EINVAL;
   const int n_vec = paired ? (count + 1) / 2 : count;  // complex vectors transformed
-  double* in = bufA;
-  double* outb = bufB;
-  // radix-8 passes, with one radix-2 or radix-4 pass first when log2 M is not a multiple of 3
-  int ns = 1;
-  const int rem = (c->log_n - 1) % 3;
-  if (rem == 1) {
-    dim3 grid((M / 2 + 255) / 256, n_vec);
-    k_enc_stage<<<grid, 256, 0, c->stream>>>(in, outb, c->d_enc_tw, M, ns);
-    double* t = in; in = outb; outb = t;
-    ns = 2;
-  } else if (rem == 2) {
-    dim3 grid((M / 4 + 255) / 256, n_vec);
-    k_enc_stage4<<<grid, 256, 0, c->stream>>>(in, outb, c->d_enc_tw, M, ns);
-    double* t = in; in = outb; outb = t;
-    ns = 4;
-  }
-  for (; ns < M; ns *= 8) {
-    dim3 grid((M / 8 + 255) / 256, n_vec);
-    k_enc_stage8<<<grid, 256, 0, c->stream>>>(in, outb, c->d_enc_tw, M, ns);
-    double* t = in; in = outb; outb = t;
-  }
+  k_enc_cols<<<dim3(kEncM2 / kEncCB, n_vec), 256, 0, c->stream>>>(src, bufB, c->d_enc_tw, M, M1);
+  k_enc_rows<<<dim3(M1 / kEncRB, n_vec), 256, 0, c->stream>>>(bufB, bufA, c->d_enc_tw, M, M1);
   dim3 grid((M + 255) / 256, n_vec);
   if (paired)
-    k_enc_final_pair<<<grid, 256, 0, c->stream>>>(in, c->d_enc_twist, scale / (double)M, M, nl, c->mt, c->d_mods, out, count, d_overflow);
+    k_enc_final_pair<<<grid, 256, 0, c->stream>>>(bufA, c->d_enc_twist, scale / (double)M, M, nl, c->mt, c->d_mods, out, count, d_overflow);
   else
-    k_enc_final<<<grid, 256, 0, c->stream>>>(in, c->d_enc_twist, scale / (double)M, M, nl, c->mt, c->d_mods, out, d_overflow);
-  return 0;
+    k_enc_final<<<grid, 256, 0, c->stream>>>(bufA, c->d_enc_twist, scale / (double)M, M, nl, c->mt, c->d_mods, out, d_overflow);
+  return BLB_OK;
 }
-void launch_enc_scatter_dense(blb_ctx* c, const double* vals, int n_vals, int count, double* buf) {
-  const int M = c->n / 2;
-  dim3 grid((M + 255) / 256, count);
-  k_enc_scatter_dense<<<grid, 256, 0, c->stream>>>(vals, n_vals, buf, c->d_slot_u, M);
+int run_encode_dense(blb_ctx* c, const double* vals, int n_vals, int count, double* bufA, double* bufB, double scale, int nl, uint64_t* out,
+                     int* d_overflow) {
+  return encode_with(c, EncSrcDense{vals, n_vals, c->d_slot_inv}, count, bufA, bufB, scale, nl, out, d_overflow, false);
 }
-void launch_enc_scatter_cp(blb_ctx* c, const double* W, CpGeom g, int p0, int count, double* buf) {
-  const int M = c->n / 2;
-  dim3 grid((M + 255) / 256, (count + 1) / 2);
-  k_enc_scatter_cp<<<grid, 256, 0, c->stream>>>(W, g, p0, count, buf, c->d_slot_u, M);
+int run_encode_cp(blb_ctx* c, const double* W, CpGeom g, int p0, int count, double* bufA, double* bufB, double scale, int nl, uint64_t* out,
+                  int* d_overflow) {
+  int lLp = 0;
+  while ((1 << lLp) < g.Lp) ++lLp;
+  return encode_with(c, EncSrcCp{W, g, p0, count, c->n / 2, lLp, c->d_slot_inv}, count, bufA, bufB, scale, nl, out, d_overflow, true);
 }
 
 // ---------------------------------------------------------------------------------------
