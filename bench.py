@@ -471,6 +471,7 @@ def run_serving(args, B, torch):
     cfg = wl.C5
     p = cfg["params"]
     n, level = p.n, p.n_q - 1
+    torch.cuda.empty_cache()  # the serving runtime sizes its plan cache and workspaces from what is free
     reqs = wl.serving_requests(args.serve_requests, args.serve_rate, cfg["ops"], cfg["L_lo"], cfg["L_hi"], n_clients=4)
     shapes = {wid: shape for _, wid, shape, _, _ in reqs}
     stream = torch.cuda.current_stream().cuda_stream

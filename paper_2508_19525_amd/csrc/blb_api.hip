@@ -671,6 +671,11 @@ int blb_ctx_create(const blb_params* prm, blb_ctx** out) {
 void blb_ctx_destroy(blb_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  {
+    // the context made the device's stream-ordered pool keep what it frees; hand that back
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, c->device) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+  }
   for (TimedSpan& t : c->spans) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);

@@ -328,7 +328,14 @@ void ws_fit(blb_server* S, int k) {
   const size_t cap = (std::max(w.need + w.need / 4, 2 * w.cap) + quantum - 1) / quantum * quantum;
   (void)hipStreamSynchronize(S->streams[k]);
   ws_release(c, w);
-  if ((c->budget && c->dev_bytes + cap > c->budget) || hipMalloc((void**)&w.base, cap) != hipSuccess) {
+  bool ok = !c->budget || c->dev_bytes + cap <= c->budget;
+  if (ok && hipMalloc((void**)&w.base, cap) != hipSuccess) {
+    // memory the stream-ordered pool keeps cached may be what is missing: release it, retry
+    (void)hipGetLastError();
+    (void)blb_ctx_trim(c);
+    ok = hipMalloc((void**)&w.base, cap) == hipSuccess;
+  }
+  if (!ok) {
     (void)hipGetLastError();
     w.base = nullptr;
     S->ws_frozen = true;  // batches take their temporaries from the pool
@@ -479,6 +486,12 @@ int blb_server_create(blb_ctx* c, const blb_server_config* cfg, blb_server** out
   if (!S) return BLB_ENOMEM;
   S->c = c;
   S->cfg = *cfg;
+  // device memory that the stream-ordered pool keeps cached would crowd out the plan arena and
+  // the batch workspaces: release it before reserving them
+  if (blb_ctx_trim(c) != BLB_OK) {
+    delete S;
+    return BLB_EDEVICE;
+  }
   S->arena.cap = cfg->plan_cache_bytes / Arena::kAlign * Arena::kAlign;
   if (S->arena.cap > 0) {
     if (c->budget && c->dev_bytes + S->arena.cap > c->budget) {
