@@ -250,17 +250,17 @@ __global__ __launch_bounds__((1 << LOGN) / kPerThread) __attribute__((amdgpu_wav
   const int tid0 = threadIdx.x;
   int p = blockIdx.x;
   if (p >= count) return;
-  // The next polynomial's words are prefetched raw (converted only when its round starts, so
+  // The next polynomial's words are prefetched raw (converted only when its iteration starts, so
   // nothing waits for them earlier).  Vector-memory completion is tracked in issue order,
-  // stores included: the only wait in a round is for its own prefetch, issued before the
-  // previous round's stores.
+  // stores included: the only wait in an iteration is for its own prefetch, issued before the
+  // previous iteration's stores.
   uint64_t nx[PF];
   {
     const PolyDesc d = descs.get(p);
 #pragma unroll
     for (int i = 0; i < PF; ++i) nx[i] = ld.raw(d, First::idx(tid0, i));
     // the first polynomial's loads complete before the loop: registers still pending on entry
-    // would make the loop head wait for the previous round's stores as well
+    // would make the loop head wait for the previous iteration's stores as well
 #pragma unroll
     for (int i = 0; i < PF; ++i) asm volatile("" : "+v"(nx[i]));
   }
@@ -275,15 +275,15 @@ __global__ __launch_bounds__((1 << LOGN) / kPerThread) __attribute__((amdgpu_wav
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
       uint64_t u = nx[i];
-      asm volatile("" : "+v"(u));  // the conversion stays in this round
+      asm volatile("" : "+v"(u));  // the conversion stays in this iteration
       x[i] = ld.cvt(d, u, q, qi);
     }
 #pragma unroll
     for (int i = PF; i < kPerThread; ++i) x[i] = ld(d, First::idx(tid, i), q, qi);
     const int pn = p + gridDim.x;
     {
-      // unconditional (the last round re-reads its own polynomial), so the loads land in nx
-      // directly and are only waited for when the next round starts
+      // unconditional (the last iteration re-reads its own polynomial), so the loads land in nx
+      // directly and are only waited for when the next iteration starts
       const PolyDesc dn = descs.get(pn < count ? pn : p);
       const double qn = mt.m[dn.mod].q, qin = mt.m[dn.mod].qinv;
 #pragma unroll
