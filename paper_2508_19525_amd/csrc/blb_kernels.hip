@@ -814,9 +814,15 @@ void launch_masked_acc(blb_ctx* c, const CcTerm* terms, const int* off, uint64_t
 // plaintext word loaded is applied to IB instances' rotated inputs, so instances sharing a
 // plan read its diagonals once per IB instances.
 // ---------------------------------------------------------------------------------------
+// The tile's tail (outputs past n_bj, instances past the group's last) is computed on clamped,
+// in-bounds operands and not stored, so the inner loop has no branches.  Operands go through
+// the global address space (pointer tables through scalar loads) and the next term's words are
+// loaded while the current term is multiplied.
 template <int TB, int IB, int CPT>
 __global__ __launch_bounds__(256) void k_cp_mac_batch(const MacGroup* __restrict__ groups, const MacItem* __restrict__ items, int n_items,
                                                       int n, ModTable mt) {
+  typedef __attribute__((address_space(1))) const uint64_t gu64c;
+  typedef __attribute__((address_space(4))) const uint64_t ku64;
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const MacItem item = items[it];
     const MacGroup gr = groups[item.group];
@@ -827,6 +833,29 @@ __global__ __launch_bounds__(256) void k_cp_mac_batch(const MacGroup* __restrict
     const double q = me.q, qi = me.qinv;
     const int bj0 = item.tile * TB;
     const int ninst = min(IB, gr.n_inst - item.inst0);
+    const size_t term = (size_t)nl * n;  // words per (bj, ai) plaintext
+    const gu64c* pt[TB];
+#pragma unroll
+    for (int t = 0; t < TB; ++t) pt[t] = (const gu64c*)(gr.pt + (size_t)min(bj0 + t, n_bj - 1) * n_ai * term + (size_t)limb * n + k0);
+    const ku64* rxtab[IB];  // row of rotated-input pointers of each instance
+#pragma unroll
+    for (int u = 0; u < IB; ++u) rxtab[u] = (const ku64*)(gr.rx + (size_t)(item.inst0 + min(u, ninst - 1)) * n_ai);
+    uint64_t rw[TB][CPT], rx0[IB][CPT], rx1[IB][CPT];  // raw words of the term in flight
+    auto fetch = [&](int ai) {
+#pragma unroll
+      for (int t = 0; t < TB; ++t)
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) rw[t][c] = __builtin_nontemporal_load(pt[t] + (size_t)ai * term + c);
+#pragma unroll
+      for (int u = 0; u < IB; ++u) {
+        const gu64c* x = (const gu64c*)rxtab[u][ai];
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+          rx0[u][c] = x[(size_t)limb * n + k0 + c];
+          rx1[u][c] = x[(size_t)(nl + limb) * n + k0 + c];
+        }
+      }
+    };
     double a0[IB][TB][CPT], a1[IB][TB][CPT];
 #pragma unroll
     for (int u = 0; u < IB; ++u)
@@ -834,40 +863,28 @@ __global__ __launch_bounds__(256) void k_cp_mac_batch(const MacGroup* __restrict
       for (int t = 0; t < TB; ++t)
 #pragma unroll
         for (int c = 0; c < CPT; ++c) { a0[u][t][c] = 0.0; a1[u][t][c] = 0.0; }
-    const size_t pt_stride_bj = (size_t)n_ai * nl * n;
+    fetch(0);
     for (int ai = 0; ai < n_ai; ++ai) {
-      double x0[IB][CPT], x1[IB][CPT];
+      double w[TB][CPT], x0[IB][CPT], x1[IB][CPT];
 #pragma unroll
-      for (int u = 0; u < IB; ++u) {
-        if (u < ninst) {
-          const uint64_t* rx = gr.rx[(size_t)(item.inst0 + u) * n_ai + ai];
+      for (int t = 0; t < TB; ++t)
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) w[t][c] = u2d(rw[t][c]);
+#pragma unroll
+      for (int u = 0; u < IB; ++u)
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) { x0[u][c] = u2d(rx0[u][c]); x1[u][c] = u2d(rx1[u][c]); }
+      fetch(min(ai + 1, n_ai - 1));  // the last term re-reads itself
+#pragma unroll
+      for (int t = 0; t < TB; ++t)
+#pragma unroll
+        for (int u = 0; u < IB; ++u)
 #pragma unroll
           for (int c = 0; c < CPT; ++c) {
-            x0[u][c] = u2d(rx[(size_t)limb * n + k0 + c]);
-            x1[u][c] = u2d(rx[(size_t)(nl + limb) * n + k0 + c]);
+            a0[u][t][c] += mulmod_s(w[t][c], x0[u][c], q, qi);
+            a1[u][t][c] += mulmod_s(w[t][c], x1[u][c], q, qi);
           }
-        } else {
-#pragma unroll
-          for (int c = 0; c < CPT; ++c) { x0[u][c] = 0.0; x1[u][c] = 0.0; }
-        }
-      }
-      const uint64_t* p = gr.pt + ((size_t)bj0 * n_ai + ai) * nl * n + (size_t)limb * n + k0;
-#pragma unroll
-      for (int t = 0; t < TB; ++t) {
-        if (bj0 + t < n_bj) {
-          double w[CPT];
-#pragma unroll
-          for (int c = 0; c < CPT; ++c) w[c] = u2d(__builtin_nontemporal_load(p + t * pt_stride_bj + c));
-#pragma unroll
-          for (int u = 0; u < IB; ++u)
-#pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-              a0[u][t][c] += mulmod_s(w[c], x0[u][c], q, qi);
-              a1[u][t][c] += mulmod_s(w[c], x1[u][c], q, qi);
-            }
-        }
-      }
-      if ((ai & 7) == 7) {
+      if ((ai & 7) == 7) {  // keep |acc| < 9q < 2^53
 #pragma unroll
         for (int u = 0; u < IB; ++u)
 #pragma unroll
