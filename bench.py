@@ -408,7 +408,7 @@ def run_batch(args, B, torch):
     # autotune the batched MAC (shape x persistent grid): bit-identical variants
     tune = {}
     B.blb_ctx_set_timing(ctx, True)
-    for var in range(5):
+    for var in range(B.BLB_BATCH_VARIANTS):
         for grid in (1024, 4096):
             B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_VARIANT, var)
             B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_GRID, grid)

@@ -717,7 +717,7 @@ int blb_ctx_set_knob(blb_ctx* c, int knob, int value) {
       c->mac_variant = value;
       return BLB_OK;
     case BLB_KNOB_BATCH_VARIANT:
-      if (value < 0 || value > 4) return BLB_EINVAL;
+      if (value < 0 || value >= BLB_BATCH_VARIANTS) return BLB_EINVAL;
       c->batch_variant = value;
       return BLB_OK;
     case BLB_KNOB_BATCH_GRID:

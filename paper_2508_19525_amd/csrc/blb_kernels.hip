@@ -919,6 +919,8 @@ int batch_mac_shape(int variant, int* tb, int* ib, int* cpt) {
     case 2: *tb = 2; *ib = 4; *cpt = 2; break;
     case 3: *tb = 4; *ib = 4; *cpt = 1; break;
     case 4: *tb = 8; *ib = 2; *cpt = 1; break;
+    case 5: *tb = 8; *ib = 4; *cpt = 1; break;
+    case 6: *tb = 4; *ib = 8; *cpt = 1; break;
     default: *tb = 4; *ib = 2; *cpt = 2; break;
   }
   return 0;
@@ -934,6 +936,8 @@ void launch_cp_mac_batch(blb_ctx* c, const MacGroup* groups, const MacItem* item
   else if (tb == 2 && ib == 4) MB(2, 4, 2);
   else if (tb == 4 && ib == 4) MB(4, 4, 1);
   else if (tb == 8 && ib == 2) MB(8, 2, 1);
+  else if (tb == 8 && ib == 4) MB(8, 4, 1);
+  else if (tb == 4 && ib == 8) MB(4, 8, 1);
   else MB(4, 2, 2);
 #undef MB
 }

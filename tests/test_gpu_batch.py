@@ -100,9 +100,9 @@ def test_batched_equals_per_instance(env):
         got = wl.unpack_spatial(vecs, I["L"], I["D"], 4096)
         assert np.abs(got - I["Xm"] @ Ws[I["D"]]).max() < 2.0 ** -20
     # knobs never change bits
-    for var in range(5):
+    for var in range(B.BLB_BATCH_VARIANTS):
         B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_VARIANT, var)
-        B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_GRID, [7, 256, 2048, 100000, 13][var])
+        B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_GRID, [7, 256, 2048, 100000, 13, 1024, 300][var])
         B.blb_batch_matmul_cp(ctx, arr)
         torch.cuda.synchronize()
         for k, I in enumerate(inst):
