@@ -57,7 +57,7 @@ struct NttSrc {
   }
 };
 
-__device__ __forceinline__ int pad_idx(int j) { return j + (j >> 4); }
+__host__ __device__ constexpr int pad_idx(int j) { return j + (j >> 4); }
 
 // One pass of R_LOG radix-2 stages starting at global stage S0.  Work-item `tid` holds
 // kPerThread values in registers: GPT groups of GS = 2^R_LOG values each, group h being the
@@ -73,11 +73,16 @@ struct Pass {
   static_assert(S0 + R_LOG <= LOGN && GS <= kPerThread, "pass shape");
 
   // coefficient index of register slot i (= h GS + k)
-  __device__ static __forceinline__ int idx(int tid, int i) {
+  __host__ __device__ static constexpr int idx(int tid, int i) {
     const int h = i / GS, k = i % GS;
     const int g = tid + h * T;
     return (g / TL) * (TL << R_LOG) + (g % TL) + k * TL;
   }
+
+  // Padded LDS word of slot i relative to slot 0.  In every pass shape used here it does not
+  // depend on the work-item (asserted for all work-items at compile time below), so an exchange
+  // needs one address per work-item and the slots become immediate offsets.
+  static constexpr int lds_off(int i) { return pad_idx(idx(0, i)) - pad_idx(idx(0, 0)); }
 
   // FWD: Cooley-Tukey stages in increasing order; else Gentleman-Sande in decreasing order.
   template <bool FWD>
@@ -139,12 +144,25 @@ __device__ __forceinline__ void lds_barrier() {
 // the previous polynomial in the persistent kernel).
 template <class PA, class PB>
 __device__ __forceinline__ void relayout(double* lds, double (&x)[kPerThread], int tid) {
+  double* la = lds + pad_idx(PA::idx(tid, 0));
+  const double* lb = lds + pad_idx(PB::idx(tid, 0));
   lds_barrier();
 #pragma unroll
-  for (int i = 0; i < kPerThread; ++i) lds[pad_idx(PA::idx(tid, i))] = x[i];
+  for (int i = 0; i < kPerThread; ++i) la[PA::lds_off(i)] = x[i];
   lds_barrier();
 #pragma unroll
-  for (int i = 0; i < kPerThread; ++i) x[i] = lds[pad_idx(PB::idx(tid, i))];
+  for (int i = 0; i < kPerThread; ++i) x[i] = lb[PB::lds_off(i)];
+}
+
+// lds_off(i) is the same for every work-item of pass P
+template <class P>
+constexpr bool lds_affine() {
+  for (int i = 1; i < kPerThread; ++i) {
+    const int off = P::lds_off(i);
+    for (int tid = 1; tid < P::T; ++tid)
+      if (pad_idx(P::idx(tid, i)) - pad_idx(P::idx(tid, 0)) != off) return false;
+  }
+  return true;
 }
 
 // Pass schedule: three passes of four stages, then the remaining LOGN - 12 stages (forward
@@ -158,6 +176,10 @@ struct Sched {
   using P2 = Pass<LOGN, 8, 4>;
   using P3 = Pass<LOGN, 12, (REM > 0 ? REM : 1)>;
   using Tail = std::conditional_t<(REM > 0), P3, P2>;  // forward-last / inverse-first pass
+  static_assert(lds_affine<P0>(), "LDS offsets of the first pass depend on the work-item");
+  static_assert(lds_affine<P1>(), "LDS offsets of the second pass depend on the work-item");
+  static_assert(lds_affine<P2>(), "LDS offsets of the third pass depend on the work-item");
+  static_assert(lds_affine<Tail>(), "LDS offsets of the last pass depend on the work-item");
 };
 template <int LOGN, bool FWD>
 using FirstPass = std::conditional_t<FWD, typename Sched<LOGN>::P0, typename Sched<LOGN>::Tail>;
