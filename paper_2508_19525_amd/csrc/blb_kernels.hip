@@ -181,37 +181,52 @@ void launch_modup(blb_ctx* c, const uint64_t* dcoef, uint64_t* X, const KsLevelC
 }
 
 // Inner product with the switching key, with the automorphism applied to the extended
-// digits (hoisted order).  Thread per (o, e, k); writes U[o][2][e][k] (evaluation form).
-__global__ void k_ks_inner(const KsOut* outs, const uint64_t* X, const KsLevelConst* kc, uint64_t* U, int n, int log_n, int nl, int n_ext,
-                           int n_digits, int n_q) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+// digits (hoisted order).  Thread per (o, e, two adjacent k); writes U[o][2][e][k] (evaluation
+// form).  For one wave the permuted reads stay inside one aligned block of 64 words: sigma_g
+// keeps the low log2(N) - 6 bits of the exponent index, which bit reversal maps to the high
+// bits of k.
+__global__ void k_ks_inner(const KsOut* __restrict__ outs, const uint64_t* __restrict__ X, const KsLevelConst* __restrict__ kc,
+                           uint64_t* __restrict__ U, int n, int log_n, int nl, int n_ext, int n_digits, int n_q) {
+  const int k0 = (blockIdx.x * blockDim.x + threadIdx.x) * 2;
   const int e = blockIdx.y % n_ext;
   const int o = blockIdx.y / n_ext;
-  if (k >= n) return;
+  if (k0 >= n) return;
   const KsOut od = outs[o];
-  const uint32_t kk = od.gal ? gal_perm((uint32_t)k, od.gal, log_n) : (uint32_t)k;
+  uint32_t kk[2];
+#pragma unroll
+  for (int v = 0; v < 2; ++v) kk[v] = od.gal ? gal_perm((uint32_t)(k0 + v), od.gal, log_n) : (uint32_t)(k0 + v);
   const ModEntry mm = kc->ext[e];
   const int key_mod = e < nl ? e : n_q + (e - nl);
-  double acc0 = 0.0, acc1 = 0.0;
+  double acc0[2] = {0.0, 0.0}, acc1[2] = {0.0, 0.0};
   for (int j = 0; j < n_digits; ++j) {
-    double x;
-    if (e >= kc->dlo[j] && e < kc->dhi[j]) x = u2d(od.c1[(size_t)e * n + kk]);
-    else x = u2d(X[(((size_t)od.src * n_digits + j) * n_ext + e) * n + kk]);
-    const uint64_t* kb = od.key + (((size_t)j * 2 + 0) * kc->n_key_mod + key_mod) * n;
-    const uint64_t* ka = od.key + (((size_t)j * 2 + 1) * kc->n_key_mod + key_mod) * n;
-    acc0 += mulmod_s(x, u2d(kb[k]), mm.q, mm.qinv);
-    acc1 += mulmod_s(x, u2d(ka[k]), mm.q, mm.qinv);
+    const uint64_t* xs = (e >= kc->dlo[j] && e < kc->dhi[j]) ? od.c1 + (size_t)e * n : X + (((size_t)od.src * n_digits + j) * n_ext + e) * n;
+    const uint64_t* kb = od.key + (((size_t)j * 2 + 0) * kc->n_key_mod + key_mod) * n + k0;
+    const uint64_t* ka = od.key + (((size_t)j * 2 + 1) * kc->n_key_mod + key_mod) * n + k0;
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const double x = u2d(xs[kk[v]]);
+      acc0[v] += mulmod_s(x, u2d(kb[v]), mm.q, mm.qinv);
+      acc1[v] += mulmod_s(x, u2d(ka[v]), mm.q, mm.qinv);
+    }
     if ((j & 3) == 3) {  // keep |acc| < 5q < 2^53
-      acc0 = reduce_s(acc0, mm.q, mm.qinv);
-      acc1 = reduce_s(acc1, mm.q, mm.qinv);
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        acc0[v] = reduce_s(acc0[v], mm.q, mm.qinv);
+        acc1[v] = reduce_s(acc1[v], mm.q, mm.qinv);
+      }
     }
   }
-  U[(((size_t)o * 2 + 0) * n_ext + e) * n + k] = d2u(canon_full(acc0, mm.q, mm.qinv));
-  U[(((size_t)o * 2 + 1) * n_ext + e) * n + k] = d2u(canon_full(acc1, mm.q, mm.qinv));
+  uint64_t* u0 = U + (((size_t)o * 2 + 0) * n_ext + e) * n + k0;
+  uint64_t* u1 = U + (((size_t)o * 2 + 1) * n_ext + e) * n + k0;
+#pragma unroll
+  for (int v = 0; v < 2; ++v) {
+    u0[v] = d2u(canon_full(acc0[v], mm.q, mm.qinv));
+    u1[v] = d2u(canon_full(acc1[v], mm.q, mm.qinv));
+  }
 }
 void launch_ks_inner(blb_ctx* c, const KsOut* outs_dev, int n_out, const uint64_t* X, const KsLevelConst* kc_dev, uint64_t* U, int nl,
                      int n_ext, int n_digits) {
-  dim3 grid((c->n + 255) / 256, n_out * n_ext);
+  dim3 grid((c->n / 2 + 255) / 256, n_out * n_ext);
   k_ks_inner<<<grid, 256, 0, c->stream>>>(outs_dev, X, kc_dev, U, c->n, c->log_n, nl, n_ext, n_digits, c->n_q);
 }
 
