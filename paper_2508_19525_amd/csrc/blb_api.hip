@@ -99,19 +99,76 @@ void dfree(blb_ctx* c, void* p, size_t bytes) {
   c->dev_bytes -= bytes;
 }
 
-// stream-ordered temporaries (pooled by the HIP runtime)
+// ------------------------------------------------------------------------------------------
+// temporaries: per-stream stacks (stream-ordered pool for what does not fit)
+// ------------------------------------------------------------------------------------------
+Workspace* stack_for(blb_ctx* c) {
+  for (Workspace* w : c->stacks)
+    if (w->stream == c->stream) return w;
+  Workspace* w = new (std::nothrow) Workspace();
+  if (!w) return nullptr;
+  w->stream = c->stream;
+  c->stacks.push_back(w);
+  return w;
+}
+void stack_release(blb_ctx* c, Workspace* w) {
+  if (w->base) {
+    (void)hipFree(w->base);
+    c->dev_bytes -= w->cap;
+  }
+  w->base = nullptr;
+  w->cap = 0;
+}
+// grow an empty stack to the deepest one seen (its earlier bytes may still be read by work
+// enqueued on its stream, so that stream drains first)
+void stack_fit(blb_ctx* c, Workspace* w) {
+  if (w->need <= w->cap || w->frozen) return;
+  const size_t quantum = size_t(64) << 20;
+  const size_t cap = (std::max(w->need + w->need / 4, 2 * w->cap) + quantum - 1) / quantum * quantum;
+  (void)hipStreamSynchronize(w->stream);
+  stack_release(c, w);
+  bool ok = !c->budget || c->dev_bytes + cap <= c->budget;
+  if (ok && hipMalloc((void**)&w->base, cap) != hipSuccess) {
+    // memory the stream-ordered pool keeps cached may be what is missing: release it, retry
+    (void)hipGetLastError();
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, c->device) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+    ok = hipMalloc((void**)&w->base, cap) == hipSuccess;
+  }
+  if (!ok) {
+    (void)hipGetLastError();
+    w->base = nullptr;
+    w->frozen = true;  // temporaries that do not fit keep coming from the pool
+    return;
+  }
+  c->dev_bytes += cap;
+  w->cap = cap;
+}
+
+// Temporaries of one scope.  Eager calls carve them from the current stream's stack (released
+// when the scope ends); a graph being recorded carves them from the executor's arena.
 struct Tmp {
   blb_ctx* c;
+  Workspace* w = nullptr;
+  size_t off0 = 0, virt0 = 0;
   std::vector<void*> ptrs;
   bool failed = false;
-  explicit Tmp(blb_ctx* cc) : c(cc) {}
+  explicit Tmp(blb_ctx* cc) : c(cc) {
+    if (c->rec) return;
+    w = stack_for(c);
+    if (!w) return;
+    if (w->off == 0) stack_fit(c, w);
+    off0 = w->off;
+    virt0 = w->virt;
+  }
   template <class T>
   T* get(size_t count) {
     void* p = nullptr;
     if (count == 0) count = 1;
+    const size_t bytes = count * sizeof(T);
     if (c->rec) {  // recording a graph: carve from the executor's arena, never freed
       ExecRec* r = c->rec;
-      const size_t off = align_up(r->arena_off, 256), bytes = count * sizeof(T);
+      const size_t off = align_up(r->arena_off, 256);
       if (off + bytes > r->arena_cap) {
         r->overflow = true;
         failed = true;
@@ -120,13 +177,16 @@ struct Tmp {
       r->arena_off = off + bytes;
       return (T*)(r->arena + off);
     }
-    if (Workspace* w = c->ws) {
+    if (w) {
+      w->virt = align_up(w->virt, 256) + bytes;
+      w->need = std::max(w->need, w->virt);
       const size_t off = align_up(w->off, 256);
-      w->off = off + count * sizeof(T);
-      w->need = std::max(w->need, w->off);
-      if (w->off <= w->cap) return (T*)(w->base + off);
+      if (off + bytes <= w->cap) {
+        w->off = off + bytes;
+        return (T*)(w->base + off);
+      }
     }
-    if (hipMallocAsync(&p, count * sizeof(T), c->stream) != hipSuccess) {
+    if (hipMallocAsync(&p, bytes, c->stream) != hipSuccess) {
       (void)hipGetLastError();
       failed = true;
       return nullptr;
@@ -135,6 +195,10 @@ struct Tmp {
     return (T*)p;
   }
   ~Tmp() {
+    if (w) {
+      w->off = off0;
+      w->virt = virt0;
+    }
     for (void* p : ptrs) (void)hipFreeAsync(p, c->stream);
   }
 };
@@ -541,6 +605,17 @@ int encode_dense_dev(blb_ctx* c, const double* d_vals, int n_vals, int count, do
 
 }  // namespace
 
+// a stream is about to be destroyed after a synchronisation: drop its stack of temporaries
+void stack_forget_stream(blb_ctx* c, hipStream_t s) {
+  for (size_t i = 0; i < c->stacks.size(); ++i)
+    if (c->stacks[i]->stream == s) {
+      stack_release(c, c->stacks[i]);
+      delete c->stacks[i];
+      c->stacks.erase(c->stacks.begin() + i);
+      return;
+    }
+}
+
 // a stream is about to be destroyed after a synchronisation: drop its upload ring
 void uploader_forget_stream(blb_ctx* c, hipStream_t s) {
   for (size_t i = 0; i < c->ups.size(); ++i)
@@ -671,6 +746,12 @@ int blb_ctx_create(const blb_params* prm, blb_ctx** out) {
 void blb_ctx_destroy(blb_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  for (Workspace* w : c->stacks) {
+    (void)hipStreamSynchronize(w->stream);
+    stack_release(c, w);
+    delete w;
+  }
+  c->stacks.clear();
   {
     // the context made the device's stream-ordered pool keep what it frees; hand that back
     hipMemPool_t pool;
@@ -704,6 +785,11 @@ uint64_t blb_ctx_device_bytes(const blb_ctx* c) { return c ? c->dev_bytes : 0; }
 int blb_ctx_trim(blb_ctx* c) {
   if (!c) return BLB_EINVAL;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return BLB_EDEVICE;
+  for (Workspace* w : c->stacks)
+    if (w->off == 0 && hipStreamSynchronize(w->stream) == hipSuccess) {  // idle: give the bytes back
+      stack_release(c, w);
+      w->need = 0;
+    }
   hipMemPool_t pool;
   if (hipDeviceGetDefaultMemPool(&pool, c->device) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
   return BLB_OK;

@@ -159,20 +159,26 @@ struct ExecRec {
   bool overflow = false;
 };
 
-// Stream-private workspace: while set on a context, temporaries of a call are carved from it
-// one after another (none is released before the call returns), so calls enqueued on one stream
-// reuse the same bytes in stream order and never reach the allocator.  A call whose temporaries
-// do not fit takes the rest from the stream-ordered pool; `need` records the largest total
-// any call asked for, so the owner can grow the workspace between calls.
+// Per-stream stack of temporaries.  Temporaries are scoped (released in reverse order of
+// creation), so each stream's are carved from one device buffer like a stack; bytes released
+// by a call are reused by the next call on the same stream in stream order, and eager calls
+// never reach the allocator in steady state.  A temporary that does not fit comes from the
+// stream-ordered pool; `need` records the deepest stack seen (counting those), and the buffer
+// grows to it the next time the stack is empty.
 struct Workspace {
+  hipStream_t stream = nullptr;
   char* base = nullptr;
-  size_t cap = 0, off = 0, need = 0;
+  size_t cap = 0;
+  size_t off = 0;   // top of the stack
+  size_t virt = 0;  // top counting the temporaries that did not fit
+  size_t need = 0;  // deepest virt seen
+  bool frozen = false;  // growing failed: stay at the current size
 };
 
 struct blb_ctx {
   int log_n, n, n_q, n_sp, dnum, alpha;
   ExecRec* rec = nullptr;
-  Workspace* ws = nullptr;
+  std::vector<Workspace*> stacks;  // stacks of temporaries by stream
   bool timing = false;
   std::vector<TimedSpan> spans;
   std::vector<hipEvent_t> ev_pool;
@@ -256,6 +262,7 @@ void launch_sample_uniform(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, u
 void launch_sample_int(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag, bool gaussian);
 int cp_check_keys(const blb_ctx* c, const blb_keys* K, int L, int d_in, int d_out);
 void uploader_forget_stream(blb_ctx* c, hipStream_t s);
+void stack_forget_stream(blb_ctx* c, hipStream_t s);
 size_t cp_plan_bytes(const blb_ctx* c, int L, int d_in, int d_out, int level);
 int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, uint64_t* mem, blb_plan** out, int* flag_host,
                    const double* W_dev);

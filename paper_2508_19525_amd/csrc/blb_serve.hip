@@ -142,10 +142,6 @@ struct blb_server {
     int slot;
   };
   std::deque<Gen> gens;  // in stream order
-  // one workspace per batch stream for the temporaries of the batches launched on it, grown
-  // between batches to the largest batch seen (a batch that outgrows it borrows from the pool)
-  std::vector<Workspace> ws;
-  bool ws_frozen = false;  // growing failed: keep the current size
   std::map<std::pair<int, int>, int> bad_plans;  // keys whose plan cannot be built -> error
   std::mutex mu;
   std::condition_variable cv;
@@ -309,42 +305,6 @@ void finish_batches(blb_server* S, bool block) {
   }
 }
 
-void ws_release(blb_ctx* c, Workspace& w) {
-  if (w.base) {
-    (void)hipFree(w.base);
-    c->dev_bytes -= w.cap;
-  }
-  w.base = nullptr;
-  w.cap = 0;
-}
-
-// grow the workspace of batch stream k to what its largest batch needed, once that stream
-// has drained (its current bytes may still be read by the batch just launched)
-void ws_fit(blb_server* S, int k) {
-  Workspace& w = S->ws[k];
-  if (w.need <= w.cap || S->ws_frozen) return;
-  blb_ctx* c = S->c;
-  const size_t quantum = size_t(256) << 20;
-  const size_t cap = (std::max(w.need + w.need / 4, 2 * w.cap) + quantum - 1) / quantum * quantum;
-  (void)hipStreamSynchronize(S->streams[k]);
-  ws_release(c, w);
-  bool ok = !c->budget || c->dev_bytes + cap <= c->budget;
-  if (ok && hipMalloc((void**)&w.base, cap) != hipSuccess) {
-    // memory the stream-ordered pool keeps cached may be what is missing: release it, retry
-    (void)hipGetLastError();
-    (void)blb_ctx_trim(c);
-    ok = hipMalloc((void**)&w.base, cap) == hipSuccess;
-  }
-  if (!ok) {
-    (void)hipGetLastError();
-    w.base = nullptr;
-    S->ws_frozen = true;  // batches take their temporaries from the pool
-    return;
-  }
-  c->dev_bytes += cap;
-  w.cap = cap;
-}
-
 void worker_loop(blb_server* S) {
   blb_ctx* c = S->c;
   (void)hipSetDevice(c->device);
@@ -435,23 +395,16 @@ void worker_loop(blb_server* S) {
       inst.push_back(I);
       r->state = 1;
     }
-    Workspace& w = S->ws[next_stream];
-    c->ws = &w;
-    w.off = 0;
     int rc = blb_batch_matmul_cp(c, inst.data(), (int)inst.size());
     for (size_t k = 0; k < batch.size() && rc == BLB_OK; ++k)
-      if (batch[k]->share) {
-        w.off = 0;  // the batch's temporaries are dead in stream order
+      if (batch[k]->share)
         rc = blb_mask_to_share(c, batch[k]->Y, batch[k]->n_out, batch[k]->mask_seed, batch[k]->target_level, batch[k]->share);
-      }
-    c->ws = nullptr;
     Batch b;
     b.reqs = batch;
     b.stream = next_stream;
     (void)hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
     (void)hipEventRecord(b.done, c->stream);
     c->stream = saved;
-    ws_fit(S, next_stream);
     next_stream = (next_stream + 1) % (int)S->streams.size();
     if (rc != BLB_OK) {
       std::lock_guard<std::mutex> lk(S->mu);
@@ -532,7 +485,6 @@ int blb_server_create(blb_ctx* c, const blb_server_config* cfg, blb_server** out
     }
     S->streams.push_back(s);
   }
-  S->ws.resize(S->streams.size());
   if (hipStreamSynchronize(c->stream) != hipSuccess) return BLB_EDEVICE;
   S->worker = std::thread(worker_loop, S);
   *out = S;
@@ -651,11 +603,12 @@ void blb_server_destroy(blb_server* S) {
   for (hipStream_t s : S->streams) {
     (void)hipStreamSynchronize(s);
     uploader_forget_stream(S->c, s);
+    stack_forget_stream(S->c, s);
     (void)hipStreamDestroy(s);
   }
-  for (Workspace& w : S->ws) ws_release(S->c, w);
   (void)hipStreamSynchronize(S->gen_stream);
   uploader_forget_stream(S->c, S->gen_stream);
+  stack_forget_stream(S->c, S->gen_stream);
   (void)hipStreamDestroy(S->gen_stream);
   (void)hipHostFree(S->gen_flag);
   for (auto& kv : S->plans)
