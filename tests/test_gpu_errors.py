@@ -104,3 +104,27 @@ def test_hbm_budget_exhausted():
         assert B.blb_ctx_device_bytes(ctx) == used
     finally:
         B.blb_ctx_destroy(ctx)
+
+
+def test_temporaries_reused_and_trimmed(env):
+    """Eager calls take their temporaries from the context's per-stream stack: once it has
+    grown, repeating a call allocates nothing more, and trimming hands the stack back (the
+    next call grows it again and still gives the same words)."""
+    B, ctx, keys = env
+    ct, t = _fresh_ct(B, ctx, keys)
+    outs = []
+    used = []
+    for _ in range(4):
+        out, to = B.new_ct(4096, 1)
+        B.blb_rotate(ctx, keys, ct, 1, out)
+        torch.cuda.synchronize()
+        outs.append(B.blb_export(ctx, out, 4096))
+        used.append(B.blb_ctx_device_bytes(ctx))
+    assert used[2] == used[3], f"device bytes still changing: {used}"
+    B.blb_ctx_trim(ctx)
+    assert B.blb_ctx_device_bytes(ctx) < used[3]  # the idle stack was released
+    out, to = B.new_ct(4096, 1)
+    B.blb_rotate(ctx, keys, ct, 1, out)
+    torch.cuda.synchronize()
+    for o in outs + [B.blb_export(ctx, out, 4096)]:
+        assert np.array_equal(o, outs[0])
