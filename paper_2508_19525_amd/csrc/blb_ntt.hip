@@ -71,6 +71,9 @@ struct Pass {
   static constexpr int GPT = kPerThread / GS;
   static constexpr int TL = N >> (S0 + R_LOG);
   static_assert(S0 + R_LOG <= LOGN && GS <= kPerThread, "pass shape");
+  // twiddles differ across the lanes of a wave (vector loads) unless the pass spans whole
+  // columns (TL >= T) or a butterfly tree covers at least 64 work-items (TL >= 64)
+  static constexpr bool LANE_TW = !(TL >= T || TL >= 64);
 
   // coefficient index of register slot i (= h GS + k)
   __host__ __device__ static constexpr int idx(int tid, int i) {
@@ -180,40 +183,71 @@ struct Sched {
   static_assert(lds_affine<P1>(), "LDS offsets of the second pass depend on the work-item");
   static_assert(lds_affine<P2>(), "LDS offsets of the third pass depend on the work-item");
   static_assert(lds_affine<Tail>(), "LDS offsets of the last pass depend on the work-item");
+  static constexpr int NP = REM > 0 ? 4 : 3;  // passes
+  // passes (in execution order) that run before the persistent kernel's prefetch is issued:
+  // the leading run of passes with per-lane twiddles
+  template <bool FWD>
+  static constexpr int issue_after() {
+    const bool lane[4] = {P0::LANE_TW, P1::LANE_TW, P2::LANE_TW, REM > 0 ? Tail::LANE_TW : false};
+    int k = 0;
+    while (k < NP && lane[FWD ? k : NP - 1 - k]) ++k;
+    return k;
+  }
 };
 template <int LOGN, bool FWD>
 using FirstPass = std::conditional_t<FWD, typename Sched<LOGN>::P0, typename Sched<LOGN>::Tail>;
 template <int LOGN, bool FWD>
 using LastPass = std::conditional_t<FWD, typename Sched<LOGN>::Tail, typename Sched<LOGN>::P0>;
 
-// x holds the first pass's operands on entry and the last pass's results on exit.
-template <int LOGN, bool FWD>
-__device__ __forceinline__ void ntt_core(double* lds, double (&x)[kPerThread], const double* tw, double q, double qi, int tid) {
+struct NoIssue {
+  __device__ void operator()() const {}
+};
+
+// x holds the first pass's operands on entry and the last pass's results on exit.  issue()
+// enqueues the persistent kernel's prefetch of the next polynomial.  Vector loads complete in
+// issue order, so a per-lane twiddle load issued after the prefetch is waited for only once
+// the whole prefetch has arrived: issue() runs after the leading passes that load per-lane
+// twiddles (before the first pass when it has none).
+template <int LOGN, bool FWD, class Issue = NoIssue>
+__device__ __forceinline__ void ntt_core(double* lds, double (&x)[kPerThread], const double* tw, double q, double qi, int tid,
+                                         const Issue& issue = Issue()) {
   using S = Sched<LOGN>;
   using P0 = typename S::P0;
   using P1 = typename S::P1;
   using P2 = typename S::P2;
   using P3 = typename S::P3;
+  constexpr int at = S::template issue_after<FWD>();  // passes run before issue()
   if constexpr (FWD) {
+    if constexpr (at == 0) issue();
     P0::template run<true>(x, tw, q, qi, tid);
+    if constexpr (at == 1) issue();
     relayout<P0, P1>(lds, x, tid);
     P1::template run<true>(x, tw, q, qi, tid);
+    if constexpr (at == 2) issue();
     relayout<P1, P2>(lds, x, tid);
     P2::template run<true>(x, tw, q, qi, tid);
+    if constexpr (at == 3) issue();
     if constexpr (S::REM > 0) {
       relayout<P2, P3>(lds, x, tid);
       P3::template run<true>(x, tw, q, qi, tid);
+      if constexpr (at == 4) issue();
     }
   } else {
+    // pass k of the inverse runs Pass index NP - 1 - k
+    if constexpr (at == 0) issue();
     if constexpr (S::REM > 0) {
       P3::template run<false>(x, tw, q, qi, tid);
+      if constexpr (at == 1) issue();
       relayout<P3, P2>(lds, x, tid);
     }
     P2::template run<false>(x, tw, q, qi, tid);
+    if constexpr (at == S::NP - 2) issue();
     relayout<P2, P1>(lds, x, tid);
     P1::template run<false>(x, tw, q, qi, tid);
+    if constexpr (at == S::NP - 1) issue();
     relayout<P1, P0>(lds, x, tid);
     P0::template run<false>(x, tw, q, qi, tid);
+    if constexpr (at == S::NP) issue();
   }
 }
 
@@ -303,15 +337,14 @@ __global__ __launch_bounds__((1 << LOGN) / kPerThread) __attribute__((amdgpu_wav
 #pragma unroll
     for (int i = PF; i < kPerThread; ++i) x[i] = ld(d, First::idx(tid, i), q, qi);
     const int pn = p + gridDim.x;
-    {
+    auto prefetch = [&] {
       // unconditional (the last iteration re-reads its own polynomial), so the loads land in nx
       // directly and are only waited for when the next iteration starts
       const PolyDesc dn = descs.get(pn < count ? pn : p);
-      const double qn = mt.m[dn.mod].q, qin = mt.m[dn.mod].qinv;
 #pragma unroll
       for (int i = 0; i < PF; ++i) nx[i] = ld.raw(dn, First::idx(tid, i));
-    }
-    ntt_core<LOGN, FWD>(lds, x, tw_all + (size_t)d.mod * N, q, qi, tid);
+    };
+    ntt_core<LOGN, FWD>(lds, x, tw_all + (size_t)d.mod * N, q, qi, tid, prefetch);
     ntt_store<LOGN, FWD>(x, d, st, q, qi, mt.m[d.mod].ninv, tid, lds);
     p = pn;
     if (p >= count) break;
