@@ -92,6 +92,10 @@ def lib():
             "orc_rerandomize": (C.c_int, [vp, _u64p, C.c_int, C.c_uint64, C.c_uint32, C.c_int, _u64p]),
             "orc_matmul_cc": (C.c_int, [vp, _u64p, _u64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, _u64p]),
             "orc_cc_galois": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, _u64p]),
+            "orc_cc_sv_geometry": (None, [vp, C.c_int, C.c_int, C.c_int, _i32p]),
+            "orc_matmul_cc_sv": (C.c_int, [vp, _u64p, _u64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p,
+                                           _u64p]),
+            "orc_matmul_cp_diag": (C.c_int, [vp, _u64p, C.c_int, _f64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, _u64p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -257,10 +261,17 @@ class Context:
         k = lib().orc_cc_galois(self._p, H_g, L, d, out)
         return out[:k].copy()
 
+    def cc_sv_geometry(self, H_g, L, d_v) -> dict:
+        """Softmax x V_h for one head group: L', c, operand cts (reduction d = L), dense outputs
+        (0: unsupported), d_v' = 2^ceil(log2 d_v)"""
+        g = np.zeros(5, np.int32)
+        lib().orc_cc_sv_geometry(self._p, H_g, L, d_v, g)
+        return dict(zip(["Lp", "c", "n_ct", "n_out", "dvp"], [int(v) for v in g]))
+
     def pack_mhp(self, mats, H_g, L, d, a, operand):
         """Multi-head packing of ciphertext a for one head group: operand 'A' puts A_h{i, a c + kappa}
         at slot i + L'(h + H_g kappa); operand 'Bp' puts B_h{a c + kappa, (i + kappa) mod L'} there
-        (B_h = mats[h], d x L, rows pre-rotated by kappa)."""
+        (B_h = mats[h], d rows and at most L' columns, rows pre-rotated by kappa)."""
         g = self.cc_geometry(H_g, L, d)
         lp, cc = g["Lp"], g["c"]
         v = np.zeros(self.slots)
@@ -275,7 +286,7 @@ class Context:
                         v[base + i] = mats[h][i, k] if i < L else 0.0
                     else:
                         j = (i + kap) % lp
-                        v[base + i] = mats[h][k, j] if j < L else 0.0
+                        v[base + i] = mats[h][k, j] if j < mats[h].shape[1] else 0.0
         return v
 
     def mask_to_share(self, ct, level: int, target_level: int, seed: int, ct_id: int):
@@ -359,6 +370,45 @@ class Keys:
         if rc != 0:
             raise ValueError(f"matmul_cc failed ({rc})")
         return O
+
+    def matmul_cc_sv(self, A_cts, B_cts, level: int, H_g: int, L: int, d_v: int, outputs=None, b_prerotated=True) -> np.ndarray:
+        """Softmax x V_h for one head group (A = attention weights, L x L; B = V_h, L x d_v, zero-padded
+        to L' columns); returns the dense diagonal-packed outputs [d_v'/c][2][level-2 or level-3][N]"""
+        c = self.ctx
+        g = c.cc_sv_geometry(H_g, L, d_v)
+        if g["n_out"] < 1:
+            raise ValueError("unsupported Softmax x V geometry")
+        O = np.zeros((g["n_out"], 2, level - (2 if b_prerotated else 3), c.n), np.uint64)
+        mask = None
+        if outputs is not None:
+            m = np.zeros(g["n_out"], np.uint8)
+            m[list(outputs)] = 1
+            mask = m.ctypes.data_as(C.c_void_p)
+        rc = lib().orc_matmul_cc_sv(self._p, _c(A_cts, np.uint64), _c(B_cts, np.uint64), g["n_ct"], level, H_g, L, d_v,
+                                    1 if b_prerotated else 0, mask, O)
+        if rc != 0:
+            raise ValueError(f"matmul_cc_sv failed ({rc})")
+        return O
+
+    def matmul_cp_diag(self, X_cts, level: int, W, L: int, n_heads: int, d_v: int, outputs=None) -> np.ndarray:
+        """Concat(Att_h) W from the dense diagonal-packed Att_h (head groups concatenated); W is
+        (n_heads d_v) x d_out; returns the spatial-first outputs [n_out][2][level][N]"""
+        c = self.ctx
+        W = _c(W, np.float64)
+        d_out = W.shape[1]
+        assert W.shape[0] == n_heads * d_v
+        dvp = 1 << int(np.ceil(np.log2(d_v)))
+        g = c.cp_geometry(L, n_heads * dvp, d_out)
+        Y = np.zeros((g["n_out"], 2, level, c.n), np.uint64)
+        mask = None
+        if outputs is not None:
+            m = np.zeros(g["n_out"], np.uint8)
+            m[list(outputs)] = 1
+            mask = m.ctypes.data_as(C.c_void_p)
+        rc = lib().orc_matmul_cp_diag(self._p, _c(X_cts, np.uint64), level, W, L, n_heads, d_v, d_out, mask, Y)
+        if rc != 0:
+            raise ValueError(f"matmul_cp_diag failed ({rc})")
+        return Y
 
     def matmul_cp(self, X_cts, level: int, W, L: int, outputs=None) -> np.ndarray:
         c = self.ctx

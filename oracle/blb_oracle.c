@@ -19,6 +19,9 @@
  *   - matmul_cp with BSGS (Section "Efficient Protocol for Fused MatMuls" and Appendix
  *     "BSGS Optimization"), spatial-first packing ("Consistent Packing for Single Operator").
  *   - matmul_cc steps 1-3 with multi-head packing ("Building Blocks", Multi-Head Optimization).
+ *   - Softmax x V_h with zero padding and the dense diagonal packing, and the matmul_cp variant
+ *     with diagonal-packed input for Concat(Att_h) W_O ("Efficient Fused Computations in
+ *     Multi-Head Attention"; Appendix "Diagonal Ciphertext-Plaintext MatMul").
  *   - CKKS-to-MPC mask-and-share, step 1 of Algorithm ckks2mpc and F_C2M.
  * Where the paper is silent (primes, randomness, key switching variant, schedules) the
  * readings are documented with the function that implements them.
@@ -851,6 +854,99 @@ int orc_cp_galois(const orc_ctx* c, int L, int d_in, int d_out, uint64_t* out) {
 }
 
 /* ------------------------------------------------------------------------------------ */
+/* matmul_cp with diagonal-packed input (Appendix "Diagonal Ciphertext-Plaintext MatMul")  */
+/* ------------------------------------------------------------------------------------ */
+/* E = Concat_h(Att_h) W for Att_h (L x d_v) in the dense diagonal packing that Softmax x V_h
+ * produces (heads split into power-of-two groups, largest first, group outputs concatenated):
+ * input ciphertext a, the o-th output of a group of H_g heads starting at head h0 with
+ * c_g = S / (L' H_g), holds at slot i + L' u the value Att_h{i, (i + tau) mod d_v'} with
+ * h = h0 + (u mod H_g) and tau = o c_g + floor(u / H_g).  Row r of E's column k is then
+ * sum over (h, tau) of Att_h{i, (i + tau) mod d_v'} W{h d_v + (i + tau) mod d_v', k}: the input
+ * blocks meet the weights of a "duplicated" spatial-first plaintext (figure diag (c)).  The
+ * schedule is the one of orc_matmul_cp with c_eff = c = S / L' and the diagonals
+ *   d_{a,b,t}[u L' + i] = W{h d_v + j, b c + (u mod c_out)},  (h, tau) = block (u + t) mod c of
+ *   input a, j = (i + tau) mod d_v', and 0 when i >= L, j >= d_v or the column is >= d_out;
+ * the output Y_b is spatial-first (column b c + u at slots u L' + i).  Geometry and Galois
+ * elements are those of orc_cp_geometry / orc_cp_galois at d_in = n_heads d_v'. */
+static void diag_block(const orc_ctx* c, int lp, int n_heads, int dvp, int a, int u, int* h, int* tau) {
+  int s = c->n / 2, rem = n_heads, h0 = 0, idx = 0;
+  while (rem > 0) {
+    int hg = 1;
+    while (hg * 2 <= rem) hg *= 2;
+    int cg = s / (lp * hg), nd = dvp / cg;
+    if (a < idx + nd) {
+      int o = a - idx;
+      *h = h0 + u % hg;
+      *tau = o * cg + u / hg;
+      return;
+    }
+    idx += nd; h0 += hg; rem -= hg;
+  }
+  *h = -1; *tau = 0;
+}
+
+int orc_matmul_cp_diag(const orc_keys* K, const uint64_t* X, int level, const double* W, int L, int n_heads, int d_v, int d_out,
+                       const uint8_t* out_mask, uint64_t* Y) {
+  const orc_ctx* c = K->c;
+  int n = c->n, s = n / 2, nl = level + 1;
+  int dvp = 1 << ceil_log2(d_v);
+  int32_t g[8]; orc_cp_geometry(c, L, n_heads * dvp, d_out, g);
+  int lp = g[0], cc = g[1], c_eff = g[2], c_out = g[3], n_in = g[4], n_out = g[5], B = g[6], G = g[7];
+  if (c_eff != cc || dvp > lp) return -3;
+  for (int rem = n_heads; rem > 0;) {
+    int hg = 1;
+    while (hg * 2 <= rem) hg *= 2;
+    if (s / (lp * hg) > dvp) return -3;
+    rem -= hg;
+  }
+  size_t ctw = (size_t)2 * nl * n;
+  double delta_w = (double)c->mod[level] / NOISE_BOOST;
+  uint64_t* xs = (uint64_t*)malloc(8 * ctw * (size_t)n_in);
+  for (int a = 0; a < n_in; ++a) scale_ct(c, X + ctw * a, (uint64_t)NOISE_BOOST, nl, xs + ctw * a);
+  uint64_t* rx = (uint64_t*)malloc(8 * ctw * (size_t)n_in * B);
+  for (int a = 0; a < n_in; ++a)
+    for (int i = 0; i < B; ++i)
+      if (orc_rotate(K, xs + ctw * a, level, (int64_t)i * lp, rx + ctw * ((size_t)a * B + i)) != 0) { free(rx); free(xs); return -1; }
+  free(xs);
+  double* vec = (double*)malloc(8 * s);
+  double* vrot = (double*)malloc(8 * s);
+  uint64_t* pt = (uint64_t*)malloc(8 * (size_t)nl * n);
+  uint64_t* inner = (uint64_t*)malloc(8 * ctw);
+  uint64_t* rot = (uint64_t*)malloc(8 * ctw);
+  uint64_t* acc = (uint64_t*)malloc(8 * ctw);
+  int rc = 0;
+  for (int b = 0; b < n_out && rc == 0; ++b) {
+    if (out_mask && !out_mask[b]) continue;
+    memset(acc, 0, 8 * ctw);
+    for (int j = 0; j < G && rc == 0; ++j) {
+      memset(inner, 0, 8 * ctw);
+      for (int a = 0; a < n_in; ++a)
+        for (int i = 0; i < B; ++i) {
+          int t = j * B + i;
+          for (int slot = 0; slot < s; ++slot) {
+            int u = slot / lp, row_i = slot % lp, h, tau;
+            diag_block(c, lp, n_heads, dvp, a, (u + t) % c_eff, &h, &tau);
+            int jj = (row_i + tau) % dvp, col = b * cc + u % c_out;
+            vec[slot] = (row_i < L && jj < d_v && col < d_out) ? W[(size_t)(h * d_v + jj) * d_out + col] : 0.0;
+          }
+          int r = j * B * lp;
+          for (int slot = 0; slot < s; ++slot) vrot[slot] = vec[((slot - r) % s + s) % s];
+          orc_encode_rns(c, vrot, s, delta_w, level, pt);
+          mac_pt(c, inner, pt, rx + ctw * ((size_t)a * B + i), nl);
+        }
+      if (j == 0) add_ct(c, acc, inner, nl, 2);
+      else {
+        if (orc_rotate(K, inner, level, (int64_t)j * B * lp, rot) != 0) { rc = -1; break; }
+        add_ct(c, acc, rot, nl, 2);
+      }
+    }
+    if (rc == 0) orc_rescale(c, acc, level, 2, Y + (size_t)b * 2 * level * n);
+  }
+  free(rx); free(vec); free(vrot); free(pt); free(inner); free(rot); free(acc);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------------------ */
 /* CKKS-to-MPC mask-and-share (Algorithm ckks2mpc step 1; F_C2M item 1)                   */
 /* ------------------------------------------------------------------------------------ */
 /* r ~ U(R_{Q_l}) in the coefficient domain, one independent uniform residue per limb
@@ -988,15 +1084,19 @@ static void tensor_acc(const orc_ctx* c, uint64_t* acc3, const uint64_t* a, cons
  *          O_g += V_t (.) M^{>=tau};  O_{(g+1) mod (L'/c)} += V_t (.) M^{<tau}  (masks at q_{level-2} / 2^10);
  *          O_g = Rescale(O_g).
  * Output: L'/c cts at level-3, [g][2][level-2][N].  out_mask (NULL = all) selects the outputs;
- * only the t that feed them are computed. */
+ * only the t that feed them are computed.
+ * n_dense < L'/c (Softmax x V_h with zero-padded columns): output g' < n_dense gathers the
+ * accumulators O_g of every g with g mod n_dense = g' (the sum of those ciphertexts, taken before
+ * their common rescale), so n_dense outputs come out. */
 static int cc_steps23(const orc_keys* K, const uint64_t* A, const uint64_t* Bp, int n_ct, int level, int H_g, int L, int d,
-                      const uint8_t* out_mask, uint64_t* O) {
+                      int n_dense, const uint8_t* out_mask, uint64_t* O) {
   const orc_ctx* c = K->c;
   int n = c->n, s = n / 2;
   if (level < 3) return -2;
   int32_t geo[4]; orc_cc_geometry(c, H_g, L, d, geo);
   int lp = geo[0], cc = geo[1], n_out = geo[3];
   if (n_ct != geo[2] || cc < 1 || cc > lp || lp * H_g * cc != s) return -3;
+  if (n_dense < 1 || n_out % n_dense) return -3;
   int nl = level + 1, l2 = level - 1, l1 = level - 2;
   size_t w3 = (size_t)2 * nl * n, w2 = (size_t)2 * (l2 + 1) * n, w1 = (size_t)2 * (l1 + 1) * n;
   double dm2 = (double)c->mod[level] * 1024.0, dm3 = (double)c->mod[l1] / NOISE_BOOST;
@@ -1011,10 +1111,10 @@ static int cc_steps23(const orc_keys* K, const uint64_t* A, const uint64_t* Bp, 
   uint64_t* T = (uint64_t*)malloc(8 * w2);
   uint64_t* Tr = (uint64_t*)malloc(8 * w1);
   uint64_t* V = (uint64_t*)malloc(8 * w1);
-  uint64_t* acc = (uint64_t*)calloc((size_t)n_out * w1, 8);
+  uint64_t* acc = (uint64_t*)calloc((size_t)n_dense * w1, 8);
   int rc = 0;
   for (int t = 0; t < lp && rc == 0; ++t) {
-    int g = t / cc, tau = t % cc, g2 = (g + 1) % n_out;
+    int g = (t / cc) % n_dense, tau = t % cc, g2 = ((t / cc + 1) % n_out) % n_dense;
     int need = !out_mask || out_mask[g] || (tau > 0 && out_mask[g2]);
     if (!need) continue;
     memset(T3, 0, 8 * (size_t)3 * (l2 + 1) * n);
@@ -1045,7 +1145,7 @@ static int cc_steps23(const orc_keys* K, const uint64_t* A, const uint64_t* Bp, 
     if (tau > 0 && (!out_mask || out_mask[g2])) { mask_blk_lt(s, blk, tau, v); mac_vec(c, acc + (size_t)g2 * w1, v, dm3, V, l1); }
   }
   if (rc == 0)
-    for (int g = 0; g < n_out; ++g)
+    for (int g = 0; g < n_dense; ++g)
       if (!out_mask || out_mask[g]) orc_rescale(c, acc + (size_t)g * w1, l1, 2, O + (size_t)g * 2 * l1 * n);
   free(v); free(rot); free(racc); free(R); free(Ad); free(T3); free(T); free(Tr); free(V); free(acc); free(bs);
   return rc;
@@ -1104,9 +1204,9 @@ static int cc_step1(const orc_keys* K, const uint64_t* A, const uint64_t* B, int
 /* One head group of matmul_cc.  b_prerotated != 0: B_a arrive pre-rotated by the client
  * (step 1 applied to the plaintext), inputs at `level` >= 3, output at level-3; else step 1
  * runs homomorphically first, inputs at `level` >= 4, output at level-4. */
-int orc_matmul_cc(const orc_keys* K, const uint64_t* A, const uint64_t* B, int n_ct, int level, int H_g, int L, int d, int b_prerotated,
-                  const uint8_t* out_mask, uint64_t* O) {
-  if (b_prerotated) return cc_steps23(K, A, B, n_ct, level, H_g, L, d, out_mask, O);
+static int cc_run(const orc_keys* K, const uint64_t* A, const uint64_t* B, int n_ct, int level, int H_g, int L, int d, int b_prerotated,
+                  int n_dense, const uint8_t* out_mask, uint64_t* O) {
+  if (b_prerotated) return cc_steps23(K, A, B, n_ct, level, H_g, L, d, n_dense, out_mask, O);
   const orc_ctx* c = K->c;
   if (level < 4) return -2;
   int32_t geo[4]; orc_cc_geometry(c, H_g, L, d, geo);
@@ -1115,9 +1215,42 @@ int orc_matmul_cc(const orc_keys* K, const uint64_t* A, const uint64_t* B, int n
   uint64_t* Ad = (uint64_t*)malloc(8 * wq);
   uint64_t* Bq = (uint64_t*)malloc(8 * wq);
   int rc = cc_step1(K, A, B, n_ct, level, H_g, L, d, Ad, Bq);
-  if (rc == 0) rc = cc_steps23(K, Ad, Bq, n_ct, level - 1, H_g, L, d, out_mask, O);
+  if (rc == 0) rc = cc_steps23(K, Ad, Bq, n_ct, level - 1, H_g, L, d, n_dense, out_mask, O);
   free(Ad); free(Bq);
   return rc;
+}
+
+int orc_matmul_cc(const orc_keys* K, const uint64_t* A, const uint64_t* B, int n_ct, int level, int H_g, int L, int d, int b_prerotated,
+                  const uint8_t* out_mask, uint64_t* O) {
+  int32_t geo[4]; orc_cc_geometry(K->c, H_g, L, d, geo);
+  return cc_run(K, A, B, n_ct, level, H_g, L, d, b_prerotated, geo[3], out_mask, O);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Softmax x V_h with zero padding ("Efficient Fused Computations in Multi-Head          */
+/* Attention"; Appendix "Diagonal Ciphertext-Plaintext MatMul", figure diag (b))          */
+/* ------------------------------------------------------------------------------------ */
+/* The ct-ct protocol needs as many output columns as reduction rows, so V_h (L x d_v) is
+ * taken as an L x L' matrix whose columns from d_v on are zero: the operands are A_h = the
+ * L x L attention weights (reduction dimension d = L) and B_h = V_h with its d_v columns.
+ * With d_v' = 2^ceil(log2 d_v), the diagonals D and D + d_v' (mod L') of the L x L' product are
+ * complementary (one of the two is zero in every row), so the L'/d_v' diagonal ciphertexts whose
+ * diagonal indices agree mod d_v' are added into one: output g' < d_v'/c holds at slot
+ * i + L'(h + H_g kappa) the value Att_h{i, (i + g' c + kappa) mod d_v'} (0 for columns >= d_v),
+ * the dense diagonal packing of the L x d_v' matrix.  Requires d_v' <= L' and c <= d_v'. */
+void orc_cc_sv_geometry(const orc_ctx* c, int H_g, int L, int d_v, int32_t* out /* [5] */) {
+  int32_t geo[4]; orc_cc_geometry(c, H_g, L, L, geo);
+  int dvp = 1 << ceil_log2(d_v);
+  out[0] = geo[0]; out[1] = geo[1]; out[2] = geo[2];
+  out[3] = (dvp <= geo[0] && geo[1] <= dvp) ? dvp / geo[1] : 0;
+  out[4] = dvp;
+}
+
+int orc_matmul_cc_sv(const orc_keys* K, const uint64_t* A, const uint64_t* B, int n_ct, int level, int H_g, int L, int d_v,
+                     int b_prerotated, const uint8_t* out_mask, uint64_t* O) {
+  int32_t geo[5]; orc_cc_sv_geometry(K->c, H_g, L, d_v, geo);
+  if (geo[3] < 1) return -3;
+  return cc_run(K, A, B, n_ct, level, H_g, L, L, b_prerotated, geo[3], out_mask, O);
 }
 
 /* Galois elements of one group's matmul_cc: left t and right L'-t for t < L', right tau H_g L' */

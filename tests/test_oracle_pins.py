@@ -635,3 +635,168 @@ def test_matmul_cc_counts():
         c_ = 8192 // (128 * H_g)
         n_tensor += 128 * (64 // c_)
     assert n_tensor == 1536 == 128 * 128 * 768 // 8192
+
+
+# --------------------------------------------------------------------------------------
+# Softmax x V_h (zero padding, dense diagonal packing) and the diagonal-input matmul_cp
+# --------------------------------------------------------------------------------------
+def _groups(heads):
+    out, h = [], heads
+    while h:
+        g = 1 << (h.bit_length() - 1)
+        out.append(g)
+        h -= g
+    return out
+
+
+def _softmax_rows(rng, L):
+    z = rng.normal(0, 1, (L, L))
+    e = np.exp(z - z.max(axis=1, keepdims=True))
+    return e / e.sum(axis=1, keepdims=True)
+
+
+def _dense_diag_vec(att, h0, H_g, lp, cg, o, L, d_v, dvp, slots):
+    """slot i + L'(h + H_g kappa) <- Att_{h0+h}{i, (i + o c_g + kappa) mod d_v'} (0 past d_v or L),
+    written element by element from the definition"""
+    v = np.zeros(slots)
+    for h in range(H_g):
+        for kap in range(cg):
+            for i in range(L):
+                col = (i + o * cg + kap) % dvp
+                if col < d_v:
+                    v[i + lp * (h + H_g * kap)] = att[h0 + h][i, col]
+    return v
+
+
+def _sv_small(orc, log_n, n_q, H_g, L, d_v, seed):
+    c = orc.Context(log_n, n_q, 2, (n_q + 1) // 2)
+    g = c.cc_sv_geometry(H_g, L, d_v)
+    rng = np.random.default_rng(seed)
+    Sm = [_softmax_rows(rng, L) for _ in range(H_g)]
+    Vm = [rng.normal(0, 1, (L, d_v)) for _ in range(H_g)]
+    keys = orc.Keys(c, 5, c.cc_galois(H_g, L, L))
+    level, scale = n_q - 1, 2.0 ** 40
+    A = np.stack([keys.encrypt(c.encode_rns(c.pack_mhp(Sm, H_g, L, L, a, "A"), scale, level), level, 10, a) for a in range(g["n_ct"])])
+    Bv = np.stack([keys.encrypt(c.encode_rns(c.pack_mhp(Vm, H_g, L, L, a, "Bp"), scale, level), level, 11, a)
+                   for a in range(g["n_ct"])])
+    return c, g, keys, Sm, Vm, A, Bv, level, scale
+
+
+@pytest.mark.parametrize("log_n,H_g,L,d_v", [(12, 4, 32, 16), (12, 4, 20, 12), (11, 4, 32, 16)])
+def test_softmax_v_dense_diagonals(orc, log_n, H_g, L, d_v):
+    """Softmax x V_h through the ct-ct protocol with V_h zero-padded to L' columns, the diagonal
+    ciphertexts folded mod d_v' (figure diag (b)): output o decodes to Att_h{i, (i + o c + kappa)
+    mod d_v'} = (S_h V_h){i, .} for every head, zero past d_v and past row L.  Covers a fold of 2
+    (L' = 2 d_v'), a ragged L with d_v = 12 (d_v' = 16, the padded columns stay zero) and two dense
+    outputs per group (c < d_v' at N = 2048).  A wrong fold index, a lost wrap term or a
+    non-complementary pair of diagonals breaks the check."""
+    c, g, keys, Sm, Vm, A, Bv, level, scale = _sv_small(orc, log_n, 4, H_g, L, d_v, log_n + L + d_v)
+    assert g["n_out"] == g["dvp"] // g["c"] >= 1
+    O = keys.matmul_cc_sv(A, Bv, level, H_g, L, d_v)
+    out_scale = scale * 1024.0 * scale / float(c.q[2])
+    lp, cg, dvp = g["Lp"], g["c"], g["dvp"]
+    ref = [Sm[h] @ Vm[h] for h in range(H_g)]
+    worst, zero = 0.0, 0.0
+    for o in range(g["n_out"]):
+        v = c.decode(keys.decrypt(O[o], 0), 0, out_scale)
+        want = _dense_diag_vec(ref, 0, H_g, lp, cg, o, L, d_v, dvp, c.slots)
+        worst = max(worst, np.abs(v - want).max())
+    assert worst < 2.0 ** -20
+    # the fold really covers every column: each (i, col < d_v) appears in exactly one dense slot
+    seen = np.zeros((H_g, L, d_v), int)
+    for o in range(g["n_out"]):
+        for h in range(H_g):
+            for kap in range(cg):
+                for i in range(L):
+                    col = (i + o * cg + kap) % dvp
+                    if col < d_v:
+                        seen[h, i, col] += 1
+    assert (seen == 1).all()
+
+
+def test_softmax_v_geometry_limits(orc):
+    """The fold needs d_v' <= L' and c <= d_v' (one output ciphertext gathers whole diagonals);
+    the ct-ct multiplication count of Softmax x V_h is m^3 H / s (Table complexity_compare)."""
+    c = orc.Context(14, 2, 1, 2)
+    g = c.cc_sv_geometry(8, 128, 64)
+    assert (g["Lp"], g["c"], g["n_ct"], g["n_out"]) == (128, 8, 16, 8)
+    g4 = c.cc_sv_geometry(4, 128, 64)
+    assert (g4["c"], g4["n_ct"], g4["n_out"]) == (16, 8, 4)
+    # 12 heads = 8 + 4: tensors = L' * sum n_ct = 128 * 24 = 3072 = m^3 H / s at s = 8192 slots
+    assert 128 * (g["n_ct"] + g4["n_ct"]) == 128 ** 3 * 12 // 8192
+    # the 12 dense outputs hold Concat(Att_h) (128 x 768) tightly: 12 = 768 * 128 / 8192
+    assert g["n_out"] + g4["n_out"] == 768 * 128 // 8192
+    assert c.cc_sv_geometry(1, 64, 64)["n_out"] == 0      # c = 128 > d_v' = 64
+    assert c.cc_sv_geometry(8, 32, 64)["n_out"] == 0      # d_v' = 64 > L' = 32
+
+
+def _diag_inputs(c, keys, att, heads, L, d_v, level, scale, seed):
+    lp = 1 << int(np.ceil(np.log2(L)))
+    dvp = 1 << int(np.ceil(np.log2(d_v)))
+    cts, h0, a = [], 0, 0
+    for H_g in _groups(heads):
+        cg = c.slots // (lp * H_g)
+        for o in range(dvp // cg):
+            v = _dense_diag_vec(att, h0, H_g, lp, cg, o, L, d_v, dvp, c.slots)
+            cts.append(keys.encrypt(c.encode_rns(v, scale, level), level, seed, a))
+            a += 1
+        h0 += H_g
+    return np.stack(cts)
+
+
+def _unpack_spatial_by_hand(vecs, lp, cc, L, D):
+    out = np.zeros((L, D))
+    for col in range(D):
+        b, u = divmod(col, cc)
+        out[:, col] = vecs[b][u * lp: u * lp + L]
+    return out
+
+
+@pytest.mark.parametrize("heads,L,d_v,d_out", [(3, 64, 32, 48), (2, 50, 24, 40), (4, 32, 16, 70)])
+def test_matmul_cp_diag_decodes(orc, heads, L, d_v, d_out):
+    """Diagonal-input ct-pt matmul: inputs in the dense diagonal packing (head groups
+    concatenated, 3 heads = 2 + 1 with different c per group), output spatial-first, decodes to
+    Concat(Att_h) @ W in FP64; W = I returns Concat(Att_h) itself, which pins the row map
+    (head, (i + tau) mod d_v') of the plaintext diagonals on its own."""
+    c = orc.Context(12, 2, 1, 2)
+    rng = np.random.default_rng(heads + L + d_v)
+    att = [rng.uniform(-1, 1, (L, d_v)) for _ in range(heads)]
+    Cm = np.concatenate(att, axis=1)
+    dvp = 1 << int(np.ceil(np.log2(d_v)))
+    g = c.cp_geometry(L, heads * dvp, d_out)
+    gi = c.cp_geometry(L, heads * dvp, heads * d_v)
+    gal = sorted(set(c.cp_galois(L, heads * dvp, d_out)) | set(c.cp_galois(L, heads * dvp, heads * d_v)))
+    keys = orc.Keys(c, 9, gal)
+    X = _diag_inputs(c, keys, att, heads, L, d_v, 1, 2.0 ** 30, 100)
+    assert X.shape[0] == g["n_in"]
+    W = rng.normal(0, 0.05, (heads * d_v, d_out))
+    Y = keys.matmul_cp_diag(X, 1, W, L, heads, d_v)
+    vecs = [c.decode(keys.decrypt(Y[b], 0), 0, 2.0 ** 30) for b in range(g["n_out"])]
+    assert np.abs(_unpack_spatial_by_hand(vecs, g["Lp"], g["c"], L, d_out) - Cm @ W).max() < 2.0 ** -10
+    # rows past L of every output block stay (near) zero
+    if L < g["Lp"]:
+        for v in vecs:
+            for u in range(g["c"]):
+                assert np.abs(v[u * g["Lp"] + L: (u + 1) * g["Lp"]]).max() < 2.0 ** -10
+    Yi = keys.matmul_cp_diag(X, 1, np.eye(heads * d_v), L, heads, d_v)
+    vi = [c.decode(keys.decrypt(Yi[b], 0), 0, 2.0 ** 30) for b in range(gi["n_out"])]
+    assert np.abs(_unpack_spatial_by_hand(vi, gi["Lp"], gi["c"], L, heads * d_v) - Cm).max() < 2.0 ** -12
+
+
+def test_attention_output_pipeline(orc):
+    """Softmax x V_h (ct-ct, zero padding, dense fold) followed by the diagonal-input ct-pt matmul
+    decodes to (S_h V_h)_h concatenated times W_O: the two operators compose with no repacking."""
+    H_g, L, d_v, d_out = 4, 32, 16, 24
+    c, g, keys, Sm, Vm, A, Bv, level, scale = _sv_small(orc, 11, 5, H_g, L, d_v, 3)
+    O = keys.matmul_cc_sv(A, Bv, level, H_g, L, d_v)
+    lvl = level - 3
+    out_scale = scale * 1024.0 * scale / float(c.q[level - 1])
+    gcp = c.cp_geometry(L, H_g * g["dvp"], d_out)
+    keys2 = orc.Keys(c, 5, sorted(set(c.cc_galois(H_g, L, L)) | set(c.cp_galois(L, H_g * g["dvp"], d_out))))
+    assert np.array_equal(keys2.secret, keys.secret)
+    rng = np.random.default_rng(8)
+    W = rng.normal(0, 0.1, (H_g * d_v, d_out))
+    E = keys2.matmul_cp_diag(O, lvl, W, L, H_g, d_v)
+    vecs = [c.decode(keys2.decrypt(E[b], lvl - 1), lvl - 1, out_scale) for b in range(gcp["n_out"])]
+    ref = np.concatenate([Sm[h] @ Vm[h] for h in range(H_g)], axis=1) @ W
+    assert np.abs(_unpack_spatial_by_hand(vecs, gcp["Lp"], gcp["c"], L, d_out) - ref).max() < 2.0 ** -16
