@@ -190,6 +190,33 @@ int blb_plan_cc_info(const blb_plan* plan, int32_t* info, int cap);
 int blb_matmul_cc(blb_ctx* ctx, const blb_keys* keys, const blb_plan* plan, const blb_ct* A, const blb_ct* Bp, int n_ct,
                   blb_ct* C_diag, int n_out);
 
+/* ---- Softmax x V_h with zero padding (Section "Efficient Fused Computations in Multi-Head
+ * Attention"; Appendix "Diagonal Ciphertext-Plaintext MatMul", figure diag (b)) -----------
+ * The same protocol (run with blb_matmul_cc) with A_h = the L x L attention weights
+ * (reduction dimension L: the packing above with d = L) and B_h = V_h, L x d_v, whose columns
+ * from d_v to L' are zero (operand B': slot i + L'(h + H kappa) holds V_h{a c + kappa,
+ * (i + kappa) mod L'}, 0 for columns >= d_v).  With d_v' = 2^ceil(log2 d_v), diagonals D and
+ * D + d_v' of the padded product are complementary, so each group's L'/c diagonal ciphertexts
+ * are accumulated mod d_v'/c before their final rescale: output o (o < d_v'/c) of a group holds
+ * at slot i + L'(h + H kappa) the value Att_h{i, (i + o c + kappa) mod d_v'} (0 for columns >= d_v),
+ * the dense diagonal packing that blb_plan_matmul_cp_diag takes.  Outputs per group: d_v'/c.
+ * Requires d_v' <= L' and c <= d_v' for every group (EINVAL otherwise); keys as blb_cc_rotations.
+ * blb_plan_cc_info reports n_out = d_v'/c per group. */
+int blb_plan_matmul_cc_sv(blb_ctx* ctx, int n_heads, int L, int d_v, int level, int32_t b_prerotated, blb_plan** out);
+
+/* ---- matmul_cp with diagonal-packed input (Appendix "Diagonal Ciphertext-Plaintext MatMul",
+ * figure diag (c)) --------------------------------------------------------------------------
+ * E = Concat_h(Att_h) W for W (host, (n_heads d_v) x d_out row-major) and inputs in the dense
+ * diagonal packing of blb_plan_matmul_cc_sv (its outputs, head groups concatenated).  Output
+ * spatial-first, as blb_matmul_cp: run the plan with blb_matmul_cp (or its executors).  The
+ * BSGS schedule and geometry are those of a spatial-first input with n_heads d_v' columns
+ * (blb_plan_info; c_eff = c = (N/2) / L'), with the diagonals
+ *     d_{a,b,t}[u L' + r] = W{h d_v + (r + tau) mod d_v', b c + (u mod c_out)},
+ * (h, tau) = head and diagonal held by block (u + t) mod c of input a, and 0 for r >= L or
+ * (r + tau) mod d_v' >= d_v; encoded at q_level / 2^10 like blb_plan_matmul_cp.  EINVAL when the
+ * head groups do not tile the input (the limits of blb_plan_matmul_cc_sv). */
+int blb_plan_matmul_cp_diag(blb_ctx* ctx, const double* W, int n_heads, int d_v, int d_out, int L, int level, blb_plan** out);
+
 /* ---- re-randomisation before mask-to-share (opt-in) -----------------------------------
  * Algorithm ckks2mpc hands the masked ciphertext to the client as evaluated; its c1 depends on
  * the server's weights, which the paper does not address.  This call adds a public-key

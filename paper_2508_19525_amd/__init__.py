@@ -79,6 +79,9 @@ _SIGS = {
     "blb_mask_to_share": (C.c_int, [C.c_void_p, C.POINTER(blb_ct), C.c_int, C.c_uint64, C.c_int, C.c_void_p]),
     "blb_cc_rotations": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int]),
     "blb_plan_matmul_cc": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int32, C.POINTER(C.c_void_p)]),
+    "blb_plan_matmul_cc_sv": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int32, C.POINTER(C.c_void_p)]),
+    "blb_plan_matmul_cp_diag": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                          C.POINTER(C.c_void_p)]),
     "blb_plan_cc_info": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "blb_matmul_cc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.POINTER(blb_ct), C.c_int,
                                 C.POINTER(blb_ct), C.c_int]),
@@ -320,6 +323,22 @@ def blb_cc_rotations(ctx, n_heads, L):
 def blb_plan_matmul_cc(ctx, n_heads, L, d_head, level, b_prerotated=True):
     out = C.c_void_p()
     _check(lib().blb_plan_matmul_cc(ctx, n_heads, L, d_head, level, 1 if b_prerotated else 0, C.byref(out)), "blb_plan_matmul_cc")
+    return out.value
+
+
+def blb_plan_matmul_cc_sv(ctx, n_heads, L, d_v, level, b_prerotated=True):
+    out = C.c_void_p()
+    _check(lib().blb_plan_matmul_cc_sv(ctx, n_heads, L, d_v, level, 1 if b_prerotated else 0, C.byref(out)), "blb_plan_matmul_cc_sv")
+    return out.value
+
+
+def blb_plan_matmul_cp_diag(ctx, W: np.ndarray, n_heads, d_v, L, level):
+    Wc = np.ascontiguousarray(W, dtype=np.float64)
+    if Wc.shape[0] != n_heads * d_v:
+        raise BlbError(BLB_EINVAL, "blb_plan_matmul_cp_diag")
+    out = C.c_void_p()
+    _check(lib().blb_plan_matmul_cp_diag(ctx, _host_ptr(Wc), n_heads, d_v, Wc.shape[1], L, level, C.byref(out)),
+           "blb_plan_matmul_cp_diag")
     return out.value
 
 

@@ -1212,6 +1212,17 @@ static CpGeom cp_geometry(const blb_ctx* c, int L, int d_in, int d_out) {
 
 }  // extern "C"
 
+// head groups of matmul_cc: powers of two, largest first (12 = 8 + 4)
+static void cc_group_sizes(int heads, std::vector<int>& out) {  // powers of two, largest first
+  int h = heads;
+  while (h > 0) {
+    int g = 1;
+    while (g * 2 <= h) g *= 2;
+    out.push_back(g);
+    h -= g;
+  }
+}
+
 // BLB_OK when K holds every Galois key matmul_cp needs at this geometry (baby and giant steps)
 int cp_check_keys(const blb_ctx* c, const blb_keys* K, int L, int d_in, int d_out) {
   const CpGeom g = cp_geometry(c, L, d_in, d_out);
@@ -1232,10 +1243,33 @@ size_t cp_plan_bytes(const blb_ctx* c, int L, int d_in, int d_out, int level) {
 // the encoder's overflow flag lands in *flag_host when the stream reaches it (non-zero: the
 // plan is unusable), and W must stay valid until then.
 int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, uint64_t* mem, blb_plan** out, int* flag_host,
-                   const double* W_dev) {
+                   const double* W_dev, int diag_heads, int diag_dv) {
   if (!c || (!W && !W_dev) || !out || d_in < 1 || d_out < 1 || L < 1 || L > c->n / 2 || level < 1 || level >= c->n_q) return BLB_EINVAL;
   *out = nullptr;
-  const CpGeom g = cp_geometry(c, L, d_in, d_out);
+  // diagonal-packed input: one table entry per input ciphertext (head groups in the order
+  // matmul_cc forms them); the geometry is that of a spatial-first input of n_heads d_v' columns
+  std::vector<CpDiagIn> dtab;
+  CpDiag dg{nullptr, 0, 0, 0};
+  int d_geom = d_in;
+  if (diag_heads > 0) {
+    if (diag_dv < 1 || (int64_t)diag_heads * diag_dv != d_in) return BLB_EINVAL;
+    const int S = c->n / 2, lp = 1 << ceil_log2(L), dvp = 1 << ceil_log2(diag_dv);
+    if (dvp > lp) return BLB_EINVAL;
+    std::vector<int> gs;
+    cc_group_sizes(diag_heads, gs);
+    int h0 = 0;
+    for (int H : gs) {
+      if (S % (lp * H)) return BLB_EINVAL;
+      const int cg = S / (lp * H);
+      if (cg > dvp) return BLB_EINVAL;
+      for (int o = 0; o < dvp / cg; ++o) dtab.push_back(CpDiagIn{h0, ceil_log2(H), cg, o});
+      h0 += H;
+    }
+    d_geom = diag_heads * dvp;
+    dg = CpDiag{nullptr, diag_dv, dvp, L};
+  }
+  const CpGeom g = cp_geometry(c, L, d_geom, d_out);
+  if (diag_heads > 0 && ((int)dtab.size() != g.n_in || g.c_eff != g.c)) return BLB_EINVAL;
   const int n = c->n, nl = level + 1;
   const int n_bj = g.n_out * g.G, n_ai = g.n_in * g.B;
   const size_t n_pt = (size_t)n_bj * n_ai;
@@ -1269,6 +1303,14 @@ int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int 
       }
       dW = w;
     }
+    if (!dtab.empty()) {
+      CpDiagIn* t = tmp.get<CpDiagIn>(dtab.size());
+      if (t && hipMemcpyAsync(t, dtab.data(), dtab.size() * sizeof(CpDiagIn), hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+        blb_plan_destroy(P);
+        return BLB_EDEVICE;
+      }
+      dg.tab = t;
+    }
     if (tmp.failed) {
       blb_plan_destroy(P);
       return BLB_ENOMEM;
@@ -1278,7 +1320,7 @@ int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int 
     for (size_t p0 = 0; p0 < n_pt; p0 += chunk) {
       const int cnt = (int)std::min<size_t>(chunk, n_pt - p0);
       uint64_t* dst = P->pt + p0 * nl * n;
-      run_encode_cp(c, dW, g, (int)p0, cnt, a, b, scale, nl, dst, c->d_flag);
+      run_encode_cp(c, dW, g, (int)p0, cnt, a, b, scale, nl, dst, c->d_flag, dg);
       ntt_regular(c, dst, (size_t)cnt * nl, nl, true);
     }
     if (flag_host) {
@@ -1304,6 +1346,11 @@ extern "C" {
 
 int blb_plan_matmul_cp(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, blb_plan** out) {
   return cp_plan_create(c, W, d_in, d_out, L, level, nullptr, out, nullptr, nullptr);
+}
+
+int blb_plan_matmul_cp_diag(blb_ctx* c, const double* W, int n_heads, int d_v, int d_out, int L, int level, blb_plan** out) {
+  if (n_heads < 1 || d_v < 1) return BLB_EINVAL;
+  return cp_plan_create(c, W, n_heads * d_v, d_out, L, level, nullptr, out, nullptr, nullptr, n_heads, d_v);
 }
 
 void blb_plan_destroy(blb_plan* P) {
@@ -1510,16 +1557,6 @@ int blb_mask_to_share(blb_ctx* c, blb_ct* cts, int n_ct, uint64_t seed, int targ
 // ==========================================================================================
 namespace {
 
-void cc_group_sizes(int heads, std::vector<int>& out) {  // powers of two, largest first
-  int h = heads;
-  while (h > 0) {
-    int g = 1;
-    while (g * 2 <= h) g *= 2;
-    out.push_back(g);
-    h -= g;
-  }
-}
-
 // encode `count` host slot vectors (S values each) at `scale` into evaluation-form
 // plaintexts out[count][level+1][N]
 int encode_vectors_ntt(blb_ctx* c, const std::vector<double>& vecs, int count, double scale, int level, uint64_t* out) {
@@ -1578,12 +1615,18 @@ int blb_cc_rotations(const blb_ctx* c, int n_heads, int L, int32_t* steps, int c
   return (int)u.size();
 }
 
-int blb_plan_matmul_cc(blb_ctx* c, int n_heads, int L, int d_head, int level, int32_t b_prerotated, blb_plan** out) {
-  if (!c || !out || n_heads < 1 || L < 1 || d_head < 1 || (b_prerotated != 0 && b_prerotated != 1)) return BLB_EINVAL;
+}  // extern "C"
+
+// matmul_cc plan; fold_dv > 0 (Softmax x V_h): V_h has fold_dv columns, zero-padded to L', and the
+// L'/c diagonal ciphertexts of each group are accumulated mod d_v'/c into d_v'/c dense outputs
+static int cc_plan_create(blb_ctx* c, int n_heads, int L, int d_head, int level, int32_t b_prerotated, int fold_dv, blb_plan** out) {
+  if (!c || !out || n_heads < 1 || L < 1 || d_head < 1 || fold_dv < 0 || (b_prerotated != 0 && b_prerotated != 1)) return BLB_EINVAL;
   if (level < (b_prerotated ? 3 : 4) || level >= c->n_q) return BLB_EINVAL;
   *out = nullptr;
   const int S = c->n / 2, n = c->n, lp = 1 << ceil_log2(L);
   if (lp > S) return BLB_EINVAL;
+  const int dvp = fold_dv > 0 ? 1 << ceil_log2(fold_dv) : lp;
+  if (dvp > lp) return BLB_EINVAL;
   std::vector<int> gs;
   cc_group_sizes(n_heads, gs);
   blb_plan* P = new (std::nothrow) blb_plan();
@@ -1612,7 +1655,12 @@ int blb_plan_matmul_cc(blb_ctx* c, int n_heads, int L, int d_head, int level, in
       return BLB_EINVAL;
     }
     g.n_ct = (d_head + g.c - 1) / g.c;
-    g.n_out = lp / g.c;
+    g.n_diag = lp / g.c;
+    if (g.c > dvp) {
+      delete P;
+      return BLB_EINVAL;
+    }
+    g.n_out = dvp / g.c;
     g.ct0 = ct0;
     g.out0 = out0;
     g.m_ge = g.m_lt = g.m_s1 = nullptr;
@@ -1690,6 +1738,17 @@ int blb_plan_matmul_cc(blb_ctx* c, int n_heads, int L, int d_head, int level, in
   }
   *out = P;
   return BLB_OK;
+}
+
+extern "C" {
+
+int blb_plan_matmul_cc(blb_ctx* c, int n_heads, int L, int d_head, int level, int32_t b_prerotated, blb_plan** out) {
+  return cc_plan_create(c, n_heads, L, d_head, level, b_prerotated, 0, out);
+}
+
+int blb_plan_matmul_cc_sv(blb_ctx* c, int n_heads, int L, int d_v, int level, int32_t b_prerotated, blb_plan** out) {
+  if (d_v < 1) return BLB_EINVAL;
+  return cc_plan_create(c, n_heads, L, L, level, b_prerotated, d_v, out);
 }
 
 int blb_plan_cc_info(const blb_plan* P, int32_t* info, int cap) {
@@ -1917,8 +1976,8 @@ int blb_matmul_cc(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct
       std::vector<std::vector<CcTerm>> per_out(g.n_out);
       for (int tt = 0; tt < nt; ++tt) {
         const int t = t0 + tt, gi = t / g.c, tau = t % g.c;
-        per_out[gi].push_back(CcTerm{vsrc[tt], g.m_ge + (size_t)tau * nl3 * n});
-        if (tau > 0) per_out[(gi + 1) % g.n_out].push_back(CcTerm{vsrc[tt], g.m_lt + (size_t)tau * nl3 * n});
+        per_out[gi % g.n_out].push_back(CcTerm{vsrc[tt], g.m_ge + (size_t)tau * nl3 * n});
+        if (tau > 0) per_out[((gi + 1) % g.n_diag) % g.n_out].push_back(CcTerm{vsrc[tt], g.m_lt + (size_t)tau * nl3 * n});
       }
       std::vector<CcTerm> terms;
       std::vector<int> off{0};

@@ -117,6 +117,18 @@ struct CpGeom {
   int Lp, c, c_eff, c_out, n_in, n_out, B, G;
 };
 
+// Diagonal-packed input of the ct-pt product (the dense outputs of Softmax x V_h, head groups
+// concatenated): input ciphertext a is the o-th output of a group of 2^logH heads starting at
+// head h0 with c_g columns per ciphertext; its block u holds head h0 + (u mod 2^logH) and
+// diagonal o c_g + floor(u / 2^logH) of that head.
+struct CpDiagIn {
+  int h0, logH, cg, o;
+};
+struct CpDiag {
+  const CpDiagIn* tab;  // device, one entry per input ciphertext; null: spatial-first input
+  int d_v, dvp, L;      // columns per head, 2^ceil(log2 d_v), rows
+};
+
 // ---------------------------------------------------------------------------------------
 // Host-side structures
 // ---------------------------------------------------------------------------------------
@@ -228,7 +240,8 @@ struct CcGroup {
   int H;      // heads in the group
   int c;      // columns (of d) per ciphertext
   int n_ct;   // ciphertexts per operand
-  int n_out;  // diagonal-packed output ciphertexts (L'/c)
+  int n_out;  // output ciphertexts: L'/c diagonal-packed, or d_v'/c dense (Softmax x V_h)
+  int n_diag; // diagonal ciphertexts the schedule accumulates (L'/c); n_out divides it
   int ct0;    // first operand ciphertext of the group
   int out0;   // first output ciphertext of the group
   uint64_t* m_ge;  // [c][nl3][N] masks M^{>=tau} at level-2, scale q_{level-2}
@@ -265,7 +278,7 @@ void uploader_forget_stream(blb_ctx* c, hipStream_t s);
 void stack_forget_stream(blb_ctx* c, hipStream_t s);
 size_t cp_plan_bytes(const blb_ctx* c, int L, int d_in, int d_out, int level);
 int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, uint64_t* mem, blb_plan** out, int* flag_host,
-                   const double* W_dev);
+                   const double* W_dev, int diag_heads = 0, int diag_dv = 0);
 void launch_sample_flood(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag, int bits);
 void upload_cdt(const uint64_t* table20);
 
@@ -304,4 +317,4 @@ void launch_zero(blb_ctx* c, uint64_t* dst, size_t words);
 int run_encode_dense(blb_ctx* c, const double* vals, int n_vals, int count, double* bufA, double* bufB, double scale, int nl, uint64_t* out,
                      int* d_overflow);
 int run_encode_cp(blb_ctx* c, const double* W, CpGeom g, int p0, int count, double* bufA, double* bufB, double scale, int nl, uint64_t* out,
-                  int* d_overflow);
+                  int* d_overflow, CpDiag dg = CpDiag{nullptr, 0, 0, 0});

@@ -533,14 +533,22 @@ struct EncSrcDense {
 //   value at slot s = W{a c + ((u + t) mod c_eff), b c + (u mod c_out)}, u = ((s - r) mod S) / L',
 //   t = jB + i, r = j B L' (plaintext pre-rotated right by r).
 // L', c, c_eff, c_out and S are powers of two (lLp = log2 L').
+// Plaintext diagonals of matmul_cp: diagonal (b, j, a, i) pre-rotated right by j B L' slots,
+// block u of the unrotated vector holding W{row, b c + (u mod c_out)} where, with
+// u' = (u + j B + i) mod c_eff, row = a c + u' for a spatial-first input (broadcast over the
+// L' slots of the block) or, for a diagonal-packed input (dg.tab set), row = h d_v + (r + tau)
+// mod d_v' at slot r of the block, (h, tau) being the head and diagonal that block u' of input
+// a holds (0 for r >= L or a padded column).
 struct EncSrcCp {
   const double* W;
   CpGeom g;
   int p0, count, M, lLp;
   const int32_t* slot_inv;
+  CpDiag dg;
   struct Diag {
     int r, t, row0, col0;
     bool used;
+    CpDiagIn in;
   };
   struct Pair {
     Diag x, y;
@@ -550,13 +558,24 @@ struct EncSrcCp {
     const int bj = p / n_ai, ai = p % n_ai;
     const int b = bj / g.G, j = bj % g.G;
     const int a = ai / g.B, i = ai % g.B;
-    return Diag{j * g.B * g.Lp, j * g.B + i, a * g.c, b * g.c, p < p0 + count};
+    const bool used = p < p0 + count;
+    const CpDiagIn in = (dg.tab && used) ? dg.tab[a] : CpDiagIn{0, 0, 1, 0};
+    return Diag{j * g.B * g.Lp, j * g.B + i, a * g.c, b * g.c, used, in};
   }
   __device__ double value(const Diag& d, int s) const {
     if (!d.used) return 0.0;
-    const int u = ((s - d.r) & (M - 1)) >> lLp;
-    const int row = d.row0 + ((u + d.t) & (g.c_eff - 1));
+    const int sr = (s - d.r) & (M - 1);
+    const int u = sr >> lLp;
+    const int ub = (u + d.t) & (g.c_eff - 1);
     const int col = d.col0 + (u & (g.c_out - 1));
+    int row = d.row0 + ub;
+    if (dg.tab) {
+      const int r = sr & (g.Lp - 1);
+      const int h = d.in.h0 + (ub & ((1 << d.in.logH) - 1));
+      const int jj = (r + d.in.o * d.in.cg + (ub >> d.in.logH)) & (dg.dvp - 1);
+      if (r >= dg.L || jj >= dg.d_v) return 0.0;
+      row = h * dg.d_v + jj;
+    }
     return (row < g.d_in && col < g.d_out) ? W[(size_t)row * g.d_out + col] : 0.0;
   }
   __device__ Pair begin(int pp) const { return Pair{diag(p0 + 2 * pp), diag(p0 + 2 * pp + 1)}; }
@@ -737,10 +756,10 @@ int run_encode_dense(blb_ctx* c, const double* vals, int n_vals, int count, doub
   return encode_with(c, EncSrcDense{vals, n_vals, c->d_slot_inv}, count, bufA, bufB, scale, nl, out, d_overflow, false);
 }
 int run_encode_cp(blb_ctx* c, const double* W, CpGeom g, int p0, int count, double* bufA, double* bufB, double scale, int nl, uint64_t* out,
-                  int* d_overflow) {
+                  int* d_overflow, CpDiag dg) {
   int lLp = 0;
   while ((1 << lLp) < g.Lp) ++lLp;
-  return encode_with(c, EncSrcCp{W, g, p0, count, c->n / 2, lLp, c->d_slot_inv}, count, bufA, bufB, scale, nl, out, d_overflow, true);
+  return encode_with(c, EncSrcCp{W, g, p0, count, c->n / 2, lLp, c->d_slot_inv, dg}, count, bufA, bufB, scale, nl, out, d_overflow, true);
 }
 
 // ---------------------------------------------------------------------------------------

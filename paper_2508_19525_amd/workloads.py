@@ -43,6 +43,10 @@ C1 = dict(params=Params(12, 2, 1, 2, 30), L=32, d_in=32, d_out=32, x_dist="unifo
 C2 = dict(params=Params(13, 3, 1, 3, 40), L=128, d_in=768, d_out=768, x_dist="normal", w_std=0.02)
 # C3: attention matmul_cc, N=16384, 4 x 50-bit primes + 2 special (dnum 2), scale 2^40
 C3 = dict(params=Params(14, 4, 2, 2, 40), heads=12, L=128, d_head=64)
+# C6: attention output -- Softmax x V_h (12 heads, 128 tokens, d_v = 64, V_h zero-padded to 128
+# columns) and Concat(Att_h) W_O (768 x 768) on the dense diagonal packing; N=16384, 5 x 50-bit
+# primes (three levels for the ct-ct product, one for the ct-pt product) + 2 special (dnum 3)
+C6 = dict(params=Params(14, 5, 2, 3, 40), heads=12, L=128, d_v=64, d_out=768, w_std=0.02)
 
 
 def activations(config: int, L: int, d: int, dist: str) -> np.ndarray:
@@ -96,11 +100,28 @@ def head_groups(heads: int):
     return out
 
 
+def attention_weights(config: int, heads: int, L: int):
+    """row-stochastic L x L matrices per head (softmax of seeded N(0, 1) logits): stand-ins for the
+    attention weights the MPC softmax hands back"""
+    rng = np.random.default_rng(seed_for(config, ROLE_X) + 1000)
+    out = []
+    for _ in range(heads):
+        z = rng.normal(0.0, 1.0, (L, L))
+        e = np.exp(z - z.max(axis=1, keepdims=True))
+        out.append(e / e.sum(axis=1, keepdims=True))
+    return out
+
+
+def head_values(config: int, heads: int, L: int, d_v: int):
+    rng = np.random.default_rng(seed_for(config, ROLE_X) + 2000)
+    return [rng.normal(0.0, 1.0, (L, d_v)) for _ in range(heads)]
+
+
 def pack_mhp(mats, H: int, L: int, d: int, a: int, operand: str, slots: int) -> np.ndarray:
     """Multi-head packing of operand ciphertext `a` of one head group (client side, before
     encryption): slot i + L'(h + H kappa) holds A_h{i, a c + kappa} for operand "A" and the
-    row-pre-rotated B_h{a c + kappa, (i + kappa) mod L'} for operand "Bp" (B_h = mats[h], d x L),
-    with L' = 2^ceil(log2 L) and c = slots / (L' H)."""
+    row-pre-rotated B_h{a c + kappa, (i + kappa) mod L'} for operand "Bp" (B_h = mats[h], d rows and
+    up to L' columns, the rest zero), with L' = 2^ceil(log2 L) and c = slots / (L' H)."""
     lp = 1 << int(np.ceil(np.log2(L)))
     c = slots // (lp * H)
     v = np.zeros(slots)
@@ -118,7 +139,7 @@ def pack_mhp(mats, H: int, L: int, d: int, a: int, operand: str, slots: int) -> 
             else:
                 j = (i + kap) % lp
                 row = np.zeros(lp)
-                row[:L] = mats[h][k, :]
+                row[:mats[h].shape[1]] = mats[h][k, :]
                 v[base: base + lp] = row[j]
     return v
 
@@ -136,6 +157,34 @@ def unpack_diag(vecs, H: int, L: int, slots: int, g0: int = 0):
                 D = (g0 + g) * c + kap
                 C[h][i, (i + D) % lp] = v[lp * (h + H * kap) + i]
     return [m[:L, :L] for m in C]
+
+
+def dense_diag_layout(heads: int, L: int, d_v: int, slots: int):
+    """Where the dense diagonal packing (the Softmax x V_h outputs, head groups concatenated)
+    puts Att_h{i, j}: arrays (ct, slot, head, row, col) over every slot that holds an element.
+    Output o of a group of H heads (c = slots / (L' H)) holds at slot i + L'(h + H kappa) the
+    element (i, (i + o c + kappa) mod d_v') of head h, d_v' = 2^ceil(log2 d_v)."""
+    lp = 1 << int(np.ceil(np.log2(L)))
+    dvp = 1 << int(np.ceil(np.log2(d_v)))
+    cts, sl, hs, rs, cs = [], [], [], [], []
+    a, h0 = 0, 0
+    i = np.arange(L)
+    for H in head_groups(heads):
+        c = slots // (lp * H)
+        for o in range(dvp // c):
+            for h in range(H):
+                for kap in range(c):
+                    col = (i + o * c + kap) % dvp
+                    keep = col < d_v
+                    n_k = int(keep.sum())
+                    cts.append(np.full(n_k, a))
+                    sl.append(i[keep] + lp * (h + H * kap))
+                    hs.append(np.full(n_k, h0 + h))
+                    rs.append(i[keep])
+                    cs.append(col[keep])
+            a += 1
+        h0 += H
+    return tuple(np.concatenate(x) for x in (cts, sl, hs, rs, cs))
 
 
 # C4: 64 independent matmul_cp instances, lengths uniform in {16..512}, hidden 768 or 1024,

@@ -164,3 +164,88 @@ def test_attention_matmul_cc_full_size(B, orc):
     finally:
         torch.cuda.synchronize()
         B.blb_ctx_destroy(ctx)
+
+
+def test_attention_output_full_size(B, orc):
+    """BERT-base attention output (N = 16384, five primes + two special): Softmax x V_h for 12
+    heads of 128 tokens with d_v = 64 (V_h zero-padded to 128 columns, folded to the dense
+    diagonal packing), then Concat(Att_h) W_O (768 x 768) on that packing.  Tensor products =
+    m^3 H / s = 3072; every head decodes to S_h V_h within 2^-20 and E to (S_h V_h)_h W_O within
+    2^-14.  On the oracle's encryptions of a dense diagonal-packed input, one sampled output of the
+    diagonal-input product equals the oracle's word for word."""
+    from paper_2508_19525_amd import workloads as wl
+    cfg = wl.C6
+    p = cfg["params"]
+    heads, L, d_v, d_out = cfg["heads"], cfg["L"], cfg["d_v"], cfg["d_out"]
+    n, level, slots = p.n, p.n_q - 1, p.n // 2
+    S = wl.attention_weights(6, heads, L)
+    V = wl.head_values(6, heads, L, d_v)
+    W = wl.weights(6, heads * d_v, d_out, cfg["w_std"])
+    o = orc.Context(p.log_n, p.n_q, p.n_special, p.dnum)
+    ctx = B.blb_ctx_create(p.log_n, p.n_q, p.n_special, p.dnum, 0, torch.cuda.current_stream().cuda_stream)
+    keep = []
+    try:
+        g = o.cp_geometry(L, heads * d_v, d_out)
+        assert (g["Lp"], g["c"], g["c_eff"], g["n_in"], g["n_out"], g["B"], g["G"]) == (128, 64, 64, 12, 12, 8, 8)
+        cp_steps = [i * g["Lp"] for i in range(1, g["B"])] + [j * g["B"] * g["Lp"] for j in range(1, g["G"])]
+        steps = list(B.blb_cc_rotations(ctx, heads, L)) + cp_steps
+        gal = sorted({o.galois_elt(s) for s in steps})
+        keys_o = orc.Keys(o, 83, gal)
+        keys = B.blb_keygen(ctx, 83, steps)
+        plan = B.blb_plan_matmul_cc_sv(ctx, heads, L, d_v, level)
+        info = B.blb_plan_cc_info(plan)
+        assert [(x["H"], x["c"], x["n_ct"], x["n_out"]) for x in info["groups"]] == [(8, 8, 16, 8), (4, 16, 8, 4)]
+        A, Bv, h0 = [], [], 0
+        for gi, grp in enumerate(info["groups"]):
+            H = grp["H"]
+            for a in range(grp["n_ct"]):
+                aw = keys_o.encrypt(o.encode_rns(o.pack_mhp(S[h0:h0 + H], H, L, L, a, "A"), p.scale, level), level, 84 + gi, a)
+                bw = keys_o.encrypt(o.encode_rns(o.pack_mhp(V[h0:h0 + H], H, L, L, a, "Bp"), p.scale, level), level, 86 + gi, a)
+                A.append(_import(B, ctx, keep, aw, n, level, p.scale))
+                Bv.append(_import(B, ctx, keep, bw, n, level, p.scale))
+            h0 += H
+        Att = [_ct(B, keep, n, level - 3) for _ in range(info["n_out"])]
+        B.blb_ctx_counters(ctx, reset=True)
+        B.blb_matmul_cc(ctx, keys, plan, A, Bv, Att)
+        cnt = B.blb_ctx_counters(ctx, reset=True)
+        torch.cuda.synchronize()
+        assert cnt["tensor_products"] == 128 ** 3 * 12 // 8192 == 3072
+        assert cnt["relinearisations"] == 2 * 128
+        assert cnt["key_switches"] == 24 * 2 * 127 + 2 * 128 + (128 - 16) + (128 - 8)
+        dec = torch.empty(n, dtype=torch.int64, device="cuda")
+
+        def decode(ct):
+            B.blb_decrypt(ctx, keys, ct, dec)
+            return B.blb_decode(ctx, dec, ct.level, ct.scale, slots)
+
+        got = np.stack([decode(ct) for ct in Att])
+        ct_i, sl, hs, rs, cs = wl.dense_diag_layout(heads, L, d_v, slots)
+        want = np.zeros_like(got)
+        want[ct_i, sl] = np.stack([S[h] @ V[h] for h in range(heads)])[hs, rs, cs]
+        assert np.abs(got - want).max() < 2.0 ** -20
+        # Concat(Att_h) W_O on the dense diagonal packing, spatial-first output
+        lvl = level - 3
+        cplan = B.blb_plan_matmul_cp_diag(ctx, W, heads, d_v, L, lvl)
+        assert B.blb_plan_info(cplan) == g
+        E = [_ct(B, keep, n, lvl - 1) for _ in range(g["n_out"])]
+        B.blb_matmul_cp(ctx, keys, cplan, Att, E)
+        vecs = [decode(e) for e in E]
+        ref = np.concatenate([S[h] @ V[h] for h in range(heads)], axis=1) @ W
+        assert np.abs(wl.unpack_spatial(vecs, L, d_out, slots) - ref).max() < 2.0 ** -14
+        # word-for-word sample of the diagonal-input product on oracle-encrypted inputs
+        rng = np.random.default_rng(wl.seed_for(6, wl.ROLE_ENC))
+        X = np.zeros((g["n_in"], slots))
+        X[ct_i, sl] = rng.uniform(-1, 1, ct_i.size)
+        xw = [keys_o.encrypt(o.encode_rns(X[a], p.scale, lvl), lvl, 88, a) for a in range(g["n_in"])]
+        Xc = [_import(B, ctx, keep, w, n, lvl, p.scale) for w in xw]
+        E2 = [_ct(B, keep, n, lvl - 1) for _ in range(g["n_out"])]
+        B.blb_matmul_cp(ctx, keys, cplan, Xc, E2)
+        sample = 5
+        want_b = keys_o.matmul_cp_diag(np.stack(xw), lvl, W, L, heads, d_v, outputs=[sample])
+        assert np.array_equal(B.blb_export(ctx, E2[sample], n), want_b[sample])
+        B.blb_plan_destroy(cplan)
+        B.blb_plan_destroy(plan)
+        B.blb_keys_destroy(keys)
+    finally:
+        torch.cuda.synchronize()
+        B.blb_ctx_destroy(ctx)
