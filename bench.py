@@ -290,6 +290,112 @@ def run_cc(args, B, torch):
     return res
 
 
+def run_attn_out(args, B, torch):
+    """BERT-base attention output: Softmax x V_h (12 heads, 128 tokens, d_v = 64, V_h zero-padded and
+    folded to the dense diagonal packing), Concat(Att_h) W_O (768 x 768) on that packing, and
+    mask-to-share of the 12 output ciphertexts; N = 16384, 5 primes + 2 special (dnum 3)."""
+    from paper_2508_19525_amd import workloads as wl
+
+    cfg = wl.C6
+    p = cfg["params"]
+    heads, L, d_v, d_out = cfg["heads"], cfg["L"], cfg["d_v"], cfg["d_out"]
+    n, level, slots = p.n, p.n_q - 1, p.n // 2
+    S = wl.attention_weights(6, heads, L)
+    V = wl.head_values(6, heads, L, d_v)
+    W = wl.weights(6, heads * d_v, d_out, cfg["w_std"])
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = B.blb_ctx_create(p.log_n, p.n_q, p.n_special, p.dnum, 0, stream)
+    t_setup = time.time()
+    lvl = level - 3
+    cplan = B.blb_plan_matmul_cp_diag(ctx, W, heads, d_v, L, lvl)
+    g = B.blb_plan_info(cplan)
+    steps_rot = list(B.blb_cc_rotations(ctx, heads, L)) + [i * g["Lp"] for i in range(1, g["B"])] + \
+        [j * g["B"] * g["Lp"] for j in range(1, g["G"])]
+    keys = B.blb_keygen(ctx, wl.seed_for(6, wl.ROLE_KEYS), steps_rot)
+    plan = B.blb_plan_matmul_cc_sv(ctx, heads, L, d_v, level)
+    info = B.blb_plan_cc_info(plan)
+    keep, A, Bv = [], [], []
+    pt = torch.empty((level + 1) * n, dtype=torch.int64, device="cuda")
+    h0 = 0
+    for grp in info["groups"]:
+        H = grp["H"]
+        for a in range(grp["n_ct"]):
+            for mats, op, dst, tag in ((S, "A", A, 0), (V, "Bp", Bv, 1)):
+                B.blb_encode(ctx, wl.pack_mhp(mats[h0:h0 + H], H, L, L, a, op, slots), p.scale, level, pt)
+                ct, t = B.new_ct(n, level)
+                keep.append(t)
+                B.blb_encrypt(ctx, keys, pt, level, p.scale, wl.seed_for(6, wl.ROLE_ENC), 2 * (grp["ct0"] + a) + tag, ct)
+                dst.append(ct)
+        h0 += H
+
+    def cts(k, lv):
+        out = []
+        for _ in range(k):
+            ct, t = B.new_ct(n, lv)
+            keep.append(t)
+            out.append(ct)
+        return out
+
+    Att, E = cts(info["n_out"], lvl), cts(g["n_out"], lvl - 1)
+    share = torch.zeros(g["n_out"] * n, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    log(f"attention-output setup {time.time() - t_setup:.1f}s: {len(steps_rot)} rotation keys, Softmax x V plan {info}, "
+        f"W_O plan {g}, device bytes {B.blb_ctx_device_bytes(ctx) / 1e9:.2f} GB")
+
+    def eager_step(seed):
+        B.blb_matmul_cc(ctx, keys, plan, A, Bv, Att)
+        B.blb_matmul_cp(ctx, keys, cplan, Att, E)
+        B.blb_mask_to_share(ctx, E, seed, 0, share)
+
+    # accuracy of E = Concat(S_h V_h) W_O (before the mask)
+    B.blb_matmul_cc(ctx, keys, plan, A, Bv, Att)
+    B.blb_matmul_cp(ctx, keys, cplan, Att, E)
+    dec = torch.empty(n, dtype=torch.int64, device="cuda")
+    vecs = []
+    for e in E:
+        B.blb_decrypt(ctx, keys, e, dec)
+        vecs.append(B.blb_decode(ctx, dec, e.level, e.scale, slots))
+    ref = np.concatenate([S[h] @ V[h] for h in range(heads)], axis=1) @ W
+    err = float(np.abs(wl.unpack_spatial(vecs, L, d_out, slots) - ref).max())
+    log(f"attention-output decoded max abs err {err:.3e}")
+    eager_step(1)
+    torch.cuda.synchronize()
+    B.blb_ctx_set_timing(ctx, True)
+    B.blb_ctx_reset_timing(ctx)
+    steps = max(1, args.steps // 4)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        eager_step(k + 2)
+    torch.cuda.synchronize()
+    dt_eager = time.perf_counter() - t0
+    split = {}
+    for name, kind in [("ntt", B.BLB_T_NTT), ("ks_inner", B.BLB_T_KS_INNER), ("modup", B.BLB_T_MODUP), ("moddown_conv", B.BLB_T_MODDOWN),
+                       ("tensor", B.BLB_T_CC_TENSOR), ("cp_mac", B.BLB_T_CP_MAC), ("masks_ew", B.BLB_T_EW)]:
+        split[name] = B.blb_ctx_read_timing(ctx, kind)[0] / steps
+    B.blb_ctx_set_timing(ctx, False)
+    ex1 = B.blb_exec_create_cc(ctx, keys, plan, A, Bv, Att)
+    ex2 = B.blb_exec_create_cp(ctx, keys, cplan, Att, E, 0, share)
+    B.blb_exec_run(ex1, 0)
+    B.blb_exec_run(ex2, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        B.blb_exec_run(ex1, 0)
+        B.blb_exec_run(ex2, k + 2)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"attention output: eager {steps / dt_eager:.1f}/s, graph {steps / dt:.1f}/s")
+    res = {"value": steps / dt, "eager": steps / dt_eager, "ms": dt / steps * 1e3, "err": err, "split_ms": split,
+           "rotation_keys": len(steps_rot), "groups": info["groups"], "wo_geometry": g}
+    B.blb_exec_destroy(ex1)
+    B.blb_exec_destroy(ex2)
+    B.blb_plan_destroy(cplan)
+    B.blb_plan_destroy(plan)
+    B.blb_keys_destroy(keys)
+    B.blb_ctx_destroy(ctx)
+    return res
+
+
 FP64_LANE_OPS = 256 * 2.4e9 * 64  # FP64 vector lane-ops/s (78.6 TFLOP/s counting an FMA as 2)
 NTT_OPS_PER_BUTTERFLY = 8  # 6 for the error-free modular product, 1 add, 1 subtract
 
@@ -615,12 +721,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cc", action="store_true", help="skip the matmul_cc measurement")
+    ap.add_argument("--no-attn-out", action="store_true", help="skip the attention-output (Softmax x V, W_O) measurement")
     ap.add_argument("--no-tune", action="store_true", help="skip the MAC launch-shape autotuner")
     ap.add_argument("--mac-variant", type=int, default=None, help="use this MAC launch shape instead of autotuning")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-ntt", action="store_true", help="skip the standalone NTT measurement")
     ap.add_argument("--ntt-only", action="store_true", help="run only the standalone NTT measurement (diagnostic)")
+    ap.add_argument("--attn-out-only", action="store_true", help="run only the attention-output measurement (diagnostic)")
     ap.add_argument("--serve-requests", type=int, default=80)
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-cache-gb", type=float, default=200.0)
@@ -638,9 +746,13 @@ def main():
     if args.ntt_only:  # diagnostic mode: the standalone NTT measurement alone
         print(json.dumps({"ntt_standalone_1GiB": run_ntt(args, B, torch)}))
         return
+    if args.attn_out_only:  # diagnostic mode: the attention-output measurement alone
+        print(json.dumps({"attention_output": run_attn_out(args, B, torch)}))
+        return
     r = run_cp(args, B, torch)
     nt = None if args.no_ntt else run_ntt(args, B, torch)
     cc = None if args.no_cc else run_cc(args, B, torch)
+    ao = None if args.no_attn_out else run_attn_out(args, B, torch)
     args.tuned_mac_variant = r["mac_variant"]  # the per-instance (unbatched) path uses the tuned MAC shape too
     bt = None if args.no_batch else run_batch(args, B, torch)
     sv = None if args.no_serve else run_serving(args, B, torch)
@@ -685,6 +797,11 @@ def main():
             "value": cc["value"], "eager_value": cc["eager"], "ms": cc["ms"], "max_abs_err": cc["err"],
             "ntt_GBps": cc["ntt_gbps"], "split_ms": cc["split_ms"], "rotation_keys": cc["rotation_keys"],
             "ntt_variant": cc["ntt_variant"], "ntt_tune_ms_per_op": cc["ntt_tune_ms"]},
+        "attention_output": None if ao is None else {
+            "metric": "attention-output ops/s (Softmax x V_h for 12 heads of 128 tokens, d_v 64, zero-padded and folded; "
+                      "Concat(Att_h) W_O 768x768 on the diagonal packing; mask-to-share of 12 cts; N=16384, 5 primes + 2 special)",
+            "value": ao["value"], "eager_value": ao["eager"], "ms": ao["ms"], "max_abs_err": ao["err"], "split_ms": ao["split_ms"],
+            "rotation_keys": ao["rotation_keys"]},
         "batched": None if bt is None else dict(
             bt, workload="64 independent matmul_cp instances, L ~ U{16..512}, hidden 768/1024 (W shared per hidden size), "
                          "N=8192, 3 primes; per-instance eager calls vs batched stages vs one graph launch"),
