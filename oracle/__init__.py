@@ -93,6 +93,7 @@ def lib():
             "orc_matmul_cc": (C.c_int, [vp, _u64p, _u64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, _u64p]),
             "orc_cc_galois": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, _u64p]),
             "orc_cc_sv_geometry": (None, [vp, C.c_int, C.c_int, C.c_int, _i32p]),
+            "orc_mhp_weight": (C.c_int, [vp, _f64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p]),
             "orc_matmul_cc_sv": (C.c_int, [vp, _u64p, _u64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p,
                                            _u64p]),
             "orc_matmul_cp_diag": (C.c_int, [vp, _u64p, C.c_int, _f64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, _u64p]),
@@ -267,6 +268,17 @@ class Context:
         g = np.zeros(5, np.int32)
         lib().orc_cc_sv_geometry(self._p, H_g, L, d_v, g)
         return dict(zip(["Lp", "c", "n_ct", "n_out", "dvp"], [int(v) for v in g]))
+
+    def mhp_weight(self, W, n_heads: int, d_head: int, L: int) -> np.ndarray:
+        """W (d_in x n_heads d_head) with its columns reordered so that matmul_cp's spatial-first
+        output is the multi-head packing of the ct-ct operands (head groups concatenated)"""
+        W = _c(W, np.float64)
+        n_cols = lib().orc_mhp_weight(self._p, W, W.shape[0], n_heads, d_head, L, None)
+        if n_cols < 0:
+            raise ValueError("unsupported multi-head geometry")
+        out = np.zeros((W.shape[0], n_cols), np.float64)
+        lib().orc_mhp_weight(self._p, W, W.shape[0], n_heads, d_head, L, out.ctypes.data_as(C.c_void_p))
+        return out
 
     def pack_mhp(self, mats, H_g, L, d, a, operand):
         """Multi-head packing of ciphertext a for one head group: operand 'A' puts A_h{i, a c + kappa}

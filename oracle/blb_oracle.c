@@ -19,6 +19,7 @@
  *   - matmul_cp with BSGS (Section "Efficient Protocol for Fused MatMuls" and Appendix
  *     "BSGS Optimization"), spatial-first packing ("Consistent Packing for Single Operator").
  *   - matmul_cc steps 1-3 with multi-head packing ("Building Blocks", Multi-Head Optimization).
+ *   - the column reordering of W_Q / W_K that makes matmul_cp emit the multi-head packing.
  *   - Softmax x V_h with zero padding and the dense diagonal packing, and the matmul_cp variant
  *     with diagonal-packed input for Concat(Att_h) W_O ("Efficient Fused Computations in
  *     Multi-Head Attention"; Appendix "Diagonal Ciphertext-Plaintext MatMul").
@@ -1251,6 +1252,51 @@ int orc_matmul_cc_sv(const orc_keys* K, const uint64_t* A, const uint64_t* B, in
   int32_t geo[5]; orc_cc_sv_geometry(K->c, H_g, L, d_v, geo);
   if (geo[3] < 1) return -3;
   return cc_run(K, A, B, n_ct, level, H_g, L, L, b_prerotated, geo[3], out_mask, O);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Column reordering of W_Q / W_K for the multi-head packing (Multi-Head Optimization, and */
+/* "Efficient Fused Computations in Multi-Head Attention": matmul_cp + matmul_cc)         */
+/* ------------------------------------------------------------------------------------ */
+/* With the columns of W (d_in x n_heads d_head, head h owning columns h d_head .. h d_head +
+ * d_head - 1) reordered in plaintext, the spatial-first output of matmul_cp IS the multi-head
+ * packing of the ct-ct operands: output ciphertext b holds column b c + u of X W' at block u
+ * (c = S / L'), and the operand ciphertext a of a head group (H_g heads from h0, c_g = S / (L' H_g),
+ * ceil(d_head / c_g) ciphertexts, groups in order) must hold Y_{h0+h}{:, a c_g + kappa} at block
+ * u = h + H_g kappa.  So column b c + u of W' is column (h0 + u mod H_g) d_head + a c_g + u / H_g
+ * of W for b = (first ciphertext of the group) + a, and zero where a c_g + u / H_g >= d_head.
+ * Writes d_in x n_cols (row-major) to out when it is not NULL; returns n_cols = c * (number of
+ * operand ciphertexts), or -1 for a geometry the packing cannot hold. */
+int orc_mhp_weight(const orc_ctx* c, const double* W, int d_in, int n_heads, int d_head, int L, double* out) {
+  int s = c->n / 2, lp = 1 << ceil_log2(L), cc = s / lp;
+  if (lp > s) return -1;
+  int n_ct = 0;
+  for (int rem = n_heads; rem > 0;) {
+    int hg = 1;
+    while (hg * 2 <= rem) hg *= 2;
+    if (s % (lp * hg)) return -1;
+    int cg = s / (lp * hg);
+    if (cg > lp) return -1;
+    n_ct += (d_head + cg - 1) / cg;
+    rem -= hg;
+  }
+  int n_cols = n_ct * cc;
+  if (!out) return n_cols;
+  int b = 0, h0 = 0;
+  for (int rem = n_heads; rem > 0;) {
+    int hg = 1;
+    while (hg * 2 <= rem) hg *= 2;
+    int cg = s / (lp * hg), nct = (d_head + cg - 1) / cg;
+    for (int a = 0; a < nct; ++a, ++b)
+      for (int u = 0; u < cc; ++u) {
+        int h = h0 + u % hg, col = a * cg + u / hg, j = b * cc + u;
+        for (int r = 0; r < d_in; ++r)
+          out[(size_t)r * n_cols + j] = col < d_head ? W[(size_t)r * n_heads * d_head + h * d_head + col] : 0.0;
+      }
+    h0 += hg;
+    rem -= hg;
+  }
+  return n_cols;
 }
 
 /* Galois elements of one group's matmul_cc: left t and right L'-t for t < L', right tau H_g L' */

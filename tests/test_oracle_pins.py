@@ -800,3 +800,83 @@ def test_attention_output_pipeline(orc):
     vecs = [c.decode(keys2.decrypt(E[b], lvl - 1), lvl - 1, out_scale) for b in range(gcp["n_out"])]
     ref = np.concatenate([Sm[h] @ Vm[h] for h in range(H_g)], axis=1) @ W
     assert np.abs(_unpack_spatial_by_hand(vecs, gcp["Lp"], gcp["c"], L, d_out) - ref).max() < 2.0 ** -16
+
+
+# --------------------------------------------------------------------------------------
+# Column-reordered W_Q / W_K: matmul_cp emits the multi-head packing; fused Q K^T from X
+# --------------------------------------------------------------------------------------
+def _mhp_by_hand(Y, heads, d_head, L, slots):
+    """operand vectors of the multi-head packing of Y_h = Y[:, h d_head:(h+1) d_head], written from
+    the definition: group of H heads from h0, c = slots / (L' H), ciphertext a, block h + H kappa
+    holds column a c + kappa of Y_{h0+h}"""
+    lp = 1 << int(np.ceil(np.log2(L)))
+    vecs, h0 = [], 0
+    for H in _groups(heads):
+        c = slots // (lp * H)
+        for a in range(-(-d_head // c)):
+            v = np.zeros(slots)
+            for h in range(H):
+                for kap in range(c):
+                    col = a * c + kap
+                    if col < d_head:
+                        v[lp * (h + H * kap): lp * (h + H * kap) + L] = Y[:, (h0 + h) * d_head + col]
+            vecs.append(v)
+        h0 += H
+    return vecs
+
+
+@pytest.mark.parametrize("heads,L,d_in,d_head", [(3, 64, 40, 48), (12, 32, 64, 8)])
+def test_mhp_weight_makes_cp_emit_multihead_packing(orc, heads, L, d_in, d_head):
+    """matmul_cp with the column-reordered weight decodes, ciphertext by ciphertext, to the
+    multi-head packing of X W (3 heads = 2 + 1 with a ragged last operand ciphertext; 12 heads =
+    8 + 4, both groups with a ragged operand ciphertext); the reordering only permutes (and
+    zero-pads) columns."""
+    c = orc.Context(12, 2, 1, 2)
+    rng = np.random.default_rng(heads + L)
+    X = rng.uniform(-1, 1, (L, d_in))
+    W = rng.normal(0, 0.05, (d_in, heads * d_head))
+    Wp = c.mhp_weight(W, heads, d_head, L)
+    nz = Wp[:, np.abs(Wp).sum(axis=0) > 0]
+    assert sorted(map(tuple, nz.T)) == sorted(map(tuple, W.T))
+    g = c.cp_geometry(L, d_in, Wp.shape[1])
+    k = orc.Keys(c, 9, c.cp_galois(L, d_in, Wp.shape[1]))
+    cts = np.stack([k.encrypt(c.encode_rns(c.pack_spatial(X, a), 2.0 ** 30, 1), 1, 100, a) for a in range(g["n_in"])])
+    Y = k.matmul_cp(cts, 1, Wp, L)
+    want = _mhp_by_hand(X @ W, heads, d_head, L, c.slots)
+    assert len(want) == g["n_out"]
+    for b in range(g["n_out"]):
+        assert np.abs(c.decode(k.decrypt(Y[b], 0), 0, 2.0 ** 30) - want[b]).max() < 2.0 ** -10
+
+
+def test_fused_qk_from_x(orc):
+    """X -> Q = X W_Q', K = X W_K' (reordered columns) -> the ct-ct product with step 1 on the
+    server, with no repacking: decodes to Q_h K_h^T for every head (six primes: one level for
+    matmul_cp, four for the ct-ct product)."""
+    c = orc.Context(11, 6, 2, 3)
+    heads, L, d_in, d_head = 4, 32, 32, 16
+    rng = np.random.default_rng(4)
+    X = rng.normal(0, 1, (L, d_in))
+    WQ = rng.normal(0, 0.2, (d_in, heads * d_head))
+    WK = rng.normal(0, 0.2, (d_in, heads * d_head))
+    WQp, WKp = c.mhp_weight(WQ, heads, d_head, L), c.mhp_weight(WK, heads, d_head, L)
+    g = c.cp_geometry(L, d_in, WQp.shape[1])
+    gal = sorted(set(c.cp_galois(L, d_in, WQp.shape[1])) | set(c.cc_galois(heads, L, d_head)))
+    k = orc.Keys(c, 7, gal)
+    level, scale = 5, 2.0 ** 40
+    xc = np.stack([k.encrypt(c.encode_rns(c.pack_spatial(X, a), scale, level), level, 100, a) for a in range(g["n_in"])])
+    Qc = k.matmul_cp(xc, level, WQp, L)
+    Kc = k.matmul_cp(xc, level, WKp, L)
+    O = k.matmul_cc(Qc, Kc, level - 1, heads, L, d_head, b_prerotated=False)
+    out_scale = scale * 1024.0 * scale / float(c.q[level - 3])
+    geo = c.cc_geometry(heads, L, d_head)
+    lp, cg = geo["Lp"], geo["c"]
+    Qm, Km = X @ WQ, X @ WK
+    for gi in range(geo["n_out"]):
+        v = c.decode(k.decrypt(O[gi], 0), 0, out_scale)
+        for h in range(heads):
+            ref = Qm[:, h * d_head:(h + 1) * d_head] @ Km[:, h * d_head:(h + 1) * d_head].T
+            for kap in range(cg):
+                D = gi * cg + kap
+                i = np.arange(L)
+                got = v[i + lp * (h + heads * kap)]
+                assert np.abs(got - ref[i, (i + D) % lp]).max() < 2.0 ** -14
