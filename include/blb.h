@@ -190,6 +190,18 @@ int blb_plan_cc_info(const blb_plan* plan, int32_t* info, int cap);
 int blb_matmul_cc(blb_ctx* ctx, const blb_keys* keys, const blb_plan* plan, const blb_ct* A, const blb_ct* Bp, int n_ct,
                   blb_ct* C_diag, int n_out);
 
+/* ---- matmul_cp feeding matmul_cc (Multi-Head Optimization; Section "Efficient Fused
+ * Computations in Multi-Head Attention": the columns of W_Q / W_K reordered in plaintext) --------
+ * A matmul_cp plan for W (host, d_in x (n_heads d_head) row-major, head h owning columns
+ * h d_head .. (h+1) d_head - 1) whose spatial-first outputs ARE the ct-ct operands in the multi-head
+ * packing above (head groups concatenated): output b = operand ciphertext b holds, for its group
+ * of H heads from h0 with c_g = (N/2) / (L' H), column a c_g + kappa of (X W)_{h0+h} at block
+ * h + H kappa (a = b minus the group's first ciphertext; 0 past d_head).  Run it with blb_matmul_cp:
+ * X W_Q' gives the A operand, X W_K' the B operand before step 1 (b_prerotated = 0).  The plan
+ * has n_out = the ct-ct plan's n_ct and the cost of a plain matmul_cp with that many outputs.
+ * EINVAL for a geometry the ct-ct packing cannot hold (c_g > L'). */
+int blb_plan_matmul_cp_mhp(blb_ctx* ctx, const double* W, int d_in, int n_heads, int d_head, int L, int level, blb_plan** out);
+
 /* ---- Softmax x V_h with zero padding (Section "Efficient Fused Computations in Multi-Head
  * Attention"; Appendix "Diagonal Ciphertext-Plaintext MatMul", figure diag (b)) -----------
  * The same protocol (run with blb_matmul_cc) with A_h = the L x L attention weights

@@ -80,6 +80,8 @@ _SIGS = {
     "blb_cc_rotations": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int]),
     "blb_plan_matmul_cc": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int32, C.POINTER(C.c_void_p)]),
     "blb_plan_matmul_cc_sv": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int32, C.POINTER(C.c_void_p)]),
+    "blb_plan_matmul_cp_mhp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                         C.POINTER(C.c_void_p)]),
     "blb_plan_matmul_cp_diag": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                           C.POINTER(C.c_void_p)]),
     "blb_plan_cc_info": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
@@ -329,6 +331,16 @@ def blb_plan_matmul_cc(ctx, n_heads, L, d_head, level, b_prerotated=True):
 def blb_plan_matmul_cc_sv(ctx, n_heads, L, d_v, level, b_prerotated=True):
     out = C.c_void_p()
     _check(lib().blb_plan_matmul_cc_sv(ctx, n_heads, L, d_v, level, 1 if b_prerotated else 0, C.byref(out)), "blb_plan_matmul_cc_sv")
+    return out.value
+
+
+def blb_plan_matmul_cp_mhp(ctx, W: np.ndarray, n_heads, d_head, L, level):
+    Wc = np.ascontiguousarray(W, dtype=np.float64)
+    if Wc.shape[1] != n_heads * d_head:
+        raise BlbError(BLB_EINVAL, "blb_plan_matmul_cp_mhp")
+    out = C.c_void_p()
+    _check(lib().blb_plan_matmul_cp_mhp(ctx, _host_ptr(Wc), Wc.shape[0], n_heads, d_head, L, level, C.byref(out)),
+           "blb_plan_matmul_cp_mhp")
     return out.value
 
 

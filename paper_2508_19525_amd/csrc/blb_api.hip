@@ -1348,6 +1348,33 @@ int blb_plan_matmul_cp(blb_ctx* c, const double* W, int d_in, int d_out, int L, 
   return cp_plan_create(c, W, d_in, d_out, L, level, nullptr, out, nullptr, nullptr);
 }
 
+int blb_plan_matmul_cp_mhp(blb_ctx* c, const double* W, int d_in, int n_heads, int d_head, int L, int level, blb_plan** out) {
+  if (!c || !W || !out || d_in < 1 || n_heads < 1 || d_head < 1 || L < 1 || L > c->n / 2) return BLB_EINVAL;
+  *out = nullptr;
+  // output ciphertext b of the plan is operand ciphertext b of the ct-ct product: block u holds
+  // column a c_g + u / H of head h0 + (u mod H) for the group (H heads from h0) that b belongs to
+  const int S = c->n / 2, lp = 1 << ceil_log2(L), cc = S / lp;
+  std::vector<int> gs;
+  cc_group_sizes(n_heads, gs);
+  std::vector<int> src;  // W column for each reordered column, -1 for a zero column
+  int h0 = 0;
+  for (int H : gs) {
+    if (S % (lp * H) || S / (lp * H) > lp) return BLB_EINVAL;
+    const int cg = S / (lp * H), nct = (d_head + cg - 1) / cg;
+    for (int a = 0; a < nct; ++a)
+      for (int u = 0; u < cc; ++u) {
+        const int col = a * cg + u / H;
+        src.push_back(col < d_head ? (h0 + u % H) * d_head + col : -1);
+      }
+    h0 += H;
+  }
+  const int n_cols = (int)src.size(), w_cols = n_heads * d_head;
+  std::vector<double> Wp((size_t)d_in * n_cols);
+  for (int r = 0; r < d_in; ++r)
+    for (int j = 0; j < n_cols; ++j) Wp[(size_t)r * n_cols + j] = src[j] < 0 ? 0.0 : W[(size_t)r * w_cols + src[j]];
+  return cp_plan_create(c, Wp.data(), d_in, n_cols, L, level, nullptr, out, nullptr, nullptr);
+}
+
 int blb_plan_matmul_cp_diag(blb_ctx* c, const double* W, int n_heads, int d_v, int d_out, int L, int level, blb_plan** out) {
   if (n_heads < 1 || d_v < 1) return BLB_EINVAL;
   return cp_plan_create(c, W, n_heads * d_v, d_out, L, level, nullptr, out, nullptr, nullptr, n_heads, d_v);

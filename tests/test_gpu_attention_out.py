@@ -274,3 +274,114 @@ def test_attention_output_pipeline_eager_and_graph(c16p5):
     B.blb_plan_destroy(plan)
     B.blb_plan_destroy(r["plan"])
     B.blb_keys_destroy(r["keys_g"])
+
+
+# --------------------------------------------------------------------------------------
+# matmul_cp with W_Q / W_K columns reordered for the multi-head packing, and Q_h K_h^T from X
+# --------------------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def c16p6(blb, orc):
+    """N = 16384, six primes + two special (dnum 3): matmul_cp, then the ct-ct product with step 1
+    on the server"""
+    x = Ctx(blb, orc, 14, 6, 2, 3)
+    yield x
+    x.close()
+
+
+def _cp_keys(c, L, d_in, d_out):
+    g = c.o.cp_geometry(L, d_in, d_out)
+    return g, [i * g["Lp"] for i in range(1, g["B"])] + [j * g["B"] * g["Lp"] for j in range(1, g["G"])]
+
+
+def test_cp_mhp_matches_oracle(c8):
+    """The reordered-column plan word for word against the oracle's matmul_cp on the oracle's own
+    reordering of W (12 heads = 8 + 4, ragged operand ciphertexts), decoded against the multi-head
+    packing of X W."""
+    from paper_2508_19525_amd import workloads as wl
+    c, B = c8, c8.B
+    heads, L, d_in, d_head, level = 12, 64, 96, 16, 2
+    rng = np.random.default_rng(12)
+    X = rng.uniform(-1, 1, (L, d_in))
+    W = rng.normal(0, 0.05, (d_in, heads * d_head))
+    Wp = c.o.mhp_weight(W, heads, d_head, L)
+    g, steps = _cp_keys(c, L, d_in, Wp.shape[1])
+    plan = B.blb_plan_matmul_cp_mhp(c.h, W, heads, d_head, L, level)
+    assert B.blb_plan_info(plan) == g
+    keys_o = c.orc.Keys(c.o, 45, c.o.cp_galois(L, d_in, Wp.shape[1]))
+    keys_g = B.blb_keygen(c.h, 45, steps)
+    scale = 2.0 ** 30
+    xw = np.stack([keys_o.encrypt(c.o.encode_rns(c.o.pack_spatial(X, a), scale, level), level, 120, a) for a in range(g["n_in"])])
+    Xc = [c.import_ct(w, level, scale) for w in xw]
+    Y = [c.ct(level - 1) for _ in range(g["n_out"])]
+    B.blb_matmul_cp(c.h, keys_g, plan, Xc, Y)
+    want = keys_o.matmul_cp(xw, level, Wp, L)
+    for b in range(g["n_out"]):
+        assert np.array_equal(c.export(Y[b]), want[b]), f"output {b}"
+    Ym, h0, b = X @ W, 0, 0
+    for H in wl.head_groups(heads):
+        mats = [Ym[:, (h0 + h) * d_head:(h0 + h + 1) * d_head] for h in range(H)]
+        cg = c.n // 2 // (g["Lp"] * H)
+        for a in range(-(-d_head // cg)):
+            v = c.decode(keys_g, Y[b])
+            assert np.abs(v - wl.pack_mhp(mats, H, L, d_head, a, "A", c.n // 2)).max() < 2.0 ** -10
+            b += 1
+        h0 += H
+    B.blb_plan_destroy(plan)
+    B.blb_keys_destroy(keys_g)
+
+
+def test_fused_qk_from_x_matches_oracle(c16p6):
+    """X -> Q = X W_Q', K = X W_K' -> ct-ct product with step 1 on the server (N = 16384, six
+    primes, 12 heads): the two reordered-column products and one sampled diagonal output of each
+    head group equal the oracle's composition word for word; every head decodes to Q_h K_h^T."""
+    from paper_2508_19525_amd import workloads as wl
+    c, B = c16p6, c16p6.B
+    heads, L, d_in, d_head, level = 12, 64, 64, 32, 5
+    rng = np.random.default_rng(13)
+    X = rng.normal(0, 1, (L, d_in))
+    WQ = rng.normal(0, 0.15, (d_in, heads * d_head))
+    WK = rng.normal(0, 0.15, (d_in, heads * d_head))
+    WQp, WKp = c.o.mhp_weight(WQ, heads, d_head, L), c.o.mhp_weight(WK, heads, d_head, L)
+    g, cp_steps = _cp_keys(c, L, d_in, WQp.shape[1])
+    steps = list(B.blb_cc_rotations(c.h, heads, L)) + cp_steps
+    keys_o = c.orc.Keys(c.o, 47, sorted({c.o.galois_elt(s) for s in steps}))
+    keys_g = B.blb_keygen(c.h, 47, steps)
+    scale = 2.0 ** 40
+    xw = np.stack([keys_o.encrypt(c.o.encode_rns(c.o.pack_spatial(X, a), scale, level), level, 130, a) for a in range(g["n_in"])])
+    Xc = [c.import_ct(w, level, scale) for w in xw]
+    pq = B.blb_plan_matmul_cp_mhp(c.h, WQ, heads, d_head, L, level)
+    pk = B.blb_plan_matmul_cp_mhp(c.h, WK, heads, d_head, L, level)
+    pcc = B.blb_plan_matmul_cc(c.h, heads, L, d_head, level - 1, b_prerotated=False)
+    info = B.blb_plan_cc_info(pcc)
+    assert info["n_ct"] == g["n_out"]
+    Qc = [c.ct(level - 1) for _ in range(g["n_out"])]
+    Kc = [c.ct(level - 1) for _ in range(g["n_out"])]
+    B.blb_matmul_cp(c.h, keys_g, pq, Xc, Qc)
+    B.blb_matmul_cp(c.h, keys_g, pk, Xc, Kc)
+    Cd = [c.ct(level - 5) for _ in range(info["n_out"])]
+    B.blb_matmul_cc(c.h, keys_g, pcc, Qc, Kc, Cd)
+    Qw, Kw = keys_o.matmul_cp(xw, level, WQp, L), keys_o.matmul_cp(xw, level, WKp, L)
+    for b in range(g["n_out"]):
+        assert np.array_equal(c.export(Qc[b]), Qw[b]), f"Q ct {b}"
+        assert np.array_equal(c.export(Kc[b]), Kw[b]), f"K ct {b}"
+    base, sample = 0, 1
+    for grp in info["groups"]:
+        sl = slice(grp["ct0"], grp["ct0"] + grp["n_ct"])
+        want = keys_o.matmul_cc(Qw[sl], Kw[sl], level - 1, grp["H"], L, d_head, outputs=[sample], b_prerotated=False)
+        assert np.array_equal(c.export(Cd[base + sample]), want[sample]), f"group H={grp['H']}"
+        base += grp["n_out"]
+    Qm, Km = X @ WQ, X @ WK
+    h0, base, err = 0, 0, 0.0
+    for grp in info["groups"]:
+        vecs = [c.decode(keys_g, Cd[base + o]) for o in range(grp["n_out"])]
+        Cs = wl.unpack_diag(vecs, grp["H"], L, c.n // 2)
+        for h in range(grp["H"]):
+            hh = h0 + h
+            ref = Qm[:, hh * d_head:(hh + 1) * d_head] @ Km[:, hh * d_head:(hh + 1) * d_head].T
+            err = max(err, float(np.abs(Cs[h] - ref).max()))
+        h0 += grp["H"]
+        base += grp["n_out"]
+    assert err < 2.0 ** -18
+    for p in (pq, pk, pcc):
+        B.blb_plan_destroy(p)
+    B.blb_keys_destroy(keys_g)
