@@ -396,6 +396,115 @@ def run_attn_out(args, B, torch):
     return res
 
 
+def run_qk_fused(args, B, torch):
+    """Fused Q_h K_h^T from X (BERT-base shape): Enc(X 128x768) times W_Q and W_K (768x768, columns
+    reordered so matmul_cp emits the multi-head packing), the 12-head ct-ct product with step 1 on
+    the server, and mask-to-share of the diagonal-packed output; N = 16384, 6 primes + 2 special."""
+    from paper_2508_19525_amd import workloads as wl
+
+    cfg = wl.C7
+    p = cfg["params"]
+    heads, L, D, d = cfg["heads"], cfg["L"], cfg["d_model"], cfg["d_head"]
+    n, level, slots = p.n, p.n_q - 1, p.n // 2
+    X = wl.activations(7, L, D, "normal")
+    WQ = wl.weights(7, D, heads * d, cfg["w_std"])
+    WK = wl.batch_weights(D, cfg["w_std"], config=7)
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = B.blb_ctx_create(p.log_n, p.n_q, p.n_special, p.dnum, 0, stream)
+    t_setup = time.time()
+    pq = B.blb_plan_matmul_cp_mhp(ctx, WQ, heads, d, L, level)
+    pk = B.blb_plan_matmul_cp_mhp(ctx, WK, heads, d, L, level)
+    g = B.blb_plan_info(pq)
+    pcc = B.blb_plan_matmul_cc(ctx, heads, L, d, level - 1, b_prerotated=False)
+    info = B.blb_plan_cc_info(pcc)
+    steps_rot = list(B.blb_cc_rotations(ctx, heads, L)) + [i * g["Lp"] for i in range(1, g["B"])] + \
+        [j * g["B"] * g["Lp"] for j in range(1, g["G"])]
+    keys = B.blb_keygen(ctx, wl.seed_for(7, wl.ROLE_KEYS), steps_rot)
+    keep = []
+
+    def cts(k, lv):
+        out = []
+        for _ in range(k):
+            ct, t = B.new_ct(n, lv)
+            keep.append(t)
+            out.append(ct)
+        return out
+
+    pt = torch.empty((level + 1) * n, dtype=torch.int64, device="cuda")
+    Xc = cts(g["n_in"], level)
+    for a, ct in enumerate(Xc):
+        B.blb_encode(ctx, wl.pack_spatial(X, slots, a), p.scale, level, pt)
+        B.blb_encrypt(ctx, keys, pt, level, p.scale, wl.seed_for(7, wl.ROLE_ENC), a, ct)
+    Qc, Kc = cts(g["n_out"], level - 1), cts(g["n_out"], level - 1)
+    Cd = cts(info["n_out"], level - 5)
+    share = torch.zeros(info["n_out"] * n, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    log(f"fused QK setup {time.time() - t_setup:.1f}s: {len(steps_rot)} rotation keys, W_Q/W_K plans {g}, ct-ct plan {info}, "
+        f"device bytes {B.blb_ctx_device_bytes(ctx) / 1e9:.2f} GB")
+
+    def eager_step(seed):
+        B.blb_matmul_cp(ctx, keys, pq, Xc, Qc)
+        B.blb_matmul_cp(ctx, keys, pk, Xc, Kc)
+        B.blb_matmul_cc(ctx, keys, pcc, Qc, Kc, Cd)
+        B.blb_mask_to_share(ctx, Cd, seed, 0, share)
+
+    B.blb_matmul_cp(ctx, keys, pq, Xc, Qc)
+    B.blb_matmul_cp(ctx, keys, pk, Xc, Kc)
+    B.blb_matmul_cc(ctx, keys, pcc, Qc, Kc, Cd)
+    dec = torch.empty(n, dtype=torch.int64, device="cuda")
+    Qm, Km = X @ WQ, X @ WK
+    err, h0, base = 0.0, 0, 0
+    for grp in info["groups"]:
+        vecs = []
+        for o in range(grp["n_out"]):
+            B.blb_decrypt(ctx, keys, Cd[base + o], dec)
+            vecs.append(B.blb_decode(ctx, dec, 0, Cd[base + o].scale, slots))
+        Cs = wl.unpack_diag(vecs, grp["H"], L, slots)
+        for h in range(grp["H"]):
+            hh = h0 + h
+            ref = Qm[:, hh * d:(hh + 1) * d] @ Km[:, hh * d:(hh + 1) * d].T
+            err = max(err, float(np.abs(Cs[h] - ref).max()))
+        h0 += grp["H"]
+        base += grp["n_out"]
+    log(f"fused QK decoded max abs err {err:.3e}")
+    eager_step(1)
+    torch.cuda.synchronize()
+    B.blb_ctx_set_timing(ctx, True)
+    B.blb_ctx_reset_timing(ctx)
+    steps = max(1, args.steps // 4)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        eager_step(k + 2)
+    torch.cuda.synchronize()
+    dt_eager = time.perf_counter() - t0
+    split = {}
+    for name, kind in [("ntt", B.BLB_T_NTT), ("ks_inner", B.BLB_T_KS_INNER), ("modup", B.BLB_T_MODUP), ("moddown_conv", B.BLB_T_MODDOWN),
+                       ("tensor", B.BLB_T_CC_TENSOR), ("cp_mac", B.BLB_T_CP_MAC), ("masks_ew", B.BLB_T_EW)]:
+        split[name] = B.blb_ctx_read_timing(ctx, kind)[0] / steps
+    B.blb_ctx_set_timing(ctx, False)
+    ex = [B.blb_exec_create_cp(ctx, keys, pq, Xc, Qc), B.blb_exec_create_cp(ctx, keys, pk, Xc, Kc),
+          B.blb_exec_create_cc(ctx, keys, pcc, Qc, Kc, Cd, 0, share)]
+    for e in ex:
+        B.blb_exec_run(e, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        for e in ex:
+            B.blb_exec_run(e, k + 2)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"fused QK: eager {steps / dt_eager:.1f}/s, graph {steps / dt:.1f}/s")
+    res = {"value": steps / dt, "eager": steps / dt_eager, "ms": dt / steps * 1e3, "err": err, "split_ms": split,
+           "rotation_keys": len(steps_rot), "wq_geometry": g, "groups": info["groups"]}
+    for e in ex:
+        B.blb_exec_destroy(e)
+    for pl in (pq, pk, pcc):
+        B.blb_plan_destroy(pl)
+    B.blb_keys_destroy(keys)
+    B.blb_ctx_destroy(ctx)
+    return res
+
+
 FP64_LANE_OPS = 256 * 2.4e9 * 64  # FP64 vector lane-ops/s (78.6 TFLOP/s counting an FMA as 2)
 NTT_OPS_PER_BUTTERFLY = 8  # 6 for the error-free modular product, 1 add, 1 subtract
 
@@ -722,6 +831,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cc", action="store_true", help="skip the matmul_cc measurement")
     ap.add_argument("--no-attn-out", action="store_true", help="skip the attention-output (Softmax x V, W_O) measurement")
+    ap.add_argument("--no-qk-fused", action="store_true", help="skip the fused Q K^T-from-X measurement")
     ap.add_argument("--no-tune", action="store_true", help="skip the MAC launch-shape autotuner")
     ap.add_argument("--mac-variant", type=int, default=None, help="use this MAC launch shape instead of autotuning")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched measurement")
@@ -746,13 +856,14 @@ def main():
     if args.ntt_only:  # diagnostic mode: the standalone NTT measurement alone
         print(json.dumps({"ntt_standalone_1GiB": run_ntt(args, B, torch)}))
         return
-    if args.attn_out_only:  # diagnostic mode: the attention-output measurement alone
-        print(json.dumps({"attention_output": run_attn_out(args, B, torch)}))
+    if args.attn_out_only:  # diagnostic mode: the attention operators alone
+        print(json.dumps({"attention_output": run_attn_out(args, B, torch), "qk_fused_from_x": run_qk_fused(args, B, torch)}))
         return
     r = run_cp(args, B, torch)
     nt = None if args.no_ntt else run_ntt(args, B, torch)
     cc = None if args.no_cc else run_cc(args, B, torch)
     ao = None if args.no_attn_out else run_attn_out(args, B, torch)
+    qk = None if args.no_qk_fused else run_qk_fused(args, B, torch)
     args.tuned_mac_variant = r["mac_variant"]  # the per-instance (unbatched) path uses the tuned MAC shape too
     bt = None if args.no_batch else run_batch(args, B, torch)
     sv = None if args.no_serve else run_serving(args, B, torch)
@@ -802,6 +913,12 @@ def main():
                       "Concat(Att_h) W_O 768x768 on the diagonal packing; mask-to-share of 12 cts; N=16384, 5 primes + 2 special)",
             "value": ao["value"], "eager_value": ao["eager"], "ms": ao["ms"], "max_abs_err": ao["err"], "split_ms": ao["split_ms"],
             "rotation_keys": ao["rotation_keys"]},
+        "qk_fused_from_x": None if qk is None else {
+            "metric": "fused Q_h K_h^T-from-X ops/s (Enc(X 128x768) x W_Q, W_K 768x768 with columns reordered for the "
+                      "multi-head packing; 12-head ct-ct product with step 1 on the server; mask-to-share; N=16384, "
+                      "6 primes + 2 special)",
+            "value": qk["value"], "eager_value": qk["eager"], "ms": qk["ms"], "max_abs_err": qk["err"], "split_ms": qk["split_ms"],
+            "rotation_keys": qk["rotation_keys"]},
         "batched": None if bt is None else dict(
             bt, workload="64 independent matmul_cp instances, L ~ U{16..512}, hidden 768/1024 (W shared per hidden size), "
                          "N=8192, 3 primes; per-instance eager calls vs batched stages vs one graph launch"),

@@ -47,6 +47,10 @@ C3 = dict(params=Params(14, 4, 2, 2, 40), heads=12, L=128, d_head=64)
 # columns) and Concat(Att_h) W_O (768 x 768) on the dense diagonal packing; N=16384, 5 x 50-bit
 # primes (three levels for the ct-ct product, one for the ct-pt product) + 2 special (dnum 3)
 C6 = dict(params=Params(14, 5, 2, 3, 40), heads=12, L=128, d_v=64, d_out=768, w_std=0.02)
+# C7: fused Q_h K_h^T from X -- X 128 x 768, W_Q and W_K 768 x 768 with columns reordered for the
+# multi-head packing, then the ct-ct product with step 1 on the server; N=16384, 6 x 50-bit primes
+# (one level for matmul_cp, four for the ct-ct product) + 2 special (dnum 3)
+C7 = dict(params=Params(14, 6, 2, 3, 40), heads=12, L=128, d_model=768, d_head=64, w_std=0.02)
 
 
 def activations(config: int, L: int, d: int, dist: str) -> np.ndarray:
