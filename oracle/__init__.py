@@ -87,6 +87,7 @@ def lib():
             "orc_matmul_cp": (C.c_int, [vp, _u64p, C.c_int, _f64p, C.c_int, C.c_int, C.c_int, C.c_void_p, _u64p]),
             "orc_cp_galois": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, _u64p]),
             "orc_mask_to_share": (None, [vp, _u64p, C.c_int, C.c_int, C.c_uint64, C.c_uint32, _u64p, _u64p]),
+            "orc_add_share": (None, [vp, _u64p, C.c_int, _u64p, _u64p]),
             "orc_num_threads": (C.c_int, []),
             "orc_cc_geometry": (None, [vp, C.c_int, C.c_int, C.c_int, _i32p]),
             "orc_rerandomize": (C.c_int, [vp, _u64p, C.c_int, C.c_uint64, C.c_uint32, C.c_int, _u64p]),
@@ -300,6 +301,12 @@ class Context:
                         j = (i + kap) % lp
                         v[base + i] = mats[h][k, j] if j < mats[h].shape[1] else 0.0
         return v
+
+    def add_share(self, ct, level: int, share) -> np.ndarray:
+        """(c0 + share, c1) mod q_i: the server's step of the MPC-to-CKKS conversion"""
+        out = np.zeros((2, level + 1, self.n), np.uint64)
+        lib().orc_add_share(self._p, _c(ct, np.uint64), level, _c(share, np.uint64), out)
+        return out
 
     def mask_to_share(self, ct, level: int, target_level: int, seed: int, ct_id: int):
         masked = np.zeros((2, target_level + 1, self.n), np.uint64)

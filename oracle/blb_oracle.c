@@ -23,7 +23,8 @@
  *   - Softmax x V_h with zero padding and the dense diagonal packing, and the matmul_cp variant
  *     with diagonal-packed input for Concat(Att_h) W_O ("Efficient Fused Computations in
  *     Multi-Head Attention"; Appendix "Diagonal Ciphertext-Plaintext MatMul").
- *   - CKKS-to-MPC mask-and-share, step 1 of Algorithm ckks2mpc and F_C2M.
+ *   - CKKS-to-MPC mask-and-share, step 1 of Algorithm ckks2mpc and F_C2M; the server's
+ *     homomorphic addition of its share in Algorithm mpc2ckks.
  * Where the paper is silent (primes, randomness, key switching variant, schedules) the
  * readings are documented with the function that implements them.
  */
@@ -964,6 +965,23 @@ void orc_mask_to_share(const orc_ctx* c, const uint64_t* ct, int level, int targ
       masked[(size_t)i * n + k] = addm(ct[(size_t)i * n + k], r, q);
       masked[((size_t)tl + i) * n + k] = ct[((size_t)nl + i) * n + k];
       share[(size_t)i * n + k] = (q - r) % q;
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* MPC-to-CKKS, the server's step (Algorithm mpc2ckks, last step)                          */
+/* ------------------------------------------------------------------------------------ */
+/* The client encrypts its field share tmp_0 and the server adds its own share tmp_1 (a ring
+ * element mod Q_level in coefficient form, one residue per limb in [0, q_i)) as a plaintext:
+ * out = (c0 + tmp_1, c1) mod q_i.  ct, out: [2][level+1][N]; share: [level+1][N]. */
+void orc_add_share(const orc_ctx* c, const uint64_t* ct, int level, const uint64_t* share, uint64_t* out) {
+  int n = c->n, nl = level + 1;
+  for (int i = 0; i < nl; ++i) {
+    uint64_t q = c->mod[i];
+    for (int k = 0; k < n; ++k) {
+      out[(size_t)i * n + k] = addm(ct[(size_t)i * n + k], share[(size_t)i * n + k] % q, q);
+      out[((size_t)nl + i) * n + k] = ct[((size_t)nl + i) * n + k];
     }
   }
 }

@@ -497,6 +497,32 @@ def test_mask_to_share_identity_and_uniformity(orc):
             assert chi2 < 45.0
 
 
+def test_mpc_to_ckks_server_addition(orc):
+    """Algorithm mpc2ckks, the server's step: Enc(tmp_0) + tmp_1 decrypts to Dec(Enc(tmp_0)) + tmp_1
+    in every limb (a big-integer CRT check), decodes to x when tmp_0 + tmp_1 = Encode(x) mod Q, and
+    undoes mask-to-share word for word (masked ciphertext plus the share -r is the original)."""
+    c = orc.Context(12, 3, 1, 3)
+    k = orc.Keys(c, 4)
+    rng = np.random.default_rng(9)
+    x = rng.normal(0, 1, c.slots)
+    level, scale = 2, 2.0 ** 40
+    pt = c.encode_rns(x, scale, level)
+    # additive shares of the encoded message over Z_Q: tmp_1 uniform per limb, tmp_0 = pt - tmp_1
+    tmp1 = np.stack([orc.sample_uniform(123, i, 0, orc.TAG_MASK, int(c.q[i]), c.n) for i in range(level + 1)])
+    tmp0 = np.stack([((pt[i].astype(object) - tmp1[i].astype(object)) % int(c.q[i])).astype(np.uint64) for i in range(level + 1)])
+    ct0 = k.encrypt(tmp0, level, 6, 0)
+    ct = c.add_share(ct0, level, tmp1)
+    d, d0 = k.decrypt(ct, level), k.decrypt(ct0, level)
+    for i in range(level + 1):
+        q = int(c.q[i])
+        assert np.array_equal(d[i].astype(object), (d0[i].astype(object) + tmp1[i].astype(object)) % q)
+    assert np.abs(c.decode(d, level, scale) - x).max() < 2.0 ** -20
+    # round trip with the CKKS-to-MPC step
+    ctx_ = k.encrypt(pt, level, 7, 1)
+    masked, share = c.mask_to_share(ctx_, level, level, 55, 2)
+    assert np.array_equal(c.add_share(masked, level, share), ctx_)
+
+
 @pytest.mark.parametrize("bits", [32, 40])
 def test_rerandomize_adds_flooded_encryption_of_zero(orc, bits):
     """Dec(rerand(ct)) - Dec(ct) = v e_pk + e0 + e1 s, the same integer in every limb (CRT
