@@ -246,6 +246,15 @@ int blb_rerandomize(blb_ctx* ctx, const blb_keys* keys, blb_ct* cts, int n_ct, u
  * server share -r mod q_i in coefficient form to share_dev[t][limb][N]. */
 int blb_mask_to_share(blb_ctx* ctx, blb_ct* cts, int n_ct, uint64_t seed, int target_level, uint64_t* share_dev);
 
+/* ---- MPC-to-CKKS, the server's step (Algorithm mpc2ckks: P_1 adds its share to the client's
+ * encryption of the other share) ---------------------------------------------------------------
+ * cts[t] = (c0 + share_t, c1) mod q_i in place, share_dev: device words [t][limb][N], the server's
+ * ring share of the encoded message in coefficient form, one residue per limb in [0, q_i)
+ * (canonical residues are the caller's contract: other words give unspecified, in-bounds results),
+ * at the ciphertexts' common level (ELEVEL if the levels differ).  Applied to the output of
+ * blb_mask_to_share with its share it restores the ciphertext word for word.  Stream-ordered. */
+int blb_add_share(blb_ctx* ctx, blb_ct* cts, int n_ct, const uint64_t* share_dev);
+
 /* ---- batched matmul_cp over independent instances ------------------------------------
  * Each instance has its own keys (its client), plan (plans may be shared between instances
  * with the same weights and L'), inputs and outputs; all plans must be at one level.  Every

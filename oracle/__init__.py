@@ -88,6 +88,7 @@ def lib():
             "orc_cp_galois": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, _u64p]),
             "orc_mask_to_share": (None, [vp, _u64p, C.c_int, C.c_int, C.c_uint64, C.c_uint32, _u64p, _u64p]),
             "orc_add_share": (None, [vp, _u64p, C.c_int, _u64p, _u64p]),
+            "orc_rotate_sum": (C.c_int, [vp, _u64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _u64p]),
             "orc_num_threads": (C.c_int, []),
             "orc_cc_geometry": (None, [vp, C.c_int, C.c_int, C.c_int, _i32p]),
             "orc_rerandomize": (C.c_int, [vp, _u64p, C.c_int, C.c_uint64, C.c_uint32, C.c_int, _u64p]),
@@ -364,6 +365,20 @@ class Keys:
         out = np.zeros((2, level + 1, self.ctx.n), np.uint64)
         if lib().orc_relinearize(self._p, _c(ct3, np.uint64), level, out) != 0:
             raise KeyError("missing relinearisation key")
+        return out
+
+    def rotate_sum(self, ct, level: int, block: int, n_blocks: int, direction: int = 0, mask=None) -> np.ndarray:
+        """rotate-and-sum over n_blocks blocks of `block` slots: summation (direction 0, with the
+        first-block mask unless mask=False) or broadcast (direction 1, never masked)"""
+        if mask is None:
+            mask = direction == 0
+        lv = level - 1 if mask else level
+        out = np.zeros((2, lv + 1, self.ctx.n), np.uint64)
+        rc = lib().orc_rotate_sum(self._p, _c(ct, np.uint64), level, block, n_blocks, direction, 1 if mask else 0, out)
+        if rc == -1:
+            raise KeyError("missing Galois key")
+        if rc != 0:
+            raise ValueError("rotate_sum: bad arguments")
         return out
 
     def rerandomize(self, ct, level: int, seed: int, ct_id: int, flood_bits: int) -> np.ndarray:

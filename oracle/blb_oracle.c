@@ -23,6 +23,7 @@
  *   - Softmax x V_h with zero padding and the dense diagonal packing, and the matmul_cp variant
  *     with diagonal-packed input for Concat(Att_h) W_O ("Efficient Fused Computations in
  *     Multi-Head Attention"; Appendix "Diagonal Ciphertext-Plaintext MatMul").
+ *   - rotate-and-sum summation / broadcast ("Consistent Packing for Single Operator").
  *   - CKKS-to-MPC mask-and-share, step 1 of Algorithm ckks2mpc and F_C2M; the server's
  *     homomorphic addition of its share in Algorithm mpc2ckks.
  * Where the paper is silent (primes, randomness, key switching variant, schedules) the
@@ -967,6 +968,48 @@ void orc_mask_to_share(const orc_ctx* c, const uint64_t* ct, int level, int targ
       share[(size_t)i * n + k] = (q - r) % q;
     }
   }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Rotate-and-sum summation and broadcast (Section "Consistent Packing for Single Operator": */
+/* Expansion and Reduction operators)                                                      */
+/* ------------------------------------------------------------------------------------ */
+/* m^0 = m, m^i = m^{i-1} + Rot^{2^{i-1} block}(m^{i-1}) for i = 1 .. log2 n_blocks, with left
+ * rotations (direction 0: summation) or right rotations (direction 1: broadcast).  Summation then
+ * keeps the first `block` slots: mask [1 x block, 0, ...] encoded at scale q_level, product
+ * rescaled (output at level-1, the input scale kept); without the mask (mask = 0), or for a
+ * broadcast, the output is m^{log2 n_blocks} at the input level.  ct, out: [2][nl][N].
+ * Returns 0, -1 on a missing key, -3 on bad arguments. */
+static void mac_vec(const orc_ctx* c, uint64_t* acc, const double* vec, double delta, const uint64_t* ct, int level);
+
+int orc_rotate_sum(const orc_keys* K, const uint64_t* ct, int level, int block, int n_blocks, int direction, int mask, uint64_t* out) {
+  const orc_ctx* c = K->c;
+  int n = c->n, s = n / 2, nl = level + 1;
+  if (block < 1 || n_blocks < 1 || (n_blocks & (n_blocks - 1)) || (int64_t)block * n_blocks > s) return -3;
+  if (mask && (direction != 0 || level < 1)) return -3;
+  size_t w = (size_t)2 * nl * n;
+  uint64_t* cur = (uint64_t*)malloc(8 * w);
+  uint64_t* rot = (uint64_t*)malloc(8 * w);
+  memcpy(cur, ct, 8 * w);
+  int rc = 0;
+  for (int64_t step = block; step < (int64_t)block * n_blocks; step *= 2) {
+    if (orc_rotate(K, cur, level, direction == 0 ? step : -step, rot) != 0) { rc = -1; break; }
+    add_ct(c, cur, rot, nl, 2);
+  }
+  if (rc == 0) {
+    if (mask) {
+      double* v = (double*)malloc(8 * s);
+      for (int j = 0; j < s; ++j) v[j] = j < block ? 1.0 : 0.0;
+      uint64_t* acc = (uint64_t*)calloc(w, 8);
+      mac_vec(c, acc, v, (double)c->mod[level], cur, level);
+      orc_rescale(c, acc, level, 2, out);
+      free(acc); free(v);
+    } else {
+      memcpy(out, cur, 8 * w);
+    }
+  }
+  free(cur); free(rot);
+  return rc;
 }
 
 /* ------------------------------------------------------------------------------------ */

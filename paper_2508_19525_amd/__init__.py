@@ -79,6 +79,7 @@ _SIGS = {
     "blb_mask_to_share": (C.c_int, [C.c_void_p, C.POINTER(blb_ct), C.c_int, C.c_uint64, C.c_int, C.c_void_p]),
     "blb_cc_rotations": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int]),
     "blb_plan_matmul_cc": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int32, C.POINTER(C.c_void_p)]),
+    "blb_add_share": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "blb_plan_matmul_cc_sv": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int32, C.POINTER(C.c_void_p)]),
     "blb_plan_matmul_cp_mhp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                          C.POINTER(C.c_void_p)]),
@@ -306,6 +307,11 @@ def blb_mask_to_share(ctx, cts, seed, target_level, share_dev):
     _check(lib().blb_mask_to_share(ctx, arr, len(cts), seed, target_level, _ptr(share_dev)), "blb_mask_to_share")
     for i in range(len(cts)):
         cts[i].level = arr[i].level
+
+
+def blb_add_share(ctx, cts, share_dev):
+    arr = (blb_ct * len(cts))(*cts)
+    _check(lib().blb_add_share(ctx, arr, len(cts), _ptr(share_dev)), "blb_add_share")
 
 
 def blb_rerandomize(ctx, keys, cts, seed, flood_bits):

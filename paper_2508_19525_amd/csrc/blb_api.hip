@@ -1576,6 +1576,28 @@ int blb_mask_to_share(blb_ctx* c, blb_ct* cts, int n_ct, uint64_t seed, int targ
   return hipGetLastError() == hipSuccess ? BLB_OK : BLB_EDEVICE;
 }
 
+// c0 += NTT(share) for every ciphertext: the server's step of the MPC-to-CKKS conversion
+int blb_add_share(blb_ctx* c, blb_ct* cts, int n_ct, const uint64_t* share_dev) {
+  if (!c || !cts || n_ct < 1 || !share_dev) return BLB_EINVAL;
+  for (int t = 0; t < n_ct; ++t) {
+    if (check_ct(c, &cts[t]) || cts[t].degree != 1) return BLB_EINVAL;
+    if (cts[t].level != cts[0].level) return BLB_ELEVEL;
+  }
+  const int n = c->n, nl = cts[0].level + 1;
+  std::vector<PolyDesc> d;
+  for (int t = 0; t < n_ct; ++t)
+    for (int i = 0; i < nl; ++i) {
+      PolyDesc x = pd(share_dev + ((size_t)t * nl + i) * n, cts[t].data + (size_t)i * n, i, c->log_n);
+      x.src2 = cts[t].data + (size_t)i * n;
+      d.push_back(x);
+    }
+  {
+    Span sp(c, BLB_T_MASK, (double)n_ct * nl * n);
+    ntt_descs(c, d, NTT_ADDTO);
+  }
+  return hipGetLastError() == hipSuccess ? BLB_OK : BLB_EDEVICE;
+}
+
 }  // extern "C"
 
 // ==========================================================================================

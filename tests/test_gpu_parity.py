@@ -244,6 +244,28 @@ def test_mask_to_share_matches_oracle(request, name):
             assert np.array_equal(sh[t], want_share)
 
 
+@pytest.mark.parametrize("name", ["c1", "c2s", "c3s"])
+def test_add_share_matches_oracle(request, name):
+    """The server's step of the MPC-to-CKKS conversion word for word (shares uniform per limb),
+    and mask-to-share followed by it restores the ciphertexts exactly."""
+    c = request.getfixturevalue(name)
+    rng = np.random.default_rng(8)
+    keys_o = c.orc.Keys(c.o, 44)
+    level = c.n_q - 1
+    words = [keys_o.encrypt(c.o.encode_rns(rng.normal(0, 1, c.n // 2), 2.0 ** 30, level), level, 9, t) for t in range(3)]
+    sh = np.stack([np.stack([c.orc.sample_uniform(77, i, t, 6, int(c.o.q[i]), c.n) for i in range(level + 1)]) for t in range(3)])
+    cts = [c.import_ct(w, level) for w in words]
+    c.B.blb_add_share(c.h, cts, c.upload_words(sh))
+    for t in range(3):
+        assert np.array_equal(c.export(cts[t]), c.o.add_share(words[t], level, sh[t])), f"ct {t}"
+    cts = [c.import_ct(w, level) for w in words]
+    share = torch.zeros(3 * (level + 1) * c.n, dtype=torch.int64, device="cuda")
+    c.B.blb_mask_to_share(c.h, cts, 4321, level, share)
+    c.B.blb_add_share(c.h, cts, share)
+    for t in range(3):
+        assert np.array_equal(c.export(cts[t]), words[t]), f"round trip ct {t}"
+
+
 @pytest.mark.parametrize("name", ["c1", "c2s"])
 def test_rerandomize_matches_oracle(request, name):
     """Public-key re-randomisation with flooding (object id = position in the list), word for

@@ -906,3 +906,48 @@ def test_fused_qk_from_x(orc):
                 i = np.arange(L)
                 got = v[i + lp * (h + heads * kap)]
                 assert np.abs(got - ref[i, (i + D) % lp]).max() < 2.0 ** -14
+
+
+# --------------------------------------------------------------------------------------
+# Rotate-and-sum summation and broadcast; MPC-to-CKKS server step
+# --------------------------------------------------------------------------------------
+@pytest.mark.parametrize("block,n_blocks", [(32, 8), (16, 64)])
+def test_rotate_sum_closed_forms(orc, block, n_blocks):
+    """Summation: slot j < block holds sum_k m[j + k block] and every other slot 0 (the first-block
+    mask); without the mask, every slot j holds sum_k m[(j + k block) mod S] (at block x n_blocks = S
+    that is the row sum in every block: mask and broadcast can be skipped).  Broadcast of a vector
+    living in the first block fills the first n_blocks blocks with it.  Row sums of a spatial-first
+    X equal X.sum(axis=1)."""
+    c = orc.Context(12, 3, 1, 3)
+    S = c.slots
+    steps = []
+    st = block
+    while st < block * n_blocks:
+        steps += [st, -st]
+        st *= 2
+    k = orc.Keys(c, 5, sorted({c.galois_elt(x) for x in steps}))
+    rng = np.random.default_rng(block)
+    level, scale = 2, 2.0 ** 40
+    m = rng.uniform(-1, 1, S)
+    ct = k.encrypt(c.encode_rns(m, scale, level), level, 3, 0)
+    idx = np.arange(S)
+    cyc = sum(m[(idx + j * block) % S] for j in range(n_blocks))
+    got = c.decode(k.decrypt(k.rotate_sum(ct, level, block, n_blocks, 0, mask=True), level - 1), level - 1, scale)
+    want = np.where(idx < block, cyc, 0.0)
+    assert np.abs(got - want).max() < 2.0 ** -20
+    got = c.decode(k.decrypt(k.rotate_sum(ct, level, block, n_blocks, 0, mask=False), level), level, scale)
+    assert np.abs(got - cyc).max() < 2.0 ** -20
+    b0 = np.where(idx < block, m, 0.0)
+    ctb = k.encrypt(c.encode_rns(b0, scale, level), level, 4, 0)
+    got = c.decode(k.decrypt(k.rotate_sum(ctb, level, block, n_blocks, 1), level), level, scale)
+    assert np.abs(got - np.where(idx < block * n_blocks, b0[idx % block], 0.0)).max() < 2.0 ** -20
+    # row sums of a spatial-first L x D matrix (D = n_blocks columns, L' = block)
+    L = block - 3
+    X = rng.normal(0, 1, (L, n_blocks))
+    v = np.zeros(S)
+    for j in range(n_blocks):
+        v[j * block: j * block + L] = X[:, j]
+    ctx_ = k.encrypt(c.encode_rns(v, scale, level), level, 5, 0)
+    got = c.decode(k.decrypt(k.rotate_sum(ctx_, level, block, n_blocks, 0), level - 1), level - 1, scale)
+    assert np.abs(got[:L] - X.sum(axis=1)).max() < 2.0 ** -18
+    assert np.abs(got[L:]).max() < 2.0 ** -18
