@@ -255,6 +255,20 @@ int blb_mask_to_share(blb_ctx* ctx, blb_ct* cts, int n_ct, uint64_t seed, int ta
  * blb_mask_to_share with its share it restores the ciphertext word for word.  Stream-ordered. */
 int blb_add_share(blb_ctx* ctx, blb_ct* cts, int n_ct, const uint64_t* share_dev);
 
+/* ---- Rotate-and-sum summation and broadcast (Section "Consistent Packing for Single Operator":
+ * the Expansion and Reduction operators) -------------------------------------------------------
+ * Per ciphertext: m^0 = m, m^i = m^{i-1} + Rot^{2^{i-1} block}(m^{i-1}), i = 1 .. log2 n_blocks,
+ * with left rotations (direction 0, summation) or right rotations (direction 1, broadcast);
+ * n_blocks a power of two, block * n_blocks <= N/2.  Summation with mask = 1 then keeps the first
+ * `block` slots (mask [1 x block, 0, ...] encoded at q_level, product rescaled: out at level - 1 with
+ * the input scale); otherwise out = m^{log2 n_blocks} at the input level.  For a spatial-first
+ * matrix (block = L', n_blocks columns per ciphertext) summation gives the row sums in the first
+ * block; broadcast of a first-block vector replicates it over n_blocks blocks.  Keys: rotations
+ * by +-2^i block (ENOKEY otherwise); inputs at one level and scale; out[t] buffers of the input
+ * size, distinct from the inputs. */
+int blb_rotate_sum(blb_ctx* ctx, const blb_keys* keys, const blb_ct* in, int n_ct, int block, int n_blocks, int direction, int mask,
+                   blb_ct* out);
+
 /* ---- batched matmul_cp over independent instances ------------------------------------
  * Each instance has its own keys (its client), plan (plans may be shared between instances
  * with the same weights and L'), inputs and outputs; all plans must be at one level.  Every

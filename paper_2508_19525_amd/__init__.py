@@ -80,6 +80,7 @@ _SIGS = {
     "blb_cc_rotations": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int]),
     "blb_plan_matmul_cc": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int32, C.POINTER(C.c_void_p)]),
     "blb_add_share": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "blb_rotate_sum": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p]),
     "blb_plan_matmul_cc_sv": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int32, C.POINTER(C.c_void_p)]),
     "blb_plan_matmul_cp_mhp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                          C.POINTER(C.c_void_p)]),
@@ -312,6 +313,19 @@ def blb_mask_to_share(ctx, cts, seed, target_level, share_dev):
 def blb_add_share(ctx, cts, share_dev):
     arr = (blb_ct * len(cts))(*cts)
     _check(lib().blb_add_share(ctx, arr, len(cts), _ptr(share_dev)), "blb_add_share")
+
+
+def blb_rotate_sum(ctx, keys, in_cts, out_cts, block, n_blocks, direction=0, mask=None):
+    """rotate-and-sum summation (direction 0, first-block mask unless mask=False) or broadcast"""
+    if mask is None:
+        mask = direction == 0
+    ia = (blb_ct * len(in_cts))(*in_cts)
+    oa = (blb_ct * len(out_cts))(*out_cts)
+    if len(in_cts) != len(out_cts):
+        raise BlbError(BLB_EINVAL, "blb_rotate_sum")
+    _check(lib().blb_rotate_sum(ctx, keys, ia, len(in_cts), block, n_blocks, direction, 1 if mask else 0, oa), "blb_rotate_sum")
+    for i in range(len(out_cts)):
+        out_cts[i].level, out_cts[i].degree, out_cts[i].scale = oa[i].level, oa[i].degree, oa[i].scale
 
 
 def blb_rerandomize(ctx, keys, cts, seed, flood_bits):

@@ -2444,3 +2444,98 @@ int blb_exec_create_batch_cp(blb_ctx* c, const blb_cp_instance* inst, int n_inst
 }
 
 }  // extern "C"
+
+// ==========================================================================================
+// Rotate-and-sum summation and broadcast (Section "Consistent Packing for Single Operator":
+// Expansion and Reduction operators)
+// ==========================================================================================
+extern "C" {
+
+int blb_rotate_sum(blb_ctx* c, const blb_keys* K, const blb_ct* in, int n_ct, int block, int n_blocks, int direction, int mask,
+                   blb_ct* out) {
+  if (!c || !K || !in || !out || n_ct < 1 || block < 1 || n_blocks < 1 || (n_blocks & (n_blocks - 1))) return BLB_EINVAL;
+  if ((direction != 0 && direction != 1) || (mask != 0 && mask != 1) || (mask && direction != 0)) return BLB_EINVAL;
+  const int S = c->n / 2, n = c->n;
+  if ((int64_t)block * n_blocks > S) return BLB_EINVAL;
+  for (int t = 0; t < n_ct; ++t) {
+    if (check_ct(c, &in[t]) || in[t].degree != 1 || !out[t].data || in[t].level != in[0].level) return BLB_EINVAL;
+    if (fabs(in[t].scale / in[0].scale - 1.0) > 1e-9) return BLB_ESCALE;
+  }
+  const int level = in[0].level, nl = level + 1;
+  if (mask && level < 1) return BLB_ELEVEL;
+  std::vector<const SwKey*> keys;
+  std::vector<uint32_t> gals;
+  for (int64_t st = block; st < (int64_t)block * n_blocks; st *= 2) {
+    const uint32_t g = galois_left(c, direction == 0 ? st : -st);
+    const SwKey* k = find_key(K, g);
+    if (!k) return BLB_ENOKEY;
+    keys.push_back(k);
+    gals.push_back(g);
+  }
+  const size_t ctw = (size_t)2 * nl * n;
+  Tmp tmp(c);
+  uint64_t* cur = tmp.get<uint64_t>((size_t)n_ct * ctw);
+  uint64_t* rot = tmp.get<uint64_t>((size_t)n_ct * ctw);
+  uint64_t* mpt = mask ? tmp.get<uint64_t>((size_t)nl * n) : nullptr;
+  if (tmp.failed) return BLB_ENOMEM;
+  for (int t = 0; t < n_ct; ++t)
+    if (hipMemcpyAsync(cur + (size_t)t * ctw, in[t].data, ctw * 8, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) return BLB_EDEVICE;
+  int rc = BLB_OK;
+  // m^i = m^{i-1} + Rot^{2^{i-1} block}(m^{i-1}): one batch of n_ct key switches, then an add
+  for (size_t s = 0; s < keys.size(); ++s) {
+    std::vector<const uint64_t*> srcs;
+    std::vector<KsReq> reqs;
+    for (int t = 0; t < n_ct; ++t) {
+      const uint64_t* x = cur + (size_t)t * ctw;
+      srcs.push_back(x + (size_t)nl * n);
+      reqs.push_back(KsReq{t, keys[s], gals[s], rot + (size_t)t * ctw, x, gals[s], nullptr});
+    }
+    if ((rc = ks_batch(c, level, srcs, reqs))) return rc;
+    std::vector<const uint64_t*> terms;
+    std::vector<uint64_t*> dsts;
+    for (int t = 0; t < n_ct; ++t) {
+      terms.push_back(cur + (size_t)t * ctw);
+      terms.push_back(rot + (size_t)t * ctw);
+      dsts.push_back(cur + (size_t)t * ctw);
+    }
+    const uint64_t* const* t_dev = upload_vec(c, terms);
+    uint64_t* const* d_dev = (uint64_t* const*)upload(c, dsts.data(), dsts.size() * sizeof(uint64_t*));
+    if (!t_dev || !d_dev) return BLB_EDEVICE;
+    Span sp(c, BLB_T_EW, (double)n_ct * ctw);
+    launch_sum_cts(c, t_dev, d_dev, n_ct, 2, nl);
+  }
+  std::vector<const uint64_t*> rin;
+  std::vector<uint64_t*> rout;
+  for (int t = 0; t < n_ct; ++t) {
+    rin.push_back(cur + (size_t)t * ctw);
+    rout.push_back(out[t].data);
+  }
+  if (mask) {
+    // keep the first block: mask [1 x block, 0, ...] at scale q_level, then rescale
+    std::vector<double> v((size_t)S, 0.0);
+    for (int j = 0; j < block; ++j) v[j] = 1.0;
+    if ((rc = encode_vectors_ntt(c, v, 1, (double)c->mod[level], level, mpt))) return rc;
+    std::vector<CcPair> pairs;
+    for (int t = 0; t < n_ct; ++t) pairs.push_back(CcPair{cur + (size_t)t * ctw, mpt, nullptr, nullptr, cur + (size_t)t * ctw});
+    const CcPair* p_dev = upload_vec(c, pairs);
+    if (!p_dev) return BLB_EDEVICE;
+    {
+      Span sp(c, BLB_T_EW, (double)n_ct * ctw);
+      c->counters[2] += n_ct;
+      launch_mask_pair(c, p_dev, n_ct, nl);
+    }
+    if ((rc = rescale_batch(c, level, 2, rin, rout))) return rc;
+  } else {
+    for (int t = 0; t < n_ct; ++t)
+      if (hipMemcpyAsync(rout[t], rin[t], ctw * 8, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) return BLB_EDEVICE;
+  }
+  const double sc = in[0].scale;
+  for (int t = 0; t < n_ct; ++t) {
+    out[t].level = mask ? level - 1 : level;
+    out[t].degree = 1;
+    out[t].scale = sc;
+  }
+  return hipGetLastError() == hipSuccess ? BLB_OK : BLB_EDEVICE;
+}
+
+}  // extern "C"

@@ -266,6 +266,34 @@ def test_add_share_matches_oracle(request, name):
         assert np.array_equal(c.export(cts[t]), words[t]), f"round trip ct {t}"
 
 
+@pytest.mark.parametrize("name,block,n_blocks", [("c1", 32, 16), ("c2s", 64, 32), ("c2s", 128, 32)])
+def test_rotate_sum_matches_oracle(request, name, block, n_blocks):
+    """Rotate-and-sum word for word against the oracle on three ciphertexts: summation with the
+    first-block mask, without it, and broadcast (block x n_blocks below and equal to N/2)."""
+    c = request.getfixturevalue(name)
+    rng = np.random.default_rng(block + n_blocks)
+    steps, st = [], block
+    while st < block * n_blocks:
+        steps += [st, -st]
+        st *= 2
+    keys_o = c.orc.Keys(c.o, 46, sorted({c.o.galois_elt(x) for x in steps}))
+    keys_g = c.B.blb_keygen(c.h, 46, steps)
+    level = c.n_q - 1
+    words = [keys_o.encrypt(c.o.encode_rns(rng.uniform(-1, 1, c.n // 2), 2.0 ** 30, level), level, 12, t) for t in range(3)]
+    for direction, mask in ((0, True), (0, False), (1, False)):
+        cts = [c.import_ct(w, level) for w in words]
+        for x in cts:
+            x.scale = 2.0 ** 30
+        lv = level - 1 if mask else level
+        outs = [c.ct(lv) for _ in range(3)]
+        c.B.blb_rotate_sum(c.h, keys_g, cts, outs, block, n_blocks, direction, mask)
+        for t in range(3):
+            assert outs[t].level == lv
+            want = keys_o.rotate_sum(words[t], level, block, n_blocks, direction, mask)
+            assert np.array_equal(c.export(outs[t]), want), f"direction {direction} mask {mask} ct {t}"
+    c.B.blb_keys_destroy(keys_g)
+
+
 @pytest.mark.parametrize("name", ["c1", "c2s"])
 def test_rerandomize_matches_oracle(request, name):
     """Public-key re-randomisation with flooding (object id = position in the list), word for
