@@ -505,6 +505,76 @@ def run_qk_fused(args, B, torch):
     return res
 
 
+def run_small_ops(args, B, torch):
+    """Per-ciphertext operators around the matmuls on the BERT-base activation layout (24 ciphertexts
+    of a 128 x 768 spatial-first matrix, N = 8192, 3 primes + 1 special): rotate-and-sum row sums
+    (5 rotations + first-block mask + rescale) and broadcast (5 rotations), the server's share
+    addition of the MPC-to-CKKS conversion, and mask-to-share."""
+    from paper_2508_19525_amd import workloads as wl
+
+    cfg = wl.C2
+    p = cfg["params"]
+    n, level, slots = p.n, p.n_q - 1, p.n // 2
+    L, D = cfg["L"], cfg["d_in"]
+    lp = wl.lp_of(L)
+    nb = slots // lp
+    X = wl.activations(2, L, D, cfg["x_dist"])
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = B.blb_ctx_create(p.log_n, p.n_q, p.n_special, p.dnum, 0, stream)
+    steps_rot, st = [], lp
+    while st < lp * nb:
+        steps_rot += [st, -st]
+        st *= 2
+    keys = B.blb_keygen(ctx, wl.seed_for(2, wl.ROLE_KEYS), steps_rot)
+    keep = []
+
+    def cts(k, lv):
+        out = []
+        for _ in range(k):
+            ct, t = B.new_ct(n, lv)
+            keep.append(t)
+            out.append(ct)
+        return out
+
+    n_ct = D * lp // slots
+    Xc = cts(n_ct, level)
+    pt = torch.empty((level + 1) * n, dtype=torch.int64, device="cuda")
+    for a, ct in enumerate(Xc):
+        B.blb_encode(ctx, wl.pack_spatial(X, slots, a), p.scale, level, pt)
+        B.blb_encrypt(ctx, keys, pt, level, p.scale, wl.seed_for(2, wl.ROLE_ENC), a, ct)
+    Ysum, Ybc = cts(n_ct, level - 1), cts(n_ct, level)
+    share = torch.zeros(n_ct * (level + 1) * n, dtype=torch.int64, device="cuda")
+    # accuracy of the row sums: ciphertext a's first block holds sum over its 32 columns
+    B.blb_rotate_sum(ctx, keys, Xc, Ysum, lp, nb, 0)
+    dec = torch.empty(n, dtype=torch.int64, device="cuda")
+    err = 0.0
+    for a, y in enumerate(Ysum):
+        B.blb_decrypt(ctx, keys, y, dec)
+        v = B.blb_decode(ctx, dec, y.level, y.scale, slots)
+        err = max(err, float(np.abs(v[:L] - X[:, a * nb:(a + 1) * nb].sum(axis=1)).max()))
+    reps = max(4, args.steps)
+    res = {"n_ct": n_ct, "row_sum_max_abs_err": err}
+
+    def timed(name, fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        res[name + "_ms"] = (time.perf_counter() - t0) / reps * 1e3
+
+    timed("rotate_sum_rowsum", lambda: B.blb_rotate_sum(ctx, keys, Xc, Ysum, lp, nb, 0))
+    timed("rotate_sum_broadcast", lambda: B.blb_rotate_sum(ctx, keys, Xc, Ybc, lp, nb, 1))
+
+    timed("add_share", lambda: B.blb_add_share(ctx, Xc, share))  # after the timings that read Xc
+    timed("mask_to_share", lambda: B.blb_mask_to_share(ctx, Ybc, 7, level, share))
+    log(f"small ops on {n_ct} cts: {res}")
+    B.blb_keys_destroy(keys)
+    B.blb_ctx_destroy(ctx)
+    return res
+
+
 FP64_LANE_OPS = 256 * 2.4e9 * 64  # FP64 vector lane-ops/s (78.6 TFLOP/s counting an FMA as 2)
 NTT_OPS_PER_BUTTERFLY = 8  # 6 for the error-free modular product, 1 add, 1 subtract
 
@@ -832,6 +902,7 @@ def main():
     ap.add_argument("--no-cc", action="store_true", help="skip the matmul_cc measurement")
     ap.add_argument("--no-attn-out", action="store_true", help="skip the attention-output (Softmax x V, W_O) measurement")
     ap.add_argument("--no-qk-fused", action="store_true", help="skip the fused Q K^T-from-X measurement")
+    ap.add_argument("--no-small-ops", action="store_true", help="skip the rotate-and-sum / share-addition measurement")
     ap.add_argument("--no-tune", action="store_true", help="skip the MAC launch-shape autotuner")
     ap.add_argument("--mac-variant", type=int, default=None, help="use this MAC launch shape instead of autotuning")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched measurement")
@@ -857,13 +928,15 @@ def main():
         print(json.dumps({"ntt_standalone_1GiB": run_ntt(args, B, torch)}))
         return
     if args.attn_out_only:  # diagnostic mode: the attention operators alone
-        print(json.dumps({"attention_output": run_attn_out(args, B, torch), "qk_fused_from_x": run_qk_fused(args, B, torch)}))
+        print(json.dumps({"attention_output": run_attn_out(args, B, torch), "qk_fused_from_x": run_qk_fused(args, B, torch),
+                          "small_ops": run_small_ops(args, B, torch)}))
         return
     r = run_cp(args, B, torch)
     nt = None if args.no_ntt else run_ntt(args, B, torch)
     cc = None if args.no_cc else run_cc(args, B, torch)
     ao = None if args.no_attn_out else run_attn_out(args, B, torch)
     qk = None if args.no_qk_fused else run_qk_fused(args, B, torch)
+    so = None if args.no_small_ops else run_small_ops(args, B, torch)
     args.tuned_mac_variant = r["mac_variant"]  # the per-instance (unbatched) path uses the tuned MAC shape too
     bt = None if args.no_batch else run_batch(args, B, torch)
     sv = None if args.no_serve else run_serving(args, B, torch)
@@ -919,6 +992,10 @@ def main():
                       "6 primes + 2 special)",
             "value": qk["value"], "eager_value": qk["eager"], "ms": qk["ms"], "max_abs_err": qk["err"], "split_ms": qk["split_ms"],
             "rotation_keys": qk["rotation_keys"]},
+        "small_ops": None if so is None else dict(
+            so, workload="24 ciphertexts of the BERT-base activation layout (128 x 768 spatial-first, N=8192, 3 primes): "
+                         "rotate-and-sum row sums (log2 32 = 5 rotations, first-block mask, rescale) and broadcast, "
+                         "the server's share addition of the MPC-to-CKKS conversion, mask-to-share; ms per call over all 24"),
         "batched": None if bt is None else dict(
             bt, workload="64 independent matmul_cp instances, L ~ U{16..512}, hidden 768/1024 (W shared per hidden size), "
                          "N=8192, 3 primes; per-instance eager calls vs batched stages vs one graph launch"),
