@@ -128,3 +128,29 @@ def test_temporaries_reused_and_trimmed(env):
     torch.cuda.synchronize()
     for o in outs + [B.blb_export(ctx, out, 4096)]:
         assert np.array_equal(o, outs[0])
+
+
+def test_attention_and_share_entry_points_reject_bad_arguments(env):
+    """The entry points of the attention operators, rotate-and-sum and the share addition refuse
+    malformed arguments before enqueuing work, leaving outputs untouched."""
+    B, ctx, keys = env
+    ct, t = _fresh_ct(B, ctx, keys)
+    out, to = B.new_ct(4096, 1)
+    to.fill_(9)
+    torch.cuda.synchronize()
+    # rotate-and-sum: n_blocks not a power of two, a masked broadcast, a width beyond N/2, a missing key
+    assert _code(B.blb_rotate_sum, ctx, keys, [ct], [out], 32, 6, 0) == B.BLB_EINVAL
+    assert _code(B.blb_rotate_sum, ctx, keys, [ct], [out], 32, 8, 1, True) == B.BLB_EINVAL
+    assert _code(B.blb_rotate_sum, ctx, keys, [ct], [out], 1024, 4, 0) == B.BLB_EINVAL
+    assert _code(B.blb_rotate_sum, ctx, keys, [ct], [out], 32, 8, 0) == B.BLB_ENOKEY
+    torch.cuda.synchronize()
+    assert bool((to == 9).all())
+    # share addition: ciphertexts at different levels
+    c0, t0 = _fresh_ct(B, ctx, keys, level=0)
+    share = torch.zeros(2 * 2 * 4096, dtype=torch.int64, device="cuda")
+    assert _code(B.blb_add_share, ctx, [ct, c0], share) == B.BLB_ELEVEL
+    # a Softmax x V plan below its three levels; a diagonal-input plan with d_v' > L'; a
+    # reordered-column plan whose head group needs more columns per ciphertext than L'
+    assert _code(B.blb_plan_matmul_cc_sv, ctx, 4, 16, 32, 1) == B.BLB_EINVAL
+    assert _code(B.blb_plan_matmul_cp_diag, ctx, np.zeros((128, 8)), 1, 128, 64, 1) == B.BLB_EINVAL
+    assert _code(B.blb_plan_matmul_cp_mhp, ctx, np.zeros((8, 16)), 1, 16, 8, 1) == B.BLB_EINVAL
