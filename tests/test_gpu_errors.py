@@ -92,6 +92,8 @@ def test_scale_mismatch(env):
 
 def test_hbm_budget_exhausted():
     """A context with a small HBM budget refuses plans and keys beyond it (forced from the host)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
     import paper_2508_19525_amd as B
     ctx = B.blb_ctx_create(13, 3, 1, 3, 0, torch.cuda.current_stream().cuda_stream, 64 << 20)
     try:
