@@ -372,6 +372,7 @@ def run_attn_out(args, B, torch):
     for name, kind in [("ntt", B.BLB_T_NTT), ("ks_inner", B.BLB_T_KS_INNER), ("modup", B.BLB_T_MODUP), ("moddown_conv", B.BLB_T_MODDOWN),
                        ("tensor", B.BLB_T_CC_TENSOR), ("cp_mac", B.BLB_T_CP_MAC), ("masks_ew", B.BLB_T_EW)]:
         split[name] = B.blb_ctx_read_timing(ctx, kind)[0] / steps
+    ntt_ms, _, ntt_polys = B.blb_ctx_read_timing(ctx, B.BLB_T_NTT)
     B.blb_ctx_set_timing(ctx, False)
     ex1 = B.blb_exec_create_cc(ctx, keys, plan, A, Bv, Att)
     ex2 = B.blb_exec_create_cp(ctx, keys, cplan, Att, E, 0, share)
@@ -386,6 +387,7 @@ def run_attn_out(args, B, torch):
     dt = time.perf_counter() - t0
     log(f"attention output: eager {steps / dt_eager:.1f}/s, graph {steps / dt:.1f}/s")
     res = {"value": steps / dt, "eager": steps / dt_eager, "ms": dt / steps * 1e3, "err": err, "split_ms": split,
+           "ntt_gbps": ntt_polys * 16 * n / (ntt_ms / 1e3) / 1e9 if ntt_ms > 0 else 0.0,
            "rotation_keys": len(steps_rot), "groups": info["groups"], "wo_geometry": g}
     B.blb_exec_destroy(ex1)
     B.blb_exec_destroy(ex2)
@@ -481,6 +483,8 @@ def run_qk_fused(args, B, torch):
     for name, kind in [("ntt", B.BLB_T_NTT), ("ks_inner", B.BLB_T_KS_INNER), ("modup", B.BLB_T_MODUP), ("moddown_conv", B.BLB_T_MODDOWN),
                        ("tensor", B.BLB_T_CC_TENSOR), ("cp_mac", B.BLB_T_CP_MAC), ("masks_ew", B.BLB_T_EW)]:
         split[name] = B.blb_ctx_read_timing(ctx, kind)[0] / steps
+    ntt_ms, _, ntt_polys = B.blb_ctx_read_timing(ctx, B.BLB_T_NTT)
+    mac_ms, mac_launches, _ = B.blb_ctx_read_timing(ctx, B.BLB_T_CP_MAC)
     B.blb_ctx_set_timing(ctx, False)
     ex = [B.blb_exec_create_cp(ctx, keys, pq, Xc, Qc), B.blb_exec_create_cp(ctx, keys, pk, Xc, Kc),
           B.blb_exec_create_cc(ctx, keys, pcc, Qc, Kc, Cd, 0, share)]
@@ -494,7 +498,12 @@ def run_qk_fused(args, B, torch):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     log(f"fused QK: eager {steps / dt_eager:.1f}/s, graph {steps / dt:.1f}/s")
+    # the W_Q / W_K MACs stream n_out G x n_in B plaintexts of (level + 1) limbs each, plus inputs and inner sums
+    nl = level + 1
+    mac_bytes = 8 * nl * n * (g["n_out"] * g["G"] * g["n_in"] * g["B"] + 2 * g["n_in"] * g["B"] + 2 * g["n_out"] * g["G"])
     res = {"value": steps / dt, "eager": steps / dt_eager, "ms": dt / steps * 1e3, "err": err, "split_ms": split,
+           "ntt_gbps": ntt_polys * 16 * n / (ntt_ms / 1e3) / 1e9 if ntt_ms > 0 else 0.0,
+           "mac_gbps": mac_bytes * mac_launches / (mac_ms / 1e3) / 1e9 if mac_ms > 0 else 0.0,
            "rotation_keys": len(steps_rot), "wq_geometry": g, "groups": info["groups"]}
     for e in ex:
         B.blb_exec_destroy(e)
@@ -985,12 +994,14 @@ def main():
             "metric": "attention-output ops/s (Softmax x V_h for 12 heads of 128 tokens, d_v 64, zero-padded and folded; "
                       "Concat(Att_h) W_O 768x768 on the diagonal packing; mask-to-share of 12 cts; N=16384, 5 primes + 2 special)",
             "value": ao["value"], "eager_value": ao["eager"], "ms": ao["ms"], "max_abs_err": ao["err"], "split_ms": ao["split_ms"],
-            "rotation_keys": ao["rotation_keys"]},
+            "ntt_GBps": ao["ntt_gbps"], "ntt_frac_hbm_peak": ao["ntt_gbps"] / HBM_PEAK_GBPS, "rotation_keys": ao["rotation_keys"]},
         "qk_fused_from_x": None if qk is None else {
             "metric": "fused Q_h K_h^T-from-X ops/s (Enc(X 128x768) x W_Q, W_K 768x768 with columns reordered for the "
                       "multi-head packing; 12-head ct-ct product with step 1 on the server; mask-to-share; N=16384, "
                       "6 primes + 2 special)",
             "value": qk["value"], "eager_value": qk["eager"], "ms": qk["ms"], "max_abs_err": qk["err"], "split_ms": qk["split_ms"],
+            "ntt_GBps": qk["ntt_gbps"], "ntt_frac_hbm_peak": qk["ntt_gbps"] / HBM_PEAK_GBPS,
+            "wq_wk_mac_GBps": qk["mac_gbps"], "wq_wk_mac_frac_hbm_peak": qk["mac_gbps"] / HBM_PEAK_GBPS,
             "rotation_keys": qk["rotation_keys"]},
         "small_ops": None if so is None else dict(
             so, workload="24 ciphertexts of the BERT-base activation layout (128 x 768 spatial-first, N=8192, 3 primes): "
