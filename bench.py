@@ -555,7 +555,7 @@ def run_small_ops(args, B, torch):
     share = torch.zeros(n_ct * (level + 1) * n, dtype=torch.int64, device="cuda")
     # accuracy of the row sums: ciphertext a's first block holds sum over its 32 columns
     B.blb_rotate_sum(ctx, keys, Xc, Ysum, lp, nb, 0)
-    dec = torch.empty(n, dtype=torch.int64, device="cuda")
+    dec = torch.empty((level + 1) * n, dtype=torch.int64, device="cuda")  # decryptions write (ct level + 1) limbs
     err = 0.0
     for a, y in enumerate(Ysum):
         B.blb_decrypt(ctx, keys, y, dec)

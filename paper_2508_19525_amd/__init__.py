@@ -154,14 +154,28 @@ def _host_ptr(a: np.ndarray):
 # ---------------------------------------------------------------------------------------
 # C ABI, one function per entry point
 # ---------------------------------------------------------------------------------------
+_CTX_N = {}  # ring degree of each live context, for the buffer-size checks below
+
+
+def _need(ctx, buf, words, what):
+    """A torch tensor passed as device words must hold at least `words` 64-bit words (raw integer
+    pointers are taken as given)."""
+    if buf is None or isinstance(buf, int) or not hasattr(buf, "numel"):
+        return
+    if buf.numel() * buf.element_size() < words * 8:
+        raise BlbError(BLB_EINVAL, f"{what}: buffer of {buf.numel() * buf.element_size()} bytes, {words * 8} needed")
+
+
 def blb_ctx_create(log_n, n_q, n_special, dnum, device=0, stream=None, hbm_budget_bytes=0):
     p = blb_params(log_n, n_q, n_special, dnum, device, stream, hbm_budget_bytes)
     out = C.c_void_p()
     _check(lib().blb_ctx_create(C.byref(p), C.byref(out)), "blb_ctx_create")
+    _CTX_N[out.value] = 1 << log_n
     return out.value
 
 
 def blb_ctx_destroy(ctx):
+    _CTX_N.pop(ctx, None)
     lib().blb_ctx_destroy(ctx)
 
 
@@ -237,18 +251,22 @@ def blb_galois_elt(ctx, steps):
 
 def blb_encode(ctx, values, scale, level, pt_dev):
     v = np.ascontiguousarray(values, dtype=np.float64)
+    _need(ctx, pt_dev, (level + 1) * _CTX_N.get(ctx, 0), "blb_encode")
     _check(lib().blb_encode(ctx, _host_ptr(v), v.size, float(scale), level, _ptr(pt_dev)), "blb_encode")
 
 
 def blb_encrypt(ctx, keys, pt_dev, level, scale, seed, ct_id, ct: blb_ct):
+    _need(ctx, pt_dev, (level + 1) * _CTX_N.get(ctx, 0), "blb_encrypt")
     _check(lib().blb_encrypt(ctx, keys, _ptr(pt_dev), level, float(scale), seed, ct_id, C.byref(ct)), "blb_encrypt")
 
 
 def blb_decrypt(ctx, keys, ct: blb_ct, pt_dev):
+    _need(ctx, pt_dev, (ct.level + 1) * _CTX_N.get(ctx, 0), "blb_decrypt")
     _check(lib().blb_decrypt(ctx, keys, C.byref(ct), _ptr(pt_dev)), "blb_decrypt")
 
 
 def blb_decode(ctx, pt_dev, level, scale, n_vals):
+    _need(ctx, pt_dev, (level + 1) * _CTX_N.get(ctx, 0), "blb_decode")
     out = np.zeros(n_vals, np.float64)
     _check(lib().blb_decode(ctx, _ptr(pt_dev), level, float(scale), _host_ptr(out), n_vals), "blb_decode")
     return out
@@ -275,6 +293,7 @@ def blb_rescale(ctx, ct_in: blb_ct, ct_out: blb_ct):
 
 def blb_ntt(ctx, data_dev, n_polys, n_limbs, inverse=False):
     """In-place batched NTT of device words [n_polys][n_limbs][N] (int64 tensor or pointer)."""
+    _need(ctx, data_dev, n_polys * n_limbs * _CTX_N.get(ctx, 0), "blb_ntt")
     _check(lib().blb_ntt(ctx, _ptr(data_dev), n_polys, n_limbs, 1 if inverse else 0), "blb_ntt")
 
 
@@ -304,6 +323,7 @@ def blb_matmul_cp(ctx, keys, plan, X_cts, Y_cts):
 
 
 def blb_mask_to_share(ctx, cts, seed, target_level, share_dev):
+    _need(ctx, share_dev, len(cts) * (target_level + 1) * _CTX_N.get(ctx, 0), "blb_mask_to_share")
     arr = (blb_ct * len(cts))(*cts)
     _check(lib().blb_mask_to_share(ctx, arr, len(cts), seed, target_level, _ptr(share_dev)), "blb_mask_to_share")
     for i in range(len(cts)):
@@ -311,6 +331,8 @@ def blb_mask_to_share(ctx, cts, seed, target_level, share_dev):
 
 
 def blb_add_share(ctx, cts, share_dev):
+    if cts:
+        _need(ctx, share_dev, len(cts) * (cts[0].level + 1) * _CTX_N.get(ctx, 0), "blb_add_share")
     arr = (blb_ct * len(cts))(*cts)
     _check(lib().blb_add_share(ctx, arr, len(cts), _ptr(share_dev)), "blb_add_share")
 

@@ -3,6 +3,8 @@
 import os
 import re
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 
@@ -40,3 +42,30 @@ def test_package_has_no_cpu_fallback():
         if fn.endswith(".py"):
             src = open(os.path.join(pkg, fn)).read()
             assert not re.search(r"^\s*(import|from)\s+oracle", src, flags=re.M), fn
+
+
+def test_binding_refuses_undersized_device_buffers():
+    """The binding checks torch buffers against the words a call reads or writes ((level + 1) N
+    for a decryption, n_ct (target + 1) N for shares, ...) before calling into the library."""
+    import torch
+    import paper_2508_19525_amd as B
+    fake_ctx = 0x1234
+    B._CTX_N[fake_ctx] = 4096
+    try:
+        ct = B.blb_ct()
+        ct.level, ct.degree = 1, 1
+        small = torch.empty(4096, dtype=torch.int64)
+        for fn, args in [(B.blb_decrypt, (fake_ctx, None, ct, small)),
+                         (B.blb_decode, (fake_ctx, small, 1, 1.0, 8)),
+                         (B.blb_encode, (fake_ctx, np.zeros(4), 1.0, 1, small)),
+                         (B.blb_mask_to_share, (fake_ctx, [ct], 1, 1, small)),
+                         (B.blb_add_share, (fake_ctx, [ct], small)),
+                         (B.blb_ntt, (fake_ctx, small, 2, 1))]:
+            try:
+                fn(*args)
+            except B.BlbError as e:
+                assert e.code == B.BLB_EINVAL
+            else:
+                raise AssertionError(f"{fn.__name__} accepted an undersized buffer")
+    finally:
+        B._CTX_N.pop(fake_ctx, None)

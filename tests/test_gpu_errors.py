@@ -69,7 +69,7 @@ def test_level_errors(env):
         assert _code(B.blb_matmul_cp, ctx, keys, plan, [ct], [y]) in (B.BLB_ELEVEL, B.BLB_ENOKEY)
     finally:
         B.blb_plan_destroy(plan)
-    share = torch.zeros(4096, dtype=torch.int64, device="cuda")
+    share = torch.zeros(2 * 4096, dtype=torch.int64, device="cuda")
     assert _code(B.blb_mask_to_share, ctx, [ct], 1, 1, share) == B.BLB_ELEVEL  # target above the level
 
 
