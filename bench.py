@@ -253,6 +253,9 @@ def run_cc(args, B, torch):
             ntt_tune[var] = (time.perf_counter() - t0) / 2 * 1e3
         B.blb_ctx_set_knob(ctx, B.BLB_KNOB_NTT_VARIANT, min(ntt_tune, key=ntt_tune.get))
         log(f"cc NTT variants (ms per op): {ntt_tune}")
+    ks_var, ks_tune = tune_knob(args, B, torch, ctx, B.BLB_KNOB_KS_VARIANT, (0, 1),
+                                lambda k: B.blb_matmul_cc(ctx, keys, plan, A, Bp, Cd))
+    log(f"cc key inner-product variants (ms per op): {ks_tune} -> {ks_var}")
     # eager (timed, with kernel timing)
     B.blb_matmul_cc(ctx, keys, plan, A, Bp, Cd)
     torch.cuda.synchronize()
@@ -282,7 +285,8 @@ def run_cc(args, B, torch):
     res = {"value": steps / dt, "eager": steps / dt_eager, "ms": dt / steps * 1e3, "err": err, "split_ms": split,
            "ntt_gbps": ntt_polys * 16 * n / (ntt_ms / 1e3) / 1e9 if ntt_ms > 0 else 0.0,
            "rotation_keys": len(steps_rot), "groups": info["groups"],
-           "ntt_variant": B.blb_ctx_get_knob(ctx, B.BLB_KNOB_NTT_VARIANT), "ntt_tune_ms": ntt_tune}
+           "ntt_variant": B.blb_ctx_get_knob(ctx, B.BLB_KNOB_NTT_VARIANT), "ntt_tune_ms": ntt_tune,
+           "ks_variant": ks_var, "ks_tune_ms": ks_tune}
     B.blb_exec_destroy(ex)
     B.blb_plan_destroy(plan)
     B.blb_keys_destroy(keys)
@@ -308,6 +312,26 @@ def tune_mac(args, B, ctx, step):
     best = min(tune, key=tune.get)
     B.blb_ctx_set_knob(ctx, B.BLB_KNOB_MAC_VARIANT, best)
     return best
+
+
+def tune_knob(args, B, torch, ctx, knob, values, step):
+    """Pick the value of a launch knob (never changes results) by timing two whole steps per value
+    after one warm-up step; returns (best, ms per step by value)."""
+    if args.no_tune:
+        return B.blb_ctx_get_knob(ctx, knob), {}
+    ms = {}
+    for v in values:
+        B.blb_ctx_set_knob(ctx, knob, v)
+        step(800)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(2):
+            step(801 + k)
+        torch.cuda.synchronize()
+        ms[v] = (time.perf_counter() - t0) / 2 * 1e3
+    best = min(ms, key=ms.get)
+    B.blb_ctx_set_knob(ctx, knob, best)
+    return best, ms
 
 
 def run_attn_out(args, B, torch):
@@ -379,6 +403,8 @@ def run_attn_out(args, B, torch):
     err = float(np.abs(wl.unpack_spatial(vecs, L, d_out, slots) - ref).max())
     log(f"attention-output decoded max abs err {err:.3e}")
     mac_var = tune_mac(args, B, ctx, eager_step)
+    ks_var, ks_tune = tune_knob(args, B, torch, ctx, B.BLB_KNOB_KS_VARIANT, (0, 1), eager_step)
+    log(f"attention-output key inner-product variants (ms per op): {ks_tune} -> {ks_var}")
     eager_step(1)
     torch.cuda.synchronize()
     B.blb_ctx_set_timing(ctx, True)
@@ -409,6 +435,7 @@ def run_attn_out(args, B, torch):
     log(f"attention output: eager {steps / dt_eager:.1f}/s, graph {steps / dt:.1f}/s")
     res = {"value": steps / dt, "eager": steps / dt_eager, "ms": dt / steps * 1e3, "err": err, "split_ms": split,
            "ntt_gbps": ntt_polys * 16 * n / (ntt_ms / 1e3) / 1e9 if ntt_ms > 0 else 0.0, "mac_variant": mac_var,
+           "ks_variant": ks_var, "ks_tune_ms": ks_tune,
            "rotation_keys": len(steps_rot), "groups": info["groups"], "wo_geometry": g}
     B.blb_exec_destroy(ex1)
     B.blb_exec_destroy(ex2)
@@ -491,6 +518,8 @@ def run_qk_fused(args, B, torch):
         base += grp["n_out"]
     log(f"fused QK decoded max abs err {err:.3e}")
     mac_var = tune_mac(args, B, ctx, eager_step)
+    ks_var, ks_tune = tune_knob(args, B, torch, ctx, B.BLB_KNOB_KS_VARIANT, (0, 1), eager_step)
+    log(f"fused QK key inner-product variants (ms per op): {ks_tune} -> {ks_var}")
     eager_step(1)
     torch.cuda.synchronize()
     B.blb_ctx_set_timing(ctx, True)
@@ -526,6 +555,7 @@ def run_qk_fused(args, B, torch):
     res = {"value": steps / dt, "eager": steps / dt_eager, "ms": dt / steps * 1e3, "err": err, "split_ms": split,
            "ntt_gbps": ntt_polys * 16 * n / (ntt_ms / 1e3) / 1e9 if ntt_ms > 0 else 0.0,
            "mac_gbps": mac_bytes * mac_launches / (mac_ms / 1e3) / 1e9 if mac_ms > 0 else 0.0, "mac_variant": mac_var,
+           "ks_variant": ks_var, "ks_tune_ms": ks_tune,
            "rotation_keys": len(steps_rot), "wq_geometry": g, "groups": info["groups"]}
     for e in ex:
         B.blb_exec_destroy(e)
@@ -1011,7 +1041,8 @@ def main():
             "metric": "ct-ct matmul/s (12-head Q_h K_h^T, 128 tokens, N=16384, 4 primes + 2 special)",
             "value": cc["value"], "eager_value": cc["eager"], "ms": cc["ms"], "max_abs_err": cc["err"],
             "ntt_GBps": cc["ntt_gbps"], "split_ms": cc["split_ms"], "rotation_keys": cc["rotation_keys"],
-            "ntt_variant": cc["ntt_variant"], "ntt_tune_ms_per_op": cc["ntt_tune_ms"]},
+            "ntt_variant": cc["ntt_variant"], "ntt_tune_ms_per_op": cc["ntt_tune_ms"],
+            "ks_variant": cc["ks_variant"], "ks_tune_ms_per_op": cc["ks_tune_ms"]},
         "attention_output": None if ao is None else {
             "metric": "attention-output ops/s (Softmax x V_h for 12 heads of 128 tokens, d_v 64, zero-padded and folded; "
                       "Concat(Att_h) W_O 768x768 on the diagonal packing; mask-to-share of 12 cts; N=16384, 5 primes + 2 special)",

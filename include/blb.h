@@ -93,10 +93,13 @@ int blb_ctx_reset_timing(blb_ctx* ctx);
 int blb_ctx_counters(blb_ctx* ctx, int64_t* out, int reset);
 
 /* ---- launch-shape knobs (never change a result bit; chosen by the autotuner) ------------ */
-enum { BLB_KNOB_MAC_VARIANT = 0, BLB_KNOB_BATCH_VARIANT = 1, BLB_KNOB_BATCH_GRID = 2, BLB_KNOB_NTT_VARIANT = 3, BLB_KNOB_KINDS = 4 };
+enum { BLB_KNOB_MAC_VARIANT = 0, BLB_KNOB_BATCH_VARIANT = 1, BLB_KNOB_BATCH_GRID = 2, BLB_KNOB_NTT_VARIANT = 3, BLB_KNOB_KS_VARIANT = 4,
+       BLB_KNOB_KINDS = 5 };
 /* value ranges: MAC variant 0..BLB_MAC_VARIANTS-1 (outputs per block x coefficients per thread x
  * input-loop unroll x full-tile split), batch variant 0..BLB_BATCH_VARIANTS-1 (outputs x instances x
- * coefficients per thread), batch grid 1..2^20 workgroups, NTT variant 0..1 */
+ * coefficients per thread), batch grid 1..2^20 workgroups, NTT variant 0..1, key inner-product
+ * variant 0..1 (0: one key-switch output per thread; 1: the outputs of a batch that share a key and
+ * Galois element, up to 16, per thread, which reads each key word once for all of them) */
 enum { BLB_MAC_VARIANTS = 14, BLB_BATCH_VARIANTS = 7 };
 int blb_ctx_set_knob(blb_ctx* ctx, int knob, int value);
 int blb_ctx_get_knob(const blb_ctx* ctx, int knob);

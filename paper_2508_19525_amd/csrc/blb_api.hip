@@ -511,7 +511,27 @@ int ks_apply(blb_ctx* c, int level, const std::vector<const uint64_t*>& srcs, co
   const KsOut* ko_dev = upload_vec(c, ko);
   if (!ko_dev) return BLB_EDEVICE;
   c->counters[0] += O;
-  {
+  if (c->ks_variant == 1 && nd <= kKsMaxDigits) {
+    // outputs grouped by (key, Galois element), stable, in runs of at most kKsGroupMax
+    std::vector<int> ord(O);
+    for (int o = 0; o < O; ++o) ord[o] = o;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+      if (ko[a].key != ko[b].key) return ko[a].key < ko[b].key;
+      return ko[a].gal < ko[b].gal;
+    });
+    std::vector<KsGroup> groups;
+    for (int i = 0; i < O;) {
+      int j = i + 1;
+      while (j < O && j - i < kKsGroupMax && ko[ord[j]].key == ko[ord[i]].key && ko[ord[j]].gal == ko[ord[i]].gal) ++j;
+      groups.push_back(KsGroup{i, j - i});
+      i = j;
+    }
+    const int* ord_dev = upload_vec(c, ord);
+    const KsGroup* g_dev = upload_vec(c, groups);
+    if (!ord_dev || !g_dev) return BLB_EDEVICE;
+    Span sp(c, BLB_T_KS_INNER, (double)O * n_ext * n);
+    launch_ks_inner_grouped(c, ko_dev, ord_dev, g_dev, (int)groups.size(), X, c->d_kc[level], U, nl, n_ext, nd);
+  } else {
     Span sp(c, BLB_T_KS_INNER, (double)O * n_ext * n);
     launch_ks_inner(c, ko_dev, O, X, c->d_kc[level], U, nl, n_ext, nd);
   }
@@ -814,6 +834,10 @@ int blb_ctx_set_knob(blb_ctx* c, int knob, int value) {
       if (value < 0 || value > 1) return BLB_EINVAL;
       c->ntt_variant = value;
       return BLB_OK;
+    case BLB_KNOB_KS_VARIANT:
+      if (value < 0 || value > 1) return BLB_EINVAL;
+      c->ks_variant = value;
+      return BLB_OK;
     default: return BLB_EINVAL;
   }
 }
@@ -824,6 +848,7 @@ int blb_ctx_get_knob(const blb_ctx* c, int knob) {
     case BLB_KNOB_BATCH_VARIANT: return c->batch_variant;
     case BLB_KNOB_BATCH_GRID: return c->batch_grid;
     case BLB_KNOB_NTT_VARIANT: return c->ntt_variant;
+    case BLB_KNOB_KS_VARIANT: return c->ks_variant;
     default: return BLB_EINVAL;
   }
 }

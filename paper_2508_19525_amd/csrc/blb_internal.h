@@ -88,6 +88,14 @@ struct KsOut {
   int32_t src;
 };
 
+// Key-grouped inner product: ord lists output indices so that each group's outputs (first,
+// count <= kKsGroupMax) share one switching key and Galois element.
+constexpr int kKsGroupMax = 16;
+constexpr int kKsMaxDigits = 4;
+struct KsGroup {
+  int first, count;
+};
+
 // matmul_cc launch records
 struct CcPair {
   const uint64_t* x;
@@ -216,6 +224,7 @@ struct blb_ctx {
   int batch_variant = 0;          // k_cp_mac_batch shape (autotuned)
   int batch_grid = 2048;          // persistent grid size of k_cp_mac_batch (autotuned)
   int ntt_variant = 1;            // 0: one workgroup per poly, 1: persistent pipelined (autotuned)
+  int ks_variant = 0;             // key inner product: 0 per output, 1 grouped by key (autotuned)
   int n_cu = 256;                 // compute units of the device
   int64_t counters[8] = {};       // operation counters (see blb_ctx_counters)
 };
@@ -294,6 +303,8 @@ void launch_automorph(blb_ctx* c, uint64_t* out, const uint64_t* in, int count, 
 void launch_modup(blb_ctx* c, const uint64_t* dcoef, uint64_t* X, const KsLevelConst* kc_dev, int n_src, int nl, int n_ext, int n_digits);
 void launch_ks_inner(blb_ctx* c, const KsOut* outs_dev, int n_out, const uint64_t* X, const KsLevelConst* kc_dev, uint64_t* U, int nl,
                      int n_ext, int n_digits);
+void launch_ks_inner_grouped(blb_ctx* c, const KsOut* outs_dev, const int* ord_dev, const KsGroup* groups_dev, int n_groups,
+                             const uint64_t* X, const KsLevelConst* kc_dev, uint64_t* U, int nl, int n_ext, int n_digits);
 void launch_moddown_conv(blb_ctx* c, const uint64_t* U, uint64_t* Corr, const KsLevelConst* kc_dev, int n_out, int nl, int n_ext);
 void launch_cp_mac(blb_ctx* c, const uint64_t* pt, const uint64_t* const* rx_tab, uint64_t* inner, int nl, int n_ai, int n_bj, int variant);
 void launch_sum_cts(blb_ctx* c, const uint64_t* const* srcs, uint64_t* const* dsts, int n_out, int n_terms, int nl);

@@ -230,6 +230,75 @@ void launch_ks_inner(blb_ctx* c, const KsOut* outs_dev, int n_out, const uint64_
   k_ks_inner<<<grid, 256, 0, c->stream>>>(outs_dev, X, kc_dev, U, c->n, c->log_n, nl, n_ext, n_digits, c->n_q);
 }
 
+// The same inner product for a group of outputs that share a switching key and Galois element:
+// the key words of the thread's two coefficients are loaded once (all digits, in registers) and
+// applied to every output of the group; per output the arithmetic and its order are those of
+// k_ks_inner, so the words are identical.
+__global__ void k_ks_inner_grp(const KsOut* __restrict__ outs, const int* __restrict__ ord, const KsGroup* __restrict__ groups,
+                               const uint64_t* __restrict__ X, const KsLevelConst* __restrict__ kc, uint64_t* __restrict__ U, int n,
+                               int log_n, int nl, int n_ext, int n_digits, int n_q) {
+  const int k0 = (blockIdx.x * blockDim.x + threadIdx.x) * 2;
+  const int e = blockIdx.y % n_ext;
+  const int gi = blockIdx.y / n_ext;
+  if (k0 >= n) return;
+  const KsGroup gr = groups[gi];
+  const KsOut lead = outs[ord[gr.first]];
+  uint32_t kk[2];
+#pragma unroll
+  for (int v = 0; v < 2; ++v) kk[v] = lead.gal ? gal_perm((uint32_t)(k0 + v), lead.gal, log_n) : (uint32_t)(k0 + v);
+  const ModEntry mm = kc->ext[e];
+  const int key_mod = e < nl ? e : n_q + (e - nl);
+  double kb[kKsMaxDigits][2], ka[kKsMaxDigits][2];
+#pragma unroll
+  for (int j = 0; j < kKsMaxDigits; ++j) {
+    if (j < n_digits) {
+      const uint64_t* b = lead.key + (((size_t)j * 2 + 0) * kc->n_key_mod + key_mod) * n + k0;
+      const uint64_t* a = lead.key + (((size_t)j * 2 + 1) * kc->n_key_mod + key_mod) * n + k0;
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        kb[j][v] = u2d(b[v]);
+        ka[j][v] = u2d(a[v]);
+      }
+    }
+  }
+  for (int i = 0; i < gr.count; ++i) {
+    const int o = ord[gr.first + i];
+    const KsOut od = outs[o];
+    double acc0[2] = {0.0, 0.0}, acc1[2] = {0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < kKsMaxDigits; ++j) {
+      if (j < n_digits) {
+        const uint64_t* xs = (e >= kc->dlo[j] && e < kc->dhi[j]) ? od.c1 + (size_t)e * n : X + (((size_t)od.src * n_digits + j) * n_ext + e) * n;
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          const double x = u2d(xs[kk[v]]);
+          acc0[v] += mulmod_s(x, kb[j][v], mm.q, mm.qinv);
+          acc1[v] += mulmod_s(x, ka[j][v], mm.q, mm.qinv);
+        }
+        if ((j & 3) == 3) {
+#pragma unroll
+          for (int v = 0; v < 2; ++v) {
+            acc0[v] = reduce_s(acc0[v], mm.q, mm.qinv);
+            acc1[v] = reduce_s(acc1[v], mm.q, mm.qinv);
+          }
+        }
+      }
+    }
+    uint64_t* u0 = U + (((size_t)o * 2 + 0) * n_ext + e) * n + k0;
+    uint64_t* u1 = U + (((size_t)o * 2 + 1) * n_ext + e) * n + k0;
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      u0[v] = d2u(canon_full(acc0[v], mm.q, mm.qinv));
+      u1[v] = d2u(canon_full(acc1[v], mm.q, mm.qinv));
+    }
+  }
+}
+void launch_ks_inner_grouped(blb_ctx* c, const KsOut* outs_dev, const int* ord_dev, const KsGroup* groups_dev, int n_groups,
+                             const uint64_t* X, const KsLevelConst* kc_dev, uint64_t* U, int nl, int n_ext, int n_digits) {
+  dim3 grid((c->n / 2 + 255) / 256, n_groups * n_ext);
+  k_ks_inner_grp<<<grid, 256, 0, c->stream>>>(outs_dev, ord_dev, groups_dev, X, kc_dev, U, c->n, c->log_n, nl, n_ext, n_digits, c->n_q);
+}
+
 // ModDown conversion: corr_i = sum_t [u_{p_t} * Phat_t^-1]_{p_t} * [Phat_t]_{q_i}  (coefficient
 // form; U's special limbs must already be in coefficient form).  Thread per (o, poly, k).
 __global__ void k_moddown_conv(const uint64_t* U, uint64_t* Corr, const KsLevelConst* kc, int n, int nl, int n_ext, int n_sp) {

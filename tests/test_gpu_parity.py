@@ -501,6 +501,35 @@ def test_ntt_variants_bit_identical(c3s):
     B.blb_keys_destroy(r["keys_g"])
 
 
+def test_ks_variants_bit_identical(c3s, c2s):
+    """The key-grouped inner product (knob 1: outputs sharing a key and Galois element in one
+    thread, groups of up to 16 split across launches' rows) gives the words of the per-output kernel
+    through a full matmul_cc (every key switch of steps 2-3 and the relinearisations) and through
+    matmul_cp (baby steps shared across inputs, giant steps across outputs); both equal the oracle."""
+    B = c3s.B
+    for c, run in ((c3s, "cc"), (c2s, "cp")):
+        default = B.blb_ctx_get_knob(c.h, B.BLB_KNOB_KS_VARIANT)
+        B.blb_ctx_set_knob(c.h, B.BLB_KNOB_KS_VARIANT, 1 - default)
+        try:
+            if run == "cc":
+                r = _cc_case(c, 12, 64, 32, 21, outputs=[0, 1])
+                base = 0
+                for O_want, outs, grp in r["want"]:
+                    for o in outs:
+                        assert np.array_equal(c.export(r["C"][base + o]), O_want[o]), f"cc group H={grp['H']} output {o}"
+                    base += grp["n_out"]
+                B.blb_plan_destroy(r["plan"])
+            else:
+                r = _cp_case(c, 100, 96, 80, 2, 7, x_std=1.0)
+                want = r["keys_o"].matmul_cp(r["X_words"], 2, r["W"], 100)
+                for b in range(r["g"]["n_out"]):
+                    assert np.array_equal(c.export(r["Yc"][b]), want[b]), f"cp output {b}"
+                B.blb_plan_destroy(r["plan"])
+            B.blb_keys_destroy(r["keys_g"])
+        finally:
+            B.blb_ctx_set_knob(c.h, B.BLB_KNOB_KS_VARIANT, default)
+
+
 @pytest.mark.parametrize("shape", [(64, 96, 64), (20, 1, 24)])
 def test_mac_variants_bit_identical(c2s, shape):
     """Every MAC launch shape gives the same words (the second shape has a single rotated input,
