@@ -224,7 +224,7 @@ struct blb_ctx {
   int batch_variant = 0;          // k_cp_mac_batch shape (autotuned)
   int batch_grid = 2048;          // persistent grid size of k_cp_mac_batch (autotuned)
   int ntt_variant = 1;            // 0: one workgroup per poly, 1: persistent pipelined (autotuned)
-  int ks_variant = 0;             // key inner product: 0 per output, 1 grouped by key (autotuned)
+  int ks_variant = 1;             // key inner product: 0 per output, 1 grouped by key (autotuned)
   int n_cu = 256;                 // compute units of the device
   int64_t counters[8] = {};       // operation counters (see blb_ctx_counters)
 };
