@@ -99,7 +99,8 @@ enum { BLB_KNOB_MAC_VARIANT = 0, BLB_KNOB_BATCH_VARIANT = 1, BLB_KNOB_BATCH_GRID
  * input-loop unroll x full-tile split), batch variant 0..BLB_BATCH_VARIANTS-1 (outputs x instances x
  * coefficients per thread), batch grid 1..2^20 workgroups, NTT variant 0..1, key inner-product
  * variant 0..1 (0: one key-switch output per thread; 1: the outputs of a batch that share a key and
- * Galois element, up to 16, per thread, which reads each key word once for all of them) */
+ * Galois element, up to 16 per thread, which reads each key word once for all of them; batches too
+ * small to keep about 8192 workgroups busy that way keep one output per thread) */
 enum { BLB_MAC_VARIANTS = 14, BLB_BATCH_VARIANTS = 7 };
 int blb_ctx_set_knob(blb_ctx* ctx, int knob, int value);
 int blb_ctx_get_knob(const blb_ctx* ctx, int knob);

@@ -511,8 +511,12 @@ int ks_apply(blb_ctx* c, int level, const std::vector<const uint64_t*>& srcs, co
   const KsOut* ko_dev = upload_vec(c, ko);
   if (!ko_dev) return BLB_EDEVICE;
   c->counters[0] += O;
-  if (c->ks_variant == 1 && nd <= kKsMaxDigits) {
-    // outputs grouped by (key, Galois element), stable, in runs of at most kKsGroupMax
+  // group size: large enough to reuse the key words, small enough to keep about 8192 workgroups
+  // in the launch (a small batch keeps one output per thread)
+  const int64_t blocks = (int64_t)O * n_ext * ((n / 2 + 255) / 256);
+  const int cap = (int)std::min<int64_t>(kKsGroupMax, std::max<int64_t>(1, blocks / 8192));
+  if (c->ks_variant == 1 && nd <= kKsMaxDigits && cap > 1) {
+    // outputs grouped by (key, Galois element), stable, in runs of at most `cap`
     std::vector<int> ord(O);
     for (int o = 0; o < O; ++o) ord[o] = o;
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
@@ -522,7 +526,7 @@ int ks_apply(blb_ctx* c, int level, const std::vector<const uint64_t*>& srcs, co
     std::vector<KsGroup> groups;
     for (int i = 0; i < O;) {
       int j = i + 1;
-      while (j < O && j - i < kKsGroupMax && ko[ord[j]].key == ko[ord[i]].key && ko[ord[j]].gal == ko[ord[i]].gal) ++j;
+      while (j < O && j - i < cap && ko[ord[j]].key == ko[ord[i]].key && ko[ord[j]].gal == ko[ord[i]].gal) ++j;
       groups.push_back(KsGroup{i, j - i});
       i = j;
     }
