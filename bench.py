@@ -979,7 +979,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB plain copy (counter reference)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
                                    "(the path shards by independent instances: see the design notes)"}))
         sys.exit(2)
     import torch

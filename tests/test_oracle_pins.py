@@ -655,7 +655,7 @@ def test_matmul_cc_counts():
             assert m * m * d // s == cm
         else:
             assert m ** 3 * H // s == cm
-    # this build's schedule: tensors = sum over groups of L' * n_ct
+    # the pinned schedule: tensors = sum over groups of L' * n_ct
     n_tensor = 0
     for H_g in (8, 4):
         c_ = 8192 // (128 * H_g)
