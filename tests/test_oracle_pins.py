@@ -256,6 +256,30 @@ def test_encode_matches_direct_formula(orc, log_n):
         assert int(got[k]) == (r if v >= 0 else -r)
 
 
+def test_encode_matches_direct_formula_sampled_n4096(orc):
+    """At N = 4096 (the smallest measured ring) 32 sampled coefficients, the first, the last, the
+    middle ones and random ones, equal the direct formula in mpmath at 40 digits (catches an error
+    in the fast transform that only shows at full size: a wrong twiddle index, a slot-order slip
+    past the first few powers of 5, lost precision in a long sum)."""
+    mpmath.mp.dps = 40
+    c = orc.Context(12, 1, 0, 1)
+    n, s = c.n, c.slots
+    rng = np.random.default_rng(4096)
+    m = rng.normal(0, 1, s)
+    delta = 2.0 ** 40
+    got = c.encode(m, delta)
+    ks = sorted(set([0, 1, 2, n // 2 - 1, n // 2, n // 2 + 1, n - 2, n - 1] + [int(k) for k in rng.integers(0, n, 24)]))
+    e = [pow(5, j, 2 * n) for j in range(s)]
+    mm = [mpmath.mpf(float(x)) for x in m]
+    for k in ks:
+        acc = mpmath.mpf(0)
+        for j in range(s):
+            acc += mm[j] * mpmath.cos(mpmath.pi * ((e[j] * k) % (2 * n)) / n)
+        v = 2 * mpmath.mpf(delta) / n * acc
+        r = int(mpmath.floor(abs(v) + mpmath.mpf("0.5")))
+        assert int(got[k]) == (r if v >= 0 else -r), k
+
+
 def test_decode_inverts_encode(orc):
     """Decode(Encode(m)) = m within the rounding bound (no rounding before pi): each slot error is
     Delta^-1 sum_k eps_k cos(.), |eps_k| <= 1/2, so it is below N/(2 Delta) always and, with
@@ -371,6 +395,121 @@ def test_rotation_keyswitch_invariant(orc, params):
             assert _noise(c, diff, level) < 2.0 ** 30  # vs Q >= 2^49
             dec = c.decode(d_rot, level, delta)
             assert np.abs(dec - np.roll(m, -steps)).max() < 1e-3
+
+
+# --------------------------------------------------------------------------------------
+# the hybrid key switch written out over the integers (no RNS limbs, no NTT): every word
+# of the oracle's rotations and relinearisations at tiny N
+# --------------------------------------------------------------------------------------
+def _prod(xs):
+    r = 1
+    for x in xs:
+        r *= int(x)
+    return r
+
+
+def _crt(res, mods):
+    M = _prod(mods)
+    x = 0
+    for r, m in zip(res, mods):
+        Mi = M // m
+        x += int(r) * Mi * pow(Mi, -1, m)
+    return x % M
+
+
+def _negacyclic_int(a, b, M):
+    n = len(a)
+    r = [0] * n
+    for i in range(n):
+        if a[i] == 0:
+            continue
+        for j in range(n):
+            k = i + j
+            if k >= n:
+                r[k - n] -= a[i] * b[j]
+            else:
+                r[k] += a[i] * b[j]
+    return [x % M for x in r]
+
+
+def _sigma_int(a, g):
+    """X^k -> X^(k g) on an integer polynomial of Z[X]/(X^N + 1)"""
+    n = len(a)
+    r = [0] * n
+    for k in range(n):
+        e = k * g % (2 * n)
+        if e < n:
+            r[e] = a[k]
+        else:
+            r[e - n] = -a[k]
+    return r
+
+
+def _keyswitch_int(ctx, swk, d, level, g):
+    """KS(d) from the formulas of the hybrid key switch, with Python integers:
+    ModUp of digit j without centring is the integer X_j = sum_{i in D_j} [d_i (Q_D/q_i)^-1]_{q_i}
+    (Q_D/q_i); sigma_g acts on X_j (after ModUp); u = sum_j sigma_g(X_j) key_j over Z_{Q_l P};
+    ModDown without centring is (u - v) / P with v = sum_t [u (P/p_t)^-1]_{p_t} (P/p_t).
+    Returns (u_0, u_1) as residues [2][l+1][N]."""
+    n, nl, alpha = ctx.n, level + 1, ctx.alpha
+    qs = [int(x) for x in ctx.q[:nl]]
+    ps = [int(x) for x in ctx.p]
+    P, QP = _prod(ps), _prod(qs) * _prod(ps)
+    key_mods = qs + ps
+    key_idx = list(range(nl)) + [ctx.n_q + t for t in range(len(ps))]
+    u = [[0] * n, [0] * n]
+    for j in range((nl + alpha - 1) // alpha):
+        lo, hi = j * alpha, min((j + 1) * alpha, nl)
+        D = qs[lo:hi]
+        QD = _prod(D)
+        X = [sum((int(d[lo + t][k]) * pow(QD // qi, -1, qi)) % qi * (QD // qi) for t, qi in enumerate(D)) for k in range(n)]
+        if g:
+            X = _sigma_int(X, g)
+        for p in range(2):
+            key = [_crt([swk[j, p, m, k] for m in key_idx], key_mods) for k in range(n)]
+            prod = _negacyclic_int(X, key, QP)
+            u[p] = [(x + y) % QP for x, y in zip(u[p], prod)]
+    out = np.zeros((2, nl, n), np.uint64)
+    for p in range(2):
+        for k in range(n):
+            x = u[p][k]
+            v = sum((x % pt) * pow(P // pt, -1, pt) % pt * (P // pt) for pt in ps)
+            w = (x - v) // P
+            assert w * P == x - v
+            for i, qi in enumerate(qs):
+                out[p, i, k] = w % qi
+    return out
+
+
+@pytest.mark.parametrize("params", [(4, 3, 1, 3), (5, 4, 2, 2), (6, 5, 2, 3)])
+def test_keyswitch_matches_integer_formulas(orc, params):
+    """Every word of the oracle's rotations (left and right) and relinearisations, at every level,
+    equals the hybrid key switch written out over the integers (catches centring in ModUp or
+    ModDown, sigma_g applied before ModUp instead of after, a lazy or missing ModDown, a digit
+    partition slip at a partial last digit, a wrong key limb at a lower level)."""
+    log_n, n_q, n_sp, dnum = params
+    c = orc.Context(log_n, n_q, n_sp, dnum)
+    n = c.n
+    steps = [1, -3]
+    gal = [c.galois_elt(t) for t in steps]
+    k = orc.Keys(c, 1234 + log_n, gal)
+    swk = {g: k.switching_key(g) for g in gal}
+    swk[0] = k.switching_key(0)
+    rng = np.random.default_rng(log_n)
+    for level in range(n_q - 1, -1, -1):
+        nl = level + 1
+        qs = [int(x) for x in c.q[:nl]]
+        ct = np.stack([np.stack([rng.integers(0, q, n, dtype=np.uint64) for q in qs]) for _ in range(3)])
+        for t, g in zip(steps, gal):
+            u = _keyswitch_int(c, swk[g], ct[1], level, g)
+            want = u.copy()
+            for i, q in enumerate(qs):
+                s0 = _sigma_int([int(x) for x in ct[0, i]], g)
+                want[0, i] = [(int(a) + b) % q for a, b in zip(u[0, i], s0)]
+            assert np.array_equal(k.rotate(ct[:2], level, t), want), f"rotation {t} at level {level}"
+        u = _keyswitch_int(c, swk[0], ct[2], level, 0)
+        want = np.stack([np.stack([(u[p, i].astype(object) + ct[p, i].astype(object)) % q for i, q in enumerate(qs)]) for p in range(2)]).astype(np.uint64)
+        assert np.array_equal(k.relinearize(ct, level), want), f"relinearisation at level {level}"
 
 
 def test_relinearize_invariant(orc):
