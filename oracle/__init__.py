@@ -99,6 +99,13 @@ def lib():
             "orc_matmul_cc_sv": (C.c_int, [vp, _u64p, _u64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p,
                                            _u64p]),
             "orc_matmul_cp_diag": (C.c_int, [vp, _u64p, C.c_int, _f64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, _u64p]),
+            "orc_ks_counts": (None, [_i64p, C.c_int]),
+            "orc_cc_bsgs_split": (None, [vp, C.c_int, C.c_int, C.c_int, _i32p]),
+            "orc_cc_galois_bsgs": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, _u64p]),
+            "orc_matmul_cc_sched": (C.c_int, [vp, _u64p, _u64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                              C.c_void_p, _u64p]),
+            "orc_matmul_cc_sv_sched": (C.c_int, [vp, _u64p, _u64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                                 C.c_void_p, _u64p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -106,6 +113,13 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+def ks_counts(reset: bool = False) -> tuple:
+    """(rotations, relinearisations) key-switched since the last reset"""
+    out = np.zeros(2, np.int64)
+    lib().orc_ks_counts(out, 1 if reset else 0)
+    return int(out[0]), int(out[1])
 
 
 def num_threads() -> int:
@@ -259,10 +273,18 @@ class Context:
         lib().orc_cc_geometry(self._p, H_g, L, d, g)
         return dict(zip(["Lp", "c", "n_ct", "n_out"], [int(v) for v in g]))
 
-    def cc_galois(self, H_g, L, d) -> np.ndarray:
+    def cc_galois(self, H_g, L, d, schedule: int = 0) -> np.ndarray:
+        """Galois elements one head group's matmul_cc uses (schedule 1: BSGS; duplicates removed)"""
         out = np.zeros(4096, np.uint64)
-        k = lib().orc_cc_galois(self._p, H_g, L, d, out)
-        return out[:k].copy()
+        f = lib().orc_cc_galois_bsgs if schedule else lib().orc_cc_galois
+        k = f(self._p, H_g, L, d, out)
+        return np.unique(out[:k])
+
+    def cc_bsgs_split(self, H_g, L, d) -> dict:
+        """BSGS split of step 2 (B baby x G giant = L') and of step 1 (b1 x g1 = c)"""
+        g = np.zeros(4, np.int32)
+        lib().orc_cc_bsgs_split(self._p, H_g, L, d, g)
+        return dict(zip(["B", "G", "b1", "g1"], [int(v) for v in g]))
 
     def cc_sv_geometry(self, H_g, L, d_v) -> dict:
         """Softmax x V_h for one head group: L', c, operand cts (reduction d = L), dense outputs
@@ -388,7 +410,8 @@ class Keys:
             raise ValueError("rerandomize: bad arguments")
         return out
 
-    def matmul_cc(self, A_cts, Bp_cts, level: int, H_g: int, L: int, d: int, outputs=None, b_prerotated=True) -> np.ndarray:
+    def matmul_cc(self, A_cts, Bp_cts, level: int, H_g: int, L: int, d: int, outputs=None, b_prerotated=True,
+                  schedule: int = 0) -> np.ndarray:
         """One head group; A_cts / Bp_cts: [n_ct][2][level+1][N]; returns [n_out][2][level-2][N]
         (B pre-rotated by the client) or [n_out][2][level-3][N] (step 1 run homomorphically)."""
         c = self.ctx
@@ -399,13 +422,14 @@ class Keys:
             m = np.zeros(g["n_out"], np.uint8)
             m[list(outputs)] = 1
             mask = m.ctypes.data_as(C.c_void_p)
-        rc = lib().orc_matmul_cc(self._p, _c(A_cts, np.uint64), _c(Bp_cts, np.uint64), g["n_ct"], level, H_g, L, d,
-                                 1 if b_prerotated else 0, mask, O)
+        rc = lib().orc_matmul_cc_sched(self._p, _c(A_cts, np.uint64), _c(Bp_cts, np.uint64), g["n_ct"], level, H_g, L, d,
+                                       1 if b_prerotated else 0, schedule, mask, O)
         if rc != 0:
             raise ValueError(f"matmul_cc failed ({rc})")
         return O
 
-    def matmul_cc_sv(self, A_cts, B_cts, level: int, H_g: int, L: int, d_v: int, outputs=None, b_prerotated=True) -> np.ndarray:
+    def matmul_cc_sv(self, A_cts, B_cts, level: int, H_g: int, L: int, d_v: int, outputs=None, b_prerotated=True,
+                     schedule: int = 0) -> np.ndarray:
         """Softmax x V_h for one head group (A = attention weights, L x L; B = V_h, L x d_v, zero-padded
         to L' columns); returns the dense diagonal-packed outputs [d_v'/c][2][level-2 or level-3][N]"""
         c = self.ctx
@@ -418,8 +442,8 @@ class Keys:
             m = np.zeros(g["n_out"], np.uint8)
             m[list(outputs)] = 1
             mask = m.ctypes.data_as(C.c_void_p)
-        rc = lib().orc_matmul_cc_sv(self._p, _c(A_cts, np.uint64), _c(B_cts, np.uint64), g["n_ct"], level, H_g, L, d_v,
-                                    1 if b_prerotated else 0, mask, O)
+        rc = lib().orc_matmul_cc_sv_sched(self._p, _c(A_cts, np.uint64), _c(B_cts, np.uint64), g["n_ct"], level, H_g, L, d_v,
+                                          1 if b_prerotated else 0, schedule, mask, O)
         if rc != 0:
             raise ValueError(f"matmul_cc_sv failed ({rc})")
         return O

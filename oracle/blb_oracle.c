@@ -654,6 +654,14 @@ static void key_switch(const orc_ctx* c, const orc_swk* key, const uint64_t* d, 
   free(acc0); free(acc1);
 }
 
+/* Key switches performed since the last reset (rotations with g != 1, relinearisations): the
+ * schedules' operation counts are checked against their closed forms through these. */
+static long g_n_rot = 0, g_n_relin = 0;
+void orc_ks_counts(int64_t out[2], int reset) {
+  out[0] = g_n_rot; out[1] = g_n_relin;
+  if (reset) g_n_rot = g_n_relin = 0;
+}
+
 /* rotate left by `steps` slots: (sigma_g(c0) + u0, u1), (u0,u1) = KS_hoisted(c1) */
 int orc_rotate(const orc_keys* K, const uint64_t* ct, int level, int64_t steps, uint64_t* out) {
   const orc_ctx* c = K->c; int n = c->n, nl = level + 1;
@@ -661,6 +669,7 @@ int orc_rotate(const orc_keys* K, const uint64_t* ct, int level, int64_t steps, 
   if (g == 1) { memcpy(out, ct, 8 * (size_t)2 * nl * n); return 0; }
   const orc_swk* key = find_key(K, g);
   if (!key) return -1;
+  ++g_n_rot;
   uint64_t* u0 = (uint64_t*)malloc(8 * (size_t)nl * n);
   uint64_t* u1 = (uint64_t*)malloc(8 * (size_t)nl * n);
   key_switch(c, key, ct + (size_t)nl * n, level, g, u0, u1);
@@ -681,6 +690,7 @@ int orc_relinearize(const orc_keys* K, const uint64_t* ct3, int level, uint64_t*
   const orc_ctx* c = K->c; int n = c->n, nl = level + 1;
   const orc_swk* key = find_key(K, 0);
   if (!key) return -1;
+  ++g_n_relin;
   uint64_t* u0 = (uint64_t*)malloc(8 * (size_t)nl * n);
   uint64_t* u1 = (uint64_t*)malloc(8 * (size_t)nl * n);
   key_switch(c, key, ct3 + (size_t)2 * nl * n, level, 1, u0, u1);
@@ -1263,12 +1273,229 @@ static int cc_step1(const orc_keys* K, const uint64_t* A, const uint64_t* B, int
   return rc;
 }
 
+/* ------------------------------------------------------------------------------------ */
+/* matmul_cc with BSGS (Appendix "BSGS Optimization", figure bsgs): baby-step inner       */
+/* rotations of B', giant-step inner rotations of A, and the giant step's own rotation     */
+/* postponed into step 3                                                                   */
+/* ------------------------------------------------------------------------------------ */
+/* Split of the L' inner rotations of step 2 and of the c row classes of step 1: a fixed rule
+ * (it changes bits), B = 2^ceil(log2(L')/2), G = L'/B; b1 = 2^ceil(log2(c)/2), g1 = c/b1. */
+void orc_cc_bsgs_split(const orc_ctx* c, int H_g, int L, int d, int32_t* out /* [4] */) {
+  int32_t geo[4]; orc_cc_geometry(c, H_g, L, d, geo);
+  int lb = ceil_log2(geo[0]), lc = ceil_log2(geo[1]);
+  out[0] = 1 << ((lb + 1) / 2); out[1] = geo[0] / out[0];
+  out[2] = 1 << ((lc + 1) / 2); out[3] = geo[1] / out[2];
+}
+
+/* slot vector v rotated left by r slots (out[k] = v[(k + r) mod S]); r may be negative */
+static void rot_vec(int s, const double* v, int64_t r, double* out) {
+  int64_t rr = ((r % s) + s) % s;
+  for (int k = 0; k < s; ++k) out[k] = v[(k + rr) % s];
+}
+
+/* Inner rotation of a ciphertext: every block of L' slots rotated left by t within itself,
+ *   Rescale( Rot_l^t(x) (.) M^lo_t + Rot_r^{L'-t}(x) (.) M^hi_t )   (t = 0: x (.) M^lo_0),
+ * masks encoded at `dm`; x at `level`, result at level-1. */
+static int inner_rot(const orc_keys* K, const uint64_t* x, int level, int lp, int t, double dm, uint64_t* out) {
+  const orc_ctx* c = K->c;
+  int n = c->n, s = n / 2, nl = level + 1;
+  size_t w = (size_t)2 * nl * n;
+  double* v = (double*)malloc(8 * s);
+  uint64_t* rot = (uint64_t*)malloc(8 * w);
+  uint64_t* acc = (uint64_t*)calloc(w, 8);
+  int rc = 0;
+  if (t == 0) {
+    mask_lo(s, lp, 0, v); mac_vec(c, acc, v, dm, x, level);
+  } else if (orc_rotate(K, x, level, t, rot) != 0) {
+    rc = -1;
+  } else {
+    mask_lo(s, lp, t, v); mac_vec(c, acc, v, dm, rot, level);
+    if (orc_rotate(K, x, level, -(int64_t)(lp - t), rot) != 0) rc = -1;
+    else { mask_hi(s, lp, t, v); mac_vec(c, acc, v, dm, rot, level); }
+  }
+  if (rc == 0) orc_rescale(c, acc, level, 2, out);
+  free(v); free(rot); free(acc);
+  return rc;
+}
+
+/* Steps 2-3 with BSGS.  Inputs at `level` (A_a and pre-rotated B'_a).  With t = j B + i:
+ *   T_t = sum_a A_a (x) InnerRot_t(B'_a) = InnerRot_{jB}( sum_a InnerRot_{-jB}(A_a) (x) InnerRot_i(B'_a) ),
+ * because an inner rotation is the same slot permutation in every block and the elementwise
+ * product commutes with it.  So
+ *   Y_{a,i}  = InnerRot_i(2^10 B'_a), masks at q_level 2^10               (baby steps, i < B)
+ *   A'_{a,j} = InnerRot_{L'-jB}(2^10 A_a), masks at q_level / 2^10 (j >= 1),  Drop(A_a) for j = 0
+ *   U_t      = Rescale( Relin( sum_a A'_{a,j} (x) Y_{a,i} ) ),  V_t = Rot_r^{tau H_g L'}(U_t)
+ * and InnerRot_{jB} commutes with the step-3 block rotation and block masks.  Step 3 therefore
+ * splits each V_t of giant step j >= 1 with the product masks M^{>=tau} H_j, M^{>=tau} Lo_j (into
+ * O_g) and M^{<tau} H_j, M^{<tau} Lo_j (into O_{g+1}), where H_j keeps the in-block positions
+ * >= jB and Lo_j the others; every accumulator (g, j, H) is rotated left by jB and every (g, j, Lo)
+ * right by L' - jB before it joins O_g (one extra mask product per V_t and one rotation per
+ * accumulator: the giant step of step 2 done once per output instead of once per ciphertext).
+ * j = 0 accumulates straight into O_g as in the plain schedule.  Step-3 masks at q_{level-2} / 2^10;
+ * O_g = Rescale(O_g).  Outputs and folding (n_dense) as in cc_steps23. */
+static int cc_steps23_bsgs(const orc_keys* K, const uint64_t* A, const uint64_t* Bp, int n_ct, int level, int H_g, int L, int d,
+                           int n_dense, const uint8_t* out_mask, uint64_t* O) {
+  const orc_ctx* c = K->c;
+  int n = c->n, s = n / 2;
+  if (level < 3) return -2;
+  int32_t geo[4]; orc_cc_geometry(c, H_g, L, d, geo);
+  int lp = geo[0], cc = geo[1], n_out = geo[3];
+  if (n_ct != geo[2] || cc < 1 || cc > lp || lp * H_g * cc != s) return -3;
+  if (n_dense < 1 || n_out % n_dense) return -3;
+  int32_t sp[4]; orc_cc_bsgs_split(c, H_g, L, d, sp);
+  int Bb = sp[0], Gg = sp[1];
+  int nl = level + 1, l2 = level - 1, l1 = level - 2;
+  size_t w3 = (size_t)2 * nl * n, w2 = (size_t)2 * (l2 + 1) * n, w1 = (size_t)2 * (l1 + 1) * n;
+  double dmB = (double)c->mod[level] * 1024.0, dmA = (double)c->mod[level] / NOISE_BOOST, dm3 = (double)c->mod[l1] / NOISE_BOOST;
+  int blk = lp * H_g;
+  /* which t feed a selected output */
+  uint8_t* need_t = (uint8_t*)calloc(lp, 1);
+  uint8_t* need_i = (uint8_t*)calloc(Bb, 1);
+  uint8_t* need_j = (uint8_t*)calloc(Gg, 1);
+  for (int t = 0; t < lp; ++t) {
+    int g = (t / cc) % n_dense, tau = t % cc, g2 = ((t / cc + 1) % n_out) % n_dense;
+    if (!out_mask || out_mask[g] || (tau > 0 && out_mask[g2])) { need_t[t] = 1; need_i[t % Bb] = 1; need_j[t / Bb] = 1; }
+  }
+  uint64_t* tmp = (uint64_t*)malloc(8 * w3);
+  uint64_t* Y = (uint64_t*)calloc((size_t)n_ct * Bb * w2, 8);
+  uint64_t* Ap = (uint64_t*)calloc((size_t)n_ct * Gg * w2, 8);
+  int rc = 0;
+  /* baby steps on B', giant steps on A (both noise-boosted) */
+  for (int a = 0; a < n_ct && rc == 0; ++a) {
+    scale_ct(c, Bp + (size_t)a * w3, (uint64_t)NOISE_BOOST, nl, tmp);
+    for (int i = 0; i < Bb && rc == 0; ++i)
+      if (need_i[i]) rc = inner_rot(K, tmp, level, lp, i, dmB, Y + ((size_t)a * Bb + i) * w2);
+    const uint64_t* aa = A + (size_t)a * w3;
+    for (int p = 0; p < 2; ++p)
+      memcpy(Ap + (size_t)a * Gg * w2 + (size_t)p * (l2 + 1) * n, aa + (size_t)p * nl * n, 8 * (size_t)(l2 + 1) * n);
+    scale_ct(c, aa, (uint64_t)NOISE_BOOST, nl, tmp);
+    for (int j = 1; j < Gg && rc == 0; ++j)
+      if (need_j[j]) rc = inner_rot(K, tmp, level, lp, lp - j * Bb, dmA, Ap + ((size_t)a * Gg + j) * w2);
+  }
+  double* v = (double*)malloc(8 * s);
+  double* mv = (double*)malloc(8 * s);
+  uint64_t* T3 = (uint64_t*)malloc(8 * (size_t)3 * (l2 + 1) * n);
+  uint64_t* T = (uint64_t*)malloc(8 * w2);
+  uint64_t* U = (uint64_t*)malloc(8 * w1);
+  uint64_t* V = (uint64_t*)malloc(8 * w1);
+  uint64_t* acc = (uint64_t*)calloc((size_t)n_dense * w1, 8);
+  /* giant-step accumulators: [g][j][part], part 0 = H_j (positions >= jB), 1 = Lo_j */
+  uint64_t* accj = (uint64_t*)calloc((size_t)n_dense * Gg * 2 * w1, 8);
+  uint8_t* used = (uint8_t*)calloc((size_t)n_dense * Gg * 2, 1);
+  for (int t = 0; t < lp && rc == 0; ++t) {
+    if (!need_t[t]) continue;
+    int j = t / Bb, i = t % Bb;
+    int g = (t / cc) % n_dense, tau = t % cc, g2 = ((t / cc + 1) % n_out) % n_dense;
+    memset(T3, 0, 8 * (size_t)3 * (l2 + 1) * n);
+    for (int a = 0; a < n_ct; ++a) tensor_acc(c, T3, Ap + ((size_t)a * Gg + j) * w2, Y + ((size_t)a * Bb + i) * w2, l2 + 1);
+    if (orc_relinearize(K, T3, l2, T) != 0) { rc = -1; break; }
+    orc_rescale(c, T, l2, 2, U);
+    if (tau == 0) memcpy(V, U, 8 * w1);
+    else if (orc_rotate(K, U, l1, -(int64_t)tau * blk, V) != 0) { rc = -1; break; }
+    for (int side = 0; side < 2; ++side) {          /* side 0: M^{>=tau} into O_g; 1: M^{<tau} into O_{g+1} */
+      int go = side == 0 ? g : g2;
+      if (side == 1 && tau == 0) continue;
+      if (out_mask && !out_mask[go]) continue;
+      if (side == 0) mask_blk_ge(s, blk, tau, v); else mask_blk_lt(s, blk, tau, v);
+      if (j == 0) { mac_vec(c, acc + (size_t)go * w1, v, dm3, V, l1); continue; }
+      for (int part = 0; part < 2; ++part) {
+        for (int k = 0; k < s; ++k) {
+          int in_hi = (k % lp) >= j * Bb;
+          mv[k] = v[k] * ((part == 0) == in_hi ? 1.0 : 0.0);
+        }
+        size_t slot = ((size_t)go * Gg + j) * 2 + part;
+        mac_vec(c, accj + slot * w1, mv, dm3, V, l1);
+        used[slot] = 1;
+      }
+    }
+  }
+  /* the postponed giant-step rotations: (g, j, H_j) left by jB, (g, j, Lo_j) right by L' - jB */
+  for (int g = 0; g < n_dense && rc == 0; ++g)
+    for (int j = 1; j < Gg && rc == 0; ++j)
+      for (int part = 0; part < 2 && rc == 0; ++part) {
+        size_t slot = ((size_t)g * Gg + j) * 2 + part;
+        if (!used[slot]) continue;
+        int64_t steps = part == 0 ? (int64_t)j * Bb : -(int64_t)(lp - j * Bb);
+        if (orc_rotate(K, accj + slot * w1, l1, steps, V) != 0) { rc = -1; break; }
+        add_ct(c, acc + (size_t)g * w1, V, l1 + 1, 2);
+      }
+  if (rc == 0)
+    for (int g = 0; g < n_dense; ++g)
+      if (!out_mask || out_mask[g]) orc_rescale(c, acc + (size_t)g * w1, l1, 2, O + (size_t)g * 2 * l1 * n);
+  free(need_t); free(need_i); free(need_j); free(tmp); free(Y); free(Ap); free(v); free(mv); free(T3); free(T); free(U); free(V);
+  free(acc); free(accj); free(used);
+  return rc;
+}
+
+/* Step 1 with BSGS: with kappa = j b1 + i and B''_a = 2^10 B_a,
+ *   sum_kappa Rot_l^kappa(B'') (.) M^1_kappa = sum_j Rot_l^{j b1}( sum_i Rot_l^i(B'') (.) Rot_r^{j b1}(M^1_kappa) )
+ *   sum_kappa Rot_r^{L'-kappa}(B'') (.) M^2_kappa = sum_j Rot_r^{L'-j b1}( sum_i Rot_l^i(B'') (.) Rot_l^{L'-j b1}(M^2_kappa) )
+ * (M^1_0 = M^0, M^2_0 = 0), the rotation of a product being the product of the rotations.  Both
+ * sums share the b1 - 1 baby rotations Rot_l^i(B''); the giant rotations (g1 - 1 left, g1 right)
+ * act on the partial sums, before the one rescale.  Pre-rotated masks are exact slot permutations
+ * of the plain schedule's masks, encoded at q_level / 2^10.  Output as cc_step1. */
+static int cc_step1_bsgs(const orc_keys* K, const uint64_t* A, const uint64_t* B, int n_ct, int level, int H_g, int L, int d,
+                         uint64_t* Ad, uint64_t* Bq) {
+  const orc_ctx* c = K->c;
+  int n = c->n, s = n / 2;
+  int32_t geo[4]; orc_cc_geometry(c, H_g, L, d, geo);
+  int lp = geo[0];
+  int32_t sp[4]; orc_cc_bsgs_split(c, H_g, L, d, sp);
+  int b1 = sp[2], g1 = sp[3];
+  int nl = level + 1;
+  size_t w = (size_t)2 * nl * n, wq = (size_t)2 * level * n;
+  double dm1 = (double)c->mod[level] / NOISE_BOOST;
+  double* v = (double*)malloc(8 * s);
+  double* rv = (double*)malloc(8 * s);
+  uint64_t* X = (uint64_t*)malloc(8 * w * (size_t)b1);
+  uint64_t* part = (uint64_t*)malloc(8 * w);
+  uint64_t* rot = (uint64_t*)malloc(8 * w);
+  uint64_t* acc = (uint64_t*)malloc(8 * w);
+  int rc = 0;
+  for (int a = 0; a < n_ct && rc == 0; ++a) {
+    scale_ct(c, B + (size_t)a * w, (uint64_t)NOISE_BOOST, nl, X);
+    for (int i = 1; i < b1 && rc == 0; ++i)
+      if (orc_rotate(K, X, level, i, X + (size_t)i * w) != 0) rc = -1;
+    if (rc) break;
+    memset(acc, 0, 8 * w);
+    for (int j = 0; j < g1 && rc == 0; ++j) {
+      for (int fam = 0; fam < 2 && rc == 0; ++fam) {   /* fam 0: left family M^1, 1: right family M^2 */
+        memset(part, 0, 8 * w);
+        int terms = 0;
+        for (int i = 0; i < b1; ++i) {
+          int kap = j * b1 + i;
+          if (fam == 1 && kap == 0) continue;
+          if (fam == 0) mask_cls(s, lp, H_g, kap, 0, kap == 0 ? lp : lp - kap, v);
+          else mask_cls(s, lp, H_g, kap, lp - kap, lp, v);
+          if (fam == 0) rot_vec(s, v, -(int64_t)j * b1, rv);          /* Rot_r^{j b1} */
+          else rot_vec(s, v, (int64_t)(lp - j * b1), rv);             /* Rot_l^{L' - j b1} */
+          mac_vec(c, part, rv, dm1, X + (size_t)i * w, level);
+          ++terms;
+        }
+        if (!terms) continue;
+        int64_t steps = fam == 0 ? (int64_t)j * b1 : -(int64_t)(lp - j * b1);
+        if (orc_rotate(K, part, level, steps, rot) != 0) { rc = -1; break; }
+        add_ct(c, acc, rot, nl, 2);
+      }
+    }
+    if (rc) break;
+    orc_rescale(c, acc, level, 2, Bq + (size_t)a * wq);
+    const uint64_t* aa = A + (size_t)a * w;
+    for (int p = 0; p < 2; ++p) memcpy(Ad + (size_t)a * wq + (size_t)p * level * n, aa + (size_t)p * nl * n, 8 * (size_t)level * n);
+  }
+  free(v); free(rv); free(X); free(part); free(rot); free(acc);
+  return rc;
+}
+
 /* One head group of matmul_cc.  b_prerotated != 0: B_a arrive pre-rotated by the client
  * (step 1 applied to the plaintext), inputs at `level` >= 3, output at level-3; else step 1
  * runs homomorphically first, inputs at `level` >= 4, output at level-4. */
 static int cc_run(const orc_keys* K, const uint64_t* A, const uint64_t* B, int n_ct, int level, int H_g, int L, int d, int b_prerotated,
-                  int n_dense, const uint8_t* out_mask, uint64_t* O) {
-  if (b_prerotated) return cc_steps23(K, A, B, n_ct, level, H_g, L, d, n_dense, out_mask, O);
+                  int schedule, int n_dense, const uint8_t* out_mask, uint64_t* O) {
+  if (schedule != 0 && schedule != 1) return -3;
+  if (b_prerotated)
+    return schedule ? cc_steps23_bsgs(K, A, B, n_ct, level, H_g, L, d, n_dense, out_mask, O)
+                    : cc_steps23(K, A, B, n_ct, level, H_g, L, d, n_dense, out_mask, O);
   const orc_ctx* c = K->c;
   if (level < 4) return -2;
   int32_t geo[4]; orc_cc_geometry(c, H_g, L, d, geo);
@@ -1276,16 +1503,26 @@ static int cc_run(const orc_keys* K, const uint64_t* A, const uint64_t* B, int n
   size_t wq = (size_t)2 * level * c->n * n_ct;
   uint64_t* Ad = (uint64_t*)malloc(8 * wq);
   uint64_t* Bq = (uint64_t*)malloc(8 * wq);
-  int rc = cc_step1(K, A, B, n_ct, level, H_g, L, d, Ad, Bq);
-  if (rc == 0) rc = cc_steps23(K, Ad, Bq, n_ct, level - 1, H_g, L, d, n_dense, out_mask, O);
+  int rc = schedule ? cc_step1_bsgs(K, A, B, n_ct, level, H_g, L, d, Ad, Bq) : cc_step1(K, A, B, n_ct, level, H_g, L, d, Ad, Bq);
+  if (rc == 0)
+    rc = schedule ? cc_steps23_bsgs(K, Ad, Bq, n_ct, level - 1, H_g, L, d, n_dense, out_mask, O)
+                  : cc_steps23(K, Ad, Bq, n_ct, level - 1, H_g, L, d, n_dense, out_mask, O);
   free(Ad); free(Bq);
   return rc;
 }
 
+/* schedule 0: one inner rotation of every B'_a per t (steps 1-3 as written in "Building Blocks");
+ * schedule 1: BSGS in steps 1 and 2 with the giant step folded into step 3 (Appendix "BSGS
+ * Optimization").  Both decode to the same product; their words differ. */
+int orc_matmul_cc_sched(const orc_keys* K, const uint64_t* A, const uint64_t* B, int n_ct, int level, int H_g, int L, int d,
+                        int b_prerotated, int schedule, const uint8_t* out_mask, uint64_t* O) {
+  int32_t geo[4]; orc_cc_geometry(K->c, H_g, L, d, geo);
+  return cc_run(K, A, B, n_ct, level, H_g, L, d, b_prerotated, schedule, geo[3], out_mask, O);
+}
+
 int orc_matmul_cc(const orc_keys* K, const uint64_t* A, const uint64_t* B, int n_ct, int level, int H_g, int L, int d, int b_prerotated,
                   const uint8_t* out_mask, uint64_t* O) {
-  int32_t geo[4]; orc_cc_geometry(K->c, H_g, L, d, geo);
-  return cc_run(K, A, B, n_ct, level, H_g, L, d, b_prerotated, geo[3], out_mask, O);
+  return orc_matmul_cc_sched(K, A, B, n_ct, level, H_g, L, d, b_prerotated, 0, out_mask, O);
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -1308,11 +1545,16 @@ void orc_cc_sv_geometry(const orc_ctx* c, int H_g, int L, int d_v, int32_t* out 
   out[4] = dvp;
 }
 
-int orc_matmul_cc_sv(const orc_keys* K, const uint64_t* A, const uint64_t* B, int n_ct, int level, int H_g, int L, int d_v,
-                     int b_prerotated, const uint8_t* out_mask, uint64_t* O) {
+int orc_matmul_cc_sv_sched(const orc_keys* K, const uint64_t* A, const uint64_t* B, int n_ct, int level, int H_g, int L, int d_v,
+                           int b_prerotated, int schedule, const uint8_t* out_mask, uint64_t* O) {
   int32_t geo[5]; orc_cc_sv_geometry(K->c, H_g, L, d_v, geo);
   if (geo[3] < 1) return -3;
-  return cc_run(K, A, B, n_ct, level, H_g, L, L, b_prerotated, geo[3], out_mask, O);
+  return cc_run(K, A, B, n_ct, level, H_g, L, L, b_prerotated, schedule, geo[3], out_mask, O);
+}
+
+int orc_matmul_cc_sv(const orc_keys* K, const uint64_t* A, const uint64_t* B, int n_ct, int level, int H_g, int L, int d_v,
+                     int b_prerotated, const uint8_t* out_mask, uint64_t* O) {
+  return orc_matmul_cc_sv_sched(K, A, B, n_ct, level, H_g, L, d_v, b_prerotated, 0, out_mask, O);
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -1366,5 +1608,25 @@ int orc_cc_galois(const orc_ctx* c, int H_g, int L, int d, uint64_t* out) {
   int lp = geo[0], cc = geo[1], cnt = 0;
   for (int t = 1; t < lp; ++t) { out[cnt++] = galois_left(c, t); out[cnt++] = galois_left(c, -(int64_t)(lp - t)); }
   for (int tau = 1; tau < cc; ++tau) out[cnt++] = galois_left(c, -(int64_t)tau * H_g * lp);
+  return cnt;
+}
+
+/* Galois elements of one group's BSGS schedule (steps 1-3), duplicates included:
+ * baby left i / right L'-i (i < B), giant on A left L'-jB / right jB and the postponed giant
+ * rotations left jB / right L'-jB (0 < j < G), step 3 right tau H_g L', and for step 1 left i
+ * (i < b1), left j b1 (0 < j < g1), right L' - j b1 (j < g1).  out holds at least 2B + 4G + c + 2 b1 + 2 g1. */
+int orc_cc_galois_bsgs(const orc_ctx* c, int H_g, int L, int d, uint64_t* out) {
+  int32_t geo[4]; orc_cc_geometry(c, H_g, L, d, geo);
+  int32_t sp[4]; orc_cc_bsgs_split(c, H_g, L, d, sp);
+  int lp = geo[0], cc = geo[1], Bb = sp[0], Gg = sp[1], b1 = sp[2], g1 = sp[3], cnt = 0;
+  for (int i = 1; i < Bb; ++i) { out[cnt++] = galois_left(c, i); out[cnt++] = galois_left(c, -(int64_t)(lp - i)); }
+  for (int j = 1; j < Gg; ++j) {
+    out[cnt++] = galois_left(c, lp - j * Bb); out[cnt++] = galois_left(c, -(int64_t)j * Bb);
+    out[cnt++] = galois_left(c, j * Bb); out[cnt++] = galois_left(c, -(int64_t)(lp - j * Bb));
+  }
+  for (int tau = 1; tau < cc; ++tau) out[cnt++] = galois_left(c, -(int64_t)tau * H_g * lp);
+  for (int i = 1; i < b1; ++i) out[cnt++] = galois_left(c, i);
+  for (int j = 1; j < g1; ++j) out[cnt++] = galois_left(c, j * b1);
+  for (int j = 0; j < g1; ++j) out[cnt++] = galois_left(c, -(int64_t)(lp - j * b1));
   return cnt;
 }

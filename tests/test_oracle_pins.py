@@ -782,6 +782,104 @@ def test_matmul_cc_decodes_to_qkt(orc, H_g, L, d, prerot):
             assert np.abs(got[0][h][L:, :]).max() < 1e-4 and np.abs(got[0][h][:, L:]).max() < 1e-4
 
 
+def _bsgs_rotation_count(lp, cc, n_ct, B, G, b1, g1, n_dense, hom1):
+    """Rotations of one head group's BSGS schedule, counted from its definition: two per inner
+    rotation of B' (i < B) and of A (0 < j < G), one step-3 rotation per t with tau != 0, one
+    postponed giant rotation per (output, giant step j > 0, half) that receives a term, and for
+    step 1 on the server b1 - 1 baby plus 2 g1 - 1 giant rotations per B ciphertext."""
+    n_diag = lp // cc
+    r = 2 * n_ct * (B - 1) + 2 * n_ct * (G - 1) + sum(1 for t in range(lp) if t % cc)
+    for j in range(1, G):
+        outs = set()
+        for t in range(j * B, j * B + B):
+            outs.add((t // cc) % n_dense)
+            if t % cc:
+                outs.add(((t // cc + 1) % n_diag) % n_dense)
+        r += 2 * len(outs)
+    if hom1:
+        r += n_ct * ((b1 - 1) + (g1 - 1) + g1 - (1 if b1 == 1 else 0))
+    return r
+
+
+@pytest.mark.parametrize("H_g,L,d,prerot", [(2, 32, 64, True), (4, 20, 32, True), (4, 20, 32, False), (8, 16, 16, False)])
+def test_matmul_cc_bsgs_decodes_to_qkt(orc, H_g, L, d, prerot):
+    """The BSGS schedule (Appendix "BSGS Optimization": baby-step inner rotations of B', giant
+    steps taken on A and postponed into step 3 with one more mask product and one rotation per
+    giant-step accumulator; step 1 split into baby and giant rotations) decodes to Q_h K_h^T
+    within 2^-20 for every head, with the plain schedule's levels and output scale, and performs
+    exactly the rotations its closed form counts (and L' relinearisations).  A giant rotation in
+    the wrong direction, a product mask on the wrong half of a block or a mask pre-rotated the
+    wrong way breaks the decoded check."""
+    c, g, keys, Q, K, A, Bp, level, scale = _cc_small(orc, H_g, L, d, H_g + L, prerot)
+    keys = orc.Keys(c, 5, c.cc_galois(H_g, L, d, schedule=1))
+    sp = c.cc_bsgs_split(H_g, L, d)
+    assert sp["B"] * sp["G"] == g["Lp"] and sp["b1"] * sp["g1"] == g["c"]
+    orc.ks_counts(reset=True)
+    O = keys.matmul_cc(A, Bp, level, H_g, L, d, b_prerotated=prerot, schedule=1)
+    n_rot, n_relin = orc.ks_counts(reset=True)
+    assert n_relin == g["Lp"]
+    assert n_rot == _bsgs_rotation_count(g["Lp"], g["c"], g["n_ct"], sp["B"], sp["G"], sp["b1"], sp["g1"], g["n_out"], not prerot)
+    lp, cc = g["Lp"], g["c"]
+    out_scale = scale * 1024.0 * scale / float(c.q[2 if prerot else 3])
+    got = [np.zeros((lp, lp)) for _ in range(H_g)]
+    for gi in range(g["n_out"]):
+        v = c.decode(keys.decrypt(O[gi], 0), 0, out_scale)
+        for h in range(H_g):
+            for kap in range(cc):
+                D = gi * cc + kap
+                for i in range(lp):
+                    got[h][i, (i + D) % lp] = v[i + lp * (h + H_g * kap)]
+    for h in range(H_g):
+        ref = Q[h] @ K[h].T
+        assert np.abs(got[h][:L, :L] - ref).max() < 2.0 ** -20
+        if L < lp:
+            assert np.abs(got[h][L:, :]).max() < 1e-4 and np.abs(got[h][:, L:]).max() < 1e-4
+
+
+def test_matmul_cc_bsgs_selected_outputs_match_full_run(orc):
+    """Computing only some outputs of the BSGS schedule (the sampled full-size checks do this)
+    gives the same words as the full run for those outputs."""
+    c, g, keys, Q, K, A, Bp, level, scale = _cc_small(orc, 4, 20, 32, 3, True)
+    keys = orc.Keys(c, 5, c.cc_galois(4, 20, 32, schedule=1))
+    full = keys.matmul_cc(A, Bp, level, 4, 20, 32, schedule=1)
+    for o in range(g["n_out"]):
+        part = keys.matmul_cc(A, Bp, level, 4, 20, 32, outputs=[o], schedule=1)
+        assert np.array_equal(part[o], full[o])
+
+
+@pytest.mark.parametrize("log_n,H_g,L,d_v", [(12, 4, 32, 16), (12, 4, 20, 12)])
+def test_softmax_v_bsgs_dense_diagonals(orc, log_n, H_g, L, d_v):
+    """Softmax x V_h through the BSGS schedule: the fold of the diagonal accumulators happens after
+    the postponed giant rotations, and every dense output decodes to (S_h V_h) within 2^-20."""
+    c, g, keys, Sm, Vm, A, Bv, level, scale = _sv_small(orc, log_n, 4, H_g, L, d_v, log_n + L + d_v)
+    keys = orc.Keys(c, 5, c.cc_galois(H_g, L, L, schedule=1))
+    O = keys.matmul_cc_sv(A, Bv, level, H_g, L, d_v, schedule=1)
+    out_scale = scale * 1024.0 * scale / float(c.q[2])
+    lp, cg, dvp = g["Lp"], g["c"], g["dvp"]
+    ref = [Sm[h] @ Vm[h] for h in range(H_g)]
+    worst = 0.0
+    for o in range(g["n_out"]):
+        v = c.decode(keys.decrypt(O[o], 0), 0, out_scale)
+        want = _dense_diag_vec(ref, 0, H_g, lp, cg, o, L, d_v, dvp, c.slots)
+        worst = max(worst, np.abs(v - want).max())
+    assert worst < 2.0 ** -20
+
+
+def test_matmul_cc_bsgs_counts_bert_base():
+    """Closed-form rotation counts of the 12-head BERT-base Q_h K_h^T (L' = 128, d_head = 64,
+    8192 slots, groups 8 + 4): the plain schedule makes 2 (L' - 1) inner-rotation key switches per
+    B' ciphertext (3048) plus 232 step-3 rotations; the BSGS schedule (B = 16, G = 8) makes 830,
+    i.e. B + G - 2 = 22 inner rotations per operand pair instead of L' - 1 = 127, plus the
+    postponed giant rotations (70)."""
+    plain = sum(2 * n * 127 + (128 - 128 // c) for c, n in ((8, 8), (16, 4)))
+    assert plain == 3048 + 232
+    bsgs = sum(_bsgs_rotation_count(128, c, n, 16, 8, 4, 4 if c == 16 else 2, 128 // c, False) for c, n in ((8, 8), (16, 4)))
+    assert bsgs == 830
+    giant = sum(_bsgs_rotation_count(128, c, n, 16, 8, 4, 2, 128 // c, False) - 2 * n * (15 + 7) - (128 - 128 // c)
+                for c, n in ((8, 8), (16, 4)))
+    assert giant == 70
+
+
 def test_matmul_cc_counts():
     """Theoretical ct-ct multiplication count m^2 d / s of the paper's Table complexity_compare
     (BERT-large, s = 16384): 1024 for Q_h K_h^T and m^3 H / s = 2048 for Softmax x V_h; the
