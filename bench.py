@@ -185,8 +185,10 @@ def run_cp(args, B, torch):
     return res
 
 
-def run_cc(args, B, torch):
-    """12-head Q_h K_h^T (BERT-base shape, 128 tokens), N = 16384, 4 primes + 2 special (dnum 2)."""
+def run_cc(args, B, torch, schedule=1):
+    """12-head Q_h K_h^T (BERT-base shape, 128 tokens), N = 16384, 4 primes + 2 special (dnum 2);
+    schedule 0: an inner rotation of every B' ciphertext per diagonal, 1: BSGS (giant steps on A,
+    their rotation postponed into step 3)."""
     from paper_2508_19525_amd import workloads as wl
 
     cfg = wl.C3
@@ -199,9 +201,9 @@ def run_cc(args, B, torch):
     stream = torch.cuda.current_stream().cuda_stream
     ctx = B.blb_ctx_create(p.log_n, p.n_q, p.n_special, p.dnum, 0, stream)
     t_setup = time.time()
-    steps_rot = B.blb_cc_rotations(ctx, heads, L)
+    steps_rot = B.blb_cc_rotations(ctx, heads, L, schedule)
     keys = B.blb_keygen(ctx, wl.seed_for(3, wl.ROLE_KEYS), steps_rot)
-    plan = B.blb_plan_matmul_cc(ctx, heads, L, d, level)
+    plan = B.blb_plan_matmul_cc(ctx, heads, L, d, level, schedule=schedule)
     info = B.blb_plan_cc_info(plan)
     keep, A, Bp = [], [], []
     pt = torch.empty((level + 1) * n, dtype=torch.int64, device="cuda")
@@ -222,10 +224,12 @@ def run_cc(args, B, torch):
         keep.append(t)
         Cd.append(ct)
     torch.cuda.synchronize()
-    log(f"cc setup {time.time() - t_setup:.1f}s: {len(steps_rot)} rotation keys, plan {info}, "
+    log(f"cc (schedule {schedule}) setup {time.time() - t_setup:.1f}s: {len(steps_rot)} rotation keys, plan {info}, "
         f"device bytes {B.blb_ctx_device_bytes(ctx) / 1e9:.2f} GB")
-    # accuracy
+    # accuracy, and the operation counts of one product
+    B.blb_ctx_counters(ctx, reset=True)
     B.blb_matmul_cc(ctx, keys, plan, A, Bp, Cd)
+    counts = B.blb_ctx_counters(ctx, reset=True)
     err, h0, base = 0.0, 0, 0
     dec = torch.empty(n, dtype=torch.int64, device="cuda")
     for grp in info["groups"]:
@@ -282,9 +286,10 @@ def run_cc(args, B, torch):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     log(f"cc: eager {steps / dt_eager:.1f}/s, graph {steps / dt:.1f}/s")
-    res = {"value": steps / dt, "eager": steps / dt_eager, "ms": dt / steps * 1e3, "err": err, "split_ms": split,
+    res = {"schedule": schedule, "value": steps / dt, "eager": steps / dt_eager, "ms": dt / steps * 1e3, "err": err, "split_ms": split,
            "ntt_gbps": ntt_polys * 16 * n / (ntt_ms / 1e3) / 1e9 if ntt_ms > 0 else 0.0,
-           "rotation_keys": len(steps_rot), "groups": info["groups"],
+           "rotation_keys": len(steps_rot), "groups": info["groups"], "ops_per_product": counts,
+           "key_bytes": B.blb_ctx_device_bytes(ctx),
            "ntt_variant": B.blb_ctx_get_knob(ctx, B.BLB_KNOB_NTT_VARIANT), "ntt_tune_ms": ntt_tune,
            "ks_variant": ks_var, "ks_tune_ms": ks_tune}
     B.blb_exec_destroy(ex)
@@ -994,7 +999,8 @@ def main():
         return
     r = run_cp(args, B, torch)
     nt = None if args.no_ntt else run_ntt(args, B, torch)
-    cc = None if args.no_cc else run_cc(args, B, torch)
+    cc_by = {} if args.no_cc else {s: run_cc(args, B, torch, s) for s in (1, 0)}
+    cc = cc_by.get(1)
     ao = None if args.no_attn_out else run_attn_out(args, B, torch)
     qk = None if args.no_qk_fused else run_qk_fused(args, B, torch)
     so = None if args.no_small_ops else run_small_ops(args, B, torch)
@@ -1038,11 +1044,17 @@ def main():
         "autotune": {"mac_variant": r["mac_variant"], "mac_avg_ms_by_variant": r["mac_tune_ms"]},
         "accuracy": {"max_abs_err": r["err"], "mse": r["mse"], "tolerance": 2.0 ** -20},
         "matmul_cc": None if cc is None else {
-            "metric": "ct-ct matmul/s (12-head Q_h K_h^T, 128 tokens, N=16384, 4 primes + 2 special)",
+            "metric": "ct-ct matmul/s (12-head Q_h K_h^T, 128 tokens, N=16384, 4 primes + 2 special; BSGS schedule)",
             "value": cc["value"], "eager_value": cc["eager"], "ms": cc["ms"], "max_abs_err": cc["err"],
             "ntt_GBps": cc["ntt_gbps"], "split_ms": cc["split_ms"], "rotation_keys": cc["rotation_keys"],
+            "ops_per_product": cc["ops_per_product"],
             "ntt_variant": cc["ntt_variant"], "ntt_tune_ms_per_op": cc["ntt_tune_ms"],
-            "ks_variant": cc["ks_variant"], "ks_tune_ms_per_op": cc["ks_tune_ms"]},
+            "ks_variant": cc["ks_variant"], "ks_tune_ms_per_op": cc["ks_tune_ms"],
+            "by_schedule": {("bsgs" if k else "plain"): {"value": v["value"], "eager_value": v["eager"], "ms": v["ms"],
+                                                          "max_abs_err": v["err"], "ops_per_product": v["ops_per_product"],
+                                                          "rotation_keys": v["rotation_keys"], "split_ms": v["split_ms"],
+                                                          "ntt_GBps": v["ntt_gbps"], "device_bytes": v["key_bytes"]}
+                            for k, v in cc_by.items()}},
         "attention_output": None if ao is None else {
             "metric": "attention-output ops/s (Softmax x V_h for 12 heads of 128 tokens, d_v 64, zero-padded and folded; "
                       "Concat(Att_h) W_O 768x768 on the diagonal packing; mask-to-share of 12 cts; N=16384, 5 primes + 2 special)",

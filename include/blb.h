@@ -194,6 +194,30 @@ int blb_plan_cc_info(const blb_plan* plan, int32_t* info, int cap);
 int blb_matmul_cc(blb_ctx* ctx, const blb_keys* keys, const blb_plan* plan, const blb_ct* A, const blb_ct* Bp, int n_ct,
                   blb_ct* C_diag, int n_out);
 
+/* ---- matmul_cc with BSGS (Appendix "BSGS Optimization", figure bsgs) ------------------
+ * The same operands, outputs, levels and output scale as blb_plan_matmul_cc / _sv, computed by
+ * a second schedule (schedule = 1; schedule = 0 is the plain one above, and the two give
+ * different words that decode to the same product).  With L' = B G (B = 2^ceil(log2(L')/2))
+ * and t = j B + i, step 2 inner-rotates each B' ciphertext only by the baby steps i < B and each
+ * A ciphertext by the giant steps (right by jB, masks at q_level / 2^10 after a 2^10 boost), and
+ * the tensor of A'_{a,j} with Y_{a,i} is diagonal t rotated right by jB within its block.  Step 3
+ * undoes that rotation once per output instead of once per ciphertext: each rotated U_t of giant
+ * step j >= 1 is split with the product of its step-3 block mask and the half-block masks
+ * (in-block position >= jB or < jB), the halves accumulate per (output, j) and are rotated left
+ * by jB or right by L' - jB before joining the output.  Depth is unchanged.  Step 1 on the
+ * server (b_prerotated = 0) uses c = b1 g1 (b1 = 2^ceil(log2(c)/2)): b1 - 1 hoisted baby
+ * rotations shared by the left and right families, whose pre-rotated masks are summed per giant
+ * step and rotated left by j b1 (g1 - 1) or right by L' - j b1 (g1).  Rotations per group:
+ * 2 n_ct (B - 1) + 2 n_ct (G - 1) + (L' - L'/c) + 2 (number of (output, j >= 1) pairs that
+ * receive a term) [+ n_ct (b1 + 2 g1 - 2) for step 1]; relinearisations L'. */
+int blb_plan_matmul_cc_sched(blb_ctx* ctx, int n_heads, int L, int d_head, int level, int32_t b_prerotated, int32_t schedule,
+                             blb_plan** out);
+int blb_plan_matmul_cc_sv_sched(blb_ctx* ctx, int n_heads, int L, int d_v, int level, int32_t b_prerotated, int32_t schedule,
+                                blb_plan** out);
+/* Rotation steps of a schedule (as blb_cc_rotations, which is schedule 0); b_prerotated = 0 adds
+ * the server-side step 1's steps. */
+int blb_cc_rotations_sched(const blb_ctx* ctx, int n_heads, int L, int32_t b_prerotated, int32_t schedule, int32_t* steps, int cap);
+
 /* ---- matmul_cp feeding matmul_cc (Multi-Head Optimization; Section "Efficient Fused
  * Computations in Multi-Head Attention": the columns of W_Q / W_K reordered in plaintext) --------
  * A matmul_cp plan for W (host, d_in x (n_heads d_head) row-major, head h owning columns

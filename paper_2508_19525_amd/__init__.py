@@ -87,6 +87,11 @@ _SIGS = {
     "blb_plan_matmul_cp_diag": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                           C.POINTER(C.c_void_p)]),
     "blb_plan_cc_info": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "blb_cc_rotations_sched": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int32, C.c_int32, C.c_void_p, C.c_int]),
+    "blb_plan_matmul_cc_sched": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int32, C.c_int32,
+                                           C.POINTER(C.c_void_p)]),
+    "blb_plan_matmul_cc_sv_sched": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int32, C.c_int32,
+                                              C.POINTER(C.c_void_p)]),
     "blb_matmul_cc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.POINTER(blb_ct), C.c_int,
                                 C.POINTER(blb_ct), C.c_int]),
     "blb_exec_create_cp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.c_int, C.POINTER(blb_ct), C.c_int,
@@ -355,24 +360,30 @@ def blb_rerandomize(ctx, keys, cts, seed, flood_bits):
     _check(lib().blb_rerandomize(ctx, keys, arr, len(cts), seed, flood_bits), "blb_rerandomize")
 
 
-def blb_cc_rotations(ctx, n_heads, L):
-    k = lib().blb_cc_rotations(ctx, n_heads, L, None, 0)
+def blb_cc_rotations(ctx, n_heads, L, schedule=0, b_prerotated=True):
+    """Rotation steps matmul_cc needs (schedule 0: plain, 1: BSGS; b_prerotated=False adds the
+    server-side step 1's steps)"""
+    pre = 1 if b_prerotated else 0
+    k = lib().blb_cc_rotations_sched(ctx, n_heads, L, pre, schedule, None, 0)
     if k < 0:
         raise BlbError(k, "blb_cc_rotations")
     out = np.zeros(max(k, 1), np.int32)
-    _check(0 if lib().blb_cc_rotations(ctx, n_heads, L, _host_ptr(out), k) >= 0 else BLB_EINVAL, "blb_cc_rotations")
+    _check(0 if lib().blb_cc_rotations_sched(ctx, n_heads, L, pre, schedule, _host_ptr(out), k) >= 0 else BLB_EINVAL,
+           "blb_cc_rotations")
     return [int(x) for x in out[:k]]
 
 
-def blb_plan_matmul_cc(ctx, n_heads, L, d_head, level, b_prerotated=True):
+def blb_plan_matmul_cc(ctx, n_heads, L, d_head, level, b_prerotated=True, schedule=0):
     out = C.c_void_p()
-    _check(lib().blb_plan_matmul_cc(ctx, n_heads, L, d_head, level, 1 if b_prerotated else 0, C.byref(out)), "blb_plan_matmul_cc")
+    _check(lib().blb_plan_matmul_cc_sched(ctx, n_heads, L, d_head, level, 1 if b_prerotated else 0, schedule, C.byref(out)),
+           "blb_plan_matmul_cc")
     return out.value
 
 
-def blb_plan_matmul_cc_sv(ctx, n_heads, L, d_v, level, b_prerotated=True):
+def blb_plan_matmul_cc_sv(ctx, n_heads, L, d_v, level, b_prerotated=True, schedule=0):
     out = C.c_void_p()
-    _check(lib().blb_plan_matmul_cc_sv(ctx, n_heads, L, d_v, level, 1 if b_prerotated else 0, C.byref(out)), "blb_plan_matmul_cc_sv")
+    _check(lib().blb_plan_matmul_cc_sv_sched(ctx, n_heads, L, d_v, level, 1 if b_prerotated else 0, schedule, C.byref(out)),
+           "blb_plan_matmul_cc_sv")
     return out.value
 
 

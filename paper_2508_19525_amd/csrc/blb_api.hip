@@ -1665,20 +1665,40 @@ int encode_vectors_ntt(blb_ctx* c, const std::vector<double>& vecs, int count, d
 
 extern "C" {
 
-int blb_cc_rotations(const blb_ctx* c, int n_heads, int L, int32_t* steps, int cap) {
-  if (!c || n_heads < 1 || L < 1 || L > c->n / 2) return BLB_EINVAL;
+int blb_cc_rotations_sched(const blb_ctx* c, int n_heads, int L, int32_t b_prerotated, int32_t schedule, int32_t* steps, int cap) {
+  if (!c || n_heads < 1 || L < 1 || L > c->n / 2 || (schedule != 0 && schedule != 1)) return BLB_EINVAL;
   const int S = c->n / 2, lp = 1 << ceil_log2(L);
+  const int Bs = 1 << ((ceil_log2(lp) + 1) / 2), G = lp / Bs;
   std::vector<int> gs;
   cc_group_sizes(n_heads, gs);
   std::vector<int32_t> v;
-  for (int t = 1; t < lp; ++t) {
-    v.push_back(t);
-    v.push_back(-(lp - t));
+  if (schedule == 0) {
+    for (int t = 1; t < lp; ++t) {
+      v.push_back(t);
+      v.push_back(-(lp - t));
+    }
+  } else {
+    for (int i = 1; i < Bs; ++i) {  // baby inner rotations of B'
+      v.push_back(i);
+      v.push_back(-(lp - i));
+    }
+    for (int j = 1; j < G; ++j) {  // giant inner rotations of A and the postponed giant rotations
+      v.push_back(lp - j * Bs);
+      v.push_back(-(j * Bs));
+      v.push_back(j * Bs);
+      v.push_back(-(lp - j * Bs));
+    }
   }
   for (int H : gs) {
     if (S % (lp * H)) return BLB_EINVAL;
     const int cc = S / (lp * H);
     for (int tau = 1; tau < cc; ++tau) v.push_back(-(tau * H * lp));
+    if (schedule == 1 && !b_prerotated) {  // step 1: baby left i, giant left j b1, right L' - j b1
+      const int b1 = 1 << ((ceil_log2(cc) + 1) / 2), g1 = cc / b1;
+      for (int i = 1; i < b1; ++i) v.push_back(i);
+      for (int j = 1; j < g1; ++j) v.push_back(j * b1);
+      for (int j = 0; j < g1; ++j) v.push_back(-(lp - j * b1));
+    }
   }
   std::vector<int32_t> u;
   for (int32_t x : v) {
@@ -1693,12 +1713,18 @@ int blb_cc_rotations(const blb_ctx* c, int n_heads, int L, int32_t* steps, int c
   return (int)u.size();
 }
 
+int blb_cc_rotations(const blb_ctx* c, int n_heads, int L, int32_t* steps, int cap) {
+  return blb_cc_rotations_sched(c, n_heads, L, 1, 0, steps, cap);
+}
+
 }  // extern "C"
 
 // matmul_cc plan; fold_dv > 0 (Softmax x V_h): V_h has fold_dv columns, zero-padded to L', and the
 // L'/c diagonal ciphertexts of each group are accumulated mod d_v'/c into d_v'/c dense outputs
-static int cc_plan_create(blb_ctx* c, int n_heads, int L, int d_head, int level, int32_t b_prerotated, int fold_dv, blb_plan** out) {
+static int cc_plan_create(blb_ctx* c, int n_heads, int L, int d_head, int level, int32_t b_prerotated, int fold_dv, int sched,
+                          blb_plan** out) {
   if (!c || !out || n_heads < 1 || L < 1 || d_head < 1 || fold_dv < 0 || (b_prerotated != 0 && b_prerotated != 1)) return BLB_EINVAL;
+  if (sched != 0 && sched != 1) return BLB_EINVAL;
   if (level < (b_prerotated ? 3 : 4) || level >= c->n_q) return BLB_EINVAL;
   *out = nullptr;
   const int S = c->n / 2, n = c->n, lp = 1 << ceil_log2(L);
@@ -1719,6 +1745,12 @@ static int cc_plan_create(blb_ctx* c, int n_heads, int L, int d_head, int level,
   P->Lp = lp;
   P->pt = nullptr;
   P->bytes = 0;
+  P->sched = sched;
+  {
+    const int lb = ceil_log2(lp);
+    P->bs_B = 1 << ((lb + 1) / 2);
+    P->bs_G = lp / P->bs_B;
+  }
   int ct0 = 0, out0 = 0;
   for (int H : gs) {
     if (S % (lp * H)) {
@@ -1741,7 +1773,12 @@ static int cc_plan_create(blb_ctx* c, int n_heads, int L, int d_head, int level,
     g.n_out = dvp / g.c;
     g.ct0 = ct0;
     g.out0 = out0;
-    g.m_ge = g.m_lt = g.m_s1 = nullptr;
+    g.m_ge = g.m_lt = g.m_s1 = g.m_bs = nullptr;
+    {
+      const int lc = ceil_log2(g.c);
+      g.b1 = 1 << ((lc + 1) / 2);
+      g.g1 = g.c / g.b1;
+    }
     ct0 += g.n_ct;
     out0 += g.n_out;
     P->groups.push_back(g);
@@ -1766,6 +1803,23 @@ static int cc_plan_create(blb_ctx* c, int n_heads, int L, int d_head, int level,
         else if (i < lp - cls) v[(size_t)cls * S + j] = 1.0;
         else v[(size_t)(g.c + cls) * S + j] = 1.0;
       }
+      if (sched == 1) {
+        // BSGS: mask kappa = j b1 + i of family 0 pre-rotated right by j b1 (slot k takes slot
+        // k - j b1), of family 1 left by L' - j b1, stored at [family][j][i]
+        std::vector<double> u((size_t)2 * g.c * S, 0.0);
+        for (int fam = 0; fam < 2; ++fam)
+          for (int jj = 0; jj < g.g1; ++jj)
+            for (int ii = 0; ii < g.b1; ++ii) {
+              const int kap = jj * g.b1 + ii;
+              const double* src = v.data() + (size_t)(fam * g.c + kap) * S;
+              double* dst = u.data() + (size_t)((fam * g.g1 + jj) * g.b1 + ii) * S;
+              if (fam == 1 && kap == 0) continue;  // M^2_0 = 0
+              const int64_t r = fam == 0 ? -(int64_t)jj * g.b1 : (int64_t)(lp - jj * g.b1);
+              const int64_t rr = ((r % S) + S) % S;
+              for (int k = 0; k < S; ++k) dst[k] = src[(k + rr) % S];
+            }
+        v.swap(u);
+      }
       if ((rc = encode_vectors_ntt(c, v, 2 * g.c, (double)c->mod[level] / BLB_NOISE_BOOST, level, g.m_s1))) {
         blb_plan_destroy(P);
         return rc;
@@ -1774,21 +1828,46 @@ static int cc_plan_create(blb_ctx* c, int n_heads, int L, int d_head, int level,
     level -= 1;  // steps 2-3 start one level down
   }
   const int nl = level + 1, nl3 = level - 1;
-  // step-2 masks at `level`, scale q_level * 2^10: M^lo_t (slot mod L' < L'-t), M^hi_t
-  P->bytes = (size_t)2 * lp * nl * n * 8;
+  // step-2 masks at `level`, scale q_level * 2^10: M^lo_t (slot mod L' < L'-t), M^hi_t, for every
+  // t < L' (plain schedule) or the baby steps t < B (BSGS)
+  const int n_t2 = sched ? P->bs_B : lp;
+  P->bytes = (size_t)2 * n_t2 * nl * n * 8;
   rc = dalloc(c, (void**)&P->pt, P->bytes);
   if (rc) {
     delete P;
     return rc;
   }
   {
-    std::vector<double> vecs((size_t)2 * lp * S);
-    for (int t = 0; t < lp; ++t)
+    std::vector<double> vecs((size_t)2 * n_t2 * S);
+    for (int t = 0; t < n_t2; ++t)
       for (int j = 0; j < S; ++j) {
         vecs[(size_t)t * S + j] = (j % lp) < lp - t ? 1.0 : 0.0;
-        vecs[(size_t)(lp + t) * S + j] = (j % lp) >= lp - t ? 1.0 : 0.0;
+        vecs[(size_t)(n_t2 + t) * S + j] = (j % lp) >= lp - t ? 1.0 : 0.0;
       }
-    if ((rc = encode_vectors_ntt(c, vecs, 2 * lp, (double)c->mod[level] * 1024.0, level, P->pt))) {
+    if ((rc = encode_vectors_ntt(c, vecs, 2 * n_t2, (double)c->mod[level] * 1024.0, level, P->pt))) {
+      blb_plan_destroy(P);
+      return rc;
+    }
+  }
+  // BSGS: masks of the giant inner rotations of A by t = L' - jB at `level`, scale q_level / 2^10
+  if (sched) {
+    const int G = P->bs_G, Bs = P->bs_B;
+    const size_t b = (size_t)2 * G * nl * n * 8;
+    if ((rc = dalloc(c, (void**)&P->pt_a, b))) {
+      blb_plan_destroy(P);
+      return rc;
+    }
+    P->extra.push_back(P->pt_a);
+    P->extra_bytes.push_back(b);
+    std::vector<double> vecs((size_t)2 * G * S, 0.0);
+    for (int j = 1; j < G; ++j) {
+      const int t = lp - j * Bs;
+      for (int k = 0; k < S; ++k) {
+        vecs[(size_t)j * S + k] = (k % lp) < lp - t ? 1.0 : 0.0;
+        vecs[(size_t)(G + j) * S + k] = (k % lp) >= lp - t ? 1.0 : 0.0;
+      }
+    }
+    if ((rc = encode_vectors_ntt(c, vecs, 2 * G, (double)c->mod[level] / BLB_NOISE_BOOST, level, P->pt_a))) {
       blb_plan_destroy(P);
       return rc;
     }
@@ -1813,6 +1892,34 @@ static int cc_plan_create(blb_ctx* c, int n_heads, int L, int d_head, int level,
       blb_plan_destroy(P);
       return rc;
     }
+    if (sched && P->bs_G > 1) {
+      // BSGS step 3: product masks [j - 1][side * 2 + half][tau]: side 0 M^{>=tau}, 1 M^{<tau};
+      // half 0 H_j (in-block position >= jB), 1 Lo_j (position < jB)
+      const int G = P->bs_G, Bs = P->bs_B;
+      const size_t cnt = (size_t)(G - 1) * 4 * g.c;
+      const size_t bb = cnt * nl3 * n * 8;
+      if ((rc = dalloc(c, (void**)&g.m_bs, bb))) {
+        blb_plan_destroy(P);
+        return rc;
+      }
+      P->extra.push_back(g.m_bs);
+      P->extra_bytes.push_back(bb);
+      std::vector<double> mv(cnt * S);
+      for (int j = 1; j < G; ++j)
+        for (int q4 = 0; q4 < 4; ++q4)
+          for (int tau = 0; tau < g.c; ++tau) {
+            double* dst = mv.data() + ((size_t)((j - 1) * 4 + q4) * g.c + tau) * S;
+            const double* side = (q4 >> 1) == 0 ? ge.data() + (size_t)tau * S : lt.data() + (size_t)tau * S;
+            for (int k = 0; k < S; ++k) {
+              const bool hi = (k % lp) >= j * Bs;
+              dst[k] = side[k] * (((q4 & 1) == 0) == hi ? 1.0 : 0.0);
+            }
+          }
+      if ((rc = encode_vectors_ntt(c, mv, (int)cnt, sc, level - 2, g.m_bs))) {
+        blb_plan_destroy(P);
+        return rc;
+      }
+    }
   }
   *out = P;
   return BLB_OK;
@@ -1821,12 +1928,23 @@ static int cc_plan_create(blb_ctx* c, int n_heads, int L, int d_head, int level,
 extern "C" {
 
 int blb_plan_matmul_cc(blb_ctx* c, int n_heads, int L, int d_head, int level, int32_t b_prerotated, blb_plan** out) {
-  return cc_plan_create(c, n_heads, L, d_head, level, b_prerotated, 0, out);
+  return cc_plan_create(c, n_heads, L, d_head, level, b_prerotated, 0, 0, out);
 }
 
 int blb_plan_matmul_cc_sv(blb_ctx* c, int n_heads, int L, int d_v, int level, int32_t b_prerotated, blb_plan** out) {
   if (d_v < 1) return BLB_EINVAL;
-  return cc_plan_create(c, n_heads, L, L, level, b_prerotated, d_v, out);
+  return cc_plan_create(c, n_heads, L, L, level, b_prerotated, d_v, 0, out);
+}
+
+int blb_plan_matmul_cc_sched(blb_ctx* c, int n_heads, int L, int d_head, int level, int32_t b_prerotated, int32_t schedule,
+                             blb_plan** out) {
+  return cc_plan_create(c, n_heads, L, d_head, level, b_prerotated, 0, schedule, out);
+}
+
+int blb_plan_matmul_cc_sv_sched(blb_ctx* c, int n_heads, int L, int d_v, int level, int32_t b_prerotated, int32_t schedule,
+                                blb_plan** out) {
+  if (d_v < 1) return BLB_EINVAL;
+  return cc_plan_create(c, n_heads, L, L, level, b_prerotated, d_v, schedule, out);
 }
 
 int blb_plan_cc_info(const blb_plan* P, int32_t* info, int cap) {
@@ -1849,6 +1967,368 @@ int blb_plan_cc_info(const blb_plan* P, int32_t* info, int cap) {
   return ng;
 }
 
+}  // extern "C"
+
+namespace {
+
+const SwKey* key_for(blb_ctx* c, const blb_keys* K, int64_t steps) { return find_key(K, galois_left(c, steps)); }
+
+// Rotation request of source `src` (a whole ciphertext at `ct`, its c1 being the source poly):
+// dst = (sigma(c0) + KS_0, KS_1)
+KsReq rot_req(blb_ctx* c, const blb_keys* K, int src, int64_t steps, const uint64_t* ct, uint64_t* dst) {
+  const uint32_t gal = galois_left(c, steps);
+  return KsReq{src, key_for(c, K, steps), gal, dst, ct, gal, nullptr};
+}
+
+// Step 1 with BSGS for one head group (m = g.n_ct ciphertexts B_a at level_in, [2][level_in+1][N]):
+// with kappa = j b1 + i and B''_a = 2^10 B_a,
+//   B'_a = Rescale( sum_j Rot_l^{j b1}( sum_i Rot_l^i(B'') (.) Rot_r^{j b1}(M^1_kappa) )
+//                 + sum_j Rot_r^{L' - j b1}( sum_i Rot_l^i(B'') (.) Rot_l^{L' - j b1}(M^2_kappa) ) ),
+// the baby rotations Rot_l^i(B'') hoisted and shared by both families; Bq gets [m][2][level_in][N].
+int cc_step1_bsgs_dev(blb_ctx* c, const blb_keys* K, const blb_plan* P, const CcGroup& g, const blb_ct* Bin, int level_in,
+                      uint64_t* Bq) {
+  const int m = g.n_ct, n = c->n, lp = P->Lp, b1 = g.b1, g1 = g.g1;
+  const int nl0 = level_in + 1;
+  const size_t w0 = (size_t)2 * nl0 * n;
+  Tmp tmp(c);
+  uint64_t* B0 = tmp.get<uint64_t>((size_t)m * w0);
+  uint64_t* X0 = tmp.get<uint64_t>(ks_modup_words(c, level_in, m));
+  uint64_t* XB = tmp.get<uint64_t>((size_t)(b1 - 1) * m * w0 + 1);
+  uint64_t* Pp = tmp.get<uint64_t>((size_t)m * g1 * 2 * w0);
+  uint64_t* PR = tmp.get<uint64_t>((size_t)m * g1 * 2 * w0);
+  uint64_t* S0 = tmp.get<uint64_t>((size_t)m * w0);
+  if (tmp.failed) return BLB_ENOMEM;
+  std::vector<const uint64_t*> bin;
+  for (int a = 0; a < m; ++a) bin.push_back(Bin[g.ct0 + a].data);
+  const uint64_t* const* bin_dev = upload_vec(c, bin);
+  if (!bin_dev) return BLB_EDEVICE;
+  launch_scale_cts(c, bin_dev, B0, m, nl0, BLB_NOISE_BOOST);
+  int rc;
+  std::vector<const uint64_t*> srcs0;
+  for (int a = 0; a < m; ++a) srcs0.push_back(B0 + (size_t)a * w0 + (size_t)nl0 * n);
+  std::vector<KsReq> baby;
+  for (int i = 1; i < b1; ++i)
+    for (int a = 0; a < m; ++a) baby.push_back(rot_req(c, K, a, i, B0 + (size_t)a * w0, XB + ((size_t)(i - 1) * m + a) * w0));
+  if (!baby.empty()) {
+    if ((rc = ks_modup(c, level_in, srcs0, X0))) return rc;
+    if ((rc = ks_apply(c, level_in, srcs0, X0, baby))) return rc;
+  }
+  // partial sums [a][j][family]
+  std::vector<CcTerm> terms;
+  std::vector<int> off{0};
+  std::vector<uint64_t*> outs;
+  std::vector<int> has((size_t)m * g1 * 2, 0);
+  for (int a = 0; a < m; ++a)
+    for (int j = 0; j < g1; ++j)
+      for (int fam = 0; fam < 2; ++fam) {
+        const size_t before = terms.size();
+        for (int i = 0; i < b1; ++i) {
+          if (fam == 1 && j == 0 && i == 0) continue;  // M^2_0 = 0
+          const uint64_t* x = i == 0 ? B0 + (size_t)a * w0 : XB + ((size_t)(i - 1) * m + a) * w0;
+          terms.push_back(CcTerm{x, g.m_s1 + (size_t)((fam * g1 + j) * b1 + i) * nl0 * n});
+        }
+        if (terms.size() == before) continue;
+        has[((size_t)a * g1 + j) * 2 + fam] = 1;
+        off.push_back((int)terms.size());
+        outs.push_back(Pp + (((size_t)a * g1 + j) * 2 + fam) * w0);
+      }
+  {
+    const CcTerm* terms_dev = upload_vec(c, terms);
+    const int* off_dev = upload_vec(c, off);
+    uint64_t* const* outs_dev = (uint64_t* const*)upload(c, outs.data(), outs.size() * sizeof(uint64_t*));
+    if (!terms_dev || !off_dev || !outs_dev) return BLB_EDEVICE;
+    Span sp(c, BLB_T_EW, (double)outs.size() * w0);
+    c->counters[2] += (int64_t)terms.size();
+    launch_masked_acc(c, terms_dev, off_dev, outs_dev, (int)outs.size(), nl0, false);
+  }
+  // giant rotations of the partial sums (each its own source), then B' = Rescale(sum)
+  std::vector<const uint64_t*> gsrc;
+  std::vector<KsReq> greq;
+  std::vector<const uint64_t*> sum_src;
+  std::vector<int> sum_off{0};
+  std::vector<uint64_t*> sum_dst;
+  for (int a = 0; a < m; ++a) {
+    for (int j = 0; j < g1; ++j)
+      for (int fam = 0; fam < 2; ++fam) {
+        const size_t k = ((size_t)a * g1 + j) * 2 + fam;
+        if (!has[k]) continue;
+        uint64_t* part = Pp + k * w0;
+        if (fam == 0 && j == 0) {
+          sum_src.push_back(part);
+          continue;
+        }
+        const int64_t steps = fam == 0 ? (int64_t)j * b1 : -(int64_t)(lp - j * b1);
+        gsrc.push_back(part + (size_t)nl0 * n);
+        greq.push_back(rot_req(c, K, (int)gsrc.size() - 1, steps, part, PR + k * w0));
+        sum_src.push_back(PR + k * w0);
+      }
+    sum_off.push_back((int)sum_src.size());
+    sum_dst.push_back(S0 + (size_t)a * w0);
+  }
+  if ((rc = ks_batch(c, level_in, gsrc, greq))) return rc;
+  {
+    const uint64_t* const* s_dev = upload_vec(c, sum_src);
+    const int* o_dev = upload_vec(c, sum_off);
+    uint64_t* const* d_dev = (uint64_t* const*)upload(c, sum_dst.data(), sum_dst.size() * sizeof(uint64_t*));
+    if (!s_dev || !o_dev || !d_dev) return BLB_EDEVICE;
+    Span sp(c, BLB_T_EW, (double)m * w0);
+    launch_sum_var(c, s_dev, o_dev, d_dev, m, nl0);
+  }
+  std::vector<const uint64_t*> rin;
+  std::vector<uint64_t*> rout;
+  for (int a = 0; a < m; ++a) {
+    rin.push_back(S0 + (size_t)a * w0);
+    rout.push_back(Bq + (size_t)a * 2 * level_in * n);
+  }
+  return rescale_batch(c, level_in, 2, rin, rout);
+}
+
+// Steps 2-3 with BSGS for one head group: A_a (a_nl limbs per poly, used through its first
+// level + 1) and B'_a (compact, level + 1 limbs) at `level`; with t = j B + i,
+//   Y_{a,i}  = Rescale(InnerRot_i(2^10 B'_a))          (baby steps; masks q_level 2^10)
+//   A'_{a,j} = Rescale(InnerRot_{L'-jB}(2^10 A_a))      (giant steps, j >= 1; masks q_level / 2^10), Drop(A_a) for j = 0
+//   U_t = Rescale(Relin(sum_a A'_{a,j} (x) Y_{a,i})),  V_t = Rot_r^{tau H L'}(U_t)
+// step 3: j = 0 terms go to O_g / O_{g+1} with M^{>=tau} / M^{<tau}; j >= 1 terms go to the
+// accumulators (g, j, half) with the product masks, which are rotated by the postponed giant step
+// (half H_j left by jB, half Lo_j right by L' - jB) and added to O_g; outputs = Rescale(O_g).
+int cc_steps23_bsgs_dev(blb_ctx* c, const blb_keys* K, const blb_plan* P, const CcGroup& g, const std::vector<const uint64_t*>& asrc,
+                        int a_nl, const std::vector<const uint64_t*>& bsrc, int level, const blb_ct* Cd) {
+  const int m = g.n_ct, n = c->n, lp = P->Lp, Bb = P->bs_B, G = P->bs_G;
+  const int nl = level + 1, nl2 = level, nl3 = level - 1;
+  const size_t w1 = (size_t)2 * nl * n, w2 = (size_t)2 * nl2 * n, w3 = (size_t)2 * nl3 * n;
+  const int TC = std::min(lp, 128);
+  Tmp tmp(c);
+  uint64_t* Bs = tmp.get<uint64_t>((size_t)m * w1);
+  uint64_t* As = tmp.get<uint64_t>((size_t)m * w1);
+  uint64_t* X = tmp.get<uint64_t>(ks_modup_words(c, level, 2 * m));
+  uint64_t* RL = tmp.get<uint64_t>((size_t)(Bb - 1) * m * w1 + 1);
+  uint64_t* RR = tmp.get<uint64_t>((size_t)(Bb - 1) * m * w1 + 1);
+  uint64_t* GL = tmp.get<uint64_t>((size_t)(G - 1) * m * w1 + 1);
+  uint64_t* GR = tmp.get<uint64_t>((size_t)(G - 1) * m * w1 + 1);
+  uint64_t* Pre = tmp.get<uint64_t>((size_t)(Bb + G - 1) * m * w1);
+  uint64_t* Y = tmp.get<uint64_t>((size_t)Bb * m * w2);
+  uint64_t* Ap = tmp.get<uint64_t>((size_t)G * m * w2);
+  uint64_t* Oacc = tmp.get<uint64_t>((size_t)g.n_out * w3);
+  uint64_t* Acc = tmp.get<uint64_t>((size_t)g.n_out * (G - 1) * 2 * w3 + 1);
+  uint64_t* F = tmp.get<uint64_t>((size_t)g.n_out * (G - 1) * 2 * w3 + 1);
+  uint64_t* T3 = tmp.get<uint64_t>((size_t)TC * 3 * nl2 * n);
+  uint64_t* Trl = tmp.get<uint64_t>((size_t)TC * w2);
+  uint64_t* T = tmp.get<uint64_t>((size_t)TC * w3);
+  uint64_t* V = tmp.get<uint64_t>((size_t)TC * w3);
+  if (tmp.failed) return BLB_ENOMEM;
+  int rc;
+  {
+    const uint64_t* const* b_dev = upload_vec(c, bsrc);
+    const uint64_t* const* a_dev = upload_vec(c, asrc);
+    if (!b_dev || !a_dev) return BLB_EDEVICE;
+    launch_scale_cts(c, b_dev, Bs, m, nl, BLB_NOISE_BOOST);
+    launch_scale_cts(c, a_dev, As, m, nl, BLB_NOISE_BOOST, a_nl);
+    launch_scale_cts(c, a_dev, Ap, m, nl2, 1.0, a_nl);  // A'_{a,0} = Drop(A_a)
+  }
+  launch_zero(c, Oacc, (size_t)g.n_out * w3);
+  if (G > 1) launch_zero(c, Acc, (size_t)g.n_out * (G - 1) * 2 * w3);
+  // hoisted baby rotations of B' and giant rotations of A, one ModUp for both
+  std::vector<const uint64_t*> srcs;
+  for (int a = 0; a < m; ++a) srcs.push_back(Bs + (size_t)a * w1 + (size_t)nl * n);
+  for (int a = 0; a < m; ++a) srcs.push_back(As + (size_t)a * w1 + (size_t)nl * n);
+  std::vector<KsReq> reqs;
+  for (int i = 1; i < Bb; ++i)
+    for (int a = 0; a < m; ++a) {
+      const size_t k = (size_t)(i - 1) * m + a;
+      reqs.push_back(rot_req(c, K, a, i, Bs + (size_t)a * w1, RL + k * w1));
+      reqs.push_back(rot_req(c, K, a, -(int64_t)(lp - i), Bs + (size_t)a * w1, RR + k * w1));
+    }
+  for (int j = 1; j < G; ++j)
+    for (int a = 0; a < m; ++a) {
+      const size_t k = (size_t)(j - 1) * m + a;
+      reqs.push_back(rot_req(c, K, m + a, lp - j * Bb, As + (size_t)a * w1, GL + k * w1));
+      reqs.push_back(rot_req(c, K, m + a, -(int64_t)(j * Bb), As + (size_t)a * w1, GR + k * w1));
+    }
+  if (!reqs.empty()) {
+    if ((rc = ks_modup(c, level, srcs, X))) return rc;
+    if ((rc = ks_apply(c, level, srcs, X, reqs))) return rc;
+  }
+  // masks, then one rescale batch: Y [i][a] and A' [j][a] (j >= 1)
+  std::vector<CcPair> pairs;
+  std::vector<const uint64_t*> rin;
+  std::vector<uint64_t*> rout;
+  for (int i = 0; i < Bb; ++i)
+    for (int a = 0; a < m; ++a) {
+      const size_t k = (size_t)i * m + a;
+      CcPair pr;
+      pr.mx = P->pt + (size_t)i * nl * n;
+      pr.my = P->pt + (size_t)(Bb + i) * nl * n;
+      pr.out = Pre + k * w1;
+      if (i == 0) {
+        pr.x = Bs + (size_t)a * w1;
+        pr.y = nullptr;
+      } else {
+        pr.x = RL + ((size_t)(i - 1) * m + a) * w1;
+        pr.y = RR + ((size_t)(i - 1) * m + a) * w1;
+      }
+      pairs.push_back(pr);
+      rin.push_back(Pre + k * w1);
+      rout.push_back(Y + k * w2);
+    }
+  for (int j = 1; j < G; ++j)
+    for (int a = 0; a < m; ++a) {
+      const size_t k = (size_t)(Bb + j - 1) * m + a, kg = (size_t)(j - 1) * m + a;
+      CcPair pr;
+      pr.mx = P->pt_a + (size_t)j * nl * n;
+      pr.my = P->pt_a + (size_t)(G + j) * nl * n;
+      pr.x = GL + kg * w1;
+      pr.y = GR + kg * w1;
+      pr.out = Pre + k * w1;
+      pairs.push_back(pr);
+      rin.push_back(Pre + k * w1);
+      rout.push_back(Ap + ((size_t)j * m + a) * w2);
+    }
+  {
+    const CcPair* pairs_dev = upload_vec(c, pairs);
+    if (!pairs_dev) return BLB_EDEVICE;
+    Span sp(c, BLB_T_EW, (double)pairs.size() * w1);
+    for (const CcPair& pr : pairs) c->counters[2] += pr.y ? 2 : 1;
+    launch_mask_pair(c, pairs_dev, (int)pairs.size(), nl);
+  }
+  if ((rc = rescale_batch(c, level, 2, rin, rout))) return rc;
+  // accumulator index of (output o, giant step j >= 1, half)
+  auto acc_idx = [&](int o, int j, int half) { return ((size_t)o * (G - 1) + (j - 1)) * 2 + half; };
+  std::vector<char> used((size_t)g.n_out * (G > 1 ? G - 1 : 0) * 2, 0);
+  for (int t0 = 0; t0 < lp; t0 += TC) {
+    const int nt = std::min(TC, lp - t0);
+    std::vector<const uint64_t*> a_tab, r_tab;
+    for (int tt = 0; tt < nt; ++tt) {
+      const int t = t0 + tt, j = t / Bb, i = t % Bb;
+      for (int a = 0; a < m; ++a) {
+        a_tab.push_back(Ap + ((size_t)j * m + a) * w2);
+        r_tab.push_back(Y + ((size_t)i * m + a) * w2);
+      }
+    }
+    {
+      const uint64_t* const* a_dev = upload_vec(c, a_tab);
+      const uint64_t* const* r_dev = upload_vec(c, r_tab);
+      if (!a_dev || !r_dev) return BLB_EDEVICE;
+      Span sp(c, BLB_T_CC_TENSOR, (double)nt * nl2 * n);
+      c->counters[3] += (int64_t)nt * m;
+      c->counters[4] += nt;
+      launch_tensor_sum(c, a_dev, r_dev, T3, nt, m, nl2, nl2, true);
+    }
+    std::vector<const uint64_t*> rs;
+    std::vector<KsReq> rr;
+    const SwKey* relin = find_key(K, 0);
+    for (int tt = 0; tt < nt; ++tt) {
+      const uint64_t* t3 = T3 + (size_t)tt * 3 * nl2 * n;
+      rs.push_back(t3 + (size_t)2 * nl2 * n);
+      rr.push_back(KsReq{tt, relin, 0, Trl + (size_t)tt * w2, t3, 0, t3 + (size_t)nl2 * n});
+    }
+    if ((rc = ks_batch(c, level - 1, rs, rr))) return rc;
+    rin.clear();
+    rout.clear();
+    for (int tt = 0; tt < nt; ++tt) {
+      rin.push_back(Trl + (size_t)tt * w2);
+      rout.push_back(T + (size_t)tt * w3);
+    }
+    if ((rc = rescale_batch(c, level - 1, 2, rin, rout))) return rc;
+    std::vector<const uint64_t*> vs;
+    std::vector<KsReq> vr;
+    std::vector<const uint64_t*> vsrc(nt);
+    for (int tt = 0; tt < nt; ++tt) {
+      const int t = t0 + tt, tau = t % g.c;
+      const uint64_t* tp = T + (size_t)tt * w3;
+      if (tau == 0) {
+        vsrc[tt] = tp;
+        continue;
+      }
+      vs.push_back(tp + (size_t)nl3 * n);
+      vr.push_back(rot_req(c, K, (int)vs.size() - 1, -(int64_t)tau * g.H * lp, tp, V + (size_t)tt * w3));
+      vsrc[tt] = V + (size_t)tt * w3;
+    }
+    if ((rc = ks_batch(c, level - 2, vs, vr))) return rc;
+    // step 3 masks into O_g (j = 0) or the giant-step accumulators (j >= 1)
+    const size_t n_acc = (size_t)g.n_out * (1 + (G > 1 ? (G - 1) * 2 : 0));
+    std::vector<std::vector<CcTerm>> per(n_acc);
+    auto slot_of = [&](int o, int j, int half) -> size_t { return j == 0 ? (size_t)o : g.n_out + acc_idx(o, j, half); };
+    for (int tt = 0; tt < nt; ++tt) {
+      const int t = t0 + tt, gi = t / g.c, tau = t % g.c, j = t / Bb;
+      const int o_ge = gi % g.n_out, o_lt = ((gi + 1) % g.n_diag) % g.n_out;
+      if (j == 0) {
+        per[o_ge].push_back(CcTerm{vsrc[tt], g.m_ge + (size_t)tau * nl3 * n});
+        if (tau > 0) per[o_lt].push_back(CcTerm{vsrc[tt], g.m_lt + (size_t)tau * nl3 * n});
+        continue;
+      }
+      for (int half = 0; half < 2; ++half) {
+        per[slot_of(o_ge, j, half)].push_back(CcTerm{vsrc[tt], g.m_bs + ((size_t)((j - 1) * 4 + half) * g.c + tau) * nl3 * n});
+        used[acc_idx(o_ge, j, half)] = 1;
+        if (tau > 0) {
+          per[slot_of(o_lt, j, half)].push_back(CcTerm{vsrc[tt], g.m_bs + ((size_t)((j - 1) * 4 + 2 + half) * g.c + tau) * nl3 * n});
+          used[acc_idx(o_lt, j, half)] = 1;
+        }
+      }
+    }
+    std::vector<CcTerm> terms;
+    std::vector<int> off{0};
+    std::vector<uint64_t*> outs;
+    for (size_t k = 0; k < n_acc; ++k) {
+      if (per[k].empty()) continue;
+      terms.insert(terms.end(), per[k].begin(), per[k].end());
+      off.push_back((int)terms.size());
+      outs.push_back(k < (size_t)g.n_out ? Oacc + k * w3 : Acc + (k - g.n_out) * w3);
+    }
+    const CcTerm* terms_dev = upload_vec(c, terms);
+    const int* off_dev = upload_vec(c, off);
+    uint64_t* const* outs_dev = (uint64_t* const*)upload(c, outs.data(), outs.size() * sizeof(uint64_t*));
+    if (!terms_dev || !off_dev || !outs_dev) return BLB_EDEVICE;
+    Span sp(c, BLB_T_EW, (double)outs.size() * w3);
+    c->counters[2] += (int64_t)terms.size();
+    launch_masked_acc(c, terms_dev, off_dev, outs_dev, (int)outs.size(), nl3, true);
+  }
+  // the postponed giant rotations, then O_g += their sum and the final rescale
+  std::vector<const uint64_t*> fsrc;
+  std::vector<KsReq> freq;
+  std::vector<std::vector<const uint64_t*>> add(g.n_out);
+  for (int o = 0; o < g.n_out; ++o) {
+    add[o].push_back(Oacc + (size_t)o * w3);
+    for (int j = 1; j < G; ++j)
+      for (int half = 0; half < 2; ++half) {
+        const size_t k = acc_idx(o, j, half);
+        if (!used[k]) continue;
+        const uint64_t* accp = Acc + k * w3;
+        const int64_t steps = half == 0 ? (int64_t)j * Bb : -(int64_t)(lp - j * Bb);
+        fsrc.push_back(accp + (size_t)nl3 * n);
+        freq.push_back(rot_req(c, K, (int)fsrc.size() - 1, steps, accp, F + k * w3));
+        add[o].push_back(F + k * w3);
+      }
+  }
+  if ((rc = ks_batch(c, level - 2, fsrc, freq))) return rc;
+  if (!fsrc.empty()) {
+    std::vector<const uint64_t*> ssrc;
+    std::vector<int> soff{0};
+    std::vector<uint64_t*> sdst;
+    for (int o = 0; o < g.n_out; ++o) {
+      ssrc.insert(ssrc.end(), add[o].begin(), add[o].end());
+      soff.push_back((int)ssrc.size());
+      sdst.push_back(Oacc + (size_t)o * w3);
+    }
+    const uint64_t* const* s_dev = upload_vec(c, ssrc);
+    const int* o_dev = upload_vec(c, soff);
+    uint64_t* const* d_dev = (uint64_t* const*)upload(c, sdst.data(), sdst.size() * sizeof(uint64_t*));
+    if (!s_dev || !o_dev || !d_dev) return BLB_EDEVICE;
+    Span sp(c, BLB_T_EW, (double)g.n_out * w3);
+    launch_sum_var(c, s_dev, o_dev, d_dev, g.n_out, nl3);
+  }
+  std::vector<const uint64_t*> oin;
+  std::vector<uint64_t*> oout;
+  for (int o = 0; o < g.n_out; ++o) {
+    oin.push_back(Oacc + (size_t)o * w3);
+    oout.push_back(Cd[g.out0 + o].data);
+  }
+  return rescale_batch(c, level - 2, 2, oin, oout);
+}
+
+}  // namespace
+
+extern "C" {
+
 int blb_matmul_cc(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct* A, const blb_ct* Bp, int n_ct, blb_ct* Cd, int n_out) {
   if (!c || !K || !P || !A || !Bp || !Cd || P->kind != 2) return BLB_EINVAL;
   if (n_ct != P->n_ct || n_out != P->n_out) return BLB_EINVAL;
@@ -1863,13 +2343,19 @@ int blb_matmul_cc(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct
   const SwKey* relin = find_key(K, 0);
   if (!relin) return BLB_ENOKEY;
   std::vector<const SwKey*> kl(lp, nullptr), kr(lp, nullptr);
-  for (int t = 1; t < lp; ++t) {
-    if (!(kl[t] = find_key(K, galois_left(c, t)))) return BLB_ENOKEY;
-    if (!(kr[t] = find_key(K, galois_left(c, -(lp - t))))) return BLB_ENOKEY;
+  {
+    const int nk = blb_cc_rotations_sched(c, P->heads, P->L, P->hom1 ? 0 : 1, P->sched, nullptr, 0);
+    if (nk < 0) return BLB_EINVAL;
+    std::vector<int32_t> st(nk);
+    if (blb_cc_rotations_sched(c, P->heads, P->L, P->hom1 ? 0 : 1, P->sched, st.data(), nk) < 0) return BLB_EINVAL;
+    for (int32_t x : st)
+      if (!find_key(K, galois_left(c, x))) return BLB_ENOKEY;
   }
-  for (const CcGroup& g : P->groups)
-    for (int tau = 1; tau < g.c; ++tau)
-      if (!find_key(K, galois_left(c, -(int64_t)tau * g.H * lp))) return BLB_ENOKEY;
+  if (P->sched == 0)
+    for (int t = 1; t < lp; ++t) {
+      kl[t] = find_key(K, galois_left(c, t));
+      kr[t] = find_key(K, galois_left(c, -(lp - t)));
+    }
   const int nl = level + 1, nl2 = level, nl3 = level - 1, nlA = level_in + 1;
   const size_t w1 = (size_t)2 * nl * n, w2 = (size_t)2 * nl2 * n, w3 = (size_t)2 * nl3 * n;
   // t values per chunk: large chunks give every stage launch hundreds of limb-polys (the
@@ -1879,6 +2365,22 @@ int blb_matmul_cc(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct
   double b_scale = Bp[0].scale;
   for (const CcGroup& g : P->groups) {
     const int m = g.n_ct;
+    if (P->sched == 1) {
+      Tmp tmp(c);
+      std::vector<const uint64_t*> asrc, bsrc;
+      for (int a = 0; a < m; ++a) {
+        asrc.push_back(A[g.ct0 + a].data);
+        bsrc.push_back(Bp[g.ct0 + a].data);
+      }
+      if (P->hom1) {
+        uint64_t* Bq = tmp.get<uint64_t>((size_t)m * w1);
+        if (tmp.failed) return BLB_ENOMEM;
+        if ((rc = cc_step1_bsgs_dev(c, K, P, g, Bp, level_in, Bq))) return rc;
+        for (int a = 0; a < m; ++a) bsrc[a] = Bq + (size_t)a * w1;
+      }
+      if ((rc = cc_steps23_bsgs_dev(c, K, P, g, asrc, nlA, bsrc, level, Cd))) return rc;
+      continue;
+    }
     Tmp tmp(c);
     // step 1 on the server: B'_a = Rescale(sum of the masked rotations of 2^10 B_a)
     std::vector<const uint64_t*> bsrc;

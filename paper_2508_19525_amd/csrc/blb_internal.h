@@ -256,7 +256,11 @@ struct CcGroup {
   uint64_t* m_ge;  // [c][nl3][N] masks M^{>=tau} at level-2, scale q_{level-2}
   uint64_t* m_lt;  // [c][nl3][N] masks M^{<tau}
   uint64_t* m_s1;  // step 1 on the server: [2c][level+1][N] masks M^0, M^1_kappa (index kappa),
-                   // M^2_kappa (index c + kappa) at the input level, scale q_level / 2^10
+                   // M^2_kappa (index c + kappa) at the input level, scale q_level / 2^10;
+                   // BSGS schedule: [2 (family)][g1][b1][level+1][N], pre-rotated per giant step
+  uint64_t* m_bs;  // BSGS schedule: [G-1 (j >= 1)][4 (side, half)][c (tau)][nl3][N] step-3 product masks
+                   // M^{>=tau} H_j, M^{>=tau} Lo_j, M^{<tau} H_j, M^{<tau} Lo_j at level-2, scale q_{level-2} / 2^10
+  int b1, g1;      // BSGS split of step 1 (b1 g1 = c)
 };
 
 struct blb_plan {
@@ -267,10 +271,15 @@ struct blb_plan {
   CpGeom g;
   bool owns_pt = true;  // false: pt lives in caller memory (the serving plan arena)
   uint64_t* pt;  // matmul_cp: [(b, j)][(a, i)][limb][N] evaluation-form plaintexts
-                 // matmul_cc: [2][L'][limb][N] step-2 masks M^lo_t, M^hi_t (level, scale q_level 2^10)
+                 // matmul_cc: [2][T][limb][N] step-2 masks M^lo_t, M^hi_t (level, scale q_level 2^10),
+                 // T = L' (plain schedule) or B (BSGS: baby steps only)
   size_t bytes;
   // matmul_cc
   int heads, L, d, Lp, n_ct, n_out;
+  int sched = 0;        // 0: an inner rotation of every B'_a per t; 1: BSGS (giant steps postponed into step 3)
+  int bs_B = 0, bs_G = 0;  // BSGS split of step 2 (B G = L')
+  uint64_t* pt_a = nullptr;  // BSGS: [2][G][limb][N] masks of the giant inner rotations of A (t = L' - jB),
+                             // level, scale q_level / 2^10 (j = 0 unused)
   std::vector<CcGroup> groups;
   std::vector<void*> extra;
   std::vector<size_t> extra_bytes;
@@ -312,14 +321,16 @@ void launch_mask_pair(blb_ctx* c, const CcPair* pairs_dev, int n_pairs, int nl);
 int batch_mac_shape(int variant, int* tb, int* ib, int* cpt);
 void launch_cp_mac_batch(blb_ctx* c, const MacGroup* groups, const MacItem* items, int n_items, int variant, int grid);
 void launch_sum_var(blb_ctx* c, const uint64_t* const* srcs, const int* off, uint64_t* const* dsts, int n_out, int nl);
-void launch_scale_cts(blb_ctx* c, const uint64_t* const* in, uint64_t* out, int count, int nl, double k);
+// out[t] ([2][nl][N]) = k * (the first nl limbs of each poly of in[t], stored with nl_in >= nl limbs)
+void launch_scale_cts(blb_ctx* c, const uint64_t* const* in, uint64_t* out, int count, int nl, double k, int nl_in = 0);
 
 // Noise boost: operands of key-switched rotations inside the matmuls are multiplied by this
 // integer first (key-switch noise is absolute, so it shrinks relative to the message); the
 // plaintext factors that follow are encoded at scales divided by it.
 #define BLB_NOISE_BOOST 1024.0
+// a_per_t: A_tab holds one operand per (t, a) ([n_t][n_ct]) instead of one per a
 void launch_tensor_sum(blb_ctx* c, const uint64_t* const* A_tab, const uint64_t* const* R_tab, uint64_t* T3, int n_t, int n_ct, int nlA,
-                       int nl2);
+                       int nl2, bool a_per_t = false);
 void launch_masked_acc(blb_ctx* c, const CcTerm* terms, const int* off, uint64_t* const* outs, int n_out, int nl, bool accumulate);
 void launch_mask_sample(blb_ctx* c, uint64_t* r_out, uint64_t* share, int n_ct, int tl, uint64_t seed, const uint64_t* seed_dev, uint32_t tag);
 void launch_set_u64(blb_ctx* c, uint64_t* dst, uint64_t value);

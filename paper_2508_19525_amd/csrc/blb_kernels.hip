@@ -855,7 +855,7 @@ void launch_mask_pair(blb_ctx* c, const CcPair* pairs_dev, int n_pairs, int nl) 
 // T3[t] = sum_a A_a (x) R[t][a]: degree-2 output (d0, d1, d2) at nl2 limbs.  A_a is at a
 // higher level (nlA limbs per poly) and is used through its first nl2 limbs.
 __global__ void k_tensor_sum(const uint64_t* const* __restrict__ A_tab, const uint64_t* const* __restrict__ R_tab,
-                             uint64_t* __restrict__ T3, int n_ct, int nlA, int nl2, int n, ModTable mt) {
+                             uint64_t* __restrict__ T3, int n_ct, int nlA, int nl2, int n, ModTable mt, int a_per_t) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int limb = blockIdx.y % nl2;
   const int t = blockIdx.y / nl2;
@@ -864,7 +864,7 @@ __global__ void k_tensor_sum(const uint64_t* const* __restrict__ A_tab, const ui
   const double q = me.q, qi = me.qinv;
   double d0 = 0.0, d1 = 0.0, d2 = 0.0;
   for (int a = 0; a < n_ct; ++a) {
-    const uint64_t* A = A_tab[a];
+    const uint64_t* A = A_tab[a_per_t ? (size_t)t * n_ct + a : (size_t)a];
     const uint64_t* R = R_tab[(size_t)t * n_ct + a];
     const double a0 = u2d(A[(size_t)limb * n + k]), a1 = u2d(A[(size_t)(nlA + limb) * n + k]);
     const double r0 = u2d(R[(size_t)limb * n + k]), r1 = u2d(R[(size_t)(nl2 + limb) * n + k]);
@@ -883,9 +883,9 @@ __global__ void k_tensor_sum(const uint64_t* const* __restrict__ A_tab, const ui
   o[(size_t)(2 * nl2 + limb) * n + k] = d2u(canon_full(d2, q, qi));
 }
 void launch_tensor_sum(blb_ctx* c, const uint64_t* const* A_tab, const uint64_t* const* R_tab, uint64_t* T3, int n_t, int n_ct, int nlA,
-                       int nl2) {
+                       int nl2, bool a_per_t) {
   dim3 grid((c->n + 255) / 256, n_t * nl2);
-  k_tensor_sum<<<grid, 256, 0, c->stream>>>(A_tab, R_tab, T3, n_ct, nlA, nl2, c->n, c->mt);
+  k_tensor_sum<<<grid, 256, 0, c->stream>>>(A_tab, R_tab, T3, n_ct, nlA, nl2, c->n, c->mt, a_per_t ? 1 : 0);
 }
 
 // out[o] (+)= sum over its terms of ct (.) mask, whole degree-1 ciphertexts at nl limbs
@@ -1066,16 +1066,20 @@ void launch_sum_var(blb_ctx* c, const uint64_t* const* srcs, const int* off, uin
   k_sum_var<<<grid, 256, 0, c->stream>>>(srcs, off, dsts, c->n, nl, c->mt);
 }
 
-// out[t] = k * in[t] for whole degree-1 ciphertexts (exact integer scalar, every limb)
-__global__ void k_scale_cts(const uint64_t* const* __restrict__ in, uint64_t* __restrict__ out, int n, int nl, double k, ModTable mt) {
+// out[t] = k * in[t] for whole degree-1 ciphertexts (exact integer scalar, every limb); in[t]
+// may hold more limbs per poly (nl_in) than out keeps (nl): the extra limbs are dropped
+__global__ void k_scale_cts(const uint64_t* const* __restrict__ in, uint64_t* __restrict__ out, int n, int nl, int nl_in, double k,
+                            ModTable mt) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   const int t = blockIdx.y;
   if (w >= 2 * nl * n) return;
-  const ModEntry me = mt.m[(w / n) % nl];
-  out[(size_t)t * 2 * nl * n + w] = d2u(canon(mulmod_s(u2d(in[t][w]), k, me.q, me.qinv), me.q));
+  const int limb = (w / n) % nl, poly = w / (nl * n);
+  const ModEntry me = mt.m[limb];
+  const size_t src = ((size_t)poly * nl_in + limb) * n + (w % n);
+  out[(size_t)t * 2 * nl * n + w] = d2u(canon(mulmod_s(u2d(in[t][src]), k, me.q, me.qinv), me.q));
 }
-void launch_scale_cts(blb_ctx* c, const uint64_t* const* in, uint64_t* out, int count, int nl, double k) {
+void launch_scale_cts(blb_ctx* c, const uint64_t* const* in, uint64_t* out, int count, int nl, double k, int nl_in) {
   if (count <= 0) return;
   dim3 grid((2 * nl * c->n + 255) / 256, count);
-  k_scale_cts<<<grid, 256, 0, c->stream>>>(in, out, c->n, nl, k, c->mt);
+  k_scale_cts<<<grid, 256, 0, c->stream>>>(in, out, c->n, nl, nl_in > nl ? nl_in : nl, k, c->mt);
 }

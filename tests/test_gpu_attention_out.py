@@ -115,18 +115,18 @@ def _dense_expected(wl, mats, heads, L, d_v, n_ct, slots):
     return v
 
 
-def _sv_case(c, heads, L, d_v, seed, outputs=None, prerot=True, extra_steps=(), with_oracle=True):
+def _sv_case(c, heads, L, d_v, seed, outputs=None, prerot=True, extra_steps=(), with_oracle=True, schedule=0):
     from paper_2508_19525_amd import workloads as wl
     B, orc = c.B, c.orc
     rng = np.random.default_rng(seed)
     S = [_softmax_rows(rng, L) for _ in range(heads)]
     V = [rng.normal(0, 1, (L, d_v)) for _ in range(heads)]
     level, scale = c.n_q - 1, 2.0 ** 40
-    steps = list(B.blb_cc_rotations(c.h, heads, L)) + [s for s in extra_steps]
+    steps = list(B.blb_cc_rotations(c.h, heads, L, schedule, b_prerotated=prerot)) + [s for s in extra_steps]
     gal = sorted({c.o.galois_elt(s) for s in steps})
     keys_o = orc.Keys(c.o, 41, gal)
     keys_g = B.blb_keygen(c.h, 41, steps)
-    plan = B.blb_plan_matmul_cc_sv(c.h, heads, L, d_v, level, b_prerotated=prerot)
+    plan = B.blb_plan_matmul_cc_sv(c.h, heads, L, d_v, level, b_prerotated=prerot, schedule=schedule)
     info = B.blb_plan_cc_info(plan)
     A_g, B_g, want, h0 = [], [], [], 0
     slots = c.n // 2
@@ -147,23 +147,25 @@ def _sv_case(c, heads, L, d_v, seed, outputs=None, prerot=True, extra_steps=(), 
         B_g += [c.import_ct(w, level, scale) for w in Bw]
         outs = None if outputs is None else [o for o in outputs if o < og["n_out"]]
         if with_oracle:
-            want.append((keys_o.matmul_cc_sv(Aw, Bw, level, H, L, d_v, outputs=outs, b_prerotated=prerot), outs, grp))
+            want.append((keys_o.matmul_cc_sv(Aw, Bw, level, H, L, d_v, outputs=outs, b_prerotated=prerot, schedule=schedule), outs,
+                         grp))
         h0 += H
     Cd = [c.ct(level - (3 if prerot else 4)) for _ in range(info["n_out"])]
     B.blb_matmul_cc(c.h, keys_g, plan, A_g, B_g, Cd)
     return dict(S=S, V=V, keys_o=keys_o, keys_g=keys_g, plan=plan, info=info, A=A_g, B=B_g, C=Cd, want=want, level=level)
 
 
-@pytest.mark.parametrize("heads,L,d_v,outputs,prerot", [(12, 64, 32, [0], True), (4, 50, 20, None, True),
-                                                       (4, 64, 32, None, False)])
-def test_softmax_v_matches_oracle(request, heads, L, d_v, outputs, prerot):
+@pytest.mark.parametrize("heads,L,d_v,outputs,prerot,schedule", [
+    (12, 64, 32, [0], True, 0), (4, 50, 20, None, True, 0), (4, 64, 32, None, False, 0),
+    (12, 64, 32, [0], True, 1), (4, 50, 20, None, True, 1), (4, 64, 32, None, False, 1)])
+def test_softmax_v_matches_oracle(request, heads, L, d_v, outputs, prerot, schedule):
     """Dense diagonal-packed Softmax x V_h word for word against the oracle (groups 8 + 4 with
     two and one dense outputs, a ragged L with d_v = 20 padded to 32, and step 1 on the server),
     and, where every output is computed, decoded against S_h V_h in FP64 (zero in the padded
-    columns and rows)."""
+    columns and rows); for the plain and the BSGS schedule."""
     from paper_2508_19525_amd import workloads as wl
     c = request.getfixturevalue("c16" if prerot else "c16p5")
-    r = _sv_case(c, heads, L, d_v, heads + L + d_v, outputs, prerot)
+    r = _sv_case(c, heads, L, d_v, heads + L + d_v, outputs, prerot, schedule=schedule)
     base = 0
     for O_want, outs, grp in r["want"]:
         for o in (range(grp["n_out"]) if outs is None else outs):

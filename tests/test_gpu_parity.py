@@ -330,18 +330,18 @@ def _unrotated_b(mats, H, L, d, a, slots):
     return v
 
 
-def _cc_case(c, heads, L, d, seed, outputs=None, prerot=True):
+def _cc_case(c, heads, L, d, seed, outputs=None, prerot=True, schedule=0):
     from paper_2508_19525_amd import workloads as wl
     B, orc = c.B, c.orc
     rng = np.random.default_rng(seed)
     Q = [rng.normal(0, 1, (L, d)) for _ in range(heads)]
     Kt = [rng.normal(0, 1, (L, d)).T.copy() for _ in range(heads)]
     level, scale = c.n_q - 1, 2.0 ** 40
-    steps = B.blb_cc_rotations(c.h, heads, L)
+    steps = B.blb_cc_rotations(c.h, heads, L, schedule, b_prerotated=prerot)
     gal = sorted({c.o.galois_elt(s) for s in steps})
     keys_o = orc.Keys(c.o, 51, gal)
     keys_g = B.blb_keygen(c.h, 51, steps)
-    plan = B.blb_plan_matmul_cc(c.h, heads, L, d, level, b_prerotated=prerot)
+    plan = B.blb_plan_matmul_cc(c.h, heads, L, d, level, b_prerotated=prerot, schedule=schedule)
     info = B.blb_plan_cc_info(plan)
     A_g, B_g, want, h0 = [], [], [], 0
     for gi, grp in enumerate(info["groups"]):
@@ -365,7 +365,7 @@ def _cc_case(c, heads, L, d, seed, outputs=None, prerot=True):
             y.scale = scale
             B_g.append(y)
         outs = None if outputs is None else [o for o in outputs if o < og["n_out"]]
-        want.append((keys_o.matmul_cc(Aw, Bw, level, H, L, d, outputs=outs, b_prerotated=prerot), outs, grp))
+        want.append((keys_o.matmul_cc(Aw, Bw, level, H, L, d, outputs=outs, b_prerotated=prerot, schedule=schedule), outs, grp))
         h0 += H
     Cd = [c.ct(level - (3 if prerot else 4)) for _ in range(info["n_out"])]
     B.blb_matmul_cc(c.h, keys_g, plan, A_g, B_g, Cd)
@@ -381,15 +381,19 @@ def c5p(blb, orc):
     x.close()
 
 
-@pytest.mark.parametrize("heads,L,d,outputs,prerot", [(8, 32, 32, None, True), (12, 64, 32, [0, 1], True),
-                                                       (8, 32, 32, None, False), (12, 40, 32, [0, 3], False)])
-def test_matmul_cc_matches_oracle(request, heads, L, d, outputs, prerot):
+@pytest.mark.parametrize("heads,L,d,outputs,prerot,schedule", [
+    (8, 32, 32, None, True, 0), (12, 64, 32, [0, 1], True, 0), (8, 32, 32, None, False, 0), (12, 40, 32, [0, 3], False, 0),
+    (8, 32, 32, None, True, 1), (12, 64, 32, None, True, 1), (12, 100, 24, [1, 2], True, 1), (8, 32, 32, None, False, 1),
+    (12, 40, 32, [0, 3], False, 1)])
+def test_matmul_cc_matches_oracle(request, heads, L, d, outputs, prerot, schedule):
     """Multi-head ct-ct matmul word for word against the oracle, including the 8 + 4 head-group
     split; decoded outputs equal Q_h K_h^T.  prerot: B pre-rotated by the client (steps 2-3,
-    four primes); otherwise step 1 runs on the server first (five primes)."""
+    four primes); otherwise step 1 runs on the server first (five primes).  schedule 1 is the
+    BSGS schedule (baby / giant inner rotations, giant rotations postponed into step 3; step 1
+    split into baby and giant rotations), with a ragged L and d among its cases."""
     from paper_2508_19525_amd import workloads as wl
     c3s = request.getfixturevalue("c3s" if prerot else "c5p")
-    r = _cc_case(c3s, heads, L, d, heads + L, outputs, prerot)
+    r = _cc_case(c3s, heads, L, d, heads + L, outputs, prerot, schedule)
     h0 = 0
     for O_want, outs, grp in r["want"]:
         sel = range(grp["n_out"]) if outs is None else outs
@@ -460,9 +464,10 @@ def _xcts(c, r, level):
     return r["_xc"]
 
 
-def test_exec_cc_replays_match_eager(c3s):
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_exec_cc_replays_match_eager(c3s, schedule):
     B = c3s.B
-    r = _cc_case(c3s, 8, 32, 32, 3)
+    r = _cc_case(c3s, 8, 32, 32, 3, schedule=schedule)
     n_out = r["info"]["n_out"]
     Cg = [c3s.ct(r["level"] - 3) for _ in range(n_out)]
     ex = B.blb_exec_create_cc(c3s.h, r["keys_g"], r["plan"], r["A"], r["B"], Cg)
