@@ -38,7 +38,8 @@ enum {
   BLB_ENOKEY = -4,  /* a needed Galois / relinearisation key was not generated */
   BLB_ENOMEM = -5,  /* device allocation failed or HBM budget exceeded */
   BLB_EDEVICE = -6, /* HIP runtime error */
-  BLB_EBUSY = -7    /* serving queue full */
+  BLB_EBUSY = -7,   /* serving queue full */
+  BLB_ETOOBIG = -8  /* operand needs more than the fixed scratch of an allocation-free entry point */
 };
 
 typedef struct blb_ctx blb_ctx;
@@ -134,6 +135,18 @@ int blb_import(blb_ctx* ctx, const uint64_t* host_words, blb_ct* ct);
 /* Left rotation by `steps` slots (Preliminaries, "Rotation"): sigma_{5^steps} and a hybrid
  * key switch with the automorphism applied after ModUp. in/out may not alias. */
 int blb_rotate(blb_ctx* ctx, const blb_keys* keys, const blb_ct* in, int32_t steps, blb_ct* out);
+/* blb_rotate for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same result, word for word, with
+ * every temporary of the key switch carved from one fixed 8 MiB array per device that the
+ * library holds until the process ends (its device address is looked up once per device when
+ * a context is created).  Allocates nothing: no hipMalloc / hipFree, no pool, no events.
+ * Needs 8 N (nl + n_digits n_ext + 2 n_ext + 2 nl) + 1024 bytes at the input's level (nl = level + 1
+ * limbs, n_ext = nl + special primes); larger inputs return BLB_ETOOBIG with the output
+ * untouched (e.g. N = 16384 with 4 primes + 2 special fits at every level; 10 primes + 2 special
+ * at dnum 5 does not at the top level).  Every call on one GPU shares that GPU's array, so calls
+ * that overlap on one GPU (other streams, other contexts, other threads) race; not callable
+ * while a graph executor is being recorded on the context (BLB_EINVAL). */
+int blb_rotate_noalloc(blb_ctx* ctx, const blb_keys* keys, const blb_ct* in, int32_t steps, blb_ct* out);
 /* Rescale (Preliminaries, "Rescaling"): divide by the last prime q_l with rounding.
  * out->data must hold (degree+1)*level*N words; out gets level-1 and scale/q_l. */
 int blb_rescale(blb_ctx* ctx, const blb_ct* in, blb_ct* out);

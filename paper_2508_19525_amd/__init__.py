@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libblb.so")
 
 BLB_OK, BLB_EINVAL, BLB_ELEVEL, BLB_ESCALE, BLB_ENOKEY, BLB_ENOMEM, BLB_EDEVICE, BLB_EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
+BLB_ETOOBIG = -8
 
 
 class BlbError(RuntimeError):
@@ -69,6 +70,7 @@ _SIGS = {
     "blb_export": (C.c_int, [C.c_void_p, C.POINTER(blb_ct), C.c_void_p]),
     "blb_import": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(blb_ct)]),
     "blb_rotate": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.c_int32, C.POINTER(blb_ct)]),
+    "blb_rotate_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.c_int32, C.POINTER(blb_ct)]),
     "blb_rescale": (C.c_int, [C.c_void_p, C.POINTER(blb_ct), C.POINTER(blb_ct)]),
     "blb_ntt": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32]),
     "blb_rerandomize": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.c_int, C.c_uint64, C.c_int]),
@@ -290,6 +292,11 @@ def blb_import(ctx, words: np.ndarray, ct: blb_ct):
 
 def blb_rotate(ctx, keys, ct_in: blb_ct, steps, ct_out: blb_ct):
     _check(lib().blb_rotate(ctx, keys, C.byref(ct_in), steps, C.byref(ct_out)), "blb_rotate")
+
+
+def blb_rotate_noalloc(ctx, keys, ct_in: blb_ct, steps, ct_out: blb_ct):
+    """blb_rotate with every temporary in the library's fixed per-device scratch (allocates nothing)"""
+    _check(lib().blb_rotate_noalloc(ctx, keys, C.byref(ct_in), steps, C.byref(ct_out)), "blb_rotate_noalloc")
 
 
 def blb_rescale(ctx, ct_in: blb_ct, ct_out: blb_ct):

@@ -5,6 +5,7 @@
 #include <math.h>
 #include <string.h>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -155,6 +156,10 @@ struct Tmp {
   bool failed = false;
   explicit Tmp(blb_ctx* cc) : c(cc) {
     if (c->rec) return;
+    if (c->fixed) {
+      off0 = c->fixed->off;
+      return;
+    }
     w = stack_for(c);
     if (!w) return;
     if (w->off == 0) stack_fit(c, w);
@@ -177,6 +182,17 @@ struct Tmp {
       r->arena_off = off + bytes;
       return (T*)(r->arena + off);
     }
+    if (c->fixed) {  // allocation-free entry point: carve from its fixed region, never allocate
+      FixedArena* f = c->fixed;
+      const size_t off = align_up(f->off, 256);
+      if (off + bytes > f->cap) {
+        f->overflow = true;
+        failed = true;
+        return nullptr;
+      }
+      f->off = off + bytes;
+      return (T*)(f->base + off);
+    }
     if (w) {
       w->virt = align_up(w->virt, 256) + bytes;
       w->need = std::max(w->need, w->virt);
@@ -198,6 +214,8 @@ struct Tmp {
     if (w) {
       w->off = off0;
       w->virt = virt0;
+    } else if (c->fixed && !c->rec) {
+      c->fixed->off = off0;
     }
     for (void* p : ptrs) (void)hipFreeAsync(p, c->stream);
   }
@@ -250,7 +268,13 @@ void* upload(blb_ctx* c, const void* data, size_t bytes) {
     memcpy(r->blob_host.data() + off, data, bytes);
     return r->blob_dev + off;
   }
-  Uploader* up = ring_for(c);
+  Uploader* up = nullptr;
+  if (c->fixed) {  // allocation-free entry point: only an existing ring (made with the context)
+    for (Uploader* x : c->ups)
+      if (x->stream == c->stream) up = x;
+  } else {
+    up = ring_for(c);
+  }
   if (!up) return nullptr;
   Uploader& u = *up;
   bytes = align_up(bytes, 256);
@@ -275,7 +299,7 @@ void* upload(blb_ctx* c, const void* data, size_t bytes) {
   if (!u.free_events.empty()) {
     ev = u.free_events.back();
     u.free_events.pop_back();
-  } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+  } else if (c->fixed || hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
     (void)hipStreamSynchronize(c->stream);
     u.head = hi;
     return u.dev + lo;
@@ -310,7 +334,7 @@ struct Span {
   double units;
   hipEvent_t a = nullptr;
   Span(blb_ctx* cc, int k, double u) : c(cc), kind(k), units(u) {
-    if (c->timing && !c->rec) {
+    if (c->timing && !c->rec && !c->fixed) {
       a = pool_event(c);
       (void)hipEventRecord(a, c->stream);
     }
@@ -650,6 +674,37 @@ void uploader_forget_stream(blb_ctx* c, hipStream_t s) {
     }
 }
 
+// ------------------------------------------------------------------------------------------
+// scratch of the allocation-free entry points: one fixed array per device, held until the
+// process ends
+// ------------------------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)8 << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) uint64_t scratch[kScratchBytes / 8];
+std::mutex g_scratch_mu;
+char* g_scratch_dev[kScratchDevices] = {};
+
+// Looks up the device address of this device's copy of `scratch` once per device, with that
+// device current (in host code the array's name is a host-side stand-in, never a device
+// address: kernels and copies get the looked-up pointer only).
+int scratch_init(int device) {
+  if (device < 0 || device >= kScratchDevices) return BLB_EINVAL;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[device]) return BLB_OK;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return BLB_EDEVICE;
+  }
+  g_scratch_dev[device] = (char*)p;
+  return BLB_OK;
+}
+char* scratch_of(int device) {
+  if (device < 0 || device >= kScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_dev[device];
+}
+
 // ==========================================================================================
 // C ABI
 // ==========================================================================================
@@ -665,6 +720,7 @@ const char* blb_status_str(int code) {
     case BLB_ENOMEM: return "out of device memory or over the HBM budget";
     case BLB_EDEVICE: return "HIP runtime error";
     case BLB_EBUSY: return "queue full";
+    case BLB_ETOOBIG: return "operand needs more than the fixed scratch of the allocation-free entry point";
     default: return "unknown status";
   }
 }
@@ -678,6 +734,10 @@ int blb_ctx_create(const blb_params* prm, blb_ctx** out) {
   const int alpha = (prm->n_q + prm->dnum - 1) / prm->dnum;
   if (alpha > BLB_MAXALPHA) return BLB_EINVAL;
   if (hipSetDevice(prm->device) != hipSuccess) return BLB_EDEVICE;
+  {
+    const int src = scratch_init(prm->device);
+    if (src) return src;
+  }
   blb_ctx* c = new (std::nothrow) blb_ctx();
   if (!c) return BLB_ENOMEM;
   {
@@ -1189,6 +1249,26 @@ int blb_rotate(blb_ctx* c, const blb_keys* K, const blb_ct* in, int32_t steps, b
   out->degree = 1;
   out->scale = in->scale;
   return BLB_OK;
+}
+
+// blb_rotate with every temporary in the device's fixed scratch array: the key switch's
+// ModUp digits, inner products and ModDown corrections (all written before they are read, so
+// nothing needs clearing).  No allocation of any kind.
+int blb_rotate_noalloc(blb_ctx* c, const blb_keys* K, const blb_ct* in, int32_t steps, blb_ct* out) {
+  if (!c || !K || !out || !out->data || check_ct(c, in) || in->degree != 1 || in->data == out->data) return BLB_EINVAL;
+  if (c->rec) return BLB_EINVAL;
+  char* base = scratch_of(c->device);
+  if (!base) return BLB_EDEVICE;
+  const KsLevelConst& kc = c->h_kc[in->level];
+  const size_t n = (size_t)c->n;
+  const size_t need = 8 * n * ((size_t)kc.nl + (size_t)kc.n_digits * kc.n_ext + 2 * (size_t)kc.n_ext + 2 * (size_t)kc.nl) + 4 * 256;
+  if (need > kScratchBytes) return BLB_ETOOBIG;
+  FixedArena fa{base, kScratchBytes, 0, false};
+  c->fixed = &fa;
+  int rc = blb_rotate(c, K, in, steps, out);
+  c->fixed = nullptr;
+  if (fa.overflow) rc = BLB_ETOOBIG;
+  return rc;
 }
 
 int blb_rescale(blb_ctx* c, const blb_ct* in, blb_ct* out) {

@@ -169,6 +169,14 @@ struct TimedSpan {
 // Recording state of a graph executor: while set on a context, temporaries come from the
 // executor's arena, descriptor tables go to its blob, timing spans are off, and the mask
 // seed is read from its parameter block.
+// A fixed device region that temporaries are carved from, stack-like, instead of the stream
+// stacks (the allocation-free entry points)
+struct FixedArena {
+  char* base;
+  size_t cap, off;
+  bool overflow;
+};
+
 struct ExecRec {
   char* arena = nullptr;
   size_t arena_cap = 0, arena_off = 0;
@@ -198,6 +206,7 @@ struct Workspace {
 struct blb_ctx {
   int log_n, n, n_q, n_sp, dnum, alpha;
   ExecRec* rec = nullptr;
+  FixedArena* fixed = nullptr;     // set only inside an allocation-free entry point
   std::vector<Workspace*> stacks;  // stacks of temporaries by stream
   bool timing = false;
   std::vector<TimedSpan> spans;
