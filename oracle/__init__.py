@@ -100,6 +100,11 @@ def lib():
                                            _u64p]),
             "orc_matmul_cp_diag": (C.c_int, [vp, _u64p, C.c_int, _f64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, _u64p]),
             "orc_ks_counts": (None, [_i64p, C.c_int]),
+            "orc_ew_add": (None, [vp, _u64p, _u64p, C.c_int, _u64p]),
+            "orc_ew_add_plain": (None, [vp, _u64p, _u64p, C.c_int, _u64p]),
+            "orc_ew_mul_plain": (None, [vp, _u64p, _u64p, C.c_int, _u64p]),
+            "orc_ew_mul_relin": (C.c_int, [vp, _u64p, _u64p, C.c_int, _u64p]),
+            "orc_scalar_op": (C.c_int, [vp, _u64p, _u64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _u64p]),
             "orc_cc_bsgs_split": (None, [vp, C.c_int, C.c_int, C.c_int, _i32p]),
             "orc_cc_galois_bsgs": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, _u64p]),
             "orc_matmul_cc_sched": (C.c_int, [vp, _u64p, _u64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
@@ -331,6 +336,24 @@ class Context:
         lib().orc_add_share(self._p, _c(ct, np.uint64), level, _c(share, np.uint64), out)
         return out
 
+    def ew_add(self, a, b, level: int) -> np.ndarray:
+        """ewadd_cc: a + b"""
+        out = np.zeros((2, level + 1, self.n), np.uint64)
+        lib().orc_ew_add(self._p, _c(a, np.uint64), _c(b, np.uint64), level, out)
+        return out
+
+    def ew_add_plain(self, a, pt, level: int) -> np.ndarray:
+        """ewadd_cp: (c0 + pt, c1), pt coefficient form [level+1][N]"""
+        out = np.zeros((2, level + 1, self.n), np.uint64)
+        lib().orc_ew_add_plain(self._p, _c(a, np.uint64), _c(pt, np.uint64), level, out)
+        return out
+
+    def ew_mul_plain(self, a, pt, level: int) -> np.ndarray:
+        """ewmul_cp: (c0 pt, c1 pt), pt coefficient form [level+1][N]"""
+        out = np.zeros((2, level + 1, self.n), np.uint64)
+        lib().orc_ew_mul_plain(self._p, _c(a, np.uint64), _c(pt, np.uint64), level, out)
+        return out
+
     def mask_to_share(self, ct, level: int, target_level: int, seed: int, ct_id: int):
         masked = np.zeros((2, target_level + 1, self.n), np.uint64)
         share = np.zeros((target_level + 1, self.n), np.uint64)
@@ -401,6 +424,22 @@ class Keys:
             raise KeyError("missing Galois key")
         if rc != 0:
             raise ValueError("rotate_sum: bad arguments")
+        return out
+
+    def ew_mul_relin(self, a, b, level: int) -> np.ndarray:
+        """ewmul_cc: the tensor of a and b, relinearised"""
+        out = np.zeros((2, level + 1, self.ctx.n), np.uint64)
+        if lib().orc_ew_mul_relin(self._p, _c(a, np.uint64), _c(b, np.uint64), level, out) != 0:
+            raise KeyError("missing relinearisation key")
+        return out
+
+    def scalar_op(self, a, s, level: int, block: int, n_blocks: int, op: int, from_sum: bool = False) -> np.ndarray:
+        """sadd (op 0) / smul (op 1) of a with the broadcast of s's first block, or (from_sum) with the
+        unmasked rotate-and-sum of s"""
+        out = np.zeros((2, level + 1, self.ctx.n), np.uint64)
+        rc = lib().orc_scalar_op(self._p, _c(a, np.uint64), _c(s, np.uint64), level, block, n_blocks, op, 1 if from_sum else 0, out)
+        if rc != 0:
+            raise ValueError(f"scalar_op failed ({rc})")
         return out
 
     def rerandomize(self, ct, level: int, seed: int, ct_id: int, flood_bits: int) -> np.ndarray:

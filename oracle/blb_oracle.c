@@ -1040,6 +1040,65 @@ void orc_add_share(const orc_ctx* c, const uint64_t* ct, int level, const uint64
 }
 
 /* ------------------------------------------------------------------------------------ */
+/* Identity and Expansion operators (Table "opertors": element-wise ewadd / ewmul of ct-ct */
+/* and ct-pt, scalar sadd / smul by broadcast; Section "Consistent Packing for Single      */
+/* Operator": a summation followed by a scalar operator skips the mask and the broadcast)  */
+/* ------------------------------------------------------------------------------------ */
+static void tensor_acc(const orc_ctx* c, uint64_t* acc3, const uint64_t* a, const uint64_t* r, int nl);
+
+/* ewadd_cc: a + b (both polys, every limb) */
+void orc_ew_add(const orc_ctx* c, const uint64_t* a, const uint64_t* b, int level, uint64_t* out) {
+  size_t w = (size_t)2 * (level + 1) * c->n;
+  memcpy(out, a, 8 * w);
+  add_ct(c, out, b, level + 1, 2);
+}
+
+/* ewadd_cp: (c0 + pt, c1), pt a coefficient-form plaintext at the ciphertext's level and scale */
+void orc_ew_add_plain(const orc_ctx* c, const uint64_t* a, const uint64_t* pt, int level, uint64_t* out) {
+  orc_add_share(c, a, level, pt, out);
+}
+
+/* ewmul_cp: (c0 pt, c1 pt) in R_{Q_level}; the scale becomes the product of the two scales */
+void orc_ew_mul_plain(const orc_ctx* c, const uint64_t* a, const uint64_t* pt, int level, uint64_t* out) {
+  size_t w = (size_t)2 * (level + 1) * c->n;
+  memset(out, 0, 8 * w);
+  mac_pt(c, out, pt, a, level + 1);
+}
+
+/* ewmul_cc: the tensor (a0 b0, a0 b1 + a1 b0, a1 b1), then relinearised with the s^2 key */
+int orc_ew_mul_relin(const orc_keys* K, const uint64_t* a, const uint64_t* b, int level, uint64_t* out) {
+  const orc_ctx* c = K->c;
+  uint64_t* t3 = (uint64_t*)calloc((size_t)3 * (level + 1) * c->n, 8);
+  tensor_acc(c, t3, a, b, level + 1);
+  int rc = orc_relinearize(K, t3, level, out);
+  free(t3);
+  return rc;
+}
+
+/* sadd / smul with a ciphertext scalar column (op 0: add, 1: multiply and relinearise).
+ * from_sum = 0: s holds the scalar column in its first block of `block` slots (zero elsewhere)
+ *   and is broadcast to n_blocks blocks by the right rotate-and-sum (log2 n_blocks rotations);
+ * from_sum = 1: s is the input of a summation over its n_blocks blocks (block * n_blocks = N/2),
+ *   whose unmasked left rotate-and-sum already holds the sum in every block: the mask and the
+ *   broadcast are skipped (log2 n_blocks rotations, no product, no level).
+ * a and s at `level`; out = a (op) that vector. */
+int orc_scalar_op(const orc_keys* K, const uint64_t* a, const uint64_t* s_ct, int level, int block, int n_blocks, int op, int from_sum,
+                  uint64_t* out) {
+  const orc_ctx* c = K->c;
+  if ((op != 0 && op != 1) || (from_sum != 0 && from_sum != 1)) return -3;
+  if (from_sum && (int64_t)block * n_blocks != c->n / 2) return -3;
+  size_t w = (size_t)2 * (level + 1) * c->n;
+  uint64_t* v = (uint64_t*)malloc(8 * w);
+  int rc = orc_rotate_sum(K, s_ct, level, block, n_blocks, from_sum ? 0 : 1, 0, v);
+  if (rc == 0) {
+    if (op == 0) orc_ew_add(c, a, v, level, out);
+    else rc = orc_ew_mul_relin(K, a, v, level, out);
+  }
+  free(v);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------------------ */
 /* Re-randomisation before mask-to-share (opt-in; the paper leaves c1 as the evaluation    */
 /* produced it, and c1 depends on the server's weights)                                    */
 /* ------------------------------------------------------------------------------------ */

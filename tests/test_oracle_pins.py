@@ -1188,3 +1188,104 @@ def test_rotate_sum_closed_forms(orc, block, n_blocks):
     got = c.decode(k.decrypt(k.rotate_sum(ctx_, level, block, n_blocks, 0), level - 1), level - 1, scale)
     assert np.abs(got[:L] - X.sum(axis=1)).max() < 2.0 ** -18
     assert np.abs(got[L:]).max() < 2.0 ** -18
+
+
+# --------------------------------------------------------------------------------------
+# Identity and Expansion operators: element-wise ct-ct / ct-pt, scalar by broadcast
+# --------------------------------------------------------------------------------------
+def _lift_limbs(words, mods):
+    return [[int(x) for x in words[i]] for i in range(len(mods))]
+
+
+def test_elementwise_add_and_plain_ops_decrypt_exactly(orc):
+    """ewadd_cc, ewadd_cp and ewmul_cp against decryption, limb by limb and exactly: Dec(a + b) =
+    Dec(a) + Dec(b); Dec(a + p) = Dec(a) + p; Dec(a p) = Dec(a) p with the product taken as the
+    schoolbook negacyclic convolution at N = 16 (decryption is linear, so these hold word for word)."""
+    for log_n in (4, 12):
+        c = orc.Context(log_n, 3, 1, 3)
+        k = orc.Keys(c, 9, [])
+        rng = np.random.default_rng(log_n)
+        level = 2
+        mods = [int(q) for q in c.moduli[:level + 1]]
+        a = k.encrypt(c.encode_rns(rng.normal(0, 1, c.slots), 2.0 ** 30, level), level, 1, 0)
+        b = k.encrypt(c.encode_rns(rng.normal(0, 1, c.slots), 2.0 ** 30, level), level, 1, 1)
+        p = np.stack([rng.integers(0, q, c.n, dtype=np.uint64) for q in mods])
+        da, db = k.decrypt(a, level), k.decrypt(b, level)
+        for i, q in enumerate(mods):
+            assert [int(x) for x in k.decrypt(c.ew_add(a, b, level), level)[i]] == [(int(x) + int(y)) % q for x, y in zip(da[i], db[i])]
+            assert [int(x) for x in k.decrypt(c.ew_add_plain(a, p, level), level)[i]] == [(int(x) + int(y)) % q for x, y in zip(da[i], p[i])]
+            if log_n == 4:
+                assert [int(x) for x in k.decrypt(c.ew_mul_plain(a, p, level), level)[i]] == schoolbook_negacyclic(da[i], p[i], q)
+
+
+def test_elementwise_mul_relin(orc):
+    """ewmul_cc: the relinearised tensor decrypts to Dec(a) Dec(b) (schoolbook at N = 16) up to a small
+    key-switch term, and at N = 4096 decodes to the slot-wise product (scale Delta^2)."""
+    c = orc.Context(4, 3, 1, 3)
+    k = orc.Keys(c, 9, [])
+    rng = np.random.default_rng(1)
+    level = 2
+    a = k.encrypt(c.encode_rns(rng.normal(0, 1, c.slots), 2.0 ** 20, level), level, 1, 0)
+    b = k.encrypt(c.encode_rns(rng.normal(0, 1, c.slots), 2.0 ** 20, level), level, 1, 1)
+    da, db = k.decrypt(a, level), k.decrypt(b, level)
+    got = k.decrypt(k.ew_mul_relin(a, b, level), level)
+    diff = np.zeros_like(got)
+    for i in range(level + 1):
+        q = int(c.moduli[i])
+        prod = schoolbook_negacyclic(da[i], db[i], q)
+        diff[i] = [(int(x) - y) % q for x, y in zip(got[i], prod)]
+    assert _noise(c, diff, level) < 2.0 ** 20
+    c = orc.Context(12, 3, 1, 3)
+    k = orc.Keys(c, 9, [])
+    x, y = rng.uniform(-1, 1, c.slots), rng.uniform(-1, 1, c.slots)
+    a = k.encrypt(c.encode_rns(x, 2.0 ** 40, level), level, 1, 0)
+    b = k.encrypt(c.encode_rns(y, 2.0 ** 40, level), level, 1, 1)
+    got = c.decode(k.decrypt(k.ew_mul_relin(a, b, level), level), level, 2.0 ** 80)
+    assert np.abs(got - x * y).max() < 2.0 ** -20
+
+
+@pytest.mark.parametrize("op", [0, 1])
+def test_scalar_ops_closed_forms_and_counts(orc, op):
+    """sadd / smul (Expansion) on the spatial-first packing, L' = 32, D = 64 blocks (the whole
+    ciphertext): with a scalar column s in the first block, out[j + k L'] = a[j + k L'] (+ or x) s[j];
+    after a summation, out[j] = a[j] (+ or x) sum_k z[(j mod L') + k L'].  Operation counts of
+    Table packing_scalar (summation followed by a scalar operator): without fusion, the masked sum
+    and the broadcast take 2 log2 D rotations, one product and one level; with fusion, log2 D
+    rotations, no product and no level."""
+    c = orc.Context(12, 3, 1, 3)
+    S, blk, D = c.slots, 32, 64
+    steps = []
+    st = blk
+    while st < blk * D:
+        steps += [st, -st]
+        st *= 2
+    k = orc.Keys(c, 5, sorted({c.galois_elt(x) for x in steps}))
+    rng = np.random.default_rng(op)
+    level, scale = 2, 2.0 ** 40
+    a = rng.uniform(-1, 1, S)
+    z = rng.uniform(-1, 1, S) / 8
+    idx = np.arange(S)
+    rowsum = sum(z[(idx % blk) + j * blk] for j in range(D))
+    A = k.encrypt(c.encode_rns(a, scale, level), level, 3, 0)
+    Z = k.encrypt(c.encode_rns(z, scale, level), level, 3, 1)
+    out_scale = scale if op == 0 else scale * scale
+    # with fusion: summation then scalar operator, no mask, no broadcast
+    orc.ks_counts(reset=True)
+    fused = k.scalar_op(A, Z, level, blk, D, op, from_sum=True)
+    assert orc.ks_counts(reset=True)[0] == int(np.log2(D))
+    got = c.decode(k.decrypt(fused, level), level, out_scale)
+    want = a + rowsum if op == 0 else a * rowsum
+    assert np.abs(got - want).max() < 2.0 ** -20
+    # without fusion: masked summation (one product, one level), then broadcast of its first block
+    s_ct = k.rotate_sum(Z, level, blk, D, 0, mask=True)
+    A1 = k.encrypt(c.encode_rns(a, scale, level - 1), level - 1, 3, 2)
+    out = k.scalar_op(A1, s_ct, level - 1, blk, D, op)
+    assert orc.ks_counts(reset=True)[0] == 2 * int(np.log2(D))
+    got = c.decode(k.decrypt(out, level - 1), level - 1, out_scale)
+    assert np.abs(got - want).max() < 2.0 ** -20
+    # the broadcast form on its own: a column in the first block reaches every block
+    col = np.where(idx < blk, rng.uniform(-1, 1, S), 0.0)
+    Sc = k.encrypt(c.encode_rns(col, scale, level), level, 3, 3)
+    got = c.decode(k.decrypt(k.scalar_op(A, Sc, level, blk, D, op), level), level, out_scale)
+    want = a + col[idx % blk] if op == 0 else a * col[idx % blk]
+    assert np.abs(got - want).max() < 2.0 ** -20
