@@ -28,6 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+# ct-ct schedule of the attention legs: 1 = BSGS (Appendix "BSGS Optimization"), 0 = plain
+CC_SCHEDULE = 1
 
 # HBM bytes per k_cp_mac launch on the BERT-base workload, by launch variant: rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch), each scaled by what the counter reads for a
@@ -358,10 +360,10 @@ def run_attn_out(args, B, torch):
     lvl = level - 3
     cplan = B.blb_plan_matmul_cp_diag(ctx, W, heads, d_v, L, lvl)
     g = B.blb_plan_info(cplan)
-    steps_rot = list(B.blb_cc_rotations(ctx, heads, L)) + [i * g["Lp"] for i in range(1, g["B"])] + \
+    steps_rot = list(B.blb_cc_rotations(ctx, heads, L, CC_SCHEDULE)) + [i * g["Lp"] for i in range(1, g["B"])] + \
         [j * g["B"] * g["Lp"] for j in range(1, g["G"])]
     keys = B.blb_keygen(ctx, wl.seed_for(6, wl.ROLE_KEYS), steps_rot)
-    plan = B.blb_plan_matmul_cc_sv(ctx, heads, L, d_v, level)
+    plan = B.blb_plan_matmul_cc_sv(ctx, heads, L, d_v, level, schedule=CC_SCHEDULE)
     info = B.blb_plan_cc_info(plan)
     keep, A, Bv = [], [], []
     pt = torch.empty((level + 1) * n, dtype=torch.int64, device="cuda")
@@ -470,9 +472,9 @@ def run_qk_fused(args, B, torch):
     pq = B.blb_plan_matmul_cp_mhp(ctx, WQ, heads, d, L, level)
     pk = B.blb_plan_matmul_cp_mhp(ctx, WK, heads, d, L, level)
     g = B.blb_plan_info(pq)
-    pcc = B.blb_plan_matmul_cc(ctx, heads, L, d, level - 1, b_prerotated=False)
+    pcc = B.blb_plan_matmul_cc(ctx, heads, L, d, level - 1, b_prerotated=False, schedule=CC_SCHEDULE)
     info = B.blb_plan_cc_info(pcc)
-    steps_rot = list(B.blb_cc_rotations(ctx, heads, L)) + [i * g["Lp"] for i in range(1, g["B"])] + \
+    steps_rot = list(B.blb_cc_rotations(ctx, heads, L, CC_SCHEDULE, b_prerotated=False)) + [i * g["Lp"] for i in range(1, g["B"])] + \
         [j * g["B"] * g["Lp"] for j in range(1, g["G"])]
     keys = B.blb_keygen(ctx, wl.seed_for(7, wl.ROLE_KEYS), steps_rot)
     keep = []
@@ -718,7 +720,7 @@ def run_batch(args, B, torch):
         steps = [k * g["Lp"] for k in range(1, g["B"])] + [j * g["B"] * g["Lp"] for j in range(1, g["G"])]
         keys = B.blb_keygen(ctx, wl.seed_for(4, wl.ROLE_KEYS) * 100 + i, steps)
         X = wl.batch_activations(i, L, D)
-        xs, ys, ys2 = [], [], []
+        xs, ys, ys2, yt, yt2 = [], [], [], [], []
         for a in range(g["n_in"]):
             B.blb_encode(ctx, wl.pack_spatial(X, n // 2, a), p.scale, level, pt)
             ct, t = B.new_ct(n, level)
@@ -726,11 +728,12 @@ def run_batch(args, B, torch):
             B.blb_encrypt(ctx, keys, pt, level, p.scale, wl.seed_for(4, wl.ROLE_ENC) * 100 + i, a, ct)
             xs.append(ct)
         for b in range(g["n_out"]):
-            for lst in (ys, ys2):
+            for lst, tl in ((ys, yt), (ys2, yt2)):
                 ct, t = B.new_ct(n, level - 1)
                 keep.append(t)
                 lst.append(ct)
-        insts.append(dict(keys=keys, plan=plan, X=xs, Y=ys, Y2=ys2))
+                tl.append(t)
+        insts.append(dict(keys=keys, plan=plan, X=xs, Y=ys, Y2=ys2, Yt=yt, Y2t=yt2, L=L, D=D))
     arr = (B.blb_cp_instance * len(insts))()
     hold = []
     for k, I in enumerate(insts):
@@ -780,12 +783,18 @@ def run_batch(args, B, torch):
         B.blb_batch_matmul_cp(ctx, arr)
     torch.cuda.synchronize()
     t_bat = (time.perf_counter() - t0) / reps
-    # bit identity (first and last output of every instance)
-    same = True
-    for k, I in enumerate(insts):
-        for b in (0, len(I["Y"]) - 1):
-            got = B.blb_export(ctx, B.blb_ct.from_address(arr[k].Y + b * ctypes.sizeof(B.blb_ct)), n)
-            same &= bool(np.array_equal(got, B.blb_export(ctx, I["Y2"][b], n)))
+    # bit identity: every output word of every instance, batched against per-instance
+    same = all(bool(torch.equal(a, b)) for I in insts for a, b in zip(I["Yt"], I["Y2t"]))
+    # decoded accuracy of the longest instance against FP64 X W
+    k_max = max(range(len(insts)), key=lambda k: (shapes[k][0], shapes[k][1]))
+    L_m, D_m = shapes[k_max]
+    dec = torch.empty(level * n, dtype=torch.int64, device="cuda")
+    vecs = []
+    for y in insts[k_max]["Y2"]:
+        B.blb_decrypt(ctx, insts[k_max]["keys"], y, dec)
+        vecs.append(B.blb_decode(ctx, dec, level - 1, y.scale, n // 2))
+    dec_err = float(np.abs(wl.unpack_spatial(vecs, L_m, D_m, n // 2) - wl.batch_activations(k_max, L_m, D_m) @ Ws[D_m]).max())
+    log(f"batch: instance {k_max} (L {L_m}, D {D_m}) decodes within {dec_err:.3e} of FP64")
     B.blb_ctx_trim(ctx)
     ex = B.blb_exec_create_batch_cp(ctx, arr)
     B.blb_exec_run(ex)
@@ -795,11 +804,10 @@ def run_batch(args, B, torch):
         B.blb_exec_run(ex)
     torch.cuda.synchronize()
     t_graph = (time.perf_counter() - t0) / reps
-    for k, I in enumerate(insts):
-        got = B.blb_export(ctx, B.blb_ct.from_address(arr[k].Y), n)
-        same &= bool(np.array_equal(got, B.blb_export(ctx, I["Y2"][0], n)))
+    same &= all(bool(torch.equal(a, b)) for I in insts for a, b in zip(I["Yt"], I["Y2t"]))
     log(f"batch: unbatched {t_unb * 1e3:.1f} ms, batched {t_bat * 1e3:.1f} ms, graph {t_graph * 1e3:.1f} ms, identical {same}")
     res = {"instances": len(insts), "plans": len(plans), "modmul_per_batch": modmul,
+           "decoded_check": {"instance": k_max, "L": L_m, "D": D_m, "max_abs_err": dec_err, "tolerance": 2.0 ** -20},
            "unbatched_ms": t_unb * 1e3, "batched_ms": t_bat * 1e3, "graph_ms": t_graph * 1e3,
            "speedup_graph_vs_unbatched": t_unb / t_graph, "speedup_batched_vs_unbatched": t_unb / t_bat,
            "modmul_per_s_graph": modmul / t_graph, "bit_identical": same, "autotune": {"best": best, "mac_ms": tune},
@@ -852,13 +860,13 @@ def run_serving(args, B, torch):
                 keep.append(t)
                 B.blb_encrypt(ctx, keys[client], pt, level, p.scale, wl.seed_for(5, wl.ROLE_ENC) + i, a, ct)
                 cts.append(ct)
-            inputs[key] = (B.blb_ct * n_in)(*cts)
+            inputs[key] = ((B.blb_ct * n_in)(*cts), X)
         ys = []
         for b in range(n_out):
             ct, t = B.new_ct(n, level - 1)
             keep.append(t)
             ys.append(ct)
-        work.append((t_arr, wid, L, client, inputs[key], (B.blb_ct * n_out)(*ys)))
+        work.append((t_arr, wid, L, client, inputs[key][0], (B.blb_ct * n_out)(*ys), inputs[key][1]))
     torch.cuda.synchronize()
     log(f"serving setup {time.time() - t_setup:.1f}s: {len(reqs)} requests, {len(inputs)} input sets, {len(steps)} rotation keys")
 
@@ -871,7 +879,7 @@ def run_serving(args, B, torch):
                 B.blb_server_add_weights(srv, wid, wl.serving_weights(wid, shape), level)
             t0 = time.perf_counter()
             ids = []
-            for t_arr, wid, L, client, X, Y in work:
+            for t_arr, wid, L, client, X, Y, _ in work:
                 dt = t0 + t_arr * stretch - time.perf_counter()
                 if dt > 0:
                     time.sleep(dt)
@@ -893,9 +901,35 @@ def run_serving(args, B, torch):
         log(f"  -> {st}")
         return st, sample
 
+    def decode_check():
+        """decoded outputs of the first request of every operator shape against FP64 X W"""
+        dec = torch.empty(level * n, dtype=torch.int64, device="cuda")
+        worst, seen = 0.0, set()
+        for t_arr, wid, L, client, X, Y, Xm in work:
+            if wid in seen:
+                continue
+            seen.add(wid)
+            vecs = []
+            for y in Y:
+                B.blb_decrypt(ctx, keys[client], y, dec)
+                vecs.append(B.blb_decode(ctx, dec, level - 1, y.scale, n // 2))
+            got = wl.unpack_spatial(vecs, Xm.shape[0], shapes[wid][1], n // 2)
+            worst = max(worst, float(np.abs(got - Xm @ wl.serving_weights(wid, shapes[wid])).max()))
+        return {"requests": len(seen), "max_abs_err": worst, "tolerance": 2.0 ** -20}
+
     served, s1 = serve(B.SERVE_RESIDENT_FIRST, 8, 2)
+    dcheck = decode_check()
+    log(f"serving: decoded check {dcheck}")
     per_op, s0 = serve(B.SERVE_FIFO, 1, 1)
+    steady = None
+    if args.serve_steady_rate > 0:  # below saturation: latency without queue growth
+        steady, _ = serve(B.SERVE_RESIDENT_FIRST, 8, 2, args.serve_steady_rate)
     st = dict(served)
+    st["decoded_check"] = dcheck
+    if steady is not None:
+        st["steady_state"] = {"offered_rps": args.serve_steady_rate, "throughput_rps": steady["throughput_rps"],
+                              "p50_ms": steady["p50_ms"], "p99_ms": steady["p99_ms"], "mean_ms": steady["mean_ms"],
+                              "completed": steady["completed"], "all_done": steady["all_done"]}
     st["offered_rate_rps"] = args.serve_rate
     st["plan_cache_GB"] = args.serve_cache_gb
     st["policy"] = "resident plans first, oldest after max_wait_ms; max_batch 8; 2 streams"
@@ -976,9 +1010,11 @@ def main():
     ap.add_argument("--no-ntt", action="store_true", help="skip the standalone NTT measurement")
     ap.add_argument("--ntt-only", action="store_true", help="run only the standalone NTT measurement (diagnostic)")
     ap.add_argument("--attn-out-only", action="store_true", help="run only the attention-output measurement (diagnostic)")
-    ap.add_argument("--serve-requests", type=int, default=80)
+    ap.add_argument("--serve-requests", type=int, default=500)
+    ap.add_argument("--serve-steady-rate", type=float, default=20.0,
+                    help="offered rate (req/s) of the below-saturation serving run (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=50.0)
-    ap.add_argument("--serve-cache-gb", type=float, default=200.0)
+    ap.add_argument("--serve-cache-gb", type=float, default=180.0)
     ap.add_argument("--serve-max-wait-ms", type=float, default=2000.0)
     ap.add_argument("--serve-sweep", type=str, default="", help="comma-separated offered rates (req/s) for a saturation curve")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB plain copy (counter reference)")

@@ -162,6 +162,7 @@ def _host_ptr(a: np.ndarray):
 # C ABI, one function per entry point
 # ---------------------------------------------------------------------------------------
 _CTX_N = {}  # ring degree of each live context, for the buffer-size checks below
+_SRV_CTX = {}  # server handle -> its context
 
 
 def _need(ctx, buf, words, what):
@@ -444,7 +445,13 @@ class Exec:
                 self._out_arr[i].level, self._out_arr[i].degree, self._out_arr[i].scale)
 
 
+def _need_share(ctx, share_dev, n_out, mask_target_level, what):
+    if mask_target_level >= 0:
+        _need(ctx, share_dev, n_out * (mask_target_level + 1) * _CTX_N.get(ctx, 0), what)
+
+
 def blb_exec_create_cp(ctx, keys, plan, X_cts, Y_cts, mask_target_level=-1, share_dev=None):
+    _need_share(ctx, share_dev, len(Y_cts), mask_target_level, "blb_exec_create_cp")
     Xa = (blb_ct * len(X_cts))(*X_cts)
     Ya = (blb_ct * len(Y_cts))(*Y_cts)
     out = C.c_void_p()
@@ -456,6 +463,7 @@ def blb_exec_create_cp(ctx, keys, plan, X_cts, Y_cts, mask_target_level=-1, shar
 
 
 def blb_exec_create_cc(ctx, keys, plan, A_cts, Bp_cts, C_cts, mask_target_level=-1, share_dev=None):
+    _need_share(ctx, share_dev, len(C_cts), mask_target_level, "blb_exec_create_cc")
     Aa = (blb_ct * len(A_cts))(*A_cts)
     Ba = (blb_ct * len(Bp_cts))(*Bp_cts)
     Ca = (blb_ct * len(C_cts))(*C_cts)
@@ -473,6 +481,8 @@ def blb_batch_matmul_cp(ctx, instances):
 
 
 def blb_exec_create_batch_cp(ctx, instances, mask_target_level=-1, share_dev=None):
+    _need_share(ctx, share_dev, sum(int(instances[k].n_out) for k in range(len(instances))), mask_target_level,
+                "blb_exec_create_batch_cp")
     out = C.c_void_p()
     _check(lib().blb_exec_create_batch_cp(ctx, instances, len(instances), mask_target_level, _ptr(share_dev), C.byref(out)),
            "blb_exec_create_batch_cp")
@@ -499,6 +509,7 @@ def blb_server_create(ctx, plan_cache_bytes, max_batch=16, max_queue=4096, n_str
     cfg = blb_server_config(plan_cache_bytes, max_batch, max_queue, n_streams, policy, max_wait_ms)
     out = C.c_void_p()
     _check(lib().blb_server_create(ctx, C.byref(cfg), C.byref(out)), "blb_server_create")
+    _SRV_CTX[out.value] = ctx
     return out.value
 
 
@@ -509,6 +520,7 @@ def blb_server_add_weights(server, weight_id, W, level):
 
 def blb_server_submit(server, keys, weight_id, L, X_arr, Y_arr, mask_seed=0, mask_target_level=-1, share_dev=None):
     """X_arr / Y_arr: ctypes arrays of blb_ct kept alive by the caller until completion"""
+    _need_share(_SRV_CTX.get(server), share_dev, len(Y_arr), mask_target_level, "blb_server_submit")
     rid = C.c_int64()
     rc = lib().blb_server_submit(server, keys, weight_id, L, C.cast(X_arr, C.c_void_p), len(X_arr), C.cast(Y_arr, C.c_void_p),
                                  len(Y_arr), mask_seed, mask_target_level, _ptr(share_dev), C.byref(rid))
@@ -536,6 +548,7 @@ def blb_server_stats(server):
 
 def blb_server_destroy(server):
     lib().blb_server_destroy(server)
+    _SRV_CTX.pop(server, None)
 
 
 # ---------------------------------------------------------------------------------------

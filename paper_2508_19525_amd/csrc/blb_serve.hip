@@ -96,6 +96,7 @@ struct Request {
   const blb_keys* keys;
   int weight_id;
   int L, Lp;
+  int level;  // input level (its weight's); a batch holds requests of one level
   std::vector<blb_ct> X;
   blb_ct* Y;  // caller's array
   int n_out;
@@ -337,6 +338,7 @@ void worker_loop(blb_server* S) {
         if (!can_launch || (int)batch.size() >= S->cfg.max_batch) break;
         if (r == oldest && overdue) continue;
         if (S->bad_plans.count(std::make_pair(r->weight_id, r->Lp))) reject(r, S->bad_plans[std::make_pair(r->weight_id, r->Lp)]);
+        else if (!batch.empty() && r->level != batch.front()->level) continue;  // one level per batch
         else if (admit_ready(S, r)) batch.push_back(r);
       }
       // queue the plans of the oldest requests that have none, up to kGenDepth at a time
@@ -352,6 +354,7 @@ void worker_loop(blb_server* S) {
       // arrival order; a missing plan is built synchronously before its request runs
       for (Request* r : pending) {
         if ((int)batch.size() >= S->cfg.max_batch) break;
+        if (!batch.empty() && r->level != batch.front()->level) break;  // one level per batch
         if (!plan_ready(S, r)) {
           r->seen = true;  // a miss
           const int g = generate_plan(S, r, false);
@@ -395,10 +398,12 @@ void worker_loop(blb_server* S) {
       inst.push_back(I);
       r->state = 1;
     }
-    int rc = blb_batch_matmul_cp(c, inst.data(), (int)inst.size());
+    const int rc = blb_batch_matmul_cp(c, inst.data(), (int)inst.size());
+    // mask-and-share per request: a failure marks that request only
+    std::vector<int> mrc(batch.size(), BLB_OK);
     for (size_t k = 0; k < batch.size() && rc == BLB_OK; ++k)
       if (batch[k]->share)
-        rc = blb_mask_to_share(c, batch[k]->Y, batch[k]->n_out, batch[k]->mask_seed, batch[k]->target_level, batch[k]->share);
+        mrc[k] = blb_mask_to_share(c, batch[k]->Y, batch[k]->n_out, batch[k]->mask_seed, batch[k]->target_level, batch[k]->share);
     Batch b;
     b.reqs = batch;
     b.stream = next_stream;
@@ -406,9 +411,11 @@ void worker_loop(blb_server* S) {
     (void)hipEventRecord(b.done, c->stream);
     c->stream = saved;
     next_stream = (next_stream + 1) % (int)S->streams.size();
-    if (rc != BLB_OK) {
+    {
       std::lock_guard<std::mutex> lk(S->mu);
-      for (Request* r : batch) r->state = rc;
+      for (size_t k = 0; k < batch.size(); ++k)
+        if (rc != BLB_OK) batch[k]->state = rc;
+        else if (mrc[k] != BLB_OK) batch[k]->state = mrc[k];
     }
     ++S->batches;
     S->running.push_back(b);
@@ -527,6 +534,11 @@ int blb_server_submit(blb_server* S, const blb_keys* keys, int weight_id, int L,
   if (n_in != (w.d_in + cc - 1) / cc || n_out != (w.d_out + cc - 1) / cc) return BLB_EINVAL;
   for (int a = 0; a < n_in; ++a)
     if (!X[a].data || X[a].level != w.level || X[a].degree != 1) return BLB_ELEVEL;
+  for (int b = 0; b < n_out; ++b)
+    if (!Y[b].data) return BLB_EINVAL;
+  // mask-to-share runs on the outputs (level w.level - 1): its target must exist and the share
+  // buffer must be given
+  if (mask_target_level >= 0 && (mask_target_level > w.level - 1 || !share_dev)) return mask_target_level > w.level - 1 ? BLB_ELEVEL : BLB_EINVAL;
   // a request whose keys lack a rotation is refused here rather than failing a whole batch
   if (cp_check_keys(S->c, keys, L, w.d_in, w.d_out) != BLB_OK) return BLB_ENOKEY;
   Request* r = new (std::nothrow) Request();
@@ -536,6 +548,7 @@ int blb_server_submit(blb_server* S, const blb_keys* keys, int weight_id, int L,
   r->weight_id = weight_id;
   r->L = L;
   r->Lp = Lp;
+  r->level = w.level;
   r->X.assign(X, X + n_in);
   r->Y = Y;
   r->n_out = n_out;

@@ -161,3 +161,66 @@ def test_batched_instance_matches_oracle(env, orc):
         B.blb_keys_destroy(I["keys"])
     for p in plans.values():
         B.blb_plan_destroy(p)
+
+
+def test_batched_c4_geometry_against_oracle(env, orc):
+    """The batched workload's largest geometry: an instance with L = 500 (L' = 512) and hidden
+    1024 at N = 8192, batched with a small hidden-768 instance.  Two sampled outputs equal the
+    oracle's words (SHA-256 of the oracle's outputs written by tests/golden/make_cp_sampled_hashes.py,
+    since the full oracle product takes minutes), and every output of both instances decodes to
+    X W in FP64 within 2^-20."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import make_cp_sampled_hashes as gold
+    B, wl, ctx = env
+    n, level, scale = 8192, 2, 2.0 ** 40
+    prm, lvl, L, src, xseed, kseed, eseed, outs = gold.CASES["c4_L500_D1024"]
+    assert prm == (13, 3, 1, 3) and lvl == level
+    table = gold.load()
+    W, X = gold.inputs("c4_L500_D1024")
+    W2, X2 = wl.batch_weights(768), wl.batch_activations(3, 37, 768)
+    keep, inst, hold = [], [], []
+    pt = torch.empty((level + 1) * n, dtype=torch.int64, device="cuda")
+    for (Wm, Xm, ks, es) in ((W, X, kseed, eseed), (W2, X2, 955, 4955)):
+        lp = wl.lp_of(Xm.shape[0])
+        plan = B.blb_plan_matmul_cp(ctx, Wm, lp, level)
+        g = B.blb_plan_info(plan)
+        steps = [k * g["Lp"] for k in range(1, g["B"])] + [j * g["B"] * g["Lp"] for j in range(1, g["G"])]
+        keys = B.blb_keygen(ctx, ks, steps)
+        xs, ys = [], []
+        for a in range(g["n_in"]):
+            B.blb_encode(ctx, wl.pack_spatial(Xm, n // 2, a), scale, level, pt)
+            ct, t = B.new_ct(n, level)
+            keep.append(t)
+            B.blb_encrypt(ctx, keys, pt, level, scale, es, a, ct)
+            xs.append(ct)
+        for b in range(g["n_out"]):
+            ct, t = B.new_ct(n, level - 1)
+            keep.append(t)
+            ys.append(ct)
+        inst.append(dict(keys=keys, plan=plan, X=xs, Y=ys, Xm=Xm, W=Wm, g=g))
+    assert (inst[0]["g"]["Lp"], inst[0]["g"]["n_in"], inst[0]["g"]["n_out"]) == (512, 128, 128)
+    arr, hold = _abi_instances(B, inst)
+    B.blb_batch_matmul_cp(ctx, arr)
+    torch.cuda.synchronize()
+    # the library's encryption of X equals the oracle's, so the hashed oracle outputs share its inputs
+    o = orc.Context(*prm)
+    keys_o = orc.Keys(o, kseed, [])
+    assert np.array_equal(B.blb_export(ctx, inst[0]["X"][0], n),
+                          keys_o.encrypt(o.encode_rns(o.pack_spatial(X, 0), scale, level), level, eseed, 0))
+    for b in outs:
+        got = B.blb_export(ctx, B.blb_ct.from_address(arr[0].Y + b * B.C.sizeof(B.blb_ct)), n)
+        assert gold.words_hash(got) == table[("c4_L500_D1024", b)], f"output {b}"
+    dec = torch.empty(level * n, dtype=torch.int64, device="cuda")
+    for k, I in enumerate(inst):
+        vecs = []
+        for b in range(I["g"]["n_out"]):
+            y = B.blb_ct.from_address(arr[k].Y + b * B.C.sizeof(B.blb_ct))
+            B.blb_decrypt(ctx, I["keys"], y, dec)
+            vecs.append(B.blb_decode(ctx, dec, level - 1, y.scale, n // 2))
+        got = wl.unpack_spatial(vecs, I["Xm"].shape[0], I["W"].shape[1], n // 2)
+        assert np.abs(got - I["Xm"] @ I["W"]).max() < 2.0 ** -20, f"instance {k}"
+    for I in inst:
+        B.blb_keys_destroy(I["keys"])
+        B.blb_plan_destroy(I["plan"])

@@ -156,3 +156,22 @@ def test_attention_and_share_entry_points_reject_bad_arguments(env):
     assert _code(B.blb_plan_matmul_cc_sv, ctx, 4, 16, 32, 1) == B.BLB_EINVAL
     assert _code(B.blb_plan_matmul_cp_diag, ctx, np.zeros((128, 8)), 1, 128, 64, 1) == B.BLB_EINVAL
     assert _code(B.blb_plan_matmul_cp_mhp, ctx, np.zeros((8, 16)), 1, 16, 8, 1) == B.BLB_EINVAL
+
+
+def test_executors_refuse_undersized_share_buffers(env):
+    """The binding checks the share tensor of an executor with mask-to-share against the words the
+    replays write (n_out (target + 1) N) before recording anything."""
+    B, ctx, keys = env
+    W = np.random.default_rng(2).normal(0, 0.02, (32, 32))
+    plan = B.blb_plan_matmul_cp(ctx, W, 32, 1)
+    try:
+        x, xt = _fresh_ct(B, ctx, keys)
+        y, yt = B.new_ct(4096, 0)
+        small = torch.zeros(4096 - 1, dtype=torch.int64, device="cuda")
+        assert _code(B.blb_exec_create_cp, ctx, keys, plan, [x], [y], 0, small) == B.BLB_EINVAL
+        arr = (B.blb_cp_instance * 1)()
+        Xa, Ya = (B.blb_ct * 1)(x), (B.blb_ct * 1)(y)
+        arr[0] = B.blb_cp_instance(keys, plan, B.C.cast(Xa, B.C.c_void_p), 1, B.C.cast(Ya, B.C.c_void_p), 1)
+        assert _code(B.blb_exec_create_batch_cp, ctx, arr, 0, small) == B.BLB_EINVAL
+    finally:
+        B.blb_plan_destroy(plan)

@@ -97,7 +97,38 @@ def test_bert_base_matmul_cp_full_size(B, orc):
         B.blb_ctx_destroy(ctx)
 
 
-def test_attention_matmul_cc_full_size(B, orc):
+def _bsgs_counts(lp, groups):
+    """Key switches and ct-pt (mask) products of the BSGS schedule with B' pre-rotated, counted
+    from its definition: groups = [(c, n_ct, n_out)], B = 2^ceil(log2(L')/2), G = L'/B; baby inner
+    rotations (i < B) of B', giant ones (0 < j < G) of A, a step-3 rotation per t with t mod c != 0,
+    one postponed rotation per (output, j > 0, half) receiving a term, one relinearisation per t."""
+    lb = (lp - 1).bit_length()
+    Bb = 1 << ((lb + 1) // 2)
+    G = lp // Bb
+    ks, ptm = 0, 0
+    for cc, m, n_out in groups:
+        n_diag = lp // cc
+        ks += 2 * m * (Bb - 1) + 2 * m * (G - 1) + sum(1 for t in range(lp) if t % cc) + lp
+        ptm += m * (1 + 2 * (Bb - 1)) + 2 * m * (G - 1)
+        for j in range(G):
+            outs = set()
+            for t in range(j * Bb, j * Bb + Bb):
+                n_mask = 1 + (1 if t % cc else 0)
+                ptm += n_mask * (1 if j == 0 else 2)
+                outs.add((t // cc) % n_out)
+                if t % cc:
+                    outs.add(((t // cc + 1) % n_diag) % n_out)
+            if j:
+                ks += 2 * len(outs)
+    return ks, ptm
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_attention_matmul_cc_full_size(B, orc, schedule):
+    """BERT-base Q_h K_h^T (12 heads of 128 tokens, d_head 64, N = 16384, four primes + two special)
+    through the plain and the BSGS schedule: operation counters equal each schedule's closed form
+    (BSGS: 1086 key switches instead of 3536), one sampled output per head group equals the
+    oracle's word for word, and every head decodes to Q_h K_h^T within 2^-20."""
     from paper_2508_19525_amd import workloads as wl
     cfg = wl.C3
     p = cfg["params"]
@@ -110,10 +141,10 @@ def test_attention_matmul_cc_full_size(B, orc):
     ctx = B.blb_ctx_create(p.log_n, p.n_q, p.n_special, p.dnum, 0, torch.cuda.current_stream().cuda_stream)
     keep = []
     try:
-        steps = B.blb_cc_rotations(ctx, heads, L)
+        steps = B.blb_cc_rotations(ctx, heads, L, schedule)
         keys_o = orc.Keys(o, 79, sorted({o.galois_elt(s) for s in steps}))
         keys = B.blb_keygen(ctx, 79, steps)
-        plan = B.blb_plan_matmul_cc(ctx, heads, L, d, level)
+        plan = B.blb_plan_matmul_cc(ctx, heads, L, d, level, schedule=schedule)
         info = B.blb_plan_cc_info(plan)
         assert [(g["H"], g["c"], g["n_ct"], g["n_out"]) for g in info["groups"]] == [(8, 8, 8, 16), (4, 16, 4, 8)]
         A, Bp, words, h0 = [], [], [], 0
@@ -136,12 +167,15 @@ def test_attention_matmul_cc_full_size(B, orc):
         # step 3: one right rotation per t with t mod c != 0
         assert cnt["tensor_products"] == 128 * 128 * 768 // 8192 == 1536
         assert cnt["relinearisations"] == 2 * 128
-        assert cnt["key_switches"] == 12 * 2 * 127 + 2 * 128 + (128 - 16) + (128 - 8)
-        assert cnt["ct_pt_products"] == 12 * (1 + 2 * 127) + (16 + 2 * 112) + (8 + 2 * 120)
+        if schedule == 0:
+            assert cnt["key_switches"] == 12 * 2 * 127 + 2 * 128 + (128 - 16) + (128 - 8)
+            assert cnt["ct_pt_products"] == 12 * (1 + 2 * 127) + (16 + 2 * 112) + (8 + 2 * 120)
+        else:
+            assert (cnt["key_switches"], cnt["ct_pt_products"]) == _bsgs_counts(128, [(8, 8, 16), (16, 4, 8)]) == (1086, 1455)
         # one sampled output per head group, word for word
         base, sample = 0, 5
         for (aw, bw), grp in zip(words, info["groups"]):
-            want = keys_o.matmul_cc(aw, bw, level, grp["H"], L, d, outputs=[sample])
+            want = keys_o.matmul_cc(aw, bw, level, grp["H"], L, d, outputs=[sample], schedule=schedule)
             assert np.array_equal(B.blb_export(ctx, Cd[base + sample], n), want[sample]), f"group H={grp['H']}"
             base += grp["n_out"]
         # every head decodes to Q_h K_h^T
@@ -166,13 +200,15 @@ def test_attention_matmul_cc_full_size(B, orc):
         B.blb_ctx_destroy(ctx)
 
 
-def test_attention_output_full_size(B, orc):
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_attention_output_full_size(B, orc, schedule):
     """BERT-base attention output (N = 16384, five primes + two special): Softmax x V_h for 12
     heads of 128 tokens with d_v = 64 (V_h zero-padded to 128 columns, folded to the dense
     diagonal packing), then Concat(Att_h) W_O (768 x 768) on that packing.  Tensor products =
-    m^3 H / s = 3072; every head decodes to S_h V_h within 2^-20 and E to (S_h V_h)_h W_O within
-    2^-14.  On the oracle's encryptions of a dense diagonal-packed input, one sampled output of the
-    diagonal-input product equals the oracle's word for word."""
+    m^3 H / s = 3072; key switches as each schedule's closed form (BSGS: 1614 instead of 6584);
+    every head decodes to S_h V_h within 2^-20 and E to (S_h V_h)_h W_O within 2^-14.  On the
+    oracle's encryptions of a dense diagonal-packed input, one sampled output of the diagonal-input
+    product equals the oracle's word for word."""
     from paper_2508_19525_amd import workloads as wl
     cfg = wl.C6
     p = cfg["params"]
@@ -188,11 +224,11 @@ def test_attention_output_full_size(B, orc):
         g = o.cp_geometry(L, heads * d_v, d_out)
         assert (g["Lp"], g["c"], g["c_eff"], g["n_in"], g["n_out"], g["B"], g["G"]) == (128, 64, 64, 12, 12, 8, 8)
         cp_steps = [i * g["Lp"] for i in range(1, g["B"])] + [j * g["B"] * g["Lp"] for j in range(1, g["G"])]
-        steps = list(B.blb_cc_rotations(ctx, heads, L)) + cp_steps
+        steps = list(B.blb_cc_rotations(ctx, heads, L, schedule)) + cp_steps
         gal = sorted({o.galois_elt(s) for s in steps})
         keys_o = orc.Keys(o, 83, gal)
         keys = B.blb_keygen(ctx, 83, steps)
-        plan = B.blb_plan_matmul_cc_sv(ctx, heads, L, d_v, level)
+        plan = B.blb_plan_matmul_cc_sv(ctx, heads, L, d_v, level, schedule=schedule)
         info = B.blb_plan_cc_info(plan)
         assert [(x["H"], x["c"], x["n_ct"], x["n_out"]) for x in info["groups"]] == [(8, 8, 16, 8), (4, 16, 8, 4)]
         A, Bv, h0 = [], [], 0
@@ -211,7 +247,10 @@ def test_attention_output_full_size(B, orc):
         torch.cuda.synchronize()
         assert cnt["tensor_products"] == 128 ** 3 * 12 // 8192 == 3072
         assert cnt["relinearisations"] == 2 * 128
-        assert cnt["key_switches"] == 24 * 2 * 127 + 2 * 128 + (128 - 16) + (128 - 8)
+        if schedule == 0:
+            assert cnt["key_switches"] == 24 * 2 * 127 + 2 * 128 + (128 - 16) + (128 - 8)
+        else:
+            assert cnt["key_switches"] == _bsgs_counts(128, [(8, 16, 8), (16, 8, 4)])[0] == 1614
         dec = torch.empty((level + 1) * n, dtype=torch.int64, device="cuda")  # room for any level
 
         def decode(ct):
@@ -232,6 +271,11 @@ def test_attention_output_full_size(B, orc):
         vecs = [decode(e) for e in E]
         ref = np.concatenate([S[h] @ V[h] for h in range(heads)], axis=1) @ W
         assert np.abs(wl.unpack_spatial(vecs, L, d_out, slots) - ref).max() < 2.0 ** -14
+        if schedule == 0:  # the diagonal-input product does not depend on the ct-ct schedule
+            B.blb_plan_destroy(cplan)
+            B.blb_plan_destroy(plan)
+            B.blb_keys_destroy(keys)
+            return
         # word-for-word sample of the diagonal-input product on oracle-encrypted inputs
         rng = np.random.default_rng(wl.seed_for(6, wl.ROLE_ENC))
         X = np.zeros((g["n_in"], slots))

@@ -171,3 +171,157 @@ def test_submit_refuses_request_without_its_keys(env):
         B.blb_keys_destroy(bare)
         for k in keys:
             B.blb_keys_destroy(k)
+
+
+def test_served_c5_geometry_against_oracle(orc):
+    """The serving configuration's own geometry: N = 16384, four primes + two special (dnum 2),
+    BERT-large 1024 x 4096 and 4096 x 1024 operators at L = 200 (L' = 256) and a GPT-2-base
+    768 x 768 operator at L = 100, submitted together.  Sampled outputs equal the oracle's words
+    (SHA-256 of the oracle's outputs written by tests/golden/make_cp_sampled_hashes.py), every
+    output decodes to X W in FP64 within 2^-20, and each request run alone afterwards gives the
+    words it gave in the mix."""
+    import os
+    import sys
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import make_cp_sampled_hashes as gold
+    import paper_2508_19525_amd as B
+    from paper_2508_19525_amd import workloads as wl
+    names = ["c5_1024x4096_L200", "c5_4096x1024_L200", "c5_768x768_L100"]
+    table = gold.load()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()  # the plan cache below is one 150 GiB device allocation
+    n, level, scale = 16384, 3, 2.0 ** 40
+    ctx = B.blb_ctx_create(14, 4, 2, 2, 0, torch.cuda.current_stream().cuda_stream)
+    keep, reqs, keys = [], [], []
+    srv = None
+    try:
+        pt = torch.empty((level + 1) * n, dtype=torch.int64, device="cuda")
+        for name in names:
+            prm, lvl, L, src, xseed, kseed, eseed, outs = gold.CASES[name]
+            assert prm == (14, 4, 2, 2) and lvl == level
+            W, X = gold.inputs(name)
+            lp = wl.lp_of(L)
+            cc = (n // 2) // lp
+            d_in, d_out = W.shape
+            ce = min(cc, 1 << int(np.ceil(np.log2(d_in))))
+            Bb = 1 << ((int(np.ceil(np.log2(ce))) + 1) // 2)
+            steps = [k * lp for k in range(1, Bb)] + [j * Bb * lp for j in range(1, ce // Bb)]
+            k = B.blb_keygen(ctx, kseed, steps)
+            keys.append(k)
+            n_in, n_out = -(-d_in // cc), -(-d_out // cc)
+            xs = []
+            for a in range(n_in):
+                B.blb_encode(ctx, wl.pack_spatial(X, n // 2, a), scale, level, pt)
+                ct, t = B.new_ct(n, level)
+                keep.append(t)
+                B.blb_encrypt(ctx, k, pt, level, scale, eseed, a, ct)
+                xs.append(ct)
+            ys = []
+            for b in range(n_out):
+                ct, t = B.new_ct(n, level - 1)
+                keep.append(t)
+                ys.append(ct)
+            reqs.append(dict(name=name, wid=src[1], W=W, X=X, L=L, keys=k, Xa=(B.blb_ct * n_in)(*xs), Y=(B.blb_ct * n_out)(*ys),
+                             outs=outs))
+        torch.cuda.synchronize()
+        srv = B.blb_server_create(ctx, plan_cache_bytes=150 << 30, max_batch=4, n_streams=2)
+        for r in reqs:
+            B.blb_server_add_weights(srv, r["wid"], r["W"], level)
+        ids = [B.blb_server_submit(srv, r["keys"], r["wid"], r["L"], r["Xa"], r["Y"]) for r in reqs]
+        B.blb_server_drain(srv, 300)
+        assert [B.blb_server_poll(srv, i)[0] for i in ids] == [2] * len(ids)
+        mix = [[B.blb_export(ctx, y, n) for y in r["Y"]] for r in reqs]
+        o = orc.Context(14, 4, 2, 2)
+        dec = torch.empty(level * n, dtype=torch.int64, device="cuda")
+        for r, words in zip(reqs, mix):
+            prm, lvl, L, src, xseed, kseed, eseed, outs = gold.CASES[r["name"]]
+            keys_o = orc.Keys(o, kseed, [])
+            want0 = keys_o.encrypt(o.encode_rns(o.pack_spatial(r["X"], 0), scale, level), level, eseed, 0)
+            assert np.array_equal(B.blb_export(ctx, r["Xa"][0], n), want0), r["name"]
+            for b in outs:
+                assert gold.words_hash(words[b]) == table[(r["name"], b)], f"{r['name']} output {b}"
+            vecs = []
+            for y in r["Y"]:
+                B.blb_decrypt(ctx, r["keys"], y, dec)
+                vecs.append(B.blb_decode(ctx, dec, level - 1, y.scale, n // 2))
+            got = wl.unpack_spatial(vecs, r["L"], r["W"].shape[1], n // 2)
+            assert np.abs(got - r["X"] @ r["W"]).max() < 2.0 ** -20, r["name"]
+        # each request alone (its plan now resident) gives the words it gave in the mix
+        for r, words in zip(reqs, mix):
+            ys = []
+            for b in range(len(r["Y"])):
+                ct, t = B.new_ct(n, level - 1)
+                keep.append(t)
+                ys.append(ct)
+            Y2 = (B.blb_ct * len(ys))(*ys)
+            rid = B.blb_server_submit(srv, r["keys"], r["wid"], r["L"], r["Xa"], Y2)
+            B.blb_server_drain(srv, 300)
+            assert B.blb_server_poll(srv, rid)[0] == 2
+            for b in range(len(ys)):
+                assert np.array_equal(B.blb_export(ctx, Y2[b], n), words[b]), f"{r['name']} output {b} alone vs mix"
+    finally:
+        if srv is not None:
+            B.blb_server_destroy(srv)
+        for k in keys:
+            B.blb_keys_destroy(k)
+        torch.cuda.synchronize()
+        B.blb_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("policy", [1, 0])
+def test_weights_at_different_levels(env, policy):
+    """Two weights registered at different levels: batches hold requests of one level, so a mix of
+    both completes, and every request gives the words it gives alone."""
+    B, wl, ctx = env
+    keys = _keys_for_all(B, wl, ctx, 2)
+    hi, keep_hi = _make_requests(B, wl, ctx, [(0, 40, 0, 21), (0, 100, 1, 22), (0, 16, 0, 23)], keys, level=2)
+    lo, keep_lo = _make_requests(B, wl, ctx, [(1, 40, 1, 24), (1, 64, 0, 25)], keys, level=1)
+    srv = B.blb_server_create(ctx, plan_cache_bytes=1 << 30, max_batch=8, n_streams=2, policy=policy, max_wait_ms=50.0)
+    try:
+        B.blb_server_add_weights(srv, 0, wl.serving_weights(0, SHAPES[0]), 2)
+        B.blb_server_add_weights(srv, 1, wl.serving_weights(1, SHAPES[1]), 1)
+        mixed = [hi[0], lo[0], hi[1], lo[1], hi[2]]
+        ids = [B.blb_server_submit(srv, keys[r["client"]], r["wid"], r["L"], r["X"], r["Y"]) for r in mixed]
+        B.blb_server_drain(srv, 120)
+        assert [B.blb_server_poll(srv, i)[0] for i in ids] == [2] * len(ids)
+        assert B.blb_server_stats(srv)["failed"] == 0
+        words = [[B.blb_export(ctx, y, 8192) for y in r["Y"]] for r in mixed]
+        for r, w in zip(mixed, words):
+            rid = B.blb_server_submit(srv, keys[r["client"]], r["wid"], r["L"], r["X"], r["Y"])
+            B.blb_server_drain(srv, 120)
+            assert B.blb_server_poll(srv, rid)[0] == 2
+            for b, y in enumerate(r["Y"]):
+                assert np.array_equal(B.blb_export(ctx, y, 8192), w[b]), f"weight {r['wid']} L {r['L']} output {b}"
+    finally:
+        B.blb_server_destroy(srv)
+        for k in keys:
+            B.blb_keys_destroy(k)
+
+
+def test_submit_checks_mask_target_and_share(env):
+    """A mask target above the outputs' level is refused at submission (ELEVEL), so it cannot fail
+    the batch it would join; an undersized share tensor is refused by the binding."""
+    B, wl, ctx = env
+    keys = _keys_for_all(B, wl, ctx, 1)
+    reqs, keep = _make_requests(B, wl, ctx, [(0, 40, 0, 31)], keys)
+    srv = B.blb_server_create(ctx, plan_cache_bytes=256 << 20, max_batch=4, n_streams=1)
+    try:
+        B.blb_server_add_weights(srv, 0, wl.serving_weights(0, SHAPES[0]), 2)
+        r = reqs[0]
+        with pytest.raises(B.BlbError) as ei:
+            B.blb_server_submit(srv, keys[0], 0, r["L"], r["X"], r["Y"], 5, 2, r["share"])
+        assert ei.value.code == B.BLB_ELEVEL
+        small = torch.zeros(8, dtype=torch.int64, device="cuda")
+        with pytest.raises(B.BlbError) as ei:
+            B.blb_server_submit(srv, keys[0], 0, r["L"], r["X"], r["Y"], 5, 1, small)
+        assert ei.value.code == B.BLB_EINVAL
+        rid = B.blb_server_submit(srv, keys[0], 0, r["L"], r["X"], r["Y"], 5, 1, r["share"])
+        B.blb_server_drain(srv, 60)
+        assert B.blb_server_poll(srv, rid)[0] == 2
+        assert B.blb_server_stats(srv)["rejected"] == 0
+    finally:
+        B.blb_server_destroy(srv)
+        for k in keys:
+            B.blb_keys_destroy(k)
