@@ -310,6 +310,33 @@ int blb_add_share(blb_ctx* ctx, blb_ct* cts, int n_ct, const uint64_t* share_dev
 int blb_rotate_sum(blb_ctx* ctx, const blb_keys* keys, const blb_ct* in, int n_ct, int block, int n_blocks, int direction, int mask,
                    blb_ct* out);
 
+/* ---- Identity and Expansion operators (Table "opertors": ewadd / ewmul of ct-ct and ct-pt,
+ * sadd / smul; Section "Consistent Packing for Single Operator": scalar operators by broadcast,
+ * and a summation followed by a scalar operator with neither mask nor broadcast) ----------------
+ * All take n_ct ciphertexts at one level (ELEVEL otherwise), degree 1, and write out[t] (buffers
+ * of the input size; out may be the first operand) at the same level; nothing is rescaled:
+ * products leave the product of the scales and the caller rescales with blb_rescale.
+ *   blb_ew_add:       a + b (ESCALE unless the scales agree within 1e-9 relative)
+ *   blb_ew_add_plain: (c0 + pt, c1), pt_dev [t][level+1][N] coefficient-form residues encoded at a's scale
+ *   blb_ew_mul_plain: (c0 pt, c1 pt), pt_dev as above, encoded at pt_scale; out scale = a.scale pt_scale
+ *   blb_ew_mul_relin: the tensor of a and b relinearised with the s^2 key (ENOKEY without it);
+ *                     out scale = a.scale b.scale
+ *   blb_scalar_op:    a (op 0: +, 1: x with relinearisation) the vector V made from s:
+ *                     from_sum = 0: s holds the scalar column in its first `block` slots (zero
+ *                     elsewhere) and V is its broadcast over n_blocks blocks (blb_rotate_sum,
+ *                     direction 1: log2 n_blocks rotations);
+ *                     from_sum = 1: s is the input of a summation over its n_blocks blocks, which
+ *                     fill the ciphertext (block n_blocks = N/2, EINVAL otherwise), and V is the
+ *                     unmasked left rotate-and-sum, which already holds the sum in every block
+ *                     (log2 n_blocks rotations, no mask product, no level).
+ *                     Keys as blb_rotate_sum (plus relinearisation for op 1). */
+int blb_ew_add(blb_ctx* ctx, const blb_ct* a, const blb_ct* b, int n_ct, blb_ct* out);
+int blb_ew_add_plain(blb_ctx* ctx, const blb_ct* a, int n_ct, const uint64_t* pt_dev, blb_ct* out);
+int blb_ew_mul_plain(blb_ctx* ctx, const blb_ct* a, int n_ct, const uint64_t* pt_dev, double pt_scale, blb_ct* out);
+int blb_ew_mul_relin(blb_ctx* ctx, const blb_keys* keys, const blb_ct* a, const blb_ct* b, int n_ct, blb_ct* out);
+int blb_scalar_op(blb_ctx* ctx, const blb_keys* keys, const blb_ct* a, const blb_ct* s, int n_ct, int block, int n_blocks, int op,
+                  int from_sum, blb_ct* out);
+
 /* ---- batched matmul_cp over independent instances ------------------------------------
  * Each instance has its own keys (its client), plan (plans may be shared between instances
  * with the same weights and L'), inputs and outputs; all plans must be at one level.  Every

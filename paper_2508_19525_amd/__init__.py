@@ -71,6 +71,12 @@ _SIGS = {
     "blb_import": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(blb_ct)]),
     "blb_rotate": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.c_int32, C.POINTER(blb_ct)]),
     "blb_rotate_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.c_int32, C.POINTER(blb_ct)]),
+    "blb_ew_add": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "blb_ew_add_plain": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "blb_ew_mul_plain": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_void_p]),
+    "blb_ew_mul_relin": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "blb_scalar_op": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                C.c_void_p]),
     "blb_rescale": (C.c_int, [C.c_void_p, C.POINTER(blb_ct), C.POINTER(blb_ct)]),
     "blb_ntt": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32]),
     "blb_rerandomize": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.c_int, C.c_uint64, C.c_int]),
@@ -298,6 +304,43 @@ def blb_rotate(ctx, keys, ct_in: blb_ct, steps, ct_out: blb_ct):
 def blb_rotate_noalloc(ctx, keys, ct_in: blb_ct, steps, ct_out: blb_ct):
     """blb_rotate with every temporary in the library's fixed per-device scratch (allocates nothing)"""
     _check(lib().blb_rotate_noalloc(ctx, keys, C.byref(ct_in), steps, C.byref(ct_out)), "blb_rotate_noalloc")
+
+
+def _cts_call(fn, what, out_cts, *args):
+    """call fn with blb_ct arrays; copies the outputs' (level, degree, scale) back"""
+    arrs = [(blb_ct * len(a))(*a) if isinstance(a, (list, tuple)) else a for a in args]
+    oa = (blb_ct * len(out_cts))(*out_cts)
+    _check(fn(*[C.cast(a, C.c_void_p) if isinstance(a, C.Array) else a for a in arrs], C.cast(oa, C.c_void_p)), what)
+    for i in range(len(out_cts)):
+        out_cts[i].level, out_cts[i].degree, out_cts[i].scale = oa[i].level, oa[i].degree, oa[i].scale
+
+
+def blb_ew_add(ctx, a_cts, b_cts, out_cts):
+    _cts_call(lambda *x: lib().blb_ew_add(ctx, x[0], x[1], len(a_cts), x[2]), "blb_ew_add", out_cts, a_cts, b_cts)
+
+
+def blb_ew_add_plain(ctx, a_cts, pt_dev, out_cts):
+    if a_cts:
+        _need(ctx, pt_dev, len(a_cts) * (a_cts[0].level + 1) * _CTX_N.get(ctx, 0), "blb_ew_add_plain")
+    _cts_call(lambda *x: lib().blb_ew_add_plain(ctx, x[0], len(a_cts), _ptr(pt_dev), x[1]), "blb_ew_add_plain", out_cts, a_cts)
+
+
+def blb_ew_mul_plain(ctx, a_cts, pt_dev, pt_scale, out_cts):
+    if a_cts:
+        _need(ctx, pt_dev, len(a_cts) * (a_cts[0].level + 1) * _CTX_N.get(ctx, 0), "blb_ew_mul_plain")
+    _cts_call(lambda *x: lib().blb_ew_mul_plain(ctx, x[0], len(a_cts), _ptr(pt_dev), float(pt_scale), x[1]), "blb_ew_mul_plain",
+              out_cts, a_cts)
+
+
+def blb_ew_mul_relin(ctx, keys, a_cts, b_cts, out_cts):
+    _cts_call(lambda *x: lib().blb_ew_mul_relin(ctx, keys, x[0], x[1], len(a_cts), x[2]), "blb_ew_mul_relin", out_cts, a_cts, b_cts)
+
+
+def blb_scalar_op(ctx, keys, a_cts, s_cts, block, n_blocks, op, from_sum, out_cts):
+    """op 0: a + V, 1: a x V (relinearised); V = broadcast of s's first block, or (from_sum) the
+    unmasked rotate-and-sum of s"""
+    _cts_call(lambda *x: lib().blb_scalar_op(ctx, keys, x[0], x[1], len(a_cts), block, n_blocks, op, 1 if from_sum else 0, x[2]),
+              "blb_scalar_op", out_cts, a_cts, s_cts)
 
 
 def blb_rescale(ctx, ct_in: blb_ct, ct_out: blb_ct):

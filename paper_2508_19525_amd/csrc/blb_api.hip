@@ -3149,4 +3149,170 @@ int blb_rotate_sum(blb_ctx* c, const blb_keys* K, const blb_ct* in, int n_ct, in
   return hipGetLastError() == hipSuccess ? BLB_OK : BLB_EDEVICE;
 }
 
+// ------------------------------------------------------------------------------------------
+// Identity and Expansion operators: element-wise ct-ct / ct-pt addition and multiplication,
+// scalar addition and multiplication by broadcast (or straight after a summation)
+// ------------------------------------------------------------------------------------------
+namespace {
+// n_ct pairs at one level; `same_scale` requires equal scales (additions)
+int check_pairs(const blb_ctx* c, const blb_ct* a, const blb_ct* b, int n_ct, const blb_ct* out, bool same_scale) {
+  if (!c || !a || !out || n_ct < 1) return BLB_EINVAL;
+  for (int t = 0; t < n_ct; ++t) {
+    if (check_ct(c, &a[t]) || a[t].degree != 1 || !out[t].data) return BLB_EINVAL;
+    if (a[t].level != a[0].level) return BLB_ELEVEL;
+    if (b) {
+      if (check_ct(c, &b[t]) || b[t].degree != 1) return BLB_EINVAL;
+      if (b[t].level != a[0].level) return BLB_ELEVEL;
+      if (same_scale && fabs(b[t].scale / a[t].scale - 1.0) > 1e-9) return BLB_ESCALE;
+    }
+  }
+  return BLB_OK;
+}
+void set_out(blb_ct* out, int n_ct, int level, const double* scales) {
+  for (int t = 0; t < n_ct; ++t) {
+    out[t].level = level;
+    out[t].degree = 1;
+    out[t].scale = scales[t];
+  }
+}
+}  // namespace
+
+int blb_ew_add(blb_ctx* c, const blb_ct* a, const blb_ct* b, int n_ct, blb_ct* out) {
+  if (!b) return BLB_EINVAL;
+  int rc = check_pairs(c, a, b, n_ct, out, true);
+  if (rc) return rc;
+  const int nl = a[0].level + 1;
+  std::vector<const uint64_t*> terms;
+  std::vector<uint64_t*> dsts;
+  std::vector<double> sc;
+  for (int t = 0; t < n_ct; ++t) {
+    terms.push_back(a[t].data);
+    terms.push_back(b[t].data);
+    dsts.push_back(out[t].data);
+    sc.push_back(a[t].scale);
+  }
+  const uint64_t* const* t_dev = upload_vec(c, terms);
+  uint64_t* const* d_dev = (uint64_t* const*)upload(c, dsts.data(), dsts.size() * sizeof(uint64_t*));
+  if (!t_dev || !d_dev) return BLB_EDEVICE;
+  {
+    Span sp(c, BLB_T_EW, (double)n_ct * 2 * nl * c->n);
+    launch_sum_cts(c, t_dev, d_dev, n_ct, 2, nl);
+  }
+  set_out(out, n_ct, a[0].level, sc.data());
+  return hipGetLastError() == hipSuccess ? BLB_OK : BLB_EDEVICE;
+}
+
+int blb_ew_add_plain(blb_ctx* c, const blb_ct* a, int n_ct, const uint64_t* pt_dev, blb_ct* out) {
+  if (!pt_dev) return BLB_EINVAL;
+  int rc = check_pairs(c, a, nullptr, n_ct, out, false);
+  if (rc) return rc;
+  const int n = c->n, nl = a[0].level + 1;
+  const size_t ctw = (size_t)2 * nl * n;
+  std::vector<double> sc;
+  for (int t = 0; t < n_ct; ++t) {
+    sc.push_back(a[t].scale);
+    if (out[t].data != a[t].data &&
+        hipMemcpyAsync(out[t].data, a[t].data, ctw * 8, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+      return BLB_EDEVICE;
+  }
+  std::vector<PolyDesc> d;
+  for (int t = 0; t < n_ct; ++t)
+    for (int i = 0; i < nl; ++i) {
+      PolyDesc x = pd(pt_dev + ((size_t)t * nl + i) * n, out[t].data + (size_t)i * n, i, c->log_n);
+      x.src2 = out[t].data + (size_t)i * n;
+      d.push_back(x);
+    }
+  {
+    Span sp(c, BLB_T_EW, (double)n_ct * nl * n);
+    ntt_descs(c, d, NTT_ADDTO);
+  }
+  set_out(out, n_ct, a[0].level, sc.data());
+  return hipGetLastError() == hipSuccess ? BLB_OK : BLB_EDEVICE;
+}
+
+int blb_ew_mul_plain(blb_ctx* c, const blb_ct* a, int n_ct, const uint64_t* pt_dev, double pt_scale, blb_ct* out) {
+  if (!pt_dev || !(pt_scale > 0)) return BLB_EINVAL;
+  int rc = check_pairs(c, a, nullptr, n_ct, out, false);
+  if (rc) return rc;
+  const int n = c->n, nl = a[0].level + 1;
+  Tmp tmp(c);
+  uint64_t* ptn = tmp.get<uint64_t>((size_t)n_ct * nl * n);
+  if (tmp.failed) return BLB_ENOMEM;
+  std::vector<PolyDesc> d;
+  for (int t = 0; t < n_ct; ++t)
+    for (int i = 0; i < nl; ++i) d.push_back(pd(pt_dev + ((size_t)t * nl + i) * n, ptn + ((size_t)t * nl + i) * n, i, c->log_n));
+  ntt_descs(c, d, NTT_FWD);
+  std::vector<CcPair> pairs;
+  std::vector<double> sc;
+  for (int t = 0; t < n_ct; ++t) {
+    pairs.push_back(CcPair{a[t].data, ptn + (size_t)t * nl * n, nullptr, nullptr, out[t].data});
+    sc.push_back(a[t].scale * pt_scale);
+  }
+  const CcPair* p_dev = upload_vec(c, pairs);
+  if (!p_dev) return BLB_EDEVICE;
+  {
+    Span sp(c, BLB_T_EW, (double)n_ct * 2 * nl * n);
+    c->counters[2] += n_ct;
+    launch_mask_pair(c, p_dev, n_ct, nl);
+  }
+  set_out(out, n_ct, a[0].level, sc.data());
+  return hipGetLastError() == hipSuccess ? BLB_OK : BLB_EDEVICE;
+}
+
+int blb_ew_mul_relin(blb_ctx* c, const blb_keys* K, const blb_ct* a, const blb_ct* b, int n_ct, blb_ct* out) {
+  if (!K || !b) return BLB_EINVAL;
+  int rc = check_pairs(c, a, b, n_ct, out, false);
+  if (rc) return rc;
+  const SwKey* relin = find_key(K, 0);
+  if (!relin) return BLB_ENOKEY;
+  const int n = c->n, level = a[0].level, nl = level + 1;
+  Tmp tmp(c);
+  uint64_t* T3 = tmp.get<uint64_t>((size_t)n_ct * 3 * nl * n);
+  if (tmp.failed) return BLB_ENOMEM;
+  std::vector<const uint64_t*> at, bt;
+  std::vector<double> sc;
+  for (int t = 0; t < n_ct; ++t) {
+    at.push_back(a[t].data);
+    bt.push_back(b[t].data);
+    sc.push_back(a[t].scale * b[t].scale);
+  }
+  const uint64_t* const* a_dev = upload_vec(c, at);
+  const uint64_t* const* b_dev = upload_vec(c, bt);
+  if (!a_dev || !b_dev) return BLB_EDEVICE;
+  {
+    Span sp(c, BLB_T_CC_TENSOR, (double)n_ct * nl * n);
+    c->counters[3] += n_ct;
+    c->counters[4] += n_ct;
+    launch_tensor_sum(c, a_dev, b_dev, T3, n_ct, 1, nl, nl, true);
+  }
+  std::vector<const uint64_t*> srcs;
+  std::vector<KsReq> reqs;
+  for (int t = 0; t < n_ct; ++t) {
+    const uint64_t* t3 = T3 + (size_t)t * 3 * nl * n;
+    srcs.push_back(t3 + (size_t)2 * nl * n);
+    reqs.push_back(KsReq{t, relin, 0, out[t].data, t3, 0, t3 + (size_t)nl * n});
+  }
+  if ((rc = ks_batch(c, level, srcs, reqs))) return rc;
+  set_out(out, n_ct, level, sc.data());
+  return BLB_OK;
+}
+
+int blb_scalar_op(blb_ctx* c, const blb_keys* K, const blb_ct* a, const blb_ct* s, int n_ct, int block, int n_blocks, int op,
+                  int from_sum, blb_ct* out) {
+  if (!c || !K || !s || (op != 0 && op != 1) || (from_sum != 0 && from_sum != 1)) return BLB_EINVAL;
+  int rc = check_pairs(c, a, s, n_ct, out, op == 0);
+  if (rc) return rc;
+  if (from_sum && (int64_t)block * n_blocks != c->n / 2) return BLB_EINVAL;
+  const int nl = a[0].level + 1;
+  const size_t ctw = (size_t)2 * nl * c->n;
+  Tmp tmp(c);
+  uint64_t* v = tmp.get<uint64_t>((size_t)n_ct * ctw);
+  if (tmp.failed) return BLB_ENOMEM;
+  std::vector<blb_ct> vs(n_ct);
+  for (int t = 0; t < n_ct; ++t) vs[t] = blb_ct{v + (size_t)t * ctw, a[0].level, 1, 0.0};
+  // broadcast of the first block (right rotate-and-sum), or the unmasked summation (left)
+  if ((rc = blb_rotate_sum(c, K, s, n_ct, block, n_blocks, from_sum ? 0 : 1, 0, vs.data()))) return rc;
+  return op == 0 ? blb_ew_add(c, a, vs.data(), n_ct, out) : blb_ew_mul_relin(c, K, a, vs.data(), n_ct, out);
+}
+
 }  // extern "C"

@@ -310,8 +310,9 @@ def test_submit_checks_mask_target_and_share(env):
     try:
         B.blb_server_add_weights(srv, 0, wl.serving_weights(0, SHAPES[0]), 2)
         r = reqs[0]
+        big = torch.zeros(len(r["Y"]) * 3 * 8192, dtype=torch.int64, device="cuda")  # room for a level-2 target
         with pytest.raises(B.BlbError) as ei:
-            B.blb_server_submit(srv, keys[0], 0, r["L"], r["X"], r["Y"], 5, 2, r["share"])
+            B.blb_server_submit(srv, keys[0], 0, r["L"], r["X"], r["Y"], 5, 2, big)
         assert ei.value.code == B.BLB_ELEVEL
         small = torch.zeros(8, dtype=torch.int64, device="cuda")
         with pytest.raises(B.BlbError) as ei:
