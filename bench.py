@@ -895,6 +895,11 @@ def run_serving(args, B, torch):
         st["throughput_rps"] = st["completed"] / (t_end - t0)
         st["wall_s"] = t_end - t0
         st["all_done"] = all(x == 2 for x in states)
+        codes = {}
+        for x in states:
+            if x != 2:
+                codes[B.status_str(x)] = codes.get(B.status_str(x), 0) + 1
+        st["not_done_by_state"] = codes
         torch.cuda.synchronize()
         # output words of a few requests, to compare across runs (same arithmetic => same bits)
         sample = [B.blb_export(ctx, work[i][5][0], n) for i in range(0, len(work), max(1, len(work) // 4))]
@@ -982,15 +987,80 @@ def run_cpu_baseline():
     t_baby = n_baby * t_rot
     per_out = max(t_one - t_baby, 0.0)
     full = t_baby + g["n_out"] * (per_out + t_mask)
+    cores = oracle.num_threads()
+    # single thread: the C2 rotation (the dominant primitive) and the whole C1 op
+    prev = oracle.set_threads(1)
+    t0 = time.perf_counter()
+    for i in range(2):
+        keys.rotate(xw[i], level, g["Lp"])
+    t_rot1 = (time.perf_counter() - t0) / 2
+    c1_single = _cpu_c1(oracle, wl)
+    oracle.set_threads(prev)
+    c1_all = _cpu_c1(oracle, wl)
+    c3 = _cpu_c3(oracle, wl)
+    model = "unknown"
+    try:
+        model = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {
         "value": 1.0 / full,
         "unit": "matmul_cp+rescale+mask ops/s (BERT-base 128x768x768, N=8192)",
-        "cores": oracle.num_threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": (f"1 of {g['n_out']} output ciphertexts timed ({t_one:.1f}s incl. {n_baby} baby rotations); "
                    f"baby rotations priced from 8 timed rotations ({t_rot * 1e3:.0f} ms each); "
                    f"full op extrapolated to {full:.1f}s"),
+        "cpu_model": model, "nproc": os.cpu_count(),
+        "c1_full_op": {"ops_s_all_cores": 1.0 / c1_all, "ops_s_single_thread": 1.0 / c1_single,
+                       "workload": "matmul_cp + rescale + mask of Enc(X 32x32) x W 32x32, N=4096, 2 primes, timed in full"},
+        "c2_rotation_ms": {"all_cores": t_rot * 1e3, "single_thread": t_rot1 * 1e3},
+        "c3_matmul_cc": c3,
     }
+
+
+def _cpu_c1(oracle, wl):
+    """seconds for the whole C1 op in the oracle: matmul_cp (with its rescale) and mask-to-share"""
+    cfg = wl.C1
+    p = cfg["params"]
+    L, d = cfg["L"], cfg["d_in"]
+    X = wl.activations(1, L, d, cfg["x_dist"])
+    W = wl.weights(1, d, d, cfg["w_std"])
+    c = oracle.Context(p.log_n, p.n_q, p.n_special, p.dnum)
+    level = p.n_q - 1
+    keys = oracle.Keys(c, 7, c.cp_galois(L, d, d))
+    xw = keys.encrypt(c.encode_rns(c.pack_spatial(X, 0), p.scale, level), level, 8, 0)
+    t0 = time.perf_counter()
+    Y = keys.matmul_cp(xw[None], level, W, L)
+    c.mask_to_share(Y[0], level - 1, level - 1, 9, 0)
+    return time.perf_counter() - t0
+
+
+def _cpu_c3(oracle, wl):
+    """The 12-head Q_h K_h^T (BSGS schedule) in the oracle: the 4-head group timed in full (all its
+    outputs), the 8-head group priced by key switches (the oracle's cost is dominated by them)"""
+    cfg = wl.C3
+    p = cfg["params"]
+    heads, L, d = cfg["heads"], cfg["L"], cfg["d_head"]
+    c = oracle.Context(p.log_n, p.n_q, p.n_special, p.dnum)
+    level = p.n_q - 1
+    rng = np.random.default_rng(wl.seed_for(3, wl.ROLE_X))
+    Q = [rng.normal(0, 1, (L, d)) for _ in range(4)]
+    Kt = [rng.normal(0, 1, (L, d)).T.copy() for _ in range(4)]
+    keys = oracle.Keys(c, wl.seed_for(3, wl.ROLE_KEYS), c.cc_galois(4, L, d, schedule=1))
+    g = c.cc_geometry(4, L, d)
+    A = np.stack([keys.encrypt(c.encode_rns(c.pack_mhp(Q, 4, L, d, a, "A"), p.scale, level), level, 1, a) for a in range(g["n_ct"])])
+    Bp = np.stack([keys.encrypt(c.encode_rns(c.pack_mhp(Kt, 4, L, d, a, "Bp"), p.scale, level), level, 2, a) for a in range(g["n_ct"])])
+    oracle.ks_counts(reset=True)
+    t0 = time.perf_counter()
+    keys.matmul_cc(A, Bp, level, 4, L, d, schedule=1)
+    t4 = time.perf_counter() - t0
+    rot, relin = oracle.ks_counts(reset=True)
+    ks4, ks_all = rot + relin, 1086
+    full = t4 * ks_all / ks4
+    return {"ops_s": 1.0 / full, "unit": "12-head Q_h K_h^T per s (N=16384, 4+2 primes, BSGS schedule)",
+            "sample": f"4-head group in full ({t4:.1f}s, {ks4} key switches); 12 heads priced by key switches ({ks_all}) "
+                      f"to {full:.1f}s", "cores": oracle.num_threads()}
 
 
 def main():

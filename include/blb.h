@@ -56,7 +56,7 @@ typedef struct {
 } blb_ct;
 
 typedef struct {
-  int32_t log_n;             /* 12..16 */
+  int32_t log_n;             /* 12..14 (N = 4096 .. 16384; EINVAL otherwise) */
   int32_t n_q;               /* ciphertext primes, 1..12 */
   int32_t n_special;         /* key-switching primes K, 1..4 */
   int32_t dnum;              /* number of key-switching digits, 1..n_q */

@@ -90,6 +90,7 @@ def lib():
             "orc_add_share": (None, [vp, _u64p, C.c_int, _u64p, _u64p]),
             "orc_rotate_sum": (C.c_int, [vp, _u64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _u64p]),
             "orc_num_threads": (C.c_int, []),
+            "orc_set_threads": (C.c_int, [C.c_int]),
             "orc_cc_geometry": (None, [vp, C.c_int, C.c_int, C.c_int, _i32p]),
             "orc_rerandomize": (C.c_int, [vp, _u64p, C.c_int, C.c_uint64, C.c_uint32, C.c_int, _u64p]),
             "orc_matmul_cc": (C.c_int, [vp, _u64p, _u64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, _u64p]),
@@ -125,6 +126,11 @@ def ks_counts(reset: bool = False) -> tuple:
     out = np.zeros(2, np.int64)
     lib().orc_ks_counts(out, 1 if reset else 0)
     return int(out[0]), int(out[1])
+
+
+def set_threads(n: int) -> int:
+    """thread count of the oracle's parallel loops from now on; returns the previous count"""
+    return int(lib().orc_set_threads(n))
 
 
 def num_threads() -> int:

@@ -1154,6 +1154,12 @@ int orc_rerandomize(const orc_keys* K, const uint64_t* ct, int level, uint64_t s
 /* number of OpenMP threads the oracle's parallel loops use */
 #include <omp.h>
 int orc_num_threads(void) { return omp_get_max_threads(); }
+/* thread count of the parallel loops from now on (n >= 1); returns the previous count */
+int orc_set_threads(int n) {
+  int prev = omp_get_max_threads();
+  if (n >= 1) omp_set_num_threads(n);
+  return prev;
+}
 
 /* ------------------------------------------------------------------------------------ */
 /* matmul_cc (Section "Efficient Protocol for Fused MatMuls", "Building Blocks": observations */
