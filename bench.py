@@ -245,21 +245,24 @@ def run_cc(args, B, torch, schedule=1):
         h0 += grp["H"]
         base += grp["n_out"]
     log(f"cc decoded max abs err {err:.3e}")
-    # autotuner: NTT launch variant (results are bit-identical across variants)
+    # autotuner: NTT launch variant and values per work-item (results are bit-identical)
     ntt_tune = {}
     if not args.no_tune:
-        for var in (0, 1):
+        for var, radix in ((0, 16), (1, 16), (0, 32), (1, 32)):
             B.blb_ctx_set_knob(ctx, B.BLB_KNOB_NTT_VARIANT, var)
+            B.blb_ctx_set_knob(ctx, B.BLB_KNOB_NTT_RADIX, radix)
             B.blb_matmul_cc(ctx, keys, plan, A, Bp, Cd)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(2):
                 B.blb_matmul_cc(ctx, keys, plan, A, Bp, Cd)
             torch.cuda.synchronize()
-            ntt_tune[var] = (time.perf_counter() - t0) / 2 * 1e3
-        B.blb_ctx_set_knob(ctx, B.BLB_KNOB_NTT_VARIANT, min(ntt_tune, key=ntt_tune.get))
-        log(f"cc NTT variants (ms per op): {ntt_tune}")
-    ks_var, ks_tune = tune_knob(args, B, torch, ctx, B.BLB_KNOB_KS_VARIANT, (0, 1),
+            ntt_tune[f"{var}/{radix}"] = (time.perf_counter() - t0) / 2 * 1e3
+        best = min(ntt_tune, key=ntt_tune.get)
+        B.blb_ctx_set_knob(ctx, B.BLB_KNOB_NTT_VARIANT, int(best.split("/")[0]))
+        B.blb_ctx_set_knob(ctx, B.BLB_KNOB_NTT_RADIX, int(best.split("/")[1]))
+        log(f"cc NTT variants (ms per op, launch variant / values per work-item): {ntt_tune}")
+    ks_var, ks_tune = tune_knob(args, B, torch, ctx, B.BLB_KNOB_KS_VARIANT, (0, 1, 2),
                                 lambda k: B.blb_matmul_cc(ctx, keys, plan, A, Bp, Cd))
     log(f"cc key inner-product variants (ms per op): {ks_tune} -> {ks_var}")
     # eager (timed, with kernel timing)
@@ -292,7 +295,8 @@ def run_cc(args, B, torch, schedule=1):
            "ntt_gbps": ntt_polys * 16 * n / (ntt_ms / 1e3) / 1e9 if ntt_ms > 0 else 0.0,
            "rotation_keys": len(steps_rot), "groups": info["groups"], "ops_per_product": counts,
            "key_bytes": B.blb_ctx_device_bytes(ctx),
-           "ntt_variant": B.blb_ctx_get_knob(ctx, B.BLB_KNOB_NTT_VARIANT), "ntt_tune_ms": ntt_tune,
+           "ntt_variant": B.blb_ctx_get_knob(ctx, B.BLB_KNOB_NTT_VARIANT), "ntt_radix": B.blb_ctx_get_knob(ctx, B.BLB_KNOB_NTT_RADIX),
+           "ntt_tune_ms": ntt_tune,
            "ks_variant": ks_var, "ks_tune_ms": ks_tune}
     B.blb_exec_destroy(ex)
     B.blb_plan_destroy(plan)
@@ -410,7 +414,8 @@ def run_attn_out(args, B, torch):
     err = float(np.abs(wl.unpack_spatial(vecs, L, d_out, slots) - ref).max())
     log(f"attention-output decoded max abs err {err:.3e}")
     mac_var = tune_mac(args, B, ctx, eager_step)
-    ks_var, ks_tune = tune_knob(args, B, torch, ctx, B.BLB_KNOB_KS_VARIANT, (0, 1), eager_step)
+    radix, radix_tune = tune_knob(args, B, torch, ctx, B.BLB_KNOB_NTT_RADIX, (16, 32), eager_step)
+    ks_var, ks_tune = tune_knob(args, B, torch, ctx, B.BLB_KNOB_KS_VARIANT, (0, 1, 2), eager_step)
     log(f"attention-output key inner-product variants (ms per op): {ks_tune} -> {ks_var}")
     eager_step(1)
     torch.cuda.synchronize()
@@ -442,7 +447,7 @@ def run_attn_out(args, B, torch):
     log(f"attention output: eager {steps / dt_eager:.1f}/s, graph {steps / dt:.1f}/s")
     res = {"value": steps / dt, "eager": steps / dt_eager, "ms": dt / steps * 1e3, "err": err, "split_ms": split,
            "ntt_gbps": ntt_polys * 16 * n / (ntt_ms / 1e3) / 1e9 if ntt_ms > 0 else 0.0, "mac_variant": mac_var,
-           "ks_variant": ks_var, "ks_tune_ms": ks_tune,
+           "ks_variant": ks_var, "ks_tune_ms": ks_tune, "ntt_radix": radix, "ntt_radix_tune_ms": radix_tune,
            "rotation_keys": len(steps_rot), "groups": info["groups"], "wo_geometry": g}
     B.blb_exec_destroy(ex1)
     B.blb_exec_destroy(ex2)
@@ -525,7 +530,8 @@ def run_qk_fused(args, B, torch):
         base += grp["n_out"]
     log(f"fused QK decoded max abs err {err:.3e}")
     mac_var = tune_mac(args, B, ctx, eager_step)
-    ks_var, ks_tune = tune_knob(args, B, torch, ctx, B.BLB_KNOB_KS_VARIANT, (0, 1), eager_step)
+    radix, radix_tune = tune_knob(args, B, torch, ctx, B.BLB_KNOB_NTT_RADIX, (16, 32), eager_step)
+    ks_var, ks_tune = tune_knob(args, B, torch, ctx, B.BLB_KNOB_KS_VARIANT, (0, 1, 2), eager_step)
     log(f"fused QK key inner-product variants (ms per op): {ks_tune} -> {ks_var}")
     eager_step(1)
     torch.cuda.synchronize()
@@ -562,7 +568,7 @@ def run_qk_fused(args, B, torch):
     res = {"value": steps / dt, "eager": steps / dt_eager, "ms": dt / steps * 1e3, "err": err, "split_ms": split,
            "ntt_gbps": ntt_polys * 16 * n / (ntt_ms / 1e3) / 1e9 if ntt_ms > 0 else 0.0,
            "mac_gbps": mac_bytes * mac_launches / (mac_ms / 1e3) / 1e9 if mac_ms > 0 else 0.0, "mac_variant": mac_var,
-           "ks_variant": ks_var, "ks_tune_ms": ks_tune,
+           "ks_variant": ks_var, "ks_tune_ms": ks_tune, "ntt_radix": radix, "ntt_radix_tune_ms": radix_tune,
            "rotation_keys": len(steps_rot), "wq_geometry": g, "groups": info["groups"]}
     for e in ex:
         B.blb_exec_destroy(e)
@@ -661,8 +667,9 @@ def run_ntt(args, B, torch):
         x = torch.randint(0, int(min(mods)), (n_polys * n_q * n,), dtype=torch.int64, device="cuda")
         x0 = x.clone()
         per_var = {}
-        for var in (0, 1):
+        for var, radix in ((0, 16), (1, 16), (0, 32), (1, 32)):
             B.blb_ctx_set_knob(ctx, B.BLB_KNOB_NTT_VARIANT, var)
+            B.blb_ctx_set_knob(ctx, B.BLB_KNOB_NTT_RADIX, radix)
             B.blb_ntt(ctx, x, n_polys, n_q, False)
             B.blb_ntt(ctx, x, n_polys, n_q, True)
             torch.cuda.synchronize()
@@ -681,11 +688,12 @@ def run_ntt(args, B, torch):
             lp_per_launch = polys / cnt
             gbps = lp_per_launch * 16 * n / t / 1e9
             bfly = lp_per_launch * (n // 2) * log_n / t
-            per_var[var] = dict(ms_per_launch=t * 1e3, GBps=gbps, frac_hbm=gbps / HBM_PEAK_GBPS, butterflies_per_s=bfly,
-                                frac_fp64_alu=bfly * NTT_OPS_PER_BUTTERFLY / FP64_LANE_OPS)
+            per_var[f"{var}/{radix}"] = dict(ms_per_launch=t * 1e3, GBps=gbps, frac_hbm=gbps / HBM_PEAK_GBPS, butterflies_per_s=bfly,
+                                             frac_fp64_alu=bfly * NTT_OPS_PER_BUTTERFLY / FP64_LANE_OPS)
         best = max(per_var, key=lambda v: per_var[v]["GBps"])
         out[f"N{n}"] = dict(per_var[best], variant=best, limb_polys_per_launch=n_polys * n_q,
-                            bytes_per_launch=n_polys * n_q * 16 * n, variants={str(k): v["GBps"] for k, v in per_var.items()})
+                            bytes_per_launch=n_polys * n_q * 16 * n, variants={k: v["GBps"] for k, v in per_var.items()},
+                            variant_key="launch variant / values per work-item")
         log(f"ntt N={n}: " + ", ".join(f"v{k} {v['GBps']:.0f} GB/s ({v['ms_per_launch']:.3f} ms)" for k, v in per_var.items()))
         del x, x0
         B.blb_ctx_destroy(ctx)
@@ -764,15 +772,18 @@ def run_batch(args, B, torch):
     B.blb_ctx_set_timing(ctx, True)
     for var in range(B.BLB_BATCH_VARIANTS):
         for grid in (1024, 4096):
-            B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_VARIANT, var)
-            B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_GRID, grid)
-            B.blb_ctx_reset_timing(ctx)
-            B.blb_batch_matmul_cp(ctx, arr)
-            tune[f"{var}/{grid}"] = B.blb_ctx_read_timing(ctx, B.BLB_T_CP_MAC)[0]
+            for limbs in (1, 0):
+                B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_VARIANT, var)
+                B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_GRID, grid)
+                B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_LIMBS, limbs)
+                B.blb_ctx_reset_timing(ctx)
+                B.blb_batch_matmul_cp(ctx, arr)
+                tune[f"{var}/{grid}/{limbs}"] = B.blb_ctx_read_timing(ctx, B.BLB_T_CP_MAC)[0]
     best = min(tune, key=tune.get)
-    var, grid = (int(x) for x in best.split("/"))
+    var, grid, limbs = (int(x) for x in best.split("/"))
     B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_VARIANT, var)
     B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_GRID, grid)
+    B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_LIMBS, limbs)
     B.blb_ctx_reset_timing(ctx)
     B.blb_ctx_set_timing(ctx, False)
     log(f"batched MAC variants (ms): {tune} -> {best}")
@@ -810,7 +821,7 @@ def run_batch(args, B, torch):
            "decoded_check": {"instance": k_max, "L": L_m, "D": D_m, "max_abs_err": dec_err, "tolerance": 2.0 ** -20},
            "unbatched_ms": t_unb * 1e3, "batched_ms": t_bat * 1e3, "graph_ms": t_graph * 1e3,
            "speedup_graph_vs_unbatched": t_unb / t_graph, "speedup_batched_vs_unbatched": t_unb / t_bat,
-           "modmul_per_s_graph": modmul / t_graph, "bit_identical": same, "autotune": {"best": best, "mac_ms": tune},
+           "modmul_per_s_graph": modmul / t_graph, "bit_identical": same, "autotune": {"best": best, "key": "MAC shape / persistent grid / limbs per work item (0 = all)", "mac_ms": tune},
            "executor_GB": B.blb_exec_device_bytes(ex) / 1e9}
     B.blb_exec_destroy(ex)
     for I in insts:
@@ -1154,7 +1165,7 @@ def main():
             "value": cc["value"], "eager_value": cc["eager"], "ms": cc["ms"], "max_abs_err": cc["err"],
             "ntt_GBps": cc["ntt_gbps"], "split_ms": cc["split_ms"], "rotation_keys": cc["rotation_keys"],
             "ops_per_product": cc["ops_per_product"],
-            "ntt_variant": cc["ntt_variant"], "ntt_tune_ms_per_op": cc["ntt_tune_ms"],
+            "ntt_variant": cc["ntt_variant"], "ntt_radix": cc["ntt_radix"], "ntt_tune_ms_per_op": cc["ntt_tune_ms"],
             "ks_variant": cc["ks_variant"], "ks_tune_ms_per_op": cc["ks_tune_ms"],
             "by_schedule": {("bsgs" if k else "plain"): {"value": v["value"], "eager_value": v["eager"], "ms": v["ms"],
                                                           "max_abs_err": v["err"], "ops_per_product": v["ops_per_product"],
@@ -1165,7 +1176,9 @@ def main():
             "metric": "attention-output ops/s (Softmax x V_h for 12 heads of 128 tokens, d_v 64, zero-padded and folded; "
                       "Concat(Att_h) W_O 768x768 on the diagonal packing; mask-to-share of 12 cts; N=16384, 5 primes + 2 special)",
             "value": ao["value"], "eager_value": ao["eager"], "ms": ao["ms"], "max_abs_err": ao["err"], "split_ms": ao["split_ms"],
-            "ntt_GBps": ao["ntt_gbps"], "ntt_frac_hbm_peak": ao["ntt_gbps"] / HBM_PEAK_GBPS, "rotation_keys": ao["rotation_keys"]},
+            "ntt_GBps": ao["ntt_gbps"], "ntt_frac_hbm_peak": ao["ntt_gbps"] / HBM_PEAK_GBPS, "rotation_keys": ao["rotation_keys"],
+            "autotune": {"ntt_radix": ao["ntt_radix"], "ntt_radix_ms": ao["ntt_radix_tune_ms"], "ks_variant": ao["ks_variant"],
+                         "ks_ms": ao["ks_tune_ms"]}},
         "qk_fused_from_x": None if qk is None else {
             "metric": "fused Q_h K_h^T-from-X ops/s (Enc(X 128x768) x W_Q, W_K 768x768 with columns reordered for the "
                       "multi-head packing; 12-head ct-ct product with step 1 on the server; mask-to-share; N=16384, "
@@ -1174,6 +1187,8 @@ def main():
             "ntt_GBps": qk["ntt_gbps"], "ntt_frac_hbm_peak": qk["ntt_gbps"] / HBM_PEAK_GBPS,
             "wq_wk_mac_GBps": qk["mac_gbps"], "wq_wk_mac_frac_hbm_peak": qk["mac_gbps"] / HBM_PEAK_GBPS,
             "mac_variant": qk["mac_variant"],
+            "autotune": {"ntt_radix": qk["ntt_radix"], "ntt_radix_ms": qk["ntt_radix_tune_ms"], "ks_variant": qk["ks_variant"],
+                         "ks_ms": qk["ks_tune_ms"]},
             "rotation_keys": qk["rotation_keys"]},
         "small_ops": None if so is None else dict(
             so, workload="24 ciphertexts of the BERT-base activation layout (128 x 768 spatial-first, N=8192, 3 primes): "

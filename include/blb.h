@@ -95,13 +95,17 @@ int blb_ctx_counters(blb_ctx* ctx, int64_t* out, int reset);
 
 /* ---- launch-shape knobs (never change a result bit; chosen by the autotuner) ------------ */
 enum { BLB_KNOB_MAC_VARIANT = 0, BLB_KNOB_BATCH_VARIANT = 1, BLB_KNOB_BATCH_GRID = 2, BLB_KNOB_NTT_VARIANT = 3, BLB_KNOB_KS_VARIANT = 4,
-       BLB_KNOB_KINDS = 5 };
+       BLB_KNOB_NTT_RADIX = 5, BLB_KNOB_BATCH_LIMBS = 6, BLB_KNOB_KINDS = 7 };
 /* value ranges: MAC variant 0..BLB_MAC_VARIANTS-1 (outputs per block x coefficients per thread x
  * input-loop unroll x full-tile split), batch variant 0..BLB_BATCH_VARIANTS-1 (outputs x instances x
- * coefficients per thread), batch grid 1..2^20 workgroups, NTT variant 0..1, key inner-product
- * variant 0..1 (0: one key-switch output per thread; 1: the outputs of a batch that share a key and
- * Galois element, up to 16 per thread, which reads each key word once for all of them; batches too
- * small to keep about 8192 workgroups busy that way keep one output per thread) */
+ * coefficients per thread), batch grid 1..2^20 workgroups, NTT variant 0..1 (one workgroup per
+ * limb-poly, or a persistent grid prefetching the next one), NTT radix 16 or 32 (values per
+ * work-item: passes of 4 or 5 radix-2 stages, N/16 or N/32 work-items per limb-poly), batched-MAC
+ * limb grouping 0..12 (RNS limbs per work item of the instance-batched MAC; 0 = all limbs), key
+ * inner-product variant 0..2 (0: one key-switch output per thread; 1: the outputs of a batch that
+ * share a key and Galois element, up to 16 per thread, which reads each key word once for all of
+ * them, where the launch keeps about 8192 workgroups busy that way (else one output per thread);
+ * 2: always grouped) */
 enum { BLB_MAC_VARIANTS = 14, BLB_BATCH_VARIANTS = 7 };
 int blb_ctx_set_knob(blb_ctx* ctx, int knob, int value);
 int blb_ctx_get_knob(const blb_ctx* ctx, int knob);

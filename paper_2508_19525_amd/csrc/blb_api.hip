@@ -125,7 +125,9 @@ void stack_release(blb_ctx* c, Workspace* w) {
 void stack_fit(blb_ctx* c, Workspace* w) {
   if (w->need <= w->cap || w->frozen) return;
   const size_t quantum = size_t(64) << 20;
-  const size_t cap = (std::max(w->need + w->need / 4, 2 * w->cap) + quantum - 1) / quantum * quantum;
+  // a quarter of headroom over the deepest need seen (doubling would hold tens of GB idle once
+  // batches of large operators have run)
+  const size_t cap = (w->need + w->need / 4 + quantum - 1) / quantum * quantum;
   (void)hipStreamSynchronize(w->stream);
   stack_release(c, w);
   bool ok = !c->budget || c->dev_bytes + cap <= c->budget;
@@ -538,8 +540,8 @@ int ks_apply(blb_ctx* c, int level, const std::vector<const uint64_t*>& srcs, co
   // group size: large enough to reuse the key words, small enough to keep about 8192 workgroups
   // in the launch (a small batch keeps one output per thread)
   const int64_t blocks = (int64_t)O * n_ext * ((n / 2 + 255) / 256);
-  const int cap = (int)std::min<int64_t>(kKsGroupMax, std::max<int64_t>(1, blocks / 8192));
-  if (c->ks_variant == 1 && nd <= kKsMaxDigits && cap > 1) {
+  const int cap = c->ks_variant == 2 ? kKsGroupMax : (int)std::min<int64_t>(kKsGroupMax, std::max<int64_t>(1, blocks / 8192));
+  if (c->ks_variant >= 1 && nd <= kKsMaxDigits && cap > 1) {
     // outputs grouped by (key, Galois element), stable, in runs of at most `cap`
     std::vector<int> ord(O);
     for (int o = 0; o < O; ++o) ord[o] = o;
@@ -873,6 +875,7 @@ int blb_ctx_trim(blb_ctx* c) {
     if (w->off == 0 && hipStreamSynchronize(w->stream) == hipSuccess) {  // idle: give the bytes back
       stack_release(c, w);
       w->need = 0;
+      w->frozen = false;  // it may grow again once memory is free
     }
   hipMemPool_t pool;
   if (hipDeviceGetDefaultMemPool(&pool, c->device) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
@@ -899,8 +902,16 @@ int blb_ctx_set_knob(blb_ctx* c, int knob, int value) {
       c->ntt_variant = value;
       return BLB_OK;
     case BLB_KNOB_KS_VARIANT:
-      if (value < 0 || value > 1) return BLB_EINVAL;
+      if (value < 0 || value > 2) return BLB_EINVAL;
       c->ks_variant = value;
+      return BLB_OK;
+    case BLB_KNOB_NTT_RADIX:
+      if (value != 16 && value != 32) return BLB_EINVAL;
+      c->ntt_radix = value;
+      return BLB_OK;
+    case BLB_KNOB_BATCH_LIMBS:
+      if (value < 0 || value > BLB_MAXQ) return BLB_EINVAL;
+      c->batch_limbs = value;
       return BLB_OK;
     default: return BLB_EINVAL;
   }
@@ -913,6 +924,8 @@ int blb_ctx_get_knob(const blb_ctx* c, int knob) {
     case BLB_KNOB_BATCH_GRID: return c->batch_grid;
     case BLB_KNOB_NTT_VARIANT: return c->ntt_variant;
     case BLB_KNOB_KS_VARIANT: return c->ks_variant;
+    case BLB_KNOB_NTT_RADIX: return c->ntt_radix;
+    case BLB_KNOB_BATCH_LIMBS: return c->batch_limbs;
     default: return BLB_EINVAL;
   }
 }
@@ -2948,10 +2961,11 @@ int blb_batch_matmul_cp(blb_ctx* c, const blb_cp_instance* inst, int n_inst) {
       c->counters[2] += (int64_t)n_ai * n_bj * mg.n_inst;
       c->counters[7] += (int64_t)n_ai * n_bj * nl * n * 8 * ((mg.n_inst + ib - 1) / ib);
       const int n_kb = n / (256 * cpt);
+      const int lg = c->batch_limbs > 0 ? std::min(c->batch_limbs, nl) : nl;  // limbs per work item
       for (int i0 = 0; i0 < mg.n_inst; i0 += ib)
-        for (int limb = 0; limb < nl; ++limb)
+        for (int limb = 0; limb < nl; limb += lg)
           for (int kb = 0; kb < n_kb; ++kb)
-            for (int t = 0; t * tb < n_bj; ++t) items.push_back(MacItem{(int)gi, i0, t, kb, limb});
+            for (int t = 0; t * tb < n_bj; ++t) items.push_back(MacItem{(int)gi, i0, t, kb, limb, std::min(lg, nl - limb)});
     }
     const MacGroup* g_dev = upload_vec(c, groups);
     const MacItem* it_dev = upload_vec(c, items);

@@ -117,7 +117,7 @@ struct MacGroup {
   int n_ai, n_bj, nl, n_inst;
 };
 struct MacItem {
-  int group, inst0, tile, kb, limb;
+  int group, inst0, tile, kb, limb, n_limb;  // limbs limb .. limb + n_limb - 1 (limb grouping)
 };
 
 struct CpGeom {
@@ -232,8 +232,11 @@ struct blb_ctx {
   int mac_variant = 0;            // k_cp_mac tile shape (autotuned; never changes results)
   int batch_variant = 0;          // k_cp_mac_batch shape (autotuned)
   int batch_grid = 2048;          // persistent grid size of k_cp_mac_batch (autotuned)
+  int batch_limbs = 1;            // limbs per work item of k_cp_mac_batch, 0 = all (autotuned)
   int ntt_variant = 1;            // 0: one workgroup per poly, 1: persistent pipelined (autotuned)
-  int ks_variant = 1;             // key inner product: 0 per output, 1 grouped by key (autotuned)
+  int ntt_radix = 16;             // values per work-item: 16 (4-stage passes) or 32 (5-stage passes) (autotuned)
+  int ks_variant = 1;             // key inner product: 0 per output, 1 grouped by key where the launch
+                                  // stays wide, 2 always grouped (autotuned)
   int n_cu = 256;                 // compute units of the device
   int64_t counters[8] = {};       // operation counters (see blb_ctx_counters)
 };

@@ -931,7 +931,8 @@ __global__ __launch_bounds__(256) void k_cp_mac_batch(const MacGroup* __restrict
     const MacGroup gr = groups[item.group];
     const int k0 = (item.kb * 256 + threadIdx.x) * CPT;
     if (k0 >= n) continue;
-    const int limb = item.limb, nl = gr.nl, n_ai = gr.n_ai, n_bj = gr.n_bj;
+    for (int limb = item.limb; limb < item.limb + item.n_limb; ++limb) {
+    const int nl = gr.nl, n_ai = gr.n_ai, n_bj = gr.n_bj;
     const ModEntry me = mt.m[limb];
     const double q = me.q, qi = me.qinv;
     const int bj0 = item.tile * TB;
@@ -1013,6 +1014,7 @@ __global__ __launch_bounds__(256) void k_cp_mac_batch(const MacGroup* __restrict
         }
       }
     }
+    }  // limbs of the item
   }
 }
 

@@ -2,9 +2,9 @@
 //
 // One workgroup transforms one N-word polynomial (N = 4096 / 8192 / 16384), exchanging
 // values through LDS (N doubles + 1/16 padding, 136 KiB at N = 16384 against 160 KiB per
-// CU).  Each of the N/16 work-items keeps 16 values in registers and runs up to four radix-2
-// stages on them per pass; the first pass reads global memory and the last writes it, so a
-// transform costs ceil(log2 N / 4) - 1 LDS round trips.  The forward transform is the
+// CU).  Each of the N/PT work-items keeps PT = 16 (or 32) values in registers and runs up to
+// four (five) radix-2 stages on them per pass; the first pass reads global memory and the last
+// writes it, so a transform costs (passes - 1) LDS round trips.  The forward transform is the
 // Cooley-Tukey ordering with twiddles psi^brv(m+i) (natural in, bit-reversed out, value j is
 // the evaluation at psi^(2 brv(j) + 1)); the inverse is the Gentleman-Sande ordering with
 // psi^-brv(m+i) followed by N^-1.  Polys are addressed through a descriptor table so a
@@ -16,7 +16,11 @@
 
 namespace {
 
-constexpr int kPerThread = 16;
+// Values per work-item (the radix of a pass: log2 of it is the number of radix-2 stages a pass
+// runs in registers).  16 (passes of 4 stages, N/16 work-items) or 32 (passes of 5 stages, N/32
+// work-items, one LDS round trip fewer); chosen per context by the autotuner, never changing a
+// result.
+constexpr int kPT16 = 16, kPT32 = 32;
 
 // Where a launch finds its polynomials: a descriptor table, or (descs == null) a regular
 // batch of `count` limb-polys stored back to back at `base`, transformed in place, poly p
@@ -60,17 +64,17 @@ struct NttSrc {
 __host__ __device__ constexpr int pad_idx(int j) { return j + (j >> 4); }
 
 // One pass of R_LOG radix-2 stages starting at global stage S0.  Work-item `tid` holds
-// kPerThread values in registers: GPT groups of GS = 2^R_LOG values each, group h being the
-// butterfly group g = tid + h T (T = N / kPerThread) whose members sit TL = N >> (S0 + R_LOG)
+// PT values in registers: GPT groups of GS = 2^R_LOG values each, group h being the
+// butterfly group g = tid + h T (T = N / PT) whose members sit TL = N >> (S0 + R_LOG)
 // words apart.
-template <int LOGN, int S0, int R_LOG>
+template <int LOGN, int PT, int S0, int R_LOG>
 struct Pass {
   static constexpr int N = 1 << LOGN;
-  static constexpr int T = N / kPerThread;
+  static constexpr int T = N / PT;
   static constexpr int GS = 1 << R_LOG;
-  static constexpr int GPT = kPerThread / GS;
+  static constexpr int GPT = PT / GS;
   static constexpr int TL = N >> (S0 + R_LOG);
-  static_assert(S0 + R_LOG <= LOGN && GS <= kPerThread, "pass shape");
+  static_assert(S0 + R_LOG <= LOGN && GS <= PT, "pass shape");
   // twiddles differ across the lanes of a wave (vector loads) unless the pass spans whole
   // columns (TL >= T) or a butterfly tree covers at least 64 work-items (TL >= 64)
   static constexpr bool LANE_TW = !(TL >= T || TL >= 64);
@@ -89,7 +93,7 @@ struct Pass {
 
   // FWD: Cooley-Tukey stages in increasing order; else Gentleman-Sande in decreasing order.
   template <bool FWD>
-  __device__ static __forceinline__ void run(double (&x)[kPerThread], const double* __restrict__ tw, double q, double qi, int tid) {
+  __device__ static __forceinline__ void run(double (&x)[PT], const double* __restrict__ tw, double q, double qi, int tid) {
 #pragma unroll
     for (int uu = 0; uu < R_LOG; ++uu) {
       const int u = FWD ? uu : (R_LOG - 1 - uu);
@@ -112,10 +116,11 @@ struct Pass {
           // < q/2 + 0.375 B (the quotient estimate is off by < B 2^-52, the dropped low part
           // of b w is < B q 2^-53), so in the forward (Cooley-Tukey) butterfly the bound grows
           // as B' = 1.375 B + q/2: from |x| <= q at the start of a pass, four stages stay below
-          // 7.01 q < 2^53, where every FP64 sum and product step is exact; values are reduced
-          // at the end of the pass only.  In the inverse (Gentleman-Sande) butterfly a + b can
-          // double, so it reduces after every second stage and at the end of the pass.
-          const bool red = FWD ? (u == R_LOG - 1) : ((u & 1) || (u == R_LOG - 1));
+          // 7.01 q < 2^53, where every FP64 sum and product step is exact (a fifth would reach
+          // 10.1 q > 2^53); values are reduced after the fourth stage and at the end of the
+          // pass.  In the inverse (Gentleman-Sande) butterfly a + b can double, so it reduces
+          // after every second stage and at the end of the pass.
+          const bool red = FWD ? (u == R_LOG - 1 || u == 3) : ((u & 1) || (u == R_LOG - 1));
           if (FWD) {
             const double v = mulmod_s(b, w, q, qi);
             const double sum = a + v, dif = a - v;
@@ -145,22 +150,22 @@ __device__ __forceinline__ void lds_barrier() {
 // Move the register values from the layout of pass PA to the layout of pass PB through LDS.
 // The leading barrier keeps the writes behind every read of the previous exchange (also of
 // the previous polynomial in the persistent kernel).
-template <class PA, class PB>
-__device__ __forceinline__ void relayout(double* lds, double (&x)[kPerThread], int tid) {
+template <class PA, class PB, int PT>
+__device__ __forceinline__ void relayout(double* lds, double (&x)[PT], int tid) {
   double* la = lds + pad_idx(PA::idx(tid, 0));
   const double* lb = lds + pad_idx(PB::idx(tid, 0));
   lds_barrier();
 #pragma unroll
-  for (int i = 0; i < kPerThread; ++i) la[PA::lds_off(i)] = x[i];
+  for (int i = 0; i < PT; ++i) la[PA::lds_off(i)] = x[i];
   lds_barrier();
 #pragma unroll
-  for (int i = 0; i < kPerThread; ++i) x[i] = lb[PB::lds_off(i)];
+  for (int i = 0; i < PT; ++i) x[i] = lb[PB::lds_off(i)];
 }
 
 // lds_off(i) is the same for every work-item of pass P
 template <class P>
 constexpr bool lds_affine() {
-  for (int i = 1; i < kPerThread; ++i) {
+  for (int i = 1; i < P::GS * P::GPT; ++i) {
     const int off = P::lds_off(i);
     for (int tid = 1; tid < P::T; ++tid)
       if (pad_idx(P::idx(tid, i)) - pad_idx(P::idx(tid, 0)) != off) return false;
@@ -168,36 +173,41 @@ constexpr bool lds_affine() {
   return true;
 }
 
-// Pass schedule: three passes of four stages, then the remaining LOGN - 12 stages (forward
-// order).  The first pass reads its operands straight from global memory and the last pass
-// writes straight to global memory, so a transform makes (passes - 1) LDS round trips.
-template <int LOGN>
+// Pass schedule (forward order).  PT = 16: three passes of four stages, then the remaining
+// LOGN - 12 stages; PT = 32: two passes of five stages, then the remaining LOGN - 10.  The first
+// pass reads its operands straight from global memory and the last pass writes straight to
+// global memory, so a transform makes (passes - 1) LDS round trips.
+template <int LOGN, int PT>
 struct Sched {
-  static constexpr int REM = LOGN - 12;
-  using P0 = Pass<LOGN, 0, 4>;
-  using P1 = Pass<LOGN, 4, 4>;
-  using P2 = Pass<LOGN, 8, 4>;
-  using P3 = Pass<LOGN, 12, (REM > 0 ? REM : 1)>;
-  using Tail = std::conditional_t<(REM > 0), P3, P2>;  // forward-last / inverse-first pass
+  static constexpr int R = PT == 32 ? 5 : 4;
+  static constexpr int REM = LOGN - 3 * R;  // stages of a fourth pass (PT = 16 only)
+  static_assert(PT == 16 || PT == 32, "values per work-item");
+  static_assert(PT == 16 || LOGN - 2 * R >= 1, "third pass");
+  using P0 = Pass<LOGN, PT, 0, R>;
+  using P1 = Pass<LOGN, PT, R, R>;
+  using P2 = Pass<LOGN, PT, 2 * R, (PT == 32 ? LOGN - 2 * R : R)>;
+  using P3 = Pass<LOGN, PT, 3 * R, (PT == 16 && REM > 0 ? REM : 1)>;
+  static constexpr bool HAS3 = PT == 16 && REM > 0;
+  using Tail = std::conditional_t<HAS3, P3, P2>;  // forward-last / inverse-first pass
   static_assert(lds_affine<P0>(), "LDS offsets of the first pass depend on the work-item");
   static_assert(lds_affine<P1>(), "LDS offsets of the second pass depend on the work-item");
   static_assert(lds_affine<P2>(), "LDS offsets of the third pass depend on the work-item");
   static_assert(lds_affine<Tail>(), "LDS offsets of the last pass depend on the work-item");
-  static constexpr int NP = REM > 0 ? 4 : 3;  // passes
+  static constexpr int NP = HAS3 ? 4 : 3;  // passes
   // passes (in execution order) that run before the persistent kernel's prefetch is issued:
   // the leading run of passes with per-lane twiddles
   template <bool FWD>
   static constexpr int issue_after() {
-    const bool lane[4] = {P0::LANE_TW, P1::LANE_TW, P2::LANE_TW, REM > 0 ? Tail::LANE_TW : false};
+    const bool lane[4] = {P0::LANE_TW, P1::LANE_TW, P2::LANE_TW, HAS3 ? Tail::LANE_TW : false};
     int k = 0;
     while (k < NP && lane[FWD ? k : NP - 1 - k]) ++k;
     return k;
   }
 };
-template <int LOGN, bool FWD>
-using FirstPass = std::conditional_t<FWD, typename Sched<LOGN>::P0, typename Sched<LOGN>::Tail>;
-template <int LOGN, bool FWD>
-using LastPass = std::conditional_t<FWD, typename Sched<LOGN>::Tail, typename Sched<LOGN>::P0>;
+template <int LOGN, int PT, bool FWD>
+using FirstPass = std::conditional_t<FWD, typename Sched<LOGN, PT>::P0, typename Sched<LOGN, PT>::Tail>;
+template <int LOGN, int PT, bool FWD>
+using LastPass = std::conditional_t<FWD, typename Sched<LOGN, PT>::Tail, typename Sched<LOGN, PT>::P0>;
 
 struct NoIssue {
   __device__ void operator()() const {}
@@ -208,10 +218,10 @@ struct NoIssue {
 // issue order, so a per-lane twiddle load issued after the prefetch is waited for only once
 // the whole prefetch has arrived: issue() runs after the leading passes that load per-lane
 // twiddles (before the first pass when it has none).
-template <int LOGN, bool FWD, class Issue = NoIssue>
-__device__ __forceinline__ void ntt_core(double* lds, double (&x)[kPerThread], const double* tw, double q, double qi, int tid,
+template <int LOGN, int PT, bool FWD, class Issue = NoIssue>
+__device__ __forceinline__ void ntt_core(double* lds, double (&x)[PT], const double* tw, double q, double qi, int tid,
                                          const Issue& issue = Issue()) {
-  using S = Sched<LOGN>;
+  using S = Sched<LOGN, PT>;
   using P0 = typename S::P0;
   using P1 = typename S::P1;
   using P2 = typename S::P2;
@@ -227,7 +237,7 @@ __device__ __forceinline__ void ntt_core(double* lds, double (&x)[kPerThread], c
     relayout<P1, P2>(lds, x, tid);
     P2::template run<true>(x, tw, q, qi, tid);
     if constexpr (at == 3) issue();
-    if constexpr (S::REM > 0) {
+    if constexpr (S::HAS3) {
       relayout<P2, P3>(lds, x, tid);
       P3::template run<true>(x, tw, q, qi, tid);
       if constexpr (at == 4) issue();
@@ -235,7 +245,7 @@ __device__ __forceinline__ void ntt_core(double* lds, double (&x)[kPerThread], c
   } else {
     // pass k of the inverse runs Pass index NP - 1 - k
     if constexpr (at == 0) issue();
-    if constexpr (S::REM > 0) {
+    if constexpr (S::HAS3) {
       P3::template run<false>(x, tw, q, qi, tid);
       if constexpr (at == 1) issue();
       relayout<P3, P2>(lds, x, tid);
@@ -251,57 +261,62 @@ __device__ __forceinline__ void ntt_core(double* lds, double (&x)[kPerThread], c
   }
 }
 
-template <int LOGN, bool FWD, class LoadOp>
-__device__ __forceinline__ void ntt_load(double (&x)[kPerThread], const PolyDesc& d, const LoadOp& ld, double q, double qi, int tid) {
+template <int LOGN, int PT, bool FWD, class LoadOp>
+__device__ __forceinline__ void ntt_load(double (&x)[PT], const PolyDesc& d, const LoadOp& ld, double q, double qi, int tid) {
 #pragma unroll
-  for (int i = 0; i < kPerThread; ++i) x[i] = ld(d, FirstPass<LOGN, FWD>::idx(tid, i), q, qi);
+  for (int i = 0; i < PT; ++i) x[i] = ld(d, FirstPass<LOGN, PT, FWD>::idx(tid, i), q, qi);
 }
 
 // canonical results of the last pass to global memory (the inverse applies N^-1 here; the
 // lazy passes leave |x| below ~2.5 q, which canon_full brings into [0, q))
-template <int LOGN, bool FWD, class StoreOp>
-__device__ __forceinline__ void ntt_store(double (&x)[kPerThread], const PolyDesc& d, const StoreOp& st, double q, double qi, double ninv, int tid,
+template <int LOGN, int PT, bool FWD, class StoreOp>
+__device__ __forceinline__ void ntt_store(double (&x)[PT], const PolyDesc& d, const StoreOp& st, double q, double qi, double ninv, int tid,
                                           double* lds) {
-  st.prepare(d, lds, tid);  // the epilogue may stage an operand in LDS (free after the last pass)
+  st.template prepare<PT>(d, lds, tid);  // the epilogue may stage an operand in LDS (free after the last pass)
   // Every operand load of the epilogue is issued before the first store: vector-memory
   // completion is tracked in issue order, so a load issued after a store could only be
   // consumed once that store had completed.
-  typename StoreOp::Operand e[kPerThread];
+  typename StoreOp::Operand e[PT];
 #pragma unroll
-  for (int i = 0; i < kPerThread; ++i) e[i] = st.fetch(d, LastPass<LOGN, FWD>::idx(tid, i));
+  for (int i = 0; i < PT; ++i) e[i] = st.fetch(d, LastPass<LOGN, PT, FWD>::idx(tid, i));
 #pragma unroll
-  for (int i = 0; i < kPerThread; ++i) {
-    const int j = LastPass<LOGN, FWD>::idx(tid, i);
+  for (int i = 0; i < PT; ++i) {
+    const int j = LastPass<LOGN, PT, FWD>::idx(tid, i);
     const double v = FWD ? canon(x[i], q) : canon_full(mulmod_s(x[i], ninv, q, qi), q, qi);
     st.put(d, j, v, e[i], q, qi, lds);
   }
 }
 
+// waves per SIMD the launch bounds promise: 4 (PT 16: 16 waves per workgroup at N = 16384, up
+// to 128 VGPRs each) or 2 (PT 32: up to 256 VGPRs, room for 32 values and their prefetch)
+template <int PT>
+constexpr int waves_per_eu() { return PT == 32 ? 2 : 4; }
+
 // One workgroup per polynomial.
-template <int LOGN, bool FWD, class LoadOp, class StoreOp>
-__global__ __launch_bounds__((1 << LOGN) / kPerThread) __attribute__((amdgpu_waves_per_eu(4))) void k_ntt(NttSrc descs, const double* __restrict__ tw_all,
-                                                                ModTable mt, LoadOp ld, StoreOp st) {
+template <int LOGN, int PT, bool FWD, class LoadOp, class StoreOp>
+__global__ __launch_bounds__((1 << LOGN) / PT) __attribute__((amdgpu_waves_per_eu(waves_per_eu<PT>()))) void k_ntt(
+    NttSrc descs, const double* __restrict__ tw_all, ModTable mt, LoadOp ld, StoreOp st) {
   constexpr int N = 1 << LOGN;
   __shared__ double lds[N + N / 16];
   const PolyDesc d = descs.get(blockIdx.x);
   const double q = mt.m[d.mod].q, qi = mt.m[d.mod].qinv;
   const int tid = threadIdx.x;
-  double x[kPerThread];
-  ntt_load<LOGN, FWD>(x, d, ld, q, qi, tid);
-  ntt_core<LOGN, FWD>(lds, x, tw_all + (size_t)d.mod * N, q, qi, tid);
-  ntt_store<LOGN, FWD>(x, d, st, q, qi, mt.m[d.mod].ninv, tid, lds);
+  double x[PT];
+  ntt_load<LOGN, PT, FWD>(x, d, ld, q, qi, tid);
+  ntt_core<LOGN, PT, FWD>(lds, x, tw_all + (size_t)d.mod * N, q, qi, tid);
+  ntt_store<LOGN, PT, FWD>(x, d, st, q, qi, mt.m[d.mod].ninv, tid, lds);
 }
 
 // Persistent, software-pipelined variant: a grid of resident workgroups walks the descriptor
 // list with a grid stride; the next polynomial's operands are loaded into registers while the
 // current one is transformed, hiding the global-memory latency that a one-shot workgroup (one
 // per CU at N = 16384) exposes.
-template <int LOGN, bool FWD, class LoadOp, class StoreOp>
-__global__ __launch_bounds__((1 << LOGN) / kPerThread) __attribute__((amdgpu_waves_per_eu(4))) void k_ntt_pipe(NttSrc descs, const double* __restrict__ tw_all,
-                                                                     ModTable mt, LoadOp ld, StoreOp st, int count) {
+template <int LOGN, int PT, bool FWD, class LoadOp, class StoreOp>
+__global__ __launch_bounds__((1 << LOGN) / PT) __attribute__((amdgpu_waves_per_eu(waves_per_eu<PT>()))) void k_ntt_pipe(
+    NttSrc descs, const double* __restrict__ tw_all, ModTable mt, LoadOp ld, StoreOp st, int count) {
   constexpr int N = 1 << LOGN;
-  constexpr int PF = kPerThread;
-  using First = FirstPass<LOGN, FWD>;
+  constexpr int PF = PT;
+  using First = FirstPass<LOGN, PT, FWD>;
   __shared__ double lds[N + N / 16];
   const int tid0 = threadIdx.x;
   int p = blockIdx.x;
@@ -327,7 +342,7 @@ __global__ __launch_bounds__((1 << LOGN) / kPerThread) __attribute__((amdgpu_wav
     asm volatile("" : "+v"(tid));
     const PolyDesc d = descs.get(p);
     const double q = mt.m[d.mod].q, qi = mt.m[d.mod].qinv;
-    double x[kPerThread];
+    double x[PT];
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
       uint64_t u = nx[i];
@@ -335,7 +350,7 @@ __global__ __launch_bounds__((1 << LOGN) / kPerThread) __attribute__((amdgpu_wav
       x[i] = ld.cvt(d, u, q, qi);
     }
 #pragma unroll
-    for (int i = PF; i < kPerThread; ++i) x[i] = ld(d, First::idx(tid, i), q, qi);
+    for (int i = PF; i < PT; ++i) x[i] = ld(d, First::idx(tid, i), q, qi);
     const int pn = p + gridDim.x;
     auto prefetch = [&] {
       // unconditional (the last iteration re-reads its own polynomial), so the loads land in nx
@@ -344,38 +359,43 @@ __global__ __launch_bounds__((1 << LOGN) / kPerThread) __attribute__((amdgpu_wav
 #pragma unroll
       for (int i = 0; i < PF; ++i) nx[i] = ld.raw(dn, First::idx(tid, i));
     };
-    ntt_core<LOGN, FWD>(lds, x, tw_all + (size_t)d.mod * N, q, qi, tid, prefetch);
-    ntt_store<LOGN, FWD>(x, d, st, q, qi, mt.m[d.mod].ninv, tid, lds);
+    ntt_core<LOGN, PT, FWD>(lds, x, tw_all + (size_t)d.mod * N, q, qi, tid, prefetch);
+    ntt_store<LOGN, PT, FWD>(x, d, st, q, qi, mt.m[d.mod].ninv, tid, lds);
     p = pn;
     if (p >= count) break;
   }
 }
 
-template <bool FWD, class LoadOp, class StoreOp>
-void launch_ntt_generic(blb_ctx* c, NttSrc d_descs, int count, LoadOp ld, StoreOp st) {
-  if (count <= 0) return;
+template <int PT, bool FWD, class LoadOp, class StoreOp>
+void launch_ntt_pt(blb_ctx* c, NttSrc d_descs, int count, LoadOp ld, StoreOp st) {
   const double* tw = FWD ? c->d_tw_fwd : c->d_tw_inv;
-  const int threads = c->n / kPerThread;
+  const int threads = c->n / PT;
   if constexpr (StoreOp::kPersistent) {
     if (c->ntt_variant == 1) {
       // resident workgroups: LDS per workgroup is 8.5 N bytes of 160 KiB per CU
       const int per_cu = std::max(1, (160 * 1024) / (int)((c->n + c->n / 16) * sizeof(double)));
       const int grid = std::min(count, c->n_cu * per_cu);
       switch (c->log_n) {
-        case 12: k_ntt_pipe<12, FWD><<<grid, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st, count); break;
-        case 13: k_ntt_pipe<13, FWD><<<grid, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st, count); break;
-        case 14: k_ntt_pipe<14, FWD><<<grid, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st, count); break;
+        case 12: k_ntt_pipe<12, PT, FWD><<<grid, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st, count); break;
+        case 13: k_ntt_pipe<13, PT, FWD><<<grid, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st, count); break;
+        case 14: k_ntt_pipe<14, PT, FWD><<<grid, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st, count); break;
         default: break;
       }
       return;
     }
   }
   switch (c->log_n) {
-    case 12: k_ntt<12, FWD><<<count, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st); break;
-    case 13: k_ntt<13, FWD><<<count, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st); break;
-    case 14: k_ntt<14, FWD><<<count, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st); break;
+    case 12: k_ntt<12, PT, FWD><<<count, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st); break;
+    case 13: k_ntt<13, PT, FWD><<<count, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st); break;
+    case 14: k_ntt<14, PT, FWD><<<count, threads, 0, c->stream>>>(d_descs, tw, c->mt, ld, st); break;
     default: break;
   }
+}
+template <bool FWD, class LoadOp, class StoreOp>
+void launch_ntt_generic(blb_ctx* c, NttSrc d_descs, int count, LoadOp ld, StoreOp st) {
+  if (count <= 0) return;
+  if (c->ntt_radix == 32) launch_ntt_pt<kPT32, FWD>(c, d_descs, count, ld, st);
+  else launch_ntt_pt<kPT16, FWD>(c, d_descs, count, ld, st);
 }
 
 }  // namespace
@@ -403,6 +423,7 @@ struct LdPlain {
 struct StPlain {
   static constexpr bool kPersistent = true;
   struct Operand {};
+  template <int PT>
   __device__ void prepare(const PolyDesc&, double*, int) const {}
   __device__ Operand fetch(const PolyDesc&, int) const { return {}; }
   __device__ void put(const PolyDesc& d, int j, double v, Operand, double, double, const double*) const { gst(d.dst, j, d2u(v)); }
@@ -423,6 +444,7 @@ struct LdCentredLift {
 struct StRescale {
   static constexpr bool kPersistent = true;
   using Operand = uint64_t;
+  template <int PT>
   __device__ void prepare(const PolyDesc&, double*, int) const {}
   __device__ Operand fetch(const PolyDesc& d, int j) const { return gld(d.src2, j); }
   __device__ void put(const PolyDesc& d, int j, double v, Operand ci, double q, double qi, const double*) const {
@@ -437,12 +459,13 @@ struct StRescale {
 struct StModDown {
   static constexpr bool kPersistent = false;
   using Operand = uint64_t;
+  template <int PT>
   __device__ void prepare(const PolyDesc& d, double* lds, int tid) const {
     if (!d.src3) return;  // uniform over the workgroup (one descriptor)
-    const int T = (1 << d.log_n) / kPerThread;
+    const int T = (1 << d.log_n) / PT;
     lds_barrier();
 #pragma unroll
-    for (int i = 0; i < kPerThread; ++i) {
+    for (int i = 0; i < PT; ++i) {
       const int j = tid + i * T;
       lds[pad_idx(j)] = u2d(gld(d.src3, j));
     }
@@ -463,6 +486,7 @@ struct StModDown {
 struct StAddTo {
   static constexpr bool kPersistent = true;
   using Operand = uint64_t;
+  template <int PT>
   __device__ void prepare(const PolyDesc&, double*, int) const {}
   __device__ Operand fetch(const PolyDesc& d, int j) const { return gld(d.src2, j); }
   __device__ void put(const PolyDesc& d, int j, double v, Operand a, double q, double, const double*) const {

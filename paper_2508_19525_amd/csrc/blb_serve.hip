@@ -398,7 +398,19 @@ void worker_loop(blb_server* S) {
       inst.push_back(I);
       r->state = 1;
     }
-    const int rc = blb_batch_matmul_cp(c, inst.data(), (int)inst.size());
+    int rc = blb_batch_matmul_cp(c, inst.data(), (int)inst.size());
+    if (rc == BLB_ENOMEM) {
+      // the batch's temporaries did not fit beside the batches in flight (the call fails before it
+      // writes any output): let those finish, give back idle memory and try again, then one
+      // request at a time
+      finish_batches(S, true);
+      (void)blb_ctx_trim(c);
+      rc = blb_batch_matmul_cp(c, inst.data(), (int)inst.size());
+      if (rc == BLB_ENOMEM && inst.size() > 1) {
+        rc = BLB_OK;
+        for (size_t q = 0; q < inst.size() && rc == BLB_OK; ++q) rc = blb_batch_matmul_cp(c, &inst[q], 1);
+      }
+    }
     // mask-and-share per request: a failure marks that request only
     std::vector<int> mrc(batch.size(), BLB_OK);
     for (size_t k = 0; k < batch.size() && rc == BLB_OK; ++k)

@@ -99,17 +99,20 @@ def test_batched_equals_per_instance(env):
             vecs.append(B.blb_decode(ctx, dec, 1, I["Y2"][b].scale, 4096))
         got = wl.unpack_spatial(vecs, I["L"], I["D"], 4096)
         assert np.abs(got - I["Xm"] @ Ws[I["D"]]).max() < 2.0 ** -20
-    # knobs never change bits
+    # knobs never change bits: MAC shape, persistent grid, limbs per work item
     for var in range(B.BLB_BATCH_VARIANTS):
         B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_VARIANT, var)
         B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_GRID, [7, 256, 2048, 100000, 13, 1024, 300][var])
+        B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_LIMBS, [1, 2, 0, 3, 1, 0, 2][var])
         B.blb_batch_matmul_cp(ctx, arr)
         torch.cuda.synchronize()
         for k, I in enumerate(inst):
-            got = B.blb_export(ctx, B.blb_ct.from_address(arr[k].Y), 8192)
-            assert np.array_equal(got, B.blb_export(ctx, I["Y2"][0], 8192)), f"variant {var} instance {k}"
+            for b in (0, len(I["Y"]) - 1):
+                got = B.blb_export(ctx, B.blb_ct.from_address(arr[k].Y + b * B.C.sizeof(B.blb_ct)), 8192)
+                assert np.array_equal(got, B.blb_export(ctx, I["Y2"][b], 8192)), f"variant {var} instance {k} output {b}"
     B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_VARIANT, 0)
     B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_GRID, 2048)
+    B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_LIMBS, 1)
     # the executor: one graph launch for the batch, every replay equal to the eager words
     share = torch.zeros(sum(len(I["Y"]) for I in inst) * 2 * 8192, dtype=torch.int64, device="cuda")
     ex = B.blb_exec_create_batch_cp(ctx, arr, 1, share)

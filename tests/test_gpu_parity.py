@@ -486,38 +486,45 @@ def test_exec_cc_replays_match_eager(c3s, schedule):
 # launch-shape knobs never change a bit
 # --------------------------------------------------------------------------------------
 def test_ntt_variants_bit_identical(c3s):
-    """The persistent pipelined NTT (knob 1) and the one-workgroup-per-poly NTT (knob 0) give
-    identical words through a full matmul_cc (rotations, rescales and ModDowns at three levels)."""
+    """Every NTT launch shape -- one workgroup per poly or the persistent pipelined grid (knob
+    NTT_VARIANT), 16 or 32 values per work-item (knob NTT_RADIX) -- gives identical words through a
+    full matmul_cc (rotations, rescales and ModDowns at three levels), equal to the oracle's."""
     B = c3s.B
     r = _cc_case(c3s, 8, 32, 32, 11)
     base = [c3s.export(x) for x in r["C"]]
-    default = B.blb_ctx_get_knob(c3s.h, B.BLB_KNOB_NTT_VARIANT)
-    B.blb_ctx_set_knob(c3s.h, B.BLB_KNOB_NTT_VARIANT, 1 - default)
+    default = (B.blb_ctx_get_knob(c3s.h, B.BLB_KNOB_NTT_VARIANT), B.blb_ctx_get_knob(c3s.h, B.BLB_KNOB_NTT_RADIX))
     try:
-        C2 = [c3s.ct(r["level"] - 3) for _ in range(len(r["C"]))]
-        B.blb_matmul_cc(c3s.h, r["keys_g"], r["plan"], r["A"], r["B"], C2)
-        for o in range(len(C2)):
-            assert np.array_equal(c3s.export(C2[o]), base[o])
+        for variant in (0, 1):
+            for radix in (16, 32):
+                B.blb_ctx_set_knob(c3s.h, B.BLB_KNOB_NTT_VARIANT, variant)
+                B.blb_ctx_set_knob(c3s.h, B.BLB_KNOB_NTT_RADIX, radix)
+                C2 = [c3s.ct(r["level"] - 3) for _ in range(len(r["C"]))]
+                B.blb_matmul_cc(c3s.h, r["keys_g"], r["plan"], r["A"], r["B"], C2)
+                for o in range(len(C2)):
+                    assert np.array_equal(c3s.export(C2[o]), base[o]), f"variant {variant} radix {radix} output {o}"
         for o in range(len(r["want"][0][0])):
-            assert np.array_equal(c3s.export(C2[o]), r["want"][0][0][o])
+            assert np.array_equal(base[o], r["want"][0][0][o])
     finally:
-        B.blb_ctx_set_knob(c3s.h, B.BLB_KNOB_NTT_VARIANT, default)
+        B.blb_ctx_set_knob(c3s.h, B.BLB_KNOB_NTT_VARIANT, default[0])
+        B.blb_ctx_set_knob(c3s.h, B.BLB_KNOB_NTT_RADIX, default[1])
     B.blb_plan_destroy(r["plan"])
     B.blb_keys_destroy(r["keys_g"])
 
 
-def test_ks_variants_bit_identical(c3s, c2s):
-    """The key-grouped inner product (knob 1: outputs sharing a key and Galois element in one
-    thread, groups of up to 16 split across launches' rows) gives the words of the per-output kernel
-    through a full matmul_cc (every key switch of steps 2-3 and the relinearisations) and through
-    matmul_cp (baby steps shared across inputs, giant steps across outputs); both equal the oracle."""
+@pytest.mark.parametrize("ks_variant", [0, 2])
+def test_ks_variants_bit_identical(c3s, c2s, ks_variant):
+    """The per-output key inner product (knob 0) and the key-grouped one forced on every batch
+    (knob 2: outputs sharing a key and Galois element in one thread, groups of up to 16, here with
+    many outputs per group -- the BSGS ct-ct product's baby steps over several operand ciphertexts and
+    its relinearisations, the cp baby steps across inputs) give the oracle's words through a full
+    matmul_cc and through matmul_cp."""
     B = c3s.B
     for c, run in ((c3s, "cc"), (c2s, "cp")):
         default = B.blb_ctx_get_knob(c.h, B.BLB_KNOB_KS_VARIANT)
-        B.blb_ctx_set_knob(c.h, B.BLB_KNOB_KS_VARIANT, 1 - default)
+        B.blb_ctx_set_knob(c.h, B.BLB_KNOB_KS_VARIANT, ks_variant)
         try:
             if run == "cc":
-                r = _cc_case(c, 12, 64, 32, 21, outputs=[0, 1])
+                r = _cc_case(c, 12, 64, 32, 21, outputs=[0, 1], schedule=1)
                 base = 0
                 for O_want, outs, grp in r["want"]:
                     for o in outs:
@@ -568,8 +575,8 @@ def _brv(log_n):
 
 
 @pytest.mark.parametrize("name,n_polys", [("c1", 3), ("c2s", 5), ("c3s", 37)])
-@pytest.mark.parametrize("variant", [0, 1])
-def test_ntt_matches_oracle(request, name, n_polys, variant):
+@pytest.mark.parametrize("variant,radix", [(0, 16), (1, 16), (0, 32), (1, 32)])
+def test_ntt_matches_oracle(request, name, n_polys, variant, radix):
     """blb_ntt: word j of the forward transform is the evaluation at psi^(2 brv(j) + 1), which is
     entry brv(j) of the oracle's natural-order textbook transform; every prime of the chain
     (special primes included); the inverse returns the input exactly; a ragged poly count."""
@@ -581,8 +588,9 @@ def test_ntt_matches_oracle(request, name, n_polys, variant):
     rng = np.random.default_rng(1000 + n_polys)
     words = np.stack([np.stack([rng.integers(0, int(q), c.n, dtype=np.uint64) for q in mods]) for _ in range(n_polys)])
     dev = c.upload_words(words)
-    default = B.blb_ctx_get_knob(c.h, B.BLB_KNOB_NTT_VARIANT)
+    default = (B.blb_ctx_get_knob(c.h, B.BLB_KNOB_NTT_VARIANT), B.blb_ctx_get_knob(c.h, B.BLB_KNOB_NTT_RADIX))
     B.blb_ctx_set_knob(c.h, B.BLB_KNOB_NTT_VARIANT, variant)
+    B.blb_ctx_set_knob(c.h, B.BLB_KNOB_NTT_RADIX, radix)
     try:
         B.blb_ntt(c.h, dev, n_polys, nl, inverse=False)
         torch.cuda.synchronize()
@@ -597,7 +605,8 @@ def test_ntt_matches_oracle(request, name, n_polys, variant):
         back = dev.cpu().numpy().view(np.uint64).reshape(n_polys, nl, c.n)
         assert np.array_equal(back, words)
     finally:
-        B.blb_ctx_set_knob(c.h, B.BLB_KNOB_NTT_VARIANT, default)
+        B.blb_ctx_set_knob(c.h, B.BLB_KNOB_NTT_VARIANT, default[0])
+        B.blb_ctx_set_knob(c.h, B.BLB_KNOB_NTT_RADIX, default[1])
     with pytest.raises(B.BlbError):
         B.blb_ntt(c.h, dev, 1, nl + 1)
     B.blb_ntt(c.h, dev, 0, 1)
