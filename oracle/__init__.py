@@ -73,6 +73,9 @@ def lib():
             "orc_encode_rns": (C.c_int, [vp, _f64p, C.c_int64, C.c_double, C.c_int, _u64p]),
             "orc_crt_centered": (None, [vp, _u64p, C.c_int, _f64p]),
             "orc_decode": (None, [vp, _u64p, C.c_int, C.c_double, C.c_int64, _f64p]),
+            "orc_encode_cplx": (C.c_int, [vp, _f64p, _f64p, C.c_int64, C.c_double, _i64p]),
+            "orc_encode_rns_cplx": (C.c_int, [vp, _f64p, _f64p, C.c_int64, C.c_double, C.c_int, _u64p]),
+            "orc_decode_cplx": (None, [vp, _u64p, C.c_int, C.c_double, C.c_int64, _f64p, _f64p]),
             "orc_keygen": (vp, [vp, C.c_uint64, _u64p, C.c_int]),
             "orc_keys_destroy": (None, [vp]),
             "orc_keys_secret": (None, [vp, _i32p]),
@@ -100,6 +103,9 @@ def lib():
             "orc_matmul_cc_sv": (C.c_int, [vp, _u64p, _u64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p,
                                            _u64p]),
             "orc_matmul_cp_diag": (C.c_int, [vp, _u64p, C.c_int, _f64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, _u64p]),
+            "orc_matmul_cp_pack": (C.c_int, [vp, _u64p, C.c_int, _f64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, _u64p]),
+            "orc_matmul_cp_diag_pack": (C.c_int, [vp, _u64p, C.c_int, _f64p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p,
+                                                  _u64p]),
             "orc_ks_counts": (None, [_i64p, C.c_int]),
             "orc_ew_add": (None, [vp, _u64p, _u64p, C.c_int, _u64p]),
             "orc_ew_add_plain": (None, [vp, _u64p, _u64p, C.c_int, _u64p]),
@@ -242,6 +248,31 @@ class Context:
         if rc != 0:
             raise ValueError("encode overflow")
         return out
+
+    def encode_cplx(self, m_re, m_im, delta: float) -> np.ndarray:
+        """complex slots m_re + i m_im (equal lengths) -> signed integer coefficients"""
+        m_re, m_im = _c(m_re, np.float64), _c(m_im, np.float64)
+        assert m_re.size == m_im.size
+        out = np.zeros(self.n, np.int64)
+        if lib().orc_encode_cplx(self._p, m_re, m_im, m_re.size, float(delta), out) != 0:
+            raise ValueError("encode overflow")
+        return out
+
+    def encode_rns_cplx(self, m_re, m_im, delta: float, level: int) -> np.ndarray:
+        m_re, m_im = _c(m_re, np.float64), _c(m_im, np.float64)
+        assert m_re.size == m_im.size
+        out = np.zeros((level + 1, self.n), np.uint64)
+        if lib().orc_encode_rns_cplx(self._p, m_re, m_im, m_re.size, float(delta), level, out) != 0:
+            raise ValueError("encode overflow")
+        return out
+
+    def decode_cplx(self, poly, level: int, delta: float, n_vals: int | None = None):
+        """(real parts, imaginary parts) of the slots"""
+        n_vals = self.slots if n_vals is None else n_vals
+        re = np.zeros(n_vals, np.float64)
+        im = np.zeros(n_vals, np.float64)
+        lib().orc_decode_cplx(self._p, _c(poly, np.uint64), level, float(delta), n_vals, re, im)
+        return re, im
 
     def crt_centered(self, poly, level: int) -> np.ndarray:
         out = np.zeros(self.n, np.float64)
@@ -493,38 +524,45 @@ class Keys:
             raise ValueError(f"matmul_cc_sv failed ({rc})")
         return O
 
-    def matmul_cp_diag(self, X_cts, level: int, W, L: int, n_heads: int, d_v: int, outputs=None) -> np.ndarray:
+    def matmul_cp_diag(self, X_cts, level: int, W, L: int, n_heads: int, d_v: int, outputs=None, cplx: bool = False) -> np.ndarray:
         """Concat(Att_h) W from the dense diagonal-packed Att_h (head groups concatenated); W is
-        (n_heads d_v) x d_out; returns the spatial-first outputs [n_out][2][level][N]"""
+        (n_heads d_v) x d_out; returns the spatial-first outputs [n_out][2][level][N] (with cplx,
+        ceil(n_out / 2) outputs, output b holding blocks 2b and 2b + 1 in the real and imaginary
+        parts)"""
         c = self.ctx
         W = _c(W, np.float64)
         d_out = W.shape[1]
         assert W.shape[0] == n_heads * d_v
         dvp = 1 << int(np.ceil(np.log2(d_v)))
         g = c.cp_geometry(L, n_heads * dvp, d_out)
-        Y = np.zeros((g["n_out"], 2, level, c.n), np.uint64)
+        n_y = (g["n_out"] + 1) // 2 if cplx else g["n_out"]
+        Y = np.zeros((n_y, 2, level, c.n), np.uint64)
         mask = None
         if outputs is not None:
-            m = np.zeros(g["n_out"], np.uint8)
+            m = np.zeros(n_y, np.uint8)
             m[list(outputs)] = 1
             mask = m.ctypes.data_as(C.c_void_p)
-        rc = lib().orc_matmul_cp_diag(self._p, _c(X_cts, np.uint64), level, W, L, n_heads, d_v, d_out, mask, Y)
+        rc = lib().orc_matmul_cp_diag_pack(self._p, _c(X_cts, np.uint64), level, W, L, n_heads, d_v, d_out, 1 if cplx else 0, mask, Y)
         if rc != 0:
             raise ValueError(f"matmul_cp_diag failed ({rc})")
         return Y
 
-    def matmul_cp(self, X_cts, level: int, W, L: int, outputs=None) -> np.ndarray:
+    def matmul_cp(self, X_cts, level: int, W, L: int, outputs=None, cplx: bool = False) -> np.ndarray:
+        """X W in the spatial-first packing; with cplx the complex-slot output packing
+        (ceil(n_out / 2) outputs, output b holding blocks 2b and 2b + 1 in the real and
+        imaginary parts of its slots)"""
         c = self.ctx
         W = _c(W, np.float64)
         d_in, d_out = W.shape
         g = c.cp_geometry(L, d_in, d_out)
-        Y = np.zeros((g["n_out"], 2, level, c.n), np.uint64)
+        n_y = (g["n_out"] + 1) // 2 if cplx else g["n_out"]
+        Y = np.zeros((n_y, 2, level, c.n), np.uint64)
         mask = None
         if outputs is not None:
-            m = np.zeros(g["n_out"], np.uint8)
+            m = np.zeros(n_y, np.uint8)
             m[list(outputs)] = 1
             mask = m.ctypes.data_as(C.c_void_p)
-        rc = lib().orc_matmul_cp(self._p, _c(X_cts, np.uint64), level, W, L, d_in, d_out, mask, Y)
+        rc = lib().orc_matmul_cp_pack(self._p, _c(X_cts, np.uint64), level, W, L, d_in, d_out, 1 if cplx else 0, mask, Y)
         if rc != 0:
             raise KeyError("missing Galois key")
         return Y

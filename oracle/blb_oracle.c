@@ -330,8 +330,11 @@ static void fft_quad(const orc_ctx* c, f128* re, f128* im, int sgn) {
 /* Encode: p_k = round_half_away( (2*Delta/N) * sum_j m_j cos(pi * e_j * k / N) ), e_j = 5^j mod 2N.
  * Computed as the inverse transform over all odd exponents r: slot values sit at r = e_j
  * and (real slots) at r = -e_j; p_k = (Delta/N) Re( zeta^(-k) sum_t z_t omega^(-t k) ) with
- * r = 2t + 1.  Slots beyond n_vals are zero.  Output: signed integer coefficients. */
-int orc_encode(const orc_ctx* c, const double* m, int64_t n_vals, double delta, int64_t* out) {
+ * r = 2t + 1.  Slots beyond n_vals are zero.  Output: signed integer coefficients.
+ * With mi (complex slots, the full space the encoding map covers): slot j holds
+ * z_j = m_j + i mi_j at r = e_j and its conjugate at r = -e_j, so that
+ * p_k = round_half_away( (2*Delta/N) * sum_j [m_j cos(pi e_j k / N) + mi_j sin(pi e_j k / N)] ). */
+static int encode_slots(const orc_ctx* c, const double* m, const double* mi, int64_t n_vals, double delta, int64_t* out) {
   int n = c->n, s = n / 2;
   if (n_vals > s || n_vals < 0) return -1;
   f128* re = (f128*)calloc(n, sizeof(f128)); f128* im = (f128*)calloc(n, sizeof(f128));
@@ -340,6 +343,11 @@ int orc_encode(const orc_ctx* c, const double* m, int64_t n_vals, double delta, 
     f128 v = j < n_vals ? (f128)m[j] : 0;
     re[(e - 1) / 2] = v;
     re[(two_n - e - 1) / 2] = v;
+    if (mi) {
+      f128 w = j < n_vals ? (f128)mi[j] : 0;
+      im[(e - 1) / 2] = w;
+      im[(two_n - e - 1) / 2] = -w;
+    }
     e = (e * 5) % two_n;
   }
   fft_quad(c, re, im, -1);
@@ -354,6 +362,12 @@ int orc_encode(const orc_ctx* c, const double* m, int64_t n_vals, double delta, 
   free(re); free(im);
   return rc;
 }
+int orc_encode(const orc_ctx* c, const double* m, int64_t n_vals, double delta, int64_t* out) {
+  return encode_slots(c, m, NULL, n_vals, delta, out);
+}
+int orc_encode_cplx(const orc_ctx* c, const double* m_re, const double* m_im, int64_t n_vals, double delta, int64_t* out) {
+  return encode_slots(c, m_re, m_im, n_vals, delta, out);
+}
 
 /* residues of a signed integer polynomial in limbs 0..n_limbs-1 */
 static void to_rns(const orc_ctx* c, const int64_t* p, int n_limbs, uint64_t* out) {
@@ -363,6 +377,14 @@ static void to_rns(const orc_ctx* c, const int64_t* p, int n_limbs, uint64_t* ou
 int orc_encode_rns(const orc_ctx* c, const double* m, int64_t n_vals, double delta, int level, uint64_t* out) {
   int64_t* p = (int64_t*)malloc(8 * c->n);
   int rc = orc_encode(c, m, n_vals, delta, p);
+  if (rc == 0) to_rns(c, p, level + 1, out);
+  free(p);
+  return rc;
+}
+int orc_encode_rns_cplx(const orc_ctx* c, const double* m_re, const double* m_im, int64_t n_vals, double delta, int level,
+                        uint64_t* out) {
+  int64_t* p = (int64_t*)malloc(8 * c->n);
+  int rc = orc_encode_cplx(c, m_re, m_im, n_vals, delta, p);
   if (rc == 0) to_rns(c, p, level + 1, out);
   free(p);
   return rc;
@@ -396,8 +418,9 @@ void orc_crt_centered(const orc_ctx* c, const uint64_t* poly, int level, double*
 }
 
 /* Decode: m_j = Delta^-1 * Re( p~(zeta^(e_j)) ), p~ = centred CRT lift (no rounding before
- * the embedding; see the reading of eq. ckks_encode in the design notes). */
-void orc_decode(const orc_ctx* c, const uint64_t* poly, int level, double delta, int64_t n_vals, double* out) {
+ * the embedding; see the reading of eq. ckks_encode in the design notes).  With out_im the
+ * imaginary parts Delta^-1 * Im( p~(zeta^(e_j)) ) too (complex slots). */
+static void decode_slots(const orc_ctx* c, const uint64_t* poly, int level, double delta, int64_t n_vals, double* out, double* out_im) {
   int n = c->n, nl = level + 1;
   f128* re = (f128*)calloc(n, sizeof(f128)); f128* im = (f128*)calloc(n, sizeof(f128));
   for (int k = 0; k < n; ++k) {
@@ -410,9 +433,17 @@ void orc_decode(const orc_ctx* c, const uint64_t* poly, int level, double delta,
   uint64_t e = 1, two_n = 2ull * n;
   for (int64_t j = 0; j < n_vals && j < n / 2; ++j) {
     out[j] = (double)(re[(e - 1) / 2] / (f128)delta);
+    if (out_im) out_im[j] = (double)(im[(e - 1) / 2] / (f128)delta);
     e = (e * 5) % two_n;
   }
   free(re); free(im);
+}
+void orc_decode(const orc_ctx* c, const uint64_t* poly, int level, double delta, int64_t n_vals, double* out) {
+  decode_slots(c, poly, level, delta, n_vals, out, NULL);
+}
+void orc_decode_cplx(const orc_ctx* c, const uint64_t* poly, int level, double delta, int64_t n_vals, double* out_re,
+                     double* out_im) {
+  decode_slots(c, poly, level, delta, n_vals, out_re, out_im);
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -796,17 +827,20 @@ void orc_pack_spatial(const orc_ctx* c, const double* X, int L, int D, int a, do
   }
 }
 
-/* Y_b = rescale( sum_{j<G} Rot_l^{jBL'}( sum_a sum_{i<B} Encode_{q_l}(Rot_r^{jBL'}(d_{a,b,jB+i})) * Rot_l^{iL'}(X_a) ) )
- * with d_{a,b,t}[u L' + i] = W{a c + ((u + t) mod c_eff), b c + (u mod c_out)} (0 out of range).
- * Inputs X: n_in cts at `level` ([ct][2][limb][N]); W: d_in x d_out row-major.  Outputs
- * Y: n_out cts at level-1 ([ct][2][level][N]).  out_mask selects which outputs to compute
- * (NULL = all; skipped outputs are left untouched).  Returns 0, or -1 on a missing key. */
-int orc_matmul_cp(const orc_keys* K, const uint64_t* X, int level, const double* W, int L, int d_in, int d_out,
-                  const uint8_t* out_mask, uint64_t* Y) {
+/* The schedule of matmul_cp ("Diagonal Ciphertext-Plaintext MatMul", BSGS over the c_eff
+ * diagonals, t = jB + i):
+ *   Y_b = rescale( sum_{j<G} Rot_l^{jBL'}( sum_a sum_{i<B} Encode_{q_l}(Rot_r^{jBL'}(d_{a,b,t})) * Rot_l^{iL'}(X_a) ) ).
+ * diag(geo, a, b, t, vec) writes the slot vector of diagonal d_{a,b,t} (before its pre-rotation;
+ * all zero for an output block b past the last).  With cplx (complex-slot output packing) output
+ * ciphertext b carries block 2b in the real and block 2b + 1 in the imaginary part of each slot:
+ * its plaintexts encode d_{a,2b,t} + i d_{a,2b+1,t}.  The inputs are real, the rotations move
+ * whole complex slots and the products are slot-wise, so the result decodes to Y_{2b} + i Y_{2b+1}. */
+typedef void (*cp_diag_fn)(const void* geo, int a, int b, int t, double* vec);
+
+static int cp_schedule(const orc_keys* K, const uint64_t* X, int level, int lp, int n_in, int n_out_ct, int B, int G,
+                       cp_diag_fn diag, const void* geo, int cplx, const uint8_t* out_mask, uint64_t* Y) {
   const orc_ctx* c = K->c;
   int n = c->n, s = n / 2, nl = level + 1;
-  int32_t g[8]; orc_cp_geometry(c, L, d_in, d_out, g);
-  int lp = g[0], cc = g[1], c_eff = g[2], c_out = g[3], n_in = g[4], n_out = g[5], B = g[6], G = g[7];
   size_t ctw = (size_t)2 * nl * n;
   /* noise boost: the inputs are multiplied by the integer 2^10 before their rotations (the
    * key-switch noise is absolute, so it shrinks by 2^10 relative to the message) and the
@@ -822,12 +856,14 @@ int orc_matmul_cp(const orc_keys* K, const uint64_t* X, int level, const double*
   free(xs);
   double* vec = (double*)malloc(8 * s);
   double* vrot = (double*)malloc(8 * s);
+  double* vec_im = (double*)malloc(8 * s);
+  double* vrot_im = (double*)malloc(8 * s);
   uint64_t* pt = (uint64_t*)malloc(8 * (size_t)nl * n);
   uint64_t* inner = (uint64_t*)malloc(8 * ctw);
   uint64_t* rot = (uint64_t*)malloc(8 * ctw);
   uint64_t* acc = (uint64_t*)malloc(8 * ctw);
   int rc = 0;
-  for (int b = 0; b < n_out && rc == 0; ++b) {
+  for (int b = 0; b < n_out_ct && rc == 0; ++b) {
     if (out_mask && !out_mask[b]) continue;
     memset(acc, 0, 8 * ctw);
     for (int j = 0; j < G && rc == 0; ++j) {
@@ -835,14 +871,16 @@ int orc_matmul_cp(const orc_keys* K, const uint64_t* X, int level, const double*
       for (int a = 0; a < n_in; ++a)
         for (int i = 0; i < B; ++i) {
           int t = j * B + i;
-          for (int slot = 0; slot < s; ++slot) {
-            int u = slot / lp;
-            int row = a * cc + (u + t) % c_eff, col = b * cc + u % c_out;
-            vec[slot] = (row < d_in && col < d_out) ? W[(size_t)row * d_out + col] : 0.0;
-          }
           int r = j * B * lp; /* Rot_r^r: out[slot] = in[slot - r] */
+          diag(geo, a, cplx ? 2 * b : b, t, vec);
           for (int slot = 0; slot < s; ++slot) vrot[slot] = vec[((slot - r) % s + s) % s];
-          orc_encode_rns(c, vrot, s, delta_w, level, pt);
+          if (cplx) {
+            diag(geo, a, 2 * b + 1, t, vec_im);
+            for (int slot = 0; slot < s; ++slot) vrot_im[slot] = vec_im[((slot - r) % s + s) % s];
+            orc_encode_rns_cplx(c, vrot, vrot_im, s, delta_w, level, pt);
+          } else {
+            orc_encode_rns(c, vrot, s, delta_w, level, pt);
+          }
           mac_pt(c, inner, pt, rx + ctw * ((size_t)a * B + i), nl);
         }
       if (j == 0) add_ct(c, acc, inner, nl, 2);
@@ -853,8 +891,40 @@ int orc_matmul_cp(const orc_keys* K, const uint64_t* X, int level, const double*
     }
     if (rc == 0) orc_rescale(c, acc, level, 2, Y + (size_t)b * 2 * level * n);
   }
-  free(rx); free(vec); free(vrot); free(pt); free(inner); free(rot); free(acc);
+  free(rx); free(vec); free(vrot); free(vec_im); free(vrot_im); free(pt); free(inner); free(rot); free(acc);
   return rc;
+}
+
+/* spatial-first input: d_{a,b,t}[u L' + i] = W{a c + ((u + t) mod c_eff), b c + (u mod c_out)}
+ * (0 out of range), broadcast over the L' slots of block u */
+typedef struct {
+  int s, lp, cc, c_eff, c_out, d_in, d_out;
+  const double* W;
+} cp_sf_geo;
+static void cp_sf_diag(const void* geo, int a, int b, int t, double* vec) {
+  const cp_sf_geo* g = (const cp_sf_geo*)geo;
+  for (int slot = 0; slot < g->s; ++slot) {
+    int u = slot / g->lp;
+    int row = a * g->cc + (u + t) % g->c_eff, col = b * g->cc + u % g->c_out;
+    vec[slot] = (row < g->d_in && col < g->d_out) ? g->W[(size_t)row * g->d_out + col] : 0.0;
+  }
+}
+
+/* Inputs X: n_in cts at `level` ([ct][2][limb][N]); W: d_in x d_out row-major.  Outputs Y:
+ * n_out cts at level-1 ([ct][2][level][N]); with cplx, ceil(n_out / 2) of them, output b holding
+ * blocks 2b (real part) and 2b + 1 (imaginary part).  out_mask selects which outputs to compute
+ * (NULL = all; skipped outputs are left untouched).  Returns 0, or -1 on a missing key. */
+int orc_matmul_cp_pack(const orc_keys* K, const uint64_t* X, int level, const double* W, int L, int d_in, int d_out, int cplx,
+                       const uint8_t* out_mask, uint64_t* Y) {
+  const orc_ctx* c = K->c;
+  int32_t g[8]; orc_cp_geometry(c, L, d_in, d_out, g);
+  cp_sf_geo geo = {c->n / 2, g[0], g[1], g[2], g[3], d_in, d_out, W};
+  int n_out_ct = cplx ? (g[5] + 1) / 2 : g[5];
+  return cp_schedule(K, X, level, g[0], g[4], n_out_ct, g[6], g[7], cp_sf_diag, &geo, cplx, out_mask, Y);
+}
+int orc_matmul_cp(const orc_keys* K, const uint64_t* X, int level, const double* W, int L, int d_in, int d_out,
+                  const uint8_t* out_mask, uint64_t* Y) {
+  return orc_matmul_cp_pack(K, X, level, W, L, d_in, d_out, 0, out_mask, Y);
 }
 
 /* Galois elements needed by matmul_cp at this geometry (baby and giant steps) */
@@ -898,13 +968,29 @@ static void diag_block(const orc_ctx* c, int lp, int n_heads, int dvp, int a, in
   *h = -1; *tau = 0;
 }
 
-int orc_matmul_cp_diag(const orc_keys* K, const uint64_t* X, int level, const double* W, int L, int n_heads, int d_v, int d_out,
-                       const uint8_t* out_mask, uint64_t* Y) {
+/* diagonal-packed input: the diagonal of the block comment above, for input a */
+typedef struct {
+  const orc_ctx* c;
+  int s, lp, cc, c_eff, c_out, L, n_heads, d_v, dvp, d_out;
+  const double* W;
+} cp_dg_geo;
+static void cp_dg_diag(const void* geo, int a, int b, int t, double* vec) {
+  const cp_dg_geo* g = (const cp_dg_geo*)geo;
+  for (int slot = 0; slot < g->s; ++slot) {
+    int u = slot / g->lp, row_i = slot % g->lp, h, tau;
+    diag_block(g->c, g->lp, g->n_heads, g->dvp, a, (u + t) % g->c_eff, &h, &tau);
+    int jj = (row_i + tau) % g->dvp, col = b * g->cc + u % g->c_out;
+    vec[slot] = (row_i < g->L && jj < g->d_v && col < g->d_out) ? g->W[(size_t)(h * g->d_v + jj) * g->d_out + col] : 0.0;
+  }
+}
+
+int orc_matmul_cp_diag_pack(const orc_keys* K, const uint64_t* X, int level, const double* W, int L, int n_heads, int d_v, int d_out,
+                            int cplx, const uint8_t* out_mask, uint64_t* Y) {
   const orc_ctx* c = K->c;
-  int n = c->n, s = n / 2, nl = level + 1;
+  int s = c->n / 2;
   int dvp = 1 << ceil_log2(d_v);
   int32_t g[8]; orc_cp_geometry(c, L, n_heads * dvp, d_out, g);
-  int lp = g[0], cc = g[1], c_eff = g[2], c_out = g[3], n_in = g[4], n_out = g[5], B = g[6], G = g[7];
+  int lp = g[0], cc = g[1], c_eff = g[2];
   if (c_eff != cc || dvp > lp) return -3;
   for (int rem = n_heads; rem > 0;) {
     int hg = 1;
@@ -912,51 +998,13 @@ int orc_matmul_cp_diag(const orc_keys* K, const uint64_t* X, int level, const do
     if (s / (lp * hg) > dvp) return -3;
     rem -= hg;
   }
-  size_t ctw = (size_t)2 * nl * n;
-  double delta_w = (double)c->mod[level] / NOISE_BOOST;
-  uint64_t* xs = (uint64_t*)malloc(8 * ctw * (size_t)n_in);
-  for (int a = 0; a < n_in; ++a) scale_ct(c, X + ctw * a, (uint64_t)NOISE_BOOST, nl, xs + ctw * a);
-  uint64_t* rx = (uint64_t*)malloc(8 * ctw * (size_t)n_in * B);
-  for (int a = 0; a < n_in; ++a)
-    for (int i = 0; i < B; ++i)
-      if (orc_rotate(K, xs + ctw * a, level, (int64_t)i * lp, rx + ctw * ((size_t)a * B + i)) != 0) { free(rx); free(xs); return -1; }
-  free(xs);
-  double* vec = (double*)malloc(8 * s);
-  double* vrot = (double*)malloc(8 * s);
-  uint64_t* pt = (uint64_t*)malloc(8 * (size_t)nl * n);
-  uint64_t* inner = (uint64_t*)malloc(8 * ctw);
-  uint64_t* rot = (uint64_t*)malloc(8 * ctw);
-  uint64_t* acc = (uint64_t*)malloc(8 * ctw);
-  int rc = 0;
-  for (int b = 0; b < n_out && rc == 0; ++b) {
-    if (out_mask && !out_mask[b]) continue;
-    memset(acc, 0, 8 * ctw);
-    for (int j = 0; j < G && rc == 0; ++j) {
-      memset(inner, 0, 8 * ctw);
-      for (int a = 0; a < n_in; ++a)
-        for (int i = 0; i < B; ++i) {
-          int t = j * B + i;
-          for (int slot = 0; slot < s; ++slot) {
-            int u = slot / lp, row_i = slot % lp, h, tau;
-            diag_block(c, lp, n_heads, dvp, a, (u + t) % c_eff, &h, &tau);
-            int jj = (row_i + tau) % dvp, col = b * cc + u % c_out;
-            vec[slot] = (row_i < L && jj < d_v && col < d_out) ? W[(size_t)(h * d_v + jj) * d_out + col] : 0.0;
-          }
-          int r = j * B * lp;
-          for (int slot = 0; slot < s; ++slot) vrot[slot] = vec[((slot - r) % s + s) % s];
-          orc_encode_rns(c, vrot, s, delta_w, level, pt);
-          mac_pt(c, inner, pt, rx + ctw * ((size_t)a * B + i), nl);
-        }
-      if (j == 0) add_ct(c, acc, inner, nl, 2);
-      else {
-        if (orc_rotate(K, inner, level, (int64_t)j * B * lp, rot) != 0) { rc = -1; break; }
-        add_ct(c, acc, rot, nl, 2);
-      }
-    }
-    if (rc == 0) orc_rescale(c, acc, level, 2, Y + (size_t)b * 2 * level * n);
-  }
-  free(rx); free(vec); free(vrot); free(pt); free(inner); free(rot); free(acc);
-  return rc;
+  cp_dg_geo geo = {c, s, lp, cc, c_eff, g[3], L, n_heads, d_v, dvp, d_out, W};
+  int n_out_ct = cplx ? (g[5] + 1) / 2 : g[5];
+  return cp_schedule(K, X, level, lp, g[4], n_out_ct, g[6], g[7], cp_dg_diag, &geo, cplx, out_mask, Y);
+}
+int orc_matmul_cp_diag(const orc_keys* K, const uint64_t* X, int level, const double* W, int L, int n_heads, int d_v, int d_out,
+                       const uint8_t* out_mask, uint64_t* Y) {
+  return orc_matmul_cp_diag_pack(K, X, level, W, L, n_heads, d_v, d_out, 0, out_mask, Y);
 }
 
 /* ------------------------------------------------------------------------------------ */

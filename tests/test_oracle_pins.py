@@ -1289,3 +1289,148 @@ def test_scalar_ops_closed_forms_and_counts(orc, op):
     got = c.decode(k.decrypt(k.scalar_op(A, Sc, level, blk, D, op), level), level, out_scale)
     want = a + col[idx % blk] if op == 0 else a * col[idx % blk]
     assert np.abs(got - want).max() < 2.0 ** -20
+
+
+# --------------------------------------------------------------------------------------
+# complex slots and the complex-slot output packing of matmul_cp
+# --------------------------------------------------------------------------------------
+def test_encode_cplx_imaginary_constant_is_x_half(orc):
+    """i b in every slot encodes to b Delta X^(N/2): zeta^(e N/2) = i^e = i for every slot
+    exponent e = 5^j = 1 (mod 4) and -i at the conjugate exponents (catches a conjugate written to
+    the wrong half or with the wrong sign)."""
+    c = orc.Context(10, 1, 0, 1)
+    for b, delta in [(0.5, 2.0 ** 30), (-1.75, 2.0 ** 40)]:
+        p = c.encode_cplx(np.zeros(c.slots), np.full(c.slots, b), delta)
+        want = np.zeros(c.n, np.int64)
+        want[c.n // 2] = int(round(b * delta))
+        assert np.array_equal(p, want)
+        # and a real constant a plus i b gives a Delta + b Delta X^(N/2)
+        p2 = c.encode_cplx(np.full(c.slots, 0.25), np.full(c.slots, b), delta)
+        want[0] = int(round(0.25 * delta))
+        assert np.array_equal(p2, want)
+
+
+@pytest.mark.parametrize("log_n", [3, 4, 5])
+def test_encode_cplx_matches_direct_formula(orc, log_n):
+    """At tiny N the complex encoding equals the direct formula
+    p_k = round_half_away((2 Delta / N) sum_j [a_j cos(pi 5^j k / N) + b_j sin(pi 5^j k / N)]),
+    the real part of (1/N) sum over all odd r of z_r zeta^(-r k) with z at -5^j the conjugate of
+    z at 5^j, evaluated in mpmath (catches a sign slip of the sine term)."""
+    mpmath.mp.dps = 50
+    c = orc.Context(log_n, 1, 0, 1)
+    n, s = c.n, c.slots
+    rng = np.random.default_rng(100 + log_n)
+    a = rng.normal(0, 1, s)
+    b = rng.normal(0, 1, s)
+    delta = 2.0 ** 40
+    got = c.encode_cplx(a, b, delta)
+    for k in range(n):
+        acc = mpmath.mpf(0)
+        for j in range(s):
+            th = mpmath.pi * (pow(5, j, 2 * n) * k) / n
+            acc += mpmath.mpf(a[j]) * mpmath.cos(th) + mpmath.mpf(b[j]) * mpmath.sin(th)
+        v = 2 * mpmath.mpf(delta) / n * acc
+        r = int(mpmath.floor(abs(v) + mpmath.mpf("0.5")))
+        assert int(got[k]) == (r if v >= 0 else -r)
+
+
+def test_encode_cplx_is_real_encodings_joined_by_x_half(orc):
+    """Before rounding, Encode(a + i b) = Encode(a) + X^(N/2) Encode(b) (multiplying by
+    X^(N/2) multiplies every slot by i; negacyclic, so coefficient k >= N/2 wraps with a minus
+    sign).  Each side rounds once per coefficient, so at N = 4096 the two differ by at most 1
+    everywhere; ties aside they mostly agree exactly.  This ties the complex encoding to the real
+    one pinned above."""
+    c = orc.Context(12, 1, 0, 1)
+    n, h = c.n, c.n // 2
+    rng = np.random.default_rng(7)
+    a = rng.normal(0, 1, c.slots)
+    b = rng.normal(0, 1, c.slots)
+    delta = 2.0 ** 38
+    pa, pb = c.encode(a, delta), c.encode(b, delta)
+    shifted = np.concatenate([-pb[h:], pb[:h]])  # X^(N/2) pb mod X^N + 1
+    d = c.encode_cplx(a, b, delta) - (pa + shifted)
+    assert np.abs(d).max() <= 1
+    assert np.count_nonzero(d) < n // 2
+
+
+def test_decode_cplx_inverts_encode_cplx(orc):
+    """Decode of a complex encoding returns both parts within the rounding bound of the real
+    decode; the real parts equal the real decode of the same polynomial; Delta X^(N/2) decodes
+    to i in every slot; and the imaginary part of a decoded real encoding is (near) zero."""
+    c = orc.Context(13, 3, 0, 1)
+    rng = np.random.default_rng(3)
+    a = rng.normal(0, 1, c.slots)
+    b = rng.normal(0, 1, c.slots)
+    delta = 2.0 ** 40
+    pt = c.encode_rns_cplx(a, b, delta, 2)
+    re, im = c.decode_cplx(pt, 2, delta)
+    bound = 8 * np.sqrt(c.n / 24) / delta
+    assert np.abs(re - a).max() < bound and np.abs(im - b).max() < bound
+    assert np.array_equal(re, c.decode(pt, 2, delta))
+    x_half = np.zeros((3, c.n), np.uint64)
+    x_half[:, c.n // 2] = int(delta)
+    re1, im1 = c.decode_cplx(x_half, 2, delta)
+    assert np.abs(re1).max() < 1e-12 and np.abs(im1 - 1.0).max() < 1e-12
+    _, im0 = c.decode_cplx(c.encode_rns(a, delta, 2), 2, delta)
+    assert np.abs(im0).max() < bound
+
+
+@pytest.mark.parametrize("shape", [(32, 64, 96), (20, 40, 24), (5, 96, 70), (16, 64, 160)])
+def test_matmul_cp_cplx_decodes_to_fp64_matmul(orc, shape):
+    """Complex-slot output packing: output ciphertext b decodes, real part, to column block 2b of
+    X @ W and, imaginary part, to block 2b + 1 (FP64, within 2^-10 at Delta = 2^30); an odd block
+    count leaves the last imaginary part (near) zero; a replicated packing (one block) leaves the
+    whole imaginary part (near) zero.  A conjugate slip in the plaintext encoding flips the sign of
+    every odd block and fails here."""
+    L, d_in, d_out = shape
+    c = orc.Context(12, 2, 1, 2)
+    rng = np.random.default_rng(sum(shape) + 1)
+    X = rng.uniform(-1, 1, (L, d_in))
+    W = rng.normal(0, 0.02, (d_in, d_out))
+    g = c.cp_geometry(L, d_in, d_out)
+    k = orc.Keys(c, 9, c.cp_galois(L, d_in, d_out))
+    cts = np.stack([k.encrypt(c.encode_rns(c.pack_spatial(X, a), 2.0 ** 30, 1), 1, 100, a) for a in range(g["n_in"])])
+    Y = k.matmul_cp(cts, 1, W, L, cplx=True)
+    assert Y.shape[0] == (g["n_out"] + 1) // 2
+    vecs = []
+    for b in range(Y.shape[0]):
+        re, im = c.decode_cplx(k.decrypt(Y[b], 0), 0, 2.0 ** 30)
+        vecs += [re, im]
+    got = _unpack(c, g, vecs[: g["n_out"]], L, d_out)
+    assert np.abs(got - X @ W).max() < 2.0 ** -10
+    if g["n_out"] % 2:
+        assert np.abs(vecs[g["n_out"]]).max() < 2.0 ** -10
+
+
+def test_matmul_cp_cplx_counts(orc):
+    """At the BERT-base shape (L = 128, 768 x 768, N = 16384) the complex packing keeps the baby
+    steps and halves the plaintexts, the output ciphertexts and the giant-step rotations:
+    24 x 12 x 32 = 9216 plaintexts (18432 real), 24 x 7 + 12 x 3 = 204 rotations (240 real)."""
+    c2 = orc.Context(13, 3, 1, 3)
+    g = c2.cp_geometry(128, 768, 768)
+    n_out_c = (g["n_out"] + 1) // 2
+    assert n_out_c == 12
+    assert g["n_in"] * n_out_c * g["c_eff"] == 9216
+    assert g["n_in"] * (g["B"] - 1) + n_out_c * (g["G"] - 1) == 204
+
+
+@pytest.mark.parametrize("heads,L,d_v,d_out", [(3, 64, 32, 48), (4, 32, 16, 70)])
+def test_matmul_cp_diag_cplx_decodes(orc, heads, L, d_v, d_out):
+    """The diagonal-input ct-pt matmul in the complex-slot output packing decodes to
+    Concat(Att_h) @ W, real parts block 2b and imaginary parts block 2b + 1."""
+    c = orc.Context(12, 2, 1, 2)
+    rng = np.random.default_rng(heads + L + d_v + 1)
+    att = [rng.uniform(-1, 1, (L, d_v)) for _ in range(heads)]
+    Cm = np.concatenate(att, axis=1)
+    dvp = 1 << int(np.ceil(np.log2(d_v)))
+    g = c.cp_geometry(L, heads * dvp, d_out)
+    keys = orc.Keys(c, 9, c.cp_galois(L, heads * dvp, d_out))
+    X = _diag_inputs(c, keys, att, heads, L, d_v, 1, 2.0 ** 30, 100)
+    W = rng.normal(0, 0.05, (heads * d_v, d_out))
+    Y = keys.matmul_cp_diag(X, 1, W, L, heads, d_v, cplx=True)
+    assert Y.shape[0] == (g["n_out"] + 1) // 2
+    vecs = []
+    for b in range(Y.shape[0]):
+        re, im = c.decode_cplx(keys.decrypt(Y[b], 0), 0, 2.0 ** 30)
+        vecs += [re, im]
+    assert np.abs(_unpack_spatial_by_hand(vecs, g["Lp"], g["c"], L, d_out) - Cm @ W).max() < 2.0 ** -10
