@@ -53,7 +53,9 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_cp(args, B, torch):
+def run_cp(args, B, torch, cplx=False):
+    """The headline fused linear operator; with cplx the complex-slot output packing (output
+    ciphertext b holds column blocks 2b and 2b + 1 in the real and imaginary parts)"""
     from paper_2508_19525_amd import workloads as wl
 
     cfg = wl.C2
@@ -65,7 +67,7 @@ def run_cp(args, B, torch):
     stream = torch.cuda.current_stream().cuda_stream
     ctx = B.blb_ctx_create(p.log_n, p.n_q, p.n_special, p.dnum, 0, stream)
     t_setup = time.time()
-    plan = B.blb_plan_matmul_cp(ctx, W, L, level)
+    plan = (B.blb_plan_matmul_cp_cplx if cplx else B.blb_plan_matmul_cp)(ctx, W, L, level)
     g = B.blb_plan_info(plan)
     steps_rot = [i * g["Lp"] for i in range(1, g["B"])] + [j * g["B"] * g["Lp"] for j in range(1, g["G"])]
     keys = B.blb_keygen(ctx, wl.seed_for(2, wl.ROLE_KEYS), steps_rot)
@@ -97,7 +99,10 @@ def run_cp(args, B, torch):
     dec = torch.empty(level * n, dtype=torch.int64, device="cuda")
     for b in range(g["n_out"]):
         B.blb_decrypt(ctx, keys, Y_cts[b], dec)
-        vecs.append(B.blb_decode(ctx, dec, level - 1, p.scale, n // 2))
+        if cplx:
+            vecs += list(B.blb_decode_cplx(ctx, dec, level - 1, p.scale, n // 2))
+        else:
+            vecs.append(B.blb_decode(ctx, dec, level - 1, p.scale, n // 2))
     got = wl.unpack_spatial(vecs, L, d_out, n // 2)
     ref = X @ W
     err = float(np.abs(got - ref).max())
@@ -160,8 +165,11 @@ def run_cp(args, B, torch):
     mac_alg_bytes = (n_ai * n_bj * nl * n + n_ai * 2 * nl * n + n_bj * 2 * nl * n) * 8
     mac_avg_s = mac_ms / 1e3 / max(mac_n, 1)
     res = {
+        "packing": "complex slots (2 column blocks per output ciphertext)" if cplx else "real slots",
         "value": args.steps / dt,
         "ms_per_step": dt / args.steps * 1e3,
+        "n_out_cts": g["n_out"], "plaintexts": n_ai * n_bj,
+        "plaintext_bytes": n_ai * n_bj * nl * n * 8,
         "eager_ops_s": args.steps / dt_eager,
         "err": err, "mse": mse,
         "mac_avg_ms": mac_avg_s * 1e3,
@@ -1085,6 +1093,7 @@ def main():
     ap.add_argument("--no-qk-fused", action="store_true", help="skip the fused Q K^T-from-X measurement")
     ap.add_argument("--no-small-ops", action="store_true", help="skip the rotate-and-sum / share-addition measurement")
     ap.add_argument("--no-tune", action="store_true", help="skip the MAC launch-shape autotuner")
+    ap.add_argument("--no-cplx", action="store_true", help="skip the complex-slot packing measurement")
     ap.add_argument("--mac-variant", type=int, default=None, help="use this MAC launch shape instead of autotuning")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
@@ -1115,6 +1124,7 @@ def main():
                           "small_ops": run_small_ops(args, B, torch)}))
         return
     r = run_cp(args, B, torch)
+    rcx = None if args.no_cplx else run_cp(args, B, torch, cplx=True)
     nt = None if args.no_ntt else run_ntt(args, B, torch)
     cc_by = {} if args.no_cc else {s: run_cc(args, B, torch, s) for s in (1, 0)}
     cc = cc_by.get(1)
@@ -1152,6 +1162,14 @@ def main():
             "kernel": "k_cp_mac (plaintext-streaming ct-pt MAC)",
             "alg_bytes_per_launch": r["mac_alg_bytes"], "avg_launch_ms": r["mac_avg_ms"]},
         "eager_value": r["eager_ops_s"],
+        "packings": {k: None if v is None else {
+            "packing": v["packing"], "value": v["value"], "ms_per_step": v["ms_per_step"], "eager_value": v["eager_ops_s"],
+            "max_abs_err": v["err"], "output_cts": v["n_out_cts"], "plaintexts": v["plaintexts"],
+            "plaintext_bytes": v["plaintext_bytes"],
+            "mac_alg_bytes_per_op": v["mac_alg_bytes"], "mac_avg_ms": v["mac_avg_ms"],
+            "roofline": {"bound": "hbm", "achieved": v["mac_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": v["mac_gbps"] / HBM_PEAK_GBPS, "kernel": "k_cp_mac", "mac_variant": v["mac_variant"]},
+            "split_ms": v["split"]} for k, v in (("real", r), ("complex", rcx))},
         "ntt": {"in_step": {"GBps": r["ntt_gbps"], "frac_hbm_peak": r["ntt_gbps"] / HBM_PEAK_GBPS,
                             "polys_per_step": r["ntt_polys_per_step"], "launches_per_step": r["ntt_launches_per_step"]},
                 "standalone_1GiB": nt,

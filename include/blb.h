@@ -119,7 +119,7 @@ void blb_keys_destroy(blb_keys* keys);
 /* Galois element 5^steps mod 2N of a left rotation by `steps` slots. */
 uint64_t blb_galois_elt(const blb_ctx* ctx, int32_t steps);
 
-/* ---- encode / encrypt / decrypt / decode (eq. ckks_encode; real slots only) ------------ */
+/* ---- encode / encrypt / decrypt / decode (eq. ckks_encode; real slots, complex on decode) - */
 /* v: host array of n <= N/2 reals (missing slots are 0); writes round-half-away(Delta *
  * pi^-1(v)) reduced into limbs 0..level of pt_dev (coefficient form, [level+1][N]). */
 int blb_encode(blb_ctx* ctx, const double* v, int64_t n, double scale, int level, uint64_t* pt_dev);
@@ -131,6 +131,9 @@ int blb_encrypt(blb_ctx* ctx, const blb_keys* keys, const uint64_t* pt_dev, int 
 int blb_decrypt(blb_ctx* ctx, const blb_keys* keys, const blb_ct* ct, uint64_t* pt_dev);
 /* v (host, n values) <- Delta^-1 * pi(centred CRT lift of pt_dev).  Synchronises. */
 int blb_decode(blb_ctx* ctx, const uint64_t* pt_dev, int level, double scale, double* v, int64_t n);
+/* Complex slots: v_re, v_im (host, n values each) <- real and imaginary parts of
+ * Delta^-1 * pi(centred CRT lift of pt_dev).  EINVAL as blb_decode or when v_im is null. */
+int blb_decode_cplx(blb_ctx* ctx, const uint64_t* pt_dev, int level, double scale, double* v_re, double* v_im, int64_t n);
 /* Canonical coefficient-form words of a ciphertext to / from host memory ([degree+1][level+1][N]). */
 int blb_export(blb_ctx* ctx, const blb_ct* ct, uint64_t* host_words);
 int blb_import(blb_ctx* ctx, const uint64_t* host_words, blb_ct* ct);
@@ -179,6 +182,16 @@ int blb_plan_info(const blb_plan* plan, int32_t* info8);
  * X: n_in ciphertexts at the plan's level; Y: n_out buffers of 2*level*N words. */
 int blb_matmul_cp(blb_ctx* ctx, const blb_keys* keys, const blb_plan* plan, const blb_ct* X, int n_in,
                   blb_ct* Y, int n_out);
+/* Complex-slot output packing (the encoding's slots are complex; "CKKS Approximate HE and
+ * Message Encoding" keeps only their real parts).  The same schedule with the plaintexts of
+ * output blocks 2b and 2b + 1 joined into one, d_{a,2b,t} + i d_{a,2b+1,t}: output ciphertext b
+ * decodes to Y_{2b} + i Y_{2b+1} (real parts block 2b, imaginary parts block 2b + 1; an odd block
+ * count leaves the last imaginary part 0).  Plaintexts, their MAC bytes, giant-step rotations,
+ * rescales and output ciphertexts halve; the baby steps stay.  blb_plan_info's n_out is the
+ * number of output ciphertexts, ceil(blocks / 2); run the plan with blb_matmul_cp (or its
+ * executors and the instance-batched call).  Decode with blb_decode_cplx.  Arguments and errors
+ * as blb_plan_matmul_cp. */
+int blb_plan_matmul_cp_cplx(blb_ctx* ctx, const double* W, int d_in, int d_out, int L, int level, blb_plan** out);
 
 /* ---- matmul_cc (Section "Efficient Protocol for Fused MatMuls": observations 1-2, the three
  * steps and the Multi-Head Optimization; output in diagonal packing) ---------------------
@@ -273,6 +286,9 @@ int blb_plan_matmul_cc_sv(blb_ctx* ctx, int n_heads, int L, int d_v, int level, 
  * (r + tau) mod d_v' >= d_v; encoded at q_level / 2^10 like blb_plan_matmul_cp.  EINVAL when the
  * head groups do not tile the input (the limits of blb_plan_matmul_cc_sv). */
 int blb_plan_matmul_cp_diag(blb_ctx* ctx, const double* W, int n_heads, int d_v, int d_out, int L, int level, blb_plan** out);
+/* The diagonal-input plan in the complex-slot output packing (see blb_plan_matmul_cp_cplx). */
+int blb_plan_matmul_cp_diag_cplx(blb_ctx* ctx, const double* W, int n_heads, int d_v, int d_out, int L, int level,
+                                 blb_plan** out);
 
 /* ---- re-randomisation before mask-to-share (opt-in) -----------------------------------
  * Algorithm ckks2mpc hands the masked ciphertext to the client as evaluated; its c1 depends on

@@ -95,6 +95,10 @@ _SIGS = {
     "blb_plan_matmul_cp_diag": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                           C.POINTER(C.c_void_p)]),
     "blb_plan_cc_info": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "blb_plan_matmul_cp_cplx": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)]),
+    "blb_plan_matmul_cp_diag_cplx": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                               C.POINTER(C.c_void_p)]),
+    "blb_decode_cplx": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_void_p, C.c_void_p, C.c_int64]),
     "blb_cc_rotations_sched": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int32, C.c_int32, C.c_void_p, C.c_int]),
     "blb_plan_matmul_cc_sched": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int32, C.c_int32,
                                            C.POINTER(C.c_void_p)]),
@@ -287,6 +291,15 @@ def blb_decode(ctx, pt_dev, level, scale, n_vals):
     return out
 
 
+def blb_decode_cplx(ctx, pt_dev, level, scale, n_vals):
+    """(real parts, imaginary parts) of the first n_vals slots"""
+    _need(ctx, pt_dev, (level + 1) * _CTX_N.get(ctx, 0), "blb_decode_cplx")
+    re = np.zeros(n_vals, np.float64)
+    im = np.zeros(n_vals, np.float64)
+    _check(lib().blb_decode_cplx(ctx, _ptr(pt_dev), level, float(scale), _host_ptr(re), _host_ptr(im), n_vals), "blb_decode_cplx")
+    return re, im
+
+
 def blb_export(ctx, ct: blb_ct, n):
     out = np.zeros((ct.degree + 1, ct.level + 1, n), np.uint64)
     _check(lib().blb_export(ctx, C.byref(ct), _host_ptr(out)), "blb_export")
@@ -358,6 +371,15 @@ def blb_plan_matmul_cp(ctx, W: np.ndarray, L, level):
     Wc = np.ascontiguousarray(W, dtype=np.float64)
     out = C.c_void_p()
     _check(lib().blb_plan_matmul_cp(ctx, _host_ptr(Wc), Wc.shape[0], Wc.shape[1], L, level, C.byref(out)), "blb_plan_matmul_cp")
+    return out.value
+
+
+def blb_plan_matmul_cp_cplx(ctx, W: np.ndarray, L, level):
+    """complex-slot output packing: output b holds column blocks 2b and 2b + 1"""
+    Wc = np.ascontiguousarray(W, dtype=np.float64)
+    out = C.c_void_p()
+    _check(lib().blb_plan_matmul_cp_cplx(ctx, _host_ptr(Wc), Wc.shape[0], Wc.shape[1], L, level, C.byref(out)),
+           "blb_plan_matmul_cp_cplx")
     return out.value
 
 
@@ -456,6 +478,16 @@ def blb_plan_matmul_cp_diag(ctx, W: np.ndarray, n_heads, d_v, L, level):
     out = C.c_void_p()
     _check(lib().blb_plan_matmul_cp_diag(ctx, _host_ptr(Wc), n_heads, d_v, Wc.shape[1], L, level, C.byref(out)),
            "blb_plan_matmul_cp_diag")
+    return out.value
+
+
+def blb_plan_matmul_cp_diag_cplx(ctx, W: np.ndarray, n_heads, d_v, L, level):
+    Wc = np.ascontiguousarray(W, dtype=np.float64)
+    if Wc.shape[0] != n_heads * d_v:
+        raise BlbError(BLB_EINVAL, "blb_plan_matmul_cp_diag_cplx")
+    out = C.c_void_p()
+    _check(lib().blb_plan_matmul_cp_diag_cplx(ctx, _host_ptr(Wc), n_heads, d_v, Wc.shape[1], L, level, C.byref(out)),
+           "blb_plan_matmul_cp_diag_cplx")
     return out.value
 
 

@@ -1160,14 +1160,19 @@ int blb_decrypt(blb_ctx* c, const blb_keys* K, const blb_ct* ct, uint64_t* pt_de
   return hipGetLastError() == hipSuccess ? BLB_OK : BLB_EDEVICE;
 }
 
-int blb_decode(blb_ctx* c, const uint64_t* pt_dev, int level, double scale, double* v, int64_t n_vals) {
+}  // extern "C"
+
+// slot values of a coefficient-form plaintext: real parts into v, imaginary parts into v_im (when
+// given)
+static int decode_host(blb_ctx* c, const uint64_t* pt_dev, int level, double scale, double* v, double* v_im, int64_t n_vals) {
   if (!c || !pt_dev || !v || level < 0 || level >= c->n_q || n_vals < 0 || n_vals > c->n / 2 || !(scale > 0)) return BLB_EINVAL;
   const int n = c->n, nl = level + 1;
   std::vector<uint64_t> h((size_t)nl * n);
   if (hipMemcpyAsync(h.data(), pt_dev, h.size() * 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess) return BLB_EDEVICE;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return BLB_EDEVICE;
   // centred CRT lift (mixed radix, long double), then the slot evaluation
-  // m_j = Delta^-1 sum_k p_k cos(pi e_j k / N)
+  // m_j = Delta^-1 sum_k p_k zeta^(e_j k): real part sum_k p_k cos(pi e_j k / N), imaginary
+  // part sum_k p_k sin(pi e_j k / N)
   std::vector<long double> lift(n);
   std::vector<uint64_t> invs((size_t)nl * nl);
   for (int i = 0; i < nl; ++i)
@@ -1191,21 +1196,36 @@ int blb_decode(blb_ctx* c, const uint64_t* pt_dev, int level, double scale, doub
     }
     lift[k] = a <= b ? a : -b;
   }
-  std::vector<long double> cosv(2 * n);
+  std::vector<long double> cosv(2 * n), sinv(v_im ? 2 * n : 0);
   for (int t = 0; t < 2 * n; ++t) cosv[t] = cosl(3.14159265358979323846264338327950288L * (long double)t / (long double)n);
+  if (v_im)
+    for (int t = 0; t < 2 * n; ++t) sinv[t] = sinl(3.14159265358979323846264338327950288L * (long double)t / (long double)n);
   uint64_t e = 1;
   for (int64_t j = 0; j < n_vals; ++j) {
-    long double acc = 0;
+    long double acc = 0, acc_im = 0;
     uint64_t idx = 0;
     for (int k = 0; k < n; ++k) {
       acc += lift[k] * cosv[idx];
+      if (v_im) acc_im += lift[k] * sinv[idx];
       idx += e;
       if (idx >= 2ull * n) idx -= 2ull * n;
     }
     v[j] = (double)(acc / (long double)scale);
+    if (v_im) v_im[j] = (double)(acc_im / (long double)scale);
     e = e * 5 % (2ull * n);
   }
   return BLB_OK;
+}
+
+extern "C" {
+
+int blb_decode(blb_ctx* c, const uint64_t* pt_dev, int level, double scale, double* v, int64_t n_vals) {
+  return decode_host(c, pt_dev, level, scale, v, nullptr, n_vals);
+}
+
+int blb_decode_cplx(blb_ctx* c, const uint64_t* pt_dev, int level, double scale, double* v_re, double* v_im, int64_t n_vals) {
+  if (!v_im) return BLB_EINVAL;
+  return decode_host(c, pt_dev, level, scale, v_re, v_im, n_vals);
 }
 
 int blb_export(blb_ctx* c, const blb_ct* ct, uint64_t* host_words) {
@@ -1329,6 +1349,7 @@ static CpGeom cp_geometry(const blb_ctx* c, int L, int d_in, int d_out) {
   g.n_out = (d_out + g.c - 1) / g.c;
   g.B = 1 << ((ceil_log2(g.c_eff) + 1) / 2);
   g.G = g.c_eff / g.B;
+  g.cplx = 0;
   return g;
 }
 
@@ -1355,9 +1376,10 @@ int cp_check_keys(const blb_ctx* c, const blb_keys* K, int L, int d_in, int d_ou
   return BLB_OK;
 }
 
-size_t cp_plan_bytes(const blb_ctx* c, int L, int d_in, int d_out, int level) {
+size_t cp_plan_bytes(const blb_ctx* c, int L, int d_in, int d_out, int level, int cplx) {
   const CpGeom g = cp_geometry(c, L, d_in, d_out);
-  return (size_t)g.n_out * g.G * g.n_in * g.B * (level + 1) * c->n * 8;
+  const int n_out = cplx ? (g.n_out + 1) / 2 : g.n_out;
+  return (size_t)n_out * g.G * g.n_in * g.B * (level + 1) * c->n * 8;
 }
 
 // matmul_cp plan; the plaintexts go to `mem` (cp_plan_bytes bytes, caller-owned) when given,
@@ -1365,7 +1387,7 @@ size_t cp_plan_bytes(const blb_ctx* c, int L, int d_in, int d_out, int level) {
 // the encoder's overflow flag lands in *flag_host when the stream reaches it (non-zero: the
 // plan is unusable), and W must stay valid until then.
 int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, uint64_t* mem, blb_plan** out, int* flag_host,
-                   const double* W_dev, int diag_heads, int diag_dv) {
+                   const double* W_dev, int diag_heads, int diag_dv, int cplx) {
   if (!c || (!W && !W_dev) || !out || d_in < 1 || d_out < 1 || L < 1 || L > c->n / 2 || level < 1 || level >= c->n_q) return BLB_EINVAL;
   *out = nullptr;
   // diagonal-packed input: one table entry per input ciphertext (head groups in the order
@@ -1390,8 +1412,12 @@ int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int 
     d_geom = diag_heads * dvp;
     dg = CpDiag{nullptr, diag_dv, dvp, L};
   }
-  const CpGeom g = cp_geometry(c, L, d_geom, d_out);
+  CpGeom g = cp_geometry(c, L, d_geom, d_out);
   if (diag_heads > 0 && ((int)dtab.size() != g.n_in || g.c_eff != g.c)) return BLB_EINVAL;
+  if (cplx) {
+    g.cplx = 1;
+    g.n_out = (g.n_out + 1) / 2;
+  }
   const int n = c->n, nl = level + 1;
   const int n_bj = g.n_out * g.G, n_ai = g.n_in * g.B;
   const size_t n_pt = (size_t)n_bj * n_ai;
@@ -1500,6 +1526,15 @@ int blb_plan_matmul_cp_mhp(blb_ctx* c, const double* W, int d_in, int n_heads, i
 int blb_plan_matmul_cp_diag(blb_ctx* c, const double* W, int n_heads, int d_v, int d_out, int L, int level, blb_plan** out) {
   if (n_heads < 1 || d_v < 1) return BLB_EINVAL;
   return cp_plan_create(c, W, n_heads * d_v, d_out, L, level, nullptr, out, nullptr, nullptr, n_heads, d_v);
+}
+
+int blb_plan_matmul_cp_cplx(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, blb_plan** out) {
+  return cp_plan_create(c, W, d_in, d_out, L, level, nullptr, out, nullptr, nullptr, 0, 0, 1);
+}
+
+int blb_plan_matmul_cp_diag_cplx(blb_ctx* c, const double* W, int n_heads, int d_v, int d_out, int L, int level, blb_plan** out) {
+  if (n_heads < 1 || d_v < 1) return BLB_EINVAL;
+  return cp_plan_create(c, W, n_heads * d_v, d_out, L, level, nullptr, out, nullptr, nullptr, n_heads, d_v, 1);
 }
 
 void blb_plan_destroy(blb_plan* P) {

@@ -123,6 +123,9 @@ struct MacItem {
 struct CpGeom {
   int d_in, d_out, L;
   int Lp, c, c_eff, c_out, n_in, n_out, B, G;
+  // complex-slot output packing: output ciphertext b carries column blocks 2b (real parts) and
+  // 2b + 1 (imaginary parts); n_out then counts output ciphertexts, ceil(blocks / 2)
+  int cplx;
 };
 
 // Diagonal-packed input of the ct-pt product (the dense outputs of Softmax x V_h, head groups
@@ -306,9 +309,9 @@ void launch_sample_int(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint6
 int cp_check_keys(const blb_ctx* c, const blb_keys* K, int L, int d_in, int d_out);
 void uploader_forget_stream(blb_ctx* c, hipStream_t s);
 void stack_forget_stream(blb_ctx* c, hipStream_t s);
-size_t cp_plan_bytes(const blb_ctx* c, int L, int d_in, int d_out, int level);
+size_t cp_plan_bytes(const blb_ctx* c, int L, int d_in, int d_out, int level, int cplx = 0);
 int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, uint64_t* mem, blb_plan** out, int* flag_host,
-                   const double* W_dev, int diag_heads = 0, int diag_dv = 0);
+                   const double* W_dev, int diag_heads = 0, int diag_dv = 0, int cplx = 0);
 void launch_sample_flood(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag, int bits);
 void upload_cdt(const uint64_t* table20);
 

@@ -598,7 +598,9 @@ struct EncSrcDense {
 };
 
 // matmul_cp diagonal plaintexts, two per complex vector (plaintext p0 + 2 pp in the real part,
-// p0 + 2 pp + 1 in the imaginary part); plaintext p = (bj, ai):
+// p0 + 2 pp + 1 in the imaginary part, split apart after the transform); with the complex-slot
+// output packing (g.cplx) one plaintext per complex vector, whose slots hold the diagonal of
+// output block 2b in the real and that of block 2b + 1 in the imaginary part; plaintext p = (bj, ai):
 //   value at slot s = W{a c + ((u + t) mod c_eff), b c + (u mod c_out)}, u = ((s - r) mod S) / L',
 //   t = jB + i, r = j B L' (plaintext pre-rotated right by r).
 // L', c, c_eff, c_out and S are powers of two (lLp = log2 L').
@@ -622,10 +624,10 @@ struct EncSrcCp {
   struct Pair {
     Diag x, y;
   };
-  __device__ Diag diag(int p) const {
+  __device__ Diag diag(int p, int half) const {
     const int n_ai = g.n_in * g.B;
     const int bj = p / n_ai, ai = p % n_ai;
-    const int b = bj / g.G, j = bj % g.G;
+    const int b = g.cplx ? 2 * (bj / g.G) + half : bj / g.G, j = bj % g.G;
     const int a = ai / g.B, i = ai % g.B;
     const bool used = p < p0 + count;
     const CpDiagIn in = (dg.tab && used) ? dg.tab[a] : CpDiagIn{0, 0, 1, 0};
@@ -647,7 +649,9 @@ struct EncSrcCp {
     }
     return (row < g.d_in && col < g.d_out) ? W[(size_t)row * g.d_out + col] : 0.0;
   }
-  __device__ Pair begin(int pp) const { return Pair{diag(p0 + 2 * pp), diag(p0 + 2 * pp + 1)}; }
+  __device__ Pair begin(int pp) const {
+    return g.cplx ? Pair{diag(p0 + pp, 0), diag(p0 + pp, 1)} : Pair{diag(p0 + 2 * pp, 0), diag(p0 + 2 * pp + 1, 0)};
+  }
   __device__ cdd operator()(const Pair& pr, int u) const {
     const int s = slot_inv[u];
     return cdd{dd{value(pr.x, s), 0.0}, dd{value(pr.y, s), 0.0}};
@@ -828,7 +832,8 @@ int run_encode_cp(blb_ctx* c, const double* W, CpGeom g, int p0, int count, doub
                   int* d_overflow, CpDiag dg) {
   int lLp = 0;
   while ((1 << lLp) < g.Lp) ++lLp;
-  return encode_with(c, EncSrcCp{W, g, p0, count, c->n / 2, lLp, c->d_slot_inv, dg}, count, bufA, bufB, scale, nl, out, d_overflow, true);
+  return encode_with(c, EncSrcCp{W, g, p0, count, c->n / 2, lLp, c->d_slot_inv, dg}, count, bufA, bufB, scale, nl, out, d_overflow,
+                     !g.cplx);
 }
 
 // ---------------------------------------------------------------------------------------
