@@ -840,9 +840,10 @@ def run_batch(args, B, torch):
     return res
 
 
-def run_serving(args, B, torch):
+def run_serving(args, B, torch, packing="complex", steady_rate=0.0):
     """Poisson arrivals of mixed BERT-large / GPT-2-base linear ops (lengths 16..512) into the
-    serving runtime: cold plan cache, HBM-budget admission, continuous batching."""
+    serving runtime: cold plan cache, HBM-budget admission, continuous batching.  packing: the
+    output packing of the served weights ("real" or "complex"), the same for both policies."""
     import ctypes
     from paper_2508_19525_amd import workloads as wl
 
@@ -881,11 +882,12 @@ def run_serving(args, B, torch):
                 cts.append(ct)
             inputs[key] = ((B.blb_ct * n_in)(*cts), X)
         ys = []
-        for b in range(n_out):
+        n_y = (n_out + 1) // 2 if packing == "complex" else n_out
+        for b in range(n_y):
             ct, t = B.new_ct(n, level - 1)
             keep.append(t)
             ys.append(ct)
-        work.append((t_arr, wid, L, client, inputs[key][0], (B.blb_ct * n_out)(*ys), inputs[key][1]))
+        work.append((t_arr, wid, L, client, inputs[key][0], (B.blb_ct * n_y)(*ys), inputs[key][1]))
     torch.cuda.synchronize()
     log(f"serving setup {time.time() - t_setup:.1f}s: {len(reqs)} requests, {len(inputs)} input sets, {len(steps)} rotation keys")
 
@@ -895,7 +897,7 @@ def run_serving(args, B, torch):
                                   policy=policy, max_wait_ms=args.serve_max_wait_ms)
         try:
             for wid, shape in shapes.items():
-                B.blb_server_add_weights(srv, wid, wl.serving_weights(wid, shape), level)
+                B.blb_server_add_weights(srv, wid, wl.serving_weights(wid, shape), level, cplx=packing == "complex")
             t0 = time.perf_counter()
             ids = []
             for t_arr, wid, L, client, X, Y, _ in work:
@@ -936,7 +938,10 @@ def run_serving(args, B, torch):
             vecs = []
             for y in Y:
                 B.blb_decrypt(ctx, keys[client], y, dec)
-                vecs.append(B.blb_decode(ctx, dec, level - 1, y.scale, n // 2))
+                if packing == "complex":
+                    vecs += list(B.blb_decode_cplx(ctx, dec, level - 1, y.scale, n // 2))
+                else:
+                    vecs.append(B.blb_decode(ctx, dec, level - 1, y.scale, n // 2))
             got = wl.unpack_spatial(vecs, Xm.shape[0], shapes[wid][1], n // 2)
             worst = max(worst, float(np.abs(got - Xm @ wl.serving_weights(wid, shapes[wid])).max()))
         return {"requests": len(seen), "max_abs_err": worst, "tolerance": 2.0 ** -20}
@@ -946,15 +951,16 @@ def run_serving(args, B, torch):
     log(f"serving: decoded check {dcheck}")
     per_op, s0 = serve(B.SERVE_FIFO, 1, 1)
     steady = None
-    if args.serve_steady_rate > 0:  # below saturation: latency without queue growth
-        steady, _ = serve(B.SERVE_RESIDENT_FIRST, 8, 2, args.serve_steady_rate)
+    if steady_rate > 0:  # below saturation: latency without queue growth
+        steady, _ = serve(B.SERVE_RESIDENT_FIRST, 8, 2, steady_rate)
     st = dict(served)
     st["decoded_check"] = dcheck
     if steady is not None:
-        st["steady_state"] = {"offered_rps": args.serve_steady_rate, "throughput_rps": steady["throughput_rps"],
+        st["steady_state"] = {"offered_rps": steady_rate, "throughput_rps": steady["throughput_rps"],
                               "p50_ms": steady["p50_ms"], "p99_ms": steady["p99_ms"], "mean_ms": steady["mean_ms"],
                               "completed": steady["completed"], "all_done": steady["all_done"]}
     st["offered_rate_rps"] = args.serve_rate
+    st["packing"] = packing
     st["plan_cache_GB"] = args.serve_cache_gb
     st["policy"] = "resident plans first, oldest after max_wait_ms; max_batch 8; 2 streams"
     st["per_op_baseline"] = dict(per_op, policy="arrival order, one request per launch, one stream (unbatched per-op path)")
@@ -1103,8 +1109,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=500)
     ap.add_argument("--serve-steady-rate", type=float, default=20.0,
                     help="offered rate (req/s) of the below-saturation serving run (0: skip)")
-    ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-rate", type=float, default=100.0, help="offered rate (req/s) of the saturation runs")
     ap.add_argument("--serve-cache-gb", type=float, default=180.0)
+    ap.add_argument("--no-serve-real", action="store_true", help="skip the serving run with real-slot packing")
     ap.add_argument("--serve-max-wait-ms", type=float, default=2000.0)
     ap.add_argument("--serve-sweep", type=str, default="", help="comma-separated offered rates (req/s) for a saturation curve")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB plain copy (counter reference)")
@@ -1133,7 +1140,9 @@ def main():
     so = None if args.no_small_ops else run_small_ops(args, B, torch)
     args.tuned_mac_variant = r["mac_variant"]  # the per-instance (unbatched) path uses the tuned MAC shape too
     bt = None if args.no_batch else run_batch(args, B, torch)
-    sv = None if args.no_serve else run_serving(args, B, torch)
+    sv = None if args.no_serve else run_serving(args, B, torch, "complex", args.serve_steady_rate)
+    if sv is not None and not args.no_serve_real:
+        sv["real_packing"] = run_serving(args, B, torch, "real", 0.0)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -1218,7 +1227,8 @@ def main():
         "serving": None if sv is None else dict(
             sv, workload="Poisson arrivals of BERT-large (1024x1024, 1024x4096, 4096x1024) and GPT-2-base (768x768, "
                          "768x3072, 3072x768) matmul_cp ops, 50/50 by model, L ~ U{16..512}, N=16384, 4 primes + 2 special; "
-                         "cold plan cache, HBM-budget admission, continuous batching"),
+                         "cold plan cache, HBM-budget admission, continuous batching; complex-slot output packing "
+                         "(real_packing: the same trace with the paper's real-slot packing)"),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -421,6 +421,10 @@ int blb_server_create(blb_ctx* ctx, const blb_server_config* cfg, blb_server** o
 /* W: host d_in x d_out row-major (copied); inputs of requests on this weight are at `level`.
  * A weight id can be registered once (EINVAL on a second registration). */
 int blb_server_add_weights(blb_server* server, int weight_id, const double* W, int d_in, int d_out, int level);
+/* The same, with the complex-slot output packing of blb_plan_matmul_cp_cplx: a request on this
+ * weight has ceil(blocks / 2) output ciphertexts, blocks = ceil(d_out / c), and its plans take
+ * half the cache. */
+int blb_server_add_weights_cplx(blb_server* server, int weight_id, const double* W, int d_in, int d_out, int level);
 /* X (n_in cts) and Y (n_out buffers of 2*level*N words) must stay alive until completion; the
  * blb_ct array Y is updated (level, scale) by the worker.  mask_target_level < 0: no mask.
  * Refused at submission: EINVAL (shapes), ELEVEL (input level), ENOKEY (keys lack a rotation
@@ -434,7 +438,10 @@ int blb_server_drain(blb_server* server, double timeout_s);
 /* out[cap >= 10]: completed, rejected, p50 ms, p99 ms, mean ms, plan hits (requests whose plan
  * was ready when first considered), plan misses (plans generated), batches, plan generation
  * seconds (enqueue to completion), resident plan bytes; out[10] (cap > 10): requests whose
- * batch failed at launch (their poll state holds the error code). */
+ * batch failed at launch (their poll state holds the error code); out[11..15] (cap > 15):
+ * plan generations deferred for lack of a free range in the plan cache, deferred for lack of
+ * device memory for their temporaries, plan bytes generated, batch launches retried after
+ * ENOMEM, seconds with queued requests and nothing on the GPU for them. */
 int blb_server_stats(blb_server* server, double* out, int cap);
 void blb_server_destroy(blb_server* server);
 

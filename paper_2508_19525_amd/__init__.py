@@ -114,6 +114,7 @@ _SIGS = {
     "blb_batch_matmul_cp": (C.c_int, [C.c_void_p, C.POINTER(blb_cp_instance), C.c_int]),
     "blb_server_create": (C.c_int, [C.c_void_p, C.POINTER(blb_server_config), C.POINTER(C.c_void_p)]),
     "blb_server_add_weights": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int]),
+    "blb_server_add_weights_cplx": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int]),
     "blb_server_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_int,
                                     C.c_uint64, C.c_int, C.c_void_p, C.POINTER(C.c_int64)]),
     "blb_server_poll": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
@@ -589,9 +590,12 @@ def blb_server_create(ctx, plan_cache_bytes, max_batch=16, max_queue=4096, n_str
     return out.value
 
 
-def blb_server_add_weights(server, weight_id, W, level):
+def blb_server_add_weights(server, weight_id, W, level, cplx=False):
+    """register W (d_in x d_out); cplx: complex-slot output packing for requests on it"""
     Wc = np.ascontiguousarray(W, dtype=np.float64)
-    _check(lib().blb_server_add_weights(server, weight_id, _host_ptr(Wc), Wc.shape[0], Wc.shape[1], level), "blb_server_add_weights")
+    fn = lib().blb_server_add_weights_cplx if cplx else lib().blb_server_add_weights
+    _check(fn(server, weight_id, _host_ptr(Wc), Wc.shape[0], Wc.shape[1], level),
+           "blb_server_add_weights_cplx" if cplx else "blb_server_add_weights")
 
 
 def blb_server_submit(server, keys, weight_id, L, X_arr, Y_arr, mask_seed=0, mask_target_level=-1, share_dev=None):
@@ -615,10 +619,11 @@ def blb_server_drain(server, timeout_s=600.0):
 
 
 def blb_server_stats(server):
-    out = np.zeros(11, np.float64)
-    _check(lib().blb_server_stats(server, _host_ptr(out), 11), "blb_server_stats")
+    out = np.zeros(16, np.float64)
+    _check(lib().blb_server_stats(server, _host_ptr(out), 16), "blb_server_stats")
     keys = ["completed", "rejected", "p50_ms", "p99_ms", "mean_ms", "plan_hits", "plan_misses", "batches", "plan_gen_s",
-            "plan_bytes", "failed"]
+            "plan_bytes", "failed", "gen_deferred_room", "gen_deferred_mem", "plan_bytes_generated", "launch_retries",
+            "stall_s"]
     return dict(zip(keys, [float(x) for x in out]))
 
 

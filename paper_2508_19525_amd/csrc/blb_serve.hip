@@ -40,6 +40,7 @@ struct Weights {
   std::vector<double> W;
   double* W_dev = nullptr;  // device copy (plans are generated from it without a host copy)
   int d_in = 0, d_out = 0, level = 0;
+  int cplx = 0;  // complex-slot output packing (two column blocks per output ciphertext)
 };
 
 struct PlanEntry {
@@ -156,6 +157,11 @@ struct blb_server {
   // statistics written by the worker and read by blb_server_stats: atomics; the others
   // change under `mu`
   std::atomic<int64_t> hits{0}, misses{0}, batches{0}, gen_ns{0};
+  // scheduling diagnostics: plan generations deferred for lack of a free arena range or of
+  // device memory for their temporaries, plan bytes generated, batch launches retried after
+  // ENOMEM, and the time the worker held queued requests with nothing on the GPU for them
+  // (no batch running, no generation in flight)
+  std::atomic<int64_t> defer_room{0}, defer_mem{0}, gen_bytes{0}, launch_retries{0}, stall_ns{0};
   int64_t rejected = 0, completed = 0, failed = 0;
   std::vector<double> latencies;
 };
@@ -212,10 +218,13 @@ int generate_plan(blb_server* S, Request* r, bool async) {
     wp = &S->weights.at(r->weight_id);
   }
   const Weights& w = *wp;
-  const size_t need = cp_plan_bytes(c, r->Lp, w.d_in, w.d_out, w.level);
+  const size_t need = cp_plan_bytes(c, r->Lp, w.d_in, w.d_out, w.level, w.cplx);
   if (Arena::round(need) > S->arena.cap) return BLB_ENOMEM;
   size_t off = 0;
-  if (!make_room(S, need, &off)) return 0;  // memory frees up when running batches finish
+  if (!make_room(S, need, &off)) {  // memory frees up when running batches finish
+    ++S->defer_room;
+    return 0;
+  }
   const double t0 = now_s();
   blb_plan* P = nullptr;
   hipStream_t saved = c->stream;
@@ -228,17 +237,21 @@ int generate_plan(blb_server* S, Request* r, bool async) {
       if (!used) break;
     }
   const int rc = cp_plan_create(c, w.W.data(), w.d_in, w.d_out, r->Lp, w.level, (uint64_t*)((char*)S->arena.base + off), &P,
-                                async ? S->gen_flag + slot : nullptr, w.W_dev);
+                                async ? S->gen_flag + slot : nullptr, w.W_dev, 0, 0, w.cplx);
   hipEvent_t ev = nullptr;
   if (rc == BLB_OK && async && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) (void)hipEventRecord(ev, c->stream);
   c->stream = saved;
   if (rc) {
     S->arena.release(off, need);
-    if (rc == BLB_ENOMEM) return 0;
+    if (rc == BLB_ENOMEM) {
+      ++S->defer_mem;
+      return 0;
+    }
     S->bad_plans[key] = rc;
     return rc;
   }
   ++S->misses;
+  S->gen_bytes += (int64_t)P->bytes;
   PlanEntry& pe = S->plans[key];
   pe.plan = P;
   pe.off = off;
@@ -310,6 +323,7 @@ void worker_loop(blb_server* S) {
   blb_ctx* c = S->c;
   (void)hipSetDevice(c->device);
   int next_stream = 0;
+  double stall_since = -1;  // start of a stretch with queued requests and nothing on the GPU for them
   for (;;) {
     std::vector<Request*> pending;
     {
@@ -328,11 +342,22 @@ void worker_loop(blb_server* S) {
     };
     if (S->cfg.policy == 1) {
       poll_generation(S);
-      // requests whose plan is ready, the oldest first when it is overdue; no new batch while
-      // n_streams + 1 are in flight (the worker keeps queueing plan generations meanwhile)
-      const bool can_launch = (int)S->running.size() < (int)S->streams.size() + 1;
       Request* oldest = pending.front();
       const bool overdue = (now_s() - oldest->t_submit) * 1e3 > S->cfg.max_wait_ms;
+      // An overdue request whose plan is missing has its plan generated first.  When the plan
+      // cache has no room for it because batches in flight hold the other plans, no new batch
+      // is formed until they finish: otherwise requests on resident plans, arriving all the
+      // time, would keep those plans pinned and starve it.
+      bool hold = false;
+      const auto okey = std::make_pair(oldest->weight_id, oldest->Lp);
+      if (overdue && !S->bad_plans.count(okey) && !S->plans.count(okey) && (int)S->gens.size() < blb_server::kGenDepth) {
+        const int g = generate_plan(S, oldest, true);
+        if (g < 0) reject(oldest, g);
+        hold = g == 0;
+      }
+      // requests whose plan is ready, the oldest first when it is overdue; no new batch while
+      // n_streams + 1 are in flight (the worker keeps queueing plan generations meanwhile)
+      const bool can_launch = !hold && (int)S->running.size() < (int)S->streams.size() + 1;
       if (can_launch && overdue && admit_ready(S, oldest)) batch.push_back(oldest);
       for (Request* r : pending) {
         if (!can_launch || (int)batch.size() >= S->cfg.max_batch) break;
@@ -343,7 +368,7 @@ void worker_loop(blb_server* S) {
       }
       // queue the plans of the oldest requests that have none, up to kGenDepth at a time
       for (Request* r : pending) {
-        if ((int)S->gens.size() >= blb_server::kGenDepth) break;
+        if (hold || (int)S->gens.size() >= blb_server::kGenDepth) break;
         if (std::find(rejected.begin(), rejected.end(), r) != rejected.end()) continue;
         if (S->plans.count(std::make_pair(r->weight_id, r->Lp))) continue;
         const int g = generate_plan(S, r, true);
@@ -378,6 +403,12 @@ void worker_loop(blb_server* S) {
       }
     }
     if (!rejected.empty()) S->cv.notify_all();
+    const bool stalled = batch.empty() && S->gens.empty() && S->running.empty() && pending.size() > rejected.size();
+    if (stalled && stall_since < 0) stall_since = now_s();
+    if (!stalled && stall_since >= 0) {
+      S->stall_ns += (int64_t)((now_s() - stall_since) * 1e9);
+      stall_since = -1;
+    }
     if (batch.empty()) {
       if (!S->gens.empty()) std::this_thread::sleep_for(std::chrono::microseconds(50));  // a plan is on its way
       else if (!S->running.empty()) finish_batches(S, true);  // a batch slot or memory frees up
@@ -400,6 +431,7 @@ void worker_loop(blb_server* S) {
     }
     int rc = blb_batch_matmul_cp(c, inst.data(), (int)inst.size());
     if (rc == BLB_ENOMEM) {
+      ++S->launch_retries;
       // the batch's temporaries did not fit beside the batches in flight (the call fails before it
       // writes any output): let those finish, give back idle memory and try again, then one
       // request at a time
@@ -510,7 +542,9 @@ int blb_server_create(blb_ctx* c, const blb_server_config* cfg, blb_server** out
   return BLB_OK;
 }
 
-int blb_server_add_weights(blb_server* S, int weight_id, const double* W, int d_in, int d_out, int level) {
+}  // extern "C"
+
+static int add_weights(blb_server* S, int weight_id, const double* W, int d_in, int d_out, int level, int cplx) {
   if (!S || !W || d_in < 1 || d_out < 1 || level < 1 || level >= S->c->n_q) return BLB_EINVAL;
   std::lock_guard<std::mutex> lk(S->mu);
   if (S->weights.count(weight_id)) return BLB_EINVAL;  // a registered weight id is immutable
@@ -530,7 +564,18 @@ int blb_server_add_weights(blb_server* S, int weight_id, const double* W, int d_
   w.d_in = d_in;
   w.d_out = d_out;
   w.level = level;
+  w.cplx = cplx;
   return BLB_OK;
+}
+
+extern "C" {
+
+int blb_server_add_weights(blb_server* S, int weight_id, const double* W, int d_in, int d_out, int level) {
+  return add_weights(S, weight_id, W, d_in, d_out, level, 0);
+}
+
+int blb_server_add_weights_cplx(blb_server* S, int weight_id, const double* W, int d_in, int d_out, int level) {
+  return add_weights(S, weight_id, W, d_in, d_out, level, 1);
 }
 
 int blb_server_submit(blb_server* S, const blb_keys* keys, int weight_id, int L, const blb_ct* X, int n_in, blb_ct* Y, int n_out,
@@ -543,7 +588,8 @@ int blb_server_submit(blb_server* S, const blb_keys* keys, int weight_id, int L,
   const Weights& w = wit->second;
   const int Lp = 1 << ceil_log2i(L);
   const int cc = (S->c->n / 2) / Lp;
-  if (n_in != (w.d_in + cc - 1) / cc || n_out != (w.d_out + cc - 1) / cc) return BLB_EINVAL;
+  const int blocks = (w.d_out + cc - 1) / cc;
+  if (n_in != (w.d_in + cc - 1) / cc || n_out != (w.cplx ? (blocks + 1) / 2 : blocks)) return BLB_EINVAL;
   for (int a = 0; a < n_in; ++a)
     if (!X[a].data || X[a].level != w.level || X[a].degree != 1) return BLB_ELEVEL;
   for (int b = 0; b < n_out; ++b)
@@ -614,6 +660,13 @@ int blb_server_stats(blb_server* S, double* out, int cap) {
   out[8] = (double)S->gen_ns.load() * 1e-9;
   out[9] = (double)S->plan_bytes.load();
   if (cap > 10) out[10] = (double)S->failed;
+  if (cap > 15) {
+    out[11] = (double)S->defer_room.load();
+    out[12] = (double)S->defer_mem.load();
+    out[13] = (double)S->gen_bytes.load();
+    out[14] = (double)S->launch_retries.load();
+    out[15] = (double)S->stall_ns.load() * 1e-9;
+  }
   return BLB_OK;
 }
 

@@ -27,8 +27,9 @@ def env():
 SHAPES = {0: (64, 64), 1: (64, 128), 2: (128, 64)}
 
 
-def _make_requests(B, wl, ctx, specs, keys, level=2, n=8192, scale=2.0 ** 40):
-    """specs: [(weight_id, L, client, input seed)] -> list of dicts with ABI arrays"""
+def _make_requests(B, wl, ctx, specs, keys, level=2, n=8192, scale=2.0 ** 40, cplx=False):
+    """specs: [(weight_id, L, client, input seed)] -> list of dicts with ABI arrays (cplx: output
+    arrays sized for the complex-slot output packing)"""
     keep, reqs = [], []
     pt = torch.empty((level + 1) * n, dtype=torch.int64, device="cuda")
     keep.append(pt)
@@ -37,6 +38,8 @@ def _make_requests(B, wl, ctx, specs, keys, level=2, n=8192, scale=2.0 ** 40):
         lp = wl.lp_of(L)
         cc = (n // 2) // lp
         n_in, n_out = -(-d_in // cc), -(-d_out // cc)
+        if cplx:
+            n_out = (n_out + 1) // 2
         X = np.random.default_rng(xs).normal(0, 1, (L, d_in))
         xcts, ycts = [], []
         for a in range(n_in):
@@ -326,3 +329,51 @@ def test_submit_checks_mask_target_and_share(env):
         B.blb_server_destroy(srv)
         for k in keys:
             B.blb_keys_destroy(k)
+
+
+def test_complex_packed_weights(env):
+    """Weights registered with the complex-slot output packing: every served request equals the
+    eager matmul_cp on a complex plan of the same weight and length, word for word, and its
+    decoded real / imaginary parts give X W; the real-packing output count is refused."""
+    B, wl, ctx = env
+    keys = _keys_for_all(B, wl, ctx, 2)
+    specs = [(i % 3, [16, 100, 33, 200, 64, 300][i % 6], i % 2, 40 + i) for i in range(8)]
+    reqs, keep = _make_requests(B, wl, ctx, specs, keys, cplx=True)
+    Ws = {wid: wl.serving_weights(wid, SHAPES[wid]) for wid in SHAPES}
+    srv = B.blb_server_create(ctx, plan_cache_bytes=600 << 20, max_batch=4, n_streams=2, policy=1, max_wait_ms=50.0)
+    try:
+        for wid, W in Ws.items():
+            B.blb_server_add_weights(srv, wid, W, 2, cplx=True)
+        # the real-packing output count is refused for a complex-packed weight
+        real, keep2 = _make_requests(B, wl, ctx, [(1, 64, 0, 99)], keys)
+        r = real[0]
+        if len(r["Y"]) > 1:
+            with pytest.raises(B.BlbError):
+                B.blb_server_submit(srv, keys[0], r["wid"], r["L"], r["X"], r["Y"], 1, -1, None)
+        ids = [B.blb_server_submit(srv, keys[r["client"]], r["wid"], r["L"], r["X"], r["Y"], 0, -1, None) for r in reqs]
+        B.blb_server_drain(srv, 300)
+        assert [B.blb_server_poll(srv, i)[0] for i in ids] == [2] * len(ids)
+    finally:
+        B.blb_server_destroy(srv)
+    dec = torch.empty(2 * 8192, dtype=torch.int64, device="cuda")
+    for r in reqs:
+        plan = B.blb_plan_matmul_cp_cplx(ctx, Ws[r["wid"]], r["L"], 2)
+        n_y = len(r["Y"])
+        assert B.blb_plan_info(plan)["n_out"] == n_y
+        Ye = []
+        for b in range(n_y):
+            ct, t = B.new_ct(8192, 1)
+            keep.append(t)
+            Ye.append(ct)
+        B.blb_matmul_cp(ctx, keys[r["client"]], plan, list(r["X"]), Ye)
+        torch.cuda.synchronize()
+        vecs = []
+        for b in range(n_y):
+            assert np.array_equal(B.blb_export(ctx, r["Y"][b], 8192), B.blb_export(ctx, Ye[b], 8192)), f"output {b}"
+            B.blb_decrypt(ctx, keys[r["client"]], r["Y"][b], dec)
+            vecs += list(B.blb_decode_cplx(ctx, dec, 1, r["Y"][b].scale, 4096))
+        got = wl.unpack_spatial(vecs, r["L"], SHAPES[r["wid"]][1], 4096)
+        assert np.abs(got - r["Xm"] @ Ws[r["wid"]]).max() < 2.0 ** -20
+        B.blb_plan_destroy(plan)
+    for k in keys:
+        B.blb_keys_destroy(k)
