@@ -40,13 +40,19 @@ MAC_TRAFFIC_BYTES = {0: 3772255748, 1: 3759417293, 2: 3775985761, 3: 3774165864,
                      7: 3787866206, 8: 3748317708, 9: 3746432573, 10: 3864620077, 11: 3813634323, 12: 3800206758, 13: 3807150531}
 
 
-def mac_traffic(variant):
+# The same for the complex-slot output packing of that operator (12 output ciphertexts, half the plaintexts).
+MAC_TRAFFIC_BYTES_CPLX = {0: 1919314763, 1: 1914374364, 2: 1906886435, 3: 1918009261, 4: 1908545797, 5: 1958441900,
+                          6: 1919435771, 7: 1963228559, 8: 1908226553, 9: 1907899886, 10: 1980373854, 11: 1958646126,
+                          12: 1925662902, 13: 1950605759}
+
+
+def mac_traffic(variant, cplx=False):
     import hashlib
     src = open(os.path.join(ROOT, "paper_2508_19525_amd", "csrc", "blb_kernels.hip")).read()
     a, b = src.find("// One block's (tile, k-chunk, limb)"), src.find("// out[o] = sum_t src[o * n_terms + t]")
     if a < 0 or b < 0 or hashlib.sha256(src[a:b].encode()).hexdigest() != MAC_TRAFFIC_SRC_SHA256:
         return None
-    return MAC_TRAFFIC_BYTES.get(variant)
+    return (MAC_TRAFFIC_BYTES_CPLX if cplx else MAC_TRAFFIC_BYTES).get(variant)
 
 
 def log(msg):
@@ -1177,7 +1183,8 @@ def main():
             "plaintext_bytes": v["plaintext_bytes"],
             "mac_alg_bytes_per_op": v["mac_alg_bytes"], "mac_avg_ms": v["mac_avg_ms"],
             "roofline": {"bound": "hbm", "achieved": v["mac_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                         "frac": v["mac_gbps"] / HBM_PEAK_GBPS, "kernel": "k_cp_mac", "mac_variant": v["mac_variant"]},
+                         "frac": v["mac_gbps"] / HBM_PEAK_GBPS, "traffic": mac_traffic(v["mac_variant"], k == "complex"),
+                         "kernel": "k_cp_mac", "mac_variant": v["mac_variant"]},
             "split_ms": v["split"]} for k, v in (("real", r), ("complex", rcx))},
         "ntt": {"in_step": {"GBps": r["ntt_gbps"], "frac_hbm_peak": r["ntt_gbps"] / HBM_PEAK_GBPS,
                             "polys_per_step": r["ntt_polys_per_step"], "launches_per_step": r["ntt_launches_per_step"]},
