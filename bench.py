@@ -846,10 +846,12 @@ def run_batch(args, B, torch):
     return res
 
 
-def run_serving(args, B, torch, packing="complex", steady_rate=0.0):
+def run_serving(args, B, torch, packing="complex", steady_rate=0.0, sat_rate=0.0):
     """Poisson arrivals of mixed BERT-large / GPT-2-base linear ops (lengths 16..512) into the
     serving runtime: cold plan cache, HBM-budget admission, continuous batching.  packing: the
-    output packing of the served weights ("real" or "complex"), the same for both policies."""
+    output packing of the served weights ("real" or "complex"), the same for both policies.
+    steady_rate: also a run below saturation (latency without queue growth); sat_rate: also both
+    policies at an offered rate above either's capacity (throughput = capacity)."""
     import ctypes
     from paper_2508_19525_amd import workloads as wl
 
@@ -973,6 +975,14 @@ def run_serving(args, B, torch, packing="complex", steady_rate=0.0):
     st["served_vs_per_op_throughput"] = served["throughput_rps"] / max(per_op["throughput_rps"], 1e-12)
     st["identical_outputs"] = all(np.array_equal(a, b) for a, b in zip(s1, s0))
     log(f"serving: served {served['throughput_rps']:.2f} rps vs per-op {per_op['throughput_rps']:.2f} rps, identical {st['identical_outputs']}")
+    if sat_rate > 0:
+        served_s, _ = serve(B.SERVE_RESIDENT_FIRST, 8, 2, sat_rate)
+        per_op_s, _ = serve(B.SERVE_FIFO, 1, 1, sat_rate)
+        keep_keys = ("throughput_rps", "p50_ms", "p99_ms", "plan_misses", "plan_bytes_generated", "completed", "all_done")
+        st["saturation"] = {"offered_rps": sat_rate, "served": {k: served_s[k] for k in keep_keys},
+                            "per_op": {k: per_op_s[k] for k in keep_keys},
+                            "served_vs_per_op_throughput": served_s["throughput_rps"] / max(per_op_s["throughput_rps"], 1e-12)}
+        log(f"serving at {sat_rate} req/s: served {served_s['throughput_rps']:.2f} vs per-op {per_op_s['throughput_rps']:.2f}")
     if args.serve_sweep:
         curve = []
         for rate in [float(x) for x in args.serve_sweep.split(",")]:
@@ -1115,7 +1125,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=500)
     ap.add_argument("--serve-steady-rate", type=float, default=20.0,
                     help="offered rate (req/s) of the below-saturation serving run (0: skip)")
-    ap.add_argument("--serve-rate", type=float, default=100.0, help="offered rate (req/s) of the saturation runs")
+    ap.add_argument("--serve-rate", type=float, default=50.0, help="offered rate (req/s) of the serving trace")
+    ap.add_argument("--serve-sat-rate", type=float, default=100.0,
+                    help="offered rate (req/s) of the capacity runs, above both policies' capacity (0: skip)")
     ap.add_argument("--serve-cache-gb", type=float, default=180.0)
     ap.add_argument("--no-serve-real", action="store_true", help="skip the serving run with real-slot packing")
     ap.add_argument("--serve-max-wait-ms", type=float, default=2000.0)
@@ -1146,7 +1158,7 @@ def main():
     so = None if args.no_small_ops else run_small_ops(args, B, torch)
     args.tuned_mac_variant = r["mac_variant"]  # the per-instance (unbatched) path uses the tuned MAC shape too
     bt = None if args.no_batch else run_batch(args, B, torch)
-    sv = None if args.no_serve else run_serving(args, B, torch, "complex", args.serve_steady_rate)
+    sv = None if args.no_serve else run_serving(args, B, torch, "complex", args.serve_steady_rate, args.serve_sat_rate)
     if sv is not None and not args.no_serve_real:
         sv["real_packing"] = run_serving(args, B, torch, "real", 0.0)
     cpu = None
@@ -1235,7 +1247,8 @@ def main():
             sv, workload="Poisson arrivals of BERT-large (1024x1024, 1024x4096, 4096x1024) and GPT-2-base (768x768, "
                          "768x3072, 3072x768) matmul_cp ops, 50/50 by model, L ~ U{16..512}, N=16384, 4 primes + 2 special; "
                          "cold plan cache, HBM-budget admission, continuous batching; complex-slot output packing "
-                         "(real_packing: the same trace with the paper's real-slot packing)"),
+                         "(real_packing: the same trace with the paper's real-slot packing; saturation: the same "
+                         "trace offered faster than either path serves it)"),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -40,7 +40,11 @@ def _import(B, ctx, keep, words, n, level, scale):
     return c
 
 
-def test_bert_base_matmul_cp_full_size(B, orc):
+@pytest.mark.parametrize("cplx", [False, True])
+def test_bert_base_matmul_cp_full_size(B, orc, cplx):
+    """The headline operator at full size, real-slot or complex-slot output packing: inputs
+    encrypted by the library equal the oracle's, counters equal the schedule's closed forms,
+    sampled outputs equal the oracle's word for word, every output decodes to X W within 2^-20."""
     from paper_2508_19525_amd import workloads as wl
     cfg = wl.C2
     p = cfg["params"]
@@ -55,9 +59,10 @@ def test_bert_base_matmul_cp_full_size(B, orc):
     ctx = B.blb_ctx_create(p.log_n, p.n_q, p.n_special, p.dnum, 0, torch.cuda.current_stream().cuda_stream)
     keep = []
     try:
-        plan = B.blb_plan_matmul_cp(ctx, W, L, level)
+        plan = (B.blb_plan_matmul_cp_cplx if cplx else B.blb_plan_matmul_cp)(ctx, W, L, level)
         g = B.blb_plan_info(plan)
-        assert (g["B"], g["G"], g["n_in"], g["n_out"]) == (8, 4, 24, 24)
+        n_y = 12 if cplx else 24  # output ciphertexts
+        assert (g["B"], g["G"], g["n_in"], g["n_out"]) == (8, 4, 24, n_y)
         steps = [k * g["Lp"] for k in range(1, g["B"])] + [j * g["B"] * g["Lp"] for j in range(1, g["G"])]
         keys = B.blb_keygen(ctx, 77, steps)
         # the library's own encode + encrypt of X equals the oracle's words
@@ -74,20 +79,23 @@ def test_bert_base_matmul_cp_full_size(B, orc):
         B.blb_matmul_cp(ctx, keys, plan, xs, ys)
         cnt = B.blb_ctx_counters(ctx, reset=True)
         torch.cuda.synchronize()
-        assert cnt["key_switches"] == 24 * 7 + 24 * 3 == 240
-        assert cnt["ct_pt_products"] == 24 * 24 * 32 == 18432
-        assert cnt["modup_sources"] == 24 + 24 * 3
-        assert cnt["rescaled_cts"] == 24
-        assert cnt["plaintext_bytes"] == 18432 * 3 * n * 8
-        samples = [0, 17]
-        want = keys_o.matmul_cp(xw, level, W, L, outputs=samples)
+        assert cnt["key_switches"] == 24 * 7 + n_y * 3  # 240 real, 204 complex
+        assert cnt["ct_pt_products"] == 24 * n_y * 32  # 18432 real, 9216 complex
+        assert cnt["modup_sources"] == 24 + n_y * 3
+        assert cnt["rescaled_cts"] == n_y
+        assert cnt["plaintext_bytes"] == 24 * n_y * 32 * 3 * n * 8
+        samples = [0, 7] if cplx else [0, 17]
+        want = keys_o.matmul_cp(xw, level, W, L, outputs=samples, cplx=cplx)
         for b in samples:
             assert np.array_equal(B.blb_export(ctx, ys[b], n), want[b]), f"output {b}"
         vecs = []
         dec = torch.empty(level * n, dtype=torch.int64, device="cuda")
         for b in range(g["n_out"]):
             B.blb_decrypt(ctx, keys, ys[b], dec)
-            vecs.append(B.blb_decode(ctx, dec, level - 1, ys[b].scale, n // 2))
+            if cplx:
+                vecs += list(B.blb_decode_cplx(ctx, dec, level - 1, ys[b].scale, n // 2))
+            else:
+                vecs.append(B.blb_decode(ctx, dec, level - 1, ys[b].scale, n // 2))
         got = wl.unpack_spatial(vecs, L, d, n // 2)
         assert np.abs(got - X @ W).max() < 2.0 ** -20
         B.blb_plan_destroy(plan)
