@@ -94,6 +94,15 @@ def run_cp(args, B, torch, cplx=False):
     share = torch.empty(g["n_out"] * level * n, dtype=torch.int64, device="cuda")
     torch.cuda.synchronize()
     log(f"cp setup {time.time() - t_setup:.1f}s: plan {g}, library device bytes {B.blb_ctx_device_bytes(ctx) / 1e9:.2f} GB")
+    # plan generation on the device (encoder + plaintext NTTs), timed on a second plan of the same W
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan2 = (B.blb_plan_matmul_cp_cplx if cplx else B.blb_plan_matmul_cp)(ctx, W, L, level)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    B.blb_plan_destroy(plan2)
+    plan_bytes = g["n_out"] * g["G"] * g["n_in"] * g["B"] * (level + 1) * n * 8
+    log(f"plan generation: {plan_bytes / 1e9:.2f} GB in {plan_s * 1e3:.1f} ms ({plan_bytes / plan_s / 1e9:.0f} GB/s)")
 
     def eager_step(k):
         B.blb_matmul_cp(ctx, keys, plan, X_cts, Y_cts)
@@ -176,6 +185,7 @@ def run_cp(args, B, torch, cplx=False):
         "ms_per_step": dt / args.steps * 1e3,
         "n_out_cts": g["n_out"], "plaintexts": n_ai * n_bj,
         "plaintext_bytes": n_ai * n_bj * nl * n * 8,
+        "plan_gen_ms": plan_s * 1e3, "plan_gen_GBps": plan_bytes / plan_s / 1e9,
         "eager_ops_s": args.steps / dt_eager,
         "err": err, "mse": mse,
         "mac_avg_ms": mac_avg_s * 1e3,
@@ -1192,7 +1202,7 @@ def main():
         "packings": {k: None if v is None else {
             "packing": v["packing"], "value": v["value"], "ms_per_step": v["ms_per_step"], "eager_value": v["eager_ops_s"],
             "max_abs_err": v["err"], "output_cts": v["n_out_cts"], "plaintexts": v["plaintexts"],
-            "plaintext_bytes": v["plaintext_bytes"],
+            "plaintext_bytes": v["plaintext_bytes"], "plan_gen_ms": v["plan_gen_ms"], "plan_gen_GBps": v["plan_gen_GBps"],
             "mac_alg_bytes_per_op": v["mac_alg_bytes"], "mac_avg_ms": v["mac_avg_ms"],
             "roofline": {"bound": "hbm", "achieved": v["mac_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                          "frac": v["mac_gbps"] / HBM_PEAK_GBPS, "traffic": mac_traffic(v["mac_variant"], k == "complex"),

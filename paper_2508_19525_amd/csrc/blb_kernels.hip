@@ -662,11 +662,12 @@ struct EncSrcCp {
 // k = k1 + M1 k2:
 //   Y[k1 + M1 k2] = sum_n2 e^(-2 pi i n2 k2 / M2) [ e^(-2 pi i n2 k1 / M) sum_n1 v[M2 n1 + n2] e^(-2 pi i n1 k1 / M1) ].
 // The column pass does the inner M1-point DFTs and the twiddles (Z[k1][n2]), the row pass the
-// outer M2-point DFTs.  Both run in LDS, so the transform makes two passes over HBM.
+// outer M2-point DFTs, so the transform makes two passes over HBM.  Each small DFT is split once
+// more into radix-8 DFTs held in registers (M1 = 8 R2 with R2 = 2, 4 or 8; M2 = 8 x 16), with one
+// exchange through LDS in between.
 constexpr int kEncM2 = 128;
-constexpr int kEncCB = 8;     // columns (n2) per workgroup in the column pass
-constexpr int kEncRB = 4;     // rows (k1) per workgroup in the row pass
-constexpr int kEncM1Max = 64;  // M <= 8192
+constexpr int kEncCB = 16;     // columns (n2) per workgroup in the column pass
+constexpr int kEncRB = 8;      // rows (k1) per workgroup in the row pass
 
 // e^(-2 pi i e / M), 0 <= e < M, from the table of eta^k = e^(2 pi i k / M), k < M/2
 __device__ __forceinline__ cdd enc_twiddle(const double* tw, int e, int M) {
@@ -680,61 +681,124 @@ __device__ __forceinline__ cdd enc_twiddle(const double* tw, int e, int M) {
   return w;
 }
 
-// radix-2 Stockham DFT (forward sign) of nv length-L vectors in LDS (vector v at a + v L),
-// with b as the second buffer; every work-item of the block takes part.  Returns the buffer
-// that holds the result.
-__device__ cdd* lds_dft(cdd* a, cdd* b, int L, int nv, const double* tw, int M) {
-  for (int ns = 1; ns < L; ns *= 2) {
-    __syncthreads();
-    for (int t = threadIdx.x; t < nv * (L / 2); t += blockDim.x) {
-      const int v = t / (L / 2), jj = t % (L / 2);
-      const int kpos = jj % ns;
-      const cdd w = enc_twiddle(tw, kpos * (M / (2 * ns)), M);  // e^(-2 pi i kpos / (2 ns))
-      const cdd x0 = a[v * L + jj];
-      const cdd x1 = cdd_mul(a[v * L + jj + L / 2], w);
-      const int idx = (jj / ns) * 2 * ns + kpos;
-      b[v * L + idx] = cdd_add(x0, x1);
-      b[v * L + idx + ns] = cdd_sub(x0, x1);
+// x (-i)
+__device__ __forceinline__ cdd cdd_mul_mi(cdd a) { return cdd{a.im, dd_neg(a.re)}; }
+
+// In-place DFT (forward sign) of R = 2, 4 or 8 values in natural order, decimation in frequency:
+// stage spans R/2 .. 1, twiddles e^(-2 pi i j / span*2) (1, -i and w8 = e^(-i pi / 4)), then the
+// bit-reversed results put back in natural order.
+template <int R>
+__device__ __forceinline__ void dft_small(cdd (&a)[R], cdd w8) {
+#pragma unroll
+  for (int span = R / 2; span >= 1; span /= 2) {
+#pragma unroll
+    for (int b = 0; b < R; b += 2 * span) {
+#pragma unroll
+      for (int j = 0; j < span; ++j) {
+        const cdd x = a[b + j], y = a[b + j + span];
+        a[b + j] = cdd_add(x, y);
+        cdd d = cdd_sub(x, y);
+        // twiddle e^(-2 pi i j / (2 span)) = w8^(j * 4 / span)
+        const int e8 = j * (4 / span);  // in units of 1/8 turn: 0..3
+        if (e8 & 1) d = cdd_mul(d, w8);
+        if (e8 & 2) d = cdd_mul_mi(d);
+        a[b + j + span] = d;
+      }
     }
-    cdd* t = a;
-    a = b;
-    b = t;
   }
-  __syncthreads();
-  return a;
+  cdd t[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    int r = 0;
+#pragma unroll
+    for (int bit = 1; bit < R; bit <<= 1) r = (r << 1) | ((k & bit) ? 1 : 0);
+    t[r] = a[k];
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) a[k] = t[k];
 }
 
-// column pass: kEncCB columns n2 of complex vector p; writes Z[p][k1][n2] (rows of M2)
-template <class Src>
-__global__ __launch_bounds__(256) void k_enc_cols(Src src, double* zbuf, const double* tw, int M, int M1) {
-  __shared__ cdd sa[kEncM1Max * kEncCB], sb[kEncM1Max * kEncCB];
+// Column pass: kEncCB columns n2 of complex vector p; writes Z[p][k1][n2] (rows of M2).
+// M1 = 8 R2: n1 = na + R2 nb, k1 = kb + 8 ka,
+//   X[kb + 8 ka] = sum_na e^(-2 pi i na ka / R2) e^(-2 pi i na kb / M1) DFT8_nb(x[na + R2 nb])[kb].
+// Step 1 (work-item (c, na), na < R2): the DFT8 over nb and its twiddle, into LDS S[kb][na][c];
+// step 2 (work-item (c, kb)): the DFT of size R2 over na, the four-step twiddle, the store.
+template <class Src, int R2>
+__global__ __launch_bounds__(kEncCB * 8) void k_enc_cols(Src src, double* zbuf, const double* tw, int M) {
+  constexpr int M1 = 8 * R2;
+  __shared__ cdd S[8 * R2 * kEncCB];
   const int n2_0 = blockIdx.x * kEncCB;
   const int p = blockIdx.y;
+  const int t = threadIdx.x;
+  const int c = t % kEncCB, q = t / kEncCB;  // q: na in step 1, kb in step 2
+  const cdd w8 = enc_twiddle(tw, M / 8, M);
   const auto ctx = src.begin(p);
-  for (int t = threadIdx.x; t < M1 * kEncCB; t += blockDim.x) {
-    const int n1 = t / kEncCB, cc = t % kEncCB;
-    sa[cc * M1 + n1] = src(ctx, kEncM2 * n1 + n2_0 + cc);
+  if (q < R2) {
+    cdd a[8];
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb) a[nb] = src(ctx, kEncM2 * (q + R2 * nb) + n2_0 + c);
+    dft_small<8>(a, w8);
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) {
+      const cdd v = kb == 0 || q == 0 ? a[kb] : cdd_mul(a[kb], enc_twiddle(tw, q * kb * (M / M1), M));
+      S[(kb * R2 + q) * kEncCB + c] = v;
+    }
   }
-  const cdd* r = lds_dft(sa, sb, M1, kEncCB, tw, M);
-  for (int t = threadIdx.x; t < M1 * kEncCB; t += blockDim.x) {
-    const int k1 = t / kEncCB, cc = t % kEncCB;
-    const int n2 = n2_0 + cc;
-    const cdd z = cdd_mul(r[cc * M1 + k1], enc_twiddle(tw, n2 * k1, M));  // n2 k1 < M2 M1 = M
+  __syncthreads();
+  cdd b[R2];
+#pragma unroll
+  for (int na = 0; na < R2; ++na) b[na] = S[(q * R2 + na) * kEncCB + c];
+  dft_small<R2>(b, w8);
+  const int n2 = n2_0 + c;
+#pragma unroll
+  for (int ka = 0; ka < R2; ++ka) {
+    const int k1 = q + 8 * ka;
+    const cdd z = cdd_mul(b[ka], enc_twiddle(tw, n2 * k1, M));  // n2 k1 < M2 M1 = M
     st_cdd(zbuf + ((size_t)p * M + (size_t)k1 * kEncM2 + n2) * 4, z);
   }
 }
 
-// row pass: kEncRB rows k1 of vector p; writes Y[p][k1 + M1 k2]
-__global__ __launch_bounds__(256) void k_enc_rows(const double* zbuf, double* ybuf, const double* tw, int M, int M1) {
-  __shared__ cdd sa[kEncRB * kEncM2], sb[kEncRB * kEncM2];
+// Row pass: kEncRB rows k1 of vector p; writes Y[p][k1 + M1 k2].  M2 = 128: n2 = na + 16 nb,
+// k2 = kb + 8 ka (na, ka < 16; nb, kb < 8),
+//   X[kb + 8 ka] = DFT16_na(s_kb)[ka],  s_kb[na] = e^(-2 pi i na kb / 128) DFT8_nb(x[na + 16 nb])[kb].
+// Step 1 (work-item (na, r)): the DFT8 over nb and its twiddle, into LDS; step 2 (work-item
+// (r, kb, h)): the first decimation-in-frequency stage of the DFT16 (h = 0: s[n] + s[n + 8] for the
+// even ka; h = 1: (s[n] - s[n + 8]) e^(-2 pi i n / 16) for the odd ka), then a DFT8.
+constexpr int kEncRowPad = kEncRB + 1;  // LDS row stride (in cdd) of S[kb][na][r]
+__global__ __launch_bounds__(kEncRB * 16) void k_enc_rows(const double* zbuf, double* ybuf, const double* tw, int M, int M1) {
+  __shared__ cdd S[8 * 16 * kEncRowPad];
   const int k1_0 = blockIdx.x * kEncRB;
   const int p = blockIdx.y;
-  for (int t = threadIdx.x; t < kEncRB * kEncM2; t += blockDim.x)
-    sa[t] = ld_cdd(zbuf + ((size_t)p * M + (size_t)k1_0 * kEncM2 + t) * 4);
-  const cdd* r = lds_dft(sa, sb, kEncM2, kEncRB, tw, M);
-  for (int t = threadIdx.x; t < kEncRB * kEncM2; t += blockDim.x) {
-    const int k2 = t / kEncRB, rr = t % kEncRB;
-    st_cdd(ybuf + ((size_t)p * M + k1_0 + rr + (size_t)M1 * k2) * 4, r[rr * kEncM2 + k2]);
+  const int t = threadIdx.x;
+  const cdd w8 = enc_twiddle(tw, M / 8, M);
+  {
+    const int na = t % 16, r = t / 16;
+    const double* row = zbuf + ((size_t)p * M + (size_t)(k1_0 + r) * kEncM2) * 4;
+    cdd a[8];
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb) a[nb] = ld_cdd(row + (size_t)(na + 16 * nb) * 4);
+    dft_small<8>(a, w8);
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) {
+      const cdd v = kb == 0 || na == 0 ? a[kb] : cdd_mul(a[kb], enc_twiddle(tw, na * kb * (M / kEncM2), M));
+      S[(kb * 16 + na) * kEncRowPad + r] = v;
+    }
+  }
+  __syncthreads();
+  const int r = t % kEncRB, q = t / kEncRB;
+  const int kb = q % 8, h = q / 8;
+  cdd b[8];
+#pragma unroll
+  for (int n = 0; n < 8; ++n) {
+    const cdd s0 = S[(kb * 16 + n) * kEncRowPad + r], s8 = S[(kb * 16 + n + 8) * kEncRowPad + r];
+    b[n] = h == 0 ? cdd_add(s0, s8) : (n == 0 ? cdd_sub(s0, s8) : cdd_mul(cdd_sub(s0, s8), enc_twiddle(tw, n * (M / 16), M)));
+  }
+  dft_small<8>(b, w8);
+  const int k1 = k1_0 + r;
+#pragma unroll
+  for (int kp = 0; kp < 8; ++kp) {
+    const int k2 = kb + 8 * (2 * kp + h);
+    st_cdd(ybuf + ((size_t)p * M + k1 + (size_t)M1 * k2) * 4, b[kp]);
   }
 }
 
@@ -813,10 +877,13 @@ template <class Src>
 int encode_with(blb_ctx* c, const Src& src, int count, double* bufA, double* bufB, double scale, int nl, uint64_t* out, int* d_overflow,
                 bool paired) {
   const int M = c->n / 2, M1 = M / kEncM2;
-  if (M1 < kEncRB || M1 > kEncM1Max) return BLB_EINVAL;
+  if (M1 != 16 && M1 != 32 && M1 != 64) return BLB_EINVAL;  // M1 = 8 R2, R2 = 2, 4, 8; M1 >= kEncRB
   const int n_vec = paired ? (count + 1) / 2 : count;  // complex vectors transformed
-  k_enc_cols<<<dim3(kEncM2 / kEncCB, n_vec), 256, 0, c->stream>>>(src, bufB, c->d_enc_tw, M, M1);
-  k_enc_rows<<<dim3(M1 / kEncRB, n_vec), 256, 0, c->stream>>>(bufB, bufA, c->d_enc_tw, M, M1);
+  const dim3 gc(kEncM2 / kEncCB, n_vec);
+  if (M1 == 64) k_enc_cols<Src, 8><<<gc, kEncCB * 8, 0, c->stream>>>(src, bufB, c->d_enc_tw, M);
+  else if (M1 == 32) k_enc_cols<Src, 4><<<gc, kEncCB * 8, 0, c->stream>>>(src, bufB, c->d_enc_tw, M);
+  else k_enc_cols<Src, 2><<<gc, kEncCB * 8, 0, c->stream>>>(src, bufB, c->d_enc_tw, M);
+  k_enc_rows<<<dim3(M1 / kEncRB, n_vec), kEncRB * 16, 0, c->stream>>>(bufB, bufA, c->d_enc_tw, M, M1);
   dim3 grid((M + 255) / 256, n_vec);
   if (paired)
     k_enc_final_pair<<<grid, 256, 0, c->stream>>>(bufA, c->d_enc_twist, scale / (double)M, M, nl, c->mt, c->d_mods, out, count, d_overflow);
