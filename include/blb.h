@@ -391,6 +391,11 @@ int blb_exec_create_cc(blb_ctx* ctx, const blb_keys* keys, const blb_plan* plan,
 int blb_exec_create_batch_cp(blb_ctx* ctx, const blb_cp_instance* inst, int n_inst, int mask_target_level, uint64_t* share_dev,
                              blb_exec** out);
 int blb_exec_run(blb_exec* exec, uint64_t mask_seed);
+/* The same replay on `stream` (a hipStream_t; null = the context stream).  Executors own their
+ * scratch, so replays of different executors (with different output buffers) may run at once
+ * on different streams and overlap on the device; replays of one executor must stay ordered
+ * (one stream, or synchronised by the caller), since they share its scratch. */
+int blb_exec_run_stream(blb_exec* exec, uint64_t mask_seed, void* stream);
 uint64_t blb_exec_device_bytes(const blb_exec* exec);
 void blb_exec_destroy(blb_exec* exec);
 

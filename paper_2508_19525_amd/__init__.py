@@ -111,6 +111,7 @@ _SIGS = {
     "blb_exec_create_cc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(blb_ct), C.POINTER(blb_ct), C.c_int,
                                      C.POINTER(blb_ct), C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
     "blb_exec_run": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "blb_exec_run_stream": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p]),
     "blb_batch_matmul_cp": (C.c_int, [C.c_void_p, C.POINTER(blb_cp_instance), C.c_int]),
     "blb_server_create": (C.c_int, [C.c_void_p, C.POINTER(blb_server_config), C.POINTER(C.c_void_p)]),
     "blb_server_add_weights": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int]),
@@ -568,6 +569,11 @@ def blb_exec_create_batch_cp(ctx, instances, mask_target_level=-1, share_dev=Non
 
 def blb_exec_run(ex, mask_seed=0):
     _check(lib().blb_exec_run(ex.h if isinstance(ex, Exec) else ex, mask_seed), "blb_exec_run")
+
+
+def blb_exec_run_stream(ex, mask_seed, stream):
+    """replay on a given hipStream_t (int handle, e.g. torch.cuda.Stream().cuda_stream)"""
+    _check(lib().blb_exec_run_stream(ex.h if isinstance(ex, Exec) else ex, mask_seed, stream), "blb_exec_run_stream")
 
 
 def blb_exec_device_bytes(ex):

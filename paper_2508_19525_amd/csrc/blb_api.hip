@@ -2855,11 +2855,17 @@ int blb_exec_create_cc(blb_ctx* c, const blb_keys* K, const blb_plan* P, const b
   return BLB_OK;
 }
 
-int blb_exec_run(blb_exec* E, uint64_t mask_seed) {
+int blb_exec_run(blb_exec* E, uint64_t mask_seed) { return blb_exec_run_stream(E, mask_seed, nullptr); }
+
+int blb_exec_run_stream(blb_exec* E, uint64_t mask_seed, void* stream) {
   if (!E || !E->exec) return BLB_EINVAL;
   blb_ctx* c = E->c;
+  const hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+  const hipStream_t saved = c->stream;
+  c->stream = s;  // the seed write goes on the replay's stream, ahead of it
   if (E->has_mask) launch_set_u64(c, E->rec.param, mask_seed);
-  return hipGraphLaunch(E->exec, c->stream) == hipSuccess ? BLB_OK : BLB_EDEVICE;
+  c->stream = saved;
+  return hipGraphLaunch(E->exec, s) == hipSuccess ? BLB_OK : BLB_EDEVICE;
 }
 
 uint64_t blb_exec_device_bytes(const blb_exec* E) { return E ? E->arena_bytes + E->blob_bytes + 256 : 0; }

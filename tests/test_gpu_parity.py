@@ -453,6 +453,35 @@ def test_exec_cp_replays_match_eager(c2s):
     B.blb_exec_destroy(ex)
 
 
+def test_exec_two_executors_on_two_streams(c2s):
+    """Two executors of one plan (own scratch, own outputs) replayed alternately on two streams
+    overlap on the device; every output equals an eager run with the same mask seed."""
+    B = c2s.B
+    L, d_in, d_out, level = 64, 96, 64, 2
+    r = _cp_case(c2s, L, d_in, d_out, level, 78, x_std=1.0)
+    n_out = r["g"]["n_out"]
+    Ys = [[c2s.ct(level - 1) for _ in range(n_out)] for _ in range(2)]
+    shares = [torch.zeros(n_out * level * c2s.n, dtype=torch.int64, device="cuda") for _ in range(2)]
+    exs = [B.blb_exec_create_cp(c2s.h, r["keys_g"], r["plan"], _xcts(c2s, r, level), Ys[e], level - 1, shares[e]) for e in range(2)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    last = {}
+    for k in range(7):
+        last[k % 2] = 900 + k
+        B.blb_exec_run_stream(exs[k % 2], last[k % 2], streams[k % 2].cuda_stream)
+    torch.cuda.synchronize()
+    for e in range(2):
+        Ye = [c2s.ct(level - 1) for _ in range(n_out)]
+        she = torch.zeros_like(shares[e])
+        B.blb_matmul_cp(c2s.h, r["keys_g"], r["plan"], _xcts(c2s, r, level), Ye)
+        B.blb_mask_to_share(c2s.h, Ye, last[e], level - 1, she)
+        torch.cuda.synchronize()
+        for b in range(n_out):
+            assert np.array_equal(c2s.export(Ys[e][b]), c2s.export(Ye[b])), f"executor {e} output {b}"
+        assert np.array_equal(shares[e].cpu().numpy(), she.cpu().numpy()), f"executor {e} share"
+    for ex in exs:
+        B.blb_exec_destroy(ex)
+
+
 def _xcts(c, r, level):
     if "_xc" not in r:
         xs = []
