@@ -101,7 +101,7 @@ def run_cp(args, B, torch, cplx=False):
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     B.blb_plan_destroy(plan2)
-    plan_bytes = g["n_out"] * g["G"] * g["n_in"] * g["B"] * (level + 1) * n * 8
+    plan_bytes = g["n_out"] * g["G"] * g["n_in"] * g["B"] * (level + 1) * n * 25 // 4
     log(f"plan generation: {plan_bytes / 1e9:.2f} GB in {plan_s * 1e3:.1f} ms ({plan_bytes / plan_s / 1e9:.0f} GB/s)")
 
     def eager_step(k):
@@ -218,7 +218,9 @@ def run_cp(args, B, torch, cplx=False):
 
     nl = level + 1
     n_ai, n_bj = g["n_in"] * g["B"], g["n_out"] * g["G"]
-    mac_alg_bytes = (n_ai * n_bj * nl * n + n_ai * 2 * nl * n + n_bj * 2 * nl * n) * 8
+    # plaintexts in 50 bits per word (25 N / 4 bytes per limb-poly), rotated inputs read and
+    # inner sums written as 64-bit words
+    mac_alg_bytes = n_ai * n_bj * nl * n * 25 // 4 + (n_ai * 2 * nl * n + n_bj * 2 * nl * n) * 8
     mac_avg_s = mac_ms / 1e3 / max(mac_n, 1)
     res = {
         "packing": "complex slots (2 column blocks per output ciphertext)" if cplx else "real slots",
@@ -227,7 +229,7 @@ def run_cp(args, B, torch, cplx=False):
         "two_stream_value": args.steps / dt2, "two_stream_ms_per_step": dt2 / args.steps * 1e3,
         "two_stream_outputs_match_eager": bool(pipe_ok),
         "n_out_cts": g["n_out"], "plaintexts": n_ai * n_bj,
-        "plaintext_bytes": n_ai * n_bj * nl * n * 8,
+        "plaintext_bytes": n_ai * n_bj * nl * n * 25 // 4,
         "plan_gen_ms": plan_s * 1e3, "plan_gen_GBps": plan_bytes / plan_s / 1e9,
         "eager_ops_s": args.steps / dt_eager,
         "err": err, "mse": mse,
@@ -631,7 +633,8 @@ def run_qk_fused(args, B, torch):
     log(f"fused QK: eager {steps / dt_eager:.1f}/s, graph {steps / dt:.1f}/s")
     # the W_Q / W_K MACs stream n_out G x n_in B plaintexts of (level + 1) limbs each, plus inputs and inner sums
     nl = level + 1
-    mac_bytes = 8 * nl * n * (g["n_out"] * g["G"] * g["n_in"] * g["B"] + 2 * g["n_in"] * g["B"] + 2 * g["n_out"] * g["G"])
+    mac_bytes = (nl * n * g["n_out"] * g["G"] * g["n_in"] * g["B"] * 25 // 4  # plaintexts, 50 bits per word
+                 + 8 * nl * n * (2 * g["n_in"] * g["B"] + 2 * g["n_out"] * g["G"]))
     res = {"value": steps / dt, "eager": steps / dt_eager, "ms": dt / steps * 1e3, "err": err, "split_ms": split,
            "ntt_gbps": ntt_polys * 16 * n / (ntt_ms / 1e3) / 1e9 if ntt_ms > 0 else 0.0,
            "mac_gbps": mac_bytes * mac_launches / (mac_ms / 1e3) / 1e9 if mac_ms > 0 else 0.0, "mac_variant": mac_var,

@@ -1379,7 +1379,7 @@ int cp_check_keys(const blb_ctx* c, const blb_keys* K, int L, int d_in, int d_ou
 size_t cp_plan_bytes(const blb_ctx* c, int L, int d_in, int d_out, int level, int cplx) {
   const CpGeom g = cp_geometry(c, L, d_in, d_out);
   const int n_out = cplx ? (g.n_out + 1) / 2 : g.n_out;
-  return (size_t)n_out * g.G * g.n_in * g.B * (level + 1) * c->n * 8;
+  return (size_t)n_out * g.G * g.n_in * g.B * (level + 1) * pt50_bytes(c->n);
 }
 
 // matmul_cp plan; the plaintexts go to `mem` (cp_plan_bytes bytes, caller-owned) when given,
@@ -1427,7 +1427,7 @@ int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int 
   P->kind = 1;
   P->level = level;
   P->g = g;
-  P->bytes = n_pt * nl * n * 8;
+  P->bytes = n_pt * nl * pt50_bytes(n);
   int rc = BLB_OK;
   if (mem) {
     P->pt = mem;
@@ -1443,6 +1443,7 @@ int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int 
     const double* dW = W_dev;
     double* a = tmp.get<double>((size_t)chunk * M * 4);
     double* b = tmp.get<double>((size_t)chunk * M * 4);
+    uint64_t* raw = tmp.get<uint64_t>((size_t)chunk * nl * n);  // a chunk of plaintexts before packing
     if (!dW) {
       double* w = tmp.get<double>((size_t)d_in * d_out);
       if (w && hipMemcpyAsync(w, W, (size_t)d_in * d_out * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
@@ -1467,9 +1468,12 @@ int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int 
     const double scale = (double)c->mod[level] / BLB_NOISE_BOOST;
     for (size_t p0 = 0; p0 < n_pt; p0 += chunk) {
       const int cnt = (int)std::min<size_t>(chunk, n_pt - p0);
-      uint64_t* dst = P->pt + p0 * nl * n;
-      run_encode_cp(c, dW, g, (int)p0, cnt, a, b, scale, nl, dst, c->d_flag, dg);
-      ntt_regular(c, dst, (size_t)cnt * nl, nl, true);
+      run_encode_cp(c, dW, g, (int)p0, cnt, a, b, scale, nl, raw, c->d_flag, dg);
+      {
+        Span sp(c, BLB_T_NTT, (double)cnt * nl);
+        c->counters[1] += (int64_t)cnt * nl;
+        launch_ntt_pack50(c, raw, (uint8_t*)P->pt + p0 * nl * pt50_bytes(n), cnt * nl, nl);
+      }
     }
     if (flag_host) {
       if (hipMemcpyAsync(flag_host, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess) {
@@ -1611,7 +1615,7 @@ int blb_matmul_cp(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct
     if (!rx_dev) return BLB_EDEVICE;
     Span sp(c, BLB_T_CP_MAC, (double)n_bj * nl * n);
     c->counters[2] += (int64_t)n_ai * n_bj;
-    c->counters[7] += (int64_t)n_ai * n_bj * nl * n * 8;
+    c->counters[7] += (int64_t)n_ai * n_bj * nl * (int64_t)pt50_bytes(n);
     launch_cp_mac(c, P->pt, rx_dev, inner, nl, n_ai, n_bj, c->mac_variant);
   }
   // giant steps
@@ -3000,7 +3004,7 @@ int blb_batch_matmul_cp(blb_ctx* c, const blb_cp_instance* inst, int n_inst) {
       mg.n_inst = (int)members[gi].size();
       groups.push_back(mg);
       c->counters[2] += (int64_t)n_ai * n_bj * mg.n_inst;
-      c->counters[7] += (int64_t)n_ai * n_bj * nl * n * 8 * ((mg.n_inst + ib - 1) / ib);
+      c->counters[7] += (int64_t)n_ai * n_bj * nl * (int64_t)pt50_bytes(n) * ((mg.n_inst + ib - 1) / ib);
       const int n_kb = n / (256 * cpt);
       const int lg = c->batch_limbs > 0 ? std::min(c->batch_limbs, nl) : nl;  // limbs per work item
       for (int i0 = 0; i0 < mg.n_inst; i0 += ib)

@@ -110,8 +110,14 @@ struct CcTerm {
 };
 
 // batched matmul_cp MAC
+// Plaintexts of a ct-pt plan are held in 50 bits per word (every prime of the chain is below
+// 2^50): a limb-poly of N words is stored as its low 32 bits (N x u32), the next 16 (N x u16)
+// and the top 2 (N/16 x u32; word k at bits 2 (k mod 16) of u32 k / 16), 25N/4 bytes against
+// 8N.  The MAC streams these planes; they are rebuilt into doubles in registers.
+__host__ __device__ constexpr size_t pt50_bytes(int n) { return (size_t)n * 25 / 4; }
+
 struct MacGroup {
-  const uint64_t* pt;           // plan plaintexts [(b, j)][(a, i)][limb][N]
+  const uint64_t* pt;           // plan plaintexts [(b, j)][(a, i)][limb] packed limb-polys (pt50_bytes each)
   const uint64_t* const* rx;    // [instance][n_ai] rotated inputs ([2][nl][N] each)
   uint64_t* const* inner;       // [instance] -> [n_bj][2][nl][N]
   int n_ai, n_bj, nl, n_inst;
@@ -335,6 +341,9 @@ void launch_sum_cts(blb_ctx* c, const uint64_t* const* srcs, uint64_t* const* ds
 void launch_mask_pair(blb_ctx* c, const CcPair* pairs_dev, int n_pairs, int nl);
 int batch_mac_shape(int variant, int* tb, int* ib, int* cpt);
 void launch_cp_mac_batch(blb_ctx* c, const MacGroup* groups, const MacItem* items, int n_items, int variant, int grid);
+// forward NTT of count limb-polys stored back to back at base ([item][nl][N]); the results go
+// to out in the 50-bit plan format (base is left as it was)
+void launch_ntt_pack50(blb_ctx* c, const uint64_t* base, uint8_t* out, int count, int nl);
 void launch_sum_var(blb_ctx* c, const uint64_t* const* srcs, const int* off, uint64_t* const* dsts, int n_out, int nl);
 // out[t] ([2][nl][N]) = k * (the first nl limbs of each poly of in[t], stored with nl_in >= nl limbs)
 void launch_scale_cts(blb_ctx* c, const uint64_t* const* in, uint64_t* out, int count, int nl, double k, int nl_in = 0);

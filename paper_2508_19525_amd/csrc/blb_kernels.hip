@@ -328,18 +328,73 @@ void launch_moddown_conv(blb_ctx* c, const uint64_t* U, uint64_t* Corr, const Ks
 // exactly once; RX tiles are re-read per output tile (L2 / MALL resident).
 // ---------------------------------------------------------------------------------------
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// Words k .. k + CPT - 1 (k even when CPT = 2) of a plan limb-poly in the 50-bit format at p,
+// fetched raw (nontemporal: the plan stream is read once per call) and rebuilt as doubles:
+// 2^52 + w has the high word 0x43300000 | w >> 32 and the low word w & 0xFFFFFFFF.
+template <int CPT>
+struct Pt50Raw {
+  uint32_t lo[CPT];
+  uint32_t mid[(CPT + 1) / 2];  // bits 32..47 of two words per u32 (the even word in the low half)
+  uint32_t top;
+};
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <int CPT>
+__device__ __forceinline__ void pt50_fetch(const uint8_t* __restrict__ p, int n, int k, Pt50Raw<CPT>& r) {
+  const uint32_t* lo = (const uint32_t*)p;
+  const uint16_t* mid = (const uint16_t*)(p + (size_t)4 * n);
+  const uint32_t* top = (const uint32_t*)(p + (size_t)6 * n);
+  if constexpr (CPT == 4) {
+    const u32x4 l = __builtin_nontemporal_load((const u32x4*)(lo + k));
+    r.lo[0] = l.x;
+    r.lo[1] = l.y;
+    r.lo[2] = l.z;
+    r.lo[3] = l.w;
+    const u32x2 m = __builtin_nontemporal_load((const u32x2*)(mid + k));
+    r.mid[0] = m.x;
+    r.mid[1] = m.y;
+  } else if constexpr (CPT == 2) {
+    const u32x2 l = __builtin_nontemporal_load((const u32x2*)(lo + k));
+    r.lo[0] = l.x;
+    r.lo[1] = l.y;
+    r.mid[0] = __builtin_nontemporal_load((const uint32_t*)(mid + k));
+  } else {
+    r.lo[0] = __builtin_nontemporal_load(lo + k);
+    r.mid[0] = __builtin_nontemporal_load(mid + k);
+  }
+  r.top = __builtin_nontemporal_load(top + (k >> 4));
+}
+__device__ __forceinline__ double pt50_make(uint32_t lo, uint32_t mid16, uint32_t top2) {
+  return __hiloint2double((int)(0x43300000u | (top2 << 16) | mid16), (int)lo) - BLB_TWO52;
+}
+template <int CPT>
+__device__ __forceinline__ void pt50_cvt(const Pt50Raw<CPT>& r, int k, double (&v)[CPT]) {
+  const uint32_t t = r.top >> (2 * (k & 15));
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) v[j] = pt50_make(r.lo[j], (j & 1) ? r.mid[j / 2] >> 16 : r.mid[j / 2] & 0xFFFFu, (t >> (2 * j)) & 3u);
+}
+
 
 // One block's (tile, k-chunk, limb): sums over the n_ai rotated inputs of plaintext x input,
 // for `rows` output rows of the tile (FULL: rows == TB, no per-row guards).
 template <int TB, int CPT, int UNR, bool FULL>
-__device__ __forceinline__ void cp_mac_tile(const uint64_t* __restrict__ pbase, const uint64_t* const* __restrict__ rx_tab,
-                                            size_t pt_stride_bj, int n, int nl, int n_ai, int limb, int k0, int rows, double q, double qi,
-                                            double (&a0)[TB][CPT], double (&a1)[TB][CPT]) {
+__device__ __forceinline__ void cp_mac_tile(const uint8_t* __restrict__ pbase, const uint64_t* const* __restrict__ rx_tab,
+                                            size_t pt_stride_bj, size_t pt_stride_ai, int n, int nl, int n_ai, int limb, int k0, int rows,
+                                            double q, double qi, double (&a0)[TB][CPT], double (&a1)[TB][CPT]) {
+  auto load_pt = [&](const uint8_t* poly, double (&v)[CPT]) {
+    Pt50Raw<CPT> r;
+    pt50_fetch<CPT>(poly, n, k0, r);
+    pt50_cvt<CPT>(r, k0, v);
+  };
   auto load2 = [&](const uint64_t* a, double (&v)[CPT], bool stream) {
-    if (CPT == 2) {
-      const u64x2 w = stream ? __builtin_nontemporal_load((const u64x2*)a) : *(const u64x2*)a;
-      v[0] = u2d(w.x);
-      v[CPT - 1] = u2d(w.y);
+    if constexpr (CPT >= 2) {
+#pragma unroll
+      for (int h = 0; h < CPT; h += 2) {
+        const u64x2 w = stream ? __builtin_nontemporal_load((const u64x2*)(a + h)) : *(const u64x2*)(a + h);
+        v[h] = u2d(w.x);
+        v[h + 1] = u2d(w.y);
+      }
     } else {
       v[0] = u2d(stream ? __builtin_nontemporal_load(a) : *a);
     }
@@ -363,7 +418,7 @@ __device__ __forceinline__ void cp_mac_tile(const uint64_t* __restrict__ pbase, 
     for (int u = 0; u < UNR; ++u)
 #pragma unroll
       for (int t = 0; t < TB; ++t)
-        if (FULL || t < rows) load2(pbase + (size_t)t * pt_stride_bj + (size_t)(ai + u) * nl * n, w[u][t], true);
+        if (FULL || t < rows) load_pt(pbase + (size_t)t * pt_stride_bj + (size_t)(ai + u) * pt_stride_ai, w[u][t]);
 #pragma unroll
     for (int u = 0; u < UNR; ++u)
 #pragma unroll
@@ -386,7 +441,7 @@ __device__ __forceinline__ void cp_mac_tile(const uint64_t* __restrict__ pbase, 
     for (int t = 0; t < TB; ++t)
       if (FULL || t < rows) {
         double w[CPT];
-        load2(pbase + (size_t)t * pt_stride_bj + (size_t)ai * nl * n, w, true);
+        load_pt(pbase + (size_t)t * pt_stride_bj + (size_t)ai * pt_stride_ai, w);
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
           a0[t][c] += mulmod_s(w[c], x0[c], q, qi);
@@ -403,7 +458,7 @@ template <int TB, int CPT, int UNR, bool SPLIT>
 __global__ __launch_bounds__(256) void k_cp_mac(const uint64_t* __restrict__ pt, const uint64_t* const* __restrict__ rx_tab,
                                                 uint64_t* __restrict__ inner, int n, int nl, int n_ai, int n_bj, ModTable mt, int n_kblk,
                                                 int n_tiles) {
-  static_assert(CPT == 1 || CPT == 2, "coefficients per thread");
+  static_assert(CPT == 1 || CPT == 2 || CPT == 4, "coefficients per thread");
   static_assert(UNR == 1 || UNR == 2, "unroll of the input loop");
   // XCD-aware block mapping: blocks that share a (k-chunk, limb) land on the same XCD, so
   // the rotated inputs they all read stay in that XCD's L2
@@ -426,10 +481,12 @@ __global__ __launch_bounds__(256) void k_cp_mac(const uint64_t* __restrict__ pt,
   for (int t = 0; t < TB; ++t)
 #pragma unroll
     for (int c = 0; c < CPT; ++c) { a0[t][c] = 0.0; a1[t][c] = 0.0; }
-  const size_t pt_stride_bj = (size_t)n_ai * nl * n;
-  const uint64_t* pbase = pt + (size_t)bj0 * pt_stride_bj + (size_t)limb * n + k0;
-  if (SPLIT && rows == TB) cp_mac_tile<TB, CPT, UNR, true>(pbase, rx_tab, pt_stride_bj, n, nl, n_ai, limb, k0, rows, q, qi, a0, a1);
-  else cp_mac_tile<TB, CPT, UNR, false>(pbase, rx_tab, pt_stride_bj, n, nl, n_ai, limb, k0, rows, q, qi, a0, a1);
+  const size_t pb = pt50_bytes(n);
+  const size_t pt_stride_ai = (size_t)nl * pb, pt_stride_bj = (size_t)n_ai * pt_stride_ai;
+  const uint8_t* pbase = (const uint8_t*)pt + (size_t)bj0 * pt_stride_bj + (size_t)limb * pb;
+  if (SPLIT && rows == TB)
+    cp_mac_tile<TB, CPT, UNR, true>(pbase, rx_tab, pt_stride_bj, pt_stride_ai, n, nl, n_ai, limb, k0, rows, q, qi, a0, a1);
+  else cp_mac_tile<TB, CPT, UNR, false>(pbase, rx_tab, pt_stride_bj, pt_stride_ai, n, nl, n_ai, limb, k0, rows, q, qi, a0, a1);
 #pragma unroll
   for (int t = 0; t < TB; ++t) {
     if (t < rows) {
@@ -449,7 +506,7 @@ __global__ __launch_bounds__(256) void k_cp_mac(const uint64_t* __restrict__ pt,
 void launch_cp_mac(blb_ctx* c, const uint64_t* pt, const uint64_t* const* rx_tab, uint64_t* inner, int nl, int n_ai, int n_bj, int variant) {
   struct Shape { int tb, cpt; };
   static const Shape shapes[BLB_MAC_VARIANTS] = {{8, 2}, {8, 1}, {16, 2}, {4, 2}, {12, 2}, {2, 2}, {4, 2}, {2, 2}, {4, 1}, {4, 1},
-                                                 {4, 2}, {4, 2}, {8, 1}, {4, 1}};
+                                                 {4, 2}, {4, 2}, {8, 1}, {4, 1}, {2, 4}, {4, 4}, {2, 4}, {4, 4}};
   const Shape sh = shapes[(variant >= 0 && variant < BLB_MAC_VARIANTS) ? variant : 0];
   const int n_kblk = c->n / (256 * sh.cpt);
   const int n_tiles = (n_bj + sh.tb - 1) / sh.tb;
@@ -470,6 +527,10 @@ void launch_cp_mac(blb_ctx* c, const uint64_t* pt, const uint64_t* const* rx_tab
     case 11: CPMAC(4, 2, 1, true); break;
     case 12: CPMAC(8, 1, 1, true); break;
     case 13: CPMAC(4, 1, 2, true); break;
+    case 14: CPMAC(2, 4, 1, false); break;
+    case 15: CPMAC(4, 4, 1, false); break;
+    case 16: CPMAC(2, 4, 1, true); break;
+    case 17: CPMAC(4, 4, 1, true); break;
     default: CPMAC(8, 2, 1, false); break;
   }
 #undef CPMAC
@@ -1009,19 +1070,19 @@ __global__ __launch_bounds__(256) void k_cp_mac_batch(const MacGroup* __restrict
     const double q = me.q, qi = me.qinv;
     const int bj0 = item.tile * TB;
     const int ninst = min(IB, gr.n_inst - item.inst0);
-    const size_t term = (size_t)nl * n;  // words per (bj, ai) plaintext
-    const gu64c* pt[TB];
+    const size_t pb = pt50_bytes(n);
+    const size_t term = (size_t)nl * pb;  // bytes per (bj, ai) plaintext
+    const uint8_t* pt[TB];
 #pragma unroll
-    for (int t = 0; t < TB; ++t) pt[t] = (const gu64c*)(gr.pt + (size_t)min(bj0 + t, n_bj - 1) * n_ai * term + (size_t)limb * n + k0);
+    for (int t = 0; t < TB; ++t) pt[t] = (const uint8_t*)gr.pt + (size_t)min(bj0 + t, n_bj - 1) * n_ai * term + (size_t)limb * pb;
     const ku64* rxtab[IB];  // row of rotated-input pointers of each instance
 #pragma unroll
     for (int u = 0; u < IB; ++u) rxtab[u] = (const ku64*)(gr.rx + (size_t)(item.inst0 + min(u, ninst - 1)) * n_ai);
-    uint64_t rw[TB][CPT], rx0[IB][CPT], rx1[IB][CPT];  // raw words of the term in flight
+    Pt50Raw<CPT> rw[TB];
+    uint64_t rx0[IB][CPT], rx1[IB][CPT];  // raw words of the term in flight
     auto fetch = [&](int ai) {
 #pragma unroll
-      for (int t = 0; t < TB; ++t)
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) rw[t][c] = __builtin_nontemporal_load(pt[t] + (size_t)ai * term + c);
+      for (int t = 0; t < TB; ++t) pt50_fetch<CPT>(pt[t] + (size_t)ai * term, n, k0, rw[t]);
 #pragma unroll
       for (int u = 0; u < IB; ++u) {
         const gu64c* x = (const gu64c*)rxtab[u][ai];
@@ -1043,9 +1104,7 @@ __global__ __launch_bounds__(256) void k_cp_mac_batch(const MacGroup* __restrict
     for (int ai = 0; ai < n_ai; ++ai) {
       double w[TB][CPT], x0[IB][CPT], x1[IB][CPT];
 #pragma unroll
-      for (int t = 0; t < TB; ++t)
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) w[t][c] = u2d(rw[t][c]);
+      for (int t = 0; t < TB; ++t) pt50_cvt<CPT>(rw[t], k0, w[t]);
 #pragma unroll
       for (int u = 0; u < IB; ++u)
 #pragma unroll

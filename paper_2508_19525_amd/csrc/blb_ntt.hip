@@ -272,6 +272,17 @@ __device__ __forceinline__ void ntt_load(double (&x)[PT], const PolyDesc& d, con
 template <int LOGN, int PT, bool FWD, class StoreOp>
 __device__ __forceinline__ void ntt_store(double (&x)[PT], const PolyDesc& d, const StoreOp& st, double q, double qi, double ninv, int tid,
                                           double* lds) {
+  if constexpr (StoreOp::kPack) {  // the epilogue takes all of a work-item's results at once
+    int j[PT];
+    double v[PT];
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+      j[i] = LastPass<LOGN, PT, FWD>::idx(tid, i);
+      v[i] = FWD ? canon(x[i], q) : canon_full(mulmod_s(x[i], ninv, q, qi), q, qi);
+    }
+    st.template put_all<LOGN, PT>(d, j, v, lds, tid);
+    return;
+  }
   st.template prepare<PT>(d, lds, tid);  // the epilogue may stage an operand in LDS (free after the last pass)
   // Every operand load of the epilogue is issued before the first store: vector-memory
   // completion is tracked in issue order, so a load issued after a store could only be
@@ -422,6 +433,7 @@ struct LdPlain {
 // polynomial that no longer fits 128 VGPRs, so it always runs one polynomial per workgroup.
 struct StPlain {
   static constexpr bool kPersistent = true;
+  static constexpr bool kPack = false;
   struct Operand {};
   template <int PT>
   __device__ void prepare(const PolyDesc&, double*, int) const {}
@@ -443,6 +455,7 @@ struct LdCentredLift {
 // rescale epilogue: dst[j] <- (c_i[j] - v) * q_l^-1 mod q_i, c_i = d.src2, aux2 = q_l^-1 mod q_i
 struct StRescale {
   static constexpr bool kPersistent = true;
+  static constexpr bool kPack = false;
   using Operand = uint64_t;
   template <int PT>
   __device__ void prepare(const PolyDesc&, double*, int) const {}
@@ -458,6 +471,7 @@ struct StRescale {
 // epilogue's global loads to one word per output.
 struct StModDown {
   static constexpr bool kPersistent = false;
+  static constexpr bool kPack = false;
   using Operand = uint64_t;
   template <int PT>
   __device__ void prepare(const PolyDesc& d, double* lds, int tid) const {
@@ -482,9 +496,56 @@ struct StModDown {
   }
 };
 
+// Plan epilogue: canonical results of a regular batch written in the 50-bit plan format (low
+// 32 bits, next 16, top 2 in u32 words of 16; see pt50_bytes) at out + (poly index) x
+// pt50_bytes(N), the poly index recovered from the batch's source address.  The top-bit codes
+// are gathered in LDS (free after the last pass), then each u32 of 16 codes written once.
+struct StPack50 {
+  static constexpr bool kPersistent = false;
+  static constexpr bool kPack = true;
+  struct Operand {};
+  const uint64_t* base;  // source of the regular batch (poly p at base + p N)
+  uint8_t* out;          // packed destination of poly 0
+  template <int LOGN, int PT>
+  __device__ void put_all(const PolyDesc& d, const int (&j)[PT], const double (&v)[PT], double* lds, int tid) const {
+    constexpr int N = 1 << LOGN, T = N / PT;
+    const size_t p = (size_t)(d.src - base) >> LOGN;
+    uint8_t* o = out + p * pt50_bytes(N);
+    uint32_t* lo = (uint32_t*)o;
+    uint16_t* mid = (uint16_t*)(o + (size_t)4 * N);
+    uint32_t* top = (uint32_t*)(o + (size_t)6 * N);
+    uint8_t* codes = (uint8_t*)lds;
+    lds_barrier();  // every work-item is past its reads of the last exchange
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+      const uint64_t w = d2u(v[i]);
+      lo[j[i]] = (uint32_t)w;
+      mid[j[i]] = (uint16_t)(w >> 32);
+      codes[j[i]] = (uint8_t)((w >> 48) & 3u);
+    }
+    lds_barrier();
+    for (int t = tid; t < N / 16; t += T) {
+      const uint32_t* c4 = (const uint32_t*)(codes + 16 * t);
+      uint32_t word = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const uint32_t x = c4[b];  // codes of words 4b .. 4b + 3, one per byte
+        const uint32_t c = (x & 3u) | ((x >> 6) & 0xCu) | ((x >> 12) & 0x30u) | ((x >> 18) & 0xC0u);
+        word |= c << (8 * b);
+      }
+      top[t] = word;
+    }
+  }
+  template <int PT>
+  __device__ void prepare(const PolyDesc&, double*, int) const {}
+  __device__ Operand fetch(const PolyDesc&, int) const { return {}; }
+  __device__ void put(const PolyDesc&, int, double, Operand, double, double, const double*) const {}
+};
+
 // add-into epilogue: dst[j] <- src2[j] + v mod q  (mask added to c0 in evaluation form)
 struct StAddTo {
   static constexpr bool kPersistent = true;
+  static constexpr bool kPack = false;
   using Operand = uint64_t;
   template <int PT>
   __device__ void prepare(const PolyDesc&, double*, int) const {}
@@ -514,4 +575,8 @@ void launch_ntt_regular(blb_ctx* c, uint64_t* base, int count, int nl, bool fwd)
   const NttSrc src{nullptr, base, nl, c->log_n};
   if (fwd) launch_ntt_generic<true>(c, src, count, LdPlain{}, StPlain{});
   else launch_ntt_generic<false>(c, src, count, LdPlain{}, StPlain{});
+}
+void launch_ntt_pack50(blb_ctx* c, const uint64_t* base, uint8_t* out, int count, int nl) {
+  const NttSrc src{nullptr, (uint64_t*)base, nl, c->log_n};
+  launch_ntt_generic<true>(c, src, count, LdPlain{}, StPack50{base, out});
 }

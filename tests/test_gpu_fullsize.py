@@ -83,7 +83,7 @@ def test_bert_base_matmul_cp_full_size(B, orc, cplx):
         assert cnt["ct_pt_products"] == 24 * n_y * 32  # 18432 real, 9216 complex
         assert cnt["modup_sources"] == 24 + n_y * 3
         assert cnt["rescaled_cts"] == n_y
-        assert cnt["plaintext_bytes"] == 24 * n_y * 32 * 3 * n * 8
+        assert cnt["plaintext_bytes"] == 24 * n_y * 32 * 3 * n * 25 // 4  # 50 bits per plaintext word
         samples = [0, 7] if cplx else [0, 17]
         want = keys_o.matmul_cp(xw, level, W, L, outputs=samples, cplx=cplx)
         for b in samples:
