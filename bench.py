@@ -35,15 +35,16 @@ CC_SCHEDULE = 1
 # FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch), each scaled by what the counter reads for a
 # plain 1 GiB copy (FETCH_SIZE x 1.99981, WRITE_SIZE x 1.0).  Valid only for the MAC source text
 # with this hash; any later change of that code reports traffic as null until re-measured.
-MAC_TRAFFIC_SRC_SHA256 = "0bbdaa4037a560f21b464eb00dc9e8562491c2bae7a0f7048babf1af5db2bc15"
-MAC_TRAFFIC_BYTES = {0: 3772255748, 1: 3759417293, 2: 3775985761, 3: 3774165864, 4: 3742168526, 5: 3780224342, 6: 3787542265,
-                     7: 3787866206, 8: 3748317708, 9: 3746432573, 10: 3864620077, 11: 3813634323, 12: 3800206758, 13: 3807150531}
+MAC_TRAFFIC_SRC_SHA256 = "291795c9dce0e08cec6b4a8ff70cc7871b225458b08440084033b0a86a4c7f8c"
+MAC_TRAFFIC_BYTES = {0: 3051766735, 1: 3182436416, 2: 3012240490, 3: 3093134223, 4: 3032768502, 5: 3097390843,
+                     6: 3037755463, 7: 3079915980, 8: 3213799622, 9: 3197911468, 10: 3084746599, 11: 3141257736,
+                     12: 3351833313, 13: 3220502132, 14: 3037617450, 15: 3013527493, 16: 3046027660, 17: 3031372198}
 
 
 # The same for the complex-slot output packing of that operator (12 output ciphertexts, half the plaintexts).
-MAC_TRAFFIC_BYTES_CPLX = {0: 1919314763, 1: 1914374364, 2: 1906886435, 3: 1918009261, 4: 1908545797, 5: 1958441900,
-                          6: 1919435771, 7: 1963228559, 8: 1908226553, 9: 1907899886, 10: 1980373854, 11: 1958646126,
-                          12: 1925662902, 13: 1950605759}
+MAC_TRAFFIC_BYTES_CPLX = {0: 1533501665, 1: 1607550181, 2: 1526534604, 3: 1554538045, 4: 1527815890, 5: 1566708451,
+                          6: 1551615954, 7: 1567909190, 8: 1615494173, 9: 1601480955, 10: 1573079558, 11: 1576279218,
+                          12: 1660405490, 13: 1618441477, 14: 1538475614, 15: 1530825354, 16: 1572645722, 17: 1533168726}
 
 
 def mac_traffic(variant, cplx=False):
