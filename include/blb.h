@@ -106,7 +106,7 @@ enum { BLB_KNOB_MAC_VARIANT = 0, BLB_KNOB_BATCH_VARIANT = 1, BLB_KNOB_BATCH_GRID
  * share a key and Galois element, up to 16 per thread, which reads each key word once for all of
  * them, where the launch keeps about 8192 workgroups busy that way (else one output per thread);
  * 2: always grouped) */
-enum { BLB_MAC_VARIANTS = 18, BLB_BATCH_VARIANTS = 7 };
+enum { BLB_MAC_VARIANTS = 18, BLB_BATCH_VARIANTS = 9 };
 int blb_ctx_set_knob(blb_ctx* ctx, int knob, int value);
 int blb_ctx_get_knob(const blb_ctx* ctx, int knob);
 

@@ -1157,6 +1157,8 @@ int batch_mac_shape(int variant, int* tb, int* ib, int* cpt) {
     case 4: *tb = 8; *ib = 2; *cpt = 1; break;
     case 5: *tb = 8; *ib = 4; *cpt = 1; break;
     case 6: *tb = 4; *ib = 8; *cpt = 1; break;
+    case 7: *tb = 4; *ib = 4; *cpt = 2; break;
+    case 8: *tb = 8; *ib = 2; *cpt = 2; break;
     default: *tb = 4; *ib = 2; *cpt = 2; break;
   }
   return 0;
@@ -1170,10 +1172,12 @@ void launch_cp_mac_batch(blb_ctx* c, const MacGroup* groups, const MacItem* item
 #define MB(a, b, d) k_cp_mac_batch<a, b, d><<<blocks, 256, 0, c->stream>>>(groups, items, n_items, c->n, c->mt)
   if (tb == 4 && ib == 1) MB(4, 1, 2);
   else if (tb == 2 && ib == 4) MB(2, 4, 2);
-  else if (tb == 4 && ib == 4) MB(4, 4, 1);
-  else if (tb == 8 && ib == 2) MB(8, 2, 1);
+  else if (tb == 4 && ib == 4 && cpt == 1) MB(4, 4, 1);
+  else if (tb == 8 && ib == 2 && cpt == 1) MB(8, 2, 1);
   else if (tb == 8 && ib == 4) MB(8, 4, 1);
   else if (tb == 4 && ib == 8) MB(4, 8, 1);
+  else if (tb == 4 && ib == 4) MB(4, 4, 2);
+  else if (tb == 8 && ib == 2) MB(8, 2, 2);
   else MB(4, 2, 2);
 #undef MB
 }

@@ -102,8 +102,8 @@ def test_batched_equals_per_instance(env):
     # knobs never change bits: MAC shape, persistent grid, limbs per work item
     for var in range(B.BLB_BATCH_VARIANTS):
         B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_VARIANT, var)
-        B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_GRID, [7, 256, 2048, 100000, 13, 1024, 300][var])
-        B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_LIMBS, [1, 2, 0, 3, 1, 0, 2][var])
+        B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_GRID, [7, 256, 2048, 100000, 13, 1024, 300, 64, 4096][var])
+        B.blb_ctx_set_knob(ctx, B.BLB_KNOB_BATCH_LIMBS, [1, 2, 0, 3, 1, 0, 2, 1, 0][var])
         B.blb_batch_matmul_cp(ctx, arr)
         torch.cuda.synchronize()
         for k, I in enumerate(inst):
