@@ -31,38 +31,47 @@ HBM_PEAK_GBPS = 8000.0
 # ct-ct schedule of the attention legs: 1 = BSGS (Appendix "BSGS Optimization"), 0 = plain
 CC_SCHEDULE = 1
 
-# HBM bytes per k_cp_mac launch on the BERT-base workload, by launch variant: rocprofv3 --pmc
-# FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch), each scaled by what the counter reads for a
-# plain 1 GiB copy (FETCH_SIZE x 1.99981, WRITE_SIZE x 1.0).  Valid only for the MAC source text
-# with this hash; any later change of that code reports traffic as null until re-measured.
-MAC_TRAFFIC_SRC_SHA256 = "291795c9dce0e08cec6b4a8ff70cc7871b225458b08440084033b0a86a4c7f8c"
-MAC_TRAFFIC_BYTES = {0: 3051766735, 1: 3182436416, 2: 3012240490, 3: 3093134223, 4: 3032768502, 5: 3097390843,
-                     6: 3037755463, 7: 3079915980, 8: 3213799622, 9: 3197911468, 10: 3084746599, 11: 3141257736,
-                     12: 3351833313, 13: 3220502132, 14: 3037617450, 15: 3013527493, 16: 3046027660, 17: 3031372198}
+# HBM bytes per k_cp_mac launch on the BERT-base workload, by plan format, output packing and
+# launch variant: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch), each scaled
+# by what the counter reads for a plain 1 GiB copy (FETCH_SIZE x 1.99989, WRITE_SIZE x 1.0).  Valid
+# only for the MAC source text with this hash; any later change of that code reports traffic as
+# null until re-measured.
+MAC_TRAFFIC_SRC_SHA256 = "1e42f92ab536cc80d6e07df8769fb6a035e107cab34937e7b8db233a22982207"
+MAC_TRAFFIC_BYTES = {  # (plan format, packing) -> {variant: bytes}
+    (0, "real"): {0: 3768779709, 1: 3751307162, 2: 3759680789, 3: 3774058990, 4: 3740322696, 5: 3780387927,
+                  6: 3785686655, 7: 3785295169, 8: 3745393129, 9: 3745599197, 10: 3861145693, 11: 3873134377,
+                  12: 3796503664, 13: 3804649251, 14: 3775367882, 15: 3823505741, 16: 3854702870, 17: 3811205598},
+    (0, "complex"): {0: 1918583374, 1: 1915172154, 2: 1906668571, 3: 1918574244, 4: 1907601767, 5: 1959353162,
+                     6: 1919383755, 7: 1963524150, 8: 1908657963, 9: 1909102482, 10: 1981949301, 11: 1960196250,
+                     12: 1927604773, 13: 1950562534, 14: 1979127018, 15: 1931899825, 16: 1987405504, 17: 1960896157},
+    (1, "real"): {0: 3050191150, 1: 3180946029, 2: 3010826510, 3: 3093002337, 4: 3030554971, 5: 3097697068,
+                  6: 3037469097, 7: 3079037559, 8: 3216070568, 9: 3198908276, 10: 3084738618, 11: 3142644411,
+                  12: 3351003728, 13: 3220368522, 14: 3037514706, 15: 3013275395, 16: 3045668399, 17: 3031510267},
+}
 
 
-# The same for the complex-slot output packing of that operator (12 output ciphertexts, half the plaintexts).
-MAC_TRAFFIC_BYTES_CPLX = {0: 1533501665, 1: 1607550181, 2: 1526534604, 3: 1554538045, 4: 1527815890, 5: 1566708451,
-                          6: 1551615954, 7: 1567909190, 8: 1615494173, 9: 1601480955, 10: 1573079558, 11: 1576279218,
-                          12: 1660405490, 13: 1618441477, 14: 1538475614, 15: 1530825354, 16: 1572645722, 17: 1533168726}
-
-
-def mac_traffic(variant, cplx=False):
+def mac_traffic(variant, cplx=False, fmt=0):
     import hashlib
     src = open(os.path.join(ROOT, "paper_2508_19525_amd", "csrc", "blb_kernels.hip")).read()
     a, b = src.find("// One block's (tile, k-chunk, limb)"), src.find("// out[o] = sum_t src[o * n_terms + t]")
     if a < 0 or b < 0 or hashlib.sha256(src[a:b].encode()).hexdigest() != MAC_TRAFFIC_SRC_SHA256:
         return None
-    return (MAC_TRAFFIC_BYTES_CPLX if cplx else MAC_TRAFFIC_BYTES).get(variant)
+    return MAC_TRAFFIC_BYTES.get((fmt, "complex" if cplx else "real"), {}).get(variant)
+
+
+def plan_poly_bytes(n, fmt):
+    """bytes of one plaintext limb-poly: 64-bit words, or 50-bit words in three planes"""
+    return n * 25 // 4 if fmt else n * 8
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_cp(args, B, torch, cplx=False):
+def run_cp(args, B, torch, cplx=False, fmt=0, light=False):
     """The headline fused linear operator; with cplx the complex-slot output packing (output
-    ciphertext b holds column blocks 2b and 2b + 1 in the real and imaginary parts)"""
+    ciphertext b holds column blocks 2b and 2b + 1 in the real and imaginary parts); fmt: the
+    plan's plaintext format (0: 64-bit words, 1: 50-bit); light: without the two-stream replay"""
     from paper_2508_19525_amd import workloads as wl
 
     cfg = wl.C2
@@ -73,6 +82,7 @@ def run_cp(args, B, torch, cplx=False):
     W = wl.weights(2, d_in, d_out, cfg["w_std"])
     stream = torch.cuda.current_stream().cuda_stream
     ctx = B.blb_ctx_create(p.log_n, p.n_q, p.n_special, p.dnum, 0, stream)
+    B.blb_ctx_set_knob(ctx, B.BLB_KNOB_PLAN_FORMAT, fmt)
     t_setup = time.time()
     plan = (B.blb_plan_matmul_cp_cplx if cplx else B.blb_plan_matmul_cp)(ctx, W, L, level)
     g = B.blb_plan_info(plan)
@@ -102,7 +112,7 @@ def run_cp(args, B, torch, cplx=False):
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     B.blb_plan_destroy(plan2)
-    plan_bytes = g["n_out"] * g["G"] * g["n_in"] * g["B"] * (level + 1) * n * 25 // 4
+    plan_bytes = g["n_out"] * g["G"] * g["n_in"] * g["B"] * (level + 1) * plan_poly_bytes(n, fmt)
     log(f"plan generation: {plan_bytes / 1e9:.2f} GB in {plan_s * 1e3:.1f} ms ({plan_bytes / plan_s / 1e9:.0f} GB/s)")
 
     def eager_step(k):
@@ -176,8 +186,59 @@ def run_cp(args, B, torch, cplx=False):
     dt = time.perf_counter() - t0
     log(f"graph: {args.steps} steps in {dt:.3f}s ({B.blb_exec_device_bytes(ex) / 1e9:.2f} GB executor memory)")
 
-    # two executors (own scratch and outputs) replayed alternately on two streams: consecutive
-    # operators overlap, one's key switching (FP64-bound) beside the other's MAC (HBM-bound)
+    if light:
+        dt2, pipe_ok = None, None
+    else:
+        dt2, pipe_ok = two_stream(args, B, torch, ctx, keys, plan, g, X_cts, Y_cts, share, ex, keep, n, level)
+
+    nl = level + 1
+    n_ai, n_bj = g["n_in"] * g["B"], g["n_out"] * g["G"]
+    # plaintexts (8 N or 25 N / 4 bytes per limb-poly) read, rotated inputs read and inner sums
+    # written as 64-bit words
+    mac_alg_bytes = n_ai * n_bj * nl * plan_poly_bytes(n, fmt) + (n_ai * 2 * nl * n + n_bj * 2 * nl * n) * 8
+    mac_avg_s = mac_ms / 1e3 / max(mac_n, 1)
+    res = {
+        "packing": "complex slots (2 column blocks per output ciphertext)" if cplx else "real slots",
+        "plan_format": "50-bit" if fmt else "64-bit words", "fmt": fmt, "cplx": cplx,
+        "value": args.steps / dt,
+        "ms_per_step": dt / args.steps * 1e3,
+        "two_stream_value": None if light else args.steps / dt2,
+        "two_stream_ms_per_step": None if light else dt2 / args.steps * 1e3,
+        "two_stream_outputs_match_eager": pipe_ok,
+        "n_out_cts": g["n_out"], "plaintexts": n_ai * n_bj,
+        "plaintext_bytes": n_ai * n_bj * nl * plan_poly_bytes(n, fmt),
+        "plan_gen_ms": plan_s * 1e3, "plan_gen_GBps": plan_bytes / plan_s / 1e9,
+        "eager_ops_s": args.steps / dt_eager,
+        "err": err, "mse": mse,
+        "mac_avg_ms": mac_avg_s * 1e3,
+        "mac_gbps": mac_alg_bytes / mac_avg_s / 1e9,
+        "mac_alg_bytes": mac_alg_bytes,
+        "ntt_gbps": ntt_polys * 16 * n / (ntt_ms / 1e3) / 1e9 if ntt_ms > 0 else 0.0,
+        "ntt_polys_per_step": ntt_polys / args.steps,
+        "ntt_launches_per_step": ntt_n / args.steps,
+        "split": split,
+        "mac_variant": B.blb_ctx_get_knob(ctx, B.BLB_KNOB_MAC_VARIANT),
+        "mac_tune_ms": tune,
+    }
+    if args.copy_probe and not light:
+        # plain copy of 1 GiB: the reference point for the FETCH_SIZE / WRITE_SIZE counters
+        a = torch.empty(1 << 27, dtype=torch.int64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+    B.blb_exec_destroy(ex)
+    B.blb_plan_destroy(plan)
+    B.blb_keys_destroy(keys)
+    B.blb_ctx_destroy(ctx)
+    return res
+
+
+def two_stream(args, B, torch, ctx, keys, plan, g, X_cts, Y_cts, share, ex, keep, n, level):
+    """Two executors (own scratch and outputs) replayed alternately on two streams: consecutive
+    operators overlap, one's key switching (FP64-bound) beside the other's MAC (HBM-bound).
+    Returns the wall time of args.steps replays and whether each executor's last replay equals an
+    eager run with the same mask seed, word for word."""
+    from paper_2508_19525_amd import workloads as wl
     Y2 = []
     for b in range(g["n_out"]):
         ct, t = B.new_ct(n, level - 1)
@@ -216,45 +277,7 @@ def run_cp(args, B, torch, cplx=False):
         pipe_ok &= all(np.array_equal(a, B.blb_export(ctx, y, n)) for a, y in zip(got, Ye)) and np.array_equal(got_sh, she.cpu().numpy())
     log(f"graph, two executors on two streams: {args.steps} steps in {dt2:.3f}s, outputs match eager: {pipe_ok}")
     B.blb_exec_destroy(ex2)
-
-    nl = level + 1
-    n_ai, n_bj = g["n_in"] * g["B"], g["n_out"] * g["G"]
-    # plaintexts in 50 bits per word (25 N / 4 bytes per limb-poly), rotated inputs read and
-    # inner sums written as 64-bit words
-    mac_alg_bytes = n_ai * n_bj * nl * n * 25 // 4 + (n_ai * 2 * nl * n + n_bj * 2 * nl * n) * 8
-    mac_avg_s = mac_ms / 1e3 / max(mac_n, 1)
-    res = {
-        "packing": "complex slots (2 column blocks per output ciphertext)" if cplx else "real slots",
-        "value": args.steps / dt,
-        "ms_per_step": dt / args.steps * 1e3,
-        "two_stream_value": args.steps / dt2, "two_stream_ms_per_step": dt2 / args.steps * 1e3,
-        "two_stream_outputs_match_eager": bool(pipe_ok),
-        "n_out_cts": g["n_out"], "plaintexts": n_ai * n_bj,
-        "plaintext_bytes": n_ai * n_bj * nl * n * 25 // 4,
-        "plan_gen_ms": plan_s * 1e3, "plan_gen_GBps": plan_bytes / plan_s / 1e9,
-        "eager_ops_s": args.steps / dt_eager,
-        "err": err, "mse": mse,
-        "mac_avg_ms": mac_avg_s * 1e3,
-        "mac_gbps": mac_alg_bytes / mac_avg_s / 1e9,
-        "mac_alg_bytes": mac_alg_bytes,
-        "ntt_gbps": ntt_polys * 16 * n / (ntt_ms / 1e3) / 1e9 if ntt_ms > 0 else 0.0,
-        "ntt_polys_per_step": ntt_polys / args.steps,
-        "ntt_launches_per_step": ntt_n / args.steps,
-        "split": split,
-        "mac_variant": B.blb_ctx_get_knob(ctx, B.BLB_KNOB_MAC_VARIANT),
-        "mac_tune_ms": tune,
-    }
-    if args.copy_probe:
-        # plain copy of 1 GiB: the reference point for the FETCH_SIZE / WRITE_SIZE counters
-        a = torch.empty(1 << 27, dtype=torch.int64, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-    B.blb_exec_destroy(ex)
-    B.blb_plan_destroy(plan)
-    B.blb_keys_destroy(keys)
-    B.blb_ctx_destroy(ctx)
-    return res
+    return dt2, bool(pipe_ok)
 
 
 def run_cc(args, B, torch, schedule=1):
@@ -634,7 +657,7 @@ def run_qk_fused(args, B, torch):
     log(f"fused QK: eager {steps / dt_eager:.1f}/s, graph {steps / dt:.1f}/s")
     # the W_Q / W_K MACs stream n_out G x n_in B plaintexts of (level + 1) limbs each, plus inputs and inner sums
     nl = level + 1
-    mac_bytes = (nl * n * g["n_out"] * g["G"] * g["n_in"] * g["B"] * 25 // 4  # plaintexts, 50 bits per word
+    mac_bytes = (nl * g["n_out"] * g["G"] * g["n_in"] * g["B"] * plan_poly_bytes(n, 0)  # plaintexts (64-bit words)
                  + 8 * nl * n * (2 * g["n_in"] * g["B"] + 2 * g["n_out"] * g["G"]))
     res = {"value": steps / dt, "eager": steps / dt_eager, "ms": dt / steps * 1e3, "err": err, "split_ms": split,
            "ntt_gbps": ntt_polys * 16 * n / (ntt_ms / 1e3) / 1e9 if ntt_ms > 0 else 0.0,
@@ -888,7 +911,7 @@ def run_batch(args, B, torch):
     t_graph = (time.perf_counter() - t0) / reps
     same &= all(bool(torch.equal(a, b)) for I in insts for a, b in zip(I["Yt"], I["Y2t"]))
     log(f"batch: unbatched {t_unb * 1e3:.1f} ms, batched {t_bat * 1e3:.1f} ms, graph {t_graph * 1e3:.1f} ms, identical {same}")
-    res = {"instances": len(insts), "plans": len(plans), "modmul_per_batch": modmul,
+    res = {"instances": len(insts), "plans": len(plans), "plan_format": "64-bit words", "modmul_per_batch": modmul,
            "decoded_check": {"instance": k_max, "L": L_m, "D": D_m, "max_abs_err": dec_err, "tolerance": 2.0 ** -20},
            "unbatched_ms": t_unb * 1e3, "batched_ms": t_bat * 1e3, "graph_ms": t_graph * 1e3,
            "speedup_graph_vs_unbatched": t_unb / t_graph, "speedup_batched_vs_unbatched": t_unb / t_bat,
@@ -958,6 +981,7 @@ def run_serving(args, B, torch, packing="complex", steady_rate=0.0, sat_rate=0.0
 
     def serve(policy, max_batch, n_streams, rate=None):
         stretch = 1.0 if rate is None else args.serve_rate / rate  # same request sequence, other offered rate
+        B.blb_ctx_set_knob(ctx, B.BLB_KNOB_PLAN_FORMAT, args.serve_plan_format)  # the server's plans take it
         srv = B.blb_server_create(ctx, int(args.serve_cache_gb * 1e9), max_batch=max_batch, max_queue=100000, n_streams=n_streams,
                                   policy=policy, max_wait_ms=args.serve_max_wait_ms)
         try:
@@ -1173,6 +1197,9 @@ def main():
     ap.add_argument("--no-small-ops", action="store_true", help="skip the rotate-and-sum / share-addition measurement")
     ap.add_argument("--no-tune", action="store_true", help="skip the MAC launch-shape autotuner")
     ap.add_argument("--no-cplx", action="store_true", help="skip the complex-slot packing measurement")
+    ap.add_argument("--no-p50", action="store_true", help="skip the measurement with plans in the 50-bit format")
+    ap.add_argument("--serve-plan-format", type=int, default=1, choices=(0, 1),
+                    help="plaintext format of the served plans (0: 64-bit words, 1: 50-bit)")
     ap.add_argument("--mac-variant", type=int, default=None, help="use this MAC launch shape instead of autotuning")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
@@ -1207,6 +1234,7 @@ def main():
         return
     r = run_cp(args, B, torch)
     rcx = None if args.no_cplx else run_cp(args, B, torch, cplx=True)
+    rp50 = None if args.no_p50 else run_cp(args, B, torch, fmt=1, light=True)
     nt = None if args.no_ntt else run_ntt(args, B, torch)
     cc_by = {} if args.no_cc else {s: run_cc(args, B, torch, s) for s in (1, 0)}
     cc = cc_by.get(1)
@@ -1242,7 +1270,7 @@ def main():
             "global_batch": 1, "seq_len": 128, "parallelism": "none (1 GPU)"},
         "roofline": {
             "bound": "hbm", "achieved": r["mac_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": r["mac_gbps"] / HBM_PEAK_GBPS, "traffic": mac_traffic(r["mac_variant"]),
+            "frac": r["mac_gbps"] / HBM_PEAK_GBPS, "traffic": mac_traffic(r["mac_variant"], r["cplx"], r["fmt"]),
             "kernel": "k_cp_mac (plaintext-streaming ct-pt MAC)",
             "alg_bytes_per_launch": r["mac_alg_bytes"], "avg_launch_ms": r["mac_avg_ms"]},
         "eager_value": r["eager_ops_s"],
@@ -1252,9 +1280,19 @@ def main():
             "plaintext_bytes": v["plaintext_bytes"], "plan_gen_ms": v["plan_gen_ms"], "plan_gen_GBps": v["plan_gen_GBps"],
             "mac_alg_bytes_per_op": v["mac_alg_bytes"], "mac_avg_ms": v["mac_avg_ms"],
             "roofline": {"bound": "hbm", "achieved": v["mac_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                         "frac": v["mac_gbps"] / HBM_PEAK_GBPS, "traffic": mac_traffic(v["mac_variant"], k == "complex"),
+                         "frac": v["mac_gbps"] / HBM_PEAK_GBPS, "traffic": mac_traffic(v["mac_variant"], v["cplx"], v["fmt"]),
                          "kernel": "k_cp_mac", "mac_variant": v["mac_variant"]},
-            "split_ms": v["split"]} for k, v in (("real", r), ("complex", rcx))},
+            "split_ms": v["split"], "two_executors_two_streams": {
+                "value": v["two_stream_value"], "ms_per_step": v["two_stream_ms_per_step"],
+                "outputs_match_eager": v["two_stream_outputs_match_eager"]}} for k, v in (("real", r), ("complex", rcx))},
+        "plan_formats": {k: None if v is None else {
+            "plan_format": v["plan_format"], "value": v["value"], "ms_per_step": v["ms_per_step"], "eager_value": v["eager_ops_s"],
+            "max_abs_err": v["err"], "plan_bytes": v["plaintext_bytes"], "plan_gen_ms": v["plan_gen_ms"],
+            "mac_alg_bytes_per_op": v["mac_alg_bytes"], "mac_avg_ms": v["mac_avg_ms"],
+            "roofline": {"bound": "hbm", "achieved": v["mac_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": v["mac_gbps"] / HBM_PEAK_GBPS, "traffic": mac_traffic(v["mac_variant"], v["cplx"], v["fmt"]),
+                         "kernel": "k_cp_mac", "mac_variant": v["mac_variant"]}}
+            for k, v in (("words64", r), ("p50", rp50))},
         "ntt": {"in_step": {"GBps": r["ntt_gbps"], "frac_hbm_peak": r["ntt_gbps"] / HBM_PEAK_GBPS,
                             "polys_per_step": r["ntt_polys_per_step"], "launches_per_step": r["ntt_launches_per_step"]},
                 "standalone_1GiB": nt,
@@ -1305,7 +1343,8 @@ def main():
                          "768x3072, 3072x768) matmul_cp ops, 50/50 by model, L ~ U{16..512}, N=16384, 4 primes + 2 special; "
                          "cold plan cache, HBM-budget admission, continuous batching; complex-slot output packing "
                          "(real_packing: the same trace with the paper's real-slot packing; saturation: the same "
-                         "trace offered faster than either path serves it)"),
+                         "trace offered faster than either path serves it); plans "
+                         + ("in the 50-bit format" if args.serve_plan_format else "as 64-bit words")),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -95,7 +95,7 @@ int blb_ctx_counters(blb_ctx* ctx, int64_t* out, int reset);
 
 /* ---- launch-shape knobs (never change a result bit; chosen by the autotuner) ------------ */
 enum { BLB_KNOB_MAC_VARIANT = 0, BLB_KNOB_BATCH_VARIANT = 1, BLB_KNOB_BATCH_GRID = 2, BLB_KNOB_NTT_VARIANT = 3, BLB_KNOB_KS_VARIANT = 4,
-       BLB_KNOB_NTT_RADIX = 5, BLB_KNOB_BATCH_LIMBS = 6, BLB_KNOB_KINDS = 7 };
+       BLB_KNOB_NTT_RADIX = 5, BLB_KNOB_BATCH_LIMBS = 6, BLB_KNOB_PLAN_FORMAT = 7, BLB_KNOB_KINDS = 8 };
 /* value ranges: MAC variant 0..BLB_MAC_VARIANTS-1 (outputs per block x coefficients per thread x
  * input-loop unroll x full-tile split), batch variant 0..BLB_BATCH_VARIANTS-1 (outputs x instances x
  * coefficients per thread), batch grid 1..2^20 workgroups, NTT variant 0..1 (one workgroup per
@@ -105,7 +105,12 @@ enum { BLB_KNOB_MAC_VARIANT = 0, BLB_KNOB_BATCH_VARIANT = 1, BLB_KNOB_BATCH_GRID
  * inner-product variant 0..2 (0: one key-switch output per thread; 1: the outputs of a batch that
  * share a key and Galois element, up to 16 per thread, which reads each key word once for all of
  * them, where the launch keeps about 8192 workgroups busy that way (else one output per thread);
- * 2: always grouped) */
+ * 2: always grouped), plan format 0..1 (how matmul_cp plans made afterwards hold their
+ * plaintexts, the same values either way: 0, the default, as 64-bit words, 8N bytes per
+ * limb-poly; 1, every prime being below 2^50, as 50-bit words in three planes, the low 32 bits,
+ * the next 16 and the top 2, 25N/4 bytes per limb-poly: 22% less plan memory and MAC traffic for
+ * some decoding work in the MAC.  A server takes the value the context has when it is created;
+ * one blb_batch_matmul_cp call takes plans of one format, EINVAL otherwise) */
 enum { BLB_MAC_VARIANTS = 18, BLB_BATCH_VARIANTS = 9 };
 int blb_ctx_set_knob(blb_ctx* ctx, int knob, int value);
 int blb_ctx_get_knob(const blb_ctx* ctx, int knob);

@@ -242,7 +242,7 @@ def blb_ctx_reset_timing(ctx):
 
 
 BLB_KNOB_MAC_VARIANT, BLB_KNOB_BATCH_VARIANT, BLB_KNOB_BATCH_GRID, BLB_KNOB_NTT_VARIANT, BLB_KNOB_KS_VARIANT = 0, 1, 2, 3, 4
-BLB_KNOB_NTT_RADIX, BLB_KNOB_BATCH_LIMBS = 5, 6
+BLB_KNOB_NTT_RADIX, BLB_KNOB_BATCH_LIMBS, BLB_KNOB_PLAN_FORMAT = 5, 6, 7
 BLB_MAC_VARIANTS = 18
 BLB_BATCH_VARIANTS = 9
 

@@ -913,6 +913,10 @@ int blb_ctx_set_knob(blb_ctx* c, int knob, int value) {
       if (value < 0 || value > BLB_MAXQ) return BLB_EINVAL;
       c->batch_limbs = value;
       return BLB_OK;
+    case BLB_KNOB_PLAN_FORMAT:
+      if (value < 0 || value > 1) return BLB_EINVAL;
+      c->plan_p50 = value;
+      return BLB_OK;
     default: return BLB_EINVAL;
   }
 }
@@ -926,6 +930,7 @@ int blb_ctx_get_knob(const blb_ctx* c, int knob) {
     case BLB_KNOB_KS_VARIANT: return c->ks_variant;
     case BLB_KNOB_NTT_RADIX: return c->ntt_radix;
     case BLB_KNOB_BATCH_LIMBS: return c->batch_limbs;
+    case BLB_KNOB_PLAN_FORMAT: return c->plan_p50;
     default: return BLB_EINVAL;
   }
 }
@@ -1376,10 +1381,10 @@ int cp_check_keys(const blb_ctx* c, const blb_keys* K, int L, int d_in, int d_ou
   return BLB_OK;
 }
 
-size_t cp_plan_bytes(const blb_ctx* c, int L, int d_in, int d_out, int level, int cplx) {
+size_t cp_plan_bytes(const blb_ctx* c, int L, int d_in, int d_out, int level, int cplx, int p50) {
   const CpGeom g = cp_geometry(c, L, d_in, d_out);
   const int n_out = cplx ? (g.n_out + 1) / 2 : g.n_out;
-  return (size_t)n_out * g.G * g.n_in * g.B * (level + 1) * pt50_bytes(c->n);
+  return (size_t)n_out * g.G * g.n_in * g.B * (level + 1) * pt_poly_bytes(c->n, p50);
 }
 
 // matmul_cp plan; the plaintexts go to `mem` (cp_plan_bytes bytes, caller-owned) when given,
@@ -1387,9 +1392,10 @@ size_t cp_plan_bytes(const blb_ctx* c, int L, int d_in, int d_out, int level, in
 // the encoder's overflow flag lands in *flag_host when the stream reaches it (non-zero: the
 // plan is unusable), and W must stay valid until then.
 int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, uint64_t* mem, blb_plan** out, int* flag_host,
-                   const double* W_dev, int diag_heads, int diag_dv, int cplx) {
+                   const double* W_dev, int diag_heads, int diag_dv, int cplx, int p50) {
   if (!c || (!W && !W_dev) || !out || d_in < 1 || d_out < 1 || L < 1 || L > c->n / 2 || level < 1 || level >= c->n_q) return BLB_EINVAL;
   *out = nullptr;
+  if (p50 < 0) p50 = c->plan_p50;
   // diagonal-packed input: one table entry per input ciphertext (head groups in the order
   // matmul_cc forms them); the geometry is that of a spatial-first input of n_heads d_v' columns
   std::vector<CpDiagIn> dtab;
@@ -1427,7 +1433,8 @@ int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int 
   P->kind = 1;
   P->level = level;
   P->g = g;
-  P->bytes = n_pt * nl * pt50_bytes(n);
+  P->p50 = p50 ? 1 : 0;
+  P->bytes = n_pt * nl * pt_poly_bytes(n, P->p50);
   int rc = BLB_OK;
   if (mem) {
     P->pt = mem;
@@ -1443,7 +1450,8 @@ int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int 
     const double* dW = W_dev;
     double* a = tmp.get<double>((size_t)chunk * M * 4);
     double* b = tmp.get<double>((size_t)chunk * M * 4);
-    uint64_t* raw = tmp.get<uint64_t>((size_t)chunk * nl * n);  // a chunk of plaintexts before packing
+    // 50-bit format: a chunk of plaintexts is encoded here, then transformed and packed into the plan
+    uint64_t* raw = P->p50 ? tmp.get<uint64_t>((size_t)chunk * nl * n) : nullptr;
     if (!dW) {
       double* w = tmp.get<double>((size_t)d_in * d_out);
       if (w && hipMemcpyAsync(w, W, (size_t)d_in * d_out * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
@@ -1468,11 +1476,14 @@ int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int 
     const double scale = (double)c->mod[level] / BLB_NOISE_BOOST;
     for (size_t p0 = 0; p0 < n_pt; p0 += chunk) {
       const int cnt = (int)std::min<size_t>(chunk, n_pt - p0);
-      run_encode_cp(c, dW, g, (int)p0, cnt, a, b, scale, nl, raw, c->d_flag, dg);
-      {
+      uint64_t* dst = P->p50 ? raw : P->pt + p0 * nl * n;
+      run_encode_cp(c, dW, g, (int)p0, cnt, a, b, scale, nl, dst, c->d_flag, dg);
+      if (P->p50) {
         Span sp(c, BLB_T_NTT, (double)cnt * nl);
         c->counters[1] += (int64_t)cnt * nl;
         launch_ntt_pack50(c, raw, (uint8_t*)P->pt + p0 * nl * pt50_bytes(n), cnt * nl, nl);
+      } else {
+        ntt_regular(c, dst, (size_t)cnt * nl, nl, true);
       }
     }
     if (flag_host) {
@@ -1615,8 +1626,8 @@ int blb_matmul_cp(blb_ctx* c, const blb_keys* K, const blb_plan* P, const blb_ct
     if (!rx_dev) return BLB_EDEVICE;
     Span sp(c, BLB_T_CP_MAC, (double)n_bj * nl * n);
     c->counters[2] += (int64_t)n_ai * n_bj;
-    c->counters[7] += (int64_t)n_ai * n_bj * nl * (int64_t)pt50_bytes(n);
-    launch_cp_mac(c, P->pt, rx_dev, inner, nl, n_ai, n_bj, c->mac_variant);
+    c->counters[7] += (int64_t)n_ai * n_bj * nl * (int64_t)pt_poly_bytes(n, P->p50);
+    launch_cp_mac(c, P->pt, rx_dev, inner, nl, n_ai, n_bj, c->mac_variant, P->p50);
   }
   // giant steps
   if (g.G > 1) {
@@ -2903,6 +2914,7 @@ int blb_batch_matmul_cp(blb_ctx* c, const blb_cp_instance* inst, int n_inst) {
     if (!I.keys || !I.plan || !I.X || !I.Y || I.plan->kind != 1) return BLB_EINVAL;
     const CpGeom& g = I.plan->g;
     if (I.plan->level != level) return BLB_ELEVEL;
+    if (I.plan->p50 != inst[0].plan->p50) return BLB_EINVAL;  // one plaintext format per call
     if (I.n_in != g.n_in || I.n_out != g.n_out) return BLB_EINVAL;
     for (int a = 0; a < I.n_in; ++a) {
       if (check_ct(c, &I.X[a]) || I.X[a].degree != 1) return BLB_EINVAL;
@@ -3004,7 +3016,7 @@ int blb_batch_matmul_cp(blb_ctx* c, const blb_cp_instance* inst, int n_inst) {
       mg.n_inst = (int)members[gi].size();
       groups.push_back(mg);
       c->counters[2] += (int64_t)n_ai * n_bj * mg.n_inst;
-      c->counters[7] += (int64_t)n_ai * n_bj * nl * (int64_t)pt50_bytes(n) * ((mg.n_inst + ib - 1) / ib);
+      c->counters[7] += (int64_t)n_ai * n_bj * nl * (int64_t)pt_poly_bytes(n, plans[gi]->p50) * ((mg.n_inst + ib - 1) / ib);
       const int n_kb = n / (256 * cpt);
       const int lg = c->batch_limbs > 0 ? std::min(c->batch_limbs, nl) : nl;  // limbs per work item
       for (int i0 = 0; i0 < mg.n_inst; i0 += ib)
@@ -3018,7 +3030,7 @@ int blb_batch_matmul_cp(blb_ctx* c, const blb_cp_instance* inst, int n_inst) {
     double units = 0;
     for (int i = 0; i < n_inst; ++i) units += (double)inst[i].plan->g.n_out * inst[i].plan->g.G * nl * n;
     Span sp(c, BLB_T_CP_MAC, units);
-    launch_cp_mac_batch(c, g_dev, it_dev, (int)items.size(), c->batch_variant, c->batch_grid);
+    launch_cp_mac_batch(c, g_dev, it_dev, (int)items.size(), c->batch_variant, c->batch_grid, inst[0].plan->p50);
   }
   // giant steps of every instance in one key-switch batch
   srcs.clear();

@@ -110,14 +110,15 @@ struct CcTerm {
 };
 
 // batched matmul_cp MAC
-// Plaintexts of a ct-pt plan are held in 50 bits per word (every prime of the chain is below
-// 2^50): a limb-poly of N words is stored as its low 32 bits (N x u32), the next 16 (N x u16)
-// and the top 2 (N/16 x u32; word k at bits 2 (k mod 16) of u32 k / 16), 25N/4 bytes against
-// 8N.  The MAC streams these planes; they are rebuilt into doubles in registers.
+// Plaintexts of a ct-pt plan are held as 64-bit words (8N bytes per limb-poly) or, in the 50-bit
+// format (every prime of the chain is below 2^50), as the words' low 32 bits (N x u32), the next
+// 16 (N x u16) and the top 2 (N/16 x u32; word k at bits 2 (k mod 16) of u32 k / 16): 25N/4
+// bytes.  The MAC streams either; 50-bit words are rebuilt into doubles in registers.
 __host__ __device__ constexpr size_t pt50_bytes(int n) { return (size_t)n * 25 / 4; }
+__host__ __device__ constexpr size_t pt_poly_bytes(int n, int p50) { return p50 ? pt50_bytes(n) : (size_t)n * 8; }
 
 struct MacGroup {
-  const uint64_t* pt;           // plan plaintexts [(b, j)][(a, i)][limb] packed limb-polys (pt50_bytes each)
+  const uint64_t* pt;           // plan plaintexts [(b, j)][(a, i)][limb] limb-polys (pt_poly_bytes each)
   const uint64_t* const* rx;    // [instance][n_ai] rotated inputs ([2][nl][N] each)
   uint64_t* const* inner;       // [instance] -> [n_bj][2][nl][N]
   int n_ai, n_bj, nl, n_inst;
@@ -242,6 +243,7 @@ struct blb_ctx {
   int batch_variant = 0;          // k_cp_mac_batch shape (autotuned)
   int batch_grid = 2048;          // persistent grid size of k_cp_mac_batch (autotuned)
   int batch_limbs = 1;            // limbs per work item of k_cp_mac_batch, 0 = all (autotuned)
+  int plan_p50 = 0;               // new ct-pt plans in the 50-bit format (else 64-bit words)
   int ntt_variant = 1;            // 0: one workgroup per poly, 1: persistent pipelined (autotuned)
   int ntt_radix = 16;             // values per work-item: 16 (4-stage passes) or 32 (5-stage passes) (autotuned)
   int ks_variant = 1;             // key inner product: 0 per output, 1 grouped by key where the launch
@@ -291,6 +293,7 @@ struct blb_plan {
   int hom1 = 0;  // matmul_cc: step 1 (row pre-rotation of B) runs on the server
   CpGeom g;
   bool owns_pt = true;  // false: pt lives in caller memory (the serving plan arena)
+  int p50 = 0;           // matmul_cp: plaintexts in the 50-bit format
   uint64_t* pt;  // matmul_cp: [(b, j)][(a, i)][limb][N] evaluation-form plaintexts
                  // matmul_cc: [2][T][limb][N] step-2 masks M^lo_t, M^hi_t (level, scale q_level 2^10),
                  // T = L' (plain schedule) or B (BSGS: baby steps only)
@@ -315,9 +318,10 @@ void launch_sample_int(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint6
 int cp_check_keys(const blb_ctx* c, const blb_keys* K, int L, int d_in, int d_out);
 void uploader_forget_stream(blb_ctx* c, hipStream_t s);
 void stack_forget_stream(blb_ctx* c, hipStream_t s);
-size_t cp_plan_bytes(const blb_ctx* c, int L, int d_in, int d_out, int level, int cplx = 0);
+size_t cp_plan_bytes(const blb_ctx* c, int L, int d_in, int d_out, int level, int cplx = 0, int p50 = 0);
+// p50: plaintext format (0: 64-bit words, 1: 50-bit, -1: the context's BLB_KNOB_PLAN_FORMAT)
 int cp_plan_create(blb_ctx* c, const double* W, int d_in, int d_out, int L, int level, uint64_t* mem, blb_plan** out, int* flag_host,
-                   const double* W_dev, int diag_heads = 0, int diag_dv = 0, int cplx = 0);
+                   const double* W_dev, int diag_heads = 0, int diag_dv = 0, int cplx = 0, int p50 = -1);
 void launch_sample_flood(blb_ctx* c, uint64_t* out, int n_limbs, ModMap map, uint64_t seed, uint32_t obj, uint32_t tag, int bits);
 void upload_cdt(const uint64_t* table20);
 
@@ -336,11 +340,12 @@ void launch_ks_inner(blb_ctx* c, const KsOut* outs_dev, int n_out, const uint64_
 void launch_ks_inner_grouped(blb_ctx* c, const KsOut* outs_dev, const int* ord_dev, const KsGroup* groups_dev, int n_groups,
                              const uint64_t* X, const KsLevelConst* kc_dev, uint64_t* U, int nl, int n_ext, int n_digits);
 void launch_moddown_conv(blb_ctx* c, const uint64_t* U, uint64_t* Corr, const KsLevelConst* kc_dev, int n_out, int nl, int n_ext);
-void launch_cp_mac(blb_ctx* c, const uint64_t* pt, const uint64_t* const* rx_tab, uint64_t* inner, int nl, int n_ai, int n_bj, int variant);
+void launch_cp_mac(blb_ctx* c, const uint64_t* pt, const uint64_t* const* rx_tab, uint64_t* inner, int nl, int n_ai, int n_bj, int variant,
+                   int p50);
 void launch_sum_cts(blb_ctx* c, const uint64_t* const* srcs, uint64_t* const* dsts, int n_out, int n_terms, int nl);
 void launch_mask_pair(blb_ctx* c, const CcPair* pairs_dev, int n_pairs, int nl);
 int batch_mac_shape(int variant, int* tb, int* ib, int* cpt);
-void launch_cp_mac_batch(blb_ctx* c, const MacGroup* groups, const MacItem* items, int n_items, int variant, int grid);
+void launch_cp_mac_batch(blb_ctx* c, const MacGroup* groups, const MacItem* items, int n_items, int variant, int grid, int p50);
 // forward NTT of count limb-polys stored back to back at base ([item][nl][N]); the results go
 // to out in the 50-bit plan format (base is left as it was)
 void launch_ntt_pack50(blb_ctx* c, const uint64_t* base, uint8_t* out, int count, int nl);

@@ -378,15 +378,10 @@ __device__ __forceinline__ void pt50_cvt(const Pt50Raw<CPT>& r, int k, double (&
 
 // One block's (tile, k-chunk, limb): sums over the n_ai rotated inputs of plaintext x input,
 // for `rows` output rows of the tile (FULL: rows == TB, no per-row guards).
-template <int TB, int CPT, int UNR, bool FULL>
+template <int TB, int CPT, int UNR, bool FULL, bool P50>
 __device__ __forceinline__ void cp_mac_tile(const uint8_t* __restrict__ pbase, const uint64_t* const* __restrict__ rx_tab,
                                             size_t pt_stride_bj, size_t pt_stride_ai, int n, int nl, int n_ai, int limb, int k0, int rows,
                                             double q, double qi, double (&a0)[TB][CPT], double (&a1)[TB][CPT]) {
-  auto load_pt = [&](const uint8_t* poly, double (&v)[CPT]) {
-    Pt50Raw<CPT> r;
-    pt50_fetch<CPT>(poly, n, k0, r);
-    pt50_cvt<CPT>(r, k0, v);
-  };
   auto load2 = [&](const uint64_t* a, double (&v)[CPT], bool stream) {
     if constexpr (CPT >= 2) {
 #pragma unroll
@@ -397,6 +392,16 @@ __device__ __forceinline__ void cp_mac_tile(const uint8_t* __restrict__ pbase, c
       }
     } else {
       v[0] = u2d(stream ? __builtin_nontemporal_load(a) : *a);
+    }
+  };
+  // poly: the (tile row, term) plaintext limb-poly
+  auto load_pt = [&](const uint8_t* poly, double (&v)[CPT]) {
+    if constexpr (P50) {
+      Pt50Raw<CPT> r;
+      pt50_fetch<CPT>(poly, n, k0, r);
+      pt50_cvt<CPT>(r, k0, v);
+    } else {
+      load2((const uint64_t*)poly + k0, v, true);
     }
   };
   auto reduce_all = [&]() {
@@ -454,7 +459,7 @@ __device__ __forceinline__ void cp_mac_tile(const uint8_t* __restrict__ pbase, c
 
 // SPLIT: full tiles run a body without per-row guards (separately compiled from the guarded
 // body of the last, partial tile); otherwise one guarded body serves every tile.
-template <int TB, int CPT, int UNR, bool SPLIT>
+template <int TB, int CPT, int UNR, bool SPLIT, bool P50>
 __global__ __launch_bounds__(256) void k_cp_mac(const uint64_t* __restrict__ pt, const uint64_t* const* __restrict__ rx_tab,
                                                 uint64_t* __restrict__ inner, int n, int nl, int n_ai, int n_bj, ModTable mt, int n_kblk,
                                                 int n_tiles) {
@@ -481,12 +486,12 @@ __global__ __launch_bounds__(256) void k_cp_mac(const uint64_t* __restrict__ pt,
   for (int t = 0; t < TB; ++t)
 #pragma unroll
     for (int c = 0; c < CPT; ++c) { a0[t][c] = 0.0; a1[t][c] = 0.0; }
-  const size_t pb = pt50_bytes(n);
+  const size_t pb = pt_poly_bytes(n, P50);
   const size_t pt_stride_ai = (size_t)nl * pb, pt_stride_bj = (size_t)n_ai * pt_stride_ai;
   const uint8_t* pbase = (const uint8_t*)pt + (size_t)bj0 * pt_stride_bj + (size_t)limb * pb;
   if (SPLIT && rows == TB)
-    cp_mac_tile<TB, CPT, UNR, true>(pbase, rx_tab, pt_stride_bj, pt_stride_ai, n, nl, n_ai, limb, k0, rows, q, qi, a0, a1);
-  else cp_mac_tile<TB, CPT, UNR, false>(pbase, rx_tab, pt_stride_bj, pt_stride_ai, n, nl, n_ai, limb, k0, rows, q, qi, a0, a1);
+    cp_mac_tile<TB, CPT, UNR, true, P50>(pbase, rx_tab, pt_stride_bj, pt_stride_ai, n, nl, n_ai, limb, k0, rows, q, qi, a0, a1);
+  else cp_mac_tile<TB, CPT, UNR, false, P50>(pbase, rx_tab, pt_stride_bj, pt_stride_ai, n, nl, n_ai, limb, k0, rows, q, qi, a0, a1);
 #pragma unroll
   for (int t = 0; t < TB; ++t) {
     if (t < rows) {
@@ -503,7 +508,8 @@ __global__ __launch_bounds__(256) void k_cp_mac(const uint64_t* __restrict__ pt,
 
 // Tuning knob (does not change any result bit): outputs per block x coefficients per thread
 // x unroll of the input loop x split full / partial tiles.
-void launch_cp_mac(blb_ctx* c, const uint64_t* pt, const uint64_t* const* rx_tab, uint64_t* inner, int nl, int n_ai, int n_bj, int variant) {
+void launch_cp_mac(blb_ctx* c, const uint64_t* pt, const uint64_t* const* rx_tab, uint64_t* inner, int nl, int n_ai, int n_bj, int variant,
+                   int p50) {
   struct Shape { int tb, cpt; };
   static const Shape shapes[BLB_MAC_VARIANTS] = {{8, 2}, {8, 1}, {16, 2}, {4, 2}, {12, 2}, {2, 2}, {4, 2}, {2, 2}, {4, 1}, {4, 1},
                                                  {4, 2}, {4, 2}, {8, 1}, {4, 1}, {2, 4}, {4, 4}, {2, 4}, {4, 4}};
@@ -511,8 +517,11 @@ void launch_cp_mac(blb_ctx* c, const uint64_t* pt, const uint64_t* const* rx_tab
   const int n_kblk = c->n / (256 * sh.cpt);
   const int n_tiles = (n_bj + sh.tb - 1) / sh.tb;
   const int blocks = n_kblk * nl * n_tiles;
-#define CPMAC(tb, cpt, unr, split) \
-  k_cp_mac<tb, cpt, unr, split><<<blocks, 256, 0, c->stream>>>(pt, rx_tab, inner, c->n, nl, n_ai, n_bj, c->mt, n_kblk, n_tiles)
+#define CPMAC(tb, cpt, unr, split)                                                                                                 \
+  do {                                                                                                                             \
+    if (p50) k_cp_mac<tb, cpt, unr, split, true><<<blocks, 256, 0, c->stream>>>(pt, rx_tab, inner, c->n, nl, n_ai, n_bj, c->mt, n_kblk, n_tiles); \
+    else k_cp_mac<tb, cpt, unr, split, false><<<blocks, 256, 0, c->stream>>>(pt, rx_tab, inner, c->n, nl, n_ai, n_bj, c->mt, n_kblk, n_tiles); \
+  } while (0)
   switch (variant) {
     case 1: CPMAC(8, 1, 1, false); break;
     case 2: CPMAC(16, 2, 1, false); break;
@@ -1054,7 +1063,7 @@ void launch_masked_acc(blb_ctx* c, const CcTerm* terms, const int* off, uint64_t
 // in-bounds operands and not stored, so the inner loop has no branches.  Operands go through
 // the global address space (pointer tables through scalar loads) and the next term's words are
 // loaded while the current term is multiplied.
-template <int TB, int IB, int CPT>
+template <int TB, int IB, int CPT, bool P50>
 __global__ __launch_bounds__(256) void k_cp_mac_batch(const MacGroup* __restrict__ groups, const MacItem* __restrict__ items, int n_items,
                                                       int n, ModTable mt) {
   typedef __attribute__((address_space(1))) const uint64_t gu64c;
@@ -1070,7 +1079,7 @@ __global__ __launch_bounds__(256) void k_cp_mac_batch(const MacGroup* __restrict
     const double q = me.q, qi = me.qinv;
     const int bj0 = item.tile * TB;
     const int ninst = min(IB, gr.n_inst - item.inst0);
-    const size_t pb = pt50_bytes(n);
+    const size_t pb = pt_poly_bytes(n, P50);
     const size_t term = (size_t)nl * pb;  // bytes per (bj, ai) plaintext
     const uint8_t* pt[TB];
 #pragma unroll
@@ -1079,10 +1088,18 @@ __global__ __launch_bounds__(256) void k_cp_mac_batch(const MacGroup* __restrict
 #pragma unroll
     for (int u = 0; u < IB; ++u) rxtab[u] = (const ku64*)(gr.rx + (size_t)(item.inst0 + min(u, ninst - 1)) * n_ai);
     Pt50Raw<CPT> rw[TB];
+    uint64_t rq[TB][CPT];
     uint64_t rx0[IB][CPT], rx1[IB][CPT];  // raw words of the term in flight
     auto fetch = [&](int ai) {
 #pragma unroll
-      for (int t = 0; t < TB; ++t) pt50_fetch<CPT>(pt[t] + (size_t)ai * term, n, k0, rw[t]);
+      for (int t = 0; t < TB; ++t) {
+        if constexpr (P50) {
+          pt50_fetch<CPT>(pt[t] + (size_t)ai * term, n, k0, rw[t]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < CPT; ++c) rq[t][c] = __builtin_nontemporal_load((const gu64c*)(pt[t] + (size_t)ai * term) + k0 + c);
+        }
+      }
 #pragma unroll
       for (int u = 0; u < IB; ++u) {
         const gu64c* x = (const gu64c*)rxtab[u][ai];
@@ -1104,7 +1121,14 @@ __global__ __launch_bounds__(256) void k_cp_mac_batch(const MacGroup* __restrict
     for (int ai = 0; ai < n_ai; ++ai) {
       double w[TB][CPT], x0[IB][CPT], x1[IB][CPT];
 #pragma unroll
-      for (int t = 0; t < TB; ++t) pt50_cvt<CPT>(rw[t], k0, w[t]);
+      for (int t = 0; t < TB; ++t) {
+        if constexpr (P50) {
+          pt50_cvt<CPT>(rw[t], k0, w[t]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < CPT; ++c) w[t][c] = u2d(rq[t][c]);
+        }
+      }
 #pragma unroll
       for (int u = 0; u < IB; ++u)
 #pragma unroll
@@ -1164,12 +1188,16 @@ int batch_mac_shape(int variant, int* tb, int* ib, int* cpt) {
   return 0;
 }
 
-void launch_cp_mac_batch(blb_ctx* c, const MacGroup* groups, const MacItem* items, int n_items, int variant, int grid) {
+void launch_cp_mac_batch(blb_ctx* c, const MacGroup* groups, const MacItem* items, int n_items, int variant, int grid, int p50) {
   if (n_items <= 0) return;
   int tb, ib, cpt;
   batch_mac_shape(variant, &tb, &ib, &cpt);
   const int blocks = std::min(n_items, grid);
-#define MB(a, b, d) k_cp_mac_batch<a, b, d><<<blocks, 256, 0, c->stream>>>(groups, items, n_items, c->n, c->mt)
+#define MB(a, b, d)                                                                                   \
+  do {                                                                                                \
+    if (p50) k_cp_mac_batch<a, b, d, true><<<blocks, 256, 0, c->stream>>>(groups, items, n_items, c->n, c->mt);  \
+    else k_cp_mac_batch<a, b, d, false><<<blocks, 256, 0, c->stream>>>(groups, items, n_items, c->n, c->mt); \
+  } while (0)
   if (tb == 4 && ib == 1) MB(4, 1, 2);
   else if (tb == 2 && ib == 4) MB(2, 4, 2);
   else if (tb == 4 && ib == 4 && cpt == 1) MB(4, 4, 1);

@@ -126,6 +126,7 @@ int ceil_log2i(int64_t v) {
 
 struct blb_server {
   blb_ctx* c;
+  int p50 = 0;  // plaintext format of the cached plans (the context's knob at creation)
   blb_server_config cfg;
   std::vector<hipStream_t> streams;
   std::map<int, Weights> weights;
@@ -218,7 +219,7 @@ int generate_plan(blb_server* S, Request* r, bool async) {
     wp = &S->weights.at(r->weight_id);
   }
   const Weights& w = *wp;
-  const size_t need = cp_plan_bytes(c, r->Lp, w.d_in, w.d_out, w.level, w.cplx);
+  const size_t need = cp_plan_bytes(c, r->Lp, w.d_in, w.d_out, w.level, w.cplx, S->p50);
   if (Arena::round(need) > S->arena.cap) return BLB_ENOMEM;
   size_t off = 0;
   if (!make_room(S, need, &off)) {  // memory frees up when running batches finish
@@ -237,7 +238,7 @@ int generate_plan(blb_server* S, Request* r, bool async) {
       if (!used) break;
     }
   const int rc = cp_plan_create(c, w.W.data(), w.d_in, w.d_out, r->Lp, w.level, (uint64_t*)((char*)S->arena.base + off), &P,
-                                async ? S->gen_flag + slot : nullptr, w.W_dev, 0, 0, w.cplx);
+                                async ? S->gen_flag + slot : nullptr, w.W_dev, 0, 0, w.cplx, S->p50);
   hipEvent_t ev = nullptr;
   if (rc == BLB_OK && async && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) (void)hipEventRecord(ev, c->stream);
   c->stream = saved;
@@ -489,6 +490,7 @@ int blb_server_create(blb_ctx* c, const blb_server_config* cfg, blb_server** out
   blb_server* S = new (std::nothrow) blb_server();
   if (!S) return BLB_ENOMEM;
   S->c = c;
+  S->p50 = c->plan_p50;
   S->cfg = *cfg;
   // device memory that the stream-ordered pool keeps cached would crowd out the plan arena and
   // the batch workspaces: release it before reserving them

@@ -28,6 +28,23 @@ def test_library_exports_every_declared_symbol():
     assert sorted(B.exported_symbols()) == names
 
 
+def test_binding_constants_match_header_enums():
+    """Every BLB_* enum constant the binding defines has the header's value (knobs, timing kinds,
+    variant counts, status codes)."""
+    import paper_2508_19525_amd as B
+    src = open(os.path.join(ROOT, "include", "blb.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    header = {}
+    for body in re.findall(r"enum\s*\{(.*?)\}", src, flags=re.S):
+        for name, val in re.findall(r"\b(BLB_[A-Z0-9_]+)\s*=\s*(-?\d+)", body):
+            header[name] = int(val)
+    assert {"BLB_KNOB_PLAN_FORMAT", "BLB_MAC_VARIANTS", "BLB_BATCH_VARIANTS", "BLB_T_CP_MAC"} <= set(header)
+    shared = [n for n in header if hasattr(B, n)]
+    assert len(shared) >= 20
+    for n in shared:
+        assert getattr(B, n) == header[n], n
+
+
 def test_status_strings():
     import paper_2508_19525_amd as B
     assert B.status_str(0) == "ok"

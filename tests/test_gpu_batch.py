@@ -76,9 +76,15 @@ def C_cast(a):
 SHAPES = [(16, 96), (40, 64), (100, 96), (33, 64), (16, 96), (200, 96)]
 
 
-def test_batched_equals_per_instance(env):
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_batched_equals_per_instance(env, fmt):
+    """With the plans' plaintexts as 64-bit words (fmt 0) or in the 50-bit format (fmt 1)"""
     B, wl, ctx = env
-    inst, plans, Ws, keep = _build(B, wl, ctx, SHAPES)
+    B.blb_ctx_set_knob(ctx, B.BLB_KNOB_PLAN_FORMAT, fmt)
+    try:
+        inst, plans, Ws, keep = _build(B, wl, ctx, SHAPES)
+    finally:
+        B.blb_ctx_set_knob(ctx, B.BLB_KNOB_PLAN_FORMAT, 0)
     for I in inst:
         B.blb_matmul_cp(ctx, I["keys"], I["plan"], I["X"], I["Y2"])
     arr, hold = _abi_instances(B, inst)
@@ -163,6 +169,28 @@ def test_batched_instance_matches_oracle(env, orc):
     for I in inst:
         B.blb_keys_destroy(I["keys"])
     for p in plans.values():
+        B.blb_plan_destroy(p)
+
+
+def test_batched_refuses_mixed_plan_formats(env):
+    """One batched call takes plans of one plaintext format: a 64-bit-word plan beside a 50-bit
+    one is refused before any work is enqueued"""
+    B, wl, ctx = env
+    inst, plans, Ws, keep = _build(B, wl, ctx, [(20, 64), (50, 64)])
+    B.blb_ctx_set_knob(ctx, B.BLB_KNOB_PLAN_FORMAT, 1)
+    try:
+        p50 = B.blb_plan_matmul_cp(ctx, Ws[64], wl.lp_of(50), 2)
+    finally:
+        B.blb_ctx_set_knob(ctx, B.BLB_KNOB_PLAN_FORMAT, 0)
+    inst[1]["plan"] = p50
+    arr, hold = _abi_instances(B, inst)
+    with pytest.raises(B.BlbError) as e:
+        B.blb_batch_matmul_cp(ctx, arr)
+    assert e.value.code == B.BLB_EINVAL
+    torch.cuda.synchronize()
+    for I in inst:
+        B.blb_keys_destroy(I["keys"])
+    for p in list(plans.values()) + [p50]:
         B.blb_plan_destroy(p)
 
 

@@ -43,6 +43,11 @@ def test_bad_parameters_rejected(env):
     assert _code(B.blb_ctx_create, 11, 2, 1, 2) == B.BLB_EINVAL  # N below the supported range
     assert _code(B.blb_ctx_create, 13, 3, 1, 4) == B.BLB_EINVAL  # dnum > n_q
     assert _code(B.blb_ctx_create, 13, 0, 1, 1) == B.BLB_EINVAL
+    # knob values out of range, unknown knobs
+    assert _code(B.blb_ctx_set_knob, ctx, B.BLB_KNOB_PLAN_FORMAT, 2) == B.BLB_EINVAL
+    assert _code(B.blb_ctx_set_knob, ctx, B.BLB_KNOB_MAC_VARIANT, B.BLB_MAC_VARIANTS) == B.BLB_EINVAL
+    assert _code(B.blb_ctx_set_knob, ctx, 8, 0) == B.BLB_EINVAL
+    assert B.blb_ctx_get_knob(ctx, B.BLB_KNOB_PLAN_FORMAT) == 0
 
 
 def test_missing_key_and_untouched_output(env):

@@ -40,11 +40,13 @@ def _import(B, ctx, keep, words, n, level, scale):
     return c
 
 
+@pytest.mark.parametrize("fmt", [0, 1])
 @pytest.mark.parametrize("cplx", [False, True])
-def test_bert_base_matmul_cp_full_size(B, orc, cplx):
-    """The headline operator at full size, real-slot or complex-slot output packing: inputs
-    encrypted by the library equal the oracle's, counters equal the schedule's closed forms,
-    sampled outputs equal the oracle's word for word, every output decodes to X W within 2^-20."""
+def test_bert_base_matmul_cp_full_size(B, orc, cplx, fmt):
+    """The headline operator at full size, real-slot or complex-slot output packing, plaintexts as
+    64-bit words (fmt 0) or in the 50-bit format (fmt 1): inputs encrypted by the library equal the
+    oracle's, counters equal the schedule's closed forms, sampled outputs equal the oracle's word
+    for word, every output decodes to X W within 2^-20."""
     from paper_2508_19525_amd import workloads as wl
     cfg = wl.C2
     p = cfg["params"]
@@ -59,6 +61,7 @@ def test_bert_base_matmul_cp_full_size(B, orc, cplx):
     ctx = B.blb_ctx_create(p.log_n, p.n_q, p.n_special, p.dnum, 0, torch.cuda.current_stream().cuda_stream)
     keep = []
     try:
+        B.blb_ctx_set_knob(ctx, B.BLB_KNOB_PLAN_FORMAT, fmt)
         plan = (B.blb_plan_matmul_cp_cplx if cplx else B.blb_plan_matmul_cp)(ctx, W, L, level)
         g = B.blb_plan_info(plan)
         n_y = 12 if cplx else 24  # output ciphertexts
@@ -83,7 +86,7 @@ def test_bert_base_matmul_cp_full_size(B, orc, cplx):
         assert cnt["ct_pt_products"] == 24 * n_y * 32  # 18432 real, 9216 complex
         assert cnt["modup_sources"] == 24 + n_y * 3
         assert cnt["rescaled_cts"] == n_y
-        assert cnt["plaintext_bytes"] == 24 * n_y * 32 * 3 * n * 25 // 4  # 50 bits per plaintext word
+        assert cnt["plaintext_bytes"] == 24 * n_y * 32 * 3 * (n * 25 // 4 if fmt else n * 8)
         samples = [0, 7] if cplx else [0, 17]
         want = keys_o.matmul_cp(xw, level, W, L, outputs=samples, cplx=cplx)
         for b in samples:

@@ -571,12 +571,26 @@ def test_ks_variants_bit_identical(c3s, c2s, ks_variant):
             B.blb_ctx_set_knob(c.h, B.BLB_KNOB_KS_VARIANT, default)
 
 
+@pytest.mark.parametrize("fmt", [0, 1])
 @pytest.mark.parametrize("shape", [(64, 96, 64), (20, 1, 24)])
-def test_mac_variants_bit_identical(c2s, shape):
-    """Every MAC launch shape gives the same words (the second shape has a single rotated input,
-    so the unrolled variants run their remainder loop, and a partial last output tile)."""
+def test_mac_variants_bit_identical(c2s, shape, fmt):
+    """Every MAC launch shape gives the oracle's words, with the plan's plaintexts held as 64-bit
+    words (fmt 0) or in the 50-bit format (fmt 1); the second shape has a single rotated input, so
+    the unrolled variants run their remainder loop, and a partial last output tile.  The plan takes
+    8N or 25N/4 bytes per limb-poly, and the MAC counts that many plaintext bytes."""
     B = c2s.B
-    r = _cp_case(c2s, *shape, 2, 5, x_std=1.0)
+    B.blb_ctx_set_knob(c2s.h, B.BLB_KNOB_PLAN_FORMAT, fmt)
+    try:
+        assert B.blb_ctx_get_knob(c2s.h, B.BLB_KNOB_PLAN_FORMAT) == fmt
+        B.blb_ctx_counters(c2s.h, reset=True)
+        r = _cp_case(c2s, *shape, 2, 5, x_std=1.0)
+        plaintext_bytes = B.blb_ctx_counters(c2s.h)["plaintext_bytes"]
+    finally:
+        B.blb_ctx_set_knob(c2s.h, B.BLB_KNOB_PLAN_FORMAT, 0)
+    g = r["g"]
+    n_pt = g["n_out"] * g["G"] * g["n_in"] * g["B"]
+    poly_bytes = c2s.n * 25 // 4 if fmt else c2s.n * 8
+    assert plaintext_bytes == n_pt * 3 * poly_bytes
     base = [c2s.export(y) for y in r["Yc"]]
     want = r["keys_o"].matmul_cp(r["X_words"], 2, r["W"], shape[0])
     assert all(np.array_equal(base[b], want[b]) for b in range(len(base)))
@@ -588,7 +602,10 @@ def test_mac_variants_bit_identical(c2s, shape):
         for b in range(len(Y)):
             assert np.array_equal(c2s.export(Y[b]), base[b]), f"variant {var}"
     B.blb_ctx_set_knob(c2s.h, B.BLB_KNOB_MAC_VARIANT, 0)
+    torch.cuda.synchronize()
+    held = B.blb_ctx_device_bytes(c2s.h)
     B.blb_plan_destroy(r["plan"])
+    assert held - B.blb_ctx_device_bytes(c2s.h) == n_pt * 3 * poly_bytes  # the plan's own allocation
     B.blb_keys_destroy(r["keys_g"])
 
 

@@ -72,16 +72,20 @@ def _keys_for_all(B, wl, ctx, n_clients):
     return [B.blb_keygen(ctx, 6100 + c, sorted(steps)) for c in range(n_clients)]
 
 
-@pytest.mark.parametrize("policy", [1, 0])
-def test_alone_equals_in_mix(env, policy):
+@pytest.mark.parametrize("policy,fmt", [(1, 0), (0, 0), (1, 1)])
+def test_alone_equals_in_mix(env, policy, fmt):
+    """A request served alone and inside a mix gives the same words and share, under either
+    admission policy and with the cached plans as 64-bit words (fmt 0) or in the 50-bit format"""
     B, wl, ctx = env
     keys = _keys_for_all(B, wl, ctx, 3)
     specs = [(0, 40, 0, 1)] + [(i % 3, [16, 100, 33, 200, 64, 7, 300][i % 7], i % 3, 10 + i) for i in range(12)]
     reqs, keep = _make_requests(B, wl, ctx, specs, keys)
     Ws = {wid: wl.serving_weights(wid, SHAPES[wid]) for wid in SHAPES}
     # plan budget fits a handful of plans: forces eviction between batches
-    srv = B.blb_server_create(ctx, plan_cache_bytes=600 << 20, max_batch=6, n_streams=2, policy=policy, max_wait_ms=50.0)
+    B.blb_ctx_set_knob(ctx, B.BLB_KNOB_PLAN_FORMAT, fmt)  # taken by the server at creation
+    srv = None
     try:
+        srv = B.blb_server_create(ctx, plan_cache_bytes=600 << 20, max_batch=6, n_streams=2, policy=policy, max_wait_ms=50.0)
         for wid, W in Ws.items():
             B.blb_server_add_weights(srv, wid, W, 2)
         r0 = reqs[0]
@@ -124,7 +128,9 @@ def test_alone_equals_in_mix(env, policy):
             got = wl.unpack_spatial(vecs, r["L"], SHAPES[r["wid"]][1], 4096)
             assert np.abs(got - r["Xm"] @ Ws[r["wid"]]).max() < 2.0 ** -20
     finally:
-        B.blb_server_destroy(srv)
+        if srv is not None:
+            B.blb_server_destroy(srv)
+        B.blb_ctx_set_knob(ctx, B.BLB_KNOB_PLAN_FORMAT, 0)
         for k in keys:
             B.blb_keys_destroy(k)
 
@@ -332,16 +338,19 @@ def test_submit_checks_mask_target_and_share(env):
 
 
 def test_complex_packed_weights(env):
-    """Weights registered with the complex-slot output packing: every served request equals the
-    eager matmul_cp on a complex plan of the same weight and length, word for word, and its
-    decoded real / imaginary parts give X W; the real-packing output count is refused."""
+    """Weights registered with the complex-slot output packing, the server's plans in the 50-bit
+    format: every served request equals the eager matmul_cp on a complex plan of 64-bit words of
+    the same weight and length, word for word, and its decoded real / imaginary parts give X W;
+    the real-packing output count is refused."""
     B, wl, ctx = env
     keys = _keys_for_all(B, wl, ctx, 2)
     specs = [(i % 3, [16, 100, 33, 200, 64, 300][i % 6], i % 2, 40 + i) for i in range(8)]
     reqs, keep = _make_requests(B, wl, ctx, specs, keys, cplx=True)
     Ws = {wid: wl.serving_weights(wid, SHAPES[wid]) for wid in SHAPES}
-    srv = B.blb_server_create(ctx, plan_cache_bytes=600 << 20, max_batch=4, n_streams=2, policy=1, max_wait_ms=50.0)
+    B.blb_ctx_set_knob(ctx, B.BLB_KNOB_PLAN_FORMAT, 1)  # taken by the server at creation
+    srv = None
     try:
+        srv = B.blb_server_create(ctx, plan_cache_bytes=600 << 20, max_batch=4, n_streams=2, policy=1, max_wait_ms=50.0)
         for wid, W in Ws.items():
             B.blb_server_add_weights(srv, wid, W, 2, cplx=True)
         # the real-packing output count is refused for a complex-packed weight
@@ -354,7 +363,9 @@ def test_complex_packed_weights(env):
         B.blb_server_drain(srv, 300)
         assert [B.blb_server_poll(srv, i)[0] for i in ids] == [2] * len(ids)
     finally:
-        B.blb_server_destroy(srv)
+        if srv is not None:
+            B.blb_server_destroy(srv)
+        B.blb_ctx_set_knob(ctx, B.BLB_KNOB_PLAN_FORMAT, 0)
     dec = torch.empty(2 * 8192, dtype=torch.int64, device="cuda")
     for r in reqs:
         plan = B.blb_plan_matmul_cp_cplx(ctx, Ws[r["wid"]], r["L"], 2)
