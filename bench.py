@@ -36,19 +36,18 @@ CC_SCHEDULE = 1
 # by what the counter reads for a plain 1 GiB copy (FETCH_SIZE x 1.99989, WRITE_SIZE x 1.0).  Valid
 # only for the MAC source text with this hash; any later change of that code reports traffic as
 # null until re-measured.
-MAC_TRAFFIC_SRC_SHA256 = "1e42f92ab536cc80d6e07df8769fb6a035e107cab34937e7b8db233a22982207"
+MAC_TRAFFIC_SRC_SHA256 = "c061e636c9f96c9f22cf88ceec2b9f216994cad426baa7bccefbae66468e8a6d"
 MAC_TRAFFIC_BYTES = {  # (plan format, packing) -> {variant: bytes}
-    (0, "real"): {0: 3768779709, 1: 3751307162, 2: 3759680789, 3: 3774058990, 4: 3740322696, 5: 3780387927,
-                  6: 3785686655, 7: 3785295169, 8: 3745393129, 9: 3745599197, 10: 3861145693, 11: 3873134377,
-                  12: 3796503664, 13: 3804649251, 14: 3775367882, 15: 3823505741, 16: 3854702870, 17: 3811205598},
-    (0, "complex"): {0: 1918583374, 1: 1915172154, 2: 1906668571, 3: 1918574244, 4: 1907601767, 5: 1959353162,
-                     6: 1919383755, 7: 1963524150, 8: 1908657963, 9: 1909102482, 10: 1981949301, 11: 1960196250,
-                     12: 1927604773, 13: 1950562534, 14: 1979127018, 15: 1931899825, 16: 1987405504, 17: 1960896157},
-    (1, "real"): {0: 3050191150, 1: 3180946029, 2: 3010826510, 3: 3093002337, 4: 3030554971, 5: 3097697068,
-                  6: 3037469097, 7: 3079037559, 8: 3216070568, 9: 3198908276, 10: 3084738618, 11: 3142644411,
-                  12: 3351003728, 13: 3220368522, 14: 3037514706, 15: 3013275395, 16: 3045668399, 17: 3031510267},
+    (0, "real"): {0: 3835377093, 1: 3824325357, 2: 3804583759, 3: 4013449152, 4: 3843329509, 5: 4349787703,
+                  6: 4084424763, 7: 4317030824, 8: 4243198349, 9: 4279550500, 10: 4086796705, 11: 4014554668,
+                  12: 3824752554, 13: 4286819634, 14: 4052420121, 15: 4001316295, 16: 4050522074, 17: 3935035563},
+    (0, "complex"): {0: 1954866042, 1: 1906951796, 2: 1906485433, 3: 1950219480, 4: 1906438417, 5: 1990073384,
+                     6: 2030832880, 7: 2202941323, 8: 1999536142, 9: 2181917238, 10: 2034560497, 11: 1950487221,
+                     12: 1906891341, 13: 2192122183, 14: 1992967428, 15: 2020405569, 16: 1992650902, 17: 2022475339},
+    (1, "real"): {0: 3003747300, 1: 3637425819, 2: 3053238536, 3: 3324696764, 4: 3145001510, 5: 3579729431,
+                  6: 3167796161, 7: 3729334279, 8: 3803934111, 9: 3832897712, 10: 3173349210, 11: 3320421765,
+                  12: 3630743106, 13: 3781555095, 14: 3265934027, 15: 3042768902, 16: 3253266801, 17: 3038618312},
 }
-
 
 def mac_traffic(variant, cplx=False, fmt=0):
     import hashlib

@@ -3,6 +3,7 @@
 #include "blb_internal.h"
 #include "blb_kernels.h"
 #include <algorithm>
+#include <type_traits>
 
 // ---------------------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): 10 rounds, multipliers 0xD2511F53 / 0xCD9E8D57,
@@ -377,23 +378,40 @@ __device__ __forceinline__ void pt50_cvt(const Pt50Raw<CPT>& r, int k, double (&
 
 
 // One block's (tile, k-chunk, limb): sums over the n_ai rotated inputs of plaintext x input,
-// for `rows` output rows of the tile (FULL: rows == TB, no per-row guards).
+// for `rows` output rows of the tile (FULL: rows == TB, no row clamping).
 template <int TB, int CPT, int UNR, bool FULL, bool P50>
 __device__ __forceinline__ void cp_mac_tile(const uint8_t* __restrict__ pbase, const uint64_t* const* __restrict__ rx_tab,
                                             size_t pt_stride_bj, size_t pt_stride_ai, int n, int nl, int n_ai, int limb, int k0, int rows,
                                             double q, double qi, double (&a0)[TB][CPT], double (&a1)[TB][CPT]) {
-  auto load2 = [&](const uint64_t* a, double (&v)[CPT], bool stream) {
+  typedef __attribute__((address_space(1))) const uint64_t gu64;
+  typedef __attribute__((address_space(1))) const u64x2 gu64x2;
+  // STREAM: non-temporal loads (the plaintexts, read once); the rotated inputs, re-read by
+  // every tile, stay cached.  A compile-time choice: a select between the two forms of the load
+  // is merged into one plain load by the optimizer, which drops the non-temporal hint.
+  auto load2 = [&](auto stream, gu64* a, double (&v)[CPT]) {
+    constexpr bool STREAM = decltype(stream)::value;
     if constexpr (CPT >= 2) {
 #pragma unroll
       for (int h = 0; h < CPT; h += 2) {
-        const u64x2 w = stream ? __builtin_nontemporal_load((const u64x2*)(a + h)) : *(const u64x2*)(a + h);
+        u64x2 w;
+        if constexpr (STREAM) w = __builtin_nontemporal_load((gu64x2*)(a + h));
+        else w = *(gu64x2*)(a + h);
         v[h] = u2d(w.x);
         v[h + 1] = u2d(w.y);
       }
     } else {
-      v[0] = u2d(stream ? __builtin_nontemporal_load(a) : *a);
+      if constexpr (STREAM) v[0] = u2d(__builtin_nontemporal_load(a));
+      else v[0] = u2d(*a);
     }
   };
+  using kStream = std::true_type;
+  using kCached = std::false_type;
+  // Row pointers: the rows past a partial tile's last re-read that row, so every row of the
+  // body runs unconditionally (branch-free, loads of all rows in flight together); their sums
+  // are never stored.
+  const uint8_t* rowp[TB];
+#pragma unroll
+  for (int t = 0; t < TB; ++t) rowp[t] = pbase + (size_t)(FULL ? t : min(t, rows - 1)) * pt_stride_bj;
   // poly: the (tile row, term) plaintext limb-poly
   auto load_pt = [&](const uint8_t* poly, double (&v)[CPT]) {
     if constexpr (P50) {
@@ -401,7 +419,7 @@ __device__ __forceinline__ void cp_mac_tile(const uint8_t* __restrict__ pbase, c
       pt50_fetch<CPT>(poly, n, k0, r);
       pt50_cvt<CPT>(r, k0, v);
     } else {
-      load2((const uint64_t*)poly + k0, v, true);
+      load2(kStream{}, (gu64*)poly + k0, v);
     }
   };
   auto reduce_all = [&]() {
@@ -415,66 +433,60 @@ __device__ __forceinline__ void cp_mac_tile(const uint8_t* __restrict__ pbase, c
     double x0[UNR][CPT], x1[UNR][CPT], w[UNR][TB][CPT];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
-      const uint64_t* rx = rx_tab[ai + u];
-      load2(rx + (size_t)limb * n + k0, x0[u], false);
-      load2(rx + (size_t)(nl + limb) * n + k0, x1[u], false);
+      gu64* rx = (gu64*)rx_tab[ai + u];
+      load2(kCached{}, rx + (size_t)limb * n + k0, x0[u]);
+      load2(kCached{}, rx + (size_t)(nl + limb) * n + k0, x1[u]);
     }
 #pragma unroll
     for (int u = 0; u < UNR; ++u)
 #pragma unroll
-      for (int t = 0; t < TB; ++t)
-        if (FULL || t < rows) load_pt(pbase + (size_t)t * pt_stride_bj + (size_t)(ai + u) * pt_stride_ai, w[u][t]);
+      for (int t = 0; t < TB; ++t) load_pt(rowp[t] + (size_t)(ai + u) * pt_stride_ai, w[u][t]);
 #pragma unroll
     for (int u = 0; u < UNR; ++u)
 #pragma unroll
       for (int t = 0; t < TB; ++t)
-        if (FULL || t < rows) {
 #pragma unroll
-          for (int c = 0; c < CPT; ++c) {
-            a0[t][c] += mulmod_s(w[u][t][c], x0[u][c], q, qi);
-            a1[t][c] += mulmod_s(w[u][t][c], x1[u][c], q, qi);
-          }
+        for (int c = 0; c < CPT; ++c) {
+          a0[t][c] += mulmod_s(w[u][t][c], x0[u][c], q, qi);
+          a1[t][c] += mulmod_s(w[u][t][c], x1[u][c], q, qi);
         }
     if (((ai + UNR) & 7) == 0) reduce_all();  // every 8 terms: |acc| stays below 2^53
   }
   for (; ai < n_ai; ++ai) {
-    double x0[CPT], x1[CPT];
-    const uint64_t* rx = rx_tab[ai];
-    load2(rx + (size_t)limb * n + k0, x0, false);
-    load2(rx + (size_t)(nl + limb) * n + k0, x1, false);
+    double x0[CPT], x1[CPT], w[TB][CPT];
+    gu64* rx = (gu64*)rx_tab[ai];
+    load2(kCached{}, rx + (size_t)limb * n + k0, x0);
+    load2(kCached{}, rx + (size_t)(nl + limb) * n + k0, x1);
+#pragma unroll
+    for (int t = 0; t < TB; ++t) load_pt(rowp[t] + (size_t)ai * pt_stride_ai, w[t]);
 #pragma unroll
     for (int t = 0; t < TB; ++t)
-      if (FULL || t < rows) {
-        double w[CPT];
-        load_pt(pbase + (size_t)t * pt_stride_bj + (size_t)ai * pt_stride_ai, w);
 #pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-          a0[t][c] += mulmod_s(w[c], x0[c], q, qi);
-          a1[t][c] += mulmod_s(w[c], x1[c], q, qi);
-        }
+      for (int c = 0; c < CPT; ++c) {
+        a0[t][c] += mulmod_s(w[t][c], x0[c], q, qi);
+        a1[t][c] += mulmod_s(w[t][c], x1[c], q, qi);
       }
     if ((ai & 7) == 7) reduce_all();
   }
 }
 
-// SPLIT: full tiles run a body without per-row guards (separately compiled from the guarded
-// body of the last, partial tile); otherwise one guarded body serves every tile.
+// SPLIT: full tiles run a body without row clamping (separately compiled from the clamped
+// body of the last, partial tile); otherwise the clamped body serves every tile.
 template <int TB, int CPT, int UNR, bool SPLIT, bool P50>
 __global__ __launch_bounds__(256) void k_cp_mac(const uint64_t* __restrict__ pt, const uint64_t* const* __restrict__ rx_tab,
                                                 uint64_t* __restrict__ inner, int n, int nl, int n_ai, int n_bj, ModTable mt, int n_kblk,
                                                 int n_tiles) {
   static_assert(CPT == 1 || CPT == 2 || CPT == 4, "coefficients per thread");
   static_assert(UNR == 1 || UNR == 2, "unroll of the input loop");
-  // XCD-aware block mapping: blocks that share a (k-chunk, limb) land on the same XCD, so
-  // the rotated inputs they all read stay in that XCD's L2
-  const int nb = gridDim.x;
-  const int per_xcd = nb / 8;
-  int lb = blockIdx.x;
-  if (per_xcd * 8 == nb) lb = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  const int tile = lb % n_tiles;
-  const int rest = lb / n_tiles;
-  const int kb = rest % n_kblk;
-  const int limb = rest / n_kblk;
+  // Block order: k-chunk fastest, then limb, then output tile.  Consecutive blocks stream
+  // consecutive 4 KB pieces of one plaintext limb-poly (the dispatcher deals them round-robin
+  // over the 8 XCDs), and the blocks of one (k-chunk, limb) -- the ones reading the same
+  // rotated-input words -- lie n_kblk * nl apart, a multiple of 8 whenever n_kblk is: one XCD,
+  // one L2.  (Tile-fastest order with the same XCD grouping streamed 2-12 % slower.)
+  const int kb = blockIdx.x % n_kblk;
+  const int limb = (blockIdx.x / n_kblk) % nl;
+  const int tile = blockIdx.x / (n_kblk * nl);
+  (void)n_tiles;
   const int k0 = (kb * 256 + threadIdx.x) * CPT;
   if (k0 >= n) return;
   const ModEntry me = mt.m[limb];
