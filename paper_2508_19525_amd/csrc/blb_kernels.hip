@@ -181,6 +181,14 @@ void launch_modup(blb_ctx* c, const uint64_t* dcoef, uint64_t* X, const KsLevelC
   k_modup<<<grid, 256, 0, c->stream>>>(dcoef, X, kc_dev, c->n, nl, n_ext, n_digits);
 }
 
+// Operands reached through descriptors in memory are addressed as global memory explicitly
+// (global, not flat, loads and stores: a flat access also counts against the LDS / scalar wait
+// counter and takes a 64-bit vector address).
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // Inner product with the switching key, with the automorphism applied to the extended
 // digits (hoisted order).  Thread per (o, e, two adjacent k); writes U[o][2][e][k] (evaluation
 // form).  For one wave the permuted reads stay inside one aligned block of 64 words: sigma_g
@@ -200,9 +208,9 @@ __global__ void k_ks_inner(const KsOut* __restrict__ outs, const uint64_t* __res
   const int key_mod = e < nl ? e : n_q + (e - nl);
   double acc0[2] = {0.0, 0.0}, acc1[2] = {0.0, 0.0};
   for (int j = 0; j < n_digits; ++j) {
-    const uint64_t* xs = (e >= kc->dlo[j] && e < kc->dhi[j]) ? od.c1 + (size_t)e * n : X + (((size_t)od.src * n_digits + j) * n_ext + e) * n;
-    const uint64_t* kb = od.key + (((size_t)j * 2 + 0) * kc->n_key_mod + key_mod) * n + k0;
-    const uint64_t* ka = od.key + (((size_t)j * 2 + 1) * kc->n_key_mod + key_mod) * n + k0;
+    const auto xs = gmem((e >= kc->dlo[j] && e < kc->dhi[j]) ? od.c1 + (size_t)e * n : X + (((size_t)od.src * n_digits + j) * n_ext + e) * n);
+    const auto kb = gmem(od.key + (((size_t)j * 2 + 0) * kc->n_key_mod + key_mod) * n + k0);
+    const auto ka = gmem(od.key + (((size_t)j * 2 + 1) * kc->n_key_mod + key_mod) * n + k0);
 #pragma unroll
     for (int v = 0; v < 2; ++v) {
       const double x = u2d(xs[kk[v]]);
@@ -253,8 +261,8 @@ __global__ void k_ks_inner_grp(const KsOut* __restrict__ outs, const int* __rest
 #pragma unroll
   for (int j = 0; j < kKsMaxDigits; ++j) {
     if (j < n_digits) {
-      const uint64_t* b = lead.key + (((size_t)j * 2 + 0) * kc->n_key_mod + key_mod) * n + k0;
-      const uint64_t* a = lead.key + (((size_t)j * 2 + 1) * kc->n_key_mod + key_mod) * n + k0;
+      const auto b = gmem(lead.key + (((size_t)j * 2 + 0) * kc->n_key_mod + key_mod) * n + k0);
+      const auto a = gmem(lead.key + (((size_t)j * 2 + 1) * kc->n_key_mod + key_mod) * n + k0);
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
         kb[j][v] = u2d(b[v]);
@@ -269,7 +277,7 @@ __global__ void k_ks_inner_grp(const KsOut* __restrict__ outs, const int* __rest
 #pragma unroll
     for (int j = 0; j < kKsMaxDigits; ++j) {
       if (j < n_digits) {
-        const uint64_t* xs = (e >= kc->dlo[j] && e < kc->dhi[j]) ? od.c1 + (size_t)e * n : X + (((size_t)od.src * n_digits + j) * n_ext + e) * n;
+        const auto xs = gmem((e >= kc->dlo[j] && e < kc->dhi[j]) ? od.c1 + (size_t)e * n : X + (((size_t)od.src * n_digits + j) * n_ext + e) * n);
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
           const double x = u2d(xs[kk[v]]);
@@ -341,25 +349,31 @@ struct Pt50Raw {
   uint32_t top;
 };
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+// (p may come from a descriptor in memory: the planes are addressed as global memory explicitly,
+// so the loads are global, not flat, ones)
 template <int CPT>
 __device__ __forceinline__ void pt50_fetch(const uint8_t* __restrict__ p, int n, int k, Pt50Raw<CPT>& r) {
-  const uint32_t* lo = (const uint32_t*)p;
-  const uint16_t* mid = (const uint16_t*)(p + (size_t)4 * n);
-  const uint32_t* top = (const uint32_t*)(p + (size_t)6 * n);
+  typedef __attribute__((address_space(1))) const uint32_t g32;
+  typedef __attribute__((address_space(1))) const uint16_t g16;
+  typedef __attribute__((address_space(1))) const u32x2 g32x2;
+  typedef __attribute__((address_space(1))) const u32x4 g32x4;
+  g32* lo = (g32*)p;
+  g16* mid = (g16*)(p + (size_t)4 * n);
+  g32* top = (g32*)(p + (size_t)6 * n);
   if constexpr (CPT == 4) {
-    const u32x4 l = __builtin_nontemporal_load((const u32x4*)(lo + k));
+    const u32x4 l = __builtin_nontemporal_load((g32x4*)(lo + k));
     r.lo[0] = l.x;
     r.lo[1] = l.y;
     r.lo[2] = l.z;
     r.lo[3] = l.w;
-    const u32x2 m = __builtin_nontemporal_load((const u32x2*)(mid + k));
+    const u32x2 m = __builtin_nontemporal_load((g32x2*)(mid + k));
     r.mid[0] = m.x;
     r.mid[1] = m.y;
   } else if constexpr (CPT == 2) {
-    const u32x2 l = __builtin_nontemporal_load((const u32x2*)(lo + k));
+    const u32x2 l = __builtin_nontemporal_load((g32x2*)(lo + k));
     r.lo[0] = l.x;
     r.lo[1] = l.y;
-    r.mid[0] = __builtin_nontemporal_load((const uint32_t*)(mid + k));
+    r.mid[0] = __builtin_nontemporal_load((g32*)(mid + k));
   } else {
     r.lo[0] = __builtin_nontemporal_load(lo + k);
     r.mid[0] = __builtin_nontemporal_load(mid + k);
@@ -566,10 +580,10 @@ __global__ void k_sum_cts(const uint64_t* const* __restrict__ srcs, uint64_t* co
   const ModEntry me = mt.m[(w / n) % nl];
   double acc = 0.0;
   for (int t = 0; t < n_terms; ++t) {
-    acc += u2d(srcs[(size_t)o * n_terms + t][w]);
+    acc += u2d(gmem(srcs[(size_t)o * n_terms + t])[w]);
     if ((t & 3) == 3) acc = reduce_s(acc, me.q, me.qinv);
   }
-  dsts[o][w] = d2u(canon_full(acc, me.q, me.qinv));
+  gmem(dsts[o])[w] = d2u(canon_full(acc, me.q, me.qinv));
 }
 void launch_sum_cts(blb_ctx* c, const uint64_t* const* srcs, uint64_t* const* dsts, int n_out, int n_terms, int nl) {
   dim3 grid((2 * nl * c->n + 255) / 256, n_out);
@@ -996,9 +1010,9 @@ __global__ void k_mask_pair(const CcPair* __restrict__ pairs, int nl, int n, Mod
   const CcPair pr = pairs[blockIdx.y];
   const int mw = w % (nl * n);
   const ModEntry me = mt.m[mw / n];
-  double r = mulmod_s(u2d(pr.x[w]), u2d(pr.mx[mw]), me.q, me.qinv);
-  if (pr.y) r += mulmod_s(u2d(pr.y[w]), u2d(pr.my[mw]), me.q, me.qinv);
-  pr.out[w] = d2u(canon_full(r, me.q, me.qinv));
+  double r = mulmod_s(u2d(gmem(pr.x)[w]), u2d(gmem(pr.mx)[mw]), me.q, me.qinv);
+  if (pr.y) r += mulmod_s(u2d(gmem(pr.y)[w]), u2d(gmem(pr.my)[mw]), me.q, me.qinv);
+  gmem(pr.out)[w] = d2u(canon_full(r, me.q, me.qinv));
 }
 void launch_mask_pair(blb_ctx* c, const CcPair* pairs_dev, int n_pairs, int nl) {
   if (n_pairs <= 0) return;
@@ -1018,8 +1032,8 @@ __global__ void k_tensor_sum(const uint64_t* const* __restrict__ A_tab, const ui
   const double q = me.q, qi = me.qinv;
   double d0 = 0.0, d1 = 0.0, d2 = 0.0;
   for (int a = 0; a < n_ct; ++a) {
-    const uint64_t* A = A_tab[a_per_t ? (size_t)t * n_ct + a : (size_t)a];
-    const uint64_t* R = R_tab[(size_t)t * n_ct + a];
+    const auto A = gmem(A_tab[a_per_t ? (size_t)t * n_ct + a : (size_t)a]);
+    const auto R = gmem(R_tab[(size_t)t * n_ct + a]);
     const double a0 = u2d(A[(size_t)limb * n + k]), a1 = u2d(A[(size_t)(nlA + limb) * n + k]);
     const double r0 = u2d(R[(size_t)limb * n + k]), r1 = u2d(R[(size_t)(nl2 + limb) * n + k]);
     d0 += mulmod_s(a0, r0, q, qi);
@@ -1050,13 +1064,14 @@ __global__ void k_masked_acc(const CcTerm* __restrict__ terms, const int* __rest
   if (w >= 2 * nl * n) return;
   const int mw = w % (nl * n);
   const ModEntry me = mt.m[mw / n];
-  double acc = accumulate ? u2d(outs[o][w]) : 0.0;
+  const auto out = gmem(outs[o]);
+  double acc = accumulate ? u2d(out[w]) : 0.0;
   int cnt = 0;
   for (int i = off[o]; i < off[o + 1]; ++i) {
-    acc += mulmod_s(u2d(terms[i].ct[w]), u2d(terms[i].mask[mw]), me.q, me.qinv);
+    acc += mulmod_s(u2d(gmem(terms[i].ct)[w]), u2d(gmem(terms[i].mask)[mw]), me.q, me.qinv);
     if ((++cnt & 3) == 0) acc = reduce_s(acc, me.q, me.qinv);
   }
-  outs[o][w] = d2u(canon_full(acc, me.q, me.qinv));
+  out[w] = d2u(canon_full(acc, me.q, me.qinv));
 }
 void launch_masked_acc(blb_ctx* c, const CcTerm* terms, const int* off, uint64_t* const* outs, int n_out, int nl, bool accumulate) {
   if (n_out <= 0) return;
@@ -1079,6 +1094,8 @@ template <int TB, int IB, int CPT, bool P50>
 __global__ __launch_bounds__(256) void k_cp_mac_batch(const MacGroup* __restrict__ groups, const MacItem* __restrict__ items, int n_items,
                                                       int n, ModTable mt) {
   typedef __attribute__((address_space(1))) const uint64_t gu64c;
+  typedef __attribute__((address_space(1))) const u64x2 gu64x2c;
+  typedef __attribute__((address_space(1))) uint64_t gu64;
   typedef __attribute__((address_space(4))) const uint64_t ku64;
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const MacItem item = items[it];
@@ -1108,17 +1125,35 @@ __global__ __launch_bounds__(256) void k_cp_mac_batch(const MacGroup* __restrict
         if constexpr (P50) {
           pt50_fetch<CPT>(pt[t] + (size_t)ai * term, n, k0, rw[t]);
         } else {
+          const gu64c* a = (const gu64c*)(pt[t] + (size_t)ai * term) + k0;
+          if constexpr (CPT >= 2) {
 #pragma unroll
-          for (int c = 0; c < CPT; ++c) rq[t][c] = __builtin_nontemporal_load((const gu64c*)(pt[t] + (size_t)ai * term) + k0 + c);
+            for (int c = 0; c < CPT; c += 2) {
+              const u64x2 w = __builtin_nontemporal_load((const gu64x2c*)(a + c));
+              rq[t][c] = w.x;
+              rq[t][c + 1] = w.y;
+            }
+          } else {
+            rq[t][0] = __builtin_nontemporal_load(a);
+          }
         }
       }
 #pragma unroll
       for (int u = 0; u < IB; ++u) {
         const gu64c* x = (const gu64c*)rxtab[u][ai];
+        if constexpr (CPT >= 2) {
 #pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-          rx0[u][c] = x[(size_t)limb * n + k0 + c];
-          rx1[u][c] = x[(size_t)(nl + limb) * n + k0 + c];
+          for (int c = 0; c < CPT; c += 2) {
+            const u64x2 w0 = *(const gu64x2c*)(x + (size_t)limb * n + k0 + c);
+            const u64x2 w1 = *(const gu64x2c*)(x + (size_t)(nl + limb) * n + k0 + c);
+            rx0[u][c] = w0.x;
+            rx0[u][c + 1] = w0.y;
+            rx1[u][c] = w1.x;
+            rx1[u][c + 1] = w1.y;
+          }
+        } else {
+          rx0[u][0] = x[(size_t)limb * n + k0];
+          rx1[u][0] = x[(size_t)(nl + limb) * n + k0];
         }
       }
     };
@@ -1167,12 +1202,12 @@ __global__ __launch_bounds__(256) void k_cp_mac_batch(const MacGroup* __restrict
 #pragma unroll
     for (int u = 0; u < IB; ++u) {
       if (u >= ninst) continue;
-      uint64_t* out = gr.inner[item.inst0 + u];
+      gu64* out = (gu64*)gr.inner[item.inst0 + u];
 #pragma unroll
       for (int t = 0; t < TB; ++t) {
         if (bj0 + t < n_bj) {
-          uint64_t* o0 = out + (((size_t)(bj0 + t) * 2 + 0) * nl + limb) * n + k0;
-          uint64_t* o1 = out + (((size_t)(bj0 + t) * 2 + 1) * nl + limb) * n + k0;
+          gu64* o0 = out + (((size_t)(bj0 + t) * 2 + 0) * nl + limb) * n + k0;
+          gu64* o1 = out + (((size_t)(bj0 + t) * 2 + 1) * nl + limb) * n + k0;
 #pragma unroll
           for (int c = 0; c < CPT; ++c) {
             o0[c] = d2u(canon_full(a0[u][t][c], q, qi));
@@ -1232,10 +1267,10 @@ __global__ void k_sum_var(const uint64_t* const* __restrict__ srcs, const int* _
   double acc = 0.0;
   int cnt = 0;
   for (int t = off[o]; t < off[o + 1]; ++t) {
-    acc += u2d(srcs[t][w]);
+    acc += u2d(gmem(srcs[t])[w]);
     if ((++cnt & 3) == 0) acc = reduce_s(acc, me.q, me.qinv);
   }
-  dsts[o][w] = d2u(canon_full(acc, me.q, me.qinv));
+  gmem(dsts[o])[w] = d2u(canon_full(acc, me.q, me.qinv));
 }
 void launch_sum_var(blb_ctx* c, const uint64_t* const* srcs, const int* off, uint64_t* const* dsts, int n_out, int nl) {
   if (n_out <= 0) return;
@@ -1253,7 +1288,7 @@ __global__ void k_scale_cts(const uint64_t* const* __restrict__ in, uint64_t* __
   const int limb = (w / n) % nl, poly = w / (nl * n);
   const ModEntry me = mt.m[limb];
   const size_t src = ((size_t)poly * nl_in + limb) * n + (w % n);
-  out[(size_t)t * 2 * nl * n + w] = d2u(canon(mulmod_s(u2d(in[t][src]), k, me.q, me.qinv), me.q));
+  out[(size_t)t * 2 * nl * n + w] = d2u(canon(mulmod_s(u2d(gmem(in[t])[src]), k, me.q, me.qinv), me.q));
 }
 void launch_scale_cts(blb_ctx* c, const uint64_t* const* in, uint64_t* out, int count, int nl, double k, int nl_in) {
   if (count <= 0) return;
