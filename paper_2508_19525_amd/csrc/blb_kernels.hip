@@ -496,7 +496,8 @@ __global__ __launch_bounds__(256) void k_cp_mac(const uint64_t* __restrict__ pt,
   // consecutive 4 KB pieces of one plaintext limb-poly (the dispatcher deals them round-robin
   // over the 8 XCDs), and the blocks of one (k-chunk, limb) -- the ones reading the same
   // rotated-input words -- lie n_kblk * nl apart, a multiple of 8 whenever n_kblk is: one XCD,
-  // one L2.  (Tile-fastest order with the same XCD grouping streamed 2-12 % slower.)
+  // one L2.  (A tile-fastest order with those readers adjacent on one XCD misses L2 less often
+  // but ran 4-5 % slower on the BERT-base operator.)
   const int kb = blockIdx.x % n_kblk;
   const int limb = (blockIdx.x / n_kblk) % nl;
   const int tile = blockIdx.x / (n_kblk * nl);
