@@ -17,11 +17,13 @@
 // Modular arithmetic on FP64 lanes.
 //
 // All primes are below 2^50, so every residue, and every sum of a few residues, is an
-// integer that a double holds exactly.  A product a*b (|a|,|b| < 2q) is split exactly into
-// p = fl(a*b) and e = fma(a, b, -p) (error-free product); the quotient estimate
-// t = rint(p * (1/q)) is within one of a*b/q, so r = fma(-t, q, p) is an exact integer below
-// 2^51 and r + e = a*b - t*q exactly.  Results are "signed-lazy": |r| < q.  CDNA4 issues
-// FP64 FMA at full rate, which makes this cheaper than 32-bit limb integer products.
+// integer that a double holds exactly.  A product a*b of integers with |a| <= A, |b| <= B is
+// split exactly into p = fl(a*b) and e = fma(a, b, -p) (error-free product, |e| <= A B 2^-53);
+// the quotient estimate t = rint(p * fl(1/q)) is within 1/2 + A B 2^-52 / q of a*b/q, so
+// r = fma(-t, q, p) is an exact integer and r + e = a*b - t*q exactly, with
+// |r + e| <= q/2 + 1.5 A B 2^-52 ("signed-lazy"): below 0.875 q for canonical operands
+// (A = B = q), and below 2^53 whenever that bound is.  CDNA4 issues FP64 FMA at full rate,
+// which makes this cheaper than 32-bit limb integer products.
 // ---------------------------------------------------------------------------------------
 #define BLB_TWO52 4503599627370496.0
 
@@ -31,7 +33,7 @@ __device__ __forceinline__ double u2d(uint64_t x) {  // x < 2^52
 __device__ __forceinline__ uint64_t d2u(double d) {  // integer 0 <= d < 2^52
   return (uint64_t)__double_as_longlong(d + BLB_TWO52) & 0x000FFFFFFFFFFFFFull;
 }
-// a*b - t*q with |result| < q for |a|,|b| < 2q
+// a*b - t*q, |result| <= q/2 + 1.5 |a| |b| 2^-52 (see above)
 __device__ __forceinline__ double mulmod_s(double a, double b, double q, double qinv) {
   const double p = a * b;
   const double e = __builtin_fma(a, b, -p);

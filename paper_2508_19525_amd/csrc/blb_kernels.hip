@@ -1191,7 +1191,7 @@ __global__ __launch_bounds__(256) void k_cp_mac_batch(const MacGroup* __restrict
             a0[u][t][c] += mulmod_s(w[t][c], x0[u][c], q, qi);
             a1[u][t][c] += mulmod_s(w[t][c], x1[u][c], q, qi);
           }
-      if ((ai & 7) == 7) {  // keep |acc| < 9q < 2^53
+      if ((ai & 7) == 7) {  // 8 products below 0.875q each on a reduced |acc| <= q/2: |acc| < 7.5q < 2^53
 #pragma unroll
         for (int u = 0; u < IB; ++u)
 #pragma unroll
