@@ -428,11 +428,26 @@ def _out_index(info, grp, o):
 # --------------------------------------------------------------------------------------
 # graph executors: every replay equals the eager result
 # --------------------------------------------------------------------------------------
-def test_exec_cp_replays_match_eager(c2s):
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_exec_cp_replays_match_eager(c2s, fmt):
+    """Graph replays of a matmul_cp + mask-to-share executor equal eager calls with the same mask
+    seeds, with the plan's plaintexts as 64-bit words (fmt 0) or in the 50-bit format (fmt 1); the
+    50-bit plan's words also equal those of a 64-bit plan of the same weight."""
     B = c2s.B
     L, d_in, d_out, level = 64, 96, 64, 2
-    r = _cp_case(c2s, L, d_in, d_out, level, 77, x_std=1.0)
+    B.blb_ctx_set_knob(c2s.h, B.BLB_KNOB_PLAN_FORMAT, fmt)
+    try:
+        r = _cp_case(c2s, L, d_in, d_out, level, 77, x_std=1.0)
+    finally:
+        B.blb_ctx_set_knob(c2s.h, B.BLB_KNOB_PLAN_FORMAT, 0)
     n_out = r["g"]["n_out"]
+    if fmt:
+        plan64 = B.blb_plan_matmul_cp(c2s.h, r["W"], L, level)
+        Y64 = [c2s.ct(level - 1) for _ in range(n_out)]
+        B.blb_matmul_cp(c2s.h, r["keys_g"], plan64, _xcts(c2s, r, level), Y64)
+        for b in range(n_out):
+            assert np.array_equal(c2s.export(r["Yc"][b]), c2s.export(Y64[b])), f"50-bit plan against 64-bit plan, output {b}"
+        B.blb_plan_destroy(plan64)
     Ye = [c2s.ct(level - 1) for _ in range(n_out)]
     Yg = [c2s.ct(level - 1) for _ in range(n_out)]
     share_e = torch.zeros(n_out * level * c2s.n, dtype=torch.int64, device="cuda")
@@ -451,6 +466,8 @@ def test_exec_cp_replays_match_eager(c2s):
             assert np.array_equal(got[b], c2s.export(Ye[b])), f"replay {rep} output {b}"
         assert np.array_equal(got_share, share_e.cpu().numpy()), f"replay {rep} share"
     B.blb_exec_destroy(ex)
+    B.blb_plan_destroy(r["plan"])
+    B.blb_keys_destroy(r["keys_g"])
 
 
 def test_exec_two_executors_on_two_streams(c2s):
